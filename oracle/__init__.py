@@ -1,0 +1,204 @@
+"""FP64 CPU oracle for the generalized MBO iteration on flat tori.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py`` may import this package.  The product
+path (``paper_1711_01365_amd``) never imports it and shares no code with it.
+
+The arithmetic lives in ``mbo_oracle.c`` (plain C, double precision, OpenMP
+over independent lines / points).  This module only compiles it with gcc when
+the shared object is missing or older than the source, and marshals numpy
+arrays.  Fields are numpy arrays of shape ``(n, n, *grid)`` in C order, i.e.
+``n*n`` real planes of ``prod(grid)`` points ("entry-planar").
+
+What each function follows (Osting & Wang, arXiv:1711.01365):
+  * ``heat``      diffusion step of Algorithm 1 on the flat torus, Section 5.1:
+                  per entry plane, transform, multiply by the heat symbol
+                  exp(-4 pi^2 tau |k|^2), transform back.
+  * ``project``   projection step of Algorithm 1: closest orthogonal matrix
+                  U V^t of Lemma 1.1, by one-sided Jacobi SVD.
+  * ``energy``    Lyapunov functional of Section 4, with weight 1/prod(grid).
+  * ``iterate``   Algorithm 1, with the per-iteration logs used by the tests.
+  * ``dft_naive`` / ``fft``   the discrete Fourier transform by definition and
+                  by radix-2 Cooley-Tukey (cross-checked against each other).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mbo_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libmbo_oracle.so")
+_lib = None
+
+_d = ctypes.POINTER(ctypes.c_double)
+_i64 = ctypes.POINTER(ctypes.c_int64)
+_i32 = ctypes.POINTER(ctypes.c_int32)
+_i8 = ctypes.POINTER(ctypes.c_int8)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle into ``oracle/libmbo_oracle.so`` (gcc, -O2, OpenMP).
+
+    No -march=native and no fast-math: the object travels to other hosts and
+    must keep IEEE double semantics.
+    """
+    stale = (not os.path.exists(_LIB_PATH)
+             or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC))
+    if force or stale:
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.orc_dft_naive.argtypes = [ctypes.c_int, _i64, _d, _d, _d, _d, ctypes.c_int]
+    lib.orc_fft.argtypes = [ctypes.c_int, _i64, _d, _d, ctypes.c_int]
+    lib.orc_heat.argtypes = [ctypes.c_int, _i64, ctypes.c_int64, ctypes.c_double, _d, _d,
+                             ctypes.c_int, _d]
+    lib.orc_project.argtypes = [ctypes.c_int64, ctypes.c_int, _d, _d, _i8, _d, _i32]
+    lib.orc_det_sign.argtypes = [ctypes.c_int64, ctypes.c_int, _d, _i8]
+    lib.orc_energy.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_double, _d,
+                               ctypes.c_int, _d]
+    lib.orc_iterate.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_double, _d,
+                                ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_int),
+                                _d, _i64, _d, _d, ctypes.c_int]
+    for f in ("orc_dft_naive", "orc_fft", "orc_heat", "orc_project", "orc_det_sign",
+              "orc_energy", "orc_iterate"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a, t=_d):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _grid(shape):
+    g = np.ascontiguousarray(np.asarray(shape, dtype=np.int64))
+    return g, len(shape)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError("oracle %s failed with code %d" % (what, rc))
+
+
+def dft_naive(x: np.ndarray, sign: int = -1) -> np.ndarray:
+    """Unscaled d-dimensional DFT by its definition (sign -1 forward, +1 inverse)."""
+    lib = _load()
+    x = np.asarray(x, dtype=np.complex128)
+    g, d = _grid(x.shape)
+    xr = np.ascontiguousarray(x.real)
+    xi = np.ascontiguousarray(x.imag)
+    yr = np.empty_like(xr)
+    yi = np.empty_like(xi)
+    _check(lib.orc_dft_naive(d, _ptr(g, _i64), _ptr(xr), _ptr(xi), _ptr(yr), _ptr(yi), sign),
+           "dft_naive")
+    return yr + 1j * yi
+
+
+def fft(x: np.ndarray, sign: int = -1) -> np.ndarray:
+    """Unscaled d-dimensional radix-2 FFT (sign -1 forward, +1 inverse)."""
+    lib = _load()
+    x = np.asarray(x, dtype=np.complex128)
+    g, d = _grid(x.shape)
+    re = np.ascontiguousarray(x.real).copy()
+    im = np.ascontiguousarray(x.imag).copy()
+    _check(lib.orc_fft(d, _ptr(g, _i64), _ptr(re), _ptr(im), sign), "fft")
+    return re + 1j * im
+
+
+def heat(planes: np.ndarray, tau: float, grid_ndim: int, naive: bool = False):
+    """Apply e^{tau Delta} to every real plane; returns (out, max |Im| after inverse).
+
+    ``planes`` has shape ``(*lead, *grid)`` with ``grid_ndim`` trailing grid axes.
+    """
+    lib = _load()
+    a = np.ascontiguousarray(planes, dtype=np.float64)
+    grid = a.shape[a.ndim - grid_ndim:]
+    nplanes = int(np.prod(a.shape[:a.ndim - grid_ndim], dtype=np.int64))
+    g, d = _grid(grid)
+    out = np.empty_like(a)
+    mi = np.zeros(1)
+    _check(lib.orc_heat(d, _ptr(g, _i64), nplanes, float(tau), _ptr(a), _ptr(out),
+                        int(naive), _ptr(mi)), "heat")
+    return out, float(mi[0])
+
+
+def project(A: np.ndarray):
+    """Closest orthogonal matrix per point.  A has shape (n, n, *grid).
+
+    Returns (Q, detsign int8 [*grid], sigma [n, *grid] unsorted, sweeps int32 [*grid]).
+    """
+    lib = _load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    assert A.shape[1] == n
+    grid = A.shape[2:]
+    P = int(np.prod(grid, dtype=np.int64))
+    Q = np.empty_like(A)
+    ds = np.empty(grid, dtype=np.int8)
+    sg = np.empty((n,) + tuple(grid), dtype=np.float64)
+    sw = np.empty(grid, dtype=np.int32)
+    _check(lib.orc_project(P, n, _ptr(A), _ptr(Q), _ptr(ds, _i8), _ptr(sg), _ptr(sw, _i32)),
+           "project")
+    return Q, ds, sg, sw
+
+
+def det_sign(A: np.ndarray) -> np.ndarray:
+    """sgn(det A) per point with sgn(0) = +1."""
+    lib = _load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    grid = A.shape[2:]
+    P = int(np.prod(grid, dtype=np.int64))
+    ds = np.empty(grid, dtype=np.int8)
+    _check(lib.orc_det_sign(P, n, _ptr(A), _ptr(ds, _i8)), "det_sign")
+    return ds
+
+
+def energy(A: np.ndarray, tau: float, naive: bool = False) -> float:
+    """Lyapunov functional E(A) = (1/tau) mean_p [n - <A, e^{tau Delta} A>_F]."""
+    lib = _load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    g, d = _grid(A.shape[2:])
+    E = np.zeros(1)
+    _check(lib.orc_energy(d, _ptr(g, _i64), n, float(tau), _ptr(A), int(naive), _ptr(E)),
+           "energy")
+    return float(E[0])
+
+
+def iterate(A0: np.ndarray, tau: float, K: int, tol: float = 0.0, naive: bool = False):
+    """Algorithm 1 for K iterations (or until max|A_s - A_{s-1}| <= tol when tol > 0).
+
+    Returns a dict: A (last iterate), iters, energy [iters+1], flips [iters],
+    delta [iters], max_imag.
+    """
+    lib = _load()
+    A = np.ascontiguousarray(A0, dtype=np.float64).copy()
+    n = A.shape[0]
+    g, d = _grid(A.shape[2:])
+    it = ctypes.c_int(0)
+    en = np.zeros(K + 1)
+    fl = np.zeros(max(K, 1), dtype=np.int64)
+    dl = np.zeros(max(K, 1))
+    mi = np.zeros(1)
+    _check(lib.orc_iterate(d, _ptr(g, _i64), n, float(tau), _ptr(A), int(K), float(tol),
+                           ctypes.byref(it), _ptr(en), _ptr(fl, _i64), _ptr(dl), _ptr(mi),
+                           int(naive)), "iterate")
+    s = it.value
+    return {"A": A, "iters": s, "energy": en[: s + 1], "flips": fl[:s], "delta": dl[:s],
+            "max_imag": float(mi[0])}

@@ -1,0 +1,485 @@
+/*
+ * FP64 CPU oracle for the generalized MBO diffusion generated motion for
+ * orthogonal matrix-valued fields on flat tori (Osting & Wang, arXiv:1711.01365:
+ * Algorithm 1, Lemma 1.1, Section 4, Section 5.1).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call
+ * this file: only the test suite, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no code, header, table or helper with the
+ * HIP implementation; it is written to be read against the paper, not to be
+ * fast.
+ *
+ * Conventions (all arrays row-major, last grid axis fastest):
+ *   grid      d axes (d = 1, 2 or 3), N[a] points on axis a, x_a = j / N[a]
+ *             on the unit-period torus (Section 5.1 identifies opposite edges
+ *             of a unit square; the offset of the square is irrelevant here).
+ *   field     "entry-planar": A[i][j][p] = entry (i,j) of the n x n matrix at
+ *             grid point p, i.e. n*n real planes of prod(N) doubles each.
+ *   DFT       forward  X(m) = sum_x x(p) exp(-2 pi i sum_a m_a j_a / N_a),
+ *             inverse  uses exp(+...), no scaling inside the transforms.
+ *
+ * Readings of points the paper leaves open (each is restated where it is used):
+ *   - the heat multiplier is the exact Fourier symbol of e^{tau Delta} on the
+ *     unit torus, exp(-4 pi^2 tau |k|^2), with k_a = m_a for m_a < N_a/2 and
+ *     m_a - N_a otherwise (so the Nyquist index counts as -N_a/2);
+ *   - the closest orthogonal matrix of a singular input is not unique; a
+ *     singular value <= n * eps * sigma_max is treated as zero and the missing
+ *     left singular directions are completed so that det Q = +1 (the matrix
+ *     analogue of sgn(0) = +1 in thresholding); the zero matrix maps to I;
+ *   - the Lyapunov functional is evaluated with quadrature weight 1/prod(N):
+ *     E(A) = (1/tau) * (1/prod(N)) * sum_p [ n - <A(p), (e^{tau Delta}A)(p)>_F ].
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <float.h>
+
+#define ORC_PI 3.14159265358979323846264338328
+#define ORC_TWO_PI (2.0 * ORC_PI)
+
+/* ------------------------------------------------------------------------ */
+/* small helpers                                                             */
+/* ------------------------------------------------------------------------ */
+
+static int64_t orc_npoints(int d, const int64_t* N)
+{
+    int64_t p = 1;
+    for (int a = 0; a < d; ++a) p *= N[a];
+    return p;
+}
+
+static int orc_is_pow2(int64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
+
+/* Pairwise (cascade) summation; error grows like log(len) instead of len. */
+static double orc_pairwise_sum(const double* v, int64_t len)
+{
+    if (len <= 8) {
+        double s = 0.0;
+        for (int64_t i = 0; i < len; ++i) s += v[i];
+        return s;
+    }
+    int64_t h = len / 2;
+    return orc_pairwise_sum(v, h) + orc_pairwise_sum(v + h, len - h);
+}
+
+/* Determinant of an n x n row-major matrix (n <= 4) by Gaussian elimination
+ * with partial pivoting. */
+static double orc_det(int n, const double* m)
+{
+    double a[16];
+    memcpy(a, m, sizeof(double) * n * n);
+    double det = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(a[r * n + c]) > fabs(a[piv * n + c])) piv = r;
+        if (a[piv * n + c] == 0.0) return 0.0;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) {
+                double t = a[c * n + k]; a[c * n + k] = a[piv * n + k]; a[piv * n + k] = t;
+            }
+            det = -det;
+        }
+        det *= a[c * n + c];
+        for (int r = c + 1; r < n; ++r) {
+            double f = a[r * n + c] / a[c * n + c];
+            for (int k = c; k < n; ++k) a[r * n + k] -= f * a[c * n + k];
+        }
+    }
+    return det;
+}
+
+/* sgn with sgn(0) = +1 (the MBO threshold keeps the boundary value). */
+static int orc_sgn(double v) { return v >= 0.0 ? 1 : -1; }
+
+/* ------------------------------------------------------------------------ */
+/* Discrete Fourier transforms                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Naive d-dimensional DFT straight from its definition, O(P^2) for P points.
+ * The phase is reduced exactly in integers per axis before the cos/sin call.
+ * sign = -1 forward, +1 inverse (unscaled).  Any N (not only powers of two). */
+int orc_dft_naive(int d, const int64_t* N, const double* xr, const double* xi,
+                  double* yr, double* yi, int sign)
+{
+    if (d < 1 || d > 3 || (sign != 1 && sign != -1)) return -1;
+    int64_t P = orc_npoints(d, N);
+    int64_t Nn[3] = {1, 1, 1};
+    for (int a = 0; a < d; ++a) Nn[3 - d + a] = N[a];
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t m = 0; m < P; ++m) {
+        int64_t m2 = m % Nn[2], m1 = (m / Nn[2]) % Nn[1], m0 = m / (Nn[2] * Nn[1]);
+        double sr = 0.0, si = 0.0;
+        for (int64_t x = 0; x < P; ++x) {
+            int64_t x2 = x % Nn[2], x1 = (x / Nn[2]) % Nn[1], x0 = x / (Nn[2] * Nn[1]);
+            double ph = (double)((m0 * x0) % Nn[0]) / (double)Nn[0] +
+                        (double)((m1 * x1) % Nn[1]) / (double)Nn[1] +
+                        (double)((m2 * x2) % Nn[2]) / (double)Nn[2];
+            double c = cos(ORC_TWO_PI * ph), s = sign * sin(ORC_TWO_PI * ph);
+            sr += xr[x] * c - xi[x] * s;
+            si += xr[x] * s + xi[x] * c;
+        }
+        yr[m] = sr;
+        yi[m] = si;
+    }
+    return 0;
+}
+
+/* In-place iterative radix-2 Cooley-Tukey transform of one line of length L
+ * (power of two) with element stride `st`.  Twiddles exp(sign 2 pi i k / L)
+ * come from tables of cos/sin(2 pi k / L) evaluated directly for each k (no
+ * recurrence).  sign = -1 forward, +1 inverse (unscaled). */
+static void orc_fft_line(double* re, double* im, int64_t L, int64_t st, int sign,
+                         const double* ct, const double* snt)
+{
+    /* bit-reversal permutation */
+    for (int64_t i = 1, j = 0; i < L; ++i) {
+        int64_t bit = L >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) {
+            double t = re[i * st]; re[i * st] = re[j * st]; re[j * st] = t;
+            t = im[i * st]; im[i * st] = im[j * st]; im[j * st] = t;
+        }
+    }
+    /* butterflies: sub-transforms of length len are merged pairwise */
+    for (int64_t len = 2; len <= L; len <<= 1) {
+        int64_t half = len >> 1, step = L / len;
+        for (int64_t b = 0; b < L; b += len) {
+            for (int64_t k = 0; k < half; ++k) {
+                double wr = ct[k * step], wi = sign * snt[k * step];
+                int64_t u = (b + k) * st, v = (b + k + half) * st;
+                double tr = re[v] * wr - im[v] * wi;
+                double ti = re[v] * wi + im[v] * wr;
+                re[v] = re[u] - tr; im[v] = im[u] - ti;
+                re[u] += tr;        im[u] += ti;
+            }
+        }
+    }
+}
+
+/* d-dimensional FFT (row-column: the 1-D transform along every axis in turn),
+ * in place, unscaled.  Requires every N[a] to be a power of two. */
+int orc_fft(int d, const int64_t* N, double* re, double* im, int sign)
+{
+    if (d < 1 || d > 3 || (sign != 1 && sign != -1)) return -1;
+    for (int a = 0; a < d; ++a) if (!orc_is_pow2(N[a])) return -2;
+    int64_t P = orc_npoints(d, N);
+    for (int a = 0; a < d; ++a) {
+        int64_t L = N[a];
+        int64_t st = 1;
+        for (int b = a + 1; b < d; ++b) st *= N[b];
+        double* ct = (double*)malloc(sizeof(double) * (size_t)L);
+        double* snt = (double*)malloc(sizeof(double) * (size_t)L);
+        for (int64_t k = 0; k < L; ++k) {
+            ct[k] = cos(ORC_TWO_PI * (double)k / (double)L);
+            snt[k] = sin(ORC_TWO_PI * (double)k / (double)L);
+        }
+        int64_t lines = P / L;
+#pragma omp parallel for schedule(static)
+        for (int64_t ln = 0; ln < lines; ++ln) {
+            int64_t outer = ln / st, inner = ln % st;
+            int64_t base = outer * L * st + inner;
+            orc_fft_line(re + base, im + base, L, st, sign, ct, snt);
+        }
+        free(ct);
+        free(snt);
+    }
+    return 0;
+}
+
+/* The heat symbol of Section 5.1 on the unit torus for the multi-index m:
+ * exp(-4 pi^2 tau sum_a k_a^2), with the wrap-around k_a = m_a or m_a - N_a. */
+static double orc_heat_symbol(int d, const int64_t* N, int64_t flat, double tau)
+{
+    double ksq = 0.0;
+    for (int a = d - 1; a >= 0; --a) {
+        int64_t m = flat % N[a];
+        flat /= N[a];
+        int64_t k = (2 * m < N[a]) ? m : m - N[a];
+        ksq += (double)k * (double)k;
+    }
+    return exp(-4.0 * ORC_PI * ORC_PI * tau * ksq);
+}
+
+/* Transform of one complex plane, by the FFT or by the naive DFT. */
+static void orc_transform(int d, const int64_t* N, double* re, double* im, int sign,
+                          int use_naive, double* tr, double* ti)
+{
+    if (use_naive) {
+        int64_t P = orc_npoints(d, N);
+        orc_dft_naive(d, N, re, im, tr, ti, sign);
+        memcpy(re, tr, sizeof(double) * (size_t)P);
+        memcpy(im, ti, sizeof(double) * (size_t)P);
+    } else {
+        orc_fft(d, N, re, im, sign);
+    }
+}
+
+/* Diffusion step of Algorithm 1 on the flat torus (Section 5.1): every real
+ * plane is transformed, multiplied by the heat symbol and transformed back,
+ * out = F^{-1}( symbol * F(in) ).  `nplanes` planes of prod(N) values.
+ * max_imag (nullable) receives max |Im| left after the inverse transform. */
+int orc_heat(int d, const int64_t* N, int64_t nplanes, double tau, const double* in,
+             double* out, int use_naive, double* max_imag)
+{
+    if (d < 1 || d > 3 || nplanes < 1 || !(tau >= 0.0)) return -1;
+    if (!use_naive)
+        for (int a = 0; a < d; ++a) if (!orc_is_pow2(N[a])) return -2;
+    int64_t P = orc_npoints(d, N);
+    double* re = (double*)malloc(sizeof(double) * (size_t)P);
+    double* im = (double*)malloc(sizeof(double) * (size_t)P);
+    double* tr = (double*)malloc(sizeof(double) * (size_t)P);
+    double* ti = (double*)malloc(sizeof(double) * (size_t)P);
+    double mi = 0.0;
+    for (int64_t pl = 0; pl < nplanes; ++pl) {
+        memcpy(re, in + pl * P, sizeof(double) * (size_t)P);
+        memset(im, 0, sizeof(double) * (size_t)P);
+        orc_transform(d, N, re, im, -1, use_naive, tr, ti);
+        for (int64_t m = 0; m < P; ++m) {
+            double g = orc_heat_symbol(d, N, m, tau);
+            re[m] *= g;
+            im[m] *= g;
+        }
+        orc_transform(d, N, re, im, +1, use_naive, tr, ti);
+        for (int64_t p = 0; p < P; ++p) {
+            out[pl * P + p] = re[p] / (double)P;
+            double a = fabs(im[p] / (double)P);
+            if (a > mi) mi = a;
+        }
+    }
+    free(re); free(im); free(tr); free(ti);
+    if (max_imag) *max_imag = mi;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Projection step: closest orthogonal matrix (Lemma 1.1)                    */
+/* ------------------------------------------------------------------------ */
+
+/* One-sided (Hestenes) Jacobi SVD of the n x n row-major matrix a:
+ * orthogonalise the columns of W = A by plane rotations, accumulating them in
+ * V, so that W = U Sigma with sigma_j = ||w_j||.  Then Q = U V^t, the minimiser
+ * of ||B - A||_F over orthogonal B (Lemma 1.1).  Returns the sweep count. */
+static int orc_project_point(int n, const double* a, double* q, double* sig)
+{
+    if (n == 1) {
+        q[0] = (double)orc_sgn(a[0]);
+        if (sig) sig[0] = fabs(a[0]);
+        return 0;
+    }
+    double W[16], V[16];
+    memcpy(W, a, sizeof(double) * n * n);
+    for (int i = 0; i < n * n; ++i) V[i] = 0.0;
+    for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+
+    int sweep = 0;
+    for (; sweep < 30; ++sweep) {
+        int rotated = 0;
+        for (int p = 0; p < n - 1; ++p) {
+            for (int r = p + 1; r < n; ++r) {
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    al += W[i * n + p] * W[i * n + p];
+                    be += W[i * n + r] * W[i * n + r];
+                    ga += W[i * n + p] * W[i * n + r];
+                }
+                if (fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
+                double zeta = (be - al) / (2.0 * ga);
+                double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+                double c = 1.0 / sqrt(1.0 + t * t);
+                double s = c * t;
+                for (int i = 0; i < n; ++i) {
+                    double wp = W[i * n + p], wr = W[i * n + r];
+                    W[i * n + p] = c * wp - s * wr;
+                    W[i * n + r] = s * wp + c * wr;
+                    double vp = V[i * n + p], vr = V[i * n + r];
+                    V[i * n + p] = c * vp - s * vr;
+                    V[i * n + r] = s * vp + c * vr;
+                }
+                rotated = 1;
+            }
+        }
+        if (!rotated) { ++sweep; break; }
+    }
+
+    double sg[4], smax = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double s2 = 0.0;
+        for (int i = 0; i < n; ++i) s2 += W[i * n + j] * W[i * n + j];
+        sg[j] = sqrt(s2);
+        if (sg[j] > smax) smax = sg[j];
+        if (sig) sig[j] = sg[j];
+    }
+    if (smax == 0.0) { /* A = 0: every orthogonal matrix is equally close; take I */
+        for (int i = 0; i < n * n; ++i) q[i] = 0.0;
+        for (int i = 0; i < n; ++i) q[i * n + i] = 1.0;
+        return sweep;
+    }
+    /* U: normalised columns; columns with a (numerically) zero singular value
+     * are completed by Gram-Schmidt against the unit vectors. */
+    double U[16];
+    int zero[4], last_zero = -1;
+    for (int j = 0; j < n; ++j) {
+        zero[j] = sg[j] <= (double)n * DBL_EPSILON * smax;
+        if (!zero[j]) for (int i = 0; i < n; ++i) U[i * n + j] = W[i * n + j] / sg[j];
+    }
+    for (int j = 0; j < n; ++j) {
+        if (!zero[j]) continue;
+        double best[4], bestn = -1.0;
+        for (int e = 0; e < n; ++e) {
+            double r[4];
+            for (int i = 0; i < n; ++i) r[i] = (i == e) ? 1.0 : 0.0;
+            for (int k = 0; k < n; ++k) {
+                if (zero[k] && k >= j) continue; /* not filled yet */
+                double dot = 0.0;
+                for (int i = 0; i < n; ++i) dot += U[i * n + k] * r[i];
+                for (int i = 0; i < n; ++i) r[i] -= dot * U[i * n + k];
+            }
+            double rn = 0.0;
+            for (int i = 0; i < n; ++i) rn += r[i] * r[i];
+            if (rn > bestn) { bestn = rn; memcpy(best, r, sizeof(double) * n); }
+        }
+        bestn = sqrt(bestn);
+        for (int i = 0; i < n; ++i) U[i * n + j] = best[i] / bestn;
+        last_zero = j;
+    }
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) {
+            double s = 0.0;
+            for (int j = 0; j < n; ++j) s += U[i * n + j] * V[k * n + j];
+            q[i * n + k] = s;
+        }
+    if (last_zero >= 0 && orc_det(n, q) < 0.0) {
+        /* the completed direction's sign is free: pick the one with det Q = +1 */
+        for (int i = 0; i < n; ++i) U[i * n + last_zero] = -U[i * n + last_zero];
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                double s = 0.0;
+                for (int j = 0; j < n; ++j) s += U[i * n + j] * V[k * n + j];
+                q[i * n + k] = s;
+            }
+    }
+    return sweep;
+}
+
+/* Pointwise projection of an entry-planar field (Algorithm 1, step 2).
+ * detsign (nullable): sign of det Q per point (+1 / -1).
+ * sigma   (nullable): singular values, sigma[j * npts + p], unsorted.
+ * sweeps  (nullable): Jacobi sweeps used per point. */
+int orc_project(int64_t npts, int n, const double* A, double* Q, int8_t* detsign,
+                double* sigma, int32_t* sweeps)
+{
+    if (npts < 0 || n < 1 || n > 4) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < npts; ++p) {
+        double a[16], q[16], sg[4];
+        for (int e = 0; e < n * n; ++e) a[e] = A[e * npts + p];
+        int sw = orc_project_point(n, a, q, sg);
+        for (int e = 0; e < n * n; ++e) Q[e * npts + p] = q[e];
+        if (detsign) detsign[p] = (int8_t)orc_sgn(orc_det(n, q));
+        if (sigma) for (int j = 0; j < n; ++j) sigma[j * npts + p] = sg[j];
+        if (sweeps) sweeps[p] = sw;
+    }
+    return 0;
+}
+
+/* sgn(det A(p)) per point of a general (not necessarily orthogonal) field. */
+int orc_det_sign(int64_t npts, int n, const double* A, int8_t* detsign)
+{
+    if (npts < 0 || n < 1 || n > 4) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < npts; ++p) {
+        double a[16];
+        for (int e = 0; e < n * n; ++e) a[e] = A[e * npts + p];
+        detsign[p] = (int8_t)orc_sgn(orc_det(n, a));
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lyapunov functional (Section 4, eq. (Lyapunov))                           */
+/* ------------------------------------------------------------------------ */
+
+/* E(A) = (1/tau) (1/P) sum_p [ n - <A(p), HA(p)>_F ], with HA given. */
+static double orc_energy_given(int64_t P, int n, double tau, const double* A, const double* HA)
+{
+    double* e = (double*)malloc(sizeof(double) * (size_t)P);
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < P; ++p) {
+        double s = 0.0;
+        for (int k = 0; k < n * n; ++k) s += A[k * P + p] * HA[k * P + p];
+        e[p] = (double)n - s;
+    }
+    double tot = orc_pairwise_sum(e, P);
+    free(e);
+    return tot / ((double)P * tau);
+}
+
+int orc_energy(int d, const int64_t* N, int n, double tau, const double* A, int use_naive,
+               double* E)
+{
+    if (n < 1 || n > 4 || !(tau > 0.0)) return -1;
+    int64_t P = orc_npoints(d, N);
+    double* HA = (double*)malloc(sizeof(double) * (size_t)(P * n * n));
+    int rc = orc_heat(d, N, (int64_t)n * n, tau, A, HA, use_naive, NULL);
+    if (rc == 0) *E = orc_energy_given(P, n, tau, A, HA);
+    free(HA);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 1: A_s = P(e^{tau Delta} A_{s-1}), s = 1..K                     */
+/* ------------------------------------------------------------------------ */
+
+/* A (in/out) holds A_0 on entry and the last iterate on return.  Logs (all
+ * nullable): energy[s] = E(A_s) for s = 0..iters, flips[s-1] = number of points
+ * whose det sign differs between A_s and A_{s-1}, delta[s-1] = max |A_s -
+ * A_{s-1}| over all entries, max_imag = largest |Im| after any inverse
+ * transform.  With tol > 0 the loop stops after the first s with delta <= tol;
+ * *iters receives the number of iterations performed. */
+int orc_iterate(int d, const int64_t* N, int n, double tau, double* A, int K, double tol,
+                int* iters, double* energy, int64_t* flips, double* delta, double* max_imag,
+                int use_naive)
+{
+    if (n < 1 || n > 4 || !(tau > 0.0) || K < 0) return -1;
+    int64_t P = orc_npoints(d, N);
+    int64_t nn = (int64_t)n * n;
+    double* At = (double*)malloc(sizeof(double) * (size_t)(P * nn));
+    double* An = (double*)malloc(sizeof(double) * (size_t)(P * nn));
+    int8_t* sp = (int8_t*)malloc((size_t)P);
+    int8_t* sn = (int8_t*)malloc((size_t)P);
+    double mi_all = 0.0, mi = 0.0;
+    int rc = 0, done = 0;
+    orc_det_sign(P, n, A, sp);
+    for (int s = 1; s <= K; ++s) {
+        rc = orc_heat(d, N, nn, tau, A, At, use_naive, &mi);           /* diffusion step */
+        if (rc) break;
+        if (mi > mi_all) mi_all = mi;
+        if (energy) energy[s - 1] = orc_energy_given(P, n, tau, A, At); /* E(A_{s-1}) */
+        orc_project(P, n, At, An, sn, NULL, NULL);                      /* projection step */
+        int64_t fl = 0;
+        double dl = 0.0;
+        for (int64_t p = 0; p < P; ++p) fl += (sn[p] != sp[p]);
+        for (int64_t k = 0; k < P * nn; ++k) {
+            double v = fabs(An[k] - A[k]);
+            if (v > dl) dl = v;
+        }
+        if (flips) flips[s - 1] = fl;
+        if (delta) delta[s - 1] = dl;
+        memcpy(A, An, sizeof(double) * (size_t)(P * nn));
+        memcpy(sp, sn, (size_t)P);
+        done = s;
+        if (tol > 0.0 && dl <= tol) break;
+    }
+    if (rc == 0 && energy) {
+        rc = orc_heat(d, N, nn, tau, A, At, use_naive, &mi);
+        if (mi > mi_all) mi_all = mi;
+        energy[done] = orc_energy_given(P, n, tau, A, At);
+    }
+    if (iters) *iters = done;
+    if (max_imag) *max_imag = mi_all;
+    free(At); free(An); free(sp); free(sn);
+    return rc;
+}

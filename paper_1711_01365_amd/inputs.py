@@ -1,0 +1,100 @@
+"""Seeded synthetic inputs shared by the HIP path's tests/benchmarks and the oracle.
+
+This module holds no arithmetic of the method itself: it only draws the initial
+fields (and the parameters of the batched workload) from numpy's
+``default_rng``.  The same float64 arrays feed the oracle and the GPU path; the
+FP32 paths receive them rounded to float32.
+
+Fields are returned in the entry-planar layout ``(n, n, *grid)``: entry (i, j)
+of the matrix at every grid point is one contiguous real plane.
+
+The paper measures on no dataset; its flat-torus experiments start from
+analytic or random fields (Section 6.1).  The workloads below are synthetic
+stand-ins with the sizes and value distributions of the measured configurations.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Tuple
+
+import numpy as np
+
+
+def uniform_field(n: int, grid: Tuple[int, ...], seed: int) -> np.ndarray:
+    """Entries iid Uniform[-1, 1)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1.0, 1.0, size=(n, n) + tuple(grid))
+
+
+def normal_field(n: int, grid: Tuple[int, ...], seed: int) -> np.ndarray:
+    """Entries iid N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(size=(n, n) + tuple(grid))
+
+
+def haar_field(n: int, grid: Tuple[int, ...], seed: int) -> np.ndarray:
+    """Haar-distributed O(n) matrix per point: QR of an iid N(0,1) matrix with the
+    columns of Q multiplied by sgn(diag R) (Mezzadri's sign fix)."""
+    rng = np.random.default_rng(seed)
+    P = int(np.prod(grid))
+    G = rng.standard_normal(size=(P, n, n))
+    Q, R = np.linalg.qr(G)
+    s = np.sign(np.diagonal(R, axis1=1, axis2=2))
+    s[s == 0] = 1.0
+    Q = Q * s[:, None, :]
+    return np.ascontiguousarray(np.moveaxis(Q, 0, -1)).reshape((n, n) + tuple(grid))
+
+
+@dataclass
+class Workload:
+    """One measured configuration: field size, time step, iteration count."""
+    name: str
+    n: int
+    grid: Tuple[int, ...]
+    tau: float
+    iters: int
+    init: str            # "uniform" | "haar" | "normal"
+    seed: int
+
+    def field(self) -> np.ndarray:
+        gen = {"uniform": uniform_field, "haar": haar_field, "normal": normal_field}[self.init]
+        return gen(self.n, self.grid, self.seed)
+
+    @property
+    def points(self) -> int:
+        return int(np.prod(self.grid))
+
+
+# The five measured configurations (sizes, distributions and seeds).
+PARITY_64 = Workload("n2_64x64_f64", 2, (64, 64), 1e-3, 20, "uniform", 0)
+HAAR_512 = Workload("n3_512x512_haar", 3, (512, 512), 2e-4, 200, "haar", 1)
+NORMAL_128_3D = Workload("n3_128x128x128_normal", 3, (128, 128, 128), 5e-4, 100, "normal", 2)
+ADJOINT_256 = Workload("n3_256x256_adjoint", 3, (256, 256), 1e-3, 50, "haar", 4001)
+ADJOINT_TARGET_SEED = 4002
+ADJOINT_TARGET_TAU = 1e-2
+ADJOINT_CHECKPOINT = 10
+
+
+@dataclass
+class BatchedWorkload:
+    """64 independent 2-D fields of mixed n, grid size and time step."""
+    seed: int = 3
+    count: int = 64
+    iters: int = 50
+    members: List[Workload] = field(default_factory=list)
+
+    def __post_init__(self):
+        if not self.members:
+            rng = np.random.default_rng(self.seed)
+            ns = rng.integers(2, 5, size=self.count)
+            Ns = rng.choice(np.array([128, 256, 512, 1024]), size=self.count)
+            taus = 10.0 ** rng.uniform(-4.0, -2.0, size=self.count)
+            self.members = [
+                Workload("batched_%02d" % b, int(ns[b]), (int(Ns[b]), int(Ns[b])),
+                         float(taus[b]), self.iters, "uniform", 3000 + b)
+                for b in range(self.count)
+            ]
+
+    @property
+    def points(self) -> int:
+        return sum(m.points for m in self.members)
