@@ -1,0 +1,151 @@
+/*
+ * mbo.h -- C ABI of libmbo: the generalized MBO diffusion generated motion for
+ * orthogonal matrix-valued fields on flat tori, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: B. Osting and D. Wang, "A generalized MBO diffusion generated motion
+ * for orthogonal matrix-valued fields", arXiv:1711.01365.  Algorithm 1 alternates
+ *   (1) a diffusion step: every entry of the n x n field A is evolved by the heat
+ *       equation for time tau; on the flat torus (Section 5.1) this is a forward
+ *       FFT, a multiplication by the heat symbol exp(-4 pi^2 |k|^2 tau), and an
+ *       inverse FFT;
+ *   (2) a projection step: each point is replaced by its closest orthogonal
+ *       matrix U V^t (Lemma 1.1), where U Sigma V^t is its SVD.
+ * The Lyapunov functional of Section 4 (eq. (Lyapunov)),
+ *       E(A) = (1/tau) * integral over the torus of [ n - <A, e^{tau Delta} A>_F ],
+ * does not increase along the iterates (Proposition 4.3).
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions shared by every entry point
+ * ---------------------------------------------------------------------------
+ * Domain      the unit-period torus [0,1)^d, d = 2 or 3, sampled at N[a] points
+ *             per axis (x = j / N[a]); each N[a] is a power of two in [8, 2048].
+ *             Axis 0 is the slowest-varying one.
+ * Field       DEVICE memory, "entry-planar", row-major:
+ *                 A[b][i][j][p]  =  entry (i, j) of the matrix at grid point p
+ *             of field b (b < batch, i, j < n, p < prod(N), last axis fastest).
+ *             Element type is double for MBO_F64 and float otherwise.  Buffers
+ *             must be 16-byte aligned.  A torch tensor of shape
+ *             (batch, n, n, *N) in C order has exactly this layout.
+ * Heat symbol exp(-4 pi^2 tau sum_a k_a^2) with k_a = m_a for m_a < N[a]/2 and
+ *             m_a - N[a] otherwise (Nyquist counts as -N[a]/2), the exact Fourier
+ *             multiplier of e^{tau Delta} on the unit torus.
+ * Energy      E(A) = (1/tau) * (1/prod(N)) * sum_p [ n - <A(p), (e^{tau Delta}A)(p)>_F ]
+ *             (quadrature weight 1/prod(N) for the integral).
+ * Projection  closest orthogonal matrix of Lemma 1.1.  When the input is singular
+ *             the minimiser is not unique: a singular value <= n*eps*sigma_max
+ *             (eps of the working precision) counts as zero and the minimiser
+ *             with det = +1 is returned; the zero matrix maps to the identity.
+ *             n = 1 is sign thresholding with sgn(0) = +1 (Remark 1.2).
+ * Ownership   the caller owns every field buffer; the plan owns its workspace,
+ *             tables and graphs and frees them in mbo_plan_destroy.  No call
+ *             keeps a caller pointer after it returns (a captured iteration graph
+ *             is keyed by the field pointer and re-captured when it changes).
+ * Streams     all device work is enqueued on the plan's HIP stream.  Calls that
+ *             return host values (mbo_energy, the logs of mbo_iterate)
+ *             synchronise that stream before returning.  A plan must not be used
+ *             by two host threads at once.
+ * Errors      every entry point returns an mbo_status; nothing is thrown and
+ *             nothing aborts.  On error the outputs are unspecified and
+ *             mbo_last_error() describes the failure.
+ * Precision   MBO_F64: all arithmetic in double.
+ *             MBO_F32: diffusion and projection in float.
+ *             MBO_F32_F64FALLBACK: as MBO_F32, but a point whose float-computed
+ *             smallest singular value of the diffused matrix is below
+ *             sigma_fallback is re-projected in double from the float values.
+ * ---------------------------------------------------------------------------
+ */
+#ifndef MBO_H
+#define MBO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mbo_plan_s* mbo_plan_t;
+
+typedef enum {
+    MBO_OK = 0,
+    MBO_ERR_INVALID_ARG = 1,  /* null pointer, d not in {2,3}, n not in [1,4],
+                                 tau not finite and > 0, batch < 1, bad precision */
+    MBO_ERR_UNSUPPORTED = 2,  /* some N[a] not a power of two in [8, 2048] */
+    MBO_ERR_ALLOC = 3,        /* device allocation failed */
+    MBO_ERR_HIP = 4,          /* a HIP runtime call failed (see mbo_last_error) */
+    MBO_ERR_NONFINITE = 5     /* NaN or Inf met in the input of a projection */
+} mbo_status;
+
+typedef enum {
+    MBO_F64 = 0,
+    MBO_F32 = 1,
+    MBO_F32_F64FALLBACK = 2
+} mbo_precision;
+
+/* Create a plan for `batch` fields of n x n matrices on the grid N[0..d-1].
+ * tau: diffusion time of one step (Algorithm 1, step 1).
+ * sigma_fallback: threshold of MBO_F32_F64FALLBACK (ignored otherwise); a value
+ *   <= 0 selects the default 1e-3.
+ * hip_stream: a hipStream_t (NULL = the default stream) on which all work runs;
+ *   the device is the current HIP device at this call.
+ * On success *out receives the plan. */
+mbo_status mbo_plan(mbo_plan_t* out, int d, const int64_t* N, int n, int64_t batch,
+                    double tau, mbo_precision prec, double sigma_fallback, void* hip_stream);
+
+/* Free a plan and everything it owns (NULL is accepted). */
+mbo_status mbo_plan_destroy(mbo_plan_t plan);
+
+/* Change the diffusion time; the heat-symbol tables are rebuilt. */
+mbo_status mbo_plan_set_tau(mbo_plan_t plan, double tau);
+
+/* Change the stream subsequent calls are enqueued on. */
+mbo_status mbo_plan_set_stream(mbo_plan_t plan, void* hip_stream);
+
+/* Diffusion step (Algorithm 1 step 1, Section 5.1):
+ *   A_out = e^{tau Delta} A_in, entry by entry, for every field of the batch.
+ * A_out may alias A_in.  Asynchronous. */
+mbo_status mbo_diffuse(mbo_plan_t plan, const void* A_in, void* A_out);
+
+/* Projection step (Algorithm 1 step 2, Lemma 1.1): A_out(p) = U(p) V(p)^t.
+ * det_sign (nullable, device, int8 [batch][prod(N)]) receives sgn det A_out(p),
+ * which equals sgn det A_in(p) for nonsingular input.  A_out may alias A_in.
+ * Returns MBO_ERR_NONFINITE (after synchronising) if any input value is NaN/Inf. */
+mbo_status mbo_project(mbo_plan_t plan, const void* A_in, void* A_out, int8_t* det_sign);
+
+/* Algorithm 1: A_s = P(e^{tau Delta} A_{s-1}) for s = 1..max_iter, in place on A
+ * (device, holds A_0 on entry and the last iterate on return).  A_0 need not be
+ * orthogonal: the first step diffuses whatever is given.
+ * tol > 0: field b stops after the first s with max|A_s - A_{s-1}| <= tol
+ *   (the change is then tracked every iteration, which costs one extra read and
+ *   write of the field per iteration); tol <= 0 runs all max_iter iterations.
+ * Host-side logs, all nullable, laid out [batch][...]:
+ *   iters_done  [batch]              iterations performed per field;
+ *   energy      [batch][max_iter+1]  E(A_s) for s = 0..iters_done (rest unset);
+ *   flips       [batch][max_iter]    points whose det sign differs between A_s
+ *                                    and A_{s-1} (A_0: sgn det with sgn(0) = +1);
+ *   delta       [batch][max_iter]    max|A_s - A_{s-1}| (only when tol > 0,
+ *                                    otherwise filled with -1);
+ *   fallbacks   [batch][max_iter]    points re-projected in double (fallback mode).
+ * The iteration runs as one captured HIP graph (re-used while A, max_iter and the
+ * requested logs stay the same); the logs are copied back once, at the end,
+ * which synchronises the stream.  max_iter = 0 only evaluates E(A_0). */
+mbo_status mbo_iterate(mbo_plan_t plan, void* A, int max_iter, double tol, int* iters_done,
+                       double* energy, int64_t* flips, double* delta, int64_t* fallbacks);
+
+/* Lyapunov functional E(A) of each field of the batch (Section 4,
+ * eq. (Lyapunov)), evaluated through Parseval in Fourier space:
+ *   E = (1/tau) (n - prod(N)^{-2} sum_m symbol(m) sum_ij |FFT(A_ij)(m)|^2).
+ * E: host, [batch].  Synchronises the stream. */
+mbo_status mbo_energy(mbo_plan_t plan, const void* A, double* E);
+
+/* Human-readable name of a status code (static storage). */
+const char* mbo_status_string(mbo_status s);
+
+/* Description of the last error on this plan (or of the last failed mbo_plan
+ * call when plan is NULL).  Valid until the next call on the same plan. */
+const char* mbo_last_error(mbo_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MBO_H */

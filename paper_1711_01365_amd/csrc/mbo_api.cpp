@@ -1,0 +1,760 @@
+// Host runtime and C ABI of libmbo (declared in include/mbo.h).
+//
+// The plan owns: the packed spectra workspace Z (ceil(n^2/2) complex planes per
+// field), per-point det signs, twiddle tables per axis length, the heat-symbol
+// tables, the device logs of mbo_iterate, and one cached HIP graph of the whole
+// iteration.  All device work goes to the plan's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mbo.h"
+#include "mbo_internal.hpp"
+
+using namespace mbo;
+
+namespace {
+
+thread_local std::string g_plan_error;  // failures of mbo_plan (no plan to hold them)
+
+int ilog2(int64_t v)
+{
+    int l = 0;
+    while ((int64_t(1) << l) < v) ++l;
+    return l;
+}
+
+bool is_pow2(int64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
+
+int lds_len(int L) { return (L - 1) + ((L - 1) >> 3) + 1; }  // lds_pad(L-1) + 1
+
+struct ColCfg {
+    int L = 0, TX = 1;
+    int64_t S = 0, outer = 0;
+    dim3 grid, block;
+    size_t lds = 0;
+    int axis = 0;
+};
+
+}  // namespace
+
+struct mbo_plan_s {
+    int device = 0;
+    int d = 2;
+    int64_t N[3] = {1, 1, 1};
+    int n = 1;
+    int64_t batch = 1;
+    double tau = 0.0;
+    mbo_precision prec = MBO_F64;
+    double sigma_fb = 1e-3;
+    int pk = 0;      // 0 = double kernels, 1 = float kernels
+    size_t esz = 8;  // bytes per real
+    int PL = 1;
+    int64_t npts = 1;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    size_t lds_max = 65536;
+
+    void* Z = nullptr;
+    int8_t* sgn = nullptr;
+    void* tw[3] = {nullptr, nullptr, nullptr};
+    void* lam_row = nullptr;    // heat axis (axis 0) factor [N0]
+    void* lam_inner = nullptr;  // product over the faster axes [npts / N0]
+    unsigned long long* counters = nullptr;  // project: [0] nonfinite, [1] fallbacks
+
+    // launch configuration
+    dim3 row_grid, row_block;
+    size_t row_lds = 0;
+    int row_rpw = 1;
+    ColCfg heat, ypass;
+
+    // logs of mbo_iterate, capacity log_K
+    int log_K = -1;
+    double* epart = nullptr;
+    double* energy = nullptr;
+    unsigned long long* flips = nullptr;
+    unsigned long long* fallbacks = nullptr;
+    unsigned long long* nonfinite = nullptr;
+    unsigned long long* delta_bits = nullptr;
+    int* stop_iter = nullptr;
+
+    // cached iteration graph
+    hipGraphExec_t gexec = nullptr;
+    void* g_A = nullptr;
+    int g_K = -1;
+    int g_key = -1;
+    double g_tol = 0.0;
+
+    std::string err;
+};
+
+namespace {
+
+mbo_status fail(mbo_plan_t p, mbo_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (p) p->err = buf;
+    else g_plan_error = buf;
+    return s;
+}
+
+#define HIP_TRY(plan, expr)                                                                   \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(plan, e_ == hipErrorOutOfMemory ? MBO_ERR_ALLOC : MBO_ERR_HIP,         \
+                        "%s failed: %s", #expr, hipGetErrorString(e_));                        \
+    } while (0)
+
+template <typename T>
+void free_dev(T*& p)
+{
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+void drop_graph(mbo_plan_t p)
+{
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+    p->g_A = nullptr;
+    p->g_K = -1;
+    p->g_key = -1;
+}
+
+void destroy(mbo_plan_t p)
+{
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    drop_graph(p);
+    free_dev(p->Z);
+    free_dev(p->sgn);
+    void* seen[3] = {nullptr, nullptr, nullptr};
+    for (int a = 0; a < 3; ++a) {
+        bool dup = false;
+        for (int b = 0; b < a; ++b) dup = dup || (seen[b] == p->tw[a]);
+        seen[a] = p->tw[a];
+        if (!dup && p->tw[a]) (void)hipFree(p->tw[a]);
+        p->tw[a] = nullptr;
+    }
+    free_dev(p->lam_row);
+    free_dev(p->lam_inner);
+    free_dev(p->counters);
+    free_dev(p->epart);
+    free_dev(p->energy);
+    free_dev(p->flips);
+    free_dev(p->fallbacks);
+    free_dev(p->nonfinite);
+    free_dev(p->delta_bits);
+    free_dev(p->stop_iter);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    delete p;
+}
+
+// Copy an FP64 host table to the device in the plan's precision.
+mbo_status upload(mbo_plan_t p, void* dst, const std::vector<double>& h)
+{
+    if (p->pk == 0) {
+        HIP_TRY(p, hipMemcpy(dst, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> f(h.size());
+        for (size_t i = 0; i < h.size(); ++i) f[i] = (float)h[i];
+        HIP_TRY(p, hipMemcpy(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    return MBO_OK;
+}
+
+// Heat-symbol factor of one axis: exp(-4 pi^2 tau k^2) / N, k the wrapped
+// frequency (m < N/2 ? m : m - N).  The 1/N folds the inverse-DFT scaling in.
+std::vector<double> axis_symbol(int64_t N, double tau)
+{
+    std::vector<double> v((size_t)N);
+    const double pi = 3.14159265358979323846;
+    for (int64_t m = 0; m < N; ++m) {
+        const double k = (2 * m < N) ? (double)m : (double)(m - N);
+        v[(size_t)m] = std::exp(-4.0 * pi * pi * tau * k * k) / (double)N;
+    }
+    return v;
+}
+
+mbo_status build_symbol_tables(mbo_plan_t p)
+{
+    std::vector<double> row = axis_symbol(p->N[0], p->tau);
+    const int64_t inner_n = p->npts / p->N[0];
+    std::vector<double> inner((size_t)inner_n);
+    if (p->d == 2) {
+        inner = axis_symbol(p->N[1], p->tau);
+    } else {
+        std::vector<double> ly = axis_symbol(p->N[1], p->tau), lx = axis_symbol(p->N[2], p->tau);
+        for (int64_t y = 0; y < p->N[1]; ++y)
+            for (int64_t x = 0; x < p->N[2]; ++x) inner[(size_t)(y * p->N[2] + x)] = ly[(size_t)y] * lx[(size_t)x];
+    }
+    mbo_status s = upload(p, p->lam_row, row);
+    if (s != MBO_OK) return s;
+    return upload(p, p->lam_inner, inner);
+}
+
+// Twiddles exp(-2 pi i m / L), m < L, interleaved (re, im).
+std::vector<double> twiddles(int64_t L)
+{
+    std::vector<double> v(2 * (size_t)L);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int64_t m = 0; m < L; ++m) {
+        v[2 * (size_t)m] = std::cos(two_pi * (double)m / (double)L);
+        v[2 * (size_t)m + 1] = -std::sin(two_pi * (double)m / (double)L);
+    }
+    return v;
+}
+
+// Strided pass along `axis` (0 = slowest): transform length L = N[axis], stride
+// S = product of the faster axes, `outer` independent blocks per field.
+mbo_status config_col(mbo_plan_t p, ColCfg& c, int axis)
+{
+    c.axis = axis;
+    c.L = (int)p->N[axis];
+    c.S = 1;
+    for (int a = axis + 1; a < p->d; ++a) c.S *= p->N[a];
+    c.outer = (int64_t)p->PL * (p->npts / (c.L * c.S));
+    const int T = c.L / 8;
+    int TX = 1;
+    while (TX < 16 && TX * 2 <= c.S && T * TX * 2 <= 512) TX *= 2;
+    const size_t per_col = (size_t)lds_len(c.L) * 2 * p->esz;
+    while (TX > 1 && per_col * TX > p->lds_max) TX /= 2;
+    if (per_col * TX > p->lds_max)
+        return fail(p, MBO_ERR_UNSUPPORTED, "axis of length %d needs more LDS than available", c.L);
+    c.TX = TX;
+    c.block = dim3((unsigned)(T * TX));
+    c.grid = dim3((unsigned)(c.outer * (c.S / TX)), (unsigned)p->batch);
+    c.lds = per_col * TX;
+    return MBO_OK;
+}
+
+// Row pass: a workgroup owns rpw whole rows (at least 256 points) of every
+// packed plane; NT = min(512, rpw * L) threads, one point per thread and pass in
+// the projection phase, groups of L/8 threads per line in the FFT phases.
+mbo_status config_row(mbo_plan_t p)
+{
+    const int L = (int)p->N[p->d - 1];
+    const int64_t rows = p->npts / L;
+    int rpw = 1;
+    while (rpw * L < 256 && rpw * 2 <= rows) rpw *= 2;
+    const size_t per_row = (size_t)p->PL * lds_len(L) * 2 * p->esz;
+    while (rpw > 1 && per_row * rpw > p->lds_max) rpw /= 2;
+    if (per_row * rpw > p->lds_max)
+        return fail(p, MBO_ERR_UNSUPPORTED,
+                    "rows of length %d with %d packed planes need %zu bytes of LDS (max %zu)", L,
+                    p->PL, per_row, p->lds_max);
+    const int nt = rpw * L < 512 ? rpw * L : 512;
+    p->row_rpw = rpw;
+    p->row_block = dim3((unsigned)nt);
+    p->row_grid = dim3((unsigned)((rows + rpw - 1) / rpw), (unsigned)p->batch);
+    p->row_lds = per_row * rpw;
+    return MBO_OK;
+}
+
+RowArgs row_args(mbo_plan_t p)
+{
+    RowArgs a;
+    std::memset(&a, 0, sizeof a);
+    const int L = (int)p->N[p->d - 1];
+    a.L = L;
+    a.log2L = ilog2(L);
+    a.rpw = p->row_rpw;
+    a.lds_plane = lds_len(L);
+    a.rows = p->npts / L;
+    a.npts = p->npts;
+    a.tw = p->tw[p->d - 1];
+    a.Z = p->Z;
+    a.sgn = p->sgn;
+    a.sigma_fb = p->sigma_fb;
+    a.K = 1;
+    return a;
+}
+
+ColArgs col_args(mbo_plan_t p, const ColCfg& c)
+{
+    ColArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.L = c.L;
+    a.log2L = ilog2(c.L);
+    a.TX = c.TX;
+    a.lds_col = lds_len(c.L);
+    a.S = c.S;
+    a.tiles = c.S / c.TX;
+    a.field_elems = (int64_t)p->PL * p->npts;
+    a.tw = p->tw[c.axis];
+    a.Z = p->Z;
+    a.lam_row = p->lam_row;
+    a.lam_inner = p->lam_inner;
+    a.nwg = (int)(c.outer * (c.S / c.TX));
+    a.slot = 0;
+    return a;
+}
+
+hipError_t run_row(mbo_plan_t p, const RowArgs& a, hipStream_t st)
+{
+    return launch_row(p->pk, p->n, a.log2L, a, p->row_grid, p->row_block, p->row_lds, st);
+}
+
+hipError_t run_col(mbo_plan_t p, const ColCfg& c, int mode, const ColArgs& a, hipStream_t st)
+{
+    return launch_col(p->pk, mode, a.log2L, a, c.grid, c.block, c.lds, st);
+}
+
+// Raise the dynamic-LDS limit of every kernel instance this plan launches to
+// the device maximum.  Advisory: the launch configuration never asks for more
+// than the device's sharedMemPerBlock, so a refusal is not an error.
+void prepare_plan_kernels(mbo_plan_t p)
+{
+    RowArgs r = row_args(p);
+    (void)launch_row(p->pk, p->n, r.log2L, r, p->row_grid, p->row_block, p->lds_max, nullptr, true);
+    for (int m = CM_FORWARD; m <= CM_ENERGY; ++m) {
+        ColArgs h = col_args(p, p->heat);
+        (void)launch_col(p->pk, m, h.log2L, h, p->heat.grid, p->heat.block, p->lds_max, nullptr, true);
+        if (p->d == 3) {
+            ColArgs y = col_args(p, p->ypass);
+            (void)launch_col(p->pk, m, y.log2L, y, p->ypass.grid, p->ypass.block, p->lds_max, nullptr, true);
+        }
+    }
+    (void)hipGetLastError();
+}
+
+mbo_status ensure_logs(mbo_plan_t p, int K)
+{
+    if (K <= p->log_K) return MBO_OK;
+    drop_graph(p);
+    free_dev(p->epart);
+    free_dev(p->energy);
+    free_dev(p->flips);
+    free_dev(p->fallbacks);
+    free_dev(p->nonfinite);
+    free_dev(p->delta_bits);
+    free_dev(p->stop_iter);
+    const size_t slots = (size_t)p->batch * (size_t)(K + 1);
+    const int nwg = (int)p->heat.grid.x;
+    HIP_TRY(p, hipMalloc((void**)&p->epart, slots * (size_t)nwg * sizeof(double)));
+    HIP_TRY(p, hipMalloc((void**)&p->energy, slots * sizeof(double)));
+    const size_t cslots = (size_t)p->batch * (size_t)(K > 0 ? K : 1);
+    HIP_TRY(p, hipMalloc((void**)&p->flips, cslots * sizeof(unsigned long long)));
+    HIP_TRY(p, hipMalloc((void**)&p->fallbacks, cslots * sizeof(unsigned long long)));
+    HIP_TRY(p, hipMalloc((void**)&p->nonfinite, cslots * sizeof(unsigned long long)));
+    HIP_TRY(p, hipMalloc((void**)&p->delta_bits, cslots * sizeof(unsigned long long)));
+    HIP_TRY(p, hipMalloc((void**)&p->stop_iter, (size_t)p->batch * sizeof(int)));
+    p->log_K = K;
+    return MBO_OK;
+}
+
+// Forward transforms of a real field into Z: rows, then (3-D, with_mid) the
+// middle axis.
+hipError_t enqueue_forward(mbo_plan_t p, const void* A, int extra_flags, bool with_mid, hipStream_t st)
+{
+    RowArgs r = row_args(p);
+    r.Ain = A;
+    r.flags = RF_LOAD_REAL | RF_FORWARD | extra_flags;
+    hipError_t e = run_row(p, r, st);
+    if (e != hipSuccess) return e;
+    if (p->d == 3 && with_mid) {
+        ColArgs y = col_args(p, p->ypass);
+        e = run_col(p, p->ypass, CM_FORWARD, y, st);
+    }
+    return e;
+}
+
+// Enqueue the whole of mbo_iterate on stream st (captured into a graph by the caller).
+hipError_t enqueue_iterate(mbo_plan_t p, void* A, int K, double tol, bool want_energy, hipStream_t st)
+{
+    const bool track = tol > 0.0;
+    const bool fallback = p->prec == MBO_F32_F64FALLBACK;
+    const int64_t cs = (int64_t)p->batch * (K > 0 ? K : 1);
+    hipError_t e;
+    if ((e = launch_fill_u64(p->flips, cs, 0ull, st)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(p->fallbacks, cs, 0ull, st)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(p->nonfinite, cs, 0ull, st)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(p->delta_bits, cs, 0ull, st)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(p->stop_iter, p->batch, K, st)) != hipSuccess) return e;
+
+    // A_0: forward row FFT (and det signs for the flip count of iteration 1);
+    // in 3-D each iteration starts with the middle-axis forward pass itself.
+    if ((e = enqueue_forward(p, A, RF_SIGN_INIT, false, st)) != hipSuccess) return e;
+
+    for (int s = 1; s <= K; ++s) {
+        ColArgs h = col_args(p, p->heat);
+        h.iter = s;
+        h.K = K;
+        h.stop_iter = p->stop_iter;
+        h.delta_bits = track ? p->delta_bits : nullptr;
+        h.tol = tol;
+        h.slot = s - 1;
+        h.epart = want_energy ? p->epart : nullptr;
+        if (p->d == 3) {
+            // the first pass of the iteration takes the stop decision
+            ColArgs y = col_args(p, p->ypass);
+            y.iter = s;
+            y.K = K;
+            y.stop_iter = p->stop_iter;
+            y.delta_bits = track ? p->delta_bits : nullptr;
+            y.tol = tol;
+            if ((e = run_col(p, p->ypass, CM_FORWARD, y, st)) != hipSuccess)
+                return e;
+            h.delta_bits = nullptr;
+        }
+        if ((e = run_col(p, p->heat, CM_HEAT, h, st)) != hipSuccess) return e;
+        if (p->d == 3) {
+            ColArgs y = col_args(p, p->ypass);
+            y.iter = s;
+            y.K = K;
+            y.stop_iter = p->stop_iter;
+            if ((e = run_col(p, p->ypass, CM_INVERSE, y, st)) != hipSuccess) return e;
+        }
+        RowArgs r = row_args(p);
+        r.Aout = A;
+        r.iter = s;
+        r.K = K;
+        r.flips = p->flips;
+        r.fallbacks = p->fallbacks;
+        r.nonfinite = p->nonfinite;
+        r.delta_bits = p->delta_bits;
+        r.stop_iter = p->stop_iter;
+        r.flags = RF_INVERSE | RF_PROJECT | RF_SIGN | RF_CHECK_STOP;
+        if (s < K || want_energy) r.flags |= RF_FORWARD;
+        if (s == K || track) r.flags |= RF_STORE_REAL;
+        if (track) r.flags |= RF_TRACK;
+        if (fallback) r.flags |= RF_FALLBACK;
+        if ((e = run_row(p, r, st)) != hipSuccess) return e;
+    }
+    if (want_energy) {
+        // E(A_final): Z holds the row spectra of the last iterate (A_0 for K = 0)
+        if (p->d == 3) {
+            ColArgs y = col_args(p, p->ypass);
+            if ((e = run_col(p, p->ypass, CM_FORWARD, y, st)) != hipSuccess) return e;
+        }
+        ColArgs h = col_args(p, p->heat);
+        h.K = K;
+        h.slot = -1;
+        h.stop_iter = p->stop_iter;
+        h.epart = p->epart;
+        if ((e = run_col(p, p->heat, CM_ENERGY, h, st)) != hipSuccess) return e;
+        ReduceArgs ra;
+        ra.epart = p->epart;
+        ra.nwg = (int)p->heat.grid.x;
+        ra.K = K;
+        ra.batch = (int)p->batch;
+        ra.n = p->n;
+        ra.npts = p->npts;
+        ra.tau = p->tau;
+        ra.stop_iter = p->stop_iter;
+        ra.energy = p->energy;
+        if ((e = launch_reduce(ra, st)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+bool use_graphs()
+{
+    const char* v = std::getenv("MBO_NO_GRAPH");
+    return !(v && v[0] == '1');
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* mbo_status_string(mbo_status s)
+{
+    switch (s) {
+    case MBO_OK: return "MBO_OK";
+    case MBO_ERR_INVALID_ARG: return "MBO_ERR_INVALID_ARG";
+    case MBO_ERR_UNSUPPORTED: return "MBO_ERR_UNSUPPORTED";
+    case MBO_ERR_ALLOC: return "MBO_ERR_ALLOC";
+    case MBO_ERR_HIP: return "MBO_ERR_HIP";
+    case MBO_ERR_NONFINITE: return "MBO_ERR_NONFINITE";
+    }
+    return "MBO_ERR_UNKNOWN";
+}
+
+const char* mbo_last_error(mbo_plan_t plan)
+{
+    return plan ? plan->err.c_str() : g_plan_error.c_str();
+}
+
+mbo_status mbo_plan(mbo_plan_t* out, int d, const int64_t* N, int n, int64_t batch, double tau,
+                    mbo_precision prec, double sigma_fallback, void* hip_stream)
+{
+    g_plan_error.clear();
+    if (!out) return fail(nullptr, MBO_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!N) return fail(nullptr, MBO_ERR_INVALID_ARG, "N is NULL");
+    if (d != 2 && d != 3) return fail(nullptr, MBO_ERR_INVALID_ARG, "d must be 2 or 3 (got %d)", d);
+    if (n < 1 || n > 4) return fail(nullptr, MBO_ERR_INVALID_ARG, "n must be in [1,4] (got %d)", n);
+    if (batch < 1) return fail(nullptr, MBO_ERR_INVALID_ARG, "batch must be >= 1");
+    if (!(tau > 0.0) || !std::isfinite(tau))
+        return fail(nullptr, MBO_ERR_INVALID_ARG, "tau must be finite and > 0");
+    if (prec != MBO_F64 && prec != MBO_F32 && prec != MBO_F32_F64FALLBACK)
+        return fail(nullptr, MBO_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
+    for (int a = 0; a < d; ++a)
+        if (!is_pow2(N[a]) || N[a] < 8 || N[a] > 2048)
+            return fail(nullptr, MBO_ERR_UNSUPPORTED,
+                        "N[%d] = %lld: each axis must be a power of two in [8, 2048]", a,
+                        (long long)N[a]);
+
+    mbo_plan_t p = new mbo_plan_s();
+    p->d = d;
+    for (int a = 0; a < d; ++a) p->N[a] = N[a];
+    p->n = n;
+    p->batch = batch;
+    p->tau = tau;
+    p->prec = prec;
+    p->sigma_fb = sigma_fallback > 0.0 ? sigma_fallback : 1e-3;
+    p->pk = prec == MBO_F64 ? 0 : 1;
+    p->esz = prec == MBO_F64 ? 8 : 4;
+    p->PL = (n * n + 1) / 2;
+    p->npts = 1;
+    for (int a = 0; a < d; ++a) p->npts *= N[a];
+    p->stream = (hipStream_t)hip_stream;
+
+#define PLAN_TRY(expr)                                                                        \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            mbo_status s_ = e_ == hipErrorOutOfMemory ? MBO_ERR_ALLOC : MBO_ERR_HIP;           \
+            fail(nullptr, s_, "%s failed: %s", #expr, hipGetErrorString(e_));                  \
+            destroy(p);                                                                        \
+            return s_;                                                                         \
+        }                                                                                      \
+    } while (0)
+#define PLAN_STATUS(expr)                                                                     \
+    do {                                                                                       \
+        mbo_status s_ = (expr);                                                                \
+        if (s_ != MBO_OK) {                                                                    \
+            g_plan_error = p->err;                                                             \
+            destroy(p);                                                                        \
+            return s_;                                                                         \
+        }                                                                                      \
+    } while (0)
+
+    PLAN_TRY(hipGetDevice(&p->device));
+    hipDeviceProp_t prop;
+    PLAN_TRY(hipGetDeviceProperties(&prop, p->device));
+    // leave room for the kernels' static LDS (reduction scratch)
+    p->lds_max = prop.sharedMemPerBlock > 4096 ? (size_t)prop.sharedMemPerBlock - 2048 : 65536;
+    PLAN_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+
+    PLAN_STATUS(config_row(p));
+    PLAN_STATUS(config_col(p, p->heat, 0));
+    if (d == 3) PLAN_STATUS(config_col(p, p->ypass, 1));
+    prepare_plan_kernels(p);
+
+    const size_t zbytes = (size_t)batch * p->PL * (size_t)p->npts * 2 * p->esz;
+    PLAN_TRY(hipMalloc(&p->Z, zbytes));
+    PLAN_TRY(hipMalloc((void**)&p->sgn, (size_t)batch * (size_t)p->npts));
+    PLAN_TRY(hipMalloc((void**)&p->counters, 4 * sizeof(unsigned long long)));
+    for (int a = 0; a < d; ++a) {
+        for (int b = 0; b < a; ++b)
+            if (N[b] == N[a]) p->tw[a] = p->tw[b];
+        if (p->tw[a]) continue;
+        PLAN_TRY(hipMalloc(&p->tw[a], (size_t)N[a] * 2 * p->esz));
+        PLAN_STATUS(upload(p, p->tw[a], twiddles(N[a])));
+    }
+    PLAN_TRY(hipMalloc(&p->lam_row, (size_t)N[0] * p->esz));
+    PLAN_TRY(hipMalloc(&p->lam_inner, (size_t)(p->npts / N[0]) * p->esz));
+    PLAN_STATUS(build_symbol_tables(p));
+#undef PLAN_TRY
+#undef PLAN_STATUS
+    *out = p;
+    return MBO_OK;
+}
+
+mbo_status mbo_plan_destroy(mbo_plan_t plan)
+{
+    destroy(plan);
+    return MBO_OK;
+}
+
+mbo_status mbo_plan_set_tau(mbo_plan_t p, double tau)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (!(tau > 0.0) || !std::isfinite(tau)) return fail(p, MBO_ERR_INVALID_ARG, "tau must be finite and > 0");
+    HIP_TRY(p, hipSetDevice(p->device));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));  // tables may be in use by queued work
+    p->tau = tau;
+    drop_graph(p);  // the energy reduction bakes tau into its arguments
+    return build_symbol_tables(p);
+}
+
+mbo_status mbo_plan_set_stream(mbo_plan_t p, void* hip_stream)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    p->stream = (hipStream_t)hip_stream;
+    return MBO_OK;
+}
+
+mbo_status mbo_diffuse(mbo_plan_t p, const void* A_in, void* A_out)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (!A_in || !A_out) return fail(p, MBO_ERR_INVALID_ARG, "A_in / A_out is NULL");
+    HIP_TRY(p, hipSetDevice(p->device));
+    HIP_TRY(p, enqueue_forward(p, A_in, 0, true, p->stream));
+    ColArgs h = col_args(p, p->heat);
+    HIP_TRY(p, run_col(p, p->heat, CM_HEAT, h, p->stream));
+    if (p->d == 3) {
+        ColArgs y = col_args(p, p->ypass);
+        HIP_TRY(p, run_col(p, p->ypass, CM_INVERSE, y, p->stream));
+    }
+    RowArgs r = row_args(p);
+    r.Aout = A_out;
+    r.flags = RF_INVERSE | RF_STORE_REAL;
+    HIP_TRY(p, run_row(p, r, p->stream));
+    return MBO_OK;
+}
+
+mbo_status mbo_project(mbo_plan_t p, const void* A_in, void* A_out, int8_t* det_sign)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (!A_in || !A_out) return fail(p, MBO_ERR_INVALID_ARG, "A_in / A_out is NULL");
+    HIP_TRY(p, hipSetDevice(p->device));
+    HIP_TRY(p, launch_fill_u64(p->counters, 4, 0ull, p->stream));
+    ProjArgs a;
+    a.npts = p->npts;
+    a.A = A_in;
+    a.Q = A_out;
+    a.dsign = det_sign;
+    a.nonfinite = p->counters;
+    a.fallbacks = p->counters + 1;
+    a.fallback = p->prec == MBO_F32_F64FALLBACK;
+    a.sigma_fb = p->sigma_fb;
+    HIP_TRY(p, launch_project(p->pk, p->n, a, (int)p->batch, p->stream));
+    unsigned long long h[4];
+    HIP_TRY(p, hipMemcpyAsync(h, p->counters, sizeof h, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    if (h[0]) return fail(p, MBO_ERR_NONFINITE, "%llu points with NaN/Inf input", h[0]);
+    return MBO_OK;
+}
+
+mbo_status mbo_energy(mbo_plan_t p, const void* A, double* E)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (!A || !E) return fail(p, MBO_ERR_INVALID_ARG, "A / E is NULL");
+    HIP_TRY(p, hipSetDevice(p->device));
+    mbo_status s = ensure_logs(p, 0);
+    if (s != MBO_OK) return s;
+    HIP_TRY(p, enqueue_forward(p, A, 0, true, p->stream));
+    ColArgs h = col_args(p, p->heat);
+    h.K = 0;
+    h.slot = 0;
+    h.epart = p->epart;
+    HIP_TRY(p, run_col(p, p->heat, CM_ENERGY, h, p->stream));
+    ReduceArgs ra;
+    ra.epart = p->epart;
+    ra.nwg = (int)p->heat.grid.x;
+    ra.K = 0;
+    ra.batch = (int)p->batch;
+    ra.n = p->n;
+    ra.npts = p->npts;
+    ra.tau = p->tau;
+    ra.stop_iter = nullptr;
+    ra.energy = p->energy;
+    HIP_TRY(p, launch_reduce(ra, p->stream));
+    HIP_TRY(p, hipMemcpyAsync(E, p->energy, (size_t)p->batch * sizeof(double), hipMemcpyDeviceToHost,
+                              p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    return MBO_OK;
+}
+
+mbo_status mbo_iterate(mbo_plan_t p, void* A, int max_iter, double tol, int* iters_done,
+                       double* energy, int64_t* flips, double* delta, int64_t* fallbacks)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (!A) return fail(p, MBO_ERR_INVALID_ARG, "A is NULL");
+    if (max_iter < 0) return fail(p, MBO_ERR_INVALID_ARG, "max_iter < 0");
+    if (std::isnan(tol)) return fail(p, MBO_ERR_INVALID_ARG, "tol is NaN");
+    HIP_TRY(p, hipSetDevice(p->device));
+    const int K = max_iter;
+    const bool want_energy = energy != nullptr;
+    mbo_status s = ensure_logs(p, K);
+    if (s != MBO_OK) return s;
+    const int key = (tol > 0.0 ? 1 : 0) | (want_energy ? 2 : 0);
+    if (use_graphs()) {
+        if (!(p->gexec && p->g_A == A && p->g_K == K && p->g_key == key && p->g_tol == tol)) {
+            drop_graph(p);
+            hipGraph_t g = nullptr;
+            HIP_TRY(p, hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+            hipError_t e = enqueue_iterate(p, A, K, tol, want_energy, p->cap);
+            hipError_t e2 = hipStreamEndCapture(p->cap, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return fail(p, MBO_ERR_HIP, "graph capture failed: %s",
+                            hipGetErrorString(e != hipSuccess ? e : e2));
+            }
+            hipError_t e3 = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e3 != hipSuccess) {
+                p->gexec = nullptr;
+                return fail(p, MBO_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e3));
+            }
+            p->g_A = A;
+            p->g_K = K;
+            p->g_key = key;
+            p->g_tol = tol;
+        }
+        HIP_TRY(p, hipGraphLaunch(p->gexec, p->stream));
+    } else {
+        HIP_TRY(p, enqueue_iterate(p, A, K, tol, want_energy, p->stream));
+    }
+
+    // one copy of the logs at the end
+    const size_t B = (size_t)p->batch;
+    const size_t cs = B * (size_t)(K > 0 ? K : 1);
+    std::vector<int> st(B);
+    std::vector<unsigned long long> hf(cs), hfb(cs), hbad(cs), hd(cs);
+    std::vector<double> he(B * (size_t)(K + 1));
+    HIP_TRY(p, hipMemcpyAsync(st.data(), p->stop_iter, B * sizeof(int), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipMemcpyAsync(hf.data(), p->flips, cs * 8, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipMemcpyAsync(hfb.data(), p->fallbacks, cs * 8, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipMemcpyAsync(hbad.data(), p->nonfinite, cs * 8, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipMemcpyAsync(hd.data(), p->delta_bits, cs * 8, hipMemcpyDeviceToHost, p->stream));
+    if (want_energy)
+        HIP_TRY(p, hipMemcpyAsync(he.data(), p->energy, he.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                  p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+
+    unsigned long long bad = 0;
+    for (size_t b = 0; b < B; ++b) {
+        const int done = st[b];
+        if (iters_done) iters_done[b] = done;
+        for (int k = 0; k < K; ++k) {
+            const size_t i = b * (size_t)K + (size_t)k;
+            const bool ran = k < done;
+            if (flips) flips[i] = ran ? (int64_t)hf[i] : 0;
+            if (fallbacks) fallbacks[i] = ran ? (int64_t)hfb[i] : 0;
+            if (delta) {
+                double dv;
+                std::memcpy(&dv, &hd[i], sizeof dv);
+                delta[i] = (ran && tol > 0.0) ? dv : -1.0;
+            }
+            if (ran) bad += hbad[i];
+        }
+        if (energy)
+            for (int k = 0; k <= K; ++k) {
+                const size_t i = b * (size_t)(K + 1) + (size_t)k;
+                energy[i] = k <= done ? he[i] : std::nan("");
+            }
+    }
+    if (bad) return fail(p, MBO_ERR_NONFINITE, "%llu projections met NaN/Inf input", bad);
+    return MBO_OK;
+}
+
+}  // extern "C"

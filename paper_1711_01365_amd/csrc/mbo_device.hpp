@@ -1,0 +1,506 @@
+// Device building blocks for gfx950: radix-8 Stockham FFT stages held in
+// registers with LDS exchanges, and the per-point closest-orthogonal-matrix
+// projection (closed form for n = 2, one-sided Jacobi for n = 3, 4).
+//
+// Method: Osting & Wang, arXiv:1711.01365.  The FFT realises the flat-torus
+// diffusion step of Section 5.1; the projection is Lemma 1.1 (Algorithm 1,
+// step 2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mbo {
+
+template <typename T> struct cx;
+template <> struct cx<float> { typedef float2 type; };
+template <> struct cx<double> { typedef double2 type; };
+
+template <typename T> struct num;
+template <> struct num<float> {
+    // unit roundoff scale used by the singular-value zero test and the Jacobi
+    // stopping rule (columns orthogonal to working precision)
+    static constexpr float eps = 1.1920928955078125e-07f;
+    static constexpr float jtol2 = 1.4210854715202004e-14f;  // eps^2
+    // hardware approximations (about 1 ulp): the rotation angle of a Jacobi step
+    // need not be correctly rounded, any accurate rotation serves
+    static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+};
+template <> struct num<double> {
+    static constexpr double eps = 2.220446049250313e-16;
+    static constexpr double jtol2 = 1e-30;  // (1e-15)^2
+    static __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+};
+
+// ---------------------------------------------------------------------------
+// FFT: small DFTs.  S = -1: forward (exp(-2 pi i jk/R)), S = +1: inverse.
+// ---------------------------------------------------------------------------
+
+template <typename T, int S>
+__device__ __forceinline__ void mul_si(T& r, T& i)  // (r + i i) * (S i)
+{
+    T t = r;
+    r = (S > 0) ? -i : i;
+    i = (S > 0) ? t : -t;
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void dft2(T* r, T* i)
+{
+    T tr = r[0] - r[1], ti = i[0] - i[1];
+    r[0] += r[1]; i[0] += i[1];
+    r[1] = tr; i[1] = ti;
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void dft4(T* r, T* i)
+{
+    T t0r = r[0] + r[2], t0i = i[0] + i[2];
+    T t1r = r[0] - r[2], t1i = i[0] - i[2];
+    T t2r = r[1] + r[3], t2i = i[1] + i[3];
+    T t3r = r[1] - r[3], t3i = i[1] - i[3];
+    mul_si<T, S>(t3r, t3i);
+    r[0] = t0r + t2r; i[0] = t0i + t2i;
+    r[2] = t0r - t2r; i[2] = t0i - t2i;
+    r[1] = t1r + t3r; i[1] = t1i + t3i;
+    r[3] = t1r - t3r; i[3] = t1i - t3i;
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void dft8(T* r, T* i)
+{
+    const T c = (T)0.70710678118654752440084436210485;
+    T er[4] = {r[0], r[2], r[4], r[6]}, ei[4] = {i[0], i[2], i[4], i[6]};
+    T orr[4] = {r[1], r[3], r[5], r[7]}, oi[4] = {i[1], i[3], i[5], i[7]};
+    dft4<T, S>(er, ei);
+    dft4<T, S>(orr, oi);
+    // odd half times exp(S 2 pi i k / 8), k = 1, 2, 3
+    {
+        T x = orr[1], y = oi[1];
+        orr[1] = c * (x - (T)S * y);
+        oi[1] = c * ((T)S * x + y);
+    }
+    mul_si<T, S>(orr[2], oi[2]);
+    {
+        T x = orr[3], y = oi[3];
+        orr[3] = c * (-x - (T)S * y);
+        oi[3] = c * ((T)S * x - y);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        r[k] = er[k] + orr[k]; i[k] = ei[k] + oi[k];
+        r[k + 4] = er[k] - orr[k]; i[k + 4] = ei[k] - oi[k];
+    }
+}
+
+template <typename T, int R, int S>
+__device__ __forceinline__ void dft(T* r, T* i)
+{
+    if constexpr (R == 8) dft8<T, S>(r, i);
+    else if constexpr (R == 4) dft4<T, S>(r, i);
+    else dft2<T, S>(r, i);
+}
+
+// Twiddle table entries hold exp(-2 pi i m / L); the inverse uses the conjugate.
+template <typename T, int S>
+__device__ __forceinline__ void twiddle(T& r, T& i, const typename cx<T>::type w)
+{
+    T wr = w.x, wi = (S < 0) ? w.y : -w.y;
+    T nr = r * wr - i * wi;
+    T ni = r * wi + i * wr;
+    r = nr;
+    i = ni;
+}
+
+// LDS index with one pad slot per eight elements (spreads the strided stage
+// writes over all banks).
+__device__ __forceinline__ int lds_pad(int j) { return j + (j >> 3); }
+
+// ---------------------------------------------------------------------------
+// Length-L Stockham FFT, L = 2^LOG2L in [8, 2048], fixed at compile time.
+//
+// Register layout: the thread with index t of Tn = L/8 cooperating threads
+// holds x[t + e*Tn], e < 8, before and after the transform.  Stage 0 has span
+// p = 1 and radix R0 = L / 8^N8 (2, 4 or, when LOG2L is a multiple of 3, 8);
+// every later stage is radix 8.  A stage of radix R and span p computes, for
+// each butterfly i (thread t owns i = t + b*Tn, b < 8/R), the length-R DFT of
+// x[i + j*L/R] * W_L^{j*k*L/(p*R)}, k = i mod p, j < R, and its output q
+// belongs at index (i - k)*R + k + q*p.  For the last stage that index is
+// t + q*Tn, so the result ends in natural order in the registers; earlier
+// stages exchange through LDS.  Only radix-8 stages with p > 1 need twiddles
+// (seven per thread and stage); they are loaded once per kernel.
+// ---------------------------------------------------------------------------
+template <int LOG2L>
+struct FftShape {
+    static constexpr int L = 1 << LOG2L;
+    static constexpr int Tn = L >> 3;
+    static constexpr int N8 = LOG2L / 3;
+    static constexpr int R0 = 1 << (LOG2L - 3 * N8);  // 1: no short first stage
+    static constexpr int NST = N8 + (R0 > 1 ? 1 : 0);
+    static constexpr int NTW = NST - 1;                // stages with twiddles
+    static constexpr int radix(int s) { return (s == 0 && R0 > 1) ? R0 : 8; }
+    static constexpr int log2span(int s)
+    {
+        return s == 0 ? 0 : (R0 > 1 ? (LOG2L - 3 * N8) + 3 * (s - 1) : 3 * s);
+    }
+};
+
+template <typename T, int LOG2L>
+struct Twiddles {
+    typename cx<T>::type w[FftShape<LOG2L>::NTW > 0 ? FftShape<LOG2L>::NTW : 1][7];
+};
+
+// table[m] = exp(-2 pi i m / L); stage s >= 1 needs W_L^{j k L/(8p)}, j = 1..7.
+template <typename T, int LOG2L>
+__device__ __forceinline__ void load_twiddles(Twiddles<T, LOG2L>& tw,
+                                              const typename cx<T>::type* __restrict__ table, int t)
+{
+    typedef FftShape<LOG2L> F;
+#pragma unroll
+    for (int s = 1; s < F::NST; ++s) {
+        const int lp = F::log2span(s);
+        const int k = t & ((1 << lp) - 1);
+        const int shift = LOG2L - 3 - lp;
+#pragma unroll
+        for (int j = 1; j < 8; ++j) tw.w[s - 1][j - 1] = table[(j * k) << shift];
+    }
+}
+
+// Butterflies of a span-1 stage of radix R: butterfly b uses registers b + j*(8/R).
+template <typename T, int R, int S>
+__device__ __forceinline__ void stage_span1(T (&r)[8], T (&im)[8])
+{
+    constexpr int B = 8 / R;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        T ur[R], ui[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) { ur[j] = r[b + j * B]; ui[j] = im[b + j * B]; }
+        dft<T, R, S>(ur, ui);
+#pragma unroll
+        for (int q = 0; q < R; ++q) { r[b + q * B] = ur[q]; im[b + q * B] = ui[q]; }
+    }
+}
+
+// Radix-8 stage with twiddles (one butterfly per thread).
+template <typename T, int S>
+__device__ __forceinline__ void stage_tw8(T (&r)[8], T (&im)[8], const typename cx<T>::type (&w)[7])
+{
+#pragma unroll
+    for (int j = 1; j < 8; ++j) twiddle<T, S>(r[j], im[j], w[j - 1]);
+    dft8<T, S>(r, im);
+}
+
+template <typename T, int S, int NP, int LOG2L, int STAGE>
+__device__ __forceinline__ void fft_stages(T (&r)[NP][8], T (&im)[NP][8], T* lr, T* li, int lplane,
+                                           int lmul, int ladd, int t, const Twiddles<T, LOG2L>& tw,
+                                           bool act)
+{
+    typedef FftShape<LOG2L> F;
+    if constexpr (STAGE < F::NST) {
+        constexpr int R = F::radix(STAGE);
+        constexpr int lp = F::log2span(STAGE);
+        constexpr int p = 1 << lp;
+#pragma unroll
+        for (int pl = 0; pl < NP; ++pl) {
+            if constexpr (STAGE == 0) stage_span1<T, R, S>(r[pl], im[pl]);
+            else stage_tw8<T, S>(r[pl], im[pl], tw.w[STAGE - 1]);
+        }
+        if constexpr (STAGE != F::NST - 1) {
+            __syncthreads();  // earlier readers of the LDS lines are done
+            if (!act) {
+            } else if constexpr (STAGE == 0) {
+                constexpr int B = 8 / R;
+#pragma unroll
+                for (int pl = 0; pl < NP; ++pl)
+#pragma unroll
+                    for (int b = 0; b < B; ++b)
+#pragma unroll
+                        for (int q = 0; q < R; ++q) {
+                            const int a = pl * lplane + lds_pad((t + b * F::Tn) * R + q) * lmul + ladd;
+                            lr[a] = r[pl][b + q * B];
+                            li[a] = im[pl][b + q * B];
+                        }
+            } else {
+                const int k = t & (p - 1);
+                const int base = ((t - k) << 3) + k;
+#pragma unroll
+                for (int pl = 0; pl < NP; ++pl)
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int a = pl * lplane + lds_pad(base + q * p) * lmul + ladd;
+                        lr[a] = r[pl][q];
+                        li[a] = im[pl][q];
+                    }
+            }
+            __syncthreads();
+            if (act) {
+#pragma unroll
+                for (int pl = 0; pl < NP; ++pl)
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int a = pl * lplane + lds_pad(t + e * F::Tn) * lmul + ladd;
+                        r[pl][e] = lr[a];
+                        im[pl][e] = li[a];
+                    }
+            }
+            fft_stages<T, S, NP, LOG2L, STAGE + 1>(r, im, lr, li, lplane, lmul, ladd, t, tw, act);
+        }
+    }
+}
+
+// In-place FFT of NP lines (S = -1 forward, +1 inverse, unscaled).  LDS element
+// j of line pl is at lr/li[pl*lplane + lds_pad(j)*lmul + ladd].  Every thread of
+// the workgroup must call it (it contains barriers); threads with act = false
+// only take part in the barriers and touch no LDS.
+template <typename T, int S, int NP, int LOG2L>
+__device__ __forceinline__ void fft_lines(T (&r)[NP][8], T (&im)[NP][8], T* lr, T* li, int lplane,
+                                          int lmul, int ladd, int t, const Twiddles<T, LOG2L>& tw,
+                                          bool act = true)
+{
+    fft_stages<T, S, NP, LOG2L, 0>(r, im, lr, li, lplane, lmul, ladd, t, tw, act);
+}
+
+// ---------------------------------------------------------------------------
+// Projection onto O(n) (Lemma 1.1): Q = U V^t of the SVD A = U Sigma V^t.
+// Matrices are row-major in registers, a[i*n + j] = A_ij.
+// ---------------------------------------------------------------------------
+
+template <typename T, int n>
+__device__ __forceinline__ T det_n(const T* m)
+{
+    if constexpr (n == 1) {
+        return m[0];
+    } else if constexpr (n == 2) {
+        return m[0] * m[3] - m[1] * m[2];
+    } else if constexpr (n == 3) {
+        return m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+               m[2] * (m[3] * m[7] - m[4] * m[6]);
+    } else {
+        // Laplace expansion along rows 0-1 (2x2 minors against rows 2-3)
+        const T a01 = m[0] * m[5] - m[1] * m[4], a02 = m[0] * m[6] - m[2] * m[4];
+        const T a03 = m[0] * m[7] - m[3] * m[4], a12 = m[1] * m[6] - m[2] * m[5];
+        const T a13 = m[1] * m[7] - m[3] * m[5], a23 = m[2] * m[7] - m[3] * m[6];
+        const T b01 = m[8] * m[13] - m[9] * m[12], b02 = m[8] * m[14] - m[10] * m[12];
+        const T b03 = m[8] * m[15] - m[11] * m[12], b12 = m[9] * m[14] - m[10] * m[13];
+        const T b13 = m[9] * m[15] - m[11] * m[13], b23 = m[10] * m[15] - m[11] * m[14];
+        return a01 * b23 - a02 * b13 + a03 * b12 + a12 * b03 - a13 * b02 + a23 * b01;
+    }
+}
+
+// n = 2 closed form.  The closest rotation [[c,-s],[s,c]] maximises
+// c (a00 + a11) + s (a10 - a01); the closest reflection [[c,s],[s,-c]] maximises
+// c (a00 - a11) + s (a01 + a10).  Lemma 1.1 keeps the sign of det A, with the
+// rotation taken when det A = 0.  Also returns sigma_min for the fallback test.
+template <typename T>
+__device__ __forceinline__ void polar2(const T* a, T* q, int& dsign, T& smin)
+{
+    const T det = a[0] * a[3] - a[1] * a[2];
+    const bool rot = det >= (T)0;
+    const T p = rot ? a[0] + a[3] : a[0] - a[3];
+    const T s = rot ? a[2] - a[1] : a[1] + a[2];
+    const T rr = p * p + s * s;
+    if (rr == (T)0) {  // only A = 0 reaches this: take the identity
+        q[0] = 1; q[1] = 0; q[2] = 0; q[3] = 1;
+        dsign = 1;
+        smin = 0;
+        return;
+    }
+    const T inv = num<T>::rsq(rr);
+    const T c = p * inv, sn = s * inv;
+    q[0] = c;
+    q[1] = rot ? -sn : sn;
+    q[2] = sn;
+    q[3] = rot ? c : -c;
+    dsign = rot ? 1 : -1;
+    const T f2 = a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + a[3] * a[3];
+    const T ad = det < (T)0 ? -det : det;
+    const T lo = f2 - 2 * ad;
+    const T smax = (T)0.5 * (num<T>::sqrt_(f2 + 2 * ad) + num<T>::sqrt_(lo > (T)0 ? lo : (T)0));
+    smin = smax > (T)0 ? ad * num<T>::rcp(smax) : (T)0;
+}
+
+// One-sided (Hestenes) Jacobi: rotate pairs of columns of W = A until they are
+// mutually orthogonal (to working precision), accumulating the rotations in V;
+// then sigma_j = |w_j|, U = W Sigma^{-1} and Q = U V^t.
+template <typename T, int n>
+__device__ __forceinline__ void polar_jacobi(const T* a, T* q, int& dsign, T& smin)
+{
+    T W[n][n], V[n][n];
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            W[i][j] = a[i * n + j];
+            V[i][j] = (i == j) ? (T)1 : (T)0;
+        }
+#pragma unroll 1
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        bool rotated = false;
+#pragma unroll
+        for (int p = 0; p < n - 1; ++p) {
+#pragma unroll
+            for (int r = p + 1; r < n; ++r) {
+                T al = 0, be = 0, ga = 0;
+#pragma unroll
+                for (int i = 0; i < n; ++i) {
+                    al += W[i][p] * W[i][p];
+                    be += W[i][r] * W[i][r];
+                    ga += W[i][p] * W[i][r];
+                }
+                if (ga * ga > num<T>::jtol2 * (al * be)) {
+                    rotated = true;
+                    const T zeta = (be - al) * num<T>::rcp(2 * ga);
+                    const T az = zeta < (T)0 ? -zeta : zeta;
+                    const T iz = num<T>::rcp(az);
+                    const T hyp = az > (T)1 ? az * num<T>::sqrt_((T)1 + iz * iz)
+                                            : num<T>::sqrt_((T)1 + az * az);
+                    T tt = num<T>::rcp(az + hyp);
+                    if (zeta < (T)0) tt = -tt;
+                    const T c = num<T>::rsq((T)1 + tt * tt);
+                    const T s = c * tt;
+#pragma unroll
+                    for (int i = 0; i < n; ++i) {
+                        const T wp = W[i][p], wr = W[i][r];
+                        W[i][p] = c * wp - s * wr;
+                        W[i][r] = s * wp + c * wr;
+                        const T vp = V[i][p], vr = V[i][r];
+                        V[i][p] = c * vp - s * vr;
+                        V[i][r] = s * vp + c * vr;
+                    }
+                }
+            }
+        }
+        if (!rotated) break;
+    }
+    T ss[n], sg[n];
+    T smax = 0;
+    smin = 0;
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+        T v = 0;
+#pragma unroll
+        for (int i = 0; i < n; ++i) v += W[i][j] * W[i][j];
+        ss[j] = v;
+        sg[j] = num<T>::sqrt_(v);
+        smax = sg[j] > smax ? sg[j] : smax;
+        smin = (j == 0 || sg[j] < smin) ? sg[j] : smin;
+    }
+    if (!(smax > (T)0)) {  // zero matrix (or NaN): identity
+#pragma unroll
+        for (int i = 0; i < n * n; ++i) q[i] = (i % (n + 1) == 0) ? (T)1 : (T)0;
+        dsign = 1;
+        return;
+    }
+    const T thr = (T)n * num<T>::eps * smax;
+    bool filled[n];
+    bool anyzero = false;
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+        filled[j] = sg[j] > thr;
+        anyzero = anyzero || !filled[j];
+        const T inv = filled[j] ? num<T>::rsq(ss[j]) : (T)0;
+#pragma unroll
+        for (int i = 0; i < n; ++i) W[i][j] *= inv;  // W becomes U
+    }
+    int lastz = -1;
+    if (anyzero) {
+        // Singular input: complete U by Gram-Schmidt of the unit vector with the
+        // largest residual against the columns already present.
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            if (filled[j]) continue;
+            T best[n];
+            T bestn = (T)-1;
+#pragma unroll
+            for (int e = 0; e < n; ++e) {
+                T rv[n];
+#pragma unroll
+                for (int i = 0; i < n; ++i) rv[i] = (i == e) ? (T)1 : (T)0;
+#pragma unroll
+                for (int k = 0; k < n; ++k) {
+                    if (!filled[k]) continue;
+                    const T dot = W[e][k];
+#pragma unroll
+                    for (int i = 0; i < n; ++i) rv[i] -= dot * W[i][k];
+                }
+                T nn = 0;
+#pragma unroll
+                for (int i = 0; i < n; ++i) nn += rv[i] * rv[i];
+                if (nn > bestn) {
+                    bestn = nn;
+#pragma unroll
+                    for (int i = 0; i < n; ++i) best[i] = rv[i];
+                }
+            }
+            const T inv = num<T>::rsq(bestn);
+#pragma unroll
+            for (int i = 0; i < n; ++i) W[i][j] = best[i] * inv;
+            filled[j] = true;
+            lastz = j;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+            T v = 0;
+#pragma unroll
+            for (int j = 0; j < n; ++j) v += W[i][j] * V[k][j];
+            q[i * n + k] = v;
+        }
+    T dq = det_n<T, n>(q);
+    if (lastz >= 0 && dq < (T)0) {
+        // the completed direction's sign is free: choose det Q = +1
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            if (j != lastz) continue;
+#pragma unroll
+            for (int i = 0; i < n; ++i) W[i][j] = -W[i][j];
+        }
+#pragma unroll
+        for (int i = 0; i < n; ++i)
+#pragma unroll
+            for (int k = 0; k < n; ++k) {
+                T v = 0;
+#pragma unroll
+                for (int j = 0; j < n; ++j) v += W[i][j] * V[k][j];
+                q[i * n + k] = v;
+            }
+        dq = -dq;
+    }
+    dsign = dq >= (T)0 ? 1 : -1;
+}
+
+// Closest orthogonal matrix of a (n*n values).  Returns sgn det Q and the
+// smallest singular value of a (used by the double-precision fallback test).
+template <typename T, int n>
+__device__ __forceinline__ void project_point(const T* a, T* q, int& dsign, T& smin)
+{
+    if constexpr (n == 1) {
+        const bool pos = a[0] >= (T)0;  // sgn(0) = +1
+        q[0] = pos ? (T)1 : (T)-1;
+        dsign = pos ? 1 : -1;
+        smin = a[0] < (T)0 ? -a[0] : a[0];
+    } else if constexpr (n == 2) {
+        polar2<T>(a, q, dsign, smin);
+    } else {
+        polar_jacobi<T, n>(a, q, dsign, smin);
+    }
+}
+
+// True when every one of the m values is finite.
+template <typename T, int m>
+__device__ __forceinline__ bool all_finite(const T* a)
+{
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < m; ++i) ok = ok && (a[i] - a[i] == (T)0);
+    return ok;
+}
+
+}  // namespace mbo

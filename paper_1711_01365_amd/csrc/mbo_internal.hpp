@@ -1,0 +1,115 @@
+// Internal interface between the host runtime (mbo_api.cpp) and the HIP
+// kernels (mbo_kernels.hpp and the mbo_*.hip units).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mbo {
+
+// Runtime flags of the row pass.
+enum RowFlags : int {
+    RF_LOAD_REAL = 1 << 0,   // read the real field A instead of the spectra Z
+    RF_INVERSE = 1 << 1,     // inverse row FFT after loading spectra
+    RF_PROJECT = 1 << 2,     // per-point projection (Algorithm 1, step 2)
+    RF_FORWARD = 1 << 3,     // forward row FFT, then store the spectra Z
+    RF_STORE_REAL = 1 << 4,  // store the (projected) real values into A / A_out
+    RF_TRACK = 1 << 5,       // read the previous iterate from A: max |change|
+    RF_SIGN = 1 << 6,        // compare det signs with sgn[] (flips) and update it
+    RF_SIGN_INIT = 1 << 7,   // write sgn det of the loaded real field into sgn[]
+    RF_FALLBACK = 1 << 8,    // float plan: re-project small-sigma points in double
+    RF_CHECK_STOP = 1 << 9,  // return when this field already stopped
+};
+
+struct RowArgs {
+    int L, log2L;            // row length (last grid axis) and its log2
+    int rpw;                 // rows per workgroup
+    int lds_plane;           // LDS elements per line (lds_pad(L - 1) + 1)
+    int64_t rows;            // rows per field plane = npts / L
+    int64_t npts;            // grid points per field
+    const void* tw;          // twiddles exp(-2 pi i m / L), m < L
+    void* Z;                 // spectra [batch][PL][npts] complex
+    const void* Ain;         // real field read by RF_LOAD_REAL [batch][n*n][npts]
+    void* Aout;              // real field written by RF_STORE_REAL / read by RF_TRACK
+    int8_t* sgn;             // det signs [batch][npts]
+    unsigned long long* flips;       // [batch][K] per-iteration counters
+    unsigned long long* fallbacks;   // [batch][K]
+    unsigned long long* nonfinite;   // [batch][K]
+    unsigned long long* delta_bits;  // [batch][K] max |A_s - A_{s-1}| (double bits)
+    int* stop_iter;          // [batch]
+    int iter;                // 1-based iteration index (log slot iter-1)
+    int K;                   // log stride
+    int flags;
+    double sigma_fb;         // fallback threshold
+};
+
+// Modes of the strided-axis pass.
+enum ColMode : int { CM_FORWARD = 0, CM_INVERSE = 1, CM_HEAT = 2, CM_ENERGY = 3 };
+
+struct ColArgs {
+    int L, log2L;            // transform length along the axis
+    int TX;                  // inner indices per workgroup
+    int lds_col;             // lds_pad(L - 1) + 1
+    int64_t S;               // element stride along the axis (= inner extent)
+    int64_t tiles;           // S / TX
+    int64_t field_elems;     // complex elements per field (PL * npts)
+    const void* tw;
+    void* Z;
+    const void* lam_row;     // heat symbol factor of this axis [L] (incl. 1/L)
+    const void* lam_inner;   // product of the factors of the faster axes [S]
+    double* epart;           // energy partials [batch][K+1][nwg]
+    int nwg;                 // workgroups per field (partial slots)
+    int slot;                // energy slot (iteration - 1); -1: use stop_iter
+    int iter;                // 1-based iteration (CM_HEAT inside mbo_iterate), 0 otherwise
+    int K;
+    int* stop_iter;          // nullable
+    const unsigned long long* delta_bits;  // nullable
+    double tol;
+};
+
+struct ProjArgs {
+    int64_t npts;
+    const void* A;
+    void* Q;
+    int8_t* dsign;           // nullable
+    unsigned long long* nonfinite;
+    unsigned long long* fallbacks;
+    int fallback;
+    double sigma_fb;
+};
+
+struct ReduceArgs {
+    const double* epart;     // [batch][K+1][nwg]
+    int nwg;
+    int K;
+    int batch;
+    int n;
+    int64_t npts;
+    double tau;
+    const int* stop_iter;    // nullable: all slots 0..K
+    double* energy;          // [batch][K+1]
+};
+
+// prec: 0 = double, 1 = float.  log2L: log2 of the transform length.  With
+// prepare = true a launcher only raises the kernel's dynamic-LDS limit.
+hipError_t launch_row(int prec, int n, int log2L, const RowArgs& a, dim3 grid, dim3 block,
+                      size_t lds, hipStream_t st, bool prepare = false);
+hipError_t launch_col(int prec, int mode, int log2L, const ColArgs& a, dim3 grid, dim3 block,
+                      size_t lds, hipStream_t st, bool prepare = false);
+hipError_t launch_project(int prec, int n, const ProjArgs& a, int batch, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v,
+                           hipStream_t st);
+hipError_t launch_fill_i32(int* p, int64_t count, int v, hipStream_t st);
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
+
+// per-translation-unit launchers behind launch_row / launch_col
+hipError_t launch_row_f32(int n, int log2L, const RowArgs& a, dim3 g, dim3 b, size_t lds,
+                          hipStream_t st, bool prepare);
+hipError_t launch_row_f64(int n, int log2L, const RowArgs& a, dim3 g, dim3 b, size_t lds,
+                          hipStream_t st, bool prepare);
+hipError_t launch_col_f32(int mode, int log2L, const ColArgs& a, dim3 g, dim3 b, size_t lds,
+                          hipStream_t st, bool prepare);
+hipError_t launch_col_f64(int mode, int log2L, const ColArgs& a, dim3 g, dim3 b, size_t lds,
+                          hipStream_t st, bool prepare);
+
+}  // namespace mbo

@@ -1,0 +1,375 @@
+// HIP kernel templates of the generalized MBO iteration (Osting & Wang,
+// arXiv:1711.01365) for gfx950.  Instantiated by the mbo_*.hip translation units.
+//
+//   row_pass   one workgroup owns whole rows (the contiguous grid axis) of all
+//              ceil(n^2/2) packed complex planes of a field: inverse row FFT,
+//              per-point projection onto O(n) (Lemma 1.1, Algorithm 1 step 2)
+//              with det-sign / fallback / change diagnostics, forward row FFT.
+//              Two real entry planes travel as one complex plane z = A_p + i A_q;
+//              this is exact because the heat symbol is real and even in k.
+//   col_pass   FFT along a strided axis for a tile of TX neighbouring inner
+//              indices (coalesced TX-wide segments).  CM_HEAT fuses forward
+//              FFT -> heat symbol exp(-4 pi^2 tau |k|^2) (Section 5.1) and the
+//              Lyapunov partial sum_m symbol |Z|^2 (Section 4) -> inverse FFT.
+#pragma once
+
+#include "mbo_device.hpp"
+#include "mbo_internal.hpp"
+
+namespace mbo {
+
+// ---------------------------------------------------------------------------
+// Deterministic workgroup reductions (result valid in thread 0).  blockDim.x is
+// a power of two; waves reduce by xor-shuffles in a fixed pattern, then wave
+// totals (or, for workgroups smaller than a wave, all values) by an LDS tree.
+// ---------------------------------------------------------------------------
+struct OpSum {
+    template <typename V> __device__ static V apply(V a, V b) { return a + b; }
+};
+struct OpMax {
+    template <typename V> __device__ static V apply(V a, V b) { return a > b ? a : b; }
+};
+
+template <typename Op, typename V>
+__device__ V block_reduce(V v, V* sh /* >= 64 entries */)
+{
+    const int tid = threadIdx.x;
+    const int nt = blockDim.x;
+    if (nt >= 64) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v = Op::apply(v, (V)__shfl_xor(v, o, 64));
+        const int nw = nt >> 6;
+        __syncthreads();
+        if ((tid & 63) == 0) sh[tid >> 6] = v;
+        __syncthreads();
+        if (tid == 0) {
+            V s = sh[0];
+            for (int w = 1; w < nw; ++w) s = Op::apply(s, sh[w]);
+            v = s;
+        }
+        return v;
+    }
+    __syncthreads();
+    sh[tid] = v;
+    __syncthreads();
+    for (int h = nt >> 1; h > 0; h >>= 1) {
+        if (tid < h) sh[tid] = Op::apply(sh[tid], sh[tid + h]);
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// ---------------------------------------------------------------------------
+// Row pass.  A workgroup owns rpw rows (contiguous grid lines of length L) of
+// every packed plane: rpw * PL "lines".  Phase 1: groups of L/8 threads load
+// one line each (a round at a time), inverse-FFT it, and leave it in natural
+// order in LDS (line j at lr/li[j * lds_plane + lds_pad(x)]).  Phase 2: every
+// thread takes points of the rows (one point per thread and pass over the
+// rpw*L points) for the projection and its diagnostics.  Phase 3: the groups
+// forward-FFT the lines from LDS and store the spectra.  The projection, which
+// dominates the arithmetic, thus runs one point per thread on all threads.
+// ---------------------------------------------------------------------------
+template <typename T, int n, int LOG2L>
+__global__ void __launch_bounds__(512) row_pass(const RowArgs a)
+{
+    constexpr int NN = n * n;
+    constexpr int PL = (NN + 1) / 2;
+    typedef FftShape<LOG2L> F;
+    constexpr int L = F::L;
+    constexpr int Tn = F::Tn;
+    typedef typename cx<T>::type C;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ unsigned long long red_u[64];
+    __shared__ double red_d[64];
+
+    const int flags = a.flags;
+    const int b = blockIdx.y;
+    if ((flags & RF_CHECK_STOP) && a.stop_iter[b] < a.iter) return;  // uniform per workgroup
+
+    const int tid = threadIdx.x;
+    const int NT = blockDim.x;
+    const int G = NT >> (LOG2L - 3);  // line groups
+    const int g = tid >> (LOG2L - 3);
+    const int t = tid & (Tn - 1);
+    const int rpw = a.rpw;
+    const int nlines = rpw * PL;
+    const int rounds = (nlines + G - 1) / G;
+    const int64_t row0 = (int64_t)blockIdx.x * rpw;
+    const int64_t npts = a.npts;
+    const int lp = a.lds_plane;
+    T* lr = reinterpret_cast<T*>(smem_raw);
+    T* li = lr + (size_t)nlines * lp;
+
+    Twiddles<T, LOG2L> tw;
+    if (flags & (RF_INVERSE | RF_FORWARD))
+        load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
+
+    // ---- phase 1: lines into LDS (natural order), inverse FFT on the way
+    for (int rd = 0; rd < rounds; ++rd) {
+        const int j = rd * G + g;
+        const int rloc = j / PL, pl = j - (j / PL) * PL;
+        const bool act = j < nlines;
+        const bool ld = act && row0 + rloc < a.rows;
+        const int64_t x0 = (row0 + rloc) * L + t;
+        T r[1][8], im[1][8];
+        if (flags & RF_LOAD_REAL) {
+            const T* A = reinterpret_cast<const T*>(a.Ain) + (size_t)b * NN * npts;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int64_t x = x0 + (int64_t)e * Tn;
+                r[0][e] = ld ? A[(int64_t)(2 * pl) * npts + x] : (T)0;
+                im[0][e] = (ld && 2 * pl + 1 < NN) ? A[(int64_t)(2 * pl + 1) * npts + x] : (T)0;
+            }
+        } else {
+            const C* Z = reinterpret_cast<const C*>(a.Z) + ((size_t)b * PL + pl) * npts;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                C v;
+                if (ld) v = Z[x0 + (int64_t)e * Tn];
+                else { v.x = 0; v.y = 0; }
+                r[0][e] = v.x;
+                im[0][e] = v.y;
+            }
+        }
+        T* lrj = lr + (size_t)(act ? j : 0) * lp;
+        T* lij = li + (size_t)(act ? j : 0) * lp;
+        if (flags & RF_INVERSE) {
+            fft_lines<T, +1, 1, LOG2L>(r, im, lrj, lij, 0, 1, 0, t, tw, act);
+            __syncthreads();  // the group has read its last exchange
+        }
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                lrj[lds_pad(t + e * Tn)] = r[0][e];
+                lij[lds_pad(t + e * Tn)] = im[0][e];
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 2: per-point work, one point per thread and pass
+    unsigned long long nflip = 0, nfb = 0, nbad = 0;
+    double dmax = 0.0;
+    if (flags & (RF_PROJECT | RF_SIGN_INIT | RF_STORE_REAL)) {
+        T* Aout = reinterpret_cast<T*>(a.Aout) + (size_t)b * NN * npts;
+        int8_t* sgn = a.sgn + (size_t)b * npts;
+        const int npass = (rpw * L) / NT;
+#pragma unroll 1
+        for (int pp = 0; pp < npass; ++pp) {
+            const int idx = pp * NT + tid;
+            const int rloc = idx >> LOG2L;
+            const int xc = idx & (L - 1);
+            const int64_t row = row0 + rloc;
+            if (row >= a.rows) continue;
+            const int64_t x = row * L + xc;
+            const int jx = lds_pad(xc);
+            T* lrr = lr + (size_t)rloc * PL * lp + jx;
+            T* lir = li + (size_t)rloc * PL * lp + jx;
+            T av[NN];
+#pragma unroll
+            for (int k = 0; k < NN; ++k) av[k] = (k & 1) ? lir[(k >> 1) * lp] : lrr[(k >> 1) * lp];
+            if (flags & RF_SIGN_INIT) sgn[x] = det_n<T, n>(av) >= (T)0 ? 1 : -1;
+            if (flags & RF_PROJECT) {
+                nbad += all_finite<T, NN>(av) ? 0ull : 1ull;
+                T qv[NN];
+                int ds;
+                T smin;
+                project_point<T, n>(av, qv, ds, smin);
+                if constexpr (sizeof(T) == 4 && n >= 2) {
+                    if ((flags & RF_FALLBACK) && (double)smin < a.sigma_fb) {
+                        double ad[NN], qd[NN], smd;
+#pragma unroll
+                        for (int k = 0; k < NN; ++k) ad[k] = (double)av[k];
+                        project_point<double, n>(ad, qd, ds, smd);
+#pragma unroll
+                        for (int k = 0; k < NN; ++k) qv[k] = (T)qd[k];
+                        ++nfb;
+                    }
+                }
+                if (flags & RF_SIGN) {
+                    nflip += (sgn[x] != (int8_t)ds) ? 1ull : 0ull;
+                    sgn[x] = (int8_t)ds;
+                }
+                if (flags & RF_TRACK) {
+                    // max |A_s - A_{s-1}|, A_{s-1} read from the caller's field
+#pragma unroll
+                    for (int k = 0; k < NN; ++k) {
+                        const double dv = fabs((double)qv[k] - (double)Aout[(int64_t)k * npts + x]);
+                        dmax = dv > dmax ? dv : dmax;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < NN; ++k) {
+                    av[k] = qv[k];
+                    if (k & 1) lir[(k >> 1) * lp] = qv[k];
+                    else lrr[(k >> 1) * lp] = qv[k];
+                }
+                if (NN & 1) lir[(NN >> 1) * lp] = (T)0;
+            }
+            if (flags & RF_STORE_REAL) {
+#pragma unroll
+                for (int k = 0; k < NN; ++k) Aout[(int64_t)k * npts + x] = av[k];
+            }
+        }
+    }
+
+    // ---- phase 3: forward FFT of the lines, store the spectra
+    if (flags & RF_FORWARD) {
+        __syncthreads();
+        for (int rd = 0; rd < rounds; ++rd) {
+            const int j = rd * G + g;
+            const int rloc = j / PL, pl = j - (j / PL) * PL;
+            const bool act = j < nlines;
+            const bool st = act && row0 + rloc < a.rows;
+            T* lrj = lr + (size_t)(act ? j : 0) * lp;
+            T* lij = li + (size_t)(act ? j : 0) * lp;
+            T r[1][8], im[1][8];
+            if (act) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    r[0][e] = lrj[lds_pad(t + e * Tn)];
+                    im[0][e] = lij[lds_pad(t + e * Tn)];
+                }
+            }
+            fft_lines<T, -1, 1, LOG2L>(r, im, lrj, lij, 0, 1, 0, t, tw, act);
+            if (st) {
+                C* Z = reinterpret_cast<C*>(a.Z) + ((size_t)b * PL + pl) * npts;
+                const int64_t x0 = (row0 + rloc) * L + t;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    C v;
+                    v.x = r[0][e];
+                    v.y = im[0][e];
+                    Z[x0 + (int64_t)e * Tn] = v;
+                }
+            }
+        }
+    }
+
+    if (flags & RF_PROJECT) {
+        const int64_t slot = (int64_t)b * a.K + (a.iter - 1);
+        nflip = block_reduce<OpSum>(nflip, red_u);
+        if (tid == 0 && nflip && a.flips) atomicAdd(a.flips + slot, nflip);
+        nfb = block_reduce<OpSum>(nfb, red_u);
+        if (tid == 0 && nfb && a.fallbacks) atomicAdd(a.fallbacks + slot, nfb);
+        nbad = block_reduce<OpSum>(nbad, red_u);
+        if (tid == 0 && nbad && a.nonfinite) atomicAdd(a.nonfinite + slot, nbad);
+        if (flags & RF_TRACK) {
+            dmax = block_reduce<OpMax>(dmax, red_d);
+            // non-negative doubles order like their bit patterns
+            if (tid == 0 && a.delta_bits)
+                atomicMax(a.delta_bits + slot, (unsigned long long)__double_as_longlong(dmax));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Strided-axis pass
+// ---------------------------------------------------------------------------
+template <typename T, int MODE, int LOG2L>
+__global__ void __launch_bounds__(512) col_pass(const ColArgs a)
+{
+    typedef typename cx<T>::type C;
+    typedef FftShape<LOG2L> F;
+    constexpr int Tn = F::Tn;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red_d[64];
+
+    const int b = blockIdx.y;
+    if (a.iter > 0 && a.stop_iter) {
+        if (a.stop_iter[b] < a.iter) return;
+        if (a.delta_bits && a.tol > 0.0 && a.iter >= 2) {
+            // the first pass of iteration s stops field b when s-1 changed it by <= tol
+            const double dprev =
+                __longlong_as_double((long long)a.delta_bits[(int64_t)b * a.K + (a.iter - 2)]);
+            if (dprev <= a.tol) {
+                if (blockIdx.x == 0 && threadIdx.x == 0) atomicMin(a.stop_iter + b, a.iter - 1);
+                return;
+            }
+        }
+    }
+
+    const int TX = a.TX;
+    const int tid = threadIdx.x;
+    const int tx = tid & (TX - 1);
+    const int t = tid / TX;
+    // XCD-aware tile order: workgroups are dealt round-robin to the eight XCDs,
+    // each with its own L2.  Give every XCD a contiguous run of tiles so that the
+    // tiles sharing a 128-byte line (TX * sizeof(C) < 128) meet in one L2.
+    const int64_t nwgx = gridDim.x;
+    const int64_t wg = (nwgx & 7) ? (int64_t)blockIdx.x
+                                  : (int64_t)(blockIdx.x & 7) * (nwgx >> 3) + (blockIdx.x >> 3);
+    const int64_t o = wg / a.tiles;
+    const int64_t inner = (wg - o * a.tiles) * TX + tx;
+    const int64_t S = a.S;
+    C* Z = reinterpret_cast<C*>(a.Z) + (size_t)b * a.field_elems + o * (int64_t)F::L * S + inner;
+    T* lr = reinterpret_cast<T*>(smem_raw);
+    T* li = lr + (size_t)a.lds_col * TX;
+
+    T r[1][8], im[1][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const C v = Z[(int64_t)(t + e * Tn) * S];
+        r[0][e] = v.x;
+        im[0][e] = v.y;
+    }
+    Twiddles<T, LOG2L> tw;
+    load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
+
+    if (MODE == CM_INVERSE)
+        fft_lines<T, +1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
+    else
+        fft_lines<T, -1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
+
+    if (MODE == CM_HEAT || MODE == CM_ENERGY) {
+        const T* lrow = reinterpret_cast<const T*>(a.lam_row);
+        const T lin = reinterpret_cast<const T*>(a.lam_inner)[inner];
+        double acc = 0.0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const T lam = lrow[t + e * Tn] * lin;
+            if (a.epart)
+                acc += (double)lam * ((double)r[0][e] * (double)r[0][e] +
+                                      (double)im[0][e] * (double)im[0][e]);
+            if (MODE == CM_HEAT) {
+                r[0][e] *= lam;
+                im[0][e] *= lam;
+            }
+        }
+        if (a.epart) {
+            acc = block_reduce<OpSum>(acc, red_d);
+            if (tid == 0) {
+                const int slot = a.slot >= 0 ? a.slot : a.stop_iter[b];
+                a.epart[((int64_t)b * (a.K + 1) + slot) * a.nwg + wg] = acc;
+            }
+        }
+    }
+    if (MODE == CM_HEAT) fft_lines<T, +1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
+
+    if (MODE != CM_ENERGY) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            C v;
+            v.x = r[0][e];
+            v.y = im[0][e];
+            Z[(int64_t)(t + e * Tn) * S] = v;
+        }
+    }
+}
+
+// Launch helpers used by the translation units: one switch over log2(L).
+#define MBO_LOG2L_SWITCH(lg, CASE)                                                             \
+    switch (lg) {                                                                              \
+    case 3: CASE(3); break;                                                                    \
+    case 4: CASE(4); break;                                                                    \
+    case 5: CASE(5); break;                                                                    \
+    case 6: CASE(6); break;                                                                    \
+    case 7: CASE(7); break;                                                                    \
+    case 8: CASE(8); break;                                                                    \
+    case 9: CASE(9); break;                                                                    \
+    case 10: CASE(10); break;                                                                  \
+    case 11: CASE(11); break;                                                                  \
+    default: return hipErrorInvalidValue;                                                      \
+    }
+
+}  // namespace mbo

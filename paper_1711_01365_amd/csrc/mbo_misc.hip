@@ -1,0 +1,139 @@
+// Pointwise and utility kernels of libmbo (gfx950): standalone projection
+// (Lemma 1.1), graph-capture-safe fills, the fixed-order energy reduction, and
+// the dispatch of the row / strided-axis passes to their translation units.
+#include "mbo_kernels.hpp"
+
+namespace mbo {
+
+// ---------------------------------------------------------------------------
+// Standalone projection, one point per thread
+// ---------------------------------------------------------------------------
+template <typename T, int n>
+__global__ void __launch_bounds__(256) project_kernel(const ProjArgs a)
+{
+    constexpr int NN = n * n;
+    const int b = blockIdx.y;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ unsigned long long red_u[64];
+    unsigned long long bad = 0, fb = 0;
+    if (p < a.npts) {
+        const T* A = reinterpret_cast<const T*>(a.A) + (size_t)b * NN * a.npts;
+        T* Q = reinterpret_cast<T*>(a.Q) + (size_t)b * NN * a.npts;
+        T av[NN], qv[NN];
+#pragma unroll
+        for (int k = 0; k < NN; ++k) av[k] = A[(int64_t)k * a.npts + p];
+        bad = !all_finite<T, NN>(av);
+        int ds;
+        T smin;
+        project_point<T, n>(av, qv, ds, smin);
+        if constexpr (sizeof(T) == 4 && n >= 2) {
+            if (a.fallback && (double)smin < a.sigma_fb) {
+                double ad[NN], qd[NN], smd;
+#pragma unroll
+                for (int k = 0; k < NN; ++k) ad[k] = (double)av[k];
+                project_point<double, n>(ad, qd, ds, smd);
+#pragma unroll
+                for (int k = 0; k < NN; ++k) qv[k] = (T)qd[k];
+                fb = 1;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NN; ++k) Q[(int64_t)k * a.npts + p] = qv[k];
+        if (a.dsign) a.dsign[(size_t)b * a.npts + p] = (int8_t)ds;
+    }
+    bad = block_reduce<OpSum>(bad, red_u);
+    if (threadIdx.x == 0 && bad) atomicAdd(a.nonfinite, bad);
+    fb = block_reduce<OpSum>(fb, red_u);
+    if (threadIdx.x == 0 && fb && a.fallbacks) atomicAdd(a.fallbacks, fb);
+}
+
+// ---------------------------------------------------------------------------
+// Small utility kernels (graph-capture safe replacements for memset)
+// ---------------------------------------------------------------------------
+__global__ void fill_u64(unsigned long long* p, int64_t count, unsigned long long v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+__global__ void fill_i32(int* p, int64_t count, int v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+// E(A_s) = (1/tau) (n - (1/npts) sum_wg partial), the partials being
+// sum_m symbol(m)/npts |Z(m)|^2 over each workgroup's modes.
+__global__ void reduce_energy(const ReduceArgs a)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)a.batch * (a.K + 1);
+    if (idx >= total) return;
+    const int b = (int)(idx / (a.K + 1));
+    const int s = (int)(idx - (int64_t)b * (a.K + 1));
+    if (a.stop_iter && s > a.stop_iter[b]) return;
+    const double* p = a.epart + idx * a.nwg;
+    double sum = 0.0;
+    for (int i = 0; i < a.nwg; ++i) sum += p[i];
+    a.energy[idx] = ((double)a.n - sum / (double)a.npts) / a.tau;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_row(int prec, int n, int log2L, const RowArgs& a, dim3 g, dim3 bl, size_t lds,
+                      hipStream_t st, bool prepare)
+{
+    return prec == 0 ? launch_row_f64(n, log2L, a, g, bl, lds, st, prepare)
+                     : launch_row_f32(n, log2L, a, g, bl, lds, st, prepare);
+}
+
+hipError_t launch_col(int prec, int mode, int log2L, const ColArgs& a, dim3 g, dim3 bl, size_t lds,
+                      hipStream_t st, bool prepare)
+{
+    return prec == 0 ? launch_col_f64(mode, log2L, a, g, bl, lds, st, prepare)
+                     : launch_col_f32(mode, log2L, a, g, bl, lds, st, prepare);
+}
+
+template <typename T>
+static hipError_t proj_dispatch(int n, const ProjArgs& a, int batch, hipStream_t st)
+{
+    dim3 bl(256);
+    dim3 g((unsigned)((a.npts + 255) / 256), (unsigned)batch);
+    switch (n) {
+    case 1: hipLaunchKernelGGL((project_kernel<T, 1>), g, bl, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((project_kernel<T, 2>), g, bl, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((project_kernel<T, 3>), g, bl, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((project_kernel<T, 4>), g, bl, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_project(int prec, int n, const ProjArgs& a, int batch, hipStream_t st)
+{
+    return prec == 0 ? proj_dispatch<double>(n, a, batch, st) : proj_dispatch<float>(n, a, batch, st);
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int* p, int64_t count, int v, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st)
+{
+    const int64_t total = (int64_t)a.batch * (a.K + 1);
+    hipLaunchKernelGGL(reduce_energy, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace mbo

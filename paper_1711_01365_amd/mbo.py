@@ -1,0 +1,194 @@
+"""ctypes binding of libmbo (include/mbo.h): same call names, argument marshalling only.
+
+Every step of the method runs in the HIP kernels of ``libmbo.so``; PyTorch only
+provides device memory and the current stream.  There is no fallback: if the
+library is missing or no GPU is present the calls raise.
+
+Field tensors are ``(batch, n, n, *grid)`` (or ``(n, n, *grid)`` for batch 1),
+contiguous, on the plan's device, float64 for ``F64`` plans and float32
+otherwise -- the entry-planar layout of the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmbo.so")
+
+F64, F32, F32_F64FALLBACK = 0, 1, 2
+_STATUS = {0: "MBO_OK", 1: "MBO_ERR_INVALID_ARG", 2: "MBO_ERR_UNSUPPORTED", 3: "MBO_ERR_ALLOC",
+           4: "MBO_ERR_HIP", 5: "MBO_ERR_NONFINITE"}
+
+_lib = None
+
+EXPORTS = ("mbo_plan", "mbo_plan_destroy", "mbo_plan_set_tau", "mbo_plan_set_stream",
+           "mbo_diffuse", "mbo_project", "mbo_iterate", "mbo_energy", "mbo_status_string",
+           "mbo_last_error")
+
+
+class MboError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+def load(path: str = LIB_PATH):
+    """Load libmbo.so and declare the C signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libmbo.so is not built (run `python -m paper_1711_01365_amd.build`)")
+    lib = ctypes.CDLL(path)
+    vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
+    dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+    lib.mbo_plan.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int64,
+                             ctypes.c_double, ctypes.c_int, ctypes.c_double, vp]
+    lib.mbo_plan_destroy.argtypes = [vp]
+    lib.mbo_plan_set_tau.argtypes = [vp, ctypes.c_double]
+    lib.mbo_plan_set_stream.argtypes = [vp, vp]
+    lib.mbo_diffuse.argtypes = [vp, vp, vp]
+    lib.mbo_project.argtypes = [vp, vp, vp, vp]
+    lib.mbo_iterate.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, ip, dp, i64p, dp, i64p]
+    lib.mbo_energy.argtypes = [vp, vp, dp]
+    for f in EXPORTS[:8]:
+        getattr(lib, f).restype = ctypes.c_int
+    lib.mbo_status_string.argtypes = [ctypes.c_int]
+    lib.mbo_status_string.restype = ctypes.c_char_p
+    lib.mbo_last_error.argtypes = [vp]
+    lib.mbo_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, handle) -> None:
+    if rc != 0:
+        msg = _lib.mbo_last_error(handle)
+        raise MboError(rc, msg.decode() if msg else "")
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Plan:
+    """Owns an ``mbo_plan_t``.  Mirrors the C entry points one to one."""
+
+    def __init__(self, grid: Sequence[int], n: int, tau: float, precision: int = F64,
+                 batch: int = 1, sigma_fallback: float = 1e-3, stream=None):
+        lib = load()
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: libmbo runs on the GPU only")
+        self.grid = tuple(int(g) for g in grid)
+        self.n, self.batch, self.precision = int(n), int(batch), int(precision)
+        self.tau = float(tau)
+        self.dtype = torch.float64 if precision == F64 else torch.float32
+        N = (ctypes.c_int64 * len(self.grid))(*self.grid)
+        h = ctypes.c_void_p()
+        rc = lib.mbo_plan(ctypes.byref(h), len(self.grid), N, self.n, self.batch, self.tau,
+                          self.precision, float(sigma_fallback), _stream_ptr(stream))
+        _check(rc, None)
+        self._h = h
+        self._lib = lib
+
+    # -- helpers -------------------------------------------------------------
+    @property
+    def shape(self):
+        return (self.batch, self.n, self.n) + self.grid
+
+    def _field(self, A, name="A"):
+        import torch
+        if not isinstance(A, torch.Tensor) or not A.is_cuda:
+            raise TypeError("%s must be a CUDA/HIP tensor" % name)
+        if A.dtype != self.dtype:
+            raise TypeError("%s must be %s" % (name, self.dtype))
+        if tuple(A.shape) not in (self.shape, self.shape[1:] if self.batch == 1 else None):
+            raise ValueError("%s has shape %s, plan expects %s" % (name, tuple(A.shape), self.shape))
+        if not A.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        return ctypes.c_void_p(A.data_ptr())
+
+    def set_stream(self, stream=None):
+        _check(self._lib.mbo_plan_set_stream(self._h, _stream_ptr(stream)), self._h)
+
+    def set_tau(self, tau: float):
+        _check(self._lib.mbo_plan_set_tau(self._h, float(tau)), self._h)
+        self.tau = float(tau)
+
+    # -- entry points ----------------------------------------------------------
+    def diffuse(self, A_in, A_out=None):
+        import torch
+        if A_out is None:
+            A_out = torch.empty_like(A_in)
+        _check(self._lib.mbo_diffuse(self._h, self._field(A_in, "A_in"), self._field(A_out, "A_out")),
+               self._h)
+        return A_out
+
+    def project(self, A_in, A_out=None, det_sign: bool = False):
+        import torch
+        if A_out is None:
+            A_out = torch.empty_like(A_in)
+        ds = None
+        if det_sign:
+            ds = torch.empty((self.batch,) + self.grid, dtype=torch.int8, device=A_in.device)
+        _check(self._lib.mbo_project(self._h, self._field(A_in, "A_in"), self._field(A_out, "A_out"),
+                                     ctypes.c_void_p(ds.data_ptr()) if ds is not None else None),
+               self._h)
+        return (A_out, ds) if det_sign else A_out
+
+    def energy(self, A):
+        E = np.zeros(self.batch)
+        _check(self._lib.mbo_energy(self._h, self._field(A),
+                                    E.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self._h)
+        return E if self.batch > 1 else float(E[0])
+
+    def iterate(self, A, max_iter: int, tol: float = 0.0, logs: bool = True):
+        """In-place Algorithm 1 on A.  Returns a dict of numpy logs (per field)."""
+        B, K = self.batch, int(max_iter)
+        it = np.zeros(B, dtype=np.int32)
+        en = np.zeros((B, K + 1)) if logs else None
+        fl = np.zeros((B, max(K, 1)), dtype=np.int64) if logs else None
+        dl = np.zeros((B, max(K, 1))) if logs else None
+        fb = np.zeros((B, max(K, 1)), dtype=np.int64) if logs else None
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int64)
+
+        def ptr(x, t):
+            return None if x is None else x.ctypes.data_as(t)
+
+        rc = self._lib.mbo_iterate(self._h, self._field(A), K, float(tol),
+                                   it.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                   ptr(en, dp), ptr(fl, ip), ptr(dl, dp), ptr(fb, ip))
+        _check(rc, self._h)
+        out = {"iters": it}
+        if logs:
+            out.update(energy=en, flips=fl[:, :K], delta=dl[:, :K], fallbacks=fb[:, :K])
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mbo_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def status_string(code: int) -> str:
+    return load().mbo_status_string(code).decode()

@@ -1,0 +1,84 @@
+"""The C ABI library loads on a host without a GPU, exports every function that
+include/mbo.h declares, and rejects invalid arguments with status codes before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1711_01365_amd import mbo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mbo.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mbo_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(mbo.LIB_PATH):
+        pytest.skip("libmbo.so not built")
+    return mbo.load()
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for f in ("mbo_plan", "mbo_diffuse", "mbo_project", "mbo_iterate", "mbo_energy"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(mbo.EXPORTS) == set(declared_functions())
+
+
+def test_status_strings(lib):
+    for code, name in mbo._STATUS.items():
+        assert mbo.status_string(code) == name
+
+
+def _plan(lib, d=2, N=(64, 64), n=2, batch=1, tau=1e-3, prec=0, out=True):
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_int64 * len(N))(*N)
+    return lib.mbo_plan(ctypes.byref(h) if out else None, d, arr, n, batch, tau, prec, 0.0, None), h
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(out=False), 1),
+    (dict(d=1, N=(64,)), 1),
+    (dict(d=4, N=(8, 8, 8, 8)), 1),
+    (dict(n=0), 1), (dict(n=5), 1),
+    (dict(batch=0), 1),
+    (dict(tau=0.0), 1), (dict(tau=-1.0), 1), (dict(tau=float("nan")), 1), (dict(tau=float("inf")), 1),
+    (dict(prec=7), 1),
+    (dict(N=(64, 48)), 2), (dict(N=(4, 64)), 2), (dict(N=(64, 4096)), 2),
+    (dict(d=3, N=(8, 8, 12)), 2),
+])
+def test_plan_validation_codes(lib, kw, code):
+    rc, h = _plan(lib, **kw)
+    assert rc == code
+    assert h.value is None
+    assert lib.mbo_last_error(None)  # a message is recorded
+
+
+def test_null_plan_is_rejected(lib):
+    assert lib.mbo_diffuse(None, None, None) == 1
+    assert lib.mbo_project(None, None, None, None) == 1
+    assert lib.mbo_energy(None, None, None) == 1
+    assert lib.mbo_iterate(None, None, 1, 0.0, None, None, None, None, None) == 1
+    assert lib.mbo_plan_set_tau(None, 1.0) == 1
+    assert lib.mbo_plan_destroy(None) == 0
+
+
+def test_binding_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError):
+        mbo.Plan((64, 64), 2, 1e-3)

@@ -1,0 +1,387 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 path <= 1e-12 max-abs on field entries; FP32 path <= 1e-5 on
+points whose projection is well conditioned (sigma_{n-1} + sigma_n >= 0.1, the
+polar factor's absolute condition number being 2 / (sigma_{n-1} + sigma_n));
+integer diagnostics (det signs, flip counts, iteration counts) identical, a det
+mismatch being allowed only where |det| of the diffused matrix is below 1e-12.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_01365_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*a):
+    print("[gpu-parity]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1711_01365_amd import mbo
+    mbo.load()
+    return torch
+
+
+def to_dev(torch, A, dtype):
+    return torch.tensor(np.ascontiguousarray(A), dtype=dtype, device="cuda")
+
+
+def point_major(A):
+    n = A.shape[0]
+    return np.moveaxis(A.reshape(n, n, -1), -1, 0)
+
+
+def cond_mask(At):
+    """Points whose polar factor is well conditioned: sigma_{n-1} + sigma_n >= 0.1."""
+    s = np.linalg.svd(point_major(At), compute_uv=False)
+    if s.shape[1] == 1:
+        return np.abs(s[:, 0]) >= 0.05
+    return (s[:, -2] + s[:, -1]) >= 0.1
+
+
+def sigma_gap(At):
+    """sigma_{n-1} + sigma_n of every point (the polar factor's absolute condition
+    number is 2 / (sigma_{n-1} + sigma_n), Higham, Functions of Matrices, Sec. 8.1)."""
+    s = np.linalg.svd(point_major(At), compute_uv=False)
+    return s[:, -2] + s[:, -1]
+
+
+def fp32_step_ok(err, gap, e_heat):
+    """FP32 one-step error per point against the FP64 oracle.  The FP32 diffusion
+    perturbs the projected matrix by e_heat (measured); the first-order bound
+    |dQ| <= 2 |dA| / (sigma_{n-1} + sigma_n) then caps what any FP32 projection
+    can reach.  Well-conditioned points (gap >= 0.1) must meet 1e-5 outright."""
+    u32 = 2.0 ** -24
+    bound = np.maximum(1e-5, 4.0 * (e_heat + 8 * u32) / gap)
+    return bool(np.all(err <= bound)) and (not np.any(gap >= 0.1) or err[gap >= 0.1].max() <= 1e-5)
+
+
+def plan(grid, n, tau, prec, batch=1):
+    from paper_1711_01365_amd import mbo
+    return mbo.Plan(grid, n, tau, precision=prec, batch=batch)
+
+
+F64, F32, FB = 0, 1, 2
+
+
+# --------------------------------------------------------------------------
+# Projection
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_project_f64(torch_cuda, n):
+    torch = torch_cuda
+    A = inputs.uniform_field(n, (64, 32), 1000 + n)
+    note("project f64 n=%d grid=64x32 seed=%d" % (n, 1000 + n))
+    P = plan((64, 32), n, 1e-3, F64)
+    Q, ds = P.project(to_dev(torch, A, torch.float64), det_sign=True)
+    torch.cuda.synchronize()
+    Qo, dso, sg, _ = oracle.project(A)
+    Qg = Q.cpu().numpy()
+    assert np.abs(Qg - Qo).max() <= 1e-12
+    assert np.array_equal(ds.cpu().numpy()[0], dso)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+@pytest.mark.parametrize("prec", [F32, FB])
+def test_project_f32(torch_cuda, n, prec):
+    torch = torch_cuda
+    A = inputs.normal_field(n, (64, 64), 1100 + n)
+    note("project f32 n=%d prec=%d seed=%d" % (n, prec, 1100 + n))
+    A32 = A.astype(np.float32)
+    P = plan((64, 64), n, 1e-3, prec)
+    Q = P.project(to_dev(torch, A32, torch.float32)).cpu().numpy()
+    Qo = oracle.project(A32.astype(np.float64))[0]
+    ok = cond_mask(A32.astype(np.float64))
+    err = np.abs(point_major(Q - Qo)).max(axis=(1, 2))
+    assert err[ok].max() <= 1e-5
+    if prec == FB:
+        # points with sigma_min < 1e-3 are re-projected in double: FP64 accuracy
+        s = np.linalg.svd(point_major(A32.astype(np.float64)), compute_uv=False)
+        small = s[:, -1] < 1e-4
+        if small.any():
+            assert err[small].max() <= 1e-5
+
+
+def test_project_singular_and_special_inputs(torch_cuda):
+    torch = torch_cuda
+    mats = [np.zeros((3, 3)), np.diag([1.0, 1.0, 0.0]), np.diag([2.0, 0.0, 0.5]),
+            np.array([[1.0, 0, 0], [0, -1.0, 0], [0, 0, 0]]), np.eye(3), -np.eye(3),
+            np.diag([3.0, 2.0, -1.0])]
+    A = np.zeros((3, 3, 8, 8))
+    for k, M in enumerate(mats):
+        A[:, :, 0, k] = M
+    A[:, :, 1:, :] = inputs.uniform_field(3, (7, 8), 5)
+    P = plan((8, 8), 3, 1e-3, F64)
+    Q = P.project(to_dev(torch, A, torch.float64)).cpu().numpy()
+    Qo = oracle.project(A)[0]
+    assert np.abs(Q - Qo).max() <= 1e-12
+    for k in range(len(mats)):
+        q = Q[:, :, 0, k]
+        assert np.abs(q.T @ q - np.eye(3)).max() < 1e-14
+
+
+def test_project_nonfinite_is_reported(torch_cuda):
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    A = inputs.uniform_field(2, (8, 8), 9)
+    A[0, 1, 3, 3] = np.nan
+    P = plan((8, 8), 2, 1e-3, F64)
+    with pytest.raises(mbo.MboError) as ei:
+        P.project(to_dev(torch, A, torch.float64))
+    assert ei.value.status == 5
+
+
+# --------------------------------------------------------------------------
+# Diffusion
+# --------------------------------------------------------------------------
+
+GRIDS = [(64, 64), (32, 16), (8, 8), (16, 128), (128, 256), (8, 16, 32), (16, 16, 16), (32, 8, 8)]
+
+
+@pytest.mark.parametrize("grid", GRIDS)
+@pytest.mark.parametrize("n", [1, 3])
+def test_diffuse_f64(torch_cuda, grid, n):
+    torch = torch_cuda
+    tau = 2e-3
+    A = inputs.uniform_field(n, grid, 7)
+    note("diffuse f64 grid=%s n=%d" % (grid, n))
+    P = plan(grid, n, tau, F64)
+    H = P.diffuse(to_dev(torch, A, torch.float64)).cpu().numpy()
+    Ho, _ = oracle.heat(A, tau, len(grid))
+    assert np.abs(H - Ho).max() <= 1e-13
+
+
+@pytest.mark.parametrize("grid", [(64, 64), (512, 512), (16, 32, 64)])
+def test_diffuse_f32(torch_cuda, grid):
+    torch = torch_cuda
+    tau = 2e-4
+    A = inputs.uniform_field(3, grid, 8).astype(np.float32)
+    note("diffuse f32 grid=%s" % (grid,))
+    P = plan(grid, 3, tau, F32)
+    H = P.diffuse(to_dev(torch, A, torch.float32)).cpu().numpy()
+    Ho, _ = oracle.heat(A.astype(np.float64), tau, len(grid))
+    assert np.abs(H - Ho).max() <= 2e-6
+
+
+def test_diffuse_single_modes(torch_cuda):
+    """Closed form: cos(2 pi k.x + phi) decays by exp(-4 pi^2 |k|^2 tau), Nyquist included."""
+    torch = torch_cuda
+    grid, tau = (32, 16), 3e-3
+    Y, X = np.meshgrid(np.arange(32) / 32, np.arange(16) / 16, indexing="ij")
+    ks = [(1, 0), (0, 3), (-5, 7), (16, -8), (3, 8)]
+    A = np.stack([np.cos(2 * np.pi * (ky * Y + kx * X) + 0.4) for ky, kx in ks[:4]]).reshape(2, 2, 32, 16)
+    P = plan(grid, 2, tau, F64)
+    H = P.diffuse(to_dev(torch, A, torch.float64)).cpu().numpy()
+    for e, (ky, kx) in enumerate(ks[:4]):
+        kyw = ((ky + 16) % 32) - 16
+        kxw = ((kx + 8) % 16) - 8
+        f = np.exp(-4 * np.pi ** 2 * tau * (kyw ** 2 + kxw ** 2))
+        assert np.abs(H.reshape(4, 32, 16)[e] - f * A.reshape(4, 32, 16)[e]).max() < 1e-13
+
+
+def test_diffuse_in_place_and_batched(torch_cuda):
+    torch = torch_cuda
+    tau = 1e-3
+    A = np.stack([inputs.uniform_field(2, (64, 32), s) for s in (1, 2, 3)])
+    P = plan((64, 32), 2, tau, F64, batch=3)
+    t = to_dev(torch, A, torch.float64)
+    P.diffuse(t, t)
+    H = t.cpu().numpy()
+    for b in range(3):
+        assert np.abs(H[b] - oracle.heat(A[b], tau, 2)[0]).max() <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# Energy
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("grid,n", [((64, 64), 2), ((32, 128), 3), ((16, 8, 32), 3), ((64, 64), 1)])
+def test_energy_f64(torch_cuda, grid, n):
+    torch = torch_cuda
+    tau = 1e-3
+    A = inputs.uniform_field(n, grid, 17)
+    P = plan(grid, n, tau, F64)
+    E = P.energy(to_dev(torch, A, torch.float64))
+    Eo = oracle.energy(A, tau)
+    assert abs(E - Eo) <= 1e-11 * max(1.0, abs(Eo))
+
+
+def test_energy_f32(torch_cuda):
+    torch = torch_cuda
+    A = inputs.haar_field(3, (256, 256), 19)
+    P = plan((256, 256), 3, 2e-4, F32)
+    E = P.energy(to_dev(torch, A.astype(np.float32), torch.float32))
+    Eo = oracle.energy(A.astype(np.float32).astype(np.float64), 2e-4)
+    assert abs(E - Eo) <= 1e-5 * abs(Eo)
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1
+# --------------------------------------------------------------------------
+
+def compare_runs(r, ro, n_iters, atol):
+    assert int(r["iters"][0]) == ro["iters"] == n_iters
+    assert np.array_equal(r["flips"][0], ro["flips"])
+    Eo = ro["energy"]
+    assert np.abs(r["energy"][0] - Eo).max() <= 1e-10 * np.abs(Eo).max()
+
+
+def test_iterate_parity_64x64_n2_f64(torch_cuda):
+    """n = 2 on 64 x 64, entries U[-1,1) (seed 0), tau = 1e-3, 20 iterations, FP64."""
+    torch = torch_cuda
+    w = inputs.PARITY_64
+    A0 = w.field()
+    note("iterate f64 %s" % w.name)
+    P = plan(w.grid, w.n, w.tau, F64)
+    t = to_dev(torch, A0, torch.float64)
+    r = P.iterate(t, w.iters)
+    ro = oracle.iterate(A0, w.tau, w.iters)
+    assert np.abs(t.cpu().numpy() - ro["A"]).max() <= 1e-12
+    compare_runs(r, ro, w.iters, 1e-12)
+    # every iterate, not only the last
+    B = A0.copy()
+    t = to_dev(torch, A0, torch.float64)
+    for s in range(5):
+        P.iterate(t, 1)
+        B = oracle.iterate(B, w.tau, 1)["A"]
+        assert np.abs(t.cpu().numpy() - B).max() <= 1e-12
+
+
+@pytest.mark.parametrize("n,grid", [(1, (64, 64)), (3, (64, 32)), (4, (32, 32)), (3, (16, 16, 16)), (2, (8, 8))])
+def test_iterate_parity_f64(torch_cuda, n, grid):
+    torch = torch_cuda
+    tau, K = 2e-3, 6
+    A0 = inputs.uniform_field(n, grid, 40 + n)
+    note("iterate f64 n=%d grid=%s" % (n, grid))
+    P = plan(grid, n, tau, F64)
+    t = to_dev(torch, A0, torch.float64)
+    r = P.iterate(t, K)
+    ro = oracle.iterate(A0, tau, K)
+    assert np.abs(t.cpu().numpy() - ro["A"]).max() <= 1e-12
+    compare_runs(r, ro, K, 1e-12)
+
+
+def test_iterate_tolerance_stop_matches_oracle(torch_cuda):
+    torch = torch_cuda
+    tau = 2e-3
+    u0 = np.where(inputs.uniform_field(1, (32, 32), 51) >= 0, 1.0, -1.0)
+    P = plan((32, 32), 1, tau, F64)
+    t = to_dev(torch, u0, torch.float64)
+    r = P.iterate(t, 200, tol=1e-300)
+    ro = oracle.iterate(u0, tau, 200, tol=1e-300)
+    assert int(r["iters"][0]) == ro["iters"] < 200
+    assert np.array_equal(t.cpu().numpy(), ro["A"])
+    k = ro["iters"]
+    assert np.array_equal(r["flips"][0][:k], ro["flips"])
+    assert np.array_equal(r["delta"][0][:k], ro["delta"])
+    assert np.abs(r["energy"][0][:k + 1] - ro["energy"]).max() <= 1e-10 * np.abs(ro["energy"]).max()
+
+
+def test_iterate_graph_replay_is_stable(torch_cuda):
+    """The captured graph is replayed: repeated calls on the same buffer continue
+    the iteration exactly like one longer call, with eager syncs in between."""
+    torch = torch_cuda
+    A0 = inputs.uniform_field(3, (64, 64), 77)
+    P = plan((64, 64), 3, 1e-3, F64)
+    t = to_dev(torch, A0, torch.float64)
+    for _ in range(3):
+        P.iterate(t, 2)
+        torch.cuda.synchronize()
+        _ = (t * 2).sum().item()
+    ro = oracle.iterate(A0, 1e-3, 6)
+    assert np.abs(t.cpu().numpy() - ro["A"]).max() <= 1e-12
+
+
+def test_iterate_batched_fields_match_single(torch_cuda):
+    torch = torch_cuda
+    A = np.stack([inputs.uniform_field(2, (32, 64), s) for s in (4, 5)])
+    P = plan((32, 64), 2, 1e-3, F64, batch=2)
+    t = to_dev(torch, A, torch.float64)
+    r = P.iterate(t, 4)
+    for b in range(2):
+        ro = oracle.iterate(A[b], 1e-3, 4)
+        assert np.abs(t.cpu().numpy()[b] - ro["A"]).max() <= 1e-12
+        assert np.array_equal(r["flips"][b], ro["flips"])
+
+
+@pytest.mark.parametrize("prec", [F32, FB])
+def test_iterate_one_step_f32_512(torch_cuda, prec):
+    """n = 3, 512 x 512, Haar O(3) (seed 1), tau = 2e-4: one FP32 step from the same
+    state against the FP64 oracle, per point within the FP32 perturbation bound
+    (and 1e-5 where the projection is well conditioned)."""
+    torch = torch_cuda
+    w = inputs.HAAR_512
+    A0 = w.field().astype(np.float32)
+    note("one step f32 prec=%d %s" % (prec, w.name))
+    P = plan(w.grid, w.n, w.tau, prec)
+    A64 = A0.astype(np.float64)
+    Ht, _ = oracle.heat(A64, w.tau, 2)
+    Hg = P.diffuse(to_dev(torch, A0, torch.float32)).cpu().numpy()
+    e_heat = float(np.abs(Hg - Ht).max())
+    t = to_dev(torch, A0, torch.float32)
+    r = P.iterate(t, 1)
+    ro = oracle.iterate(A64, w.tau, 1)
+    gap = sigma_gap(Ht)
+    err = np.abs(point_major(t.cpu().numpy() - ro["A"])).max(axis=(1, 2))
+    note("one step f32: diffusion err %.3g, step err max %.3g, median %.3g, min gap %.3g, "
+         "fallbacks %d" % (e_heat, err.max(), np.median(err), gap.min(), r["fallbacks"][0][0]))
+    assert e_heat <= 2e-6
+    assert fp32_step_ok(err, gap, e_heat)
+    assert abs(r["energy"][0][0] - ro["energy"][0]) <= 1e-5 * abs(ro["energy"][0])
+    if prec == FB:
+        assert r["fallbacks"][0][0] > 0
+
+
+def test_iterate_full_size_512_f64_two_steps(torch_cuda):
+    torch = torch_cuda
+    w = inputs.HAAR_512
+    A0 = w.field()
+    note("two steps f64 %s" % w.name)
+    P = plan(w.grid, w.n, w.tau, F64)
+    t = to_dev(torch, A0, torch.float64)
+    r = P.iterate(t, 2)
+    ro = oracle.iterate(A0, w.tau, 2)
+    assert np.abs(t.cpu().numpy() - ro["A"]).max() <= 1e-12
+    assert np.array_equal(r["flips"][0], ro["flips"])
+
+
+def test_bench_configuration_properties(torch_cuda):
+    """The measured configuration (n = 3, 512^2, 200 FP32+fallback iterations) at
+    full size: every point orthogonal, energy non-increasing from s = 1 (within
+    FP32 rounding), the logged final energy equal to the oracle's energy of the
+    returned field, and the last step equal to one oracle step from iterate 199."""
+    torch = torch_cuda
+    w = inputs.HAAR_512
+    A0 = w.field().astype(np.float32)
+    note("bench configuration %s, 199 + 1 iterations" % w.name)
+    P = plan(w.grid, w.n, w.tau, FB)
+    t = to_dev(torch, A0, torch.float32)
+    r = P.iterate(t, w.iters - 1)
+    A199 = t.cpu().numpy()
+    r2 = P.iterate(t, 1)
+    A200 = t.cpu().numpy()
+    M = point_major(A200).astype(np.float64)
+    assert np.abs(M.transpose(0, 2, 1) @ M - np.eye(3)).max() < 1e-5
+    E = np.concatenate([r["energy"][0], r2["energy"][0][1:]])
+    assert np.all(np.diff(E[1:]) <= 1e-5 * E[1])
+    assert abs(E[-1] - oracle.energy(A200.astype(np.float64), w.tau)) <= 1e-5 * E[-1]
+    ro = oracle.iterate(A199.astype(np.float64), w.tau, 1)
+    Ht, _ = oracle.heat(A199.astype(np.float64), w.tau, 2)
+    Hg = P.diffuse(to_dev(torch, A199, torch.float32)).cpu().numpy()
+    e_heat = float(np.abs(Hg - Ht).max())
+    gap = sigma_gap(Ht)
+    err = np.abs(point_major(A200 - ro["A"])).max(axis=(1, 2))
+    note("bench config last step: diffusion err %.3g, step err max %.3g, well-cond (%d pts) %.3g"
+         % (e_heat, err.max(), int((gap >= 0.1).sum()), err[gap >= 0.1].max() if (gap >= 0.1).any() else 0))
+    assert fp32_step_ok(err, gap, e_heat)
+    assert r2["flips"][0][0] == ro["flips"][0] or abs(int(r2["flips"][0][0]) - int(ro["flips"][0])) <= 2
