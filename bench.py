@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark of the generalized MBO iteration (Osting & Wang, arXiv:1711.01365).
+
+Workload (one "step"): Algorithm 1 on an n = 3 field over a 512 x 512 periodic
+grid of [0,1)^2, initial values Haar-random in O(3) per point (seed 1),
+tau = 2e-4, 200 iterations, FP32 diffusion and projection with FP64 re-projection
+of points whose smallest singular value is below 1e-3.  Each step restores the
+initial field (a device copy) and runs the 200 iterations as one captured HIP
+graph, with the Lyapunov energy, det-flip and fallback logs copied back once.
+The same workload in full FP64 is timed beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  `value` is point-iterations per second (points x
+iterations x steps / seconds) on one GPU.  `roofline` prices the dominant kernel
+(the row pass) by its algorithmic bytes per launch -- one read and one write of
+the n x n FP32 field, 72 bytes per point -- over its average duration, taken
+from HIP start/stop events recorded by each dispatch in three more steps run
+right after the timed ones (launched directly, since events inside a captured
+graph cannot be timed).  `cpu_baseline` is
+the FP64 CPU oracle on a bounded sample (the first iterations of the same
+workload).
+
+    python bench.py --copy-calibration
+
+runs only a plain device copy of 256 MiB (ten times), the reference the
+hardware byte counters are scaled by.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "row_pass_n3_512x512_f32fb_traffic.txt")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1711_01365_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM traffic of the row pass per launch from the committed counter summary,
+    or None when it is missing or was taken on different kernel sources."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    kv = {}
+    for line in open(PROFILE_TRAFFIC):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    import torch
+    n = 64 * 1024 * 1024  # floats: 256 MiB
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 10}))
+
+
+def run_gpu(w, precision, steps, warmup, timing_steps):
+    """Timed region: `steps` steps through the captured graph (the product path).
+    Then `timing_steps` more steps with per-kernel HIP events (direct launches)."""
+    import numpy as np
+    import torch
+    from paper_1711_01365_amd import mbo
+
+    dt = torch.float64 if precision == mbo.F64 else torch.float32
+    A0 = torch.tensor(w.field(), dtype=dt, device="cuda")
+    A = A0.clone()
+    plan = mbo.Plan(w.grid, w.n, w.tau, precision=precision)
+    for _ in range(warmup):
+        A.copy_(A0)
+        plan.iterate(A, w.iters)
+    torch.cuda.synchronize()
+    logs = None
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        A.copy_(A0)
+        logs = plan.iterate(A, w.iters)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    row_us, col_us = [], []
+    if timing_steps:
+        plan.set_timing(True)
+        for k in range(timing_steps + 1):
+            A.copy_(A0)
+            plan.iterate(A, w.iters)
+            if k:  # the first one warms the direct-launch path
+                r, c, _k = plan.last_timing()
+                row_us.append(r)
+                col_us.append(c)
+        torch.cuda.synchronize()
+    plan.close()
+    return {
+        "seconds": sec,
+        "value": w.points * w.iters * steps / sec,
+        "ms_per_step": 1000.0 * sec / steps,
+        "row_us": float(np.mean(row_us)) if row_us else None,
+        "heat_us": float(np.mean(col_us)) if col_us else None,
+        "energy_first_last": [float(logs["energy"][0][0]), float(logs["energy"][0][-1])],
+        "fallbacks_total": int(logs["fallbacks"][0].sum()),
+        "flips_first": int(logs["flips"][0][0]),
+    }
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The FP64 oracle on the first iterations of the same workload."""
+    import oracle
+    A0 = w.field()
+    t0 = time.perf_counter()
+    oracle.iterate(A0, w.tau, 1)
+    t1 = time.perf_counter() - t0
+    iters = int(max(2, min(50, budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.iterate(A0, w.tau, iters)
+    sec = time.perf_counter() - t0
+    return {
+        "value": w.points * iters / sec,
+        "unit": "point-iterations/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": "first %d of the %d iterations of the same 512x512 n=3 workload, FP64 C oracle "
+                  "(%.1f s)" % (iters, w.iters, sec),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the iteration would shard); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    from paper_1711_01365_amd import inputs, mbo
+    w = inputs.HAAR_512
+    log("workload %s: n=%d grid=%s tau=%g iterations=%d" % (w.name, w.n, w.grid, w.tau, w.iters))
+    main_run = run_gpu(w, mbo.F32_F64FALLBACK, args.steps, args.warmup, timing_steps=3)
+    log("fp32+fp64 fallback: %.3e point-iter/s, %.3f ms/step, row pass %.2f us, heat pass %.2f us"
+        % (main_run["value"], main_run["ms_per_step"], main_run["row_us"], main_run["heat_us"]))
+    f64 = None
+    if not args.no_f64:
+        f64 = run_gpu(w, mbo.F64, args.steps, min(args.warmup, 1), timing_steps=3)
+        log("fp64: %.3e point-iter/s, row pass %.2f us, heat pass %.2f us"
+            % (f64["value"], f64["row_us"], f64["heat_us"]))
+
+    bytes_per_launch = 2 * w.n * w.n * 4 * w.points  # one read + one write of the FP32 field
+    dominant_us = max(main_run["row_us"], main_run["heat_us"])
+    dominant = "row_pass" if main_run["row_us"] >= main_run["heat_us"] else "heat_pass"
+    achieved = bytes_per_launch / (dominant_us * 1e-6) / 1e9
+    traffic = read_traffic() if dominant == "row_pass" else None
+    out = {
+        "metric": "MBO point-iterations/s (n=3, 512², FP32 vs FP64) + % of HBM peak",
+        "value": main_run["value"],
+        "unit": "point-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: Haar-random O(3) field per point, seed 1",
+        "config": {"workload": "n3_512x512_haar_tau2e-4_200it_f32_f64fallback", "n": 3,
+                   "grid": [512, 512], "tau": 2e-4, "iterations": 200,
+                   "precision": "f32 + f64 fallback (sigma_min < 1e-3)"},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_us": dominant_us},
+        "kernels_us": {"row_pass": main_run["row_us"], "heat_pass": main_run["heat_us"]},
+        "fallback_points_total": main_run["fallbacks_total"],
+    }
+    if f64 is not None:
+        out["f64"] = {"value": f64["value"], "ms_per_step": f64["ms_per_step"],
+                      "kernels_us": {"row_pass": f64["row_us"], "heat_pass": f64["heat_us"]},
+                      "f32_over_f64": main_run["value"] / f64["value"]}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(w)
+        log("cpu baseline: %.3e point-iter/s on %d threads" % (out["cpu_baseline"]["value"],
+                                                             out["cpu_baseline"]["cores"]))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -100,6 +100,18 @@ mbo_status mbo_plan_set_tau(mbo_plan_t plan, double tau);
 /* Change the stream subsequent calls are enqueued on. */
 mbo_status mbo_plan_set_stream(mbo_plan_t plan, void* hip_stream);
 
+/* Kernel timing (a diagnostic, off by default).  When enabled, mbo_iterate
+ * launches its kernels directly on the plan's stream instead of through the
+ * captured graph, each row pass (inverse row FFT, projection, forward row FFT)
+ * and heat pass (strided-axis FFT, heat symbol, inverse) with HIP start/stop
+ * events recorded by its own dispatch. */
+mbo_status mbo_plan_set_timing(mbo_plan_t plan, int enable);
+
+/* Average durations, in microseconds, of the row passes and heat passes of the
+ * last mbo_iterate call made with timing enabled, and the number of iterations
+ * averaged over (all nullable). */
+mbo_status mbo_last_timing(mbo_plan_t plan, double* row_us, double* heat_us, int* launches);
+
 /* Diffusion step (Algorithm 1 step 1, Section 5.1):
  *   A_out = e^{tau Delta} A_in, entry by entry, for every field of the batch.
  * A_out may alias A_in.  Asynchronous. */

@@ -74,11 +74,17 @@ def _load():
     lib.orc_iterate.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_double, _d,
                                 ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_int),
                                 _d, _i64, _d, _d, ctypes.c_int]
+    lib.orc_num_threads.argtypes = []
     for f in ("orc_dft_naive", "orc_fft", "orc_heat", "orc_project", "orc_det_sign",
-              "orc_energy", "orc_iterate"):
+              "orc_energy", "orc_iterate", "orc_num_threads"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(_load().orc_num_threads())
 
 
 def _ptr(a, t=_d):

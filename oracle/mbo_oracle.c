@@ -483,3 +483,11 @@ int orc_iterate(int d, const int64_t* N, int n, double tau, double* A, int K, do
     free(At); free(An); free(sp); free(sn);
     return rc;
 }
+
+/* Number of threads the OpenMP loops above use (1 without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+int orc_num_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_num_threads(void) { return 1; }
+#endif

@@ -84,6 +84,13 @@ struct mbo_plan_s {
     unsigned long long* delta_bits = nullptr;
     int* stop_iter = nullptr;
 
+    // optional kernel timing: events around every row / heat pass of mbo_iterate
+    bool timing = false;
+    std::vector<hipEvent_t> ev;   // [4 * K]: row start, row end, heat start, heat end
+    int ev_K = 0;
+    double t_row_us = 0.0, t_col_us = 0.0;
+    int t_launches = 0;
+
     // cached iteration graph
     hipGraphExec_t gexec = nullptr;
     void* g_A = nullptr;
@@ -158,6 +165,7 @@ void destroy(mbo_plan_t p)
     free_dev(p->nonfinite);
     free_dev(p->delta_bits);
     free_dev(p->stop_iter);
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     if (p->cap) (void)hipStreamDestroy(p->cap);
     delete p;
 }
@@ -302,14 +310,16 @@ ColArgs col_args(mbo_plan_t p, const ColCfg& c)
     return a;
 }
 
-hipError_t run_row(mbo_plan_t p, const RowArgs& a, hipStream_t st)
+hipError_t run_row(mbo_plan_t p, const RowArgs& a, hipStream_t st, hipEvent_t ev0 = nullptr,
+                   hipEvent_t ev1 = nullptr)
 {
-    return launch_row(p->pk, p->n, a.log2L, a, p->row_grid, p->row_block, p->row_lds, st);
+    return launch_row(p->pk, p->n, a.log2L, a, p->row_grid, p->row_block, p->row_lds, st, false, ev0, ev1);
 }
 
-hipError_t run_col(mbo_plan_t p, const ColCfg& c, int mode, const ColArgs& a, hipStream_t st)
+hipError_t run_col(mbo_plan_t p, const ColCfg& c, int mode, const ColArgs& a, hipStream_t st,
+                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
-    return launch_col(p->pk, mode, a.log2L, a, c.grid, c.block, c.lds, st);
+    return launch_col(p->pk, mode, a.log2L, a, c.grid, c.block, c.lds, st, false, ev0, ev1);
 }
 
 // Raise the dynamic-LDS limit of every kernel instance this plan launches to
@@ -409,7 +419,9 @@ hipError_t enqueue_iterate(mbo_plan_t p, void* A, int K, double tol, bool want_e
                 return e;
             h.delta_bits = nullptr;
         }
-        if ((e = run_col(p, p->heat, CM_HEAT, h, st)) != hipSuccess) return e;
+        hipEvent_t hs = p->timing ? p->ev[4 * (s - 1) + 2] : nullptr;
+        hipEvent_t he = p->timing ? p->ev[4 * (s - 1) + 3] : nullptr;
+        if ((e = run_col(p, p->heat, CM_HEAT, h, st, hs, he)) != hipSuccess) return e;
         if (p->d == 3) {
             ColArgs y = col_args(p, p->ypass);
             y.iter = s;
@@ -431,7 +443,9 @@ hipError_t enqueue_iterate(mbo_plan_t p, void* A, int K, double tol, bool want_e
         if (s == K || track) r.flags |= RF_STORE_REAL;
         if (track) r.flags |= RF_TRACK;
         if (fallback) r.flags |= RF_FALLBACK;
-        if ((e = run_row(p, r, st)) != hipSuccess) return e;
+        hipEvent_t rs = p->timing ? p->ev[4 * (s - 1)] : nullptr;
+        hipEvent_t re = p->timing ? p->ev[4 * (s - 1) + 1] : nullptr;
+        if ((e = run_row(p, r, st, rs, re)) != hipSuccess) return e;
     }
     if (want_energy) {
         // E(A_final): Z holds the row spectra of the last iterate (A_0 for K = 0)
@@ -595,6 +609,23 @@ mbo_status mbo_plan_set_tau(mbo_plan_t p, double tau)
     return build_symbol_tables(p);
 }
 
+mbo_status mbo_plan_set_timing(mbo_plan_t p, int enable)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (p->timing != (enable != 0)) drop_graph(p);
+    p->timing = enable != 0;
+    return MBO_OK;
+}
+
+mbo_status mbo_last_timing(mbo_plan_t p, double* row_us, double* heat_us, int* launches)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (row_us) *row_us = p->t_row_us;
+    if (heat_us) *heat_us = p->t_col_us;
+    if (launches) *launches = p->t_launches;
+    return MBO_OK;
+}
+
 mbo_status mbo_plan_set_stream(mbo_plan_t p, void* hip_stream)
 {
     if (!p) return MBO_ERR_INVALID_ARG;
@@ -686,8 +717,18 @@ mbo_status mbo_iterate(mbo_plan_t p, void* A, int max_iter, double tol, int* ite
     const bool want_energy = energy != nullptr;
     mbo_status s = ensure_logs(p, K);
     if (s != MBO_OK) return s;
-    const int key = (tol > 0.0 ? 1 : 0) | (want_energy ? 2 : 0);
-    if (use_graphs()) {
+    if (p->timing && p->ev_K < K) {
+        p->ev.reserve(4 * (size_t)K);
+        while ((int)p->ev.size() < 4 * K) {
+            hipEvent_t e;
+            HIP_TRY(p, hipEventCreate(&e));
+            p->ev.push_back(e);
+        }
+        p->ev_K = K;
+        drop_graph(p);
+    }
+    const int key = (tol > 0.0 ? 1 : 0) | (want_energy ? 2 : 0) | (p->timing ? 4 : 0);
+    if (use_graphs() && !p->timing) {
         if (!(p->gexec && p->g_A == A && p->g_K == K && p->g_key == key && p->g_tol == tol)) {
             drop_graph(p);
             hipGraph_t g = nullptr;
@@ -730,6 +771,23 @@ mbo_status mbo_iterate(mbo_plan_t p, void* A, int max_iter, double tol, int* ite
         HIP_TRY(p, hipMemcpyAsync(he.data(), p->energy, he.size() * sizeof(double), hipMemcpyDeviceToHost,
                                   p->stream));
     HIP_TRY(p, hipStreamSynchronize(p->stream));
+
+    if (p->timing && K > 0) {
+        // average over the iterations every field ran (stopped fields skip kernels)
+        int ran = K;
+        for (size_t b = 0; b < B; ++b) ran = st[b] < ran ? st[b] : ran;
+        double tr = 0.0, tc = 0.0;
+        for (int k = 0; k < ran; ++k) {
+            float ms_r = 0.f, ms_c = 0.f;
+            HIP_TRY(p, hipEventElapsedTime(&ms_r, p->ev[4 * k], p->ev[4 * k + 1]));
+            HIP_TRY(p, hipEventElapsedTime(&ms_c, p->ev[4 * k + 2], p->ev[4 * k + 3]));
+            tr += ms_r;
+            tc += ms_c;
+        }
+        p->t_launches = ran;
+        p->t_row_us = ran ? 1000.0 * tr / ran : 0.0;
+        p->t_col_us = ran ? 1000.0 * tc / ran : 0.0;
+    }
 
     unsigned long long bad = 0;
     for (size_t b = 0; b < B; ++b) {

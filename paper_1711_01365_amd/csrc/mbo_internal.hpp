@@ -92,10 +92,14 @@ struct ReduceArgs {
 
 // prec: 0 = double, 1 = float.  log2L: log2 of the transform length.  With
 // prepare = true a launcher only raises the kernel's dynamic-LDS limit.
+// ev0 / ev1 (optional): events recorded by the dispatch itself at the kernel's
+// start and end (AMD's extended launch), for kernel timing.
 hipError_t launch_row(int prec, int n, int log2L, const RowArgs& a, dim3 grid, dim3 block,
-                      size_t lds, hipStream_t st, bool prepare = false);
+                      size_t lds, hipStream_t st, bool prepare = false, hipEvent_t ev0 = nullptr,
+                      hipEvent_t ev1 = nullptr);
 hipError_t launch_col(int prec, int mode, int log2L, const ColArgs& a, dim3 grid, dim3 block,
-                      size_t lds, hipStream_t st, bool prepare = false);
+                      size_t lds, hipStream_t st, bool prepare = false, hipEvent_t ev0 = nullptr,
+                      hipEvent_t ev1 = nullptr);
 hipError_t launch_project(int prec, int n, const ProjArgs& a, int batch, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v,
                            hipStream_t st);
@@ -104,12 +108,12 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
 
 // per-translation-unit launchers behind launch_row / launch_col
 hipError_t launch_row_f32(int n, int log2L, const RowArgs& a, dim3 g, dim3 b, size_t lds,
-                          hipStream_t st, bool prepare);
+                          hipStream_t st, bool prepare, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_row_f64(int n, int log2L, const RowArgs& a, dim3 g, dim3 b, size_t lds,
-                          hipStream_t st, bool prepare);
+                          hipStream_t st, bool prepare, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_col_f32(int mode, int log2L, const ColArgs& a, dim3 g, dim3 b, size_t lds,
-                          hipStream_t st, bool prepare);
+                          hipStream_t st, bool prepare, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_col_f64(int mode, int log2L, const ColArgs& a, dim3 g, dim3 b, size_t lds,
-                          hipStream_t st, bool prepare);
+                          hipStream_t st, bool prepare, hipEvent_t ev0, hipEvent_t ev1);
 
 }  // namespace mbo

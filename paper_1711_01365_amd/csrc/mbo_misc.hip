@@ -82,17 +82,17 @@ __global__ void reduce_energy(const ReduceArgs a)
 // Launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_row(int prec, int n, int log2L, const RowArgs& a, dim3 g, dim3 bl, size_t lds,
-                      hipStream_t st, bool prepare)
+                      hipStream_t st, bool prepare, hipEvent_t ev0, hipEvent_t ev1)
 {
-    return prec == 0 ? launch_row_f64(n, log2L, a, g, bl, lds, st, prepare)
-                     : launch_row_f32(n, log2L, a, g, bl, lds, st, prepare);
+    return prec == 0 ? launch_row_f64(n, log2L, a, g, bl, lds, st, prepare, ev0, ev1)
+                     : launch_row_f32(n, log2L, a, g, bl, lds, st, prepare, ev0, ev1);
 }
 
 hipError_t launch_col(int prec, int mode, int log2L, const ColArgs& a, dim3 g, dim3 bl, size_t lds,
-                      hipStream_t st, bool prepare)
+                      hipStream_t st, bool prepare, hipEvent_t ev0, hipEvent_t ev1)
 {
-    return prec == 0 ? launch_col_f64(mode, log2L, a, g, bl, lds, st, prepare)
-                     : launch_col_f32(mode, log2L, a, g, bl, lds, st, prepare);
+    return prec == 0 ? launch_col_f64(mode, log2L, a, g, bl, lds, st, prepare, ev0, ev1)
+                     : launch_col_f32(mode, log2L, a, g, bl, lds, st, prepare, ev0, ev1);
 }
 
 template <typename T>

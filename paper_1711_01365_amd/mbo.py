@@ -26,8 +26,8 @@ _STATUS = {0: "MBO_OK", 1: "MBO_ERR_INVALID_ARG", 2: "MBO_ERR_UNSUPPORTED", 3: "
 _lib = None
 
 EXPORTS = ("mbo_plan", "mbo_plan_destroy", "mbo_plan_set_tau", "mbo_plan_set_stream",
-           "mbo_diffuse", "mbo_project", "mbo_iterate", "mbo_energy", "mbo_status_string",
-           "mbo_last_error")
+           "mbo_plan_set_timing", "mbo_last_timing", "mbo_diffuse", "mbo_project", "mbo_iterate",
+           "mbo_energy", "mbo_status_string", "mbo_last_error")
 
 
 class MboError(RuntimeError):
@@ -51,12 +51,15 @@ def load(path: str = LIB_PATH):
     lib.mbo_plan_destroy.argtypes = [vp]
     lib.mbo_plan_set_tau.argtypes = [vp, ctypes.c_double]
     lib.mbo_plan_set_stream.argtypes = [vp, vp]
+    lib.mbo_plan_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.mbo_last_timing.argtypes = [vp, dp, dp, ip]
     lib.mbo_diffuse.argtypes = [vp, vp, vp]
     lib.mbo_project.argtypes = [vp, vp, vp, vp]
     lib.mbo_iterate.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, ip, dp, i64p, dp, i64p]
     lib.mbo_energy.argtypes = [vp, vp, dp]
-    for f in EXPORTS[:8]:
-        getattr(lib, f).restype = ctypes.c_int
+    for f in EXPORTS:
+        if f not in ("mbo_status_string", "mbo_last_error"):
+            getattr(lib, f).restype = ctypes.c_int
     lib.mbo_status_string.argtypes = [ctypes.c_int]
     lib.mbo_status_string.restype = ctypes.c_char_p
     lib.mbo_last_error.argtypes = [vp]
@@ -117,6 +120,16 @@ class Plan:
 
     def set_stream(self, stream=None):
         _check(self._lib.mbo_plan_set_stream(self._h, _stream_ptr(stream)), self._h)
+
+    def set_timing(self, enable: bool = True):
+        _check(self._lib.mbo_plan_set_timing(self._h, int(bool(enable))), self._h)
+
+    def last_timing(self):
+        """(row pass us, heat pass us, iterations averaged) of the last timed iterate."""
+        r, c, k = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        _check(self._lib.mbo_last_timing(self._h, ctypes.byref(r), ctypes.byref(c), ctypes.byref(k)),
+               self._h)
+        return r.value, c.value, k.value
 
     def set_tau(self, tau: float):
         _check(self._lib.mbo_plan_set_tau(self._h, float(tau)), self._h)
