@@ -35,7 +35,7 @@ bool is_pow2(int64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
 int lds_len(int L) { return (L - 1) + ((L - 1) >> 3) + 1; }  // lds_pad(L-1) + 1
 
 struct ColCfg {
-    int L = 0, TX = 1;
+    int L = 0, TX = 1, pitch = 0;
     int64_t S = 0, outer = 0;
     dim3 grid, block;
     size_t lds = 0;
@@ -236,15 +236,30 @@ mbo_status config_col(mbo_plan_t p, ColCfg& c, int axis)
     c.outer = (int64_t)p->PL * (p->npts / (c.L * c.S));
     const int T = c.L / 8;
     int TX = 1;
-    while (TX < 16 && TX * 2 <= c.S && T * TX * 2 <= 512) TX *= 2;
-    const size_t per_col = (size_t)lds_len(c.L) * 2 * p->esz;
-    while (TX > 1 && per_col * TX > p->lds_max) TX /= 2;
-    if (per_col * TX > p->lds_max)
-        return fail(p, MBO_ERR_UNSUPPORTED, "axis of length %d needs more LDS than available", c.L);
+    if (c.L <= 512) {
+        // lines inside one wave: a tile of TX lines is staged through LDS with a
+        // line pitch of 8 (mod 64) words, so the coalesced staging is free of
+        // bank conflicts; up to 512 threads per workgroup
+        c.pitch = lds_len(c.L);
+        c.pitch += ((8 - c.pitch % 64) + 64) % 64;
+        while (TX * 2 <= c.S && T * TX * 2 <= 512) TX *= 2;
+        const size_t per_line = (size_t)c.pitch * 2 * p->esz;
+        while (TX > 1 && per_line * TX > p->lds_max) TX /= 2;
+        if (per_line * TX > p->lds_max)
+            return fail(p, MBO_ERR_UNSUPPORTED, "axis of length %d needs more LDS than available", c.L);
+        c.lds = per_line * TX;
+    } else {
+        c.pitch = lds_len(c.L);
+        while (TX < 16 && TX * 2 <= c.S && T * TX * 2 <= 512) TX *= 2;
+        const size_t per_col = (size_t)c.pitch * 2 * p->esz;
+        while (TX > 1 && per_col * TX > p->lds_max) TX /= 2;
+        if (per_col * TX > p->lds_max)
+            return fail(p, MBO_ERR_UNSUPPORTED, "axis of length %d needs more LDS than available", c.L);
+        c.lds = per_col * TX;
+    }
     c.TX = TX;
     c.block = dim3((unsigned)(T * TX));
     c.grid = dim3((unsigned)(c.outer * (c.S / TX)), (unsigned)p->batch);
-    c.lds = per_col * TX;
     return MBO_OK;
 }
 
@@ -258,11 +273,14 @@ mbo_status config_row(mbo_plan_t p)
     int rpw = 1;
     while (rpw * L < 256 && rpw * 2 <= rows) rpw *= 2;
     const size_t per_row = (size_t)p->PL * lds_len(L) * 2 * p->esz;
-    while (rpw > 1 && per_row * rpw > p->lds_max) rpw /= 2;
-    if (per_row * rpw > p->lds_max)
+    const size_t budget = p->lds_max - row_fb_lds((int)p->esz, p->n, ilog2(L));
+    while (rpw > 1 && per_row * rpw > budget) rpw /= 2;
+    if (per_row * rpw > budget)
         return fail(p, MBO_ERR_UNSUPPORTED,
                     "rows of length %d with %d packed planes need %zu bytes of LDS (max %zu)", L,
-                    p->PL, per_row, p->lds_max);
+                    p->PL, per_row, budget);
+    if (rpw * L > row_fb_queue_len(ilog2(L)))
+        return fail(p, MBO_ERR_UNSUPPORTED, "row workgroup of %d points exceeds its queue", rpw * L);
     const int nt = rpw * L < 512 ? rpw * L : 512;
     p->row_rpw = rpw;
     p->row_block = dim3((unsigned)nt);
@@ -297,7 +315,7 @@ ColArgs col_args(mbo_plan_t p, const ColCfg& c)
     a.L = c.L;
     a.log2L = ilog2(c.L);
     a.TX = c.TX;
-    a.lds_col = lds_len(c.L);
+    a.lds_col = c.pitch;
     a.S = c.S;
     a.tiles = c.S / c.TX;
     a.field_elems = (int64_t)p->PL * p->npts;

@@ -22,6 +22,9 @@ template <> struct num<float> {
     // stopping rule (columns orthogonal to working precision)
     static constexpr float eps = 1.1920928955078125e-07f;
     static constexpr float jtol2 = 1.4210854715202004e-14f;  // eps^2
+    // a sweep whose rotations all had |sin| below this leaves inner products
+    // of order sin^2 < eps: the next sweep would not rotate
+    static constexpr float sdone = 2.5e-4f;
     // hardware approximations (about 1 ulp): the rotation angle of a Jacobi step
     // need not be correctly rounded, any accurate rotation serves
     static __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -31,7 +34,15 @@ template <> struct num<float> {
 template <> struct num<double> {
     static constexpr double eps = 2.220446049250313e-16;
     static constexpr double jtol2 = 1e-30;  // (1e-15)^2
-    static __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+    static constexpr double sdone = 1e-8;
+    // hardware estimate refined by two Newton steps y <- y (3 - x y^2) / 2
+    static __device__ __forceinline__ double rsq(double x)
+    {
+        double y = __builtin_amdgcn_rsq(x);
+        y = y * (1.5 - 0.5 * x * y * y);
+        y = y * (1.5 - 0.5 * x * y * y);
+        return y;
+    }
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
 };
@@ -253,6 +264,67 @@ __device__ __forceinline__ void fft_stages(T (&r)[NP][8], T (&im)[NP][8], T* lr,
     }
 }
 
+// Orders LDS accesses among the lanes of one wave: a wave issues its LDS
+// operations in program order, so a fence at wavefront scope (which keeps the
+// compiler from moving LDS accesses across it) is all the exchange needs.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The same transform for a line whose L/8 threads lie inside one wave
+// (L <= 512): exchanges need no workgroup barrier.  LDS element j of the line is
+// at lr/li[lds_pad(j)].  Threads with act = false touch no LDS.
+template <typename T, int S, int LOG2L, int STAGE = 0>
+__device__ __forceinline__ void fft_wave(T (&r)[8], T (&im)[8], T* lr, T* li, int t,
+                                         const Twiddles<T, LOG2L>& tw, bool act)
+{
+    typedef FftShape<LOG2L> F;
+    static_assert(LOG2L <= 9, "a line must fit in one wave");
+    if constexpr (STAGE < F::NST) {
+        constexpr int R = F::radix(STAGE);
+        constexpr int p = 1 << F::log2span(STAGE);
+        if constexpr (STAGE == 0) stage_span1<T, R, S>(r, im);
+        else stage_tw8<T, S>(r, im, tw.w[STAGE - 1]);
+        if constexpr (STAGE != F::NST - 1) {
+            wave_lds_sync();  // earlier reads of the line are done
+            if (act) {
+                if constexpr (STAGE == 0) {
+                    constexpr int B = 8 / R;
+#pragma unroll
+                    for (int b = 0; b < B; ++b)
+#pragma unroll
+                        for (int q = 0; q < R; ++q) {
+                            const int a = lds_pad((t + b * F::Tn) * R + q);
+                            lr[a] = r[b + q * B];
+                            li[a] = im[b + q * B];
+                        }
+                } else {
+                    const int k = t & (p - 1);
+                    const int base = ((t - k) << 3) + k;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int a = lds_pad(base + q * p);
+                        lr[a] = r[q];
+                        li[a] = im[q];
+                    }
+                }
+            }
+            wave_lds_sync();
+            if (act) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int a = lds_pad(t + e * F::Tn);
+                    r[e] = lr[a];
+                    im[e] = li[a];
+                }
+            }
+            fft_wave<T, S, LOG2L, STAGE + 1>(r, im, lr, li, t, tw, act);
+        }
+    }
+}
+
 // In-place FFT of NP lines (S = -1 forward, +1 inverse, unscaled).  LDS element
 // j of line pl is at lr/li[pl*lplane + lds_pad(j)*lmul + ladd].  Every thread of
 // the workgroup must call it (it contains barriers); threads with act = false
@@ -327,20 +399,23 @@ __device__ __forceinline__ void polar2(const T* a, T* q, int& dsign, T& smin)
 // One-sided (Hestenes) Jacobi: rotate pairs of columns of W = A until they are
 // mutually orthogonal (to working precision), accumulating the rotations in V;
 // then sigma_j = |w_j|, U = W Sigma^{-1} and Q = U V^t.
+//
+// The rotation of a pair (p, r) with a = |w_p|^2, b = |w_r|^2, g = 2 w_p.w_r
+// zeroes their inner product: with h = b - a and k = |h| / sqrt(h^2 + g^2)
+// (= cos 2phi), c = sqrt((1 + k)/2) and s = sgn(h) g / (2 c sqrt(h^2 + g^2)), so
+// that c^2 + s^2 = 1 holds identically; only two reciprocal square roots are
+// needed.  It is applied unconditionally with (c, s) = (1, 0) when the pair is
+// already orthogonal, which keeps the wave free of divergent branches.  A lane
+// stops after a sweep without rotations, or after a sweep whose rotations all
+// had |s| < sdone (the inner products left are then of order s^2, below the
+// tolerance, so the confirming sweep is skipped).
 template <typename T, int n>
-__device__ __forceinline__ void polar_jacobi(const T* a, T* q, int& dsign, T& smin)
+__device__ __forceinline__ void jacobi_sweeps(T (&W)[n][n], T (&V)[n][n])
 {
-    T W[n][n], V[n][n];
-#pragma unroll
-    for (int i = 0; i < n; ++i)
-#pragma unroll
-        for (int j = 0; j < n; ++j) {
-            W[i][j] = a[i * n + j];
-            V[i][j] = (i == j) ? (T)1 : (T)0;
-        }
 #pragma unroll 1
     for (int sweep = 0; sweep < 30; ++sweep) {
         bool rotated = false;
+        T smax = 0;
 #pragma unroll
         for (int p = 0; p < n - 1; ++p) {
 #pragma unroll
@@ -352,31 +427,54 @@ __device__ __forceinline__ void polar_jacobi(const T* a, T* q, int& dsign, T& sm
                     be += W[i][r] * W[i][r];
                     ga += W[i][p] * W[i][r];
                 }
-                if (ga * ga > num<T>::jtol2 * (al * be)) {
-                    rotated = true;
-                    const T zeta = (be - al) * num<T>::rcp(2 * ga);
-                    const T az = zeta < (T)0 ? -zeta : zeta;
-                    const T iz = num<T>::rcp(az);
-                    const T hyp = az > (T)1 ? az * num<T>::sqrt_((T)1 + iz * iz)
-                                            : num<T>::sqrt_((T)1 + az * az);
-                    T tt = num<T>::rcp(az + hyp);
-                    if (zeta < (T)0) tt = -tt;
-                    const T c = num<T>::rsq((T)1 + tt * tt);
-                    const T s = c * tt;
+                const bool rot = ga * ga > num<T>::jtol2 * (al * be);
+                rotated = rotated || rot;
+                const T h = be - al;
+                const T g = ga + ga;
+                const T rinv = num<T>::rsq(h * h + g * g);
+                const T k = (h < (T)0 ? -h : h) * rinv;
+                const T hk = (T)0.5 + (T)0.5 * k;
+                const T qq = num<T>::rsq(hk);
+                const T c = rot ? hk * qq : (T)1;
+                const T sn = rot ? (h >= (T)0 ? g : -g) * rinv * (T)0.5 * qq : (T)0;
+                const T asn = sn < (T)0 ? -sn : sn;
+                smax = asn > smax ? asn : smax;
 #pragma unroll
-                    for (int i = 0; i < n; ++i) {
-                        const T wp = W[i][p], wr = W[i][r];
-                        W[i][p] = c * wp - s * wr;
-                        W[i][r] = s * wp + c * wr;
-                        const T vp = V[i][p], vr = V[i][r];
-                        V[i][p] = c * vp - s * vr;
-                        V[i][r] = s * vp + c * vr;
-                    }
+                for (int i = 0; i < n; ++i) {
+                    const T wp = W[i][p], wr = W[i][r];
+                    W[i][p] = c * wp - sn * wr;
+                    W[i][r] = sn * wp + c * wr;
+                    const T vp = V[i][p], vr = V[i][r];
+                    V[i][p] = c * vp - sn * vr;
+                    V[i][r] = sn * vp + c * vr;
                 }
             }
         }
-        if (!rotated) break;
+        if (!rotated || smax < num<T>::sdone) break;
     }
+}
+
+// Largest |entry| as a power of two 2^ex (ex = 0 for a zero or non-finite
+// matrix): scaling by 2^-ex is exact and keeps every square representable.
+template <typename T, int n>
+__device__ __forceinline__ int scale_exponent(const T* a)
+{
+    T amax = 0;
+#pragma unroll
+    for (int i = 0; i < n * n; ++i) {
+        const T v = a[i] < (T)0 ? -a[i] : a[i];
+        amax = v > amax ? v : amax;
+    }
+    int ex = 0;
+    if (amax > (T)0 && amax - amax == (T)0) (void)frexp(amax, &ex);
+    return ex;
+}
+
+// Q = U V^t from the orthogonalised columns W = U Sigma (scaled by 2^-ex).
+template <typename T, int n>
+__device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const T (&V)[n][n], int ex, T* q,
+                                              int& dsign, T& smin)
+{
     T ss[n], sg[n];
     T smax = 0;
     smin = 0;
@@ -390,6 +488,7 @@ __device__ __forceinline__ void polar_jacobi(const T* a, T* q, int& dsign, T& sm
         smax = sg[j] > smax ? sg[j] : smax;
         smin = (j == 0 || sg[j] < smin) ? sg[j] : smin;
     }
+    smin = ldexp(smin, ex);  // singular values of the unscaled input
     if (!(smax > (T)0)) {  // zero matrix (or NaN): identity
 #pragma unroll
         for (int i = 0; i < n * n; ++i) q[i] = (i % (n + 1) == 0) ? (T)1 : (T)0;
@@ -476,6 +575,68 @@ __device__ __forceinline__ void polar_jacobi(const T* a, T* q, int& dsign, T& sm
     dsign = dq >= (T)0 ? 1 : -1;
 }
 
+
+template <typename T, int n>
+__device__ __forceinline__ void polar_jacobi(const T* a_in, T* q, int& dsign, T& smin)
+{
+    const int ex = scale_exponent<T, n>(a_in);
+    T W[n][n], V[n][n];
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            W[i][j] = ldexp(a_in[i * n + j], -ex);
+            V[i][j] = (i == j) ? (T)1 : (T)0;
+        }
+    jacobi_sweeps<T, n>(W, V);
+    jacobi_finish<T, n>(W, V, ex, q, dsign, smin);
+}
+
+// The same in double, warm-started from the right singular vectors V0 of a
+// lower-precision run on the same matrix: V0 is re-orthonormalised in double
+// (modified Gram-Schmidt), W = A V0 is then nearly column-orthogonal and the
+// sweeps converge in one or two passes.  The result is the same closest
+// orthogonal matrix (unique for nonsingular A) to double rounding.
+template <int n>
+__device__ __forceinline__ void polar_jacobi_warm(const double* a_in, const float (&V0)[n][n],
+                                                  double* q, int& dsign, double& smin)
+{
+    const int ex = scale_exponent<double, n>(a_in);
+    double V[n][n], W[n][n];
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int j = 0; j < n; ++j) V[i][j] = (double)V0[i][j];
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+#pragma unroll
+        for (int k = 0; k < j; ++k) {
+            double d = 0;
+#pragma unroll
+            for (int i = 0; i < n; ++i) d += V[i][k] * V[i][j];
+#pragma unroll
+            for (int i = 0; i < n; ++i) V[i][j] -= d * V[i][k];
+        }
+        double nn = 0;
+#pragma unroll
+        for (int i = 0; i < n; ++i) nn += V[i][j] * V[i][j];
+        const double inv = num<double>::rsq(nn);
+#pragma unroll
+        for (int i = 0; i < n; ++i) V[i][j] *= inv;
+    }
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            double v = 0;
+#pragma unroll
+            for (int k = 0; k < n; ++k) v += a_in[i * n + k] * V[k][j];
+            W[i][j] = ldexp(v, -ex);
+        }
+    jacobi_sweeps<double, n>(W, V);
+    jacobi_finish<double, n>(W, V, ex, q, dsign, smin);
+}
+
 // Closest orthogonal matrix of a (n*n values).  Returns sgn det Q and the
 // smallest singular value of a (used by the double-precision fallback test).
 template <typename T, int n>
@@ -491,6 +652,77 @@ __device__ __forceinline__ void project_point(const T* a, T* q, int& dsign, T& s
     } else {
         polar_jacobi<T, n>(a, q, dsign, smin);
     }
+}
+
+// Float Jacobi of a point of a plan with the double fallback: when the smallest
+// singular value is below sigma_fb it stops before forming Q and returns true,
+// leaving in V the right singular vectors that warm-start the double run;
+// otherwise it returns false with the float result in q and dsign.
+template <int n>
+__device__ __forceinline__ bool polar_jacobi_f32_fb(const float* a, float* q, int& dsign,
+                                                    float (&V)[n][n], double sigma_fb)
+{
+    const int ex = scale_exponent<float, n>(a);
+    float W[n][n];
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            W[i][j] = ldexp(a[i * n + j], -ex);
+            V[i][j] = (i == j) ? 1.0f : 0.0f;
+        }
+    jacobi_sweeps<float, n>(W, V);
+    float s2 = 0;
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+        float v = 0;
+#pragma unroll
+        for (int i = 0; i < n; ++i) v += W[i][j] * W[i][j];
+        s2 = (j == 0 || v < s2) ? v : s2;
+    }
+    if ((double)ldexp(num<float>::sqrt_(s2), ex) < sigma_fb) return true;
+    float smin;
+    jacobi_finish<float, n>(W, V, ex, q, dsign, smin);
+    return false;
+}
+
+// Projection of a point in the plan's precision T, with the double-precision
+// fallback of float plans: when fallback is set and the float-computed smallest
+// singular value is below sigma_fb, the point is projected again in double from
+// the same float values (n = 2 by the closed form, n >= 3 by Jacobi
+// warm-started from the float run's V).  Returns true when it fell back.
+template <typename T, int n>
+__device__ __forceinline__ bool project_point_fb(const T* a, T* q, int& dsign, bool fallback,
+                                                 double sigma_fb)
+{
+    constexpr int NN = n * n;
+    if constexpr (sizeof(T) == 4 && n >= 3) {
+        if (fallback) {
+            float V[n][n];
+            if (!polar_jacobi_f32_fb<n>(a, q, dsign, V, sigma_fb)) return false;
+            double ad[NN], qd[NN], smd;
+#pragma unroll
+            for (int k = 0; k < NN; ++k) ad[k] = (double)a[k];
+            polar_jacobi_warm<n>(ad, V, qd, dsign, smd);
+#pragma unroll
+            for (int k = 0; k < NN; ++k) q[k] = (T)qd[k];
+            return true;
+        }
+    }
+    T smin;
+    project_point<T, n>(a, q, dsign, smin);
+    if constexpr (sizeof(T) == 4 && n == 2) {
+        if (fallback && (double)smin < sigma_fb) {
+            double ad[4], qd[4], smd;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) ad[k] = (double)a[k];
+            polar2<double>(ad, qd, dsign, smd);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q[k] = (T)qd[k];
+            return true;
+        }
+    }
+    return false;
 }
 
 // True when every one of the m values is finite.

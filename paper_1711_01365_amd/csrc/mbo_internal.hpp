@@ -43,13 +43,25 @@ struct RowArgs {
     double sigma_fb;         // fallback threshold
 };
 
+// Double-precision re-projection queue of the float row pass for n >= 3: one
+// 16-bit index per point of the workgroup's rows (at most max(256, L) points)
+// and the float right singular vectors of the first ROW_FB_STASH queued points.
+constexpr int ROW_FB_STASH = 32;
+constexpr int row_fb_queue_len(int log2L) { return (1 << log2L) > 256 ? (1 << log2L) : 256; }
+// Static LDS the queue adds to a row-pass workgroup, in bytes.
+constexpr size_t row_fb_lds(int esz, int n, int log2L)
+{
+    return (esz == 4 && n >= 3) ? (size_t)row_fb_queue_len(log2L) * 2 + (size_t)ROW_FB_STASH * n * n * 4 + 16
+                                : 0;
+}
+
 // Modes of the strided-axis pass.
 enum ColMode : int { CM_FORWARD = 0, CM_INVERSE = 1, CM_HEAT = 2, CM_ENERGY = 3 };
 
 struct ColArgs {
     int L, log2L;            // transform length along the axis
     int TX;                  // inner indices per workgroup
-    int lds_col;             // lds_pad(L - 1) + 1
+    int lds_col;             // LDS words per line (>= lds_pad(L - 1) + 1)
     int64_t S;               // element stride along the axis (= inner extent)
     int64_t tiles;           // S / TX
     int64_t field_elems;     // complex elements per field (PL * npts)

@@ -8,9 +8,10 @@
 //              Two real entry planes travel as one complex plane z = A_p + i A_q;
 //              this is exact because the heat symbol is real and even in k.
 //   col_pass   FFT along a strided axis for a tile of TX neighbouring inner
-//              indices (coalesced TX-wide segments).  CM_HEAT fuses forward
-//              FFT -> heat symbol exp(-4 pi^2 tau |k|^2) (Section 5.1) and the
-//              Lyapunov partial sum_m symbol |Z|^2 (Section 4) -> inverse FFT.
+//              indices (coalesced TX-wide segments, staged through LDS when a
+//              line fits in one wave).  CM_HEAT fuses forward FFT -> heat symbol
+//              exp(-4 pi^2 tau |k|^2) (Section 5.1) and the Lyapunov partial
+//              sum_m symbol |Z|^2 (Section 4) -> inverse FFT.
 #pragma once
 
 #include "mbo_device.hpp"
@@ -63,14 +64,21 @@ __device__ V block_reduce(V v, V* sh /* >= 64 entries */)
 // Row pass.  A workgroup owns rpw rows (contiguous grid lines of length L) of
 // every packed plane: rpw * PL "lines".  Phase 1: groups of L/8 threads load
 // one line each (a round at a time), inverse-FFT it, and leave it in natural
-// order in LDS (line j at lr/li[j * lds_plane + lds_pad(x)]).  Phase 2: every
+// order in LDS (line j at lr/li[j * lds_plane + lds_pad(x)]).  For L <= 512 a
+// group lies inside one wave and its exchanges need no workgroup barrier.  Phase 2: every
 // thread takes points of the rows (one point per thread and pass over the
 // rpw*L points) for the projection and its diagnostics.  Phase 3: the groups
 // forward-FFT the lines from LDS and store the spectra.  The projection, which
 // dominates the arithmetic, thus runs one point per thread on all threads.
 // ---------------------------------------------------------------------------
+// Waves per SIMD the row pass is compiled for: float rows of up to 512 points
+// and n <= 3 are held to 128 VGPRs, so that two 512-thread workgroups share a
+// compute unit.
 template <typename T, int n, int LOG2L>
-__global__ void __launch_bounds__(512) row_pass(const RowArgs a)
+constexpr int row_waves_per_simd() { return (sizeof(T) == 4 && n <= 3 && LOG2L <= 9) ? 4 : 1; }
+
+template <typename T, int n, int LOG2L>
+__global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_pass(const RowArgs a)
 {
     constexpr int NN = n * n;
     constexpr int PL = (NN + 1) / 2;
@@ -99,10 +107,6 @@ __global__ void __launch_bounds__(512) row_pass(const RowArgs a)
     const int lp = a.lds_plane;
     T* lr = reinterpret_cast<T*>(smem_raw);
     T* li = lr + (size_t)nlines * lp;
-
-    Twiddles<T, LOG2L> tw;
-    if (flags & (RF_INVERSE | RF_FORWARD))
-        load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
 
     // ---- phase 1: lines into LDS (natural order), inverse FFT on the way
     for (int rd = 0; rd < rounds; ++rd) {
@@ -134,8 +138,15 @@ __global__ void __launch_bounds__(512) row_pass(const RowArgs a)
         T* lrj = lr + (size_t)(act ? j : 0) * lp;
         T* lij = li + (size_t)(act ? j : 0) * lp;
         if (flags & RF_INVERSE) {
-            fft_lines<T, +1, 1, LOG2L>(r, im, lrj, lij, 0, 1, 0, t, tw, act);
-            __syncthreads();  // the group has read its last exchange
+            Twiddles<T, LOG2L> tw;
+            load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
+            if constexpr (LOG2L <= 9) {
+                fft_wave<T, +1, LOG2L>(r[0], im[0], lrj, lij, t, tw, act);
+                wave_lds_sync();  // the line's last exchange has been read
+            } else {
+                fft_lines<T, +1, 1, LOG2L>(r, im, lrj, lij, 0, 1, 0, t, tw, act);
+                __syncthreads();  // the group has read its last exchange
+            }
         }
         if (act) {
 #pragma unroll
@@ -148,11 +159,48 @@ __global__ void __launch_bounds__(512) row_pass(const RowArgs a)
     __syncthreads();
 
     // ---- phase 2: per-point work, one point per thread and pass
+    // Float plans with the double fallback (n >= 3) queue the points whose
+    // smallest singular value is small (index, and the float V for the warm
+    // start) and re-project them in double after the pass loop, when the float
+    // state is dead: the double code then neither adds to the registers of the
+    // loop nor runs once per wave that holds such a point.
+    constexpr bool DEFER = sizeof(T) == 4 && n >= 3;
+    constexpr int QCAP = DEFER ? row_fb_queue_len(LOG2L) : 1;
+    constexpr int SCAP = DEFER ? ROW_FB_STASH : 1;
+    __shared__ unsigned short fq[QCAP];
+    __shared__ float fv[SCAP * NN];
+    __shared__ int fq_n;
     unsigned long long nflip = 0, nfb = 0, nbad = 0;
     double dmax = 0.0;
     if (flags & (RF_PROJECT | RF_SIGN_INIT | RF_STORE_REAL)) {
         T* Aout = reinterpret_cast<T*>(a.Aout) + (size_t)b * NN * npts;
         int8_t* sgn = a.sgn + (size_t)b * npts;
+        const bool defer = DEFER && (flags & RF_PROJECT) && (flags & RF_FALLBACK);
+        if (defer) {
+            if (tid == 0) fq_n = 0;
+            __syncthreads();
+        }
+        // diagnostics and write-back of a projected point
+        auto finish = [&](int64_t x, T* lrr, T* lir, const T (&qv)[NN], int ds) {
+            if (flags & RF_SIGN) {
+                nflip += (sgn[x] != (int8_t)ds) ? 1ull : 0ull;
+                sgn[x] = (int8_t)ds;
+            }
+            if (flags & RF_TRACK) {
+                // max |A_s - A_{s-1}|, A_{s-1} read from the caller's field
+#pragma unroll
+                for (int k = 0; k < NN; ++k) {
+                    const double dv = fabs((double)qv[k] - (double)Aout[(int64_t)k * npts + x]);
+                    dmax = dv > dmax ? dv : dmax;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NN; ++k) {
+                if (k & 1) lir[(k >> 1) * lp] = qv[k];
+                else lrr[(k >> 1) * lp] = qv[k];
+            }
+            if (NN & 1) lir[(NN >> 1) * lp] = (T)0;
+        };
         const int npass = (rpw * L) / NT;
 #pragma unroll 1
         for (int pp = 0; pp < npass; ++pp) {
@@ -173,48 +221,79 @@ __global__ void __launch_bounds__(512) row_pass(const RowArgs a)
                 nbad += all_finite<T, NN>(av) ? 0ull : 1ull;
                 T qv[NN];
                 int ds;
-                T smin;
-                project_point<T, n>(av, qv, ds, smin);
-                if constexpr (sizeof(T) == 4 && n >= 2) {
-                    if ((flags & RF_FALLBACK) && (double)smin < a.sigma_fb) {
-                        double ad[NN], qd[NN], smd;
+                bool queued = false;
+                if constexpr (DEFER) {
+                    if (defer) {
+                        float V[n][n];
+                        queued = polar_jacobi_f32_fb<n>(av, qv, ds, V, a.sigma_fb);
+                        if (queued) {
+                            const int s = atomicAdd(&fq_n, 1);
+                            fq[s] = (unsigned short)idx;
+                            if (s < SCAP) {
 #pragma unroll
-                        for (int k = 0; k < NN; ++k) ad[k] = (double)av[k];
-                        project_point<double, n>(ad, qd, ds, smd);
-#pragma unroll
-                        for (int k = 0; k < NN; ++k) qv[k] = (T)qd[k];
+                                for (int k = 0; k < NN; ++k) fv[s * NN + k] = V[k / n][k % n];
+                            }
+                        }
+                    } else {
+                        T smin;
+                        project_point<T, n>(av, qv, ds, smin);
+                    }
+                } else {
+                    if (project_point_fb<T, n>(av, qv, ds, (flags & RF_FALLBACK) != 0, a.sigma_fb))
                         ++nfb;
-                    }
                 }
-                if (flags & RF_SIGN) {
-                    nflip += (sgn[x] != (int8_t)ds) ? 1ull : 0ull;
-                    sgn[x] = (int8_t)ds;
-                }
-                if (flags & RF_TRACK) {
-                    // max |A_s - A_{s-1}|, A_{s-1} read from the caller's field
+                if (queued) continue;
+                finish(x, lrr, lir, qv, ds);
 #pragma unroll
-                    for (int k = 0; k < NN; ++k) {
-                        const double dv = fabs((double)qv[k] - (double)Aout[(int64_t)k * npts + x]);
-                        dmax = dv > dmax ? dv : dmax;
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < NN; ++k) {
-                    av[k] = qv[k];
-                    if (k & 1) lir[(k >> 1) * lp] = qv[k];
-                    else lrr[(k >> 1) * lp] = qv[k];
-                }
-                if (NN & 1) lir[(NN >> 1) * lp] = (T)0;
+                for (int k = 0; k < NN; ++k) av[k] = qv[k];
             }
             if (flags & RF_STORE_REAL) {
 #pragma unroll
                 for (int k = 0; k < NN; ++k) Aout[(int64_t)k * npts + x] = av[k];
             }
         }
+        if constexpr (DEFER) {
+            if (defer) {
+                __syncthreads();
+                const int nq = fq_n;
+#pragma unroll 1
+                for (int qi = tid; qi < nq; qi += NT) {
+                    const int idx = fq[qi];
+                    const int rloc = idx >> LOG2L;
+                    const int jx = lds_pad(idx & (L - 1));
+                    const int64_t x = (row0 + rloc) * L + (idx & (L - 1));
+                    T* lrr = lr + (size_t)rloc * PL * lp + jx;
+                    T* lir = li + (size_t)rloc * PL * lp + jx;
+                    double ad[NN], qd[NN], smd;
+                    float V[n][n];
+#pragma unroll
+                    for (int k = 0; k < NN; ++k) {
+                        ad[k] = (double)((k & 1) ? lir[(k >> 1) * lp] : lrr[(k >> 1) * lp]);
+                        // points beyond the stash start from V = I (a cold start)
+                        V[k / n][k % n] = qi < SCAP ? fv[qi * NN + k] : (k / n == k % n ? 1.0f : 0.0f);
+                    }
+                    int ds;
+                    polar_jacobi_warm<n>(ad, V, qd, ds, smd);
+                    T qv[NN];
+#pragma unroll
+                    for (int k = 0; k < NN; ++k) qv[k] = (T)qd[k];
+                    ++nfb;
+                    finish(x, lrr, lir, qv, ds);
+                    if (flags & RF_STORE_REAL) {
+#pragma unroll
+                        for (int k = 0; k < NN; ++k) Aout[(int64_t)k * npts + x] = qv[k];
+                    }
+                }
+            }
+        }
     }
 
     // ---- phase 3: forward FFT of the lines, store the spectra
     if (flags & RF_FORWARD) {
+        // twiddles are (re)loaded here rather than kept in registers through
+        // the projection
+        Twiddles<T, LOG2L> tw;
+        load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
         __syncthreads();
         for (int rd = 0; rd < rounds; ++rd) {
             const int j = rd * G + g;
@@ -231,7 +310,8 @@ __global__ void __launch_bounds__(512) row_pass(const RowArgs a)
                     im[0][e] = lij[lds_pad(t + e * Tn)];
                 }
             }
-            fft_lines<T, -1, 1, LOG2L>(r, im, lrj, lij, 0, 1, 0, t, tw, act);
+            if constexpr (LOG2L <= 9) fft_wave<T, -1, LOG2L>(r[0], im[0], lrj, lij, t, tw, act);
+            else fft_lines<T, -1, 1, LOG2L>(r, im, lrj, lij, 0, 1, 0, t, tw, act);
             if (st) {
                 C* Z = reinterpret_cast<C*>(a.Z) + ((size_t)b * PL + pl) * npts;
                 const int64_t x0 = (row0 + rloc) * L + t;
@@ -267,7 +347,7 @@ __global__ void __launch_bounds__(512) row_pass(const RowArgs a)
 // Strided-axis pass
 // ---------------------------------------------------------------------------
 template <typename T, int MODE, int LOG2L>
-__global__ void __launch_bounds__(512) col_pass(const ColArgs a)
+__global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) col_pass(const ColArgs a)
 {
     typedef typename cx<T>::type C;
     typedef FftShape<LOG2L> F;
@@ -292,7 +372,6 @@ __global__ void __launch_bounds__(512) col_pass(const ColArgs a)
     const int TX = a.TX;
     const int tid = threadIdx.x;
     const int tx = tid & (TX - 1);
-    const int t = tid / TX;
     // XCD-aware tile order: workgroups are dealt round-robin to the eight XCDs,
     // each with its own L2.  Give every XCD a contiguous run of tiles so that the
     // tiles sharing a 128-byte line (TX * sizeof(C) < 128) meet in one L2.
@@ -300,59 +379,135 @@ __global__ void __launch_bounds__(512) col_pass(const ColArgs a)
     const int64_t wg = (nwgx & 7) ? (int64_t)blockIdx.x
                                   : (int64_t)(blockIdx.x & 7) * (nwgx >> 3) + (blockIdx.x >> 3);
     const int64_t o = wg / a.tiles;
-    const int64_t inner = (wg - o * a.tiles) * TX + tx;
+    const int64_t tile0 = (wg - o * a.tiles) * TX;
     const int64_t S = a.S;
-    C* Z = reinterpret_cast<C*>(a.Z) + (size_t)b * a.field_elems + o * (int64_t)F::L * S + inner;
-    T* lr = reinterpret_cast<T*>(smem_raw);
-    T* li = lr + (size_t)a.lds_col * TX;
+    C* Zt = reinterpret_cast<C*>(a.Z) + (size_t)b * a.field_elems + o * (int64_t)F::L * S + tile0;
+    const C* tw_tab = reinterpret_cast<const C*>(a.tw);
 
-    T r[1][8], im[1][8];
+    if constexpr (LOG2L <= 9) {
+        // Tile of TX lines staged through LDS: coalesced row segments of TX
+        // elements in, one line per group of Tn threads (inside one wave), wave
+        // level exchanges, coalesced segments out.  Line c at lr/li[c * pitch].
+        const int pitch = a.lds_col;
+        T* lrb = reinterpret_cast<T*>(smem_raw);
+        T* lib = lrb + (size_t)TX * pitch;
+        const int nt = blockDim.x;
+        const int c = tid >> (LOG2L - 3);
+        const int tt = tid & (Tn - 1);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const C v = Z[(int64_t)(t + e * Tn) * S];
-        r[0][e] = v.x;
-        im[0][e] = v.y;
-    }
-    Twiddles<T, LOG2L> tw;
-    load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
-
-    if (MODE == CM_INVERSE)
-        fft_lines<T, +1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
-    else
-        fft_lines<T, -1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
-
-    if (MODE == CM_HEAT || MODE == CM_ENERGY) {
-        const T* lrow = reinterpret_cast<const T*>(a.lam_row);
-        const T lin = reinterpret_cast<const T*>(a.lam_inner)[inner];
-        double acc = 0.0;
+        for (int k = 0; k < 8; ++k) {
+            const int i = k * nt + tid;
+            const int row = i / TX, cc = i - (i / TX) * TX;
+            const C v = Zt[(int64_t)row * S + cc];
+            lrb[cc * pitch + lds_pad(row)] = v.x;
+            lib[cc * pitch + lds_pad(row)] = v.y;
+        }
+        Twiddles<T, LOG2L> tw;
+        load_twiddles<T, LOG2L>(tw, tw_tab, tt);
+        __syncthreads();
+        T* lr = lrb + (size_t)c * pitch;
+        T* li = lib + (size_t)c * pitch;
+        T r[8], im[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const T lam = lrow[t + e * Tn] * lin;
-            if (a.epart)
-                acc += (double)lam * ((double)r[0][e] * (double)r[0][e] +
-                                      (double)im[0][e] * (double)im[0][e]);
-            if (MODE == CM_HEAT) {
-                r[0][e] *= lam;
-                im[0][e] *= lam;
+            r[e] = lr[lds_pad(tt + e * Tn)];
+            im[e] = li[lds_pad(tt + e * Tn)];
+        }
+        if (MODE == CM_INVERSE) fft_wave<T, +1, LOG2L>(r, im, lr, li, tt, tw, true);
+        else fft_wave<T, -1, LOG2L>(r, im, lr, li, tt, tw, true);
+        if (MODE == CM_HEAT || MODE == CM_ENERGY) {
+            const T* lrow = reinterpret_cast<const T*>(a.lam_row);
+            const T lin = reinterpret_cast<const T*>(a.lam_inner)[tile0 + c];
+            double acc = 0.0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const T lam = lrow[tt + e * Tn] * lin;
+                if (a.epart)
+                    acc += (double)lam * ((double)r[e] * (double)r[e] + (double)im[e] * (double)im[e]);
+                if (MODE == CM_HEAT) {
+                    r[e] *= lam;
+                    im[e] *= lam;
+                }
+            }
+            if (a.epart) {
+                acc = block_reduce<OpSum>(acc, red_d);
+                if (tid == 0) {
+                    const int slot = a.slot >= 0 ? a.slot : a.stop_iter[b];
+                    a.epart[((int64_t)b * (a.K + 1) + slot) * a.nwg + wg] = acc;
+                }
             }
         }
-        if (a.epart) {
-            acc = block_reduce<OpSum>(acc, red_d);
-            if (tid == 0) {
-                const int slot = a.slot >= 0 ? a.slot : a.stop_iter[b];
-                a.epart[((int64_t)b * (a.K + 1) + slot) * a.nwg + wg] = acc;
+        if (MODE == CM_HEAT) fft_wave<T, +1, LOG2L>(r, im, lr, li, tt, tw, true);
+        if (MODE != CM_ENERGY) {
+            wave_lds_sync();  // the line's last exchange has been read
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                lr[lds_pad(tt + e * Tn)] = r[e];
+                li[lds_pad(tt + e * Tn)] = im[e];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int i = k * nt + tid;
+                const int row = i / TX, cc = i - (i / TX) * TX;
+                C v;
+                v.x = lrb[cc * pitch + lds_pad(row)];
+                v.y = lib[cc * pitch + lds_pad(row)];
+                Zt[(int64_t)row * S + cc] = v;
             }
         }
-    }
-    if (MODE == CM_HEAT) fft_lines<T, +1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
-
-    if (MODE != CM_ENERGY) {
+    } else {
+        // Long lines (L > 512): each line spans several waves; thread (t, tx)
+        // holds x[t + e*L/8] of line tx and the exchanges use workgroup barriers.
+        const int t = tid / TX;
+        C* Z = Zt + tx;
+        T* lr = reinterpret_cast<T*>(smem_raw);
+        T* li = lr + (size_t)a.lds_col * TX;
+        T r[1][8], im[1][8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            C v;
-            v.x = r[0][e];
-            v.y = im[0][e];
-            Z[(int64_t)(t + e * Tn) * S] = v;
+            const C v = Z[(int64_t)(t + e * Tn) * S];
+            r[0][e] = v.x;
+            im[0][e] = v.y;
+        }
+        Twiddles<T, LOG2L> tw;
+        load_twiddles<T, LOG2L>(tw, tw_tab, t);
+        if (MODE == CM_INVERSE)
+            fft_lines<T, +1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
+        else
+            fft_lines<T, -1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
+        if (MODE == CM_HEAT || MODE == CM_ENERGY) {
+            const T* lrow = reinterpret_cast<const T*>(a.lam_row);
+            const T lin = reinterpret_cast<const T*>(a.lam_inner)[tile0 + tx];
+            double acc = 0.0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const T lam = lrow[t + e * Tn] * lin;
+                if (a.epart)
+                    acc += (double)lam * ((double)r[0][e] * (double)r[0][e] +
+                                          (double)im[0][e] * (double)im[0][e]);
+                if (MODE == CM_HEAT) {
+                    r[0][e] *= lam;
+                    im[0][e] *= lam;
+                }
+            }
+            if (a.epart) {
+                acc = block_reduce<OpSum>(acc, red_d);
+                if (tid == 0) {
+                    const int slot = a.slot >= 0 ? a.slot : a.stop_iter[b];
+                    a.epart[((int64_t)b * (a.K + 1) + slot) * a.nwg + wg] = acc;
+                }
+            }
+        }
+        if (MODE == CM_HEAT) fft_lines<T, +1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
+        if (MODE != CM_ENERGY) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                C v;
+                v.x = r[0][e];
+                v.y = im[0][e];
+                Z[(int64_t)(t + e * Tn) * S] = v;
+            }
         }
     }
 }

@@ -24,19 +24,7 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjArgs a)
         for (int k = 0; k < NN; ++k) av[k] = A[(int64_t)k * a.npts + p];
         bad = !all_finite<T, NN>(av);
         int ds;
-        T smin;
-        project_point<T, n>(av, qv, ds, smin);
-        if constexpr (sizeof(T) == 4 && n >= 2) {
-            if (a.fallback && (double)smin < a.sigma_fb) {
-                double ad[NN], qd[NN], smd;
-#pragma unroll
-                for (int k = 0; k < NN; ++k) ad[k] = (double)av[k];
-                project_point<double, n>(ad, qd, ds, smd);
-#pragma unroll
-                for (int k = 0; k < NN; ++k) qv[k] = (T)qd[k];
-                fb = 1;
-            }
-        }
+        fb = project_point_fb<T, n>(av, qv, ds, a.fallback != 0, a.sigma_fb) ? 1ull : 0ull;
 #pragma unroll
         for (int k = 0; k < NN; ++k) Q[(int64_t)k * a.npts + p] = qv[k];
         if (a.dsign) a.dsign[(size_t)b * a.npts + p] = (int8_t)ds;
