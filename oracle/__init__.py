@@ -18,6 +18,11 @@ What each function follows (Osting & Wang, arXiv:1711.01365):
                   U V^t of Lemma 1.1, by one-sided Jacobi SVD.
   * ``energy``    Lyapunov functional of Section 4, with weight 1/prod(grid).
   * ``iterate``   Algorithm 1, with the per-iteration logs used by the tests.
+  * ``heat_dtau`` derivative of the diffusion step in tau (symbol
+                  -4 pi^2 |k|^2 exp(-4 pi^2 tau |k|^2)).
+  * ``project_vjp``  vector-Jacobian product of the projection U V^t.
+  * ``unroll_grad``  loss (1/2)||A_K - T||^2 of K steps of Algorithm 1 and its
+                  gradients in A_0 and tau, by the chain rule run backwards.
   * ``dft_naive`` / ``fft``   the discrete Fourier transform by definition and
                   by radix-2 Cooley-Tukey (cross-checked against each other).
 """
@@ -74,9 +79,14 @@ def _load():
     lib.orc_iterate.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_double, _d,
                                 ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_int),
                                 _d, _i64, _d, _d, ctypes.c_int]
+    lib.orc_heat_dtau.argtypes = [ctypes.c_int, _i64, ctypes.c_int64, ctypes.c_double, _d, _d]
+    lib.orc_project_vjp.argtypes = [ctypes.c_int64, ctypes.c_int, _d, _d, _d]
+    lib.orc_unroll_grad.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_double, _d, _d,
+                                    ctypes.c_int, _d, _d, _d, _i64]
     lib.orc_num_threads.argtypes = []
     for f in ("orc_dft_naive", "orc_fft", "orc_heat", "orc_project", "orc_det_sign",
-              "orc_energy", "orc_iterate", "orc_num_threads"):
+              "orc_energy", "orc_iterate", "orc_num_threads", "orc_heat_dtau", "orc_project_vjp",
+              "orc_unroll_grad"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -208,3 +218,49 @@ def iterate(A0: np.ndarray, tau: float, K: int, tol: float = 0.0, naive: bool = 
     s = it.value
     return {"A": A, "iters": s, "energy": en[: s + 1], "flips": fl[:s], "delta": dl[:s],
             "max_imag": float(mi[0])}
+
+
+def heat_dtau(planes: np.ndarray, tau: float, grid_ndim: int) -> np.ndarray:
+    """d/dtau of e^{tau Delta} applied to every real plane (FFT route)."""
+    lib = _load()
+    a = np.ascontiguousarray(planes, dtype=np.float64)
+    grid = a.shape[a.ndim - grid_ndim:]
+    nplanes = int(np.prod(a.shape[:a.ndim - grid_ndim], dtype=np.int64))
+    g, d = _grid(grid)
+    out = np.empty_like(a)
+    _check(lib.orc_heat_dtau(d, _ptr(g, _i64), nplanes, float(tau), _ptr(a), _ptr(out)),
+           "heat_dtau")
+    return out
+
+
+def project_vjp(A: np.ndarray, G: np.ndarray) -> np.ndarray:
+    """Cotangent of A for the cotangent G of Q = U V^t, per point.  Shapes (n, n, *grid)."""
+    lib = _load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    assert A.shape == G.shape
+    n = A.shape[0]
+    P = int(np.prod(A.shape[2:], dtype=np.int64))
+    GA = np.empty_like(A)
+    _check(lib.orc_project_vjp(P, n, _ptr(A), _ptr(G), _ptr(GA)), "project_vjp")
+    return GA
+
+
+def unroll_grad(A0: np.ndarray, T: np.ndarray, tau: float, K: int):
+    """Loss (1/2) sum ||A_K - T||_F^2 of K steps of Algorithm 1 and its gradients.
+
+    Returns a dict: loss, gA0 (shape of A0), gtau, flips [K] of the forward run.
+    """
+    lib = _load()
+    A0 = np.ascontiguousarray(A0, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    assert A0.shape == T.shape
+    n = A0.shape[0]
+    g, d = _grid(A0.shape[2:])
+    loss = np.zeros(1)
+    gtau = np.zeros(1)
+    gA0 = np.empty_like(A0)
+    fl = np.zeros(max(K, 1), dtype=np.int64)
+    _check(lib.orc_unroll_grad(d, _ptr(g, _i64), n, float(tau), _ptr(A0), _ptr(T), int(K),
+                               _ptr(loss), _ptr(gA0), _ptr(gtau), _ptr(fl, _i64)), "unroll_grad")
+    return {"loss": float(loss[0]), "gA0": gA0, "gtau": float(gtau[0]), "flips": fl[:K]}

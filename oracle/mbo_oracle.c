@@ -221,8 +221,39 @@ static void orc_transform(int d, const int64_t* N, double* re, double* im, int s
  * plane is transformed, multiplied by the heat symbol and transformed back,
  * out = F^{-1}( symbol * F(in) ).  `nplanes` planes of prod(N) values.
  * max_imag (nullable) receives max |Im| left after the inverse transform. */
+static int orc_apply_symbol(int d, const int64_t* N, int64_t nplanes, double tau, const double* in,
+                            double* out, int use_naive, double* max_imag, int dtau);
+
 int orc_heat(int d, const int64_t* N, int64_t nplanes, double tau, const double* in,
              double* out, int use_naive, double* max_imag)
+{
+    return orc_apply_symbol(d, N, nplanes, tau, in, out, use_naive, max_imag, 0);
+}
+
+/* Derivative of the diffusion step with respect to tau (used by the adjoint):
+ * d/dtau e^{tau Delta} = Delta e^{tau Delta}, whose Fourier symbol is
+ * -4 pi^2 |k|^2 exp(-4 pi^2 tau |k|^2).  Same conventions as orc_heat. */
+int orc_heat_dtau(int d, const int64_t* N, int64_t nplanes, double tau, const double* in,
+                  double* out)
+{
+    return orc_apply_symbol(d, N, nplanes, tau, in, out, 0, NULL, 1);
+}
+
+/* -4 pi^2 |k|^2 for the multi-index m (same wrap-around as the heat symbol). */
+static double orc_laplace_symbol(int d, const int64_t* N, int64_t flat)
+{
+    double ksq = 0.0;
+    for (int a = d - 1; a >= 0; --a) {
+        int64_t m = flat % N[a];
+        flat /= N[a];
+        int64_t k = (2 * m < N[a]) ? m : m - N[a];
+        ksq += (double)k * (double)k;
+    }
+    return -4.0 * ORC_PI * ORC_PI * ksq;
+}
+
+static int orc_apply_symbol(int d, const int64_t* N, int64_t nplanes, double tau, const double* in,
+                            double* out, int use_naive, double* max_imag, int dtau)
 {
     if (d < 1 || d > 3 || nplanes < 1 || !(tau >= 0.0)) return -1;
     if (!use_naive)
@@ -239,6 +270,7 @@ int orc_heat(int d, const int64_t* N, int64_t nplanes, double tau, const double*
         orc_transform(d, N, re, im, -1, use_naive, tr, ti);
         for (int64_t m = 0; m < P; ++m) {
             double g = orc_heat_symbol(d, N, m, tau);
+            if (dtau) g *= orc_laplace_symbol(d, N, m);
             re[m] *= g;
             im[m] *= g;
         }
@@ -262,11 +294,24 @@ int orc_heat(int d, const int64_t* N, int64_t nplanes, double tau, const double*
  * orthogonalise the columns of W = A by plane rotations, accumulating them in
  * V, so that W = U Sigma with sigma_j = ||w_j||.  Then Q = U V^t, the minimiser
  * of ||B - A||_F over orthogonal B (Lemma 1.1).  Returns the sweep count. */
+static int orc_project_point_usv(int n, const double* a, double* q, double* sig, double* Uo,
+                                 double* Vo);
+
 static int orc_project_point(int n, const double* a, double* q, double* sig)
+{
+    return orc_project_point_usv(n, a, q, sig, NULL, NULL);
+}
+
+/* The same, also returning (nullable) the factors U and V of Q = U V^t, row
+ * major, with U completed as described for singular input; A = U diag(sig) V^t. */
+static int orc_project_point_usv(int n, const double* a, double* q, double* sig, double* Uo,
+                                 double* Vo)
 {
     if (n == 1) {
         q[0] = (double)orc_sgn(a[0]);
         if (sig) sig[0] = fabs(a[0]);
+        if (Uo) Uo[0] = q[0];
+        if (Vo) Vo[0] = 1.0;
         return 0;
     }
     double W[16], V[16];
@@ -315,6 +360,8 @@ static int orc_project_point(int n, const double* a, double* q, double* sig)
     if (smax == 0.0) { /* A = 0: every orthogonal matrix is equally close; take I */
         for (int i = 0; i < n * n; ++i) q[i] = 0.0;
         for (int i = 0; i < n; ++i) q[i * n + i] = 1.0;
+        if (Uo) memcpy(Uo, q, sizeof(double) * n * n);
+        if (Vo) memcpy(Vo, q, sizeof(double) * n * n);
         return sweep;
     }
     /* U: normalised columns; columns with a (numerically) zero singular value
@@ -361,6 +408,8 @@ static int orc_project_point(int n, const double* a, double* q, double* sig)
                 q[i * n + k] = s;
             }
     }
+    if (Uo) memcpy(Uo, U, sizeof(double) * n * n);
+    if (Vo) memcpy(Vo, V, sizeof(double) * n * n);
     return sweep;
 }
 
@@ -481,6 +530,123 @@ int orc_iterate(int d, const int64_t* N, int n, double tau, double* A, int K, do
     if (iters) *iters = done;
     if (max_imag) *max_imag = mi_all;
     free(At); free(An); free(sp); free(sn);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of K unrolled steps of Algorithm 1                                */
+/* ------------------------------------------------------------------------ */
+
+/* Vector-Jacobian product of the projection step (Lemma 1.1: Q = U V^t for
+ * A = U Sigma V^t).  A perturbation dA moves the orthogonal polar factor by
+ * dQ = U X V^t with X skew, X_ij = (F_ij - F_ji) / (sigma_i + sigma_j) and
+ * F = U^t dA V.  Hence for a cotangent G of Q the cotangent of A is
+ *     G_A = U K V^t,  K_ij = (M_ij - M_ji) / (sigma_i + sigma_j),  M = U^t G V,
+ * (K_ii = 0).  n = 1 (sign thresholding) has zero derivative away from 0.  A
+ * pair with sigma_i + sigma_j = 0 (rank <= n - 2, where Q is not a function of
+ * A) contributes 0. */
+int orc_project_vjp(int64_t npts, int n, const double* A, const double* G, double* GA)
+{
+    if (npts < 0 || n < 1 || n > 4) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < npts; ++p) {
+        double a[16], g[16], q[16], sg[4], U[16], V[16], M[16], Kx[16], T1[16];
+        for (int e = 0; e < n * n; ++e) {
+            a[e] = A[e * npts + p];
+            g[e] = G[e * npts + p];
+        }
+        if (n == 1) {
+            GA[p] = 0.0;
+            continue;
+        }
+        orc_project_point_usv(n, a, q, sg, U, V);
+        for (int i = 0; i < n; ++i)          /* M = U^t G V */
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < n; ++k)
+                    for (int l = 0; l < n; ++l) s += U[k * n + i] * g[k * n + l] * V[l * n + j];
+                M[i * n + j] = s;
+            }
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double den = sg[i] + sg[j];
+                Kx[i * n + j] = (i == j || den == 0.0) ? 0.0 : (M[i * n + j] - M[j * n + i]) / den;
+            }
+        for (int i = 0; i < n; ++i)          /* T1 = U K */
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < n; ++k) s += U[i * n + k] * Kx[k * n + j];
+                T1[i * n + j] = s;
+            }
+        for (int i = 0; i < n; ++i)          /* G_A = T1 V^t */
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < n; ++k) s += T1[i * n + k] * V[j * n + k];
+                GA[(i * n + j) * npts + p] = s;
+            }
+    }
+    return 0;
+}
+
+/* Loss L = (1/2) sum_p ||A_K(p) - T(p)||_F^2 of K steps of Algorithm 1 from A_0
+ * and its gradients by the chain rule taken backwards:
+ *     Gbar_K = A_K - T;  for s = K..1:
+ *         Gtil_s = VJP of the projection at Atil_s = e^{tau Delta} A_{s-1},
+ *         dL/dtau += <Gtil_s, Delta e^{tau Delta} A_{s-1}>,
+ *         Gbar_{s-1} = e^{tau Delta} Gtil_s   (the heat operator is self-adjoint);
+ *     dL/dA_0 = Gbar_0.
+ * All iterates are kept.  flips (nullable, [K]) logs the det sign changes of
+ * the forward run, as orc_iterate does. */
+int orc_unroll_grad(int d, const int64_t* N, int n, double tau, const double* A0, const double* T,
+                    int K, double* loss, double* gA0, double* gtau, int64_t* flips)
+{
+    if (n < 1 || n > 4 || !(tau > 0.0) || K < 0) return -1;
+    int64_t P = orc_npoints(d, N);
+    int64_t nn = (int64_t)n * n, F = P * nn;
+    double* As = (double*)malloc(sizeof(double) * (size_t)(F * (K + 1)));
+    double* At = (double*)malloc(sizeof(double) * (size_t)F);
+    double* Gb = (double*)malloc(sizeof(double) * (size_t)F);
+    double* Gt = (double*)malloc(sizeof(double) * (size_t)F);
+    double* Dt = (double*)malloc(sizeof(double) * (size_t)F);
+    int8_t* sp = (int8_t*)malloc((size_t)P);
+    int8_t* sn = (int8_t*)malloc((size_t)P);
+    int rc = 0;
+    memcpy(As, A0, sizeof(double) * (size_t)F);
+    orc_det_sign(P, n, As, sp);
+    for (int s = 1; s <= K && rc == 0; ++s) {
+        rc = orc_heat(d, N, nn, tau, As + (s - 1) * F, At, 0, NULL);
+        if (rc) break;
+        orc_project(P, n, At, As + s * F, sn, NULL, NULL);
+        int64_t fl = 0;
+        for (int64_t p = 0; p < P; ++p) fl += (sn[p] != sp[p]);
+        if (flips) flips[s - 1] = fl;
+        memcpy(sp, sn, (size_t)P);
+    }
+    double gt = 0.0;
+    if (rc == 0) {
+        const double* AK = As + (int64_t)K * F;
+        for (int64_t k = 0; k < F; ++k) {
+            Gb[k] = AK[k] - T[k];
+            Dt[k] = 0.5 * Gb[k] * Gb[k];
+        }
+        *loss = orc_pairwise_sum(Dt, F);
+        for (int s = K; s >= 1 && rc == 0; --s) {
+            const double* Aprev = As + (int64_t)(s - 1) * F;
+            rc = orc_heat(d, N, nn, tau, Aprev, At, 0, NULL);
+            if (rc) break;
+            orc_project_vjp(P, n, At, Gb, Gt);
+            rc = orc_heat_dtau(d, N, nn, tau, Aprev, Dt);
+            if (rc) break;
+            for (int64_t k = 0; k < F; ++k) Dt[k] *= Gt[k];
+            gt += orc_pairwise_sum(Dt, F);
+            rc = orc_heat(d, N, nn, tau, Gt, Gb, 0, NULL);
+        }
+    }
+    if (rc == 0) {
+        memcpy(gA0, Gb, sizeof(double) * (size_t)F);
+        *gtau = gt;
+    }
+    free(As); free(At); free(Gb); free(Gt); free(Dt); free(sp); free(sn);
     return rc;
 }
 
