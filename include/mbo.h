@@ -149,6 +149,39 @@ mbo_status mbo_iterate(mbo_plan_t plan, void* A, int max_iter, double tol, int* 
  * E: host, [batch].  Synchronises the stream. */
 mbo_status mbo_energy(mbo_plan_t plan, const void* A, double* E);
 
+/* ---------------------------------------------------------------------------
+ * Adjoint building blocks.  The paper stops at the forward iteration; these
+ * calls differentiate it.  With L a scalar function of A_K = P(H A_{K-1}) ...,
+ * H = e^{tau Delta}, the chain rule runs backwards over s = K..1:
+ *     Gtil_s = mbo_project_vjp(H A_{s-1}, Gbar_s)
+ *     dL/dtau += <Gtil_s, d/dtau H A_{s-1}>       (mbo_diffuse_dtau with G, dot)
+ *     Gbar_{s-1} = H Gtil_s                        (mbo_diffuse: H is self-adjoint)
+ * and dL/dA_0 = Gbar_0.
+ * ------------------------------------------------------------------------- */
+
+/* Vector-Jacobian product of the projection step (Lemma 1.1): for every point,
+ * with A_tilde = U Sigma V^t (so that the projection is Q = U V^t) and the
+ * cotangent G_Q of Q,
+ *     G_A = U K V^t,   K_ij = (M_ij - M_ji) / (sigma_i + sigma_j),   M = U^t G_Q V,
+ * K_ii = 0; a pair with sigma_i + sigma_j = 0 (rank <= n-2, where the projection
+ * is not a function of A_tilde) contributes 0.  n = 1 gives G_A = 0 (sign
+ * thresholding is locally constant).  Float plans with the double fallback
+ * evaluate points whose smallest singular value is below sigma_fallback in
+ * double.  All three fields are device buffers in the plan's layout; G_A may
+ * alias G_Q but not A_tilde.  Returns MBO_ERR_NONFINITE (after synchronising) if
+ * A_tilde holds NaN/Inf. */
+mbo_status mbo_project_vjp(mbo_plan_t plan, const void* A_tilde, const void* G_Q, void* G_A);
+
+/* Derivative of the diffusion step (Section 5.1) with respect to tau:
+ *     out = d/dtau e^{tau Delta} A = Delta e^{tau Delta} A,
+ * Fourier symbol -4 pi^2 |k|^2 exp(-4 pi^2 tau |k|^2), entry by entry.
+ * out (device, nullable) receives the field; if G (device) and dot (host,
+ * [batch]) are both given, dot[b] = sum over grid points and entries of
+ * G_b * (d/dtau e^{tau Delta} A_b), accumulated in double, and the call
+ * synchronises the stream.  At least one of out and (G, dot) must be given.
+ * out may alias A. */
+mbo_status mbo_diffuse_dtau(mbo_plan_t plan, const void* A, void* out, const void* G, double* dot);
+
 /* Human-readable name of a status code (static storage). */
 const char* mbo_status_string(mbo_status s);
 

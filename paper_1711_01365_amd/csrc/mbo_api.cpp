@@ -66,6 +66,10 @@ struct mbo_plan_s {
     void* tw[3] = {nullptr, nullptr, nullptr};
     void* lam_row = nullptr;    // heat axis (axis 0) factor [N0]
     void* lam_inner = nullptr;  // product over the faster axes [npts / N0]
+    void* mu_row = nullptr;     // -4 pi^2 k^2 of axis 0 [N0]
+    void* mu_inner = nullptr;   // -4 pi^2 |k|^2 over the faster axes [npts / N0]
+    double* dpart = nullptr;    // dot-product partials [batch][row workgroups]
+    double* dsum = nullptr;     // [batch]
     unsigned long long* counters = nullptr;  // project: [0] nonfinite, [1] fallbacks
 
     // launch configuration
@@ -157,6 +161,10 @@ void destroy(mbo_plan_t p)
     }
     free_dev(p->lam_row);
     free_dev(p->lam_inner);
+    free_dev(p->mu_row);
+    free_dev(p->mu_inner);
+    free_dev(p->dpart);
+    free_dev(p->dsum);
     free_dev(p->counters);
     free_dev(p->epart);
     free_dev(p->energy);
@@ -211,6 +219,36 @@ mbo_status build_symbol_tables(mbo_plan_t p)
     mbo_status s = upload(p, p->lam_row, row);
     if (s != MBO_OK) return s;
     return upload(p, p->lam_inner, inner);
+}
+
+// -4 pi^2 k^2 per index of an axis (same wrap-around as axis_symbol).
+std::vector<double> axis_laplace(int64_t N)
+{
+    std::vector<double> v((size_t)N);
+    const double pi = 3.14159265358979323846;
+    for (int64_t m = 0; m < N; ++m) {
+        const double k = (2 * m < N) ? (double)m : (double)(m - N);
+        v[(size_t)m] = -4.0 * pi * pi * k * k;
+    }
+    return v;
+}
+
+// Tables of the tau-derivative multiplier: -4 pi^2 |k|^2 = row + inner term.
+mbo_status build_laplace_tables(mbo_plan_t p)
+{
+    std::vector<double> row = axis_laplace(p->N[0]);
+    const int64_t inner_n = p->npts / p->N[0];
+    std::vector<double> inner((size_t)inner_n);
+    if (p->d == 2) {
+        inner = axis_laplace(p->N[1]);
+    } else {
+        std::vector<double> ly = axis_laplace(p->N[1]), lx = axis_laplace(p->N[2]);
+        for (int64_t y = 0; y < p->N[1]; ++y)
+            for (int64_t x = 0; x < p->N[2]; ++x) inner[(size_t)(y * p->N[2] + x)] = ly[(size_t)y] + lx[(size_t)x];
+    }
+    mbo_status s = upload(p, p->mu_row, row);
+    if (s != MBO_OK) return s;
+    return upload(p, p->mu_inner, inner);
 }
 
 // Twiddles exp(-2 pi i m / L), m < L, interleaved (re, im).
@@ -323,6 +361,8 @@ ColArgs col_args(mbo_plan_t p, const ColCfg& c)
     a.Z = p->Z;
     a.lam_row = p->lam_row;
     a.lam_inner = p->lam_inner;
+    a.mu_row = p->mu_row;
+    a.mu_inner = p->mu_inner;
     a.nwg = (int)(c.outer * (c.S / c.TX));
     a.slot = 0;
     return a;
@@ -604,6 +644,11 @@ mbo_status mbo_plan(mbo_plan_t* out, int d, const int64_t* N, int n, int64_t bat
     PLAN_TRY(hipMalloc(&p->lam_row, (size_t)N[0] * p->esz));
     PLAN_TRY(hipMalloc(&p->lam_inner, (size_t)(p->npts / N[0]) * p->esz));
     PLAN_STATUS(build_symbol_tables(p));
+    PLAN_TRY(hipMalloc(&p->mu_row, (size_t)N[0] * p->esz));
+    PLAN_TRY(hipMalloc(&p->mu_inner, (size_t)(p->npts / N[0]) * p->esz));
+    PLAN_STATUS(build_laplace_tables(p));
+    PLAN_TRY(hipMalloc((void**)&p->dpart, (size_t)batch * p->row_grid.x * sizeof(double)));
+    PLAN_TRY(hipMalloc((void**)&p->dsum, (size_t)batch * sizeof(double)));
 #undef PLAN_TRY
 #undef PLAN_STATUS
     *out = p;
@@ -686,6 +731,58 @@ mbo_status mbo_project(mbo_plan_t p, const void* A_in, void* A_out, int8_t* det_
     a.fallback = p->prec == MBO_F32_F64FALLBACK;
     a.sigma_fb = p->sigma_fb;
     HIP_TRY(p, launch_project(p->pk, p->n, a, (int)p->batch, p->stream));
+    unsigned long long h[4];
+    HIP_TRY(p, hipMemcpyAsync(h, p->counters, sizeof h, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    if (h[0]) return fail(p, MBO_ERR_NONFINITE, "%llu points with NaN/Inf input", h[0]);
+    return MBO_OK;
+}
+
+mbo_status mbo_diffuse_dtau(mbo_plan_t p, const void* A, void* out, const void* G, double* dot)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (!A) return fail(p, MBO_ERR_INVALID_ARG, "A is NULL");
+    const bool want_dot = G != nullptr && dot != nullptr;
+    if (!out && !want_dot) return fail(p, MBO_ERR_INVALID_ARG, "neither out nor (G, dot) given");
+    if ((G == nullptr) != (dot == nullptr)) return fail(p, MBO_ERR_INVALID_ARG, "G and dot go together");
+    HIP_TRY(p, hipSetDevice(p->device));
+    HIP_TRY(p, enqueue_forward(p, A, 0, true, p->stream));
+    ColArgs h = col_args(p, p->heat);
+    HIP_TRY(p, run_col(p, p->heat, CM_DTAU, h, p->stream));
+    if (p->d == 3) {
+        ColArgs y = col_args(p, p->ypass);
+        HIP_TRY(p, run_col(p, p->ypass, CM_INVERSE, y, p->stream));
+    }
+    RowArgs r = row_args(p);
+    r.Aout = out;
+    r.flags = RF_INVERSE | (out ? RF_STORE_REAL : 0) | (want_dot ? RF_DOT : 0);
+    r.Gdot = G;
+    r.dpart = p->dpart;
+    HIP_TRY(p, run_row(p, r, p->stream));
+    if (want_dot) {
+        HIP_TRY(p, launch_sum_rows(p->dpart, (int64_t)p->row_grid.x, (int)p->batch, p->dsum, p->stream));
+        HIP_TRY(p, hipMemcpyAsync(dot, p->dsum, (size_t)p->batch * sizeof(double), hipMemcpyDeviceToHost,
+                                  p->stream));
+        HIP_TRY(p, hipStreamSynchronize(p->stream));
+    }
+    return MBO_OK;
+}
+
+mbo_status mbo_project_vjp(mbo_plan_t p, const void* A_tilde, const void* G_Q, void* G_A)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (!A_tilde || !G_Q || !G_A) return fail(p, MBO_ERR_INVALID_ARG, "A_tilde / G_Q / G_A is NULL");
+    HIP_TRY(p, hipSetDevice(p->device));
+    HIP_TRY(p, launch_fill_u64(p->counters, 4, 0ull, p->stream));
+    VjpArgs a;
+    a.npts = p->npts;
+    a.A = A_tilde;
+    a.G = G_Q;
+    a.GA = G_A;
+    a.nonfinite = p->counters;
+    a.fallback = p->prec == MBO_F32_F64FALLBACK;
+    a.sigma_fb = p->sigma_fb;
+    HIP_TRY(p, launch_vjp(p->pk, p->n, a, (int)p->batch, p->stream));
     unsigned long long h[4];
     HIP_TRY(p, hipMemcpyAsync(h, p->counters, sizeof h, hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(p, hipStreamSynchronize(p->stream));

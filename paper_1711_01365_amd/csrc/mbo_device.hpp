@@ -470,10 +470,12 @@ __device__ __forceinline__ int scale_exponent(const T* a)
     return ex;
 }
 
-// Q = U V^t from the orthogonalised columns W = U Sigma (scaled by 2^-ex).
+// Q = U V^t from the orthogonalised columns W = U Sigma (scaled by 2^-ex).  On
+// return W holds U (completed for zero singular values) unless the matrix is
+// zero; sig (nullable) receives the singular values of the unscaled input.
 template <typename T, int n>
 __device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const T (&V)[n][n], int ex, T* q,
-                                              int& dsign, T& smin)
+                                              int& dsign, T& smin, T* sig = nullptr)
 {
     T ss[n], sg[n];
     T smax = 0;
@@ -489,6 +491,10 @@ __device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const T (&V)[n][n], 
         smin = (j == 0 || sg[j] < smin) ? sg[j] : smin;
     }
     smin = ldexp(smin, ex);  // singular values of the unscaled input
+    if (sig) {
+#pragma unroll
+        for (int j = 0; j < n; ++j) sig[j] = ldexp(sg[j], ex);
+    }
     if (!(smax > (T)0)) {  // zero matrix (or NaN): identity
 #pragma unroll
         for (int i = 0; i < n * n; ++i) q[i] = (i % (n + 1) == 0) ? (T)1 : (T)0;
@@ -652,6 +658,85 @@ __device__ __forceinline__ void project_point(const T* a, T* q, int& dsign, T& s
     } else {
         polar_jacobi<T, n>(a, q, dsign, smin);
     }
+}
+
+// Vector-Jacobian product of the projection at a (n >= 2): with a = U Sigma V^t
+// and Q = U V^t, a perturbation da moves Q by U X V^t, X skew with
+// X_ij = (F_ij - F_ji) / (sigma_i + sigma_j), F = U^t da V.  The cotangent g of
+// Q therefore pulls back to ga = U K V^t, K_ij = (M_ij - M_ji) / (sigma_i +
+// sigma_j), M = U^t g V (K_ii = 0; a pair with sigma_i + sigma_j = 0 gives 0).
+// Returns the smallest singular value of a.
+template <typename T, int n>
+__device__ __forceinline__ T polar_vjp(const T* a, const T* g, T* ga)
+{
+    const int ex = scale_exponent<T, n>(a);
+    T W[n][n], V[n][n], sig[n], q[n * n];
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            W[i][j] = ldexp(a[i * n + j], -ex);
+            V[i][j] = (i == j) ? (T)1 : (T)0;
+        }
+    jacobi_sweeps<T, n>(W, V);
+    int ds;
+    T smin;
+    jacobi_finish<T, n>(W, V, ex, q, ds, smin, sig);
+    T smax = 0;
+#pragma unroll
+    for (int j = 0; j < n; ++j) smax = sig[j] > smax ? sig[j] : smax;
+    if (!(smax > (T)0)) {  // zero matrix: no pair has a positive denominator
+#pragma unroll
+        for (int k = 0; k < n * n; ++k) ga[k] = 0;
+        return smin;
+    }
+    T GV[n][n], K[n][n];
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            T v = 0;
+#pragma unroll
+            for (int l = 0; l < n; ++l) v += g[i * n + l] * V[l][j];
+            GV[i][j] = v;
+        }
+    T M[n][n];
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            T v = 0;
+#pragma unroll
+            for (int k = 0; k < n; ++k) v += W[k][i] * GV[k][j];
+            M[i][j] = v;
+        }
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            const T den = sig[i] + sig[j];
+            K[i][j] = (i == j || !(den > (T)0)) ? (T)0 : (M[i][j] - M[j][i]) / den;
+        }
+    // ga = U K V^t
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            T uk = 0;
+#pragma unroll
+            for (int k = 0; k < n; ++k) uk += W[i][k] * K[k][j];
+            GV[i][j] = uk;
+        }
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            T v = 0;
+#pragma unroll
+            for (int k = 0; k < n; ++k) v += GV[i][k] * V[j][k];
+            ga[i * n + j] = v;
+        }
+    return smin;
 }
 
 // Float Jacobi of a point of a plan with the double fallback: when the smallest

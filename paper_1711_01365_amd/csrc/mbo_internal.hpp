@@ -19,6 +19,7 @@ enum RowFlags : int {
     RF_SIGN_INIT = 1 << 7,   // write sgn det of the loaded real field into sgn[]
     RF_FALLBACK = 1 << 8,    // float plan: re-project small-sigma points in double
     RF_CHECK_STOP = 1 << 9,  // return when this field already stopped
+    RF_DOT = 1 << 10,        // per-workgroup partials of <G, values after the inverse FFT>
 };
 
 struct RowArgs {
@@ -41,6 +42,8 @@ struct RowArgs {
     int K;                   // log stride
     int flags;
     double sigma_fb;         // fallback threshold
+    const void* Gdot;        // RF_DOT: real field G [batch][n*n][npts]
+    double* dpart;           // RF_DOT: partials [batch][gridDim.x]
 };
 
 // Double-precision re-projection queue of the float row pass for n >= 3: one
@@ -56,7 +59,7 @@ constexpr size_t row_fb_lds(int esz, int n, int log2L)
 }
 
 // Modes of the strided-axis pass.
-enum ColMode : int { CM_FORWARD = 0, CM_INVERSE = 1, CM_HEAT = 2, CM_ENERGY = 3 };
+enum ColMode : int { CM_FORWARD = 0, CM_INVERSE = 1, CM_HEAT = 2, CM_ENERGY = 3, CM_DTAU = 4 };
 
 struct ColArgs {
     int L, log2L;            // transform length along the axis
@@ -69,6 +72,8 @@ struct ColArgs {
     void* Z;
     const void* lam_row;     // heat symbol factor of this axis [L] (incl. 1/L)
     const void* lam_inner;   // product of the factors of the faster axes [S]
+    const void* mu_row;      // CM_DTAU: -4 pi^2 k^2 of this axis [L]
+    const void* mu_inner;    // CM_DTAU: -4 pi^2 |k|^2 summed over the faster axes [S]
     double* epart;           // energy partials [batch][K+1][nwg]
     int nwg;                 // workgroups per field (partial slots)
     int slot;                // energy slot (iteration - 1); -1: use stop_iter
@@ -86,6 +91,17 @@ struct ProjArgs {
     int8_t* dsign;           // nullable
     unsigned long long* nonfinite;
     unsigned long long* fallbacks;
+    int fallback;
+    double sigma_fb;
+};
+
+// Vector-Jacobian product of the projection, one point per thread.
+struct VjpArgs {
+    int64_t npts;
+    const void* A;           // point of the projection (the diffused field)
+    const void* G;           // cotangent of the projected field
+    void* GA;                // cotangent of A
+    unsigned long long* nonfinite;
     int fallback;
     double sigma_fb;
 };
@@ -117,6 +133,9 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long l
                            hipStream_t st);
 hipError_t launch_fill_i32(int* p, int64_t count, int v, hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
+hipError_t launch_vjp(int prec, int n, const VjpArgs& a, int batch, hipStream_t st);
+// out[b] = sum of part[b * m .. b * m + m - 1] in a fixed order
+hipError_t launch_sum_rows(const double* part, int64_t m, int batch, double* out, hipStream_t st);
 
 // per-translation-unit launchers behind launch_row / launch_col
 hipError_t launch_row_f32(int n, int log2L, const RowArgs& a, dim3 g, dim3 b, size_t lds,

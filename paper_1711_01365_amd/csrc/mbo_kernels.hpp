@@ -171,8 +171,8 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
     __shared__ float fv[SCAP * NN];
     __shared__ int fq_n;
     unsigned long long nflip = 0, nfb = 0, nbad = 0;
-    double dmax = 0.0;
-    if (flags & (RF_PROJECT | RF_SIGN_INIT | RF_STORE_REAL)) {
+    double dmax = 0.0, dacc = 0.0;
+    if (flags & (RF_PROJECT | RF_SIGN_INIT | RF_STORE_REAL | RF_DOT)) {
         T* Aout = reinterpret_cast<T*>(a.Aout) + (size_t)b * NN * npts;
         int8_t* sgn = a.sgn + (size_t)b * npts;
         const bool defer = DEFER && (flags & RF_PROJECT) && (flags & RF_FALLBACK);
@@ -217,6 +217,11 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
 #pragma unroll
             for (int k = 0; k < NN; ++k) av[k] = (k & 1) ? lir[(k >> 1) * lp] : lrr[(k >> 1) * lp];
             if (flags & RF_SIGN_INIT) sgn[x] = det_n<T, n>(av) >= (T)0 ? 1 : -1;
+            if (flags & RF_DOT) {
+                const T* Gd = reinterpret_cast<const T*>(a.Gdot) + (size_t)b * NN * npts;
+#pragma unroll
+                for (int k = 0; k < NN; ++k) dacc += (double)Gd[(int64_t)k * npts + x] * (double)av[k];
+            }
             if (flags & RF_PROJECT) {
                 nbad += all_finite<T, NN>(av) ? 0ull : 1ull;
                 T qv[NN];
@@ -326,6 +331,10 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
         }
     }
 
+    if (flags & RF_DOT) {
+        dacc = block_reduce<OpSum>(dacc, red_d);
+        if (tid == 0) a.dpart[(int64_t)b * gridDim.x + blockIdx.x] = dacc;
+    }
     if (flags & RF_PROJECT) {
         const int64_t slot = (int64_t)b * a.K + (a.iter - 1);
         nflip = block_reduce<OpSum>(nflip, red_u);
@@ -415,16 +424,18 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
         }
         if (MODE == CM_INVERSE) fft_wave<T, +1, LOG2L>(r, im, lr, li, tt, tw, true);
         else fft_wave<T, -1, LOG2L>(r, im, lr, li, tt, tw, true);
-        if (MODE == CM_HEAT || MODE == CM_ENERGY) {
+        if (MODE == CM_HEAT || MODE == CM_ENERGY || MODE == CM_DTAU) {
             const T* lrow = reinterpret_cast<const T*>(a.lam_row);
             const T lin = reinterpret_cast<const T*>(a.lam_inner)[tile0 + c];
+            const T muin = MODE == CM_DTAU ? reinterpret_cast<const T*>(a.mu_inner)[tile0 + c] : (T)0;
             double acc = 0.0;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const T lam = lrow[tt + e * Tn] * lin;
+                T lam = lrow[tt + e * Tn] * lin;
+                if (MODE == CM_DTAU) lam *= reinterpret_cast<const T*>(a.mu_row)[tt + e * Tn] + muin;
                 if (a.epart)
                     acc += (double)lam * ((double)r[e] * (double)r[e] + (double)im[e] * (double)im[e]);
-                if (MODE == CM_HEAT) {
+                if (MODE == CM_HEAT || MODE == CM_DTAU) {
                     r[e] *= lam;
                     im[e] *= lam;
                 }
@@ -437,7 +448,7 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
                 }
             }
         }
-        if (MODE == CM_HEAT) fft_wave<T, +1, LOG2L>(r, im, lr, li, tt, tw, true);
+        if (MODE == CM_HEAT || MODE == CM_DTAU) fft_wave<T, +1, LOG2L>(r, im, lr, li, tt, tw, true);
         if (MODE != CM_ENERGY) {
             wave_lds_sync();  // the line's last exchange has been read
 #pragma unroll
@@ -476,17 +487,19 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
             fft_lines<T, +1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
         else
             fft_lines<T, -1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
-        if (MODE == CM_HEAT || MODE == CM_ENERGY) {
+        if (MODE == CM_HEAT || MODE == CM_ENERGY || MODE == CM_DTAU) {
             const T* lrow = reinterpret_cast<const T*>(a.lam_row);
             const T lin = reinterpret_cast<const T*>(a.lam_inner)[tile0 + tx];
+            const T muin = MODE == CM_DTAU ? reinterpret_cast<const T*>(a.mu_inner)[tile0 + tx] : (T)0;
             double acc = 0.0;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const T lam = lrow[t + e * Tn] * lin;
+                T lam = lrow[t + e * Tn] * lin;
+                if (MODE == CM_DTAU) lam *= reinterpret_cast<const T*>(a.mu_row)[t + e * Tn] + muin;
                 if (a.epart)
                     acc += (double)lam * ((double)r[0][e] * (double)r[0][e] +
                                           (double)im[0][e] * (double)im[0][e]);
-                if (MODE == CM_HEAT) {
+                if (MODE == CM_HEAT || MODE == CM_DTAU) {
                     r[0][e] *= lam;
                     im[0][e] *= lam;
                 }
@@ -499,7 +512,7 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
                 }
             }
         }
-        if (MODE == CM_HEAT) fft_lines<T, +1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
+        if (MODE == CM_HEAT || MODE == CM_DTAU) fft_lines<T, +1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
         if (MODE != CM_ENERGY) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {

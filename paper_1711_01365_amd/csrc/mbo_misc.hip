@@ -1,5 +1,6 @@
 // Pointwise and utility kernels of libmbo (gfx950): standalone projection
-// (Lemma 1.1), graph-capture-safe fills, the fixed-order energy reduction, and
+// (Lemma 1.1) and its vector-Jacobian product, graph-capture-safe fills, the
+// fixed-order energy and dot-product reductions, and
 // the dispatch of the row / strided-axis passes to their translation units.
 #include "mbo_kernels.hpp"
 
@@ -33,6 +34,66 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjArgs a)
     if (threadIdx.x == 0 && bad) atomicAdd(a.nonfinite, bad);
     fb = block_reduce<OpSum>(fb, red_u);
     if (threadIdx.x == 0 && fb && a.fallbacks) atomicAdd(a.fallbacks, fb);
+}
+
+// ---------------------------------------------------------------------------
+// Vector-Jacobian product of the projection, one point per thread.  Float
+// plans with the double fallback redo points whose smallest singular value is
+// below the threshold in double, as the forward projection does.
+// ---------------------------------------------------------------------------
+template <typename T, int n>
+__global__ void __launch_bounds__(256) vjp_kernel(const VjpArgs a)
+{
+    constexpr int NN = n * n;
+    const int b = blockIdx.y;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ unsigned long long red_u[64];
+    unsigned long long bad = 0;
+    if (p < a.npts) {
+        const T* A = reinterpret_cast<const T*>(a.A) + (size_t)b * NN * a.npts;
+        const T* G = reinterpret_cast<const T*>(a.G) + (size_t)b * NN * a.npts;
+        T* GA = reinterpret_cast<T*>(a.GA) + (size_t)b * NN * a.npts;
+        T av[NN], gv[NN], ov[NN];
+#pragma unroll
+        for (int k = 0; k < NN; ++k) {
+            av[k] = A[(int64_t)k * a.npts + p];
+            gv[k] = G[(int64_t)k * a.npts + p];
+        }
+        bad = !all_finite<T, NN>(av);
+        if constexpr (n == 1) {
+            ov[0] = 0;  // sign thresholding is locally constant
+        } else {
+            const T smin = polar_vjp<T, n>(av, gv, ov);
+            if constexpr (sizeof(T) == 4) {
+                if (a.fallback && (double)smin < a.sigma_fb) {
+                    double ad[NN], gd[NN], od[NN];
+#pragma unroll
+                    for (int k = 0; k < NN; ++k) {
+                        ad[k] = av[k];
+                        gd[k] = gv[k];
+                    }
+                    (void)polar_vjp<double, n>(ad, gd, od);
+#pragma unroll
+                    for (int k = 0; k < NN; ++k) ov[k] = (T)od[k];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NN; ++k) GA[(int64_t)k * a.npts + p] = ov[k];
+    }
+    bad = block_reduce<OpSum>(bad, red_u);
+    if (threadIdx.x == 0 && bad) atomicAdd(a.nonfinite, bad);
+}
+
+// out[b] = fixed-order sum of the m partials of field b (one workgroup per field)
+__global__ void __launch_bounds__(256) sum_rows(const double* part, int64_t m, double* out)
+{
+    __shared__ double red_d[64];
+    const int b = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) acc += part[(int64_t)b * m + i];
+    acc = block_reduce<OpSum>(acc, red_d);
+    if (threadIdx.x == 0) out[b] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -101,6 +162,32 @@ static hipError_t proj_dispatch(int n, const ProjArgs& a, int batch, hipStream_t
 hipError_t launch_project(int prec, int n, const ProjArgs& a, int batch, hipStream_t st)
 {
     return prec == 0 ? proj_dispatch<double>(n, a, batch, st) : proj_dispatch<float>(n, a, batch, st);
+}
+
+template <typename T>
+static hipError_t vjp_dispatch(int n, const VjpArgs& a, int batch, hipStream_t st)
+{
+    dim3 bl(256);
+    dim3 g((unsigned)((a.npts + 255) / 256), (unsigned)batch);
+    switch (n) {
+    case 1: hipLaunchKernelGGL((vjp_kernel<T, 1>), g, bl, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((vjp_kernel<T, 2>), g, bl, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((vjp_kernel<T, 3>), g, bl, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((vjp_kernel<T, 4>), g, bl, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp(int prec, int n, const VjpArgs& a, int batch, hipStream_t st)
+{
+    return prec == 0 ? vjp_dispatch<double>(n, a, batch, st) : vjp_dispatch<float>(n, a, batch, st);
+}
+
+hipError_t launch_sum_rows(const double* part, int64_t m, int batch, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(sum_rows, dim3((unsigned)batch), dim3(256), 0, st, part, m, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, hipStream_t st)

@@ -27,7 +27,8 @@ _lib = None
 
 EXPORTS = ("mbo_plan", "mbo_plan_destroy", "mbo_plan_set_tau", "mbo_plan_set_stream",
            "mbo_plan_set_timing", "mbo_last_timing", "mbo_diffuse", "mbo_project", "mbo_iterate",
-           "mbo_energy", "mbo_status_string", "mbo_last_error")
+           "mbo_energy", "mbo_project_vjp", "mbo_diffuse_dtau", "mbo_status_string",
+           "mbo_last_error")
 
 
 class MboError(RuntimeError):
@@ -57,6 +58,8 @@ def load(path: str = LIB_PATH):
     lib.mbo_project.argtypes = [vp, vp, vp, vp]
     lib.mbo_iterate.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, ip, dp, i64p, dp, i64p]
     lib.mbo_energy.argtypes = [vp, vp, dp]
+    lib.mbo_project_vjp.argtypes = [vp, vp, vp, vp]
+    lib.mbo_diffuse_dtau.argtypes = [vp, vp, vp, vp, dp]
     for f in EXPORTS:
         if f not in ("mbo_status_string", "mbo_last_error"):
             getattr(lib, f).restype = ctypes.c_int
@@ -155,6 +158,33 @@ class Plan:
                                      ctypes.c_void_p(ds.data_ptr()) if ds is not None else None),
                self._h)
         return (A_out, ds) if det_sign else A_out
+
+    def project_vjp(self, A_tilde, G_Q, G_A=None):
+        """Cotangent of the projection's input for the cotangent G_Q of its output."""
+        import torch
+        if G_A is None:
+            G_A = torch.empty_like(G_Q)
+        _check(self._lib.mbo_project_vjp(self._h, self._field(A_tilde, "A_tilde"),
+                                         self._field(G_Q, "G_Q"), self._field(G_A, "G_A")), self._h)
+        return G_A
+
+    def diffuse_dtau(self, A, out=None, G=None):
+        """d/dtau e^{tau Delta} A into `out` (allocated when neither out nor G is
+        given); with G also returns <G, d/dtau e^{tau Delta} A> per field.
+        Returns out, dot or (out, dot)."""
+        import torch
+        if out is None and G is None:
+            out = torch.empty_like(A)
+        dot = np.zeros(self.batch) if G is not None else None
+        _check(self._lib.mbo_diffuse_dtau(
+            self._h, self._field(A), self._field(out, "out") if out is not None else None,
+            self._field(G, "G") if G is not None else None,
+            dot.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if dot is not None else None),
+            self._h)
+        if dot is not None:
+            d = dot if self.batch > 1 else float(dot[0])
+            return (out, d) if out is not None else d
+        return out
 
     def energy(self, A):
         E = np.zeros(self.batch)
