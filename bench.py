@@ -19,7 +19,9 @@ from HIP start/stop events recorded by each dispatch in three more steps run
 right after the timed ones (launched directly, since events inside a captured
 graph cannot be timed).  `cpu_baseline` is
 the FP64 CPU oracle on a bounded sample (the first iterations of the same
-workload).
+workload).  Beside the main line: the 3-D configuration (n = 3, 128^3, 100
+iterations, FP32 + fallback) and the gradient of 50 unrolled steps (n = 3,
+256^2, FP32 + fallback and FP64), forward and backward time.
 
     python bench.py --copy-calibration
 
@@ -129,6 +131,68 @@ def run_gpu(w, precision, steps, warmup, timing_steps):
     }
 
 
+def run_3d(steps, warmup):
+    """The 3-D configuration (n = 3, 128^3, 100 iterations, FP32 + FP64 fallback)
+    through the captured graph; point-iterations per second."""
+    import torch
+    from paper_1711_01365_amd import inputs, mbo
+    w = inputs.NORMAL_128_3D
+    A0 = torch.tensor(w.field(), dtype=torch.float32, device="cuda")
+    A = A0.clone()
+    plan = mbo.Plan(w.grid, w.n, w.tau, precision=mbo.F32_F64FALLBACK)
+    for _ in range(warmup):
+        A.copy_(A0)
+        plan.iterate(A, w.iters)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        A.copy_(A0)
+        plan.iterate(A, w.iters)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    plan.close()
+    return {"workload": "n3_128x128x128_normal_tau5e-4_100it_f32_f64fallback",
+            "value": w.points * w.iters * steps / sec, "unit": "point-iterations/s",
+            "ms_per_run": 1000.0 * sec / steps}
+
+
+def run_adjoint(precision, reps):
+    """Gradients of K = 50 unrolled steps (n = 3, 256^2, checkpoint every 10):
+    forward and backward wall time of the autograd function."""
+    import torch
+    from paper_1711_01365_amd import inputs, mbo
+    from paper_1711_01365_amd.autograd import unrolled_mbo
+    w = inputs.ADJOINT_256
+    dt = torch.float64 if precision == mbo.F64 else torch.float32
+    # target: projection of a heat-smoothed (tau = 1e-2) N(0,1) field, made on the GPU
+    G = torch.tensor(inputs.normal_field(w.n, w.grid, inputs.ADJOINT_TARGET_SEED), dtype=dt, device="cuda")
+    with mbo.Plan(w.grid, w.n, inputs.ADJOINT_TARGET_TAU, precision=precision) as pt:
+        Td = pt.project(pt.diffuse(G))
+    A0 = torch.tensor(w.field(), dtype=dt, device="cuda")
+    plan = mbo.Plan(w.grid, w.n, w.tau, precision=precision)
+    fw, bw = [], []
+    for k in range(reps + 1):
+        A = A0.clone().requires_grad_(True)
+        tau = torch.tensor(w.tau, dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        AK = unrolled_mbo(A, tau, plan, w.iters, inputs.ADJOINT_CHECKPOINT)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss = 0.5 * ((AK - Td) ** 2).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if k:  # the first run captures the graphs
+            fw.append(t1 - t0)
+            bw.append(t2 - t1)
+    plan.close()
+    f, b = min(fw), min(bw)
+    return {"workload": "n3_256x256_K50_checkpoint10", "forward_ms": 1000 * f, "backward_ms": 1000 * b,
+            "backward_over_forward": b / f,
+            "point_steps_per_s": w.points * w.iters * 2 / (f + b)}
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle on the first iterations of the same workload."""
     import oracle
@@ -157,6 +221,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 3-D and adjoint legs (reported beside the main line)")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
 
@@ -219,6 +285,14 @@ def main():
         out["f64"] = {"value": f64["value"], "ms_per_step": f64["ms_per_step"],
                       "kernels_us": {"row_pass": f64["row_us"], "heat_pass": f64["heat_us"]},
                       "f32_over_f64": main_run["value"] / f64["value"]}
+    if not args.no_extra:
+        out["config_3d"] = run_3d(3, 1)
+        log("3-D n=3 128^3 fp32+fallback: %.3e point-iter/s" % out["config_3d"]["value"])
+        out["adjoint"] = {"f32_f64fallback": run_adjoint(mbo.F32_F64FALLBACK, 2),
+                          "f64": run_adjoint(mbo.F64, 2)}
+        log("adjoint K=50 256^2: fp32+fb fwd %.1f ms bwd %.1f ms, fp64 fwd %.1f ms bwd %.1f ms"
+            % (out["adjoint"]["f32_f64fallback"]["forward_ms"], out["adjoint"]["f32_f64fallback"]["backward_ms"],
+               out["adjoint"]["f64"]["forward_ms"], out["adjoint"]["f64"]["backward_ms"]))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -385,3 +385,68 @@ def test_bench_configuration_properties(torch_cuda):
          % (e_heat, err.max(), int((gap >= 0.1).sum()), err[gap >= 0.1].max() if (gap >= 0.1).any() else 0))
     assert fp32_step_ok(err, gap, e_heat)
     assert r2["flips"][0][0] == ro["flips"][0] or abs(int(r2["flips"][0][0]) - int(ro["flips"][0])) <= 2
+
+
+def test_iterate_full_size_128cube_f64_two_steps(torch_cuda):
+    """n = 3 on the 128^3 torus, iid N(0,1) entries (seed 2), tau = 5e-4: two FP64
+    steps against the oracle (<= 1e-12) with identical flip counts."""
+    torch = torch_cuda
+    w = inputs.NORMAL_128_3D
+    A0 = w.field()
+    note("two steps f64 %s" % w.name)
+    P = plan(w.grid, w.n, w.tau, F64)
+    t = to_dev(torch, A0, torch.float64)
+    r = P.iterate(t, 2)
+    ro = oracle.iterate(A0, w.tau, 2)
+    err = np.abs(t.cpu().numpy() - ro["A"]).max()
+    note("  max err %.3e, flips %s vs %s" % (err, list(r["flips"][0]), list(ro["flips"])))
+    assert err <= 1e-12
+    assert np.array_equal(r["flips"][0], ro["flips"])
+    assert abs(r["energy"][0][2] - ro["energy"][2]) <= 1e-12 * abs(ro["energy"][2])
+
+
+def test_3d_configuration_properties(torch_cuda):
+    """The 3-D configuration at full size (n = 3, 128^3, 100 FP32+fallback
+    iterations): one FP32 step from A_0 within the FP32 bound of the oracle step,
+    every point of the result orthogonal, energy non-increasing from s = 1 within
+    FP32 rounding, the final logged energy equal to the oracle's energy of the
+    returned field, and the last step equal to one oracle step from iterate 99."""
+    torch = torch_cuda
+    w = inputs.NORMAL_128_3D
+    A0 = w.field().astype(np.float32)
+    note("3-D configuration %s" % w.name)
+    P = plan(w.grid, w.n, w.tau, FB)
+    # one step from A_0
+    A64 = A0.astype(np.float64)
+    Ht, _ = oracle.heat(A64.reshape((9,) + w.grid), w.tau, 3)
+    Ht = Ht.reshape(A64.shape)
+    Hg = P.diffuse(to_dev(torch, A0, torch.float32)).cpu().numpy()
+    e_heat = float(np.abs(Hg - Ht).max())
+    t = to_dev(torch, A0, torch.float32)
+    r1 = P.iterate(t, 1)
+    ro = oracle.iterate(A64, w.tau, 1)
+    gap = sigma_gap(Ht)
+    err = np.abs(point_major(t.cpu().numpy() - ro["A"])).max(axis=(1, 2))
+    note("  step 1: diffusion err %.3g, step err max %.3g, fallbacks %d"
+         % (e_heat, err.max(), r1["fallbacks"][0][0]))
+    assert e_heat <= 2e-6
+    assert fp32_step_ok(err, gap, e_heat)
+    # the rest of the run
+    r = P.iterate(t, w.iters - 2)
+    A99 = t.cpu().numpy()
+    r2 = P.iterate(t, 1)
+    A100 = t.cpu().numpy()
+    M = point_major(A100).astype(np.float64)
+    assert np.abs(M.transpose(0, 2, 1) @ M - np.eye(3)).max() < 1e-5
+    E = np.concatenate([r1["energy"][0][1:], r["energy"][0][1:], r2["energy"][0][1:]])
+    assert np.all(np.diff(E) <= 1e-5 * E[0])
+    assert abs(E[-1] - oracle.energy(A100.astype(np.float64), w.tau)) <= 1e-5 * E[-1]
+    Ht, _ = oracle.heat(A99.astype(np.float64).reshape((9,) + w.grid), w.tau, 3)
+    Ht = Ht.reshape(A99.shape)
+    ro = oracle.iterate(A99.astype(np.float64), w.tau, 1)
+    Hg = P.diffuse(to_dev(torch, A99, torch.float32)).cpu().numpy()
+    e_heat = float(np.abs(Hg - Ht).max())
+    gap = sigma_gap(Ht)
+    err = np.abs(point_major(A100 - ro["A"])).max(axis=(1, 2))
+    note("  last step: diffusion err %.3g, step err max %.3g" % (e_heat, err.max()))
+    assert fp32_step_ok(err, gap, e_heat)
