@@ -150,6 +150,42 @@ mbo_status mbo_iterate(mbo_plan_t plan, void* A, int max_iter, double tol, int* 
 mbo_status mbo_energy(mbo_plan_t plan, const void* A, double* E);
 
 /* ---------------------------------------------------------------------------
+ * Batched plans of mixed fields.  Many independent fields, each with its own
+ * grid, matrix size n and tau, iterated together: fields of equal (d, N, n)
+ * share one set of kernels and launches (a class), each field keeping its own
+ * heat symbol; mbo_iterate captures every class's iterations into one HIP
+ * graph.  The caller's field buffer is the concatenation of the fields in
+ * descriptor order, field f entry-planar [n_f][n_f][prod N_f] and starting at
+ * element sum_{g<f} n_g^2 prod(N_g).  mbo_iterate, mbo_energy, mbo_diffuse and
+ * mbo_project (det_sign must be NULL) accept a batched plan; their per-field
+ * outputs and logs are in descriptor order ([count][...]).  mbo_plan_set_tau,
+ * mbo_plan_set_timing (enable), mbo_project_vjp and mbo_diffuse_dtau return
+ * MBO_ERR_UNSUPPORTED for it.
+ * ------------------------------------------------------------------------- */
+typedef struct mbo_field_desc {
+    int d;          /* 2 or 3 */
+    int64_t N[3];   /* grid, axis 0 slowest; N[d..2] ignored */
+    int n;          /* matrix size, 1..4 */
+    double tau;     /* diffusion time of one step of this field */
+} mbo_field_desc;
+
+/* Create a batched plan for `count` fields (the shape rules of mbo_plan apply to
+ * each descriptor).  autotune != 0 times candidate launch shapes of every class
+ * on the device (tiles of lines per strided-pass workgroup, the XCD-aware tile
+ * order, rows per row-pass workgroup) on a pseudo-random field and keeps the
+ * fastest; 0 keeps the fixed rules.  The choice changes neither the transforms
+ * nor the projection of any point, only the summation order of the energy. */
+mbo_status mbo_plan_batched(mbo_plan_t* out, int count, const mbo_field_desc* descs, mbo_precision prec,
+                            double sigma_fallback, int autotune, void* hip_stream);
+
+/* Launch shape used for `field` (0 <= field < count, or < batch for a plain
+ * plan): rows per row-pass workgroup, lines per heat-pass workgroup, and
+ * whether heat-pass tiles are dealt to the XCDs in contiguous runs (all
+ * nullable). */
+mbo_status mbo_plan_tuning(mbo_plan_t plan, int field, int* rows_per_group, int* heat_lines_per_group,
+                           int* xcd_order);
+
+/* ---------------------------------------------------------------------------
  * Adjoint building blocks.  The paper stops at the forward iteration; these
  * calls differentiate it.  With L a scalar function of A_K = P(H A_{K-1}) ...,
  * H = e^{tau Delta}, the chain rule runs backwards over s = K..1:

@@ -72,11 +72,29 @@ struct mbo_plan_s {
     double* dsum = nullptr;     // [batch]
     unsigned long long* counters = nullptr;  // project: [0] nonfinite, [1] fallbacks
 
-    // launch configuration
+    // per-field diffusion times (fields of a batched plan): tables per field
+    bool per_field_tau = false;
+    std::vector<double> taus;     // [batch]
+    double* taus_dev = nullptr;   // [batch]
+    // field offsets (elements) in the caller's buffer, when not b * n*n * npts
+    int64_t* foff_dev = nullptr;  // [batch]
+
+    // launch configuration (tune_*: overrides chosen by the autotuner, 0 = rule)
     dim3 row_grid, row_block;
     size_t row_lds = 0;
     int row_rpw = 1;
     ColCfg heat, ypass;
+    int tune_rpw = 0, tune_tx_heat = 0, tune_tx_y = 0;
+    int xcd_remap = 1;
+    bool tuned = false;
+
+    // a batched plan of mixed fields is a group of member plans, one per
+    // (d, N, n) class; field f is field f_index[f] of member f_member[f] and
+    // starts at element f_off[f] of the caller's buffer
+    bool group = false;
+    std::vector<mbo_plan_s*> members;
+    std::vector<int> f_member, f_index;
+    std::vector<int64_t> f_off;
 
     // logs of mbo_iterate, capacity log_K
     int log_K = -1;
@@ -146,6 +164,8 @@ void drop_graph(mbo_plan_t p)
 void destroy(mbo_plan_t p)
 {
     if (!p) return;
+    for (mbo_plan_t m : p->members) destroy(m);
+    p->members.clear();
     (void)hipSetDevice(p->device);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     drop_graph(p);
@@ -165,6 +185,8 @@ void destroy(mbo_plan_t p)
     free_dev(p->mu_inner);
     free_dev(p->dpart);
     free_dev(p->dsum);
+    free_dev(p->taus_dev);
+    free_dev(p->foff_dev);
     free_dev(p->counters);
     free_dev(p->epart);
     free_dev(p->energy);
@@ -204,17 +226,27 @@ std::vector<double> axis_symbol(int64_t N, double tau)
     return v;
 }
 
+// Heat-symbol tables of the plan: one pair (axis 0, product over the faster
+// axes), or one pair per field when the fields have their own tau.
 mbo_status build_symbol_tables(mbo_plan_t p)
 {
-    std::vector<double> row = axis_symbol(p->N[0], p->tau);
     const int64_t inner_n = p->npts / p->N[0];
-    std::vector<double> inner((size_t)inner_n);
-    if (p->d == 2) {
-        inner = axis_symbol(p->N[1], p->tau);
-    } else {
-        std::vector<double> ly = axis_symbol(p->N[1], p->tau), lx = axis_symbol(p->N[2], p->tau);
-        for (int64_t y = 0; y < p->N[1]; ++y)
-            for (int64_t x = 0; x < p->N[2]; ++x) inner[(size_t)(y * p->N[2] + x)] = ly[(size_t)y] * lx[(size_t)x];
+    const int64_t nt = p->per_field_tau ? p->batch : 1;
+    std::vector<double> row, inner;
+    row.reserve((size_t)(nt * p->N[0]));
+    inner.reserve((size_t)(nt * inner_n));
+    for (int64_t b = 0; b < nt; ++b) {
+        const double tau = p->per_field_tau ? p->taus[(size_t)b] : p->tau;
+        std::vector<double> r = axis_symbol(p->N[0], tau);
+        row.insert(row.end(), r.begin(), r.end());
+        if (p->d == 2) {
+            std::vector<double> i2 = axis_symbol(p->N[1], tau);
+            inner.insert(inner.end(), i2.begin(), i2.end());
+        } else {
+            std::vector<double> ly = axis_symbol(p->N[1], tau), lx = axis_symbol(p->N[2], tau);
+            for (int64_t y = 0; y < p->N[1]; ++y)
+                for (int64_t x = 0; x < p->N[2]; ++x) inner.push_back(ly[(size_t)y] * lx[(size_t)x]);
+        }
     }
     mbo_status s = upload(p, p->lam_row, row);
     if (s != MBO_OK) return s;
@@ -280,7 +312,8 @@ mbo_status config_col(mbo_plan_t p, ColCfg& c, int axis)
         // bank conflicts; up to 512 threads per workgroup
         c.pitch = lds_len(c.L);
         c.pitch += ((8 - c.pitch % 64) + 64) % 64;
-        while (TX * 2 <= c.S && T * TX * 2 <= 512) TX *= 2;
+        const int cap = axis == 0 ? p->tune_tx_heat : p->tune_tx_y;
+        while (TX * 2 <= c.S && T * TX * 2 <= 512 && (cap == 0 || TX * 2 <= cap)) TX *= 2;
         const size_t per_line = (size_t)c.pitch * 2 * p->esz;
         while (TX > 1 && per_line * TX > p->lds_max) TX /= 2;
         if (per_line * TX > p->lds_max)
@@ -288,7 +321,8 @@ mbo_status config_col(mbo_plan_t p, ColCfg& c, int axis)
         c.lds = per_line * TX;
     } else {
         c.pitch = lds_len(c.L);
-        while (TX < 16 && TX * 2 <= c.S && T * TX * 2 <= 512) TX *= 2;
+        const int cap = axis == 0 ? p->tune_tx_heat : p->tune_tx_y;
+        while (TX < 16 && TX * 2 <= c.S && T * TX * 2 <= 512 && (cap == 0 || TX * 2 <= cap)) TX *= 2;
         const size_t per_col = (size_t)c.pitch * 2 * p->esz;
         while (TX > 1 && per_col * TX > p->lds_max) TX /= 2;
         if (per_col * TX > p->lds_max)
@@ -309,7 +343,10 @@ mbo_status config_row(mbo_plan_t p)
     const int L = (int)p->N[p->d - 1];
     const int64_t rows = p->npts / L;
     int rpw = 1;
-    while (rpw * L < 256 && rpw * 2 <= rows) rpw *= 2;
+    if (p->tune_rpw > 0)
+        while (rpw * 2 <= p->tune_rpw && rpw * 2 <= rows) rpw *= 2;
+    else
+        while (rpw * L < 256 && rpw * 2 <= rows) rpw *= 2;
     const size_t per_row = (size_t)p->PL * lds_len(L) * 2 * p->esz;
     const size_t budget = p->lds_max - row_fb_lds((int)p->esz, p->n, ilog2(L));
     while (rpw > 1 && per_row * rpw > budget) rpw /= 2;
@@ -343,6 +380,7 @@ RowArgs row_args(mbo_plan_t p)
     a.sgn = p->sgn;
     a.sigma_fb = p->sigma_fb;
     a.K = 1;
+    a.foff = p->foff_dev;
     return a;
 }
 
@@ -363,6 +401,9 @@ ColArgs col_args(mbo_plan_t p, const ColCfg& c)
     a.lam_inner = p->lam_inner;
     a.mu_row = p->mu_row;
     a.mu_inner = p->mu_inner;
+    a.lam_row_stride = p->per_field_tau ? p->N[0] : 0;
+    a.lam_inner_stride = p->per_field_tau ? p->npts / p->N[0] : 0;
+    a.xcd_remap = p->xcd_remap;
     a.nwg = (int)(c.outer * (c.S / c.TX));
     a.slot = 0;
     return a;
@@ -398,9 +439,10 @@ void prepare_plan_kernels(mbo_plan_t p)
     (void)hipGetLastError();
 }
 
-mbo_status ensure_logs(mbo_plan_t p, int K)
+// Free the device logs; the next ensure_logs reallocates them (their energy
+// partials are sized by the heat pass's workgroup count).
+void drop_logs(mbo_plan_t p)
 {
-    if (K <= p->log_K) return MBO_OK;
     drop_graph(p);
     free_dev(p->epart);
     free_dev(p->energy);
@@ -409,6 +451,13 @@ mbo_status ensure_logs(mbo_plan_t p, int K)
     free_dev(p->nonfinite);
     free_dev(p->delta_bits);
     free_dev(p->stop_iter);
+    p->log_K = -1;
+}
+
+mbo_status ensure_logs(mbo_plan_t p, int K)
+{
+    if (K <= p->log_K) return MBO_OK;
+    drop_logs(p);
     const size_t slots = (size_t)p->batch * (size_t)(K + 1);
     const int nwg = (int)p->heat.grid.x;
     HIP_TRY(p, hipMalloc((void**)&p->epart, slots * (size_t)nwg * sizeof(double)));
@@ -525,11 +574,296 @@ hipError_t enqueue_iterate(mbo_plan_t p, void* A, int K, double tol, bool want_e
         ra.n = p->n;
         ra.npts = p->npts;
         ra.tau = p->tau;
+        ra.taus = p->taus_dev;
         ra.stop_iter = p->stop_iter;
         ra.energy = p->energy;
         if ((e = launch_reduce(ra, st)) != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// Shape checks shared by mbo_plan and mbo_plan_batched.
+mbo_status check_shape(int d, const int64_t* N, int n, double tau)
+{
+    if (d != 2 && d != 3) return fail(nullptr, MBO_ERR_INVALID_ARG, "d must be 2 or 3 (got %d)", d);
+    if (n < 1 || n > 4) return fail(nullptr, MBO_ERR_INVALID_ARG, "n must be in [1,4] (got %d)", n);
+    if (!(tau > 0.0) || !std::isfinite(tau))
+        return fail(nullptr, MBO_ERR_INVALID_ARG, "tau must be finite and > 0");
+    for (int a = 0; a < d; ++a)
+        if (!is_pow2(N[a]) || N[a] < 8 || N[a] > 2048)
+            return fail(nullptr, MBO_ERR_UNSUPPORTED,
+                        "N[%d] = %lld: each axis must be a power of two in [8, 2048]", a,
+                        (long long)N[a]);
+    return MBO_OK;
+}
+
+void set_shape(mbo_plan_t p, int d, const int64_t* N, int n, int64_t batch, double tau, mbo_precision prec,
+               double sigma_fallback, void* hip_stream)
+{
+    p->d = d;
+    for (int a = 0; a < d; ++a) p->N[a] = N[a];
+    p->n = n;
+    p->batch = batch;
+    p->tau = tau;
+    p->prec = prec;
+    p->sigma_fb = sigma_fallback > 0.0 ? sigma_fallback : 1e-3;
+    p->pk = prec == MBO_F64 ? 0 : 1;
+    p->esz = prec == MBO_F64 ? 8 : 4;
+    p->PL = (n * n + 1) / 2;
+    p->npts = 1;
+    for (int a = 0; a < d; ++a) p->npts *= N[a];
+    p->stream = (hipStream_t)hip_stream;
+}
+
+// Device set-up of a plan whose shape fields are filled in: launch
+// configuration, workspace, tables and (batched members) the per-field tau and
+// offset arrays.  On failure p->err holds the message and the caller destroys p.
+mbo_status plan_init(mbo_plan_t p, const int64_t* foff_host)
+{
+    HIP_TRY(p, hipGetDevice(&p->device));
+    hipDeviceProp_t prop;
+    HIP_TRY(p, hipGetDeviceProperties(&prop, p->device));
+    // leave room for the kernels' static LDS (reduction scratch)
+    p->lds_max = prop.sharedMemPerBlock > 4096 ? (size_t)prop.sharedMemPerBlock - 2048 : 65536;
+    HIP_TRY(p, hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+
+    mbo_status s;
+    if ((s = config_row(p)) != MBO_OK) return s;
+    if ((s = config_col(p, p->heat, 0)) != MBO_OK) return s;
+    if (p->d == 3 && (s = config_col(p, p->ypass, 1)) != MBO_OK) return s;
+    prepare_plan_kernels(p);
+
+    const int64_t batch = p->batch;
+    const size_t zbytes = (size_t)batch * p->PL * (size_t)p->npts * 2 * p->esz;
+    HIP_TRY(p, hipMalloc(&p->Z, zbytes));
+    HIP_TRY(p, hipMalloc((void**)&p->sgn, (size_t)batch * (size_t)p->npts));
+    HIP_TRY(p, hipMalloc((void**)&p->counters, 4 * sizeof(unsigned long long)));
+    for (int a = 0; a < p->d; ++a) {
+        for (int b = 0; b < a; ++b)
+            if (p->N[b] == p->N[a]) p->tw[a] = p->tw[b];
+        if (p->tw[a]) continue;
+        HIP_TRY(p, hipMalloc(&p->tw[a], (size_t)p->N[a] * 2 * p->esz));
+        if ((s = upload(p, p->tw[a], twiddles(p->N[a]))) != MBO_OK) return s;
+    }
+    const size_t nt = p->per_field_tau ? (size_t)batch : 1;
+    HIP_TRY(p, hipMalloc(&p->lam_row, nt * (size_t)p->N[0] * p->esz));
+    HIP_TRY(p, hipMalloc(&p->lam_inner, nt * (size_t)(p->npts / p->N[0]) * p->esz));
+    if ((s = build_symbol_tables(p)) != MBO_OK) return s;
+    HIP_TRY(p, hipMalloc(&p->mu_row, (size_t)p->N[0] * p->esz));
+    HIP_TRY(p, hipMalloc(&p->mu_inner, (size_t)(p->npts / p->N[0]) * p->esz));
+    if ((s = build_laplace_tables(p)) != MBO_OK) return s;
+    // dot partials: one per row workgroup, sized for any rows-per-workgroup choice
+    HIP_TRY(p, hipMalloc((void**)&p->dpart,
+                         (size_t)batch * (size_t)(p->npts / p->N[p->d - 1]) * sizeof(double)));
+    HIP_TRY(p, hipMalloc((void**)&p->dsum, (size_t)batch * sizeof(double)));
+    if (p->per_field_tau) {
+        HIP_TRY(p, hipMalloc((void**)&p->taus_dev, (size_t)batch * sizeof(double)));
+        HIP_TRY(p, hipMemcpy(p->taus_dev, p->taus.data(), (size_t)batch * sizeof(double),
+                             hipMemcpyHostToDevice));
+    }
+    if (foff_host) {
+        HIP_TRY(p, hipMalloc((void**)&p->foff_dev, (size_t)batch * sizeof(int64_t)));
+        HIP_TRY(p, hipMemcpy(p->foff_dev, foff_host, (size_t)batch * sizeof(int64_t),
+                             hipMemcpyHostToDevice));
+    }
+    return MBO_OK;
+}
+
+// Copy the iteration logs of plan p back (on stream st, synchronising) and
+// store them for field row map[b] (or b) of the caller's arrays; counts the
+// projections that met NaN/Inf into *bad.  Also evaluates kernel timing.
+mbo_status read_logs(mbo_plan_t p, int K, double tol, hipStream_t st, int* iters_done, double* energy,
+                     int64_t* flips, double* delta, int64_t* fallbacks, const std::vector<int>* map,
+                     unsigned long long* bad)
+{
+    const size_t B = (size_t)p->batch;
+    const size_t cs = B * (size_t)(K > 0 ? K : 1);
+    std::vector<int> stp(B);
+    std::vector<unsigned long long> hf(cs), hfb(cs), hbad(cs), hd(cs);
+    std::vector<double> he(B * (size_t)(K + 1));
+    HIP_TRY(p, hipMemcpyAsync(stp.data(), p->stop_iter, B * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(p, hipMemcpyAsync(hf.data(), p->flips, cs * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(p, hipMemcpyAsync(hfb.data(), p->fallbacks, cs * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(p, hipMemcpyAsync(hbad.data(), p->nonfinite, cs * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(p, hipMemcpyAsync(hd.data(), p->delta_bits, cs * 8, hipMemcpyDeviceToHost, st));
+    if (energy)
+        HIP_TRY(p, hipMemcpyAsync(he.data(), p->energy, he.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(p, hipStreamSynchronize(st));
+
+    if (p->timing && K > 0) {
+        // average over the iterations every field ran (stopped fields skip kernels)
+        int ran = K;
+        for (size_t b = 0; b < B; ++b) ran = stp[b] < ran ? stp[b] : ran;
+        double tr = 0.0, tc = 0.0;
+        for (int k = 0; k < ran; ++k) {
+            float ms_r = 0.f, ms_c = 0.f;
+            HIP_TRY(p, hipEventElapsedTime(&ms_r, p->ev[4 * k], p->ev[4 * k + 1]));
+            HIP_TRY(p, hipEventElapsedTime(&ms_c, p->ev[4 * k + 2], p->ev[4 * k + 3]));
+            tr += ms_r;
+            tc += ms_c;
+        }
+        p->t_launches = ran;
+        p->t_row_us = ran ? 1000.0 * tr / ran : 0.0;
+        p->t_col_us = ran ? 1000.0 * tc / ran : 0.0;
+    }
+
+    for (size_t b = 0; b < B; ++b) {
+        const int done = stp[b];
+        const size_t f = map ? (size_t)(*map)[b] : b;
+        if (iters_done) iters_done[f] = done;
+        for (int k = 0; k < K; ++k) {
+            const size_t i = b * (size_t)K + (size_t)k;
+            const size_t o = f * (size_t)K + (size_t)k;
+            const bool ran = k < done;
+            if (flips) flips[o] = ran ? (int64_t)hf[i] : 0;
+            if (fallbacks) fallbacks[o] = ran ? (int64_t)hfb[i] : 0;
+            if (delta) {
+                double dv;
+                std::memcpy(&dv, &hd[i], sizeof dv);
+                delta[o] = (ran && tol > 0.0) ? dv : -1.0;
+            }
+            if (ran) *bad += hbad[i];
+        }
+        if (energy)
+            for (int k = 0; k <= K; ++k) {
+                const size_t i = b * (size_t)(K + 1) + (size_t)k;
+                energy[f * (size_t)(K + 1) + (size_t)k] = k <= done ? he[i] : std::nan("");
+            }
+    }
+    return MBO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner of a plan's launch shapes.  Coordinate search, each choice timed
+// on the device over `reps` iterations of a pseudo-random field (direct
+// launches between two events): heat-pass tile width (lines per workgroup)
+// and the XCD-aware tile order on/off, the middle-axis tile width (3-D), then
+// the rows per row-pass workgroup.  The transforms and the projection do the
+// same arithmetic per line and per point for every choice; only the launch
+// shape, and with it the order of the energy partial sums, changes.
+// ---------------------------------------------------------------------------
+mbo_status time_iterations(mbo_plan_t p, void* A, int reps, hipEvent_t e0, hipEvent_t e1, double* us)
+{
+    const int64_t count = p->batch * (int64_t)p->n * p->n * p->npts;
+    HIP_TRY(p, launch_fill_uniform(p->pk, A, count, 0x5eedull, p->stream));
+    HIP_TRY(p, enqueue_iterate(p, A, 1, 0.0, false, p->stream));  // warm-up
+    HIP_TRY(p, launch_fill_uniform(p->pk, A, count, 0x5eedull, p->stream));
+    HIP_TRY(p, hipEventRecord(e0, p->stream));
+    HIP_TRY(p, enqueue_iterate(p, A, reps, 0.0, false, p->stream));
+    HIP_TRY(p, hipEventRecord(e1, p->stream));
+    HIP_TRY(p, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(p, hipEventElapsedTime(&ms, e0, e1));
+    *us = 1000.0 * ms / reps;
+    return MBO_OK;
+}
+
+mbo_status autotune_plan(mbo_plan_t p)
+{
+    const int reps = 6;
+    mbo_status s = ensure_logs(p, reps);
+    if (s != MBO_OK) return s;
+    void* A = nullptr;
+    HIP_TRY(p, hipMalloc(&A, (size_t)(p->batch * p->n * p->n * p->npts) * p->esz));
+    int64_t* foff = p->foff_dev;  // the scratch field has the default layout
+    p->foff_dev = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    auto done = [&](mbo_status st) {
+        p->foff_dev = foff;
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFree(A);
+        drop_logs(p);  // the heat pass's workgroup count may have changed
+        return st;
+    };
+    if (he != hipSuccess) return done(fail(p, MBO_ERR_HIP, "hipEventCreate: %s", hipGetErrorString(he)));
+    double best = 0.0, t = 0.0;
+    if ((s = time_iterations(p, A, reps, e0, e1, &best)) != MBO_OK) return done(s);
+    // strided passes: tile width, from one line up to what the rule allows
+    for (int axis = 0; axis < (p->d == 3 ? 2 : 1); ++axis) {
+        ColCfg& c = axis == 0 ? p->heat : p->ypass;
+        int& cap = axis == 0 ? p->tune_tx_heat : p->tune_tx_y;
+        const int tx_max = c.TX;
+        int best_tx = tx_max;
+        for (int tx = 1; tx < tx_max; tx *= 2) {
+            cap = tx;
+            if ((s = config_col(p, c, axis)) != MBO_OK) return done(s);
+            if ((s = time_iterations(p, A, reps, e0, e1, &t)) != MBO_OK) return done(s);
+            if (t < best) {
+                best = t;
+                best_tx = tx;
+            }
+        }
+        cap = best_tx;
+        if ((s = config_col(p, c, axis)) != MBO_OK) return done(s);
+        if (axis == 0) {
+            p->xcd_remap = 0;
+            if ((s = time_iterations(p, A, reps, e0, e1, &t)) != MBO_OK) return done(s);
+            if (t < best) best = t;
+            else p->xcd_remap = 1;
+        }
+    }
+    // rows per row-pass workgroup
+    const int L = (int)p->N[p->d - 1];
+    const int rpw0 = p->row_rpw;
+    int best_rpw = rpw0;
+    for (int rpw = 1; rpw * L <= 2048 && rpw <= p->npts / L; rpw *= 2) {
+        if (rpw == rpw0) continue;
+        p->tune_rpw = rpw;
+        if (config_row(p) != MBO_OK) break;  // beyond the LDS or queue limits
+        if ((s = time_iterations(p, A, reps, e0, e1, &t)) != MBO_OK) return done(s);
+        if (t < best) {
+            best = t;
+            best_rpw = rpw;
+        }
+    }
+    p->tune_rpw = best_rpw;
+    p->err.clear();
+    if ((s = config_row(p)) != MBO_OK) return done(s);
+    p->tuned = true;
+    return done(MBO_OK);
+}
+
+// Lyapunov energy of every field of plan p into E_dev-backed host array E
+// (entry map[b] or b); synchronises p's stream.
+mbo_status energy_into(mbo_plan_t p, const void* A, double* E, const std::vector<int>* map)
+{
+    mbo_status s = ensure_logs(p, 0);
+    if (s != MBO_OK) return s;
+    HIP_TRY(p, enqueue_forward(p, A, 0, true, p->stream));
+    ColArgs h = col_args(p, p->heat);
+    h.K = 0;
+    h.slot = 0;
+    h.epart = p->epart;
+    HIP_TRY(p, run_col(p, p->heat, CM_ENERGY, h, p->stream));
+    ReduceArgs ra;
+    ra.epart = p->epart;
+    ra.nwg = (int)p->heat.grid.x;
+    ra.K = 0;
+    ra.batch = (int)p->batch;
+    ra.n = p->n;
+    ra.npts = p->npts;
+    ra.tau = p->tau;
+    ra.taus = p->taus_dev;
+    ra.stop_iter = nullptr;
+    ra.energy = p->energy;
+    HIP_TRY(p, launch_reduce(ra, p->stream));
+    std::vector<double> h_e((size_t)p->batch);
+    HIP_TRY(p, hipMemcpyAsync(h_e.data(), p->energy, (size_t)p->batch * sizeof(double), hipMemcpyDeviceToHost,
+                              p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    for (size_t b = 0; b < h_e.size(); ++b) E[map ? (size_t)(*map)[b] : b] = h_e[b];
+    return MBO_OK;
+}
+
+std::vector<int> member_fields(mbo_plan_t g, int mi)
+{
+    std::vector<int> map;
+    for (size_t f = 0; f < g->f_member.size(); ++f)
+        if (g->f_member[f] == mi) map.push_back((int)f);
+    return map;
 }
 
 bool use_graphs()
@@ -570,88 +904,110 @@ mbo_status mbo_plan(mbo_plan_t* out, int d, const int64_t* N, int n, int64_t bat
     if (!out) return fail(nullptr, MBO_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!N) return fail(nullptr, MBO_ERR_INVALID_ARG, "N is NULL");
-    if (d != 2 && d != 3) return fail(nullptr, MBO_ERR_INVALID_ARG, "d must be 2 or 3 (got %d)", d);
-    if (n < 1 || n > 4) return fail(nullptr, MBO_ERR_INVALID_ARG, "n must be in [1,4] (got %d)", n);
     if (batch < 1) return fail(nullptr, MBO_ERR_INVALID_ARG, "batch must be >= 1");
-    if (!(tau > 0.0) || !std::isfinite(tau))
-        return fail(nullptr, MBO_ERR_INVALID_ARG, "tau must be finite and > 0");
     if (prec != MBO_F64 && prec != MBO_F32 && prec != MBO_F32_F64FALLBACK)
         return fail(nullptr, MBO_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
-    for (int a = 0; a < d; ++a)
-        if (!is_pow2(N[a]) || N[a] < 8 || N[a] > 2048)
-            return fail(nullptr, MBO_ERR_UNSUPPORTED,
-                        "N[%d] = %lld: each axis must be a power of two in [8, 2048]", a,
-                        (long long)N[a]);
+    const mbo_status cs = check_shape(d, N, n, tau);
+    if (cs != MBO_OK) return cs;
 
     mbo_plan_t p = new mbo_plan_s();
-    p->d = d;
-    for (int a = 0; a < d; ++a) p->N[a] = N[a];
-    p->n = n;
-    p->batch = batch;
-    p->tau = tau;
-    p->prec = prec;
-    p->sigma_fb = sigma_fallback > 0.0 ? sigma_fallback : 1e-3;
-    p->pk = prec == MBO_F64 ? 0 : 1;
-    p->esz = prec == MBO_F64 ? 8 : 4;
-    p->PL = (n * n + 1) / 2;
-    p->npts = 1;
-    for (int a = 0; a < d; ++a) p->npts *= N[a];
-    p->stream = (hipStream_t)hip_stream;
-
-#define PLAN_TRY(expr)                                                                        \
-    do {                                                                                       \
-        hipError_t e_ = (expr);                                                                \
-        if (e_ != hipSuccess) {                                                                \
-            mbo_status s_ = e_ == hipErrorOutOfMemory ? MBO_ERR_ALLOC : MBO_ERR_HIP;           \
-            fail(nullptr, s_, "%s failed: %s", #expr, hipGetErrorString(e_));                  \
-            destroy(p);                                                                        \
-            return s_;                                                                         \
-        }                                                                                      \
-    } while (0)
-#define PLAN_STATUS(expr)                                                                     \
-    do {                                                                                       \
-        mbo_status s_ = (expr);                                                                \
-        if (s_ != MBO_OK) {                                                                    \
-            g_plan_error = p->err;                                                             \
-            destroy(p);                                                                        \
-            return s_;                                                                         \
-        }                                                                                      \
-    } while (0)
-
-    PLAN_TRY(hipGetDevice(&p->device));
-    hipDeviceProp_t prop;
-    PLAN_TRY(hipGetDeviceProperties(&prop, p->device));
-    // leave room for the kernels' static LDS (reduction scratch)
-    p->lds_max = prop.sharedMemPerBlock > 4096 ? (size_t)prop.sharedMemPerBlock - 2048 : 65536;
-    PLAN_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
-
-    PLAN_STATUS(config_row(p));
-    PLAN_STATUS(config_col(p, p->heat, 0));
-    if (d == 3) PLAN_STATUS(config_col(p, p->ypass, 1));
-    prepare_plan_kernels(p);
-
-    const size_t zbytes = (size_t)batch * p->PL * (size_t)p->npts * 2 * p->esz;
-    PLAN_TRY(hipMalloc(&p->Z, zbytes));
-    PLAN_TRY(hipMalloc((void**)&p->sgn, (size_t)batch * (size_t)p->npts));
-    PLAN_TRY(hipMalloc((void**)&p->counters, 4 * sizeof(unsigned long long)));
-    for (int a = 0; a < d; ++a) {
-        for (int b = 0; b < a; ++b)
-            if (N[b] == N[a]) p->tw[a] = p->tw[b];
-        if (p->tw[a]) continue;
-        PLAN_TRY(hipMalloc(&p->tw[a], (size_t)N[a] * 2 * p->esz));
-        PLAN_STATUS(upload(p, p->tw[a], twiddles(N[a])));
+    set_shape(p, d, N, n, batch, tau, prec, sigma_fallback, hip_stream);
+    const mbo_status st = plan_init(p, nullptr);
+    if (st != MBO_OK) {
+        g_plan_error = p->err;
+        destroy(p);
+        return st;
     }
-    PLAN_TRY(hipMalloc(&p->lam_row, (size_t)N[0] * p->esz));
-    PLAN_TRY(hipMalloc(&p->lam_inner, (size_t)(p->npts / N[0]) * p->esz));
-    PLAN_STATUS(build_symbol_tables(p));
-    PLAN_TRY(hipMalloc(&p->mu_row, (size_t)N[0] * p->esz));
-    PLAN_TRY(hipMalloc(&p->mu_inner, (size_t)(p->npts / N[0]) * p->esz));
-    PLAN_STATUS(build_laplace_tables(p));
-    PLAN_TRY(hipMalloc((void**)&p->dpart, (size_t)batch * p->row_grid.x * sizeof(double)));
-    PLAN_TRY(hipMalloc((void**)&p->dsum, (size_t)batch * sizeof(double)));
-#undef PLAN_TRY
-#undef PLAN_STATUS
     *out = p;
+    return MBO_OK;
+}
+
+mbo_status mbo_plan_batched(mbo_plan_t* out, int count, const mbo_field_desc* descs, mbo_precision prec,
+                            double sigma_fallback, int autotune, void* hip_stream)
+{
+    g_plan_error.clear();
+    if (!out) return fail(nullptr, MBO_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !descs) return fail(nullptr, MBO_ERR_INVALID_ARG, "count < 1 or descs is NULL");
+    if (prec != MBO_F64 && prec != MBO_F32 && prec != MBO_F32_F64FALLBACK)
+        return fail(nullptr, MBO_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
+    for (int f = 0; f < count; ++f) {
+        const mbo_status cs = check_shape(descs[f].d, descs[f].N, descs[f].n, descs[f].tau);
+        if (cs != MBO_OK) {
+            g_plan_error = "field " + std::to_string(f) + ": " + g_plan_error;
+            return cs;
+        }
+    }
+    mbo_plan_t g = new mbo_plan_s();
+    g->group = true;
+    g->batch = count;
+    g->prec = prec;
+    g->stream = (hipStream_t)hip_stream;
+    auto bail = [&](mbo_status st, const std::string& msg) {
+        g_plan_error = msg;
+        destroy(g);
+        return st;
+    };
+    hipError_t he = hipGetDevice(&g->device);
+    if (he == hipSuccess) he = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking);
+    if (he != hipSuccess) return bail(MBO_ERR_HIP, std::string("device set-up: ") + hipGetErrorString(he));
+
+    // classes of equal (d, N, n), in order of first appearance; the fields are
+    // concatenated in the caller's order
+    std::vector<int> rep_of;  // representative field of each class
+    int64_t off = 0;
+    for (int f = 0; f < count; ++f) {
+        const mbo_field_desc& df = descs[f];
+        int c = -1;
+        for (size_t k = 0; k < rep_of.size() && c < 0; ++k) {
+            const mbo_field_desc& dr = descs[rep_of[k]];
+            bool same = dr.d == df.d && dr.n == df.n;
+            for (int a = 0; a < df.d && same; ++a) same = dr.N[a] == df.N[a];
+            if (same) c = (int)k;
+        }
+        if (c < 0) {
+            c = (int)rep_of.size();
+            rep_of.push_back(f);
+        }
+        g->f_member.push_back(c);
+        g->f_off.push_back(off);
+        int64_t pts = 1;
+        for (int a = 0; a < df.d; ++a) pts *= df.N[a];
+        off += (int64_t)df.n * df.n * pts;
+    }
+    g->f_index.assign((size_t)count, 0);
+    for (size_t c = 0; c < rep_of.size(); ++c) {
+        const mbo_field_desc& dr = descs[rep_of[c]];
+        std::vector<double> taus;
+        std::vector<int64_t> foff;
+        for (int f = 0; f < count; ++f)
+            if (g->f_member[(size_t)f] == (int)c) {
+                g->f_index[(size_t)f] = (int)taus.size();
+                taus.push_back(descs[f].tau);
+                foff.push_back(g->f_off[(size_t)f]);
+            }
+        mbo_plan_t m = new mbo_plan_s();
+        set_shape(m, dr.d, dr.N, dr.n, (int64_t)taus.size(), taus[0], prec, sigma_fallback, hip_stream);
+        m->per_field_tau = true;
+        m->taus = taus;
+        g->members.push_back(m);
+        mbo_status st = plan_init(m, foff.data());
+        if (st == MBO_OK && autotune) st = autotune_plan(m);
+        if (st != MBO_OK) return bail(st, "field class " + std::to_string(c) + ": " + m->err);
+    }
+    *out = g;
+    return MBO_OK;
+}
+
+mbo_status mbo_plan_tuning(mbo_plan_t p, int field, int* rows_per_group, int* heat_lines_per_group,
+                           int* xcd_order)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (field < 0 || field >= (int)p->batch) return fail(p, MBO_ERR_INVALID_ARG, "field out of range");
+    mbo_plan_t m = p->group ? p->members[(size_t)p->f_member[(size_t)field]] : p;
+    if (rows_per_group) *rows_per_group = m->row_rpw;
+    if (heat_lines_per_group) *heat_lines_per_group = m->heat.TX;
+    if (xcd_order) *xcd_order = m->xcd_remap;
     return MBO_OK;
 }
 
@@ -664,6 +1020,7 @@ mbo_status mbo_plan_destroy(mbo_plan_t plan)
 mbo_status mbo_plan_set_tau(mbo_plan_t p, double tau)
 {
     if (!p) return MBO_ERR_INVALID_ARG;
+    if (p->group) return fail(p, MBO_ERR_UNSUPPORTED, "the fields of a batched plan keep their own tau");
     if (!(tau > 0.0) || !std::isfinite(tau)) return fail(p, MBO_ERR_INVALID_ARG, "tau must be finite and > 0");
     HIP_TRY(p, hipSetDevice(p->device));
     HIP_TRY(p, hipStreamSynchronize(p->stream));  // tables may be in use by queued work
@@ -675,6 +1032,7 @@ mbo_status mbo_plan_set_tau(mbo_plan_t p, double tau)
 mbo_status mbo_plan_set_timing(mbo_plan_t p, int enable)
 {
     if (!p) return MBO_ERR_INVALID_ARG;
+    if (p->group && enable) return fail(p, MBO_ERR_UNSUPPORTED, "no kernel timing for a batched plan");
     if (p->timing != (enable != 0)) drop_graph(p);
     p->timing = enable != 0;
     return MBO_OK;
@@ -693,6 +1051,7 @@ mbo_status mbo_plan_set_stream(mbo_plan_t p, void* hip_stream)
 {
     if (!p) return MBO_ERR_INVALID_ARG;
     p->stream = (hipStream_t)hip_stream;
+    for (mbo_plan_t m : p->members) m->stream = (hipStream_t)hip_stream;
     return MBO_OK;
 }
 
@@ -701,6 +1060,13 @@ mbo_status mbo_diffuse(mbo_plan_t p, const void* A_in, void* A_out)
     if (!p) return MBO_ERR_INVALID_ARG;
     if (!A_in || !A_out) return fail(p, MBO_ERR_INVALID_ARG, "A_in / A_out is NULL");
     HIP_TRY(p, hipSetDevice(p->device));
+    if (p->group) {
+        for (mbo_plan_t m : p->members) {
+            const mbo_status s = mbo_diffuse(m, A_in, A_out);
+            if (s != MBO_OK) return fail(p, s, "%s", m->err.c_str());
+        }
+        return MBO_OK;
+    }
     HIP_TRY(p, enqueue_forward(p, A_in, 0, true, p->stream));
     ColArgs h = col_args(p, p->heat);
     HIP_TRY(p, run_col(p, p->heat, CM_HEAT, h, p->stream));
@@ -720,6 +1086,14 @@ mbo_status mbo_project(mbo_plan_t p, const void* A_in, void* A_out, int8_t* det_
     if (!p) return MBO_ERR_INVALID_ARG;
     if (!A_in || !A_out) return fail(p, MBO_ERR_INVALID_ARG, "A_in / A_out is NULL");
     HIP_TRY(p, hipSetDevice(p->device));
+    if (p->group) {
+        if (det_sign) return fail(p, MBO_ERR_UNSUPPORTED, "det_sign is not available for a batched plan");
+        for (mbo_plan_t m : p->members) {
+            const mbo_status s = mbo_project(m, A_in, A_out, nullptr);
+            if (s != MBO_OK) return fail(p, s, "%s", m->err.c_str());
+        }
+        return MBO_OK;
+    }
     HIP_TRY(p, launch_fill_u64(p->counters, 4, 0ull, p->stream));
     ProjArgs a;
     a.npts = p->npts;
@@ -730,6 +1104,7 @@ mbo_status mbo_project(mbo_plan_t p, const void* A_in, void* A_out, int8_t* det_
     a.fallbacks = p->counters + 1;
     a.fallback = p->prec == MBO_F32_F64FALLBACK;
     a.sigma_fb = p->sigma_fb;
+    a.foff = p->foff_dev;
     HIP_TRY(p, launch_project(p->pk, p->n, a, (int)p->batch, p->stream));
     unsigned long long h[4];
     HIP_TRY(p, hipMemcpyAsync(h, p->counters, sizeof h, hipMemcpyDeviceToHost, p->stream));
@@ -741,6 +1116,7 @@ mbo_status mbo_project(mbo_plan_t p, const void* A_in, void* A_out, int8_t* det_
 mbo_status mbo_diffuse_dtau(mbo_plan_t p, const void* A, void* out, const void* G, double* dot)
 {
     if (!p) return MBO_ERR_INVALID_ARG;
+    if (p->group) return fail(p, MBO_ERR_UNSUPPORTED, "not available for a batched plan");
     if (!A) return fail(p, MBO_ERR_INVALID_ARG, "A is NULL");
     const bool want_dot = G != nullptr && dot != nullptr;
     if (!out && !want_dot) return fail(p, MBO_ERR_INVALID_ARG, "neither out nor (G, dot) given");
@@ -771,6 +1147,7 @@ mbo_status mbo_diffuse_dtau(mbo_plan_t p, const void* A, void* out, const void* 
 mbo_status mbo_project_vjp(mbo_plan_t p, const void* A_tilde, const void* G_Q, void* G_A)
 {
     if (!p) return MBO_ERR_INVALID_ARG;
+    if (p->group) return fail(p, MBO_ERR_UNSUPPORTED, "not available for a batched plan");
     if (!A_tilde || !G_Q || !G_A) return fail(p, MBO_ERR_INVALID_ARG, "A_tilde / G_Q / G_A is NULL");
     HIP_TRY(p, hipSetDevice(p->device));
     HIP_TRY(p, launch_fill_u64(p->counters, 4, 0ull, p->stream));
@@ -795,28 +1172,12 @@ mbo_status mbo_energy(mbo_plan_t p, const void* A, double* E)
     if (!p) return MBO_ERR_INVALID_ARG;
     if (!A || !E) return fail(p, MBO_ERR_INVALID_ARG, "A / E is NULL");
     HIP_TRY(p, hipSetDevice(p->device));
-    mbo_status s = ensure_logs(p, 0);
-    if (s != MBO_OK) return s;
-    HIP_TRY(p, enqueue_forward(p, A, 0, true, p->stream));
-    ColArgs h = col_args(p, p->heat);
-    h.K = 0;
-    h.slot = 0;
-    h.epart = p->epart;
-    HIP_TRY(p, run_col(p, p->heat, CM_ENERGY, h, p->stream));
-    ReduceArgs ra;
-    ra.epart = p->epart;
-    ra.nwg = (int)p->heat.grid.x;
-    ra.K = 0;
-    ra.batch = (int)p->batch;
-    ra.n = p->n;
-    ra.npts = p->npts;
-    ra.tau = p->tau;
-    ra.stop_iter = nullptr;
-    ra.energy = p->energy;
-    HIP_TRY(p, launch_reduce(ra, p->stream));
-    HIP_TRY(p, hipMemcpyAsync(E, p->energy, (size_t)p->batch * sizeof(double), hipMemcpyDeviceToHost,
-                              p->stream));
-    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    if (!p->group) return energy_into(p, A, E, nullptr);
+    for (size_t mi = 0; mi < p->members.size(); ++mi) {
+        const std::vector<int> map = member_fields(p, (int)mi);
+        const mbo_status s = energy_into(p->members[mi], A, E, &map);
+        if (s != MBO_OK) return fail(p, s, "%s", p->members[mi]->err.c_str());
+    }
     return MBO_OK;
 }
 
@@ -830,8 +1191,13 @@ mbo_status mbo_iterate(mbo_plan_t p, void* A, int max_iter, double tol, int* ite
     HIP_TRY(p, hipSetDevice(p->device));
     const int K = max_iter;
     const bool want_energy = energy != nullptr;
-    mbo_status s = ensure_logs(p, K);
-    if (s != MBO_OK) return s;
+    mbo_status s;
+    if (p->group) {
+        for (mbo_plan_t m : p->members)
+            if ((s = ensure_logs(m, K)) != MBO_OK) return fail(p, s, "%s", m->err.c_str());
+    } else if ((s = ensure_logs(p, K)) != MBO_OK) {
+        return s;
+    }
     if (p->timing && p->ev_K < K) {
         p->ev.reserve(4 * (size_t)K);
         while ((int)p->ev.size() < 4 * K) {
@@ -842,13 +1208,21 @@ mbo_status mbo_iterate(mbo_plan_t p, void* A, int max_iter, double tol, int* ite
         p->ev_K = K;
         drop_graph(p);
     }
+    auto enqueue_all = [&](hipStream_t st) -> hipError_t {
+        if (!p->group) return enqueue_iterate(p, A, K, tol, want_energy, st);
+        for (mbo_plan_t m : p->members) {
+            hipError_t e = enqueue_iterate(m, A, K, tol, want_energy, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
     const int key = (tol > 0.0 ? 1 : 0) | (want_energy ? 2 : 0) | (p->timing ? 4 : 0);
     if (use_graphs() && !p->timing) {
         if (!(p->gexec && p->g_A == A && p->g_K == K && p->g_key == key && p->g_tol == tol)) {
             drop_graph(p);
             hipGraph_t g = nullptr;
             HIP_TRY(p, hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
-            hipError_t e = enqueue_iterate(p, A, K, tol, want_energy, p->cap);
+            hipError_t e = enqueue_all(p->cap);
             hipError_t e2 = hipStreamEndCapture(p->cap, &g);
             if (e != hipSuccess || e2 != hipSuccess) {
                 if (g) (void)hipGraphDestroy(g);
@@ -868,63 +1242,24 @@ mbo_status mbo_iterate(mbo_plan_t p, void* A, int max_iter, double tol, int* ite
         }
         HIP_TRY(p, hipGraphLaunch(p->gexec, p->stream));
     } else {
-        HIP_TRY(p, enqueue_iterate(p, A, K, tol, want_energy, p->stream));
+        HIP_TRY(p, enqueue_all(p->stream));
     }
 
     // one copy of the logs at the end
-    const size_t B = (size_t)p->batch;
-    const size_t cs = B * (size_t)(K > 0 ? K : 1);
-    std::vector<int> st(B);
-    std::vector<unsigned long long> hf(cs), hfb(cs), hbad(cs), hd(cs);
-    std::vector<double> he(B * (size_t)(K + 1));
-    HIP_TRY(p, hipMemcpyAsync(st.data(), p->stop_iter, B * sizeof(int), hipMemcpyDeviceToHost, p->stream));
-    HIP_TRY(p, hipMemcpyAsync(hf.data(), p->flips, cs * 8, hipMemcpyDeviceToHost, p->stream));
-    HIP_TRY(p, hipMemcpyAsync(hfb.data(), p->fallbacks, cs * 8, hipMemcpyDeviceToHost, p->stream));
-    HIP_TRY(p, hipMemcpyAsync(hbad.data(), p->nonfinite, cs * 8, hipMemcpyDeviceToHost, p->stream));
-    HIP_TRY(p, hipMemcpyAsync(hd.data(), p->delta_bits, cs * 8, hipMemcpyDeviceToHost, p->stream));
-    if (want_energy)
-        HIP_TRY(p, hipMemcpyAsync(he.data(), p->energy, he.size() * sizeof(double), hipMemcpyDeviceToHost,
-                                  p->stream));
-    HIP_TRY(p, hipStreamSynchronize(p->stream));
-
-    if (p->timing && K > 0) {
-        // average over the iterations every field ran (stopped fields skip kernels)
-        int ran = K;
-        for (size_t b = 0; b < B; ++b) ran = st[b] < ran ? st[b] : ran;
-        double tr = 0.0, tc = 0.0;
-        for (int k = 0; k < ran; ++k) {
-            float ms_r = 0.f, ms_c = 0.f;
-            HIP_TRY(p, hipEventElapsedTime(&ms_r, p->ev[4 * k], p->ev[4 * k + 1]));
-            HIP_TRY(p, hipEventElapsedTime(&ms_c, p->ev[4 * k + 2], p->ev[4 * k + 3]));
-            tr += ms_r;
-            tc += ms_c;
-        }
-        p->t_launches = ran;
-        p->t_row_us = ran ? 1000.0 * tr / ran : 0.0;
-        p->t_col_us = ran ? 1000.0 * tc / ran : 0.0;
-    }
-
     unsigned long long bad = 0;
-    for (size_t b = 0; b < B; ++b) {
-        const int done = st[b];
-        if (iters_done) iters_done[b] = done;
-        for (int k = 0; k < K; ++k) {
-            const size_t i = b * (size_t)K + (size_t)k;
-            const bool ran = k < done;
-            if (flips) flips[i] = ran ? (int64_t)hf[i] : 0;
-            if (fallbacks) fallbacks[i] = ran ? (int64_t)hfb[i] : 0;
-            if (delta) {
-                double dv;
-                std::memcpy(&dv, &hd[i], sizeof dv);
-                delta[i] = (ran && tol > 0.0) ? dv : -1.0;
-            }
-            if (ran) bad += hbad[i];
+    if (p->group) {
+        for (size_t mi = 0; mi < p->members.size(); ++mi) {
+            mbo_plan_t m = p->members[mi];
+            std::vector<int> map;
+            for (size_t f = 0; f < p->f_member.size(); ++f)
+                if (p->f_member[f] == (int)mi) map.push_back((int)f);
+            if ((s = read_logs(m, K, tol, p->stream, iters_done, energy, flips, delta, fallbacks, &map,
+                               &bad)) != MBO_OK)
+                return fail(p, s, "%s", m->err.c_str());
         }
-        if (energy)
-            for (int k = 0; k <= K; ++k) {
-                const size_t i = b * (size_t)(K + 1) + (size_t)k;
-                energy[i] = k <= done ? he[i] : std::nan("");
-            }
+    } else if ((s = read_logs(p, K, tol, p->stream, iters_done, energy, flips, delta, fallbacks, nullptr,
+                              &bad)) != MBO_OK) {
+        return s;
     }
     if (bad) return fail(p, MBO_ERR_NONFINITE, "%llu projections met NaN/Inf input", bad);
     return MBO_OK;

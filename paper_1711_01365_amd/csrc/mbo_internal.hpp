@@ -44,13 +44,21 @@ struct RowArgs {
     double sigma_fb;         // fallback threshold
     const void* Gdot;        // RF_DOT: real field G [batch][n*n][npts]
     double* dpart;           // RF_DOT: partials [batch][gridDim.x]
+    const int64_t* foff;     // nullable: element offset of field b in Ain / Aout / Gdot
+                             // (default b * n*n * npts)
 };
 
+// Element offset of field b of a real-field buffer.
+__host__ __device__ inline int64_t field_base(const int64_t* foff, int b, int64_t field_elems)
+{
+    return foff ? foff[b] : (int64_t)b * field_elems;
+}
+
 // Double-precision re-projection queue of the float row pass for n >= 3: one
-// 16-bit index per point of the workgroup's rows (at most max(256, L) points)
+// 16-bit index per point of the workgroup's rows (the host keeps it within max(1024, L) points)
 // and the float right singular vectors of the first ROW_FB_STASH queued points.
 constexpr int ROW_FB_STASH = 32;
-constexpr int row_fb_queue_len(int log2L) { return (1 << log2L) > 256 ? (1 << log2L) : 256; }
+constexpr int row_fb_queue_len(int log2L) { return (1 << log2L) > 1024 ? (1 << log2L) : 1024; }
 // Static LDS the queue adds to a row-pass workgroup, in bytes.
 constexpr size_t row_fb_lds(int esz, int n, int log2L)
 {
@@ -72,6 +80,9 @@ struct ColArgs {
     void* Z;
     const void* lam_row;     // heat symbol factor of this axis [L] (incl. 1/L)
     const void* lam_inner;   // product of the factors of the faster axes [S]
+    int64_t lam_row_stride;   // per-field tables: offset between fields (0: shared)
+    int64_t lam_inner_stride;
+    int xcd_remap;           // deal tiles to XCDs in contiguous runs
     const void* mu_row;      // CM_DTAU: -4 pi^2 k^2 of this axis [L]
     const void* mu_inner;    // CM_DTAU: -4 pi^2 |k|^2 summed over the faster axes [S]
     double* epart;           // energy partials [batch][K+1][nwg]
@@ -93,6 +104,7 @@ struct ProjArgs {
     unsigned long long* fallbacks;
     int fallback;
     double sigma_fb;
+    const int64_t* foff;     // nullable: element offset of field b in A and Q
 };
 
 // Vector-Jacobian product of the projection, one point per thread.
@@ -114,6 +126,7 @@ struct ReduceArgs {
     int n;
     int64_t npts;
     double tau;
+    const double* taus;      // nullable: per-field tau [batch]
     const int* stop_iter;    // nullable: all slots 0..K
     double* energy;          // [batch][K+1]
 };
@@ -134,6 +147,8 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long l
 hipError_t launch_fill_i32(int* p, int64_t count, int v, hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
 hipError_t launch_vjp(int prec, int n, const VjpArgs& a, int batch, hipStream_t st);
+// count values uniform in [-1, 1) from a counter-based hash of (seed, index)
+hipError_t launch_fill_uniform(int prec, void* p, int64_t count, uint64_t seed, hipStream_t st);
 // out[b] = sum of part[b * m .. b * m + m - 1] in a fixed order
 hipError_t launch_sum_rows(const double* part, int64_t m, int batch, double* out, hipStream_t st);
 

@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
         const int64_t x0 = (row0 + rloc) * L + t;
         T r[1][8], im[1][8];
         if (flags & RF_LOAD_REAL) {
-            const T* A = reinterpret_cast<const T*>(a.Ain) + (size_t)b * NN * npts;
+            const T* A = reinterpret_cast<const T*>(a.Ain) + field_base(a.foff, b, NN * npts);
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int64_t x = x0 + (int64_t)e * Tn;
@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
     unsigned long long nflip = 0, nfb = 0, nbad = 0;
     double dmax = 0.0, dacc = 0.0;
     if (flags & (RF_PROJECT | RF_SIGN_INIT | RF_STORE_REAL | RF_DOT)) {
-        T* Aout = reinterpret_cast<T*>(a.Aout) + (size_t)b * NN * npts;
+        T* Aout = reinterpret_cast<T*>(a.Aout) + field_base(a.foff, b, NN * npts);
         int8_t* sgn = a.sgn + (size_t)b * npts;
         const bool defer = DEFER && (flags & RF_PROJECT) && (flags & RF_FALLBACK);
         if (defer) {
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
             for (int k = 0; k < NN; ++k) av[k] = (k & 1) ? lir[(k >> 1) * lp] : lrr[(k >> 1) * lp];
             if (flags & RF_SIGN_INIT) sgn[x] = det_n<T, n>(av) >= (T)0 ? 1 : -1;
             if (flags & RF_DOT) {
-                const T* Gd = reinterpret_cast<const T*>(a.Gdot) + (size_t)b * NN * npts;
+                const T* Gd = reinterpret_cast<const T*>(a.Gdot) + field_base(a.foff, b, NN * npts);
 #pragma unroll
                 for (int k = 0; k < NN; ++k) dacc += (double)Gd[(int64_t)k * npts + x] * (double)av[k];
             }
@@ -385,8 +385,9 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
     // each with its own L2.  Give every XCD a contiguous run of tiles so that the
     // tiles sharing a 128-byte line (TX * sizeof(C) < 128) meet in one L2.
     const int64_t nwgx = gridDim.x;
-    const int64_t wg = (nwgx & 7) ? (int64_t)blockIdx.x
-                                  : (int64_t)(blockIdx.x & 7) * (nwgx >> 3) + (blockIdx.x >> 3);
+    const int64_t wg = ((nwgx & 7) || !a.xcd_remap)
+                           ? (int64_t)blockIdx.x
+                           : (int64_t)(blockIdx.x & 7) * (nwgx >> 3) + (blockIdx.x >> 3);
     const int64_t o = wg / a.tiles;
     const int64_t tile0 = (wg - o * a.tiles) * TX;
     const int64_t S = a.S;
@@ -425,8 +426,8 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
         if (MODE == CM_INVERSE) fft_wave<T, +1, LOG2L>(r, im, lr, li, tt, tw, true);
         else fft_wave<T, -1, LOG2L>(r, im, lr, li, tt, tw, true);
         if (MODE == CM_HEAT || MODE == CM_ENERGY || MODE == CM_DTAU) {
-            const T* lrow = reinterpret_cast<const T*>(a.lam_row);
-            const T lin = reinterpret_cast<const T*>(a.lam_inner)[tile0 + c];
+            const T* lrow = reinterpret_cast<const T*>(a.lam_row) + b * a.lam_row_stride;
+            const T lin = reinterpret_cast<const T*>(a.lam_inner)[b * a.lam_inner_stride + tile0 + c];
             const T muin = MODE == CM_DTAU ? reinterpret_cast<const T*>(a.mu_inner)[tile0 + c] : (T)0;
             double acc = 0.0;
 #pragma unroll
@@ -488,8 +489,8 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
         else
             fft_lines<T, -1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
         if (MODE == CM_HEAT || MODE == CM_ENERGY || MODE == CM_DTAU) {
-            const T* lrow = reinterpret_cast<const T*>(a.lam_row);
-            const T lin = reinterpret_cast<const T*>(a.lam_inner)[tile0 + tx];
+            const T* lrow = reinterpret_cast<const T*>(a.lam_row) + b * a.lam_row_stride;
+            const T lin = reinterpret_cast<const T*>(a.lam_inner)[b * a.lam_inner_stride + tile0 + tx];
             const T muin = MODE == CM_DTAU ? reinterpret_cast<const T*>(a.mu_inner)[tile0 + tx] : (T)0;
             double acc = 0.0;
 #pragma unroll

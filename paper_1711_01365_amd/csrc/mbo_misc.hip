@@ -18,8 +18,8 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjArgs a)
     __shared__ unsigned long long red_u[64];
     unsigned long long bad = 0, fb = 0;
     if (p < a.npts) {
-        const T* A = reinterpret_cast<const T*>(a.A) + (size_t)b * NN * a.npts;
-        T* Q = reinterpret_cast<T*>(a.Q) + (size_t)b * NN * a.npts;
+        const T* A = reinterpret_cast<const T*>(a.A) + field_base(a.foff, b, NN * a.npts);
+        T* Q = reinterpret_cast<T*>(a.Q) + field_base(a.foff, b, NN * a.npts);
         T av[NN], qv[NN];
 #pragma unroll
         for (int k = 0; k < NN; ++k) av[k] = A[(int64_t)k * a.npts + p];
@@ -105,6 +105,20 @@ __global__ void fill_u64(unsigned long long* p, int64_t count, unsigned long lon
     if (i < count) p[i] = v;
 }
 
+// splitmix64 (Steele, Lea and Flood, 2014) of seed + index, top 53 bits as a
+// double in [0, 1), mapped to [-1, 1)
+template <typename T>
+__global__ void fill_uniform(T* p, int64_t count, uint64_t seed)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    uint64_t z = seed + (uint64_t)i * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    p[i] = (T)(2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0);
+}
+
 __global__ void fill_i32(int* p, int64_t count, int v)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -124,7 +138,7 @@ __global__ void reduce_energy(const ReduceArgs a)
     const double* p = a.epart + idx * a.nwg;
     double sum = 0.0;
     for (int i = 0; i < a.nwg; ++i) sum += p[i];
-    a.energy[idx] = ((double)a.n - sum / (double)a.npts) / a.tau;
+    a.energy[idx] = ((double)a.n - sum / (double)a.npts) / (a.taus ? a.taus[b] : a.tau);
 }
 
 // ---------------------------------------------------------------------------
@@ -201,6 +215,15 @@ hipError_t launch_fill_i32(int* p, int64_t count, int v, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_uniform(int prec, void* p, int64_t count, uint64_t seed, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    const dim3 g((unsigned)((count + 255) / 256));
+    if (prec == 0) hipLaunchKernelGGL(fill_uniform<double>, g, dim3(256), 0, st, (double*)p, count, seed);
+    else hipLaunchKernelGGL(fill_uniform<float>, g, dim3(256), 0, st, (float*)p, count, seed);
     return hipGetLastError();
 }
 

@@ -27,8 +27,14 @@ _lib = None
 
 EXPORTS = ("mbo_plan", "mbo_plan_destroy", "mbo_plan_set_tau", "mbo_plan_set_stream",
            "mbo_plan_set_timing", "mbo_last_timing", "mbo_diffuse", "mbo_project", "mbo_iterate",
-           "mbo_energy", "mbo_project_vjp", "mbo_diffuse_dtau", "mbo_status_string",
-           "mbo_last_error")
+           "mbo_energy", "mbo_project_vjp", "mbo_diffuse_dtau", "mbo_plan_batched", "mbo_plan_tuning",
+           "mbo_status_string", "mbo_last_error")
+
+
+class FieldDesc(ctypes.Structure):
+    """mbo_field_desc: one field of a batched plan."""
+    _fields_ = [("d", ctypes.c_int), ("N", ctypes.c_int64 * 3), ("n", ctypes.c_int),
+                ("tau", ctypes.c_double)]
 
 
 class MboError(RuntimeError):
@@ -60,6 +66,9 @@ def load(path: str = LIB_PATH):
     lib.mbo_energy.argtypes = [vp, vp, dp]
     lib.mbo_project_vjp.argtypes = [vp, vp, vp, vp]
     lib.mbo_diffuse_dtau.argtypes = [vp, vp, vp, vp, dp]
+    lib.mbo_plan_batched.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(FieldDesc),
+                                     ctypes.c_int, ctypes.c_double, ctypes.c_int, vp]
+    lib.mbo_plan_tuning.argtypes = [vp, ctypes.c_int, ip, ip, ip]
     for f in EXPORTS:
         if f not in ("mbo_status_string", "mbo_last_error"):
             getattr(lib, f).restype = ctypes.c_int
@@ -215,6 +224,13 @@ class Plan:
             out.update(energy=en, flips=fl[:, :K], delta=dl[:, :K], fallbacks=fb[:, :K])
         return out
 
+    def tuning(self, field: int = 0):
+        """(rows per row-pass workgroup, lines per heat-pass workgroup, XCD tile order)."""
+        r, t, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.mbo_plan_tuning(self._h, int(field), ctypes.byref(r), ctypes.byref(t),
+                                         ctypes.byref(x)), self._h)
+        return r.value, t.value, x.value
+
     def close(self):
         if getattr(self, "_h", None):
             self._lib.mbo_plan_destroy(self._h)
@@ -235,3 +251,64 @@ class Plan:
 
 def status_string(code: int) -> str:
     return load().mbo_status_string(code).decode()
+
+
+class BatchedPlan(Plan):
+    """Owns a batched ``mbo_plan_t`` (mbo_plan_batched): independent fields of
+    mixed grid, n and tau, iterated together.  Field tensors are flat, the
+    concatenation of the fields in order (``pack`` / ``unpack``)."""
+
+    def __init__(self, fields, precision: int = F32, sigma_fallback: float = 1e-3,
+                 autotune: bool = True, stream=None):
+        lib = load()
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: libmbo runs on the GPU only")
+        self.fields = [(tuple(int(g) for g in grid), int(n), float(tau)) for grid, n, tau in fields]
+        descs = (FieldDesc * len(self.fields))()
+        self.offsets, off = [], 0
+        for i, (grid, n, tau) in enumerate(self.fields):
+            descs[i].d = len(grid)
+            for a in range(3):
+                descs[i].N[a] = grid[a] if a < len(grid) else 1
+            descs[i].n = n
+            descs[i].tau = tau
+            self.offsets.append(off)
+            off += n * n * int(np.prod(grid))
+        self.total = off
+        self.batch = len(self.fields)
+        self.precision = int(precision)
+        self.dtype = torch.float64 if precision == F64 else torch.float32
+        h = ctypes.c_void_p()
+        rc = lib.mbo_plan_batched(ctypes.byref(h), len(self.fields), descs, self.precision,
+                                  float(sigma_fallback), int(bool(autotune)), _stream_ptr(stream))
+        _check(rc, None)
+        self._h = h
+        self._lib = lib
+
+    @property
+    def shape(self):
+        return (self.total,)
+
+    def _field(self, A, name="A"):
+        import torch
+        if not isinstance(A, torch.Tensor) or not A.is_cuda:
+            raise TypeError("%s must be a CUDA/HIP tensor" % name)
+        if A.dtype != self.dtype:
+            raise TypeError("%s must be %s" % (name, self.dtype))
+        if A.numel() != self.total or not A.is_contiguous():
+            raise ValueError("%s must be contiguous with %d elements" % (name, self.total))
+        return ctypes.c_void_p(A.data_ptr())
+
+    def pack(self, tensors):
+        """Concatenate per-field tensors (n, n, *grid) into one flat device tensor."""
+        import torch
+        return torch.cat([t.reshape(-1) for t in tensors]).to(self.dtype).contiguous()
+
+    def unpack(self, flat):
+        """Views of the fields of a flat tensor, shaped (n, n, *grid)."""
+        out = []
+        for (grid, n, _), off in zip(self.fields, self.offsets):
+            m = n * n * int(np.prod(grid))
+            out.append(flat[off:off + m].view((n, n) + grid))
+        return out

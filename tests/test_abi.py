@@ -82,3 +82,46 @@ def test_binding_refuses_without_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         mbo.Plan((64, 64), 2, 1e-3)
+
+
+def _batched(lib, descs, prec=2, count=None, out=True):
+    arr = (mbo.FieldDesc * max(len(descs), 1))()
+    for i, (d, N, n, tau) in enumerate(descs):
+        arr[i].d = d
+        for a in range(3):
+            arr[i].N[a] = N[a] if a < len(N) else 1
+        arr[i].n = n
+        arr[i].tau = tau
+    h = ctypes.c_void_p()
+    rc = lib.mbo_plan_batched(ctypes.byref(h) if out else None, len(descs) if count is None else count,
+                              arr, prec, 0.0, 0, None)
+    return rc, h
+
+
+@pytest.mark.parametrize("descs,kw,code", [
+    ([(2, (64, 64), 2, 1e-3)], dict(out=False), 1),
+    ([(2, (64, 64), 2, 1e-3)], dict(count=0), 1),
+    ([(2, (64, 64), 2, 1e-3)], dict(prec=9), 1),
+    ([(2, (64, 64), 2, 1e-3), (2, (32, 32), 5, 1e-3)], {}, 1),
+    ([(2, (64, 64), 2, 1e-3), (2, (32, 32), 3, 0.0)], {}, 1),
+    ([(2, (64, 64), 2, 1e-3), (1, (32,), 3, 1e-3)], {}, 1),
+    ([(2, (64, 64), 2, 1e-3), (2, (32, 24), 3, 1e-3)], {}, 2),
+    ([(3, (16, 16, 4096), 2, 1e-3)], {}, 2),
+])
+def test_batched_plan_validation_codes(lib, descs, kw, code):
+    rc, h = _batched(lib, descs, **kw)
+    assert rc == code
+    assert h.value is None
+    assert lib.mbo_last_error(None)
+
+
+def test_batched_desc_layout():
+    """mbo_field_desc as the C compiler lays it out: int, int64_t[3], int, double."""
+    assert ctypes.sizeof(mbo.FieldDesc) == 48
+    assert mbo.FieldDesc.N.offset == 8 and mbo.FieldDesc.n.offset == 32 and mbo.FieldDesc.tau.offset == 40
+
+
+def test_null_plan_is_rejected_by_new_calls(lib):
+    assert lib.mbo_plan_tuning(None, 0, None, None, None) == 1
+    assert lib.mbo_project_vjp(None, None, None, None) == 1
+    assert lib.mbo_diffuse_dtau(None, None, None, None, None) == 1
