@@ -20,8 +20,10 @@ right after the timed ones (launched directly, since events inside a captured
 graph cannot be timed).  `cpu_baseline` is
 the FP64 CPU oracle on a bounded sample (the first iterations of the same
 workload).  Beside the main line: the 3-D configuration (n = 3, 128^3, 100
-iterations, FP32 + fallback) and the gradient of 50 unrolled steps (n = 3,
-256^2, FP32 + fallback and FP64), forward and backward time.
+iterations, FP32 + fallback), the batched configuration (64 fields of mixed n,
+grid and tau, 50 iterations in one graph; FP32 autotuned, FP32 with the fixed
+launch rules, FP64) and the gradient of 50 unrolled steps (n = 3, 256^2, FP32 +
+fallback and FP64), forward and backward time.
 
     python bench.py --copy-calibration
 
@@ -193,6 +195,34 @@ def run_adjoint(precision, reps):
             "point_steps_per_s": w.points * w.iters * 2 / (f + b)}
 
 
+def run_batched(precision, autotune, steps):
+    """64 fields of mixed n, grid and tau (seed 3), 50 iterations each, one graph:
+    total point-iterations per second over all fields."""
+    import torch
+    from paper_1711_01365_amd import inputs, mbo
+    bw = inputs.BatchedWorkload()
+    dt = torch.float64 if precision == mbo.F64 else torch.float32
+    t0 = time.perf_counter()
+    bp = mbo.BatchedPlan([(m.grid, m.n, m.tau) for m in bw.members], precision=precision,
+                         autotune=autotune)
+    plan_s = time.perf_counter() - t0
+    F0 = bp.pack([torch.tensor(m.field(), dtype=dt, device="cuda") for m in bw.members])
+    F = F0.clone()
+    F.copy_(F0)
+    bp.iterate(F, bw.iters, logs=False)  # captures the graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        F.copy_(F0)
+        bp.iterate(F, bw.iters, logs=False)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    bp.close()
+    return {"workload": "64 fields seed 3, n in {2,3,4}, 128^2..1024^2, 50 it",
+            "value": bw.points * bw.iters * steps / sec, "unit": "point-iterations/s",
+            "ms_per_run": 1000.0 * sec / steps, "plan_s": plan_s, "autotune": bool(autotune)}
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle on the first iterations of the same workload."""
     import oracle
@@ -288,6 +318,12 @@ def main():
     if not args.no_extra:
         out["config_3d"] = run_3d(3, 1)
         log("3-D n=3 128^3 fp32+fallback: %.3e point-iter/s" % out["config_3d"]["value"])
+        out["batched"] = {"f32_autotuned": run_batched(mbo.F32, True, 3),
+                          "f32_fixed_rules": run_batched(mbo.F32, False, 3),
+                          "f64_autotuned": run_batched(mbo.F64, True, 2)}
+        log("batched 64 fields: f32 tuned %.3e, f32 rules %.3e, f64 tuned %.3e point-iter/s"
+            % (out["batched"]["f32_autotuned"]["value"], out["batched"]["f32_fixed_rules"]["value"],
+               out["batched"]["f64_autotuned"]["value"]))
         out["adjoint"] = {"f32_f64fallback": run_adjoint(mbo.F32_F64FALLBACK, 2),
                           "f64": run_adjoint(mbo.F64, 2)}
         log("adjoint K=50 256^2: fp32+fb fwd %.1f ms bwd %.1f ms, fp64 fwd %.1f ms bwd %.1f ms"

@@ -391,6 +391,8 @@ ColArgs col_args(mbo_plan_t p, const ColCfg& c)
     a.L = c.L;
     a.log2L = ilog2(c.L);
     a.TX = c.TX;
+    a.log2TX = ilog2(c.TX);
+    a.log2S = ilog2(c.S);
     a.lds_col = c.pitch;
     a.S = c.S;
     a.tiles = c.S / c.TX;

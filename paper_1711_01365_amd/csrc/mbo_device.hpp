@@ -131,6 +131,16 @@ __device__ __forceinline__ void twiddle(T& r, T& i, const typename cx<T>::type w
 // writes over all banks).
 __device__ __forceinline__ int lds_pad(int j) { return j + (j >> 3); }
 
+// lds_pad(j0 + m * STEP) = lds_pad(j0) + m * (STEP + STEP / 8) when STEP is a
+// multiple of 8: the offset is a compile-time constant the compiler folds into
+// the LDS instruction, so a thread keeps one address instead of one per element.
+template <int STEP>
+__device__ __forceinline__ int lds_pad_at(int j0, int pad_j0, int m)
+{
+    if constexpr (STEP % 8 == 0) return pad_j0 + m * (STEP + STEP / 8);
+    else return lds_pad(j0 + m * STEP);
+}
+
 // ---------------------------------------------------------------------------
 // Length-L Stockham FFT, L = 2^LOG2L in [8, 2048], fixed at compile time.
 //
@@ -291,21 +301,25 @@ __device__ __forceinline__ void fft_wave(T (&r)[8], T (&im)[8], T* lr, T* li, in
             wave_lds_sync();  // earlier reads of the line are done
             if (act) {
                 if constexpr (STAGE == 0) {
+                    // element (t + b*Tn)*R + q; R divides 8, so q never carries
+                    // into the padding term
                     constexpr int B = 8 / R;
+                    const int j0 = t * R, pj0 = lds_pad(j0);
 #pragma unroll
                     for (int b = 0; b < B; ++b)
 #pragma unroll
                         for (int q = 0; q < R; ++q) {
-                            const int a = lds_pad((t + b * F::Tn) * R + q);
+                            const int a = lds_pad_at<F::Tn * R>(j0, pj0, b) + q;
                             lr[a] = r[b + q * B];
                             li[a] = im[b + q * B];
                         }
                 } else {
                     const int k = t & (p - 1);
                     const int base = ((t - k) << 3) + k;
+                    const int pbase = lds_pad(base);
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
-                        const int a = lds_pad(base + q * p);
+                        const int a = lds_pad_at<p>(base, pbase, q);
                         lr[a] = r[q];
                         li[a] = im[q];
                     }
@@ -313,9 +327,10 @@ __device__ __forceinline__ void fft_wave(T (&r)[8], T (&im)[8], T* lr, T* li, in
             }
             wave_lds_sync();
             if (act) {
+                const int pt = lds_pad(t);
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    const int a = lds_pad(t + e * F::Tn);
+                    const int a = lds_pad_at<F::Tn>(t, pt, e);
                     r[e] = lr[a];
                     im[e] = li[a];
                 }

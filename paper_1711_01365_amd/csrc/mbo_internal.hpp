@@ -71,7 +71,9 @@ enum ColMode : int { CM_FORWARD = 0, CM_INVERSE = 1, CM_HEAT = 2, CM_ENERGY = 3,
 
 struct ColArgs {
     int L, log2L;            // transform length along the axis
-    int TX;                  // inner indices per workgroup
+    int TX;                  // inner indices per workgroup (a power of two)
+    int log2TX;
+    int log2S;               // log2 of S (S is a power of two)
     int lds_col;             // LDS words per line (>= lds_pad(L - 1) + 1)
     int64_t S;               // element stride along the axis (= inner extent)
     int64_t tiles;           // S / TX

@@ -151,8 +151,8 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
         if (act) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                lrj[lds_pad(t + e * Tn)] = r[0][e];
-                lij[lds_pad(t + e * Tn)] = im[0][e];
+                lrj[lds_pad_at<Tn>(t, lds_pad(t), e)] = r[0][e];
+                lij[lds_pad_at<Tn>(t, lds_pad(t), e)] = im[0][e];
             }
         }
     }
@@ -311,8 +311,8 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
             if (act) {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    r[0][e] = lrj[lds_pad(t + e * Tn)];
-                    im[0][e] = lij[lds_pad(t + e * Tn)];
+                    r[0][e] = lrj[lds_pad_at<Tn>(t, lds_pad(t), e)];
+                    im[0][e] = lij[lds_pad_at<Tn>(t, lds_pad(t), e)];
                 }
             }
             if constexpr (LOG2L <= 9) fft_wave<T, -1, LOG2L>(r[0], im[0], lrj, lij, t, tw, act);
@@ -401,16 +401,20 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
         const int pitch = a.lds_col;
         T* lrb = reinterpret_cast<T*>(smem_raw);
         T* lib = lrb + (size_t)TX * pitch;
-        const int nt = blockDim.x;
         const int c = tid >> (LOG2L - 3);
         const int tt = tid & (Tn - 1);
+        const int ptt = lds_pad(tt);
+        // staging: thread tid moves element (row k*Tn + r0, column cc) of the
+        // tile for k = 0..7 (the workgroup has Tn * TX threads)
+        const int r0 = tid >> a.log2TX, cc = tid & (TX - 1);
+        C* const zp = Zt + ((int64_t)r0 << a.log2S) + cc;
+        const int64_t kstride = (int64_t)Tn << a.log2S;
+        const int pr0 = lds_pad(r0);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const int i = k * nt + tid;
-            const int row = i / TX, cc = i - (i / TX) * TX;
-            const C v = Zt[(int64_t)row * S + cc];
-            lrb[cc * pitch + lds_pad(row)] = v.x;
-            lib[cc * pitch + lds_pad(row)] = v.y;
+            const C v = zp[k * kstride];
+            lrb[cc * pitch + lds_pad_at<Tn>(r0, pr0, k)] = v.x;
+            lib[cc * pitch + lds_pad_at<Tn>(r0, pr0, k)] = v.y;
         }
         Twiddles<T, LOG2L> tw;
         load_twiddles<T, LOG2L>(tw, tw_tab, tt);
@@ -420,8 +424,8 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
         T r[8], im[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            r[e] = lr[lds_pad(tt + e * Tn)];
-            im[e] = li[lds_pad(tt + e * Tn)];
+            r[e] = lr[lds_pad_at<Tn>(tt, ptt, e)];
+            im[e] = li[lds_pad_at<Tn>(tt, ptt, e)];
         }
         if (MODE == CM_INVERSE) fft_wave<T, +1, LOG2L>(r, im, lr, li, tt, tw, true);
         else fft_wave<T, -1, LOG2L>(r, im, lr, li, tt, tw, true);
@@ -454,18 +458,16 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
             wave_lds_sync();  // the line's last exchange has been read
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                lr[lds_pad(tt + e * Tn)] = r[e];
-                li[lds_pad(tt + e * Tn)] = im[e];
+                lr[lds_pad_at<Tn>(tt, ptt, e)] = r[e];
+                li[lds_pad_at<Tn>(tt, ptt, e)] = im[e];
             }
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                const int i = k * nt + tid;
-                const int row = i / TX, cc = i - (i / TX) * TX;
                 C v;
-                v.x = lrb[cc * pitch + lds_pad(row)];
-                v.y = lib[cc * pitch + lds_pad(row)];
-                Zt[(int64_t)row * S + cc] = v;
+                v.x = lrb[cc * pitch + lds_pad_at<Tn>(r0, pr0, k)];
+                v.y = lib[cc * pitch + lds_pad_at<Tn>(r0, pr0, k)];
+                zp[k * kstride] = v;
             }
         }
     } else {
