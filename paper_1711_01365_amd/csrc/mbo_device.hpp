@@ -754,6 +754,77 @@ __device__ __forceinline__ T polar_vjp(const T* a, const T* g, T* ga)
     return smin;
 }
 
+// Cofactor matrix of a row-major 3x3 matrix (cof(X) = det(X) X^{-T}).
+__device__ __forceinline__ void cofactor3(const float* x, float* c)
+{
+    c[0] = x[4] * x[8] - x[5] * x[7];
+    c[1] = x[5] * x[6] - x[3] * x[8];
+    c[2] = x[3] * x[7] - x[4] * x[6];
+    c[3] = x[2] * x[7] - x[1] * x[8];
+    c[4] = x[0] * x[8] - x[2] * x[6];
+    c[5] = x[1] * x[6] - x[0] * x[7];
+    c[6] = x[1] * x[5] - x[2] * x[4];
+    c[7] = x[2] * x[3] - x[0] * x[5];
+    c[8] = x[0] * x[4] - x[1] * x[3];
+}
+
+// Closest orthogonal matrix of a float 3x3 matrix by the scaled Newton
+// iteration for the polar decomposition, X <- (zeta X + X^{-T} / zeta) / 2
+// (Higham, 1986), with Frobenius-norm scaling zeta = (|X^{-1}|_F / |X|_F)^{1/2}
+// until the step is below 1e-2 and unscaled steps after it.  Each step maps
+// every singular value s to (zeta s + 1/(zeta s)) / 2 and keeps U, V and the
+// sign of det, so the limit is U V^t; convergence is quadratic, and a step
+// below 3e-4 leaves an error below the float rounding of the result.  Returns
+// false (q unset) when 1/|A^{-1}|_F < thr, i.e. possibly sigma_min < sqrt(3) thr;
+// then sigma_min is decided by the Jacobi route.  Otherwise sigma_min >= thr.
+__device__ __forceinline__ bool polar_newton3(const float* a, float* q, int& dsign, float thr)
+{
+    float X[9], C[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) X[k] = a[k];
+    cofactor3(X, C);
+    float det = X[0] * C[0] + X[1] * C[1] + X[2] * C[2];
+    float cf2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) cf2 += C[k] * C[k];
+    const float adet = det < 0.f ? -det : det;
+    if (!(adet >= thr * num<float>::sqrt_(cf2))) return false;  // also NaN input
+    dsign = det >= 0.f ? 1 : -1;
+    bool scaled = true;
+#pragma unroll 1
+    for (int it = 0; it < 16; ++it) {
+        if (it > 0) {
+            cofactor3(X, C);
+            det = X[0] * C[0] + X[1] * C[1] + X[2] * C[2];
+            cf2 = 0.f;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) cf2 += C[k] * C[k];
+        }
+        float xf2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) xf2 += X[k] * X[k];
+        const float idet = 1.0f / det;
+        // zeta^2 = |C/det|_F / |X|_F
+        const float zeta = scaled ? num<float>::sqrt_(num<float>::sqrt_(cf2) * (idet < 0.f ? -idet : idet) *
+                                                      num<float>::rsq(xf2))
+                                  : 1.0f;
+        const float cx = 0.5f * zeta, cc = 0.5f * idet / zeta;
+        float diff = 0.f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const float xn = cx * X[k] + cc * C[k];
+            const float dv = xn - X[k];
+            diff = fmaxf(diff, dv < 0.f ? -dv : dv);
+            X[k] = xn;
+        }
+        if (diff < 1e-2f) scaled = false;
+        if (diff < 3e-4f) break;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) q[k] = X[k];
+    return true;
+}
+
 // Float Jacobi of a point of a plan with the double fallback: when the smallest
 // singular value is below sigma_fb it stops before forming Q and returns true,
 // leaving in V the right singular vectors that warm-start the double run;
@@ -796,6 +867,10 @@ __device__ __forceinline__ bool project_point_fb(const T* a, T* q, int& dsign, b
                                                  double sigma_fb)
 {
     constexpr int NN = n * n;
+    if constexpr (sizeof(T) == 4 && n == 3) {
+        // well-conditioned points (sigma_min >= sigma_fb): Newton, no fallback
+        if (polar_newton3(a, q, dsign, (float)sigma_fb)) return false;
+    }
     if constexpr (sizeof(T) == 4 && n >= 3) {
         if (fallback) {
             float V[n][n];

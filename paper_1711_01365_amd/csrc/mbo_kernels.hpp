@@ -228,7 +228,10 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
                 int ds;
                 bool queued = false;
                 if constexpr (DEFER) {
-                    if (defer) {
+                    bool newton = false;
+                    if constexpr (n == 3) newton = polar_newton3(av, qv, ds, (float)a.sigma_fb);
+                    if (newton) {
+                    } else if (defer) {
                         float V[n][n];
                         queued = polar_jacobi_f32_fb<n>(av, qv, ds, V, a.sigma_fb);
                         if (queued) {
