@@ -14,6 +14,8 @@
 //              sum_m symbol |Z|^2 (Section 4) -> inverse FFT.
 #pragma once
 
+#include <type_traits>
+
 #include "mbo_device.hpp"
 #include "mbo_internal.hpp"
 
@@ -71,6 +73,55 @@ __device__ V block_reduce(V v, V* sh /* >= 64 entries */)
 // forward-FFT the lines from LDS and store the spectra.  The projection, which
 // dominates the arithmetic, thus runs one point per thread on all threads.
 // ---------------------------------------------------------------------------
+// Copy the workgroup's lines between the spectra and LDS with all threads, 16
+// bytes per access (two float or one double complex values).  Line j (row
+// rloc = j / PL of the workgroup, packed plane pl = j % PL) is
+// Zb[pl * npts + (row0 + rloc) * L + x], x < L, and sits at
+// lr/li[j * lp + lds_pad(x)].  Rows at or beyond `rows` are skipped.
+template <typename T, int PL, int LOG2L, bool TO_LDS>
+__device__ __forceinline__ void stage_lines(typename cx<T>::type* Zb, T* lr, T* li, int lp, int nlines,
+                                            int64_t row0, int64_t rows, int64_t npts, int tid, int NT)
+{
+    constexpr int L = 1 << LOG2L;
+    constexpr int EPV = sizeof(T) == 4 ? 2 : 1;  // complex values per access
+    constexpr int VPL = L / EPV;                 // accesses per line
+    typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type V;
+    const int nvec = nlines * VPL;
+    for (int i = tid; i < nvec; i += NT) {
+        const int j = i / VPL;
+        const int x = (i - j * VPL) * EPV;
+        const int rloc = j / PL, pl = j - (j / PL) * PL;
+        if (row0 + rloc >= rows) continue;
+        V* gp = reinterpret_cast<V*>(Zb + (int64_t)pl * npts + (row0 + rloc) * L + x);
+        T* lrj = lr + j * lp + lds_pad(x);
+        T* lij = li + j * lp + lds_pad(x);
+        if constexpr (TO_LDS) {
+            const V v = *gp;
+            if constexpr (EPV == 2) {
+                lrj[0] = v.x;
+                lij[0] = v.y;
+                lrj[1] = v.z;  // x is even: x + 1 gets no extra padding
+                lij[1] = v.w;
+            } else {
+                lrj[0] = v.x;
+                lij[0] = v.y;
+            }
+        } else {
+            V v;
+            if constexpr (EPV == 2) {
+                v.x = lrj[0];
+                v.y = lij[0];
+                v.z = lrj[1];
+                v.w = lij[1];
+            } else {
+                v.x = lrj[0];
+                v.y = lij[0];
+            }
+            *gp = v;
+        }
+    }
+}
+
 // Waves per SIMD the row pass is compiled for: float rows of up to 512 points
 // and n <= 3 are held to 128 VGPRs, so that two 512-thread workgroups share a
 // compute unit.
@@ -109,7 +160,45 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
     T* li = lr + (size_t)nlines * lp;
 
     // ---- phase 1: lines into LDS (natural order), inverse FFT on the way
-    for (int rd = 0; rd < rounds; ++rd) {
+    C* Zb = reinterpret_cast<C*>(a.Z) + (size_t)b * PL * npts;
+    const bool staged = LOG2L <= 9 && !(flags & RF_LOAD_REAL);
+    if constexpr (LOG2L <= 9) {
+        if (staged) {
+            // spectra staged by all threads, then each line group transforms its
+            // line in place in LDS
+            stage_lines<T, PL, LOG2L, true>(Zb, lr, li, lp, nlines, row0, a.rows, npts, tid, NT);
+            __syncthreads();
+            if (flags & RF_INVERSE) {
+                Twiddles<T, LOG2L> tw;
+                load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
+                const int pt = lds_pad(t);
+                for (int rd = 0; rd < rounds; ++rd) {
+                    const int j = rd * G + g;
+                    const bool act = j < nlines;
+                    T* lrj = lr + (size_t)(act ? j : 0) * lp;
+                    T* lij = li + (size_t)(act ? j : 0) * lp;
+                    T r[8], im[8];
+                    if (act) {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            r[e] = lrj[lds_pad_at<Tn>(t, pt, e)];
+                            im[e] = lij[lds_pad_at<Tn>(t, pt, e)];
+                        }
+                    }
+                    fft_wave<T, +1, LOG2L>(r, im, lrj, lij, t, tw, act);
+                    wave_lds_sync();  // the line's last exchange has been read
+                    if (act) {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            lrj[lds_pad_at<Tn>(t, pt, e)] = r[e];
+                            lij[lds_pad_at<Tn>(t, pt, e)] = im[e];
+                        }
+                    }
+                }
+            }
+        }
+    }
+    for (int rd = 0; rd < (staged ? 0 : rounds); ++rd) {
         const int j = rd * G + g;
         const int rloc = j / PL, pl = j - (j / PL) * PL;
         const bool act = j < nlines;
@@ -307,7 +396,7 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
             const int j = rd * G + g;
             const int rloc = j / PL, pl = j - (j / PL) * PL;
             const bool act = j < nlines;
-            const bool st = act && row0 + rloc < a.rows;
+            const bool st = act && row0 + rloc < a.rows && LOG2L > 9;
             T* lrj = lr + (size_t)(act ? j : 0) * lp;
             T* lij = li + (size_t)(act ? j : 0) * lp;
             T r[1][8], im[1][8];
@@ -318,8 +407,20 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
                     im[0][e] = lij[lds_pad_at<Tn>(t, lds_pad(t), e)];
                 }
             }
-            if constexpr (LOG2L <= 9) fft_wave<T, -1, LOG2L>(r[0], im[0], lrj, lij, t, tw, act);
-            else fft_lines<T, -1, 1, LOG2L>(r, im, lrj, lij, 0, 1, 0, t, tw, act);
+            if constexpr (LOG2L <= 9) {
+                // back to LDS in natural order; all threads store after the loop
+                fft_wave<T, -1, LOG2L>(r[0], im[0], lrj, lij, t, tw, act);
+                wave_lds_sync();
+                if (act) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        lrj[lds_pad_at<Tn>(t, lds_pad(t), e)] = r[0][e];
+                        lij[lds_pad_at<Tn>(t, lds_pad(t), e)] = im[0][e];
+                    }
+                }
+            } else {
+                fft_lines<T, -1, 1, LOG2L>(r, im, lrj, lij, 0, 1, 0, t, tw, act);
+            }
             if (st) {
                 C* Z = reinterpret_cast<C*>(a.Z) + ((size_t)b * PL + pl) * npts;
                 const int64_t x0 = (row0 + rloc) * L + t;
@@ -331,6 +432,10 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
                     Z[x0 + (int64_t)e * Tn] = v;
                 }
             }
+        }
+        if constexpr (LOG2L <= 9) {
+            __syncthreads();
+            stage_lines<T, PL, LOG2L, false>(Zb, lr, li, lp, nlines, row0, a.rows, npts, tid, NT);
         }
     }
 
