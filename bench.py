@@ -7,7 +7,9 @@ tau = 2e-4, 200 iterations, FP32 diffusion and projection with FP64 re-projectio
 of points whose smallest singular value is below 1e-3.  Each step restores the
 initial field (a device copy) and runs the 200 iterations as one captured HIP
 graph, with the Lyapunov energy, det-flip and fallback logs copied back once.
-The same workload in full FP64 is timed beside it.
+The plan's launch shapes are chosen by its autotuner (mbo_plan_autotune) before
+the timed region; the JSON line records them.  The same workload in full FP64
+is timed beside it.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
@@ -19,7 +21,8 @@ from HIP start/stop events recorded by each dispatch in three more steps run
 right after the timed ones (launched directly, since events inside a captured
 graph cannot be timed).  `cpu_baseline` is
 the FP64 CPU oracle on a bounded sample (the first iterations of the same
-workload).  Beside the main line: the 3-D configuration (n = 3, 128^3, 100
+workload).  Beside the main line: a 2048^2 bandwidth control (the same
+kernels on a field 16x larger), the 3-D configuration (n = 3, 128^3, 100
 iterations, FP32 + fallback), the batched configuration (64 fields of mixed n,
 grid and tau, 50 iterations in one graph; FP32 autotuned, FP32 with the fixed
 launch rules, FP64) and the gradient of 50 unrolled steps (n = 3, 256^2, FP32 +
@@ -87,7 +90,7 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 10}))
 
 
-def run_gpu(w, precision, steps, warmup, timing_steps):
+def run_gpu(w, precision, steps, warmup, timing_steps, autotune=True):
     """Timed region: `steps` steps through the captured graph (the product path).
     Then `timing_steps` more steps with per-kernel HIP events (direct launches)."""
     import numpy as np
@@ -98,6 +101,7 @@ def run_gpu(w, precision, steps, warmup, timing_steps):
     A0 = torch.tensor(w.field(), dtype=dt, device="cuda")
     A = A0.clone()
     plan = mbo.Plan(w.grid, w.n, w.tau, precision=precision)
+    tuning = plan.autotune() if autotune else plan.tuning()
     for _ in range(warmup):
         A.copy_(A0)
         plan.iterate(A, w.iters)
@@ -129,8 +133,24 @@ def run_gpu(w, precision, steps, warmup, timing_steps):
         "heat_us": float(np.mean(col_us)) if col_us else None,
         "energy_first_last": [float(logs["energy"][0][0]), float(logs["energy"][0][-1])],
         "fallbacks_total": int(logs["fallbacks"][0].sum()),
+        "launch_shape": {"rows_per_row_workgroup": tuning[0], "lines_per_heat_workgroup": tuning[1],
+                         "xcd_tile_order": tuning[2], "autotuned": bool(autotune)},
         "flips_first": int(logs["flips"][0][0]),
     }
+
+
+def run_control_2048():
+    """n = 3 on 2048^2 (20 iterations, FP32 + fallback): the same kernels on a
+    field 16x larger, where the passes stream from HBM; kernel times from
+    dispatch events and their algorithmic bandwidth."""
+    from paper_1711_01365_amd import inputs, mbo
+    w = inputs.CONTROL_2048
+    r = run_gpu(w, mbo.F32_F64FALLBACK, 3, 1, timing_steps=2)
+    bpl = 2 * w.n * w.n * 4 * w.points
+    return {"workload": "n3_2048x2048_haar_20it_f32_f64fallback", "value": r["value"],
+            "unit": "point-iterations/s", "row_us": r["row_us"], "heat_us": r["heat_us"],
+            "bytes_per_launch": bpl,
+            "row_GBps": bpl / (r["row_us"] * 1e-6) / 1e9, "heat_GBps": bpl / (r["heat_us"] * 1e-6) / 1e9}
 
 
 def run_3d(steps, warmup):
@@ -142,6 +162,7 @@ def run_3d(steps, warmup):
     A0 = torch.tensor(w.field(), dtype=torch.float32, device="cuda")
     A = A0.clone()
     plan = mbo.Plan(w.grid, w.n, w.tau, precision=mbo.F32_F64FALLBACK)
+    plan.autotune()
     for _ in range(warmup):
         A.copy_(A0)
         plan.iterate(A, w.iters)
@@ -310,12 +331,17 @@ def main():
                      "avg_launch_us": dominant_us},
         "kernels_us": {"row_pass": main_run["row_us"], "heat_pass": main_run["heat_us"]},
         "fallback_points_total": main_run["fallbacks_total"],
+        "launch_shape": main_run["launch_shape"],
     }
     if f64 is not None:
         out["f64"] = {"value": f64["value"], "ms_per_step": f64["ms_per_step"],
                       "kernels_us": {"row_pass": f64["row_us"], "heat_pass": f64["heat_us"]},
                       "f32_over_f64": main_run["value"] / f64["value"]}
     if not args.no_extra:
+        out["control_2048"] = run_control_2048()
+        log("2048^2 control: %.3e point-iter/s, row %.1f us (%.0f GB/s), heat %.1f us (%.0f GB/s)"
+            % (out["control_2048"]["value"], out["control_2048"]["row_us"], out["control_2048"]["row_GBps"],
+               out["control_2048"]["heat_us"], out["control_2048"]["heat_GBps"]))
         out["config_3d"] = run_3d(3, 1)
         log("3-D n=3 128^3 fp32+fallback: %.3e point-iter/s" % out["config_3d"]["value"])
         out["batched"] = {"f32_autotuned": run_batched(mbo.F32, True, 3),

@@ -178,6 +178,12 @@ typedef struct mbo_field_desc {
 mbo_status mbo_plan_batched(mbo_plan_t* out, int count, const mbo_field_desc* descs, mbo_precision prec,
                             double sigma_fallback, int autotune, void* hip_stream);
 
+/* Run the autotuner described above on an existing plan (plain or batched):
+ * candidate launch shapes are timed on a pseudo-random field in the plan's own
+ * workspace and the fastest kept.  Synchronises the plan's stream; a captured
+ * iteration graph is rebuilt on the next mbo_iterate. */
+mbo_status mbo_plan_autotune(mbo_plan_t plan);
+
 /* Launch shape used for `field` (0 <= field < count, or < batch for a plain
  * plan): rows per row-pass workgroup, lines per heat-pass workgroup, and
  * whether heat-pass tiles are dealt to the XCDs in contiguous runs (all

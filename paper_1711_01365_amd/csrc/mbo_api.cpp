@@ -310,12 +310,26 @@ mbo_status config_col(mbo_plan_t p, ColCfg& c, int axis)
         // lines inside one wave: a tile of TX lines is staged through LDS with a
         // line pitch of 8 (mod 64) words, so the coalesced staging is free of
         // bank conflicts; up to 512 threads per workgroup
-        c.pitch = lds_len(c.L);
-        c.pitch += ((8 - c.pitch % 64) + 64) % 64;
+        // rule: workgroups of at most 256 threads (a tile per four waves keeps
+        // enough workgroups to balance the CUs); the autotuner may widen it
         const int cap = axis == 0 ? p->tune_tx_heat : p->tune_tx_y;
-        while (TX * 2 <= c.S && T * TX * 2 <= 512 && (cap == 0 || TX * 2 <= cap)) TX *= 2;
+        const int tmax = cap ? 512 : 256;
+        while (TX * 2 <= c.S && T * TX * 2 <= tmax && (cap == 0 || TX * 2 <= cap)) TX *= 2;
+        // LDS is read and written 32 lanes at a time over 32 banks; the staging
+        // of a tile puts lanes (line cc < TX, row r0 < 32/TX) at cc * pitch + r0,
+        // all in distinct banks when pitch = 32/TX (mod 32)
+        auto pitch_for = [&](int tx) {
+            int pt = lds_len(c.L);
+            const int want = tx > 1 ? 32 / tx : 0;
+            if (want) pt += ((want - pt % 32) + 32) % 32;
+            return pt;
+        };
+        c.pitch = pitch_for(TX);
+        while (TX > 1 && (size_t)c.pitch * 2 * p->esz * TX > p->lds_max) {
+            TX /= 2;
+            c.pitch = pitch_for(TX);
+        }
         const size_t per_line = (size_t)c.pitch * 2 * p->esz;
-        while (TX > 1 && per_line * TX > p->lds_max) TX /= 2;
         if (per_line * TX > p->lds_max)
             return fail(p, MBO_ERR_UNSUPPORTED, "axis of length %d needs more LDS than available", c.L);
         c.lds = per_line * TX;
@@ -787,9 +801,13 @@ mbo_status autotune_plan(mbo_plan_t p)
     for (int axis = 0; axis < (p->d == 3 ? 2 : 1); ++axis) {
         ColCfg& c = axis == 0 ? p->heat : p->ypass;
         int& cap = axis == 0 ? p->tune_tx_heat : p->tune_tx_y;
+        const int tx_rule = c.TX;
+        cap = 1 << 20;  // widest tile the LDS and 512 threads allow
+        if ((s = config_col(p, c, axis)) != MBO_OK) return done(s);
         const int tx_max = c.TX;
-        int best_tx = tx_max;
-        for (int tx = 1; tx < tx_max; tx *= 2) {
+        int best_tx = tx_rule;
+        for (int tx = 1; tx <= tx_max; tx *= 2) {
+            if (tx == tx_rule) continue;  // timed above
             cap = tx;
             if ((s = config_col(p, c, axis)) != MBO_OK) return done(s);
             if ((s = time_iterations(p, A, reps, e0, e1, &t)) != MBO_OK) return done(s);
@@ -999,6 +1017,22 @@ mbo_status mbo_plan_batched(mbo_plan_t* out, int count, const mbo_field_desc* de
     }
     *out = g;
     return MBO_OK;
+}
+
+mbo_status mbo_plan_autotune(mbo_plan_t p)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    HIP_TRY(p, hipSetDevice(p->device));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    if (p->group) {
+        for (mbo_plan_t m : p->members) {
+            const mbo_status s = autotune_plan(m);
+            if (s != MBO_OK) return fail(p, s, "%s", m->err.c_str());
+        }
+        drop_graph(p);
+        return MBO_OK;
+    }
+    return autotune_plan(p);
 }
 
 mbo_status mbo_plan_tuning(mbo_plan_t p, int field, int* rows_per_group, int* heat_lines_per_group,

@@ -270,9 +270,9 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
             __syncthreads();
         }
         // diagnostics and write-back of a projected point
-        auto finish = [&](int64_t x, T* lrr, T* lir, const T (&qv)[NN], int ds) {
+        auto finish = [&](int64_t x, T* lrr, T* lir, const T (&qv)[NN], int ds, int8_t s_old) {
             if (flags & RF_SIGN) {
-                nflip += (sgn[x] != (int8_t)ds) ? 1ull : 0ull;
+                nflip += (s_old != (int8_t)ds) ? 1ull : 0ull;
                 sgn[x] = (int8_t)ds;
             }
             if (flags & RF_TRACK) {
@@ -302,6 +302,8 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
             const int jx = lds_pad(xc);
             T* lrr = lr + (size_t)rloc * PL * lp + jx;
             T* lir = li + (size_t)rloc * PL * lp + jx;
+            // previous det sign, loaded before the projection hides its latency
+            const int8_t s_old = (flags & RF_SIGN) ? sgn[x] : (int8_t)0;
             T av[NN];
 #pragma unroll
             for (int k = 0; k < NN; ++k) av[k] = (k & 1) ? lir[(k >> 1) * lp] : lrr[(k >> 1) * lp];
@@ -340,7 +342,7 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
                         ++nfb;
                 }
                 if (queued) continue;
-                finish(x, lrr, lir, qv, ds);
+                finish(x, lrr, lir, qv, ds, s_old);
 #pragma unroll
                 for (int k = 0; k < NN; ++k) av[k] = qv[k];
             }
@@ -375,7 +377,7 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
 #pragma unroll
                     for (int k = 0; k < NN; ++k) qv[k] = (T)qd[k];
                     ++nfb;
-                    finish(x, lrr, lir, qv, ds);
+                    finish(x, lrr, lir, qv, ds, (flags & RF_SIGN) ? sgn[x] : (int8_t)0);
                     if (flags & RF_STORE_REAL) {
 #pragma unroll
                         for (int k = 0; k < NN; ++k) Aout[(int64_t)k * npts + x] = qv[k];
@@ -529,6 +531,18 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
         __syncthreads();
         T* lr = lrb + (size_t)c * pitch;
         T* li = lib + (size_t)c * pitch;
+        // symbol values of this thread's 8 modes, loaded before the transform
+        T lam[8];
+        if (MODE == CM_HEAT || MODE == CM_ENERGY || MODE == CM_DTAU) {
+            const T* lrow = reinterpret_cast<const T*>(a.lam_row) + b * a.lam_row_stride;
+            const T lin = reinterpret_cast<const T*>(a.lam_inner)[b * a.lam_inner_stride + tile0 + c];
+            const T muin = MODE == CM_DTAU ? reinterpret_cast<const T*>(a.mu_inner)[tile0 + c] : (T)0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                lam[e] = lrow[tt + e * Tn] * lin;
+                if (MODE == CM_DTAU) lam[e] *= reinterpret_cast<const T*>(a.mu_row)[tt + e * Tn] + muin;
+            }
+        }
         T r[8], im[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -538,19 +552,17 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
         if (MODE == CM_INVERSE) fft_wave<T, +1, LOG2L>(r, im, lr, li, tt, tw, true);
         else fft_wave<T, -1, LOG2L>(r, im, lr, li, tt, tw, true);
         if (MODE == CM_HEAT || MODE == CM_ENERGY || MODE == CM_DTAU) {
-            const T* lrow = reinterpret_cast<const T*>(a.lam_row) + b * a.lam_row_stride;
-            const T lin = reinterpret_cast<const T*>(a.lam_inner)[b * a.lam_inner_stride + tile0 + c];
-            const T muin = MODE == CM_DTAU ? reinterpret_cast<const T*>(a.mu_inner)[tile0 + c] : (T)0;
             double acc = 0.0;
+            if (a.epart) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                T lam = lrow[tt + e * Tn] * lin;
-                if (MODE == CM_DTAU) lam *= reinterpret_cast<const T*>(a.mu_row)[tt + e * Tn] + muin;
-                if (a.epart)
-                    acc += (double)lam * ((double)r[e] * (double)r[e] + (double)im[e] * (double)im[e]);
-                if (MODE == CM_HEAT || MODE == CM_DTAU) {
-                    r[e] *= lam;
-                    im[e] *= lam;
+                for (int e = 0; e < 8; ++e)
+                    acc += (double)lam[e] * ((double)r[e] * (double)r[e] + (double)im[e] * (double)im[e]);
+            }
+            if (MODE == CM_HEAT || MODE == CM_DTAU) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    r[e] *= lam[e];
+                    im[e] *= lam[e];
                 }
             }
             if (a.epart) {
@@ -585,6 +597,17 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
         C* Z = Zt + tx;
         T* lr = reinterpret_cast<T*>(smem_raw);
         T* li = lr + (size_t)a.lds_col * TX;
+        T lam[8];
+        if (MODE == CM_HEAT || MODE == CM_ENERGY || MODE == CM_DTAU) {
+            const T* lrow = reinterpret_cast<const T*>(a.lam_row) + b * a.lam_row_stride;
+            const T lin = reinterpret_cast<const T*>(a.lam_inner)[b * a.lam_inner_stride + tile0 + tx];
+            const T muin = MODE == CM_DTAU ? reinterpret_cast<const T*>(a.mu_inner)[tile0 + tx] : (T)0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                lam[e] = lrow[t + e * Tn] * lin;
+                if (MODE == CM_DTAU) lam[e] *= reinterpret_cast<const T*>(a.mu_row)[t + e * Tn] + muin;
+            }
+        }
         T r[1][8], im[1][8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -599,20 +622,18 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
         else
             fft_lines<T, -1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
         if (MODE == CM_HEAT || MODE == CM_ENERGY || MODE == CM_DTAU) {
-            const T* lrow = reinterpret_cast<const T*>(a.lam_row) + b * a.lam_row_stride;
-            const T lin = reinterpret_cast<const T*>(a.lam_inner)[b * a.lam_inner_stride + tile0 + tx];
-            const T muin = MODE == CM_DTAU ? reinterpret_cast<const T*>(a.mu_inner)[tile0 + tx] : (T)0;
             double acc = 0.0;
+            if (a.epart) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                T lam = lrow[t + e * Tn] * lin;
-                if (MODE == CM_DTAU) lam *= reinterpret_cast<const T*>(a.mu_row)[t + e * Tn] + muin;
-                if (a.epart)
-                    acc += (double)lam * ((double)r[0][e] * (double)r[0][e] +
-                                          (double)im[0][e] * (double)im[0][e]);
-                if (MODE == CM_HEAT || MODE == CM_DTAU) {
-                    r[0][e] *= lam;
-                    im[0][e] *= lam;
+                for (int e = 0; e < 8; ++e)
+                    acc += (double)lam[e] * ((double)r[0][e] * (double)r[0][e] +
+                                             (double)im[0][e] * (double)im[0][e]);
+            }
+            if (MODE == CM_HEAT || MODE == CM_DTAU) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    r[0][e] *= lam[e];
+                    im[0][e] *= lam[e];
                 }
             }
             if (a.epart) {

@@ -69,6 +69,9 @@ class Workload:
 PARITY_64 = Workload("n2_64x64_f64", 2, (64, 64), 1e-3, 20, "uniform", 0)
 HAAR_512 = Workload("n3_512x512_haar", 3, (512, 512), 2e-4, 200, "haar", 1)
 NORMAL_128_3D = Workload("n3_128x128x128_normal", 3, (128, 128, 128), 5e-4, 100, "normal", 2)
+# bandwidth control: the measured configuration's per-point work on a grid 16x
+# larger (tau scaled with the grid spacing squared, so tau / h^2 is unchanged)
+CONTROL_2048 = Workload("n3_2048x2048_haar", 3, (2048, 2048), 2e-4 / 16, 20, "haar", 11)
 ADJOINT_256 = Workload("n3_256x256_adjoint", 3, (256, 256), 1e-3, 50, "haar", 4001)
 ADJOINT_TARGET_SEED = 4002
 ADJOINT_TARGET_TAU = 1e-2

@@ -28,6 +28,7 @@ _lib = None
 EXPORTS = ("mbo_plan", "mbo_plan_destroy", "mbo_plan_set_tau", "mbo_plan_set_stream",
            "mbo_plan_set_timing", "mbo_last_timing", "mbo_diffuse", "mbo_project", "mbo_iterate",
            "mbo_energy", "mbo_project_vjp", "mbo_diffuse_dtau", "mbo_plan_batched", "mbo_plan_tuning",
+           "mbo_plan_autotune",
            "mbo_status_string", "mbo_last_error")
 
 
@@ -69,6 +70,7 @@ def load(path: str = LIB_PATH):
     lib.mbo_plan_batched.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(FieldDesc),
                                      ctypes.c_int, ctypes.c_double, ctypes.c_int, vp]
     lib.mbo_plan_tuning.argtypes = [vp, ctypes.c_int, ip, ip, ip]
+    lib.mbo_plan_autotune.argtypes = [vp]
     for f in EXPORTS:
         if f not in ("mbo_status_string", "mbo_last_error"):
             getattr(lib, f).restype = ctypes.c_int
@@ -223,6 +225,11 @@ class Plan:
         if logs:
             out.update(energy=en, flips=fl[:, :K], delta=dl[:, :K], fallbacks=fb[:, :K])
         return out
+
+    def autotune(self):
+        """Time candidate launch shapes on the device and keep the fastest."""
+        _check(self._lib.mbo_plan_autotune(self._h), self._h)
+        return self.tuning(0)
 
     def tuning(self, field: int = 0):
         """(rows per row-pass workgroup, lines per heat-pass workgroup, XCD tile order)."""
