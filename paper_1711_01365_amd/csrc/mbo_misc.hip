@@ -127,18 +127,21 @@ __global__ void fill_i32(int* p, int64_t count, int v)
 
 // E(A_s) = (1/tau) (n - (1/npts) sum_wg partial), the partials being
 // sum_m symbol(m)/npts |Z(m)|^2 over each workgroup's modes.
-__global__ void reduce_energy(const ReduceArgs a)
+// One workgroup per (field, iterate) slot; the partials are summed in a fixed
+// order (strided per thread, then the fixed tree of block_reduce).
+__global__ void __launch_bounds__(256) reduce_energy(const ReduceArgs a)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)a.batch * (a.K + 1);
-    if (idx >= total) return;
+    __shared__ double red_d[64];
+    const int64_t idx = blockIdx.x;
     const int b = (int)(idx / (a.K + 1));
     const int s = (int)(idx - (int64_t)b * (a.K + 1));
-    if (a.stop_iter && s > a.stop_iter[b]) return;
+    if (a.stop_iter && s > a.stop_iter[b]) return;  // uniform per workgroup
     const double* p = a.epart + idx * a.nwg;
     double sum = 0.0;
-    for (int i = 0; i < a.nwg; ++i) sum += p[i];
-    a.energy[idx] = ((double)a.n - sum / (double)a.npts) / (a.taus ? a.taus[b] : a.tau);
+    for (int i = threadIdx.x; i < a.nwg; i += blockDim.x) sum += p[i];
+    sum = block_reduce<OpSum>(sum, red_d);
+    if (threadIdx.x == 0)
+        a.energy[idx] = ((double)a.n - sum / (double)a.npts) / (a.taus ? a.taus[b] : a.tau);
 }
 
 // ---------------------------------------------------------------------------
@@ -230,7 +233,7 @@ hipError_t launch_fill_uniform(int prec, void* p, int64_t count, uint64_t seed, 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st)
 {
     const int64_t total = (int64_t)a.batch * (a.K + 1);
-    hipLaunchKernelGGL(reduce_energy, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, st, a);
+    hipLaunchKernelGGL(reduce_energy, dim3((unsigned)total), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
