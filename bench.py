@@ -51,13 +51,17 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+# sources that decide the row pass's code and launch shape (its traffic)
+ROW_PASS_SOURCES = ("mbo_device.hpp", "mbo_kernels.hpp", "mbo_internal.hpp", "mbo_row_f32.hip",
+                    "mbo_api.cpp")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1711_01365_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp", ".cpp")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+    for f in ROW_PASS_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 
