@@ -85,6 +85,7 @@ struct mbo_plan_s {
     int row_rpw = 1;
     ColCfg heat, ypass;
     int tune_rpw = 0, tune_tx_heat = 0, tune_tx_y = 0;
+    int tune_row_groups = 0;  // row workgroup sized by line groups instead of points
     int xcd_remap = 1;
     bool tuned = false;
 
@@ -370,7 +371,19 @@ mbo_status config_row(mbo_plan_t p)
                     p->PL, per_row, budget);
     if (rpw * L > row_fb_queue_len(ilog2(L)))
         return fail(p, MBO_ERR_UNSUPPORTED, "row workgroup of %d points exceeds its queue", rpw * L);
-    const int nt = rpw * L < 512 ? rpw * L : 512;
+    // threads: one per point up to 512 (rule), or one L/8-thread group per line
+    // of the workgroup (the transform phases then keep every wave busy and the
+    // projection takes several passes)
+    int nt = rpw * L < 512 ? rpw * L : 512;
+    if (p->tune_row_groups) {
+        const int per_line = L / 8 < 64 ? 64 : L / 8;
+        const int lines = rpw * p->PL;
+        int g = lines * (L / 8);
+        g = (g + 63) / 64 * 64;
+        if (g < per_line) g = per_line;
+        nt = g < 512 ? g : 512;
+    }
+    nt = (nt + 63) / 64 * 64;  // whole waves (the kernel's reductions assume them)
     p->row_rpw = rpw;
     p->row_block = dim3((unsigned)nt);
     p->row_grid = dim3((unsigned)((rows + rpw - 1) / rpw), (unsigned)p->batch);
@@ -420,7 +433,9 @@ ColArgs col_args(mbo_plan_t p, const ColCfg& c)
     a.lam_row_stride = p->per_field_tau ? p->N[0] : 0;
     a.lam_inner_stride = p->per_field_tau ? p->npts / p->N[0] : 0;
     a.xcd_remap = p->xcd_remap;
-    a.nwg = (int)(c.outer * (c.S / c.TX));
+    // energy partials per field and iterate: one per whole wave (one per
+    // workgroup when the workgroup is not a whole number of waves)
+    a.nwg = (int)(c.outer * (c.S / c.TX)) * ((c.block.x % 64) ? 1 : (int)(c.block.x / 64));
     a.slot = 0;
     return a;
 }
@@ -455,6 +470,13 @@ void prepare_plan_kernels(mbo_plan_t p)
     (void)hipGetLastError();
 }
 
+// Energy partials per field and iterate: one per wave of the heat pass.
+int energy_partials(mbo_plan_t p)
+{
+    const unsigned bx = p->heat.block.x;
+    return (int)(p->heat.grid.x * ((bx % 64) ? 1 : bx / 64));  // = col_args(p, p->heat).nwg
+}
+
 // Free the device logs; the next ensure_logs reallocates them (their energy
 // partials are sized by the heat pass's workgroup count).
 void drop_logs(mbo_plan_t p)
@@ -475,7 +497,7 @@ mbo_status ensure_logs(mbo_plan_t p, int K)
     if (K <= p->log_K) return MBO_OK;
     drop_logs(p);
     const size_t slots = (size_t)p->batch * (size_t)(K + 1);
-    const int nwg = (int)p->heat.grid.x;
+    const int nwg = energy_partials(p);
     HIP_TRY(p, hipMalloc((void**)&p->epart, slots * (size_t)nwg * sizeof(double)));
     HIP_TRY(p, hipMalloc((void**)&p->energy, slots * sizeof(double)));
     const size_t cslots = (size_t)p->batch * (size_t)(K > 0 ? K : 1);
@@ -584,7 +606,7 @@ hipError_t enqueue_iterate(mbo_plan_t p, void* A, int K, double tol, bool want_e
         if ((e = run_col(p, p->heat, CM_ENERGY, h, st)) != hipSuccess) return e;
         ReduceArgs ra;
         ra.epart = p->epart;
-        ra.nwg = (int)p->heat.grid.x;
+        ra.nwg = energy_partials(p);
         ra.K = K;
         ra.batch = (int)p->batch;
         ra.n = p->n;
@@ -825,21 +847,25 @@ mbo_status autotune_plan(mbo_plan_t p)
             else p->xcd_remap = 1;
         }
     }
-    // rows per row-pass workgroup
+    // rows per row-pass workgroup, threads per point or per line group
     const int L = (int)p->N[p->d - 1];
     const int rpw0 = p->row_rpw;
-    int best_rpw = rpw0;
-    for (int rpw = 1; rpw * L <= 2048 && rpw <= p->npts / L; rpw *= 2) {
-        if (rpw == rpw0) continue;
-        p->tune_rpw = rpw;
-        if (config_row(p) != MBO_OK) break;  // beyond the LDS or queue limits
-        if ((s = time_iterations(p, A, reps, e0, e1, &t)) != MBO_OK) return done(s);
-        if (t < best) {
-            best = t;
-            best_rpw = rpw;
+    int best_rpw = rpw0, best_groups = 0;
+    for (int groups = 0; groups < 2; ++groups)
+        for (int rpw = 1; rpw * L <= 2048 && rpw <= p->npts / L; rpw *= 2) {
+            if (rpw == rpw0 && groups == 0) continue;  // timed above
+            p->tune_rpw = rpw;
+            p->tune_row_groups = groups;
+            if (config_row(p) != MBO_OK) break;  // beyond the LDS or queue limits
+            if ((s = time_iterations(p, A, reps, e0, e1, &t)) != MBO_OK) return done(s);
+            if (t < best) {
+                best = t;
+                best_rpw = rpw;
+                best_groups = groups;
+            }
         }
-    }
     p->tune_rpw = best_rpw;
+    p->tune_row_groups = best_groups;
     p->err.clear();
     if ((s = config_row(p)) != MBO_OK) return done(s);
     p->tuned = true;
@@ -860,7 +886,7 @@ mbo_status energy_into(mbo_plan_t p, const void* A, double* E, const std::vector
     HIP_TRY(p, run_col(p, p->heat, CM_ENERGY, h, p->stream));
     ReduceArgs ra;
     ra.epart = p->epart;
-    ra.nwg = (int)p->heat.grid.x;
+    ra.nwg = energy_partials(p);
     ra.K = 0;
     ra.batch = (int)p->batch;
     ra.n = p->n;
@@ -1035,13 +1061,14 @@ mbo_status mbo_plan_autotune(mbo_plan_t p)
     return autotune_plan(p);
 }
 
-mbo_status mbo_plan_tuning(mbo_plan_t p, int field, int* rows_per_group, int* heat_lines_per_group,
-                           int* xcd_order)
+mbo_status mbo_plan_tuning(mbo_plan_t p, int field, int* rows_per_group, int* row_threads,
+                           int* heat_lines_per_group, int* xcd_order)
 {
     if (!p) return MBO_ERR_INVALID_ARG;
     if (field < 0 || field >= (int)p->batch) return fail(p, MBO_ERR_INVALID_ARG, "field out of range");
     mbo_plan_t m = p->group ? p->members[(size_t)p->f_member[(size_t)field]] : p;
     if (rows_per_group) *rows_per_group = m->row_rpw;
+    if (row_threads) *row_threads = (int)m->row_block.x;
     if (heat_lines_per_group) *heat_lines_per_group = m->heat.TX;
     if (xcd_order) *xcd_order = m->xcd_remap;
     return MBO_OK;

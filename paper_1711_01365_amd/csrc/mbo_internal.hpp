@@ -88,7 +88,7 @@ struct ColArgs {
     const void* mu_row;      // CM_DTAU: -4 pi^2 k^2 of this axis [L]
     const void* mu_inner;    // CM_DTAU: -4 pi^2 |k|^2 summed over the faster axes [S]
     double* epart;           // energy partials [batch][K+1][nwg]
-    int nwg;                 // workgroups per field (partial slots)
+    int nwg;                 // energy partials per field and iterate
     int slot;                // energy slot (iteration - 1); -1: use stop_iter
     int iter;                // 1-based iteration (CM_HEAT inside mbo_iterate), 0 otherwise
     int K;

@@ -62,6 +62,15 @@ __device__ V block_reduce(V v, V* sh /* >= 64 entries */)
     return sh[0];
 }
 
+// Sum over the 64 lanes of a wave (butterfly order, the same on every lane).
+template <typename V>
+__device__ __forceinline__ V wave_sum(V v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += (V)__shfl_xor(v, o, 64);
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // Row pass.  A workgroup owns rpw rows (contiguous grid lines of length L) of
 // every packed plane: rpw * PL "lines".  Phase 1: groups of L/8 threads load
@@ -159,6 +168,24 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
     T* lr = reinterpret_cast<T*>(smem_raw);
     T* li = lr + (size_t)nlines * lp;
 
+    // fallback queue of phase 2 (see there); its counter is cleared before the
+    // first workgroup barrier
+    constexpr bool DEFER = sizeof(T) == 4 && n >= 3;
+    constexpr int QCAP = DEFER ? row_fb_queue_len(LOG2L) : 1;
+    constexpr int SCAP = DEFER ? ROW_FB_STASH : 1;
+    __shared__ unsigned short fq[QCAP];
+    __shared__ float fv[SCAP * NN];
+    __shared__ int fq_n;
+    // per-workgroup counters (packed counts, max change bits, waves done)
+    __shared__ unsigned long long wg_cnt[3];
+    if (tid == 0) {
+        if (DEFER) fq_n = 0;
+        wg_cnt[0] = 0;
+        wg_cnt[1] = 0;
+        wg_cnt[2] = 0;
+    }
+    bool lds_synced = false;  // no LDS write since the last workgroup barrier
+
     // ---- phase 1: lines into LDS (natural order), inverse FFT on the way
     C* Zb = reinterpret_cast<C*>(a.Z) + (size_t)b * PL * npts;
     const bool staged = LOG2L <= 9 && !(flags & RF_LOAD_REAL);
@@ -253,22 +280,12 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
     // start) and re-project them in double after the pass loop, when the float
     // state is dead: the double code then neither adds to the registers of the
     // loop nor runs once per wave that holds such a point.
-    constexpr bool DEFER = sizeof(T) == 4 && n >= 3;
-    constexpr int QCAP = DEFER ? row_fb_queue_len(LOG2L) : 1;
-    constexpr int SCAP = DEFER ? ROW_FB_STASH : 1;
-    __shared__ unsigned short fq[QCAP];
-    __shared__ float fv[SCAP * NN];
-    __shared__ int fq_n;
     unsigned long long nflip = 0, nfb = 0, nbad = 0;
     double dmax = 0.0, dacc = 0.0;
     if (flags & (RF_PROJECT | RF_SIGN_INIT | RF_STORE_REAL | RF_DOT)) {
         T* Aout = reinterpret_cast<T*>(a.Aout) + field_base(a.foff, b, NN * npts);
         int8_t* sgn = a.sgn + (size_t)b * npts;
         const bool defer = DEFER && (flags & RF_PROJECT) && (flags & RF_FALLBACK);
-        if (defer) {
-            if (tid == 0) fq_n = 0;
-            __syncthreads();
-        }
         // diagnostics and write-back of a projected point
         auto finish = [&](int64_t x, T* lrr, T* lir, const T (&qv)[NN], int ds, int8_t s_old) {
             if (flags & RF_SIGN) {
@@ -290,10 +307,11 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
             }
             if (NN & 1) lir[(NN >> 1) * lp] = (T)0;
         };
-        const int npass = (rpw * L) / NT;
+        const int npass = (rpw * L + NT - 1) / NT;
 #pragma unroll 1
         for (int pp = 0; pp < npass; ++pp) {
             const int idx = pp * NT + tid;
+            if (idx >= rpw * L) continue;  // last pass when NT does not divide the points
             const int rloc = idx >> LOG2L;
             const int xc = idx & (L - 1);
             const int64_t row = row0 + rloc;
@@ -355,6 +373,7 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
             if (defer) {
                 __syncthreads();
                 const int nq = fq_n;
+                lds_synced = nq == 0;  // uniform: read after the barrier
 #pragma unroll 1
                 for (int qi = tid; qi < nq; qi += NT) {
                     const int idx = fq[qi];
@@ -393,7 +412,7 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
         // the projection
         Twiddles<T, LOG2L> tw;
         load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
-        __syncthreads();
+        if (!lds_synced) __syncthreads();
         for (int rd = 0; rd < rounds; ++rd) {
             const int j = rd * G + g;
             const int rloc = j / PL, pl = j - (j / PL) * PL;
@@ -446,18 +465,42 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
         if (tid == 0) a.dpart[(int64_t)b * gridDim.x + blockIdx.x] = dacc;
     }
     if (flags & RF_PROJECT) {
-        const int64_t slot = (int64_t)b * a.K + (a.iter - 1);
-        nflip = block_reduce<OpSum>(nflip, red_u);
-        if (tid == 0 && nflip && a.flips) atomicAdd(a.flips + slot, nflip);
-        nfb = block_reduce<OpSum>(nfb, red_u);
-        if (tid == 0 && nfb && a.fallbacks) atomicAdd(a.fallbacks + slot, nfb);
-        nbad = block_reduce<OpSum>(nbad, red_u);
-        if (tid == 0 && nbad && a.nonfinite) atomicAdd(a.nonfinite + slot, nbad);
+        // The three counts of a workgroup are below 2^21 each and travel packed;
+        // each wave adds its sums to the workgroup's LDS counters, and the last
+        // wave to finish (the release/acquire on the done counter orders every
+        // other wave's additions before it) adds the totals to the logs.  No
+        // workgroup barrier: waves leave as soon as they are done.
+        unsigned long long packed = wave_sum(nflip | (nfb << 21) | (nbad << 42));
+        unsigned long long dbits = 0;
         if (flags & RF_TRACK) {
-            dmax = block_reduce<OpMax>(dmax, red_d);
             // non-negative doubles order like their bit patterns
-            if (tid == 0 && a.delta_bits)
-                atomicMax(a.delta_bits + slot, (unsigned long long)__double_as_longlong(dmax));
+            dbits = (unsigned long long)__double_as_longlong(dmax);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const unsigned long long ob = (unsigned long long)__shfl_xor((long long)dbits, o, 64);
+                dbits = ob > dbits ? ob : dbits;
+            }
+        }
+        if ((tid & 63) == 0) {
+            if (packed) __hip_atomic_fetch_add(&wg_cnt[0], packed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (dbits) __hip_atomic_fetch_max(&wg_cnt[1], dbits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const unsigned long long done =
+                __hip_atomic_fetch_add(&wg_cnt[2], 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (done == (unsigned long long)(NT >> 6) - 1) {
+                const int64_t slot = (int64_t)b * a.K + (a.iter - 1);
+                const unsigned long long tot =
+                    __hip_atomic_load(&wg_cnt[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const unsigned long long m21 = (1ull << 21) - 1;
+                const unsigned long long f = tot & m21, fb = (tot >> 21) & m21, bad = tot >> 42;
+                if (f && a.flips) atomicAdd(a.flips + slot, f);
+                if (fb && a.fallbacks) atomicAdd(a.fallbacks + slot, fb);
+                if (bad && a.nonfinite) atomicAdd(a.nonfinite + slot, bad);
+                if ((flags & RF_TRACK) && a.delta_bits) {
+                    const unsigned long long mx =
+                        __hip_atomic_load(&wg_cnt[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    atomicMax(a.delta_bits + slot, mx);
+                }
+            }
         }
     }
 }
@@ -566,10 +609,15 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
                 }
             }
             if (a.epart) {
-                acc = block_reduce<OpSum>(acc, red_d);
-                if (tid == 0) {
-                    const int slot = a.slot >= 0 ? a.slot : a.stop_iter[b];
-                    a.epart[((int64_t)b * (a.K + 1) + slot) * a.nwg + wg] = acc;
+                const int slot = a.slot >= 0 ? a.slot : a.stop_iter[b];
+                double* ep = a.epart + ((int64_t)b * (a.K + 1) + slot) * a.nwg;
+                if ((blockDim.x & 63) == 0) {
+                    // whole waves: one partial per wave (fixed order, no barrier)
+                    acc = wave_sum(acc);
+                    if ((tid & 63) == 0) ep[wg * (blockDim.x >> 6) + (tid >> 6)] = acc;
+                } else {
+                    acc = block_reduce<OpSum>(acc, red_d);
+                    if (tid == 0) ep[wg] = acc;
                 }
             }
         }
@@ -637,10 +685,15 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
                 }
             }
             if (a.epart) {
+                // the workgroup's sum in its first partial, zeros in the others
+                // (one partial per whole wave, as in the short-line path)
                 acc = block_reduce<OpSum>(acc, red_d);
-                if (tid == 0) {
-                    const int slot = a.slot >= 0 ? a.slot : a.stop_iter[b];
-                    a.epart[((int64_t)b * (a.K + 1) + slot) * a.nwg + wg] = acc;
+                const int slot = a.slot >= 0 ? a.slot : a.stop_iter[b];
+                double* ep = a.epart + ((int64_t)b * (a.K + 1) + slot) * a.nwg;
+                if ((blockDim.x & 63) == 0) {
+                    if ((tid & 63) == 0) ep[wg * (blockDim.x >> 6) + (tid >> 6)] = tid == 0 ? acc : 0.0;
+                } else if (tid == 0) {
+                    ep[wg] = acc;
                 }
             }
         }

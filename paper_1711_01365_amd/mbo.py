@@ -69,7 +69,7 @@ def load(path: str = LIB_PATH):
     lib.mbo_diffuse_dtau.argtypes = [vp, vp, vp, vp, dp]
     lib.mbo_plan_batched.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(FieldDesc),
                                      ctypes.c_int, ctypes.c_double, ctypes.c_int, vp]
-    lib.mbo_plan_tuning.argtypes = [vp, ctypes.c_int, ip, ip, ip]
+    lib.mbo_plan_tuning.argtypes = [vp, ctypes.c_int, ip, ip, ip, ip]
     lib.mbo_plan_autotune.argtypes = [vp]
     for f in EXPORTS:
         if f not in ("mbo_status_string", "mbo_last_error"):
@@ -232,11 +232,12 @@ class Plan:
         return self.tuning(0)
 
     def tuning(self, field: int = 0):
-        """(rows per row-pass workgroup, lines per heat-pass workgroup, XCD tile order)."""
-        r, t, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(self._lib.mbo_plan_tuning(self._h, int(field), ctypes.byref(r), ctypes.byref(t),
-                                         ctypes.byref(x)), self._h)
-        return r.value, t.value, x.value
+        """(rows per row-pass workgroup, its threads, lines per heat-pass workgroup,
+        XCD tile order)."""
+        r, n, t, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.mbo_plan_tuning(self._h, int(field), ctypes.byref(r), ctypes.byref(n),
+                                         ctypes.byref(t), ctypes.byref(x)), self._h)
+        return r.value, n.value, t.value, x.value
 
     def close(self):
         if getattr(self, "_h", None):

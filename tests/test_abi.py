@@ -122,7 +122,7 @@ def test_batched_desc_layout():
 
 
 def test_null_plan_is_rejected_by_new_calls(lib):
-    assert lib.mbo_plan_tuning(None, 0, None, None, None) == 1
+    assert lib.mbo_plan_tuning(None, 0, None, None, None, None) == 1
     assert lib.mbo_plan_autotune(None) == 1
     assert lib.mbo_project_vjp(None, None, None, None) == 1
     assert lib.mbo_diffuse_dtau(None, None, None, None, None) == 1

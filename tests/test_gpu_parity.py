@@ -205,7 +205,8 @@ def test_diffuse_in_place_and_batched(torch_cuda):
 # Energy
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("grid,n", [((64, 64), 2), ((32, 128), 3), ((16, 8, 32), 3), ((64, 64), 1)])
+@pytest.mark.parametrize("grid,n", [((64, 64), 2), ((32, 128), 3), ((16, 8, 32), 3), ((64, 64), 1),
+                                    ((8, 8), 2), ((8, 16), 3), ((8, 8, 8), 2)])
 def test_energy_f64(torch_cuda, grid, n):
     torch = torch_cuda
     tau = 1e-3
@@ -450,3 +451,25 @@ def test_3d_configuration_properties(torch_cuda):
     err = np.abs(point_major(A100 - ro["A"])).max(axis=(1, 2))
     note("  last step: diffusion err %.3g, step err max %.3g" % (e_heat, err.max()))
     assert fp32_step_ok(err, gap, e_heat)
+
+
+@pytest.mark.parametrize("grid,n,prec", [((64, 64), 3, F64), ((8, 32), 2, F64), ((16, 8, 16), 3, FB),
+                                         ((128, 64), 4, FB)])
+def test_autotune_keeps_results(torch_cuda, grid, n, prec):
+    """Launch shapes chosen by mbo_plan_autotune change no iterate (bit for bit)
+    and only the summation order of the energy."""
+    torch = torch_cuda
+    dt = torch.float64 if prec == F64 else torch.float32
+    A = inputs.uniform_field(n, grid, 21)
+    P0 = plan(grid, n, 2e-3, prec)
+    P1 = plan(grid, n, 2e-3, prec)
+    shape = P1.autotune()
+    note("autotune %s n=%d prec=%d -> %s (rule %s)" % (grid, n, prec, shape, P0.tuning()))
+    t0, t1 = to_dev(torch, A, dt), to_dev(torch, A, dt)
+    r0, r1 = P0.iterate(t0, 6), P1.iterate(t1, 6)
+    assert torch.equal(t0, t1)
+    assert np.array_equal(r0["flips"], r1["flips"])
+    assert np.allclose(r0["energy"], r1["energy"], rtol=1e-12 if prec == F64 else 1e-5, atol=0)
+    if prec == F64:
+        Eo = oracle.energy(t1.cpu().numpy(), 2e-3)
+        assert abs(r1["energy"][0][-1] - Eo) <= 1e-11 * max(1.0, abs(Eo))
