@@ -82,51 +82,45 @@ __device__ __forceinline__ V wave_sum(V v)
 // forward-FFT the lines from LDS and store the spectra.  The projection, which
 // dominates the arithmetic, thus runs one point per thread on all threads.
 // ---------------------------------------------------------------------------
-// Copy the workgroup's lines between the spectra and LDS with all threads, 16
-// bytes per access (two float or one double complex values).  Line j (row
-// rloc = j / PL of the workgroup, packed plane pl = j % PL) is
-// Zb[pl * npts + (row0 + rloc) * L + x], x < L, and sits at
-// lr/li[j * lp + lds_pad(x)].  Rows at or beyond `rows` are skipped.
-template <typename T, int PL, int LOG2L, bool TO_LDS>
-__device__ __forceinline__ void stage_lines(typename cx<T>::type* Zb, T* lr, T* li, int lp, int nlines,
-                                            int64_t row0, int64_t rows, int64_t npts, int tid, int NT)
+// One line of L complex values moved between global memory (contiguous, from
+// zline) and LDS (natural order, lr/li[lds_pad(x)]) by the L/8 threads of its
+// group, 16 bytes per access; consecutive threads take consecutive vectors.
+template <typename T, int LOG2L, bool TO_LDS>
+__device__ __forceinline__ void line_stage(typename cx<T>::type* zline, T* lr, T* li, int t)
 {
     constexpr int L = 1 << LOG2L;
+    constexpr int Tn = L / 8;
     constexpr int EPV = sizeof(T) == 4 ? 2 : 1;  // complex values per access
-    constexpr int VPL = L / EPV;                 // accesses per line
+    constexpr int VPT = 8 / EPV;                 // accesses per thread
     typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type V;
-    const int nvec = nlines * VPL;
-    for (int i = tid; i < nvec; i += NT) {
-        const int j = i / VPL;
-        const int x = (i - j * VPL) * EPV;
-        const int rloc = j / PL, pl = j - (j / PL) * PL;
-        if (row0 + rloc >= rows) continue;
-        V* gp = reinterpret_cast<V*>(Zb + (int64_t)pl * npts + (row0 + rloc) * L + x);
-        T* lrj = lr + j * lp + lds_pad(x);
-        T* lij = li + j * lp + lds_pad(x);
+    V* zv = reinterpret_cast<V*>(zline);
+    const int x0 = t * EPV, px0 = lds_pad(x0);
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) {
+        const int a = lds_pad_at<Tn * EPV>(x0, px0, v);  // element x0 + v * Tn * EPV
         if constexpr (TO_LDS) {
-            const V v = *gp;
+            const V w = zv[v * Tn + t];
             if constexpr (EPV == 2) {
-                lrj[0] = v.x;
-                lij[0] = v.y;
-                lrj[1] = v.z;  // x is even: x + 1 gets no extra padding
-                lij[1] = v.w;
+                lr[a] = w.x;
+                li[a] = w.y;
+                lr[a + 1] = w.z;  // x0 is even: x0 + 1 gets no extra padding
+                li[a + 1] = w.w;
             } else {
-                lrj[0] = v.x;
-                lij[0] = v.y;
+                lr[a] = w.x;
+                li[a] = w.y;
             }
         } else {
-            V v;
+            V w;
             if constexpr (EPV == 2) {
-                v.x = lrj[0];
-                v.y = lij[0];
-                v.z = lrj[1];
-                v.w = lij[1];
+                w.x = lr[a];
+                w.y = li[a];
+                w.z = lr[a + 1];
+                w.w = li[a + 1];
             } else {
-                v.x = lrj[0];
-                v.y = lij[0];
+                w.x = lr[a];
+                w.y = li[a];
             }
-            *gp = v;
+            zv[v * Tn + t] = w;
         }
     }
 }
@@ -191,19 +185,21 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
     const bool staged = LOG2L <= 9 && !(flags & RF_LOAD_REAL);
     if constexpr (LOG2L <= 9) {
         if (staged) {
-            // spectra staged by all threads, then each line group transforms its
-            // line in place in LDS
-            stage_lines<T, PL, LOG2L, true>(Zb, lr, li, lp, nlines, row0, a.rows, npts, tid, NT);
-            __syncthreads();
-            if (flags & RF_INVERSE) {
-                Twiddles<T, LOG2L> tw;
-                load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
-                const int pt = lds_pad(t);
-                for (int rd = 0; rd < rounds; ++rd) {
-                    const int j = rd * G + g;
-                    const bool act = j < nlines;
-                    T* lrj = lr + (size_t)(act ? j : 0) * lp;
-                    T* lij = li + (size_t)(act ? j : 0) * lp;
+            // each line group stages its own line through LDS (16-byte
+            // accesses) and transforms it in place: only wave-level ordering
+            Twiddles<T, LOG2L> tw;
+            if (flags & RF_INVERSE) load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
+            const int pt = lds_pad(t);
+            for (int rd = 0; rd < rounds; ++rd) {
+                const int j = rd * G + g;
+                const bool act = j < nlines;
+                const int rloc = j / PL, pl = j - (j / PL) * PL;
+                T* lrj = lr + (size_t)(act ? j : 0) * lp;
+                T* lij = li + (size_t)(act ? j : 0) * lp;
+                if (act && row0 + rloc < a.rows)
+                    line_stage<T, LOG2L, true>(Zb + (int64_t)pl * npts + (row0 + rloc) * L, lrj, lij, t);
+                wave_lds_sync();
+                if (flags & RF_INVERSE) {
                     T r[8], im[8];
                     if (act) {
 #pragma unroll
@@ -429,7 +425,7 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
                 }
             }
             if constexpr (LOG2L <= 9) {
-                // back to LDS in natural order; all threads store after the loop
+                // back to LDS in natural order, then the group stores its line
                 fft_wave<T, -1, LOG2L>(r[0], im[0], lrj, lij, t, tw, act);
                 wave_lds_sync();
                 if (act) {
@@ -439,6 +435,9 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
                         lij[lds_pad_at<Tn>(t, lds_pad(t), e)] = im[0][e];
                     }
                 }
+                wave_lds_sync();
+                if (act && row0 + rloc < a.rows)
+                    line_stage<T, LOG2L, false>(Zb + (int64_t)pl * npts + (row0 + rloc) * L, lrj, lij, t);
             } else {
                 fft_lines<T, -1, 1, LOG2L>(r, im, lrj, lij, 0, 1, 0, t, tw, act);
             }
@@ -453,10 +452,6 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
                     Z[x0 + (int64_t)e * Tn] = v;
                 }
             }
-        }
-        if constexpr (LOG2L <= 9) {
-            __syncthreads();
-            stage_lines<T, PL, LOG2L, false>(Zb, lr, li, lp, nlines, row0, a.rows, npts, tid, NT);
         }
     }
 
