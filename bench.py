@@ -137,8 +137,9 @@ def run_gpu(w, precision, steps, warmup, timing_steps, autotune=True):
         "heat_us": float(np.mean(col_us)) if col_us else None,
         "energy_first_last": [float(logs["energy"][0][0]), float(logs["energy"][0][-1])],
         "fallbacks_total": int(logs["fallbacks"][0].sum()),
-        "launch_shape": {"rows_per_row_workgroup": tuning[0], "lines_per_heat_workgroup": tuning[1],
-                         "xcd_tile_order": tuning[2], "autotuned": bool(autotune)},
+        "launch_shape": {"rows_per_row_workgroup": tuning[0], "row_workgroup_threads": tuning[1],
+                         "lines_per_heat_workgroup": tuning[2], "xcd_tile_order": tuning[3],
+                         "autotuned": bool(autotune)},
         "flips_first": int(logs["flips"][0][0]),
     }
 

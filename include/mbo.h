@@ -172,7 +172,7 @@ typedef struct mbo_field_desc {
 /* Create a batched plan for `count` fields (the shape rules of mbo_plan apply to
  * each descriptor).  autotune != 0 times candidate launch shapes of every class
  * on the device (tiles of lines per strided-pass workgroup, the XCD-aware tile
- * order, rows per row-pass workgroup) on a pseudo-random field and keeps the
+ * order, rows and threads per row-pass workgroup) on a pseudo-random field and keeps the
  * fastest; 0 keeps the fixed rules.  The choice changes neither the transforms
  * nor the projection of any point, only the summation order of the energy. */
 mbo_status mbo_plan_batched(mbo_plan_t* out, int count, const mbo_field_desc* descs, mbo_precision prec,
@@ -185,11 +185,11 @@ mbo_status mbo_plan_batched(mbo_plan_t* out, int count, const mbo_field_desc* de
 mbo_status mbo_plan_autotune(mbo_plan_t plan);
 
 /* Launch shape used for `field` (0 <= field < count, or < batch for a plain
- * plan): rows per row-pass workgroup, lines per heat-pass workgroup, and
- * whether heat-pass tiles are dealt to the XCDs in contiguous runs (all
- * nullable). */
-mbo_status mbo_plan_tuning(mbo_plan_t plan, int field, int* rows_per_group, int* heat_lines_per_group,
-                           int* xcd_order);
+ * plan): rows per row-pass workgroup and its thread count, lines per heat-pass
+ * workgroup, and whether heat-pass tiles are dealt to the XCDs in contiguous
+ * runs (all nullable). */
+mbo_status mbo_plan_tuning(mbo_plan_t plan, int field, int* rows_per_group, int* row_threads,
+                           int* heat_lines_per_group, int* xcd_order);
 
 /* ---------------------------------------------------------------------------
  * Adjoint building blocks.  The paper stops at the forward iteration; these

@@ -424,9 +424,12 @@ __device__ __forceinline__ void polar2(const T* a, T* q, int& dsign, T& smin)
 // stops after a sweep without rotations, or after a sweep whose rotations all
 // had |s| < sdone (the inner products left are then of order s^2, below the
 // tolerance, so the confirming sweep is skipped).
-template <typename T, int n>
+template <typename T, int n, bool FOR_FLOAT = false>
 __device__ __forceinline__ void jacobi_sweeps(T (&W)[n][n], T (&V)[n][n])
 {
+    // a double run whose result is rounded to float may stop once the
+    // remaining inner products (of order s^2) are far below float rounding
+    constexpr T sdone = FOR_FLOAT ? (T)1e-6 : num<T>::sdone;
 #pragma unroll 1
     for (int sweep = 0; sweep < 30; ++sweep) {
         bool rotated = false;
@@ -465,7 +468,7 @@ __device__ __forceinline__ void jacobi_sweeps(T (&W)[n][n], T (&V)[n][n])
                 }
             }
         }
-        if (!rotated || smax < num<T>::sdone) break;
+        if (!rotated || smax < sdone) break;
     }
 }
 
@@ -614,10 +617,10 @@ __device__ __forceinline__ void polar_jacobi(const T* a_in, T* q, int& dsign, T&
 }
 
 // The same in double, warm-started from the right singular vectors V0 of a
-// lower-precision run on the same matrix: V0 is re-orthonormalised in double
-// (modified Gram-Schmidt), W = A V0 is then nearly column-orthogonal and the
-// sweeps converge in one or two passes.  The result is the same closest
-// orthogonal matrix (unique for nonsingular A) to double rounding.
+// float run on the same matrix, for a result that is rounded to float: V0 is
+// re-orthonormalised in double (modified Gram-Schmidt), W = A V0 is then nearly
+// column-orthogonal and one sweep (rotations of order float rounding) leaves
+// inner products of order 1e-14, far below what the float result resolves.
 template <int n>
 __device__ __forceinline__ void polar_jacobi_warm(const double* a_in, const float (&V0)[n][n],
                                                   double* q, int& dsign, double& smin)
@@ -654,7 +657,7 @@ __device__ __forceinline__ void polar_jacobi_warm(const double* a_in, const floa
             for (int k = 0; k < n; ++k) v += a_in[i * n + k] * V[k][j];
             W[i][j] = ldexp(v, -ex);
         }
-    jacobi_sweeps<double, n>(W, V);
+    jacobi_sweeps<double, n, true>(W, V);
     jacobi_finish<double, n>(W, V, ex, q, dsign, smin);
 }
 
