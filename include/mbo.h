@@ -224,6 +224,24 @@ mbo_status mbo_project_vjp(mbo_plan_t plan, const void* A_tilde, const void* G_Q
  * out may alias A. */
 mbo_status mbo_diffuse_dtau(mbo_plan_t plan, const void* A, void* out, const void* G, double* dot);
 
+/* One step of Algorithm 1 without logs: A_next = P(e^{tau Delta} A_prev), with
+ * the plan's precision and fallback, bit for bit the iterate mbo_iterate
+ * produces from A_prev.  Asynchronous (no synchronisation, no NaN check: a
+ * non-finite input propagates).  Device buffers; A_next must not alias A_prev.
+ * Used to recompute iterates between checkpoints of the adjoint. */
+mbo_status mbo_step(mbo_plan_t plan, const void* A_prev, void* A_next);
+
+/* Backward step of the adjoint (the chain rule through one step of
+ * Algorithm 1), asynchronous: with A~ = e^{tau Delta} A_prev and on entry G =
+ * Gbar_s, the cotangent of A_s = P(A~),
+ *     G~      = mbo_project_vjp(A~, Gbar_s)
+ *     dtau[b] += <G~_b, d/dtau e^{tau Delta} A_prev_b>   (device, [batch], double;
+ *                                                        skipped when NULL)
+ *     G      <- e^{tau Delta} G~  (= Gbar_{s-1}; the heat operator is self-adjoint).
+ * Plan-owned workspaces of two fields are allocated on the first call.  No
+ * NaN check (a non-finite input propagates).  G must not alias A_prev. */
+mbo_status mbo_step_vjp(mbo_plan_t plan, const void* A_prev, void* G, double* dtau);
+
 /* Human-readable name of a status code (static storage). */
 const char* mbo_status_string(mbo_status s);
 

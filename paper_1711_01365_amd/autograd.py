@@ -5,15 +5,17 @@ the pointwise closest orthogonal matrix (Lemma 1.1), run by ``mbo_iterate`` in
 segments of ``checkpoint`` steps; only the segment starts are kept.
 
 Backward (the paper has no adjoint; this is the chain rule): for each segment,
-last first, the iterates are recomputed from its start (``mbo_diffuse`` and
-``mbo_project``), then for s from the segment's end down to its start
+last first, the iterates are recomputed from its start (``mbo_step``), then for
+s from the segment's end down to its start one ``mbo_step_vjp`` computes
 
-    Gtil_s      = VJP of P at H A_{s-1} applied to Gbar_s   (mbo_project_vjp)
-    dL/dtau    += <Gtil_s, d/dtau H A_{s-1}>                 (mbo_diffuse_dtau)
-    Gbar_{s-1}  = H Gtil_s                                   (mbo_diffuse; H is self-adjoint)
+    Gtil_s      = VJP of P at H A_{s-1} applied to Gbar_s
+    dL/dtau    += <Gtil_s, d/dtau H A_{s-1}>      (accumulated on the device)
+    Gbar_{s-1}  = H Gtil_s                        (H is self-adjoint)
 
-and dL/dA_0 = Gbar_0.  Every step runs in the HIP kernels of libmbo; this module
-only orders the calls and keeps the checkpoints (torch tensors on the device).
+and dL/dA_0 = Gbar_0.  Nothing in the backward pass waits for the host until
+the tau-gradient is read at the end.  Every step runs in the HIP kernels of
+libmbo; this module only orders the calls and keeps the checkpoints (torch
+tensors on the device).
 """
 from __future__ import annotations
 
@@ -52,28 +54,20 @@ class UnrolledMBO(torch.autograd.Function):
         plan, K, c = ctx.plan, ctx.K, ctx.checkpoint
         plan.set_tau(ctx.tau)
         G = grad_out.detach().to(plan.dtype).contiguous().clone()
-        dtau = 0.0
+        # dL/dtau accumulates on the device; one read at the end
+        dtau = torch.zeros(plan.batch, dtype=torch.float64, device=G.device)
         for j in reversed(range(len(ctx.ckpts))):
             s0, s1 = j * c, min(j * c + c, K)
-            prev = [ctx.ckpts[j]]      # A_{s-1} for s = s0+1..s1
-            tilde = []                 # H A_{s-1}
-            X = ctx.ckpts[j]
-            for s in range(s0 + 1, s1 + 1):
-                At = plan.diffuse(X)
-                tilde.append(At)
-                if s < s1:
-                    X = plan.project(At)
-                    prev.append(X)
-            for i in reversed(range(len(tilde))):
-                Gt = plan.project_vjp(tilde[i], G)
-                d = plan.diffuse_dtau(prev[i], G=Gt)
-                dtau += float(d.sum()) if hasattr(d, "sum") else float(d)
-                G = plan.diffuse(Gt)
+            prev = [ctx.ckpts[j]]  # A_{s-1} for s = s0+1 .. s1, recomputed
+            for _ in range(s0 + 1, s1):
+                prev.append(plan.step(prev[-1]))
+            for X in reversed(prev):
+                plan.step_vjp(X, G, dtau)  # G: Gbar_s -> Gbar_{s-1}
         ctx.ckpts = None
         gtau = None
         if ctx.tau_is_tensor and ctx.needs_input_grad[1]:
             dt, dev = ctx.tau_meta
-            gtau = torch.tensor(dtau, dtype=dt, device=dev)
+            gtau = dtau.sum().to(device=dev, dtype=dt)
         gA0 = G if ctx.needs_input_grad[0] else None
         return gA0, gtau, None, None, None
 

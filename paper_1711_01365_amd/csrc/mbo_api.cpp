@@ -70,6 +70,8 @@ struct mbo_plan_s {
     void* mu_inner = nullptr;   // -4 pi^2 |k|^2 over the faster axes [npts / N0]
     double* dpart = nullptr;    // dot-product partials [batch][row workgroups]
     double* dsum = nullptr;     // [batch]
+    void* ws_a = nullptr;       // adjoint step workspaces, one field each (lazy)
+    void* ws_g = nullptr;
     unsigned long long* counters = nullptr;  // project: [0] nonfinite, [1] fallbacks
 
     // per-field diffusion times (fields of a batched plan): tables per field
@@ -186,6 +188,8 @@ void destroy(mbo_plan_t p)
     free_dev(p->mu_inner);
     free_dev(p->dpart);
     free_dev(p->dsum);
+    free_dev(p->ws_a);
+    free_dev(p->ws_g);
     free_dev(p->taus_dev);
     free_dev(p->foff_dev);
     free_dev(p->counters);
@@ -912,6 +916,42 @@ std::vector<int> member_fields(mbo_plan_t g, int mi)
     return map;
 }
 
+// out = e^{tau Delta} in (one diffusion step), enqueued on st.
+hipError_t enqueue_diffuse(mbo_plan_t p, const void* in, void* out, hipStream_t st)
+{
+    hipError_t e = enqueue_forward(p, in, 0, true, st);
+    if (e != hipSuccess) return e;
+    ColArgs h = col_args(p, p->heat);
+    if ((e = run_col(p, p->heat, CM_HEAT, h, st)) != hipSuccess) return e;
+    if (p->d == 3) {
+        ColArgs y = col_args(p, p->ypass);
+        if ((e = run_col(p, p->ypass, CM_INVERSE, y, st)) != hipSuccess) return e;
+    }
+    RowArgs r = row_args(p);
+    r.Aout = out;
+    r.flags = RF_INVERSE | RF_STORE_REAL;
+    return run_row(p, r, st);
+}
+
+// dot[b] += <G_b, d/dtau e^{tau Delta} A_b> (device accumulator), enqueued on st.
+hipError_t enqueue_dtau_dot(mbo_plan_t p, const void* A, const void* G, double* dot, hipStream_t st)
+{
+    hipError_t e = enqueue_forward(p, A, 0, true, st);
+    if (e != hipSuccess) return e;
+    ColArgs h = col_args(p, p->heat);
+    if ((e = run_col(p, p->heat, CM_DTAU, h, st)) != hipSuccess) return e;
+    if (p->d == 3) {
+        ColArgs y = col_args(p, p->ypass);
+        if ((e = run_col(p, p->ypass, CM_INVERSE, y, st)) != hipSuccess) return e;
+    }
+    RowArgs r = row_args(p);
+    r.flags = RF_INVERSE | RF_DOT;
+    r.Gdot = G;
+    r.dpart = p->dpart;
+    if ((e = run_row(p, r, st)) != hipSuccess) return e;
+    return launch_sum_rows(p->dpart, (int64_t)p->row_grid.x, (int)p->batch, dot, st, true);
+}
+
 bool use_graphs()
 {
     const char* v = std::getenv("MBO_NO_GRAPH");
@@ -1227,6 +1267,58 @@ mbo_status mbo_project_vjp(mbo_plan_t p, const void* A_tilde, const void* G_Q, v
     HIP_TRY(p, hipMemcpyAsync(h, p->counters, sizeof h, hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(p, hipStreamSynchronize(p->stream));
     if (h[0]) return fail(p, MBO_ERR_NONFINITE, "%llu points with NaN/Inf input", h[0]);
+    return MBO_OK;
+}
+
+mbo_status mbo_step(mbo_plan_t p, const void* A_prev, void* A_next)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (p->group) return fail(p, MBO_ERR_UNSUPPORTED, "not available for a batched plan");
+    if (!A_prev || !A_next) return fail(p, MBO_ERR_INVALID_ARG, "A_prev / A_next is NULL");
+    if (A_prev == A_next) return fail(p, MBO_ERR_INVALID_ARG, "A_next must not alias A_prev");
+    HIP_TRY(p, hipSetDevice(p->device));
+    HIP_TRY(p, enqueue_forward(p, A_prev, 0, true, p->stream));
+    ColArgs h = col_args(p, p->heat);
+    HIP_TRY(p, run_col(p, p->heat, CM_HEAT, h, p->stream));
+    if (p->d == 3) {
+        ColArgs y = col_args(p, p->ypass);
+        HIP_TRY(p, run_col(p, p->ypass, CM_INVERSE, y, p->stream));
+    }
+    RowArgs r = row_args(p);
+    r.Aout = A_next;
+    r.flags = RF_INVERSE | RF_PROJECT | RF_STORE_REAL;
+    if (p->prec == MBO_F32_F64FALLBACK) r.flags |= RF_FALLBACK;
+    HIP_TRY(p, run_row(p, r, p->stream));
+    return MBO_OK;
+}
+
+mbo_status mbo_step_vjp(mbo_plan_t p, const void* A_prev, void* G, double* dtau)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (p->group) return fail(p, MBO_ERR_UNSUPPORTED, "not available for a batched plan");
+    if (!A_prev || !G) return fail(p, MBO_ERR_INVALID_ARG, "A_prev / G is NULL");
+    if (A_prev == (const void*)G) return fail(p, MBO_ERR_INVALID_ARG, "G must not alias A_prev");
+    HIP_TRY(p, hipSetDevice(p->device));
+    const size_t fbytes = (size_t)p->batch * p->n * p->n * (size_t)p->npts * p->esz;
+    if (!p->ws_a) HIP_TRY(p, hipMalloc(&p->ws_a, fbytes));
+    if (!p->ws_g) HIP_TRY(p, hipMalloc(&p->ws_g, fbytes));
+    hipStream_t st = p->stream;
+    // A~ = e^{tau Delta} A_{s-1}
+    HIP_TRY(p, enqueue_diffuse(p, A_prev, p->ws_a, st));
+    // G~ = VJP of the projection at A~
+    VjpArgs v;
+    v.npts = p->npts;
+    v.A = p->ws_a;
+    v.G = G;
+    v.GA = p->ws_g;
+    v.nonfinite = p->counters;
+    v.fallback = p->prec == MBO_F32_F64FALLBACK;
+    v.sigma_fb = p->sigma_fb;
+    HIP_TRY(p, launch_vjp(p->pk, p->n, v, (int)p->batch, st));
+    // dL/dtau += <G~, d/dtau e^{tau Delta} A_{s-1}>
+    if (dtau) HIP_TRY(p, enqueue_dtau_dot(p, A_prev, p->ws_g, dtau, st));
+    // Gbar_{s-1} = e^{tau Delta} G~
+    HIP_TRY(p, enqueue_diffuse(p, p->ws_g, G, st));
     return MBO_OK;
 }
 

@@ -151,8 +151,9 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
 hipError_t launch_vjp(int prec, int n, const VjpArgs& a, int batch, hipStream_t st);
 // count values uniform in [-1, 1) from a counter-based hash of (seed, index)
 hipError_t launch_fill_uniform(int prec, void* p, int64_t count, uint64_t seed, hipStream_t st);
-// out[b] = sum of part[b * m .. b * m + m - 1] in a fixed order
-hipError_t launch_sum_rows(const double* part, int64_t m, int batch, double* out, hipStream_t st);
+// out[b] = (accumulate ? out[b] : 0) + sum of part[b * m .. b * m + m - 1] in a fixed order
+hipError_t launch_sum_rows(const double* part, int64_t m, int batch, double* out, hipStream_t st,
+                           bool accumulate = false);
 
 // per-translation-unit launchers behind launch_row / launch_col
 hipError_t launch_row_f32(int n, int log2L, const RowArgs& a, dim3 g, dim3 b, size_t lds,

@@ -85,15 +85,15 @@ __global__ void __launch_bounds__(256) vjp_kernel(const VjpArgs a)
     if (threadIdx.x == 0 && bad) atomicAdd(a.nonfinite, bad);
 }
 
-// out[b] = fixed-order sum of the m partials of field b (one workgroup per field)
-__global__ void __launch_bounds__(256) sum_rows(const double* part, int64_t m, double* out)
+// out[b] (+)= fixed-order sum of the m partials of field b (one workgroup per field)
+__global__ void __launch_bounds__(256) sum_rows(const double* part, int64_t m, double* out, int accumulate)
 {
     __shared__ double red_d[64];
     const int b = blockIdx.x;
     double acc = 0.0;
     for (int64_t i = threadIdx.x; i < m; i += blockDim.x) acc += part[(int64_t)b * m + i];
     acc = block_reduce<OpSum>(acc, red_d);
-    if (threadIdx.x == 0) out[b] = acc;
+    if (threadIdx.x == 0) out[b] = accumulate ? out[b] + acc : acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -201,9 +201,10 @@ hipError_t launch_vjp(int prec, int n, const VjpArgs& a, int batch, hipStream_t 
     return prec == 0 ? vjp_dispatch<double>(n, a, batch, st) : vjp_dispatch<float>(n, a, batch, st);
 }
 
-hipError_t launch_sum_rows(const double* part, int64_t m, int batch, double* out, hipStream_t st)
+hipError_t launch_sum_rows(const double* part, int64_t m, int batch, double* out, hipStream_t st,
+                           bool accumulate)
 {
-    hipLaunchKernelGGL(sum_rows, dim3((unsigned)batch), dim3(256), 0, st, part, m, out);
+    hipLaunchKernelGGL(sum_rows, dim3((unsigned)batch), dim3(256), 0, st, part, m, out, accumulate ? 1 : 0);
     return hipGetLastError();
 }
 

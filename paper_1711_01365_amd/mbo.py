@@ -28,7 +28,7 @@ _lib = None
 EXPORTS = ("mbo_plan", "mbo_plan_destroy", "mbo_plan_set_tau", "mbo_plan_set_stream",
            "mbo_plan_set_timing", "mbo_last_timing", "mbo_diffuse", "mbo_project", "mbo_iterate",
            "mbo_energy", "mbo_project_vjp", "mbo_diffuse_dtau", "mbo_plan_batched", "mbo_plan_tuning",
-           "mbo_plan_autotune",
+           "mbo_plan_autotune", "mbo_step", "mbo_step_vjp",
            "mbo_status_string", "mbo_last_error")
 
 
@@ -71,6 +71,8 @@ def load(path: str = LIB_PATH):
                                      ctypes.c_int, ctypes.c_double, ctypes.c_int, vp]
     lib.mbo_plan_tuning.argtypes = [vp, ctypes.c_int, ip, ip, ip, ip]
     lib.mbo_plan_autotune.argtypes = [vp]
+    lib.mbo_step.argtypes = [vp, vp, vp]
+    lib.mbo_step_vjp.argtypes = [vp, vp, vp, vp]
     for f in EXPORTS:
         if f not in ("mbo_status_string", "mbo_last_error"):
             getattr(lib, f).restype = ctypes.c_int
@@ -169,6 +171,26 @@ class Plan:
                                      ctypes.c_void_p(ds.data_ptr()) if ds is not None else None),
                self._h)
         return (A_out, ds) if det_sign else A_out
+
+    def step(self, A_prev, A_next=None):
+        """A_next = P(e^{tau Delta} A_prev), asynchronous (no logs, no NaN check)."""
+        import torch
+        if A_next is None:
+            A_next = torch.empty_like(A_prev)
+        _check(self._lib.mbo_step(self._h, self._field(A_prev, "A_prev"), self._field(A_next, "A_next")),
+               self._h)
+        return A_next
+
+    def step_vjp(self, A_prev, G, dtau=None):
+        """In place G <- cotangent of A_prev from G = cotangent of P(e^{tau Delta} A_prev);
+        dtau (device float64 [batch] tensor, optional) += the step's tau-derivative term."""
+        import torch
+        if dtau is not None and (dtau.dtype != torch.float64 or not dtau.is_cuda or dtau.numel() != self.batch):
+            raise ValueError("dtau must be a float64 device tensor of %d values" % self.batch)
+        _check(self._lib.mbo_step_vjp(self._h, self._field(A_prev, "A_prev"), self._field(G, "G"),
+                                      ctypes.c_void_p(dtau.data_ptr()) if dtau is not None else None),
+               self._h)
+        return G
 
     def project_vjp(self, A_tilde, G_Q, G_A=None):
         """Cotangent of the projection's input for the cotangent G_Q of its output."""

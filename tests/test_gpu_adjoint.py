@@ -319,3 +319,30 @@ def test_unrolled_grad_f32_full(torch_cuda, adjoint_ref, prec):
          % (prec, loss, ref["loss"], e_l2, e_max, e_t))
     assert abs(loss - ref["loss"]) <= 1e-5 * ref["loss"]
     assert e_max <= 1e-4 and e_l2 <= 1e-4 and e_t <= 1e-4
+
+
+def test_step_matches_iterate_and_step_vjp_matches_pieces(torch_cuda):
+    """mbo_step reproduces one iterate of mbo_iterate bit for bit; mbo_step_vjp
+    equals the composition of mbo_diffuse, mbo_project_vjp, mbo_diffuse_dtau."""
+    torch = torch_cuda
+    n, grid, tau = 3, (64, 32), 2e-3
+    A = inputs.uniform_field(n, grid, 140)
+    G = inputs.normal_field(n, grid, 141)
+    for prec in (F64, FB):
+        dt = torch.float64 if prec == F64 else torch.float32
+        p = plan(grid, n, tau, prec)
+        a0 = to_dev(torch, A, dt)
+        x = a0.clone()
+        p.iterate(x, 1)
+        y = p.step(a0)
+        assert torch.equal(x, y)
+        g = to_dev(torch, G, dt)
+        dtau = torch.zeros(1, dtype=torch.float64, device="cuda")
+        g2 = g.clone()
+        p.step_vjp(a0, g2, dtau)
+        at = p.diffuse(a0)
+        gt = p.project_vjp(at, g)
+        d_ref = p.diffuse_dtau(a0, G=gt)
+        g_ref = p.diffuse(gt)
+        assert torch.equal(g2, g_ref)
+        assert dtau.item() == d_ref
