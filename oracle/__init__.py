@@ -23,6 +23,10 @@ What each function follows (Osting & Wang, arXiv:1711.01365):
   * ``project_vjp``  vector-Jacobian product of the projection U V^t.
   * ``unroll_grad``  loss (1/2)||A_K - T||^2 of K steps of Algorithm 1 and its
                   gradients in A_0 and tau, by the chain rule run backwards.
+  * ``volume_project``  Section 7: T^+ / T^- of Lemma 7.1, Delta E, and the
+                  reassignment of Lemma 7.2 keeping exactly n_plus points in
+                  SO(n) (the n_plus largest Delta E, ties by point index).
+  * ``iterate_volume``  volume-preserving MBO: Algorithm 1 with that step 2.
   * ``dft_naive`` / ``fft``   the discrete Fourier transform by definition and
                   by radix-2 Cooley-Tukey (cross-checked against each other).
 """
@@ -83,10 +87,14 @@ def _load():
     lib.orc_project_vjp.argtypes = [ctypes.c_int64, ctypes.c_int, _d, _d, _d]
     lib.orc_unroll_grad.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_double, _d, _d,
                                     ctypes.c_int, _d, _d, _d, _i64]
+    lib.orc_volume_project.argtypes = [ctypes.c_int64, ctypes.c_int, _d, ctypes.c_int64, _d, _d,
+                                       _i8]
+    lib.orc_iterate_volume.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_double, _d,
+                                       ctypes.c_int, ctypes.c_int64, _d, _i64, _i64]
     lib.orc_num_threads.argtypes = []
     for f in ("orc_dft_naive", "orc_fft", "orc_heat", "orc_project", "orc_det_sign",
               "orc_energy", "orc_iterate", "orc_num_threads", "orc_heat_dtau", "orc_project_vjp",
-              "orc_unroll_grad"):
+              "orc_unroll_grad", "orc_volume_project", "orc_iterate_volume"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -264,3 +272,42 @@ def unroll_grad(A0: np.ndarray, T: np.ndarray, tau: float, K: int):
     _check(lib.orc_unroll_grad(d, _ptr(g, _i64), n, float(tau), _ptr(A0), _ptr(T), int(K),
                                _ptr(loss), _ptr(gA0), _ptr(gtau), _ptr(fl, _i64)), "unroll_grad")
     return {"loss": float(loss[0]), "gA0": gA0, "gtau": float(gtau[0]), "flips": fl[:K]}
+
+
+def volume_project(A: np.ndarray, n_plus: int):
+    """Volume-constrained projection (Section 7, Lemma 7.2).  A has shape (n, n, *grid).
+
+    Returns (B, dE [*grid], selected int8 [*grid]): B = T^+ on the n_plus points
+    with the largest Delta E (ties by ascending flat index), T^- elsewhere.
+    """
+    lib = _load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    assert A.shape[1] == n
+    grid = A.shape[2:]
+    P = int(np.prod(grid, dtype=np.int64))
+    B = np.empty_like(A)
+    dE = np.empty(grid, dtype=np.float64)
+    sel = np.empty(grid, dtype=np.int8)
+    _check(lib.orc_volume_project(P, n, _ptr(A), int(n_plus), _ptr(B), _ptr(dE), _ptr(sel, _i8)),
+           "volume_project")
+    return B, dE, sel
+
+
+def iterate_volume(A0: np.ndarray, tau: float, K: int, n_plus: int | None = None):
+    """Volume-preserving MBO (Section 7) for K iterations.
+
+    n_plus None takes #{det A_0 >= 0}.  Returns a dict: A (last iterate),
+    energy [K+1], n_pos [K+1] (#{det A_s >= 0}), n_plus.
+    """
+    lib = _load()
+    A = np.ascontiguousarray(A0, dtype=np.float64).copy()
+    n = A.shape[0]
+    g, d = _grid(A.shape[2:])
+    en = np.zeros(K + 1)
+    npos = np.zeros(K + 1, dtype=np.int64)
+    used = np.zeros(1, dtype=np.int64)
+    _check(lib.orc_iterate_volume(d, _ptr(g, _i64), n, float(tau), _ptr(A), int(K),
+                                  -1 if n_plus is None else int(n_plus), _ptr(en),
+                                  _ptr(npos, _i64), _ptr(used, _i64)), "iterate_volume")
+    return {"A": A, "energy": en, "n_pos": npos, "n_plus": int(used[0])}

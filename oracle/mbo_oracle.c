@@ -1,7 +1,8 @@
 /*
  * FP64 CPU oracle for the generalized MBO diffusion generated motion for
  * orthogonal matrix-valued fields on flat tori (Osting & Wang, arXiv:1711.01365:
- * Algorithm 1, Lemma 1.1, Section 4, Section 5.1).
+ * Algorithm 1, Lemma 1.1, Section 4, Section 5.1; the volume-preserving
+ * variant of Section 7: Lemmas 7.1, 7.2).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call
  * this file: only the test suite, the smoke check and the CPU-baseline leg of
@@ -647,6 +648,134 @@ int orc_unroll_grad(int d, const int64_t* N, int n, double tau, const double* A0
         *gtau = gt;
     }
     free(As); free(At); free(Gb); free(Gt); free(Dt); free(sp); free(sn);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Volume-preserving MBO (Section 7)                                         */
+/* ------------------------------------------------------------------------ */
+
+/* T^+(A), T^-(A) and Delta E = <T^+(A) - T^-(A), A>_F of one matrix.
+ * With A = U Sigma V^t, U V^t is the closest orthogonal matrix (Lemma 1.1) and
+ * U D_n V^t, which reverses the direction of the smallest singular value, the
+ * closest one of the opposite determinant (Lemma 7.1).  T^+ is whichever of the
+ * two has determinant +1 (the closest point of SO(n)) and T^- the other (the
+ * closest point of SO^-(n)); for det A > 0 this is U V^t and U D_n V^t, for
+ * det A < 0 the reverse, as Section 7 defines them.  The Jacobi singular values
+ * are unsorted: D_n acts on the first column holding the smallest one (when
+ * that value is repeated, T^- is not unique and this picks one minimiser). */
+static double orc_vp_point(int n, const double* a, double* tp, double* tm)
+{
+    double q[16], r[16], sig[4], U[16], V[16];
+    orc_project_point_usv(n, a, q, sig, U, V);
+    int jm = 0;
+    for (int j = 1; j < n; ++j)
+        if (sig[j] < sig[jm]) jm = j;
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) r[i * n + k] = q[i * n + k] - 2.0 * U[i * n + jm] * V[k * n + jm];
+    const int q_plus = orc_det(n, q) >= 0.0;
+    memcpy(tp, q_plus ? q : r, sizeof(double) * n * n);
+    memcpy(tm, q_plus ? r : q, sizeof(double) * n * n);
+    double de = 0.0;
+    for (int e = 0; e < n * n; ++e) de += (tp[e] - tm[e]) * a[e];
+    return de;
+}
+
+typedef struct {
+    double de;
+    int64_t idx;
+} orc_rank_t;
+
+/* Descending Delta E; equal values in ascending point index. */
+static int orc_rank_cmp(const void* x, const void* y)
+{
+    const orc_rank_t* u = (const orc_rank_t*)x;
+    const orc_rank_t* v = (const orc_rank_t*)y;
+    if (u->de > v->de) return -1;
+    if (u->de < v->de) return 1;
+    return (u->idx > v->idx) - (u->idx < v->idx);
+}
+
+/* Volume-constrained projection of an entry-planar field A (the reassignment of
+ * Lemma 7.2 on a uniform grid): the n_plus points with the largest Delta E
+ * receive T^+, all others T^-, so that exactly n_plus points end in SO(n).
+ * Choosing the first n_plus values of Delta E sorted in descending order is the
+ * flat-torus rule at the end of Section 7; equal values are taken in ascending
+ * point index (the paper leaves ties open).  dE and selected are nullable.
+ * Returns -1 on bad arguments, -2 when a Delta E is not finite. */
+int orc_volume_project(int64_t npts, int n, const double* A, int64_t n_plus, double* B, double* dE,
+                       int8_t* selected)
+{
+    if (npts < 0 || n < 1 || n > 4 || n_plus < 0 || n_plus > npts) return -1;
+    const int64_t nn = (int64_t)n * n;
+    double* tp = (double*)malloc(sizeof(double) * (size_t)(npts * nn + 1));
+    double* tm = (double*)malloc(sizeof(double) * (size_t)(npts * nn + 1));
+    orc_rank_t* rk = (orc_rank_t*)malloc(sizeof(orc_rank_t) * (size_t)(npts + 1));
+    int8_t* sel = (int8_t*)malloc((size_t)npts + 1);
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t p = 0; p < npts; ++p) {
+        double a[16];
+        for (int e = 0; e < nn; ++e) a[e] = A[e * npts + p];
+        rk[p].de = orc_vp_point(n, a, tp + p * nn, tm + p * nn);
+        rk[p].idx = p;
+        bad |= !isfinite(rk[p].de);
+    }
+    if (!bad) {
+        if (dE)
+            for (int64_t p = 0; p < npts; ++p) dE[p] = rk[p].de;
+        qsort(rk, (size_t)npts, sizeof(orc_rank_t), orc_rank_cmp);
+        memset(sel, 0, (size_t)npts);
+        for (int64_t r = 0; r < n_plus; ++r) sel[rk[r].idx] = 1;
+        for (int64_t p = 0; p < npts; ++p) {
+            const double* t = sel[p] ? tp + p * nn : tm + p * nn;
+            for (int e = 0; e < nn; ++e) B[e * npts + p] = t[e];
+        }
+        if (selected) memcpy(selected, sel, (size_t)npts);
+    }
+    free(tp); free(tm); free(rk); free(sel);
+    return bad ? -2 : 0;
+}
+
+/* Volume-preserving MBO: Algorithm 1 with step 2 replaced by the projection
+ * above, for K iterations in place on A.  n_plus < 0 takes the number of points
+ * of A_0 with det >= 0 (the volume of its SO(n) region).  Logs (nullable):
+ * energy[s] = E(A_s) for s = 0..K, n_pos[s] = #{p : det A_s(p) >= 0}.  The
+ * n_plus used is returned in *n_plus_used (nullable). */
+int orc_iterate_volume(int d, const int64_t* N, int n, double tau, double* A, int K, int64_t n_plus,
+                       double* energy, int64_t* n_pos, int64_t* n_plus_used)
+{
+    if (n < 1 || n > 4 || !(tau > 0.0) || K < 0) return -1;
+    int64_t P = orc_npoints(d, N);
+    int64_t nn = (int64_t)n * n;
+    double* At = (double*)malloc(sizeof(double) * (size_t)(P * nn));
+    int8_t* sg = (int8_t*)malloc((size_t)P);
+    int rc = 0;
+    orc_det_sign(P, n, A, sg);
+    int64_t c0 = 0;
+    for (int64_t p = 0; p < P; ++p) c0 += sg[p] > 0;
+    if (n_pos) n_pos[0] = c0;
+    if (n_plus < 0) n_plus = c0;
+    if (n_plus > P) rc = -1;
+    for (int s = 1; s <= K && rc == 0; ++s) {
+        rc = orc_heat(d, N, nn, tau, A, At, 0, NULL);                   /* diffusion step */
+        if (rc) break;
+        if (energy) energy[s - 1] = orc_energy_given(P, n, tau, A, At); /* E(A_{s-1}) */
+        rc = orc_volume_project(P, n, At, n_plus, A, NULL, NULL);      /* Lemma 7.2 step */
+        if (rc) break;
+        if (n_pos) {
+            orc_det_sign(P, n, A, sg);
+            int64_t c = 0;
+            for (int64_t p = 0; p < P; ++p) c += sg[p] > 0;
+            n_pos[s] = c;
+        }
+    }
+    if (rc == 0 && energy) {
+        rc = orc_heat(d, N, nn, tau, A, At, 0, NULL);
+        energy[K] = orc_energy_given(P, n, tau, A, At);
+    }
+    if (n_plus_used) *n_plus_used = n_plus;
+    free(At); free(sg);
     return rc;
 }
 

@@ -45,6 +45,30 @@ def haar_field(n: int, grid: Tuple[int, ...], seed: int) -> np.ndarray:
     return np.ascontiguousarray(np.moveaxis(Q, 0, -1)).reshape((n, n) + tuple(grid))
 
 
+def star_defect_field(grid: Tuple[int, int]) -> np.ndarray:
+    """The closed star-shaped line defect of the paper's first flat-torus example
+    (Section 6.1; also the volume-preserving example of Section 7), n = 2.
+
+    On [-1/2, 1/2)^2 sampled at x = -1/2 + i/N0 (axis 0), y = -1/2 + j/N1
+    (axis 1), with alpha = (pi/2) sin(2 pi (x + y)) and polar coordinates
+    (r, theta) of (x, y): the rotation by alpha inside r < 0.3 + 0.06 sin(6 theta),
+    the reflection [[cos a, sin a], [sin a, -cos a]] outside.
+    """
+    N0, N1 = grid
+    x = -0.5 + np.arange(N0) / N0
+    y = -0.5 + np.arange(N1) / N1
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    al = 0.5 * np.pi * np.sin(2.0 * np.pi * (X + Y))
+    inside = np.hypot(X, Y) < 0.3 + 0.06 * np.sin(6.0 * np.arctan2(Y, X))
+    c, s = np.cos(al), np.sin(al)
+    A = np.empty((2, 2, N0, N1))
+    A[0, 0] = c
+    A[0, 1] = np.where(inside, -s, s)
+    A[1, 0] = s
+    A[1, 1] = np.where(inside, c, -c)
+    return A
+
+
 @dataclass
 class Workload:
     """One measured configuration: field size, time step, iteration count."""
@@ -53,10 +77,13 @@ class Workload:
     grid: Tuple[int, ...]
     tau: float
     iters: int
-    init: str            # "uniform" | "haar" | "normal"
+    init: str            # "uniform" | "haar" | "normal" | "star"
     seed: int
 
     def field(self) -> np.ndarray:
+        if self.init == "star":
+            assert self.n == 2 and len(self.grid) == 2
+            return star_defect_field(self.grid)
         gen = {"uniform": uniform_field, "haar": haar_field, "normal": normal_field}[self.init]
         return gen(self.n, self.grid, self.seed)
 
@@ -76,6 +103,11 @@ ADJOINT_256 = Workload("n3_256x256_adjoint", 3, (256, 256), 1e-3, 50, "haar", 40
 ADJOINT_TARGET_SEED = 4002
 ADJOINT_TARGET_TAU = 1e-2
 ADJOINT_CHECKPOINT = 10
+# volume-preserving MBO (Section 7): the paper's example (star-shaped defect,
+# n = 2, 1024^2, tau = 8 dx), and the measured n = 3 configuration with the
+# volume of its initial SO(3) region held fixed
+VOLUME_STAR_1024 = Workload("n2_1024x1024_star_volume", 2, (1024, 1024), 8.0 / 1024, 100, "star", 0)
+VOLUME_HAAR_512 = Workload("n3_512x512_haar_volume", 3, (512, 512), 2e-4, 200, "haar", 1)
 
 
 @dataclass
