@@ -150,6 +150,56 @@ mbo_status mbo_iterate(mbo_plan_t plan, void* A, int max_iter, double tol, int* 
 mbo_status mbo_energy(mbo_plan_t plan, const void* A, double* E);
 
 /* ---------------------------------------------------------------------------
+ * Volume-preserving MBO (Section 7).  Step 2 of Algorithm 1 is replaced by a
+ * reassignment that keeps the number of grid points in SO(n) fixed (the volume
+ * of the SO(n) region on the uniform grid).  For the diffused matrix A~ at a
+ * point, with A~ = U Sigma V^t:
+ *   T+(A~)  the closest point of SO(n), T-(A~) the closest point of SO^-(n):
+ *           U V^t and U D_n V^t (Lemma 1.1, Lemma 7.1), D_n reversing the
+ *           direction of the smallest singular value; which of the two has
+ *           det +1 decides which is T+;
+ *   Delta E = <T+ - T-, A~>_F = 2 sgn(det A~) sigma_min(A~).
+ * The n_plus points of a field with the largest Delta E receive T+, all others
+ * T- (Lemma 7.2, with the flat-torus rule of taking the first n_plus values in
+ * descending order).  Equal values are taken in ascending point index (flat
+ * index p of the entry-planar layout); the paper leaves ties open.  When the
+ * smallest singular value is repeated, T- is not unique and one minimiser is
+ * returned.  MBO_F32_F64FALLBACK re-evaluates a point in double when its float
+ * sigma_min (|Delta E| / 2) is below sigma_fallback.
+ * Batched plans return MBO_ERR_UNSUPPORTED.
+ * ------------------------------------------------------------------------- */
+
+/* Selection alone: selected[b][p] = 1 for the n_plus[b] points of field b with
+ * the largest dE[b][p] (ties in ascending p), 0 elsewhere.
+ * dE: device, [batch][prod(N)] in the plan's element type, finite values (NaN
+ * orders by its sign bit); n_plus: host [batch], each in [0, prod(N)]
+ * (MBO_ERR_INVALID_ARG otherwise); selected: device uint8 [batch][prod(N)].
+ * Asynchronous. */
+mbo_status mbo_volume_select(mbo_plan_t plan, const void* dE, const int64_t* n_plus, uint8_t* selected);
+
+/* The volume-constrained step 2 on a given field (no diffusion):
+ * A_out = T+(A_in) on the n_plus[b] selected points of field b, T-(A_in)
+ * elsewhere.  dE (nullable, device, [batch][prod(N)], plan element type)
+ * receives Delta E.  A_out may alias A_in.  n_plus: host [batch], each in
+ * [0, prod(N)].  Synchronises; MBO_ERR_NONFINITE if any input is NaN/Inf. */
+mbo_status mbo_project_volume(mbo_plan_t plan, const void* A_in, void* A_out, const int64_t* n_plus,
+                              void* dE);
+
+/* Volume-preserving MBO: A_s = V(e^{tau Delta} A_{s-1}), s = 1..max_iter, in
+ * place on A, V the step above.  n_plus: host [batch] points to keep in SO(n),
+ * or NULL for the number of points of A_0 with det >= 0.  Host logs, nullable:
+ *   n_plus_used [batch]               the n_plus of each field;
+ *   energy      [batch][max_iter+1]   E(A_s), s = 0..max_iter (Proposition 7.3:
+ *                                     non-increasing once A_0 has n_plus points
+ *                                     with det > 0);
+ *   flips       [batch][max_iter]     points whose det sign changed;
+ *   fallbacks   [batch][max_iter]     points evaluated in double.
+ * Runs as one captured HIP graph (re-used while A, max_iter, the energy request
+ * and whether n_plus is given stay the same); synchronises at the end. */
+mbo_status mbo_iterate_volume(mbo_plan_t plan, void* A, int max_iter, const int64_t* n_plus,
+                              int64_t* n_plus_used, double* energy, int64_t* flips, int64_t* fallbacks);
+
+/* ---------------------------------------------------------------------------
  * Batched plans of mixed fields.  Many independent fields, each with its own
  * grid, matrix size n and tau, iterated together: fields of equal (d, N, n)
  * share one set of kernels and launches (a class), each field keeping its own

@@ -26,6 +26,7 @@ What each function follows (Osting & Wang, arXiv:1711.01365):
   * ``volume_project``  Section 7: T^+ / T^- of Lemma 7.1, Delta E, and the
                   reassignment of Lemma 7.2 keeping exactly n_plus points in
                   SO(n) (the n_plus largest Delta E, ties by point index).
+  * ``volume_select``   the selection alone (n_plus largest, ties by index).
   * ``iterate_volume``  volume-preserving MBO: Algorithm 1 with that step 2.
   * ``dft_naive`` / ``fft``   the discrete Fourier transform by definition and
                   by radix-2 Cooley-Tukey (cross-checked against each other).
@@ -87,6 +88,7 @@ def _load():
     lib.orc_project_vjp.argtypes = [ctypes.c_int64, ctypes.c_int, _d, _d, _d]
     lib.orc_unroll_grad.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_double, _d, _d,
                                     ctypes.c_int, _d, _d, _d, _i64]
+    lib.orc_volume_select.argtypes = [ctypes.c_int64, _d, ctypes.c_int64, _i8]
     lib.orc_volume_project.argtypes = [ctypes.c_int64, ctypes.c_int, _d, ctypes.c_int64, _d, _d,
                                        _i8]
     lib.orc_iterate_volume.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_double, _d,
@@ -94,7 +96,8 @@ def _load():
     lib.orc_num_threads.argtypes = []
     for f in ("orc_dft_naive", "orc_fft", "orc_heat", "orc_project", "orc_det_sign",
               "orc_energy", "orc_iterate", "orc_num_threads", "orc_heat_dtau", "orc_project_vjp",
-              "orc_unroll_grad", "orc_volume_project", "orc_iterate_volume"):
+              "orc_unroll_grad", "orc_volume_select", "orc_volume_project",
+              "orc_iterate_volume"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -272,6 +275,16 @@ def unroll_grad(A0: np.ndarray, T: np.ndarray, tau: float, K: int):
     _check(lib.orc_unroll_grad(d, _ptr(g, _i64), n, float(tau), _ptr(A0), _ptr(T), int(K),
                                _ptr(loss), _ptr(gA0), _ptr(gtau), _ptr(fl, _i64)), "unroll_grad")
     return {"loss": float(loss[0]), "gA0": gA0, "gtau": float(gtau[0]), "flips": fl[:K]}
+
+
+def volume_select(dE: np.ndarray, n_plus: int) -> np.ndarray:
+    """int8 mask of the n_plus largest values of dE (any shape, flat index order
+    breaks ties: the lower index first)."""
+    lib = _load()
+    v = np.ascontiguousarray(dE, dtype=np.float64)
+    sel = np.empty(v.shape, dtype=np.int8)
+    _check(lib.orc_volume_select(int(v.size), _ptr(v), int(n_plus), _ptr(sel, _i8)), "volume_select")
+    return sel
 
 
 def volume_project(A: np.ndarray, n_plus: int):

@@ -696,13 +696,33 @@ static int orc_rank_cmp(const void* x, const void* y)
     return (u->idx > v->idx) - (u->idx < v->idx);
 }
 
+/* The flat-torus selection rule at the end of Section 7: sort Delta E in
+ * descending order and take the first n_plus points; equal values are taken
+ * in ascending point index (the paper leaves ties open).  sel[p] = 1 for the
+ * selected points, 0 elsewhere.  Returns -1 on bad arguments, -2 when a value
+ * is not finite. */
+int orc_volume_select(int64_t npts, const double* dE, int64_t n_plus, int8_t* sel)
+{
+    if (npts < 0 || n_plus < 0 || n_plus > npts) return -1;
+    for (int64_t p = 0; p < npts; ++p)
+        if (!isfinite(dE[p])) return -2;
+    orc_rank_t* rk = (orc_rank_t*)malloc(sizeof(orc_rank_t) * (size_t)(npts + 1));
+    for (int64_t p = 0; p < npts; ++p) {
+        rk[p].de = dE[p];
+        rk[p].idx = p;
+    }
+    qsort(rk, (size_t)npts, sizeof(orc_rank_t), orc_rank_cmp);
+    memset(sel, 0, (size_t)npts);
+    for (int64_t r = 0; r < n_plus; ++r) sel[rk[r].idx] = 1;
+    free(rk);
+    return 0;
+}
+
 /* Volume-constrained projection of an entry-planar field A (the reassignment of
- * Lemma 7.2 on a uniform grid): the n_plus points with the largest Delta E
+ * Lemma 7.2 on a uniform grid): the n_plus points selected by the rule above
  * receive T^+, all others T^-, so that exactly n_plus points end in SO(n).
- * Choosing the first n_plus values of Delta E sorted in descending order is the
- * flat-torus rule at the end of Section 7; equal values are taken in ascending
- * point index (the paper leaves ties open).  dE and selected are nullable.
- * Returns -1 on bad arguments, -2 when a Delta E is not finite. */
+ * dE and selected are nullable.  Returns -1 on bad arguments, -2 when a Delta E
+ * is not finite. */
 int orc_volume_project(int64_t npts, int n, const double* A, int64_t n_plus, double* B, double* dE,
                        int8_t* selected)
 {
@@ -710,31 +730,25 @@ int orc_volume_project(int64_t npts, int n, const double* A, int64_t n_plus, dou
     const int64_t nn = (int64_t)n * n;
     double* tp = (double*)malloc(sizeof(double) * (size_t)(npts * nn + 1));
     double* tm = (double*)malloc(sizeof(double) * (size_t)(npts * nn + 1));
-    orc_rank_t* rk = (orc_rank_t*)malloc(sizeof(orc_rank_t) * (size_t)(npts + 1));
+    double* de = (double*)malloc(sizeof(double) * (size_t)(npts + 1));
     int8_t* sel = (int8_t*)malloc((size_t)npts + 1);
-    int bad = 0;
-#pragma omp parallel for schedule(static) reduction(| : bad)
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < npts; ++p) {
         double a[16];
         for (int e = 0; e < nn; ++e) a[e] = A[e * npts + p];
-        rk[p].de = orc_vp_point(n, a, tp + p * nn, tm + p * nn);
-        rk[p].idx = p;
-        bad |= !isfinite(rk[p].de);
+        de[p] = orc_vp_point(n, a, tp + p * nn, tm + p * nn);
     }
-    if (!bad) {
-        if (dE)
-            for (int64_t p = 0; p < npts; ++p) dE[p] = rk[p].de;
-        qsort(rk, (size_t)npts, sizeof(orc_rank_t), orc_rank_cmp);
-        memset(sel, 0, (size_t)npts);
-        for (int64_t r = 0; r < n_plus; ++r) sel[rk[r].idx] = 1;
+    int rc = orc_volume_select(npts, de, n_plus, sel);
+    if (rc == 0) {
         for (int64_t p = 0; p < npts; ++p) {
             const double* t = sel[p] ? tp + p * nn : tm + p * nn;
             for (int e = 0; e < nn; ++e) B[e * npts + p] = t[e];
         }
+        if (dE) memcpy(dE, de, sizeof(double) * (size_t)npts);
         if (selected) memcpy(selected, sel, (size_t)npts);
     }
-    free(tp); free(tm); free(rk); free(sel);
-    return bad ? -2 : 0;
+    free(tp); free(tm); free(de); free(sel);
+    return rc;
 }
 
 /* Volume-preserving MBO: Algorithm 1 with step 2 replaced by the projection

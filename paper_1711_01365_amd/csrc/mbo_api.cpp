@@ -123,6 +123,18 @@ struct mbo_plan_s {
     int g_key = -1;
     double g_tol = 0.0;
 
+    // volume-preserving step (allocated on first use): Delta E per point, the
+    // selection state, its histograms and tie counts, points to select
+    void* vde = nullptr;          // [batch][npts], plan precision
+    VpSel* vsel = nullptr;        // [batch]
+    unsigned* vhist = nullptr;    // [batch][1 << SEL_BITS]
+    unsigned* vtcnt = nullptr;    // [batch][chunks]
+    long long* vnplus = nullptr;  // [batch]
+    hipGraphExec_t vexec = nullptr;  // cached graph of mbo_iterate_volume
+    void* vg_A = nullptr;
+    int vg_K = -1;
+    int vg_key = -1;
+
     std::string err;
 };
 
@@ -162,6 +174,11 @@ void drop_graph(mbo_plan_t p)
     p->g_A = nullptr;
     p->g_K = -1;
     p->g_key = -1;
+    if (p->vexec) (void)hipGraphExecDestroy(p->vexec);
+    p->vexec = nullptr;
+    p->vg_A = nullptr;
+    p->vg_K = -1;
+    p->vg_key = -1;
 }
 
 void destroy(mbo_plan_t p)
@@ -200,6 +217,11 @@ void destroy(mbo_plan_t p)
     free_dev(p->nonfinite);
     free_dev(p->delta_bits);
     free_dev(p->stop_iter);
+    free_dev(p->vde);
+    free_dev(p->vsel);
+    free_dev(p->vhist);
+    free_dev(p->vtcnt);
+    free_dev(p->vnplus);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     if (p->cap) (void)hipStreamDestroy(p->cap);
     delete p;
@@ -530,6 +552,35 @@ hipError_t enqueue_forward(mbo_plan_t p, const void* A, int extra_flags, bool wi
     return e;
 }
 
+// E(A_final) into energy slot stop_iter[b] (Z holds the row spectra of the last
+// iterate, A_0 for K = 0), then every energy of the run from its partials.
+hipError_t enqueue_final_energy(mbo_plan_t p, int K, hipStream_t st)
+{
+    hipError_t e;
+    if (p->d == 3) {
+        ColArgs y = col_args(p, p->ypass);
+        if ((e = run_col(p, p->ypass, CM_FORWARD, y, st)) != hipSuccess) return e;
+    }
+    ColArgs h = col_args(p, p->heat);
+    h.K = K;
+    h.slot = -1;
+    h.stop_iter = p->stop_iter;
+    h.epart = p->epart;
+    if ((e = run_col(p, p->heat, CM_ENERGY, h, st)) != hipSuccess) return e;
+    ReduceArgs ra;
+    ra.epart = p->epart;
+    ra.nwg = energy_partials(p);
+    ra.K = K;
+    ra.batch = (int)p->batch;
+    ra.n = p->n;
+    ra.npts = p->npts;
+    ra.tau = p->tau;
+    ra.taus = p->taus_dev;
+    ra.stop_iter = p->stop_iter;
+    ra.energy = p->energy;
+    return launch_reduce(ra, st);
+}
+
 // Enqueue the whole of mbo_iterate on stream st (captured into a graph by the caller).
 hipError_t enqueue_iterate(mbo_plan_t p, void* A, int K, double tol, bool want_energy, hipStream_t st)
 {
@@ -596,31 +647,127 @@ hipError_t enqueue_iterate(mbo_plan_t p, void* A, int K, double tol, bool want_e
         hipEvent_t re = p->timing ? p->ev[4 * (s - 1) + 1] : nullptr;
         if ((e = run_row(p, r, st, rs, re)) != hipSuccess) return e;
     }
-    if (want_energy) {
-        // E(A_final): Z holds the row spectra of the last iterate (A_0 for K = 0)
+    if (want_energy) return enqueue_final_energy(p, K, st);
+    return hipSuccess;
+}
+
+// ---- volume-preserving step (Section 7) -----------------------------------
+
+int64_t sel_chunks(mbo_plan_t p) { return (p->npts + SEL_CHUNK - 1) / SEL_CHUNK; }
+
+// Workspace of the volume-preserving step, allocated on first use.  The
+// histograms start at zero; every selection leaves them at zero.
+mbo_status ensure_volume(mbo_plan_t p)
+{
+    if (p->vnplus) return MBO_OK;  // allocated last
+    const size_t B = (size_t)p->batch;
+    if (!p->vde) HIP_TRY(p, hipMalloc(&p->vde, B * (size_t)p->npts * p->esz));
+    if (!p->vsel) HIP_TRY(p, hipMalloc((void**)&p->vsel, B * sizeof(VpSel)));
+    if (!p->vhist) HIP_TRY(p, hipMalloc((void**)&p->vhist, B * ((size_t)1 << SEL_BITS) * sizeof(unsigned)));
+    if (!p->vtcnt) HIP_TRY(p, hipMalloc((void**)&p->vtcnt, B * (size_t)sel_chunks(p) * sizeof(unsigned)));
+    HIP_TRY(p, launch_fill_u64(reinterpret_cast<unsigned long long*>(p->vhist),
+                               (int64_t)B * ((1 << SEL_BITS) / 2), 0ull, p->stream));
+    RowArgs r = row_args(p);
+    (void)launch_row_vp(p->pk, p->n, r.log2L, r, p->row_grid, p->row_block, p->lds_max, nullptr, true);
+    (void)hipGetLastError();
+    HIP_TRY(p, hipMalloc((void**)&p->vnplus, B * sizeof(long long)));
+    return MBO_OK;
+}
+
+SelArgs sel_args(mbo_plan_t p, const void* dE)
+{
+    SelArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.dE = dE;
+    a.npts = p->npts;
+    a.nplus = reinterpret_cast<const int64_t*>(p->vnplus);
+    a.st = p->vsel;
+    a.hist = p->vhist;
+    a.tcnt = p->vtcnt;
+    a.chunks = sel_chunks(p);
+    return a;
+}
+
+hipError_t run_row_vp(mbo_plan_t p, const RowArgs& a, hipStream_t st)
+{
+    return launch_row_vp(p->pk, p->n, a.log2L, a, p->row_grid, p->row_block, p->row_lds, st);
+}
+
+// Points to select per field, from the host, checked against [0, npts].
+mbo_status upload_nplus(mbo_plan_t p, const int64_t* n_plus)
+{
+    for (int64_t b = 0; b < p->batch; ++b)
+        if (n_plus[b] < 0 || n_plus[b] > p->npts)
+            return fail(p, MBO_ERR_INVALID_ARG, "n_plus[%lld] = %lld is outside [0, %lld]", (long long)b,
+                        (long long)n_plus[b], (long long)p->npts);
+    HIP_TRY(p, hipMemcpyAsync(p->vnplus, n_plus, (size_t)p->batch * sizeof(long long),
+                              hipMemcpyHostToDevice, p->stream));
+    return MBO_OK;
+}
+
+// The volume-preserving step on the real values the row pass loads or the
+// inverse row transform yields (load_flags): Delta E into vde, the selection,
+// then T+ / T- with the extra flags of the applying launch (apply).
+hipError_t enqueue_volume_step(mbo_plan_t p, int load_flags, const void* Ain, void* vde, RowArgs apply,
+                               hipStream_t st)
+{
+    const int fb = p->prec == MBO_F32_F64FALLBACK ? RF_FALLBACK : 0;
+    RowArgs r = row_args(p);
+    r.Ain = Ain;
+    r.vde = vde;
+    r.flags = load_flags | RF_VP_KEY | fb;
+    hipError_t e = run_row_vp(p, r, st);
+    if (e != hipSuccess) return e;
+    if ((e = launch_select(p->pk, sel_args(p, vde), (int)p->batch, st)) != hipSuccess) return e;
+    apply.Ain = Ain;
+    apply.vde = vde;
+    apply.vsel = p->vsel;
+    apply.flags |= load_flags | RF_VP_APPLY | fb;
+    return run_row_vp(p, apply, st);
+}
+
+// Enqueue the whole of mbo_iterate_volume on stream st.  from_a0: the points to
+// select are the points of A_0 with det >= 0 (else vnplus holds them).
+hipError_t enqueue_iterate_volume(mbo_plan_t p, void* A, int K, bool from_a0, bool want_energy, hipStream_t st)
+{
+    const int64_t cs = (int64_t)p->batch * (K > 0 ? K : 1);
+    hipError_t e;
+    if ((e = launch_fill_u64(p->flips, cs, 0ull, st)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(p->fallbacks, cs, 0ull, st)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(p->nonfinite, cs, 0ull, st)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(p->stop_iter, p->batch, K, st)) != hipSuccess) return e;
+    if ((e = enqueue_forward(p, A, RF_SIGN_INIT, false, st)) != hipSuccess) return e;
+    if (from_a0 && (e = launch_count_pos(p->sgn, p->npts, (int)p->batch, p->vnplus, st)) != hipSuccess)
+        return e;
+    for (int s = 1; s <= K; ++s) {
         if (p->d == 3) {
             ColArgs y = col_args(p, p->ypass);
             if ((e = run_col(p, p->ypass, CM_FORWARD, y, st)) != hipSuccess) return e;
         }
         ColArgs h = col_args(p, p->heat);
+        h.iter = s;
         h.K = K;
-        h.slot = -1;
         h.stop_iter = p->stop_iter;
-        h.epart = p->epart;
-        if ((e = run_col(p, p->heat, CM_ENERGY, h, st)) != hipSuccess) return e;
-        ReduceArgs ra;
-        ra.epart = p->epart;
-        ra.nwg = energy_partials(p);
-        ra.K = K;
-        ra.batch = (int)p->batch;
-        ra.n = p->n;
-        ra.npts = p->npts;
-        ra.tau = p->tau;
-        ra.taus = p->taus_dev;
-        ra.stop_iter = p->stop_iter;
-        ra.energy = p->energy;
-        if ((e = launch_reduce(ra, st)) != hipSuccess) return e;
+        h.slot = s - 1;
+        h.epart = want_energy ? p->epart : nullptr;
+        if ((e = run_col(p, p->heat, CM_HEAT, h, st)) != hipSuccess) return e;
+        if (p->d == 3) {
+            ColArgs y = col_args(p, p->ypass);
+            if ((e = run_col(p, p->ypass, CM_INVERSE, y, st)) != hipSuccess) return e;
+        }
+        RowArgs r = row_args(p);
+        r.Aout = A;
+        r.iter = s;
+        r.K = K;
+        r.flips = p->flips;
+        r.fallbacks = p->fallbacks;
+        r.nonfinite = p->nonfinite;
+        r.flags = RF_SIGN;
+        if (s < K || want_energy) r.flags |= RF_FORWARD;
+        if (s == K) r.flags |= RF_STORE_REAL;
+        if ((e = enqueue_volume_step(p, RF_INVERSE, nullptr, p->vde, r, st)) != hipSuccess) return e;
     }
+    if (want_energy) return enqueue_final_energy(p, K, st);
     return hipSuccess;
 }
 
@@ -1416,6 +1563,106 @@ mbo_status mbo_iterate(mbo_plan_t p, void* A, int max_iter, double tol, int* ite
                               &bad)) != MBO_OK) {
         return s;
     }
+    if (bad) return fail(p, MBO_ERR_NONFINITE, "%llu projections met NaN/Inf input", bad);
+    return MBO_OK;
+}
+
+mbo_status mbo_volume_select(mbo_plan_t p, const void* dE, const int64_t* n_plus, uint8_t* selected)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (p->group) return fail(p, MBO_ERR_UNSUPPORTED, "not available for a batched plan");
+    if (!dE || !n_plus || !selected) return fail(p, MBO_ERR_INVALID_ARG, "dE / n_plus / selected is NULL");
+    HIP_TRY(p, hipSetDevice(p->device));
+    mbo_status s;
+    if ((s = ensure_volume(p)) != MBO_OK) return s;
+    if ((s = upload_nplus(p, n_plus)) != MBO_OK) return s;
+    SelArgs a = sel_args(p, dE);
+    a.mask = selected;
+    HIP_TRY(p, launch_select(p->pk, a, (int)p->batch, p->stream));
+    HIP_TRY(p, launch_sel_mark(p->pk, a, (int)p->batch, p->stream));
+    return MBO_OK;
+}
+
+mbo_status mbo_project_volume(mbo_plan_t p, const void* A_in, void* A_out, const int64_t* n_plus, void* dE)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (p->group) return fail(p, MBO_ERR_UNSUPPORTED, "not available for a batched plan");
+    if (!A_in || !A_out || !n_plus) return fail(p, MBO_ERR_INVALID_ARG, "A_in / A_out / n_plus is NULL");
+    HIP_TRY(p, hipSetDevice(p->device));
+    mbo_status s;
+    if ((s = ensure_logs(p, 1)) != MBO_OK) return s;
+    if ((s = ensure_volume(p)) != MBO_OK) return s;
+    if ((s = upload_nplus(p, n_plus)) != MBO_OK) return s;
+    HIP_TRY(p, launch_fill_u64(p->nonfinite, p->batch, 0ull, p->stream));
+    HIP_TRY(p, launch_fill_u64(p->fallbacks, p->batch, 0ull, p->stream));
+    RowArgs r = row_args(p);
+    r.Aout = A_out;
+    r.iter = 1;
+    r.K = 1;
+    r.nonfinite = p->nonfinite;
+    r.fallbacks = p->fallbacks;
+    r.flags = RF_STORE_REAL;
+    HIP_TRY(p, enqueue_volume_step(p, RF_LOAD_REAL, A_in, dE ? dE : p->vde, r, p->stream));
+    std::vector<unsigned long long> h((size_t)p->batch);
+    HIP_TRY(p, hipMemcpyAsync(h.data(), p->nonfinite, h.size() * 8, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    unsigned long long bad = 0;
+    for (unsigned long long v : h) bad += v;
+    if (bad) return fail(p, MBO_ERR_NONFINITE, "%llu points with NaN/Inf input", bad);
+    return MBO_OK;
+}
+
+mbo_status mbo_iterate_volume(mbo_plan_t p, void* A, int max_iter, const int64_t* n_plus, int64_t* n_plus_used,
+                              double* energy, int64_t* flips, int64_t* fallbacks)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (p->group) return fail(p, MBO_ERR_UNSUPPORTED, "not available for a batched plan");
+    if (!A) return fail(p, MBO_ERR_INVALID_ARG, "A is NULL");
+    if (max_iter < 0) return fail(p, MBO_ERR_INVALID_ARG, "max_iter < 0");
+    HIP_TRY(p, hipSetDevice(p->device));
+    const int K = max_iter;
+    const bool want_energy = energy != nullptr;
+    const bool from_a0 = n_plus == nullptr;
+    mbo_status s;
+    if ((s = ensure_logs(p, K)) != MBO_OK) return s;
+    if ((s = ensure_volume(p)) != MBO_OK) return s;
+    if (!from_a0 && (s = upload_nplus(p, n_plus)) != MBO_OK) return s;
+    const int key = (want_energy ? 1 : 0) | (from_a0 ? 2 : 0);
+    if (use_graphs()) {
+        if (!(p->vexec && p->vg_A == A && p->vg_K == K && p->vg_key == key)) {
+            if (p->vexec) (void)hipGraphExecDestroy(p->vexec);
+            p->vexec = nullptr;
+            hipGraph_t g = nullptr;
+            HIP_TRY(p, hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+            hipError_t e = enqueue_iterate_volume(p, A, K, from_a0, want_energy, p->cap);
+            hipError_t e2 = hipStreamEndCapture(p->cap, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return fail(p, MBO_ERR_HIP, "graph capture failed: %s",
+                            hipGetErrorString(e != hipSuccess ? e : e2));
+            }
+            hipError_t e3 = hipGraphInstantiate(&p->vexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e3 != hipSuccess) {
+                p->vexec = nullptr;
+                return fail(p, MBO_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e3));
+            }
+            p->vg_A = A;
+            p->vg_K = K;
+            p->vg_key = key;
+        }
+        HIP_TRY(p, hipGraphLaunch(p->vexec, p->stream));
+    } else {
+        HIP_TRY(p, enqueue_iterate_volume(p, A, K, from_a0, want_energy, p->stream));
+    }
+    std::vector<long long> used((size_t)p->batch);
+    HIP_TRY(p, hipMemcpyAsync(used.data(), p->vnplus, used.size() * sizeof(long long), hipMemcpyDeviceToHost,
+                              p->stream));
+    unsigned long long bad = 0;
+    if ((s = read_logs(p, K, 0.0, p->stream, nullptr, energy, flips, nullptr, fallbacks, nullptr, &bad)) != MBO_OK)
+        return s;
+    if (n_plus_used)
+        for (int64_t b = 0; b < p->batch; ++b) n_plus_used[b] = (int64_t)used[(size_t)b];
     if (bad) return fail(p, MBO_ERR_NONFINITE, "%llu projections met NaN/Inf input", bad);
     return MBO_OK;
 }

@@ -20,6 +20,28 @@ enum RowFlags : int {
     RF_FALLBACK = 1 << 8,    // float plan: re-project small-sigma points in double
     RF_CHECK_STOP = 1 << 9,  // return when this field already stopped
     RF_DOT = 1 << 10,        // per-workgroup partials of <G, values after the inverse FFT>
+    RF_VP_KEY = 1 << 11,     // volume-preserving step: Delta E of the loaded values into vde[]
+    RF_VP_APPLY = 1 << 12,   // volume-preserving step: T+ / T- as the selection vsel[] says
+};
+
+// Selection of the n_plus points with the largest Delta E of a field (the
+// volume-preserving step), found by a radix search over order-preserving keys
+// of Delta E: the key kstar of the n_plus-th largest value, and among the
+// points whose key equals kstar, those up to index istar.
+enum VpMode : int {
+    VS_SEARCH = 0,     // digits of kstar still being found
+    VS_NONE = 1,       // n_plus = 0
+    VS_ALL = 2,        // n_plus = all points
+    VS_TIES_ALL = 3,   // selected: key >= kstar
+    VS_TIES_PART = 4,  // selected: key > kstar, or key == kstar and index <= istar
+};
+struct VpSel {
+    unsigned long long kstar;  // while searching: the digits found so far
+    long long need;            // points still to select among those matching kstar's digits
+    long long ties;            // points whose key matches kstar's digits found so far
+    long long istar;
+    int mode;
+    int pad;
 };
 
 struct RowArgs {
@@ -46,6 +68,8 @@ struct RowArgs {
     double* dpart;           // RF_DOT: partials [batch][gridDim.x]
     const int64_t* foff;     // nullable: element offset of field b in Ain / Aout / Gdot
                              // (default b * n*n * npts)
+    void* vde;               // RF_VP_KEY / RF_VP_APPLY: Delta E per point [batch][npts]
+    const VpSel* vsel;       // RF_VP_APPLY: finished selection of each field [batch]
 };
 
 // Element offset of field b of a real-field buffer.
@@ -155,6 +179,30 @@ hipError_t launch_fill_uniform(int prec, void* p, int64_t count, uint64_t seed, 
 hipError_t launch_sum_rows(const double* part, int64_t m, int batch, double* out, hipStream_t st,
                            bool accumulate = false);
 
+// Radix selection of the volume-preserving step over the Delta E values dE
+// (plan precision) of each field; keys are taken SEL_BITS bits at a time from
+// the top, the histograms of a pass built per chunk of SEL_CHUNK points.
+constexpr int SEL_CHUNK = 4096;
+constexpr int SEL_BITS = 11;
+struct SelArgs {
+    const void* dE;          // [batch][npts]
+    int64_t npts;
+    const int64_t* nplus;    // [batch] points to select per field
+    VpSel* st;               // [batch]
+    unsigned* hist;          // [batch][1 << SEL_BITS], zero between passes
+    unsigned* tcnt;          // [batch][chunks] points per chunk whose key is kstar
+    int64_t chunks;          // ceil(npts / SEL_CHUNK)
+    uint8_t* mask;           // launch_sel_mark: 1 = selected [batch][npts]
+};
+hipError_t launch_select(int prec, const SelArgs& a, int batch, hipStream_t st);
+hipError_t launch_sel_mark(int prec, const SelArgs& a, int batch, hipStream_t st);
+// out[b] = number of points p with sgn[b][p] > 0 (out is overwritten)
+hipError_t launch_count_pos(const int8_t* sgn, int64_t npts, int batch, long long* out,
+                            hipStream_t st);
+// Row pass of the volume-preserving step (flags RF_VP_KEY / RF_VP_APPLY)
+hipError_t launch_row_vp(int prec, int n, int log2L, const RowArgs& a, dim3 grid, dim3 block,
+                         size_t lds, hipStream_t st, bool prepare = false);
+
 // per-translation-unit launchers behind launch_row / launch_col
 hipError_t launch_row_f32(int n, int log2L, const RowArgs& a, dim3 g, dim3 b, size_t lds,
                           hipStream_t st, bool prepare, hipEvent_t ev0, hipEvent_t ev1);
@@ -164,5 +212,9 @@ hipError_t launch_col_f32(int mode, int log2L, const ColArgs& a, dim3 g, dim3 b,
                           hipStream_t st, bool prepare, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_col_f64(int mode, int log2L, const ColArgs& a, dim3 g, dim3 b, size_t lds,
                           hipStream_t st, bool prepare, hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_row_vp_f32(int n, int log2L, const RowArgs& a, dim3 g, dim3 b, size_t lds,
+                             hipStream_t st, bool prepare);
+hipError_t launch_row_vp_f64(int n, int log2L, const RowArgs& a, dim3 g, dim3 b, size_t lds,
+                             hipStream_t st, bool prepare);
 
 }  // namespace mbo

@@ -18,6 +18,7 @@
 
 #include "mbo_device.hpp"
 #include "mbo_internal.hpp"
+#include "mbo_volume.hpp"
 
 namespace mbo {
 
@@ -128,11 +129,16 @@ __device__ __forceinline__ void line_stage(typename cx<T>::type* zline, T* lr, T
 // Waves per SIMD the row pass is compiled for: float rows of up to 512 points
 // and n <= 3 are held to 128 VGPRs, so that two 512-thread workgroups share a
 // compute unit.
-template <typename T, int n, int LOG2L>
-constexpr int row_waves_per_simd() { return (sizeof(T) == 4 && n <= 3 && LOG2L <= 9) ? 4 : 1; }
+// The volume-preserving instance (VP) evaluates both candidates of a point and
+// is not held.
+template <typename T, int n, int LOG2L, bool VP = false>
+constexpr int row_waves_per_simd() { return (!VP && sizeof(T) == 4 && n <= 3 && LOG2L <= 9) ? 4 : 1; }
 
-template <typename T, int n, int LOG2L>
-__global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_pass(const RowArgs a)
+// VP = false: Algorithm 1 (flags RF_PROJECT ...); VP = true: the volume-
+// preserving step of Section 7 in two launches, RF_VP_KEY (Delta E of every
+// point) and, after the selection, RF_VP_APPLY (T+ or T- per point).
+template <typename T, int n, int LOG2L, bool VP = false>
+__global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L, VP>())) row_pass(const RowArgs a)
 {
     constexpr int NN = n * n;
     constexpr int PL = (NN + 1) / 2;
@@ -141,7 +147,6 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
     constexpr int Tn = F::Tn;
     typedef typename cx<T>::type C;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ unsigned long long red_u[64];
     __shared__ double red_d[64];
 
     const int flags = a.flags;
@@ -164,7 +169,7 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
 
     // fallback queue of phase 2 (see there); its counter is cleared before the
     // first workgroup barrier
-    constexpr bool DEFER = sizeof(T) == 4 && n >= 3;
+    constexpr bool DEFER = !VP && sizeof(T) == 4 && n >= 3;
     constexpr int QCAP = DEFER ? row_fb_queue_len(LOG2L) : 1;
     constexpr int SCAP = DEFER ? ROW_FB_STASH : 1;
     __shared__ unsigned short fq[QCAP];
@@ -278,7 +283,7 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
     // loop nor runs once per wave that holds such a point.
     unsigned long long nflip = 0, nfb = 0, nbad = 0;
     double dmax = 0.0, dacc = 0.0;
-    if (flags & (RF_PROJECT | RF_SIGN_INIT | RF_STORE_REAL | RF_DOT)) {
+    if (flags & (RF_PROJECT | RF_SIGN_INIT | RF_STORE_REAL | RF_DOT | RF_VP_KEY | RF_VP_APPLY)) {
         T* Aout = reinterpret_cast<T*>(a.Aout) + field_base(a.foff, b, NN * npts);
         int8_t* sgn = a.sgn + (size_t)b * npts;
         const bool defer = DEFER && (flags & RF_PROJECT) && (flags & RF_FALLBACK);
@@ -327,7 +332,29 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
 #pragma unroll
                 for (int k = 0; k < NN; ++k) dacc += (double)Gd[(int64_t)k * npts + x] * (double)av[k];
             }
-            if (flags & RF_PROJECT) {
+            if constexpr (VP) {
+                // Section 7: both candidates and Delta E (recomputed identically
+                // by the two launches); the keying launch stores Delta E, the
+                // applying one takes T+ for the selected points and T- elsewhere
+                if (flags & (RF_VP_KEY | RF_VP_APPLY)) {
+                    T tp[NN], tm[NN], de;
+                    const bool fb = vp_point<T, n>(av, tp, tm, de, (flags & RF_FALLBACK) != 0, a.sigma_fb);
+                    T* vde = reinterpret_cast<T*>(a.vde) + (size_t)b * npts;
+                    if (flags & RF_VP_KEY) vde[x] = de;
+                    if (flags & RF_VP_APPLY) {
+                        nbad += all_finite<T, NN>(av) ? 0ull : 1ull;
+                        nfb += fb ? 1ull : 0ull;
+                        const bool in = vp_member(a.vsel[b], vp_key(vde[x]), x);
+                        T qv[NN];
+#pragma unroll
+                        for (int k = 0; k < NN; ++k) qv[k] = in ? tp[k] : tm[k];
+                        finish(x, lrr, lir, qv, in ? 1 : -1, s_old);
+#pragma unroll
+                        for (int k = 0; k < NN; ++k) av[k] = qv[k];
+                    }
+                }
+            }
+            if (!VP && (flags & RF_PROJECT)) {
                 nbad += all_finite<T, NN>(av) ? 0ull : 1ull;
                 T qv[NN];
                 int ds;
@@ -459,7 +486,7 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L>())) row_
         dacc = block_reduce<OpSum>(dacc, red_d);
         if (tid == 0) a.dpart[(int64_t)b * gridDim.x + blockIdx.x] = dacc;
     }
-    if (flags & RF_PROJECT) {
+    if (flags & (RF_PROJECT | RF_VP_APPLY)) {
         // The three counts of a workgroup are below 2^21 each and travel packed;
         // each wave adds its sums to the workgroup's LDS counters, and the last
         // wave to finish (the release/acquire on the done counter orders every

@@ -28,8 +28,8 @@ _lib = None
 EXPORTS = ("mbo_plan", "mbo_plan_destroy", "mbo_plan_set_tau", "mbo_plan_set_stream",
            "mbo_plan_set_timing", "mbo_last_timing", "mbo_diffuse", "mbo_project", "mbo_iterate",
            "mbo_energy", "mbo_project_vjp", "mbo_diffuse_dtau", "mbo_plan_batched", "mbo_plan_tuning",
-           "mbo_plan_autotune", "mbo_step", "mbo_step_vjp",
-           "mbo_status_string", "mbo_last_error")
+           "mbo_plan_autotune", "mbo_step", "mbo_step_vjp", "mbo_volume_select",
+           "mbo_project_volume", "mbo_iterate_volume", "mbo_status_string", "mbo_last_error")
 
 
 class FieldDesc(ctypes.Structure):
@@ -73,6 +73,9 @@ def load(path: str = LIB_PATH):
     lib.mbo_plan_autotune.argtypes = [vp]
     lib.mbo_step.argtypes = [vp, vp, vp]
     lib.mbo_step_vjp.argtypes = [vp, vp, vp, vp]
+    lib.mbo_volume_select.argtypes = [vp, vp, i64p, vp]
+    lib.mbo_project_volume.argtypes = [vp, vp, vp, i64p, vp]
+    lib.mbo_iterate_volume.argtypes = [vp, vp, ctypes.c_int, i64p, i64p, dp, i64p, i64p]
     for f in EXPORTS:
         if f not in ("mbo_status_string", "mbo_last_error"):
             getattr(lib, f).restype = ctypes.c_int
@@ -246,6 +249,64 @@ class Plan:
         out = {"iters": it}
         if logs:
             out.update(energy=en, flips=fl[:, :K], delta=dl[:, :K], fallbacks=fb[:, :K])
+        return out
+
+    # -- volume-preserving MBO (Section 7) -------------------------------------
+    def _nplus(self, n_plus):
+        v = np.ascontiguousarray(np.broadcast_to(np.asarray(n_plus, dtype=np.int64), (self.batch,)))
+        return v, v.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+    def volume_select(self, dE, n_plus):
+        """uint8 mask (batch, *grid): the n_plus largest dE per field (ties by index)."""
+        import torch
+        if not isinstance(dE, torch.Tensor) or not dE.is_cuda or dE.dtype != self.dtype \
+                or not dE.is_contiguous() or dE.numel() != self.batch * int(np.prod(self.grid)):
+            raise ValueError("dE must be a contiguous %s device tensor of batch * prod(grid) values"
+                             % self.dtype)
+        mask = torch.empty((self.batch,) + self.grid, dtype=torch.uint8, device=dE.device)
+        v, vp_ = self._nplus(n_plus)
+        _check(self._lib.mbo_volume_select(self._h, ctypes.c_void_p(dE.data_ptr()), vp_,
+                                           ctypes.c_void_p(mask.data_ptr())), self._h)
+        return mask
+
+    def project_volume(self, A_in, n_plus, A_out=None, want_dE: bool = False):
+        """Volume-constrained step 2: T+ on the n_plus points of largest Delta E,
+        T- elsewhere.  Returns A_out, or (A_out, dE) with want_dE."""
+        import torch
+        if A_out is None:
+            A_out = torch.empty_like(A_in)
+        dE = torch.empty((self.batch,) + self.grid, dtype=self.dtype, device=A_in.device) \
+            if want_dE else None
+        v, vp_ = self._nplus(n_plus)
+        _check(self._lib.mbo_project_volume(self._h, self._field(A_in, "A_in"),
+                                            self._field(A_out, "A_out"), vp_,
+                                            ctypes.c_void_p(dE.data_ptr()) if dE is not None else None),
+               self._h)
+        return (A_out, dE) if want_dE else A_out
+
+    def iterate_volume(self, A, max_iter: int, n_plus=None, logs: bool = True):
+        """In-place volume-preserving MBO on A.  n_plus None: #{det A_0 >= 0} per field.
+        Returns a dict of numpy logs (per field)."""
+        B, K = self.batch, int(max_iter)
+        used = np.zeros(B, dtype=np.int64)
+        en = np.zeros((B, K + 1)) if logs else None
+        fl = np.zeros((B, max(K, 1)), dtype=np.int64) if logs else None
+        fb = np.zeros((B, max(K, 1)), dtype=np.int64) if logs else None
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int64)
+
+        def ptr(x, t):
+            return None if x is None else x.ctypes.data_as(t)
+
+        npv = None
+        if n_plus is not None:
+            npv, _ = self._nplus(n_plus)
+        rc = self._lib.mbo_iterate_volume(self._h, self._field(A), K, ptr(npv, ip), ptr(used, ip),
+                                          ptr(en, dp), ptr(fl, ip), ptr(fb, ip))
+        _check(rc, self._h)
+        out = {"n_plus": used}
+        if logs:
+            out.update(energy=en, flips=fl[:, :K], fallbacks=fb[:, :K])
         return out
 
     def autotune(self):

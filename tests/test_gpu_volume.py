@@ -1,0 +1,335 @@
+"""GPU parity of the volume-preserving MBO step (Section 7) through the C ABI.
+
+Bars:
+  * selection on given Delta E values: bit-exact against the oracle's rule (the
+    n_plus largest, ties by ascending index), in FP64 and FP32;
+  * Delta E: FP64 <= 1e-12, FP32 <= 1e-5 (times the field's scale);
+  * the number of points assigned to SO(n) is n_plus exactly, and outside a band
+    of the Delta E tolerance around the threshold (where rounding may decide)
+    the same points are selected;
+  * values: each point's result equals the oracle's T+ or T- of the same input
+    (the one the selection picked) to 1e-12 (FP64) or 1e-5 (FP32) where that
+    candidate is well conditioned (sigma_{n-1} - sigma_n >= 1e-3, or >= 0.1 in
+    FP32: U D_n V^t moves by about |dA| / (sigma_{n-1} - sigma_n)); elsewhere
+    the result must still be orthogonal, of the selected determinant, and at the
+    distance Lemma 7.1 gives;
+  * iterates: FP64 trajectories equal the oracle's to 1e-10 on inputs whose
+    selection is unambiguous at every step (checked on the oracle's side).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_01365_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*a):
+    print("[gpu-volume]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1711_01365_amd import mbo
+    mbo.load()
+    return torch
+
+
+def dev(torch, A, dtype):
+    return torch.tensor(np.ascontiguousarray(A), dtype=dtype, device="cuda")
+
+
+def pm(A):
+    n = A.shape[0]
+    return np.moveaxis(A.reshape(n, n, -1), -1, 0)
+
+
+def candidates(A):
+    P = int(np.prod(A.shape[2:]))
+    Tp, dE, _ = oracle.volume_project(A, P)
+    Tm, _, _ = oracle.volume_project(A, 0)
+    return Tp, Tm, dE
+
+
+def check_step(A, B, dE_gpu, n_plus, vtol, dtol, gmin, otol):
+    """One volume-constrained step: A the input (n, n, *grid) in float64, B and
+    dE_gpu the GPU's result (float64 copies)."""
+    n = A.shape[0]
+    P = int(np.prod(A.shape[2:]))
+    Tp, Tm, dE_o = candidates(A)
+    scale = max(1.0, float(np.abs(A).max()))
+    if dE_gpu is not None:
+        err = float(np.abs(dE_gpu.ravel() - dE_o.ravel()).max())
+        assert err <= dtol * scale, "Delta E differs by %g" % err
+    Bp = pm(B)
+    det = np.linalg.det(Bp)
+    sel = det > 0
+    assert int(sel.sum()) == n_plus
+    d = dE_o.ravel()
+    if 0 < n_plus < P:
+        srt = np.sort(d)[::-1]
+        hi, lo = srt[n_plus - 1], srt[n_plus]
+        amb = (d >= lo - 2 * dtol * scale) & (d <= hi + 2 * dtol * scale)
+        sel_o = oracle.volume_select(d, n_plus).astype(bool)
+        assert np.array_equal(sel[~amb], sel_o[~amb])
+    want = np.where(sel[:, None, None], pm(Tp), pm(Tm))
+    s = np.linalg.svd(pm(A), compute_uv=False)
+    gap = s[:, -2] - s[:, -1] if n > 1 else np.full(P, np.inf)
+    well = gap >= gmin
+    err = np.abs(Bp - want).max(axis=(1, 2))
+    if well.any():
+        assert float(err[well].max()) <= vtol, "value error %g on well-conditioned points" % err[well].max()
+    # every point: orthogonal, the selected determinant, Lemma 7.1's distance
+    orth = np.abs(np.einsum("pki,pkj->pij", Bp, Bp) - np.eye(n)).max()
+    assert orth <= otol
+    assert np.all(np.abs(np.abs(det) - 1.0) <= otol * n)
+    dA = np.sign(np.linalg.det(pm(A)))
+    near = ((s - 1.0) ** 2).sum(axis=1)
+    dist = near + np.where((dA > 0) == sel, 0.0, 4.0 * s[:, -1])
+    got = ((Bp - pm(A)) ** 2).sum(axis=(1, 2))
+    assert float(np.abs(got - dist).max()) <= 50 * vtol * (1.0 + float(dist.max()))
+    return err
+
+
+# ---------------------------------------------------------------------------
+# selection alone: bit-exact
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("grid", [(8, 8), (64, 64), (128, 64), (8, 8, 16), (512, 512)])
+def test_select_bit_exact(torch_cuda, prec, grid):
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    P = int(np.prod(grid))
+    note("select", prec, grid)
+    rng = np.random.default_rng(900 + P % 97)
+    fields = [rng.integers(-3, 4, P).astype(np.float64),          # many ties
+              rng.standard_normal(P),                               # distinct values
+              np.where(rng.random(P) < 0.5, 0.0, -0.0),             # +0 / -0 only
+              np.full(P, 0.25)]                                     # all equal
+    dt = torch.float64 if prec == "f64" else torch.float32
+    pr = mbo.F64 if prec == "f64" else mbo.F32
+    plan = mbo.Plan(grid, 2, 1e-3, precision=pr, batch=len(fields))
+    vals = np.stack(fields).reshape((len(fields),) + grid)
+    if prec == "f32":
+        vals = vals.astype(np.float32).astype(np.float64)
+    for n_plus in ([0, 1, P // 3, P], [P // 2 + 7, P - 1, 5, 12345 % P],
+                   [P, 0, P // 2, P - 1]):
+        mask = plan.volume_select(dev(torch, vals, dt), n_plus).cpu().numpy()
+        for b in range(len(fields)):
+            want = oracle.volume_select(vals[b], n_plus[b])
+            assert np.array_equal(mask[b].astype(np.int8), want), (b, n_plus[b])
+    plan.close()
+
+
+def test_select_rejects_bad_counts(torch_cuda):
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    plan = mbo.Plan((16, 16), 2, 1e-3, precision=mbo.F64)
+    dE = torch.zeros((1, 16, 16), dtype=torch.float64, device="cuda")
+    for bad in (-1, 257):
+        with pytest.raises(mbo.MboError) as ei:
+            plan.volume_select(dE, bad)
+        assert ei.value.status == 1
+    plan.close()
+
+
+# ---------------------------------------------------------------------------
+# one volume-constrained step on a given field
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+@pytest.mark.parametrize("grid", [(32, 32), (16, 64), (8, 8, 16), (8, 1024)])
+def test_project_volume_f64(torch_cuda, n, grid):
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    P = int(np.prod(grid))
+    note("project_volume f64 n=%d" % n, grid)
+    A = np.stack([inputs.uniform_field(n, grid, 910 + n), inputs.normal_field(n, grid, 920 + n)])
+    plan = mbo.Plan(grid, n, 1e-3, precision=mbo.F64, batch=2)
+    for n_plus in ([0, P], [P // 3, P // 2 + 7], [P, 1]):
+        B, dE = plan.project_volume(dev(torch, A, torch.float64), n_plus, want_dE=True)
+        B, dE = B.cpu().numpy(), dE.cpu().numpy()
+        for b in range(2):
+            check_step(A[b], B[b], dE[b], n_plus[b], vtol=1e-11, dtol=1e-12, gmin=1e-3, otol=1e-12)
+    plan.close()
+
+
+def test_project_volume_aliasing_and_constant_field(torch_cuda):
+    """A_out = A_in; a constant field ties every point: the first n_plus win."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    grid = (64, 64)
+    P = 4096
+    rng = np.random.default_rng(930)
+    while True:
+        a = rng.standard_normal((3, 3))
+        s = np.linalg.svd(a, compute_uv=False)
+        if s[1] - s[2] > 0.2:
+            break
+    A = np.broadcast_to(a[:, :, None, None], (3, 3) + grid).copy()
+    plan = mbo.Plan(grid, 3, 1e-3, precision=mbo.F64)
+    X = dev(torch, A, torch.float64)
+    plan.project_volume(X, 1234, A_out=X)
+    B = X.cpu().numpy()
+    det = np.linalg.det(pm(B))
+    assert np.array_equal(np.flatnonzero(det > 0), np.arange(1234))
+    Tp, Tm, _ = candidates(A[:, :, :1, :1])
+    assert np.abs(pm(B)[:1234] - Tp[:, :, 0, 0]).max() <= 1e-12
+    assert np.abs(pm(B)[1234:] - Tm[:, :, 0, 0]).max() <= 1e-12
+    plan.close()
+    # n = 1 with ties: exactly +-1 on the oracle's points
+    v = np.round(rng.uniform(-1, 1, grid), 1).reshape(1, 1, *grid)
+    plan = mbo.Plan(grid, 1, 1e-3, precision=mbo.F64)
+    B = plan.project_volume(dev(torch, v, torch.float64), 2000).cpu().numpy()
+    Bo, _, _ = oracle.volume_project(v, 2000)
+    assert np.array_equal(B.reshape(v.shape), Bo)
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f32fb"])
+@pytest.mark.parametrize("n", [2, 3])
+def test_project_volume_fp32(torch_cuda, prec, n):
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    grid = (128, 64)
+    P = 8192
+    note("project_volume", prec, "n=%d" % n)
+    A = inputs.uniform_field(n, grid, 940 + n)
+    A32 = A.astype(np.float32).astype(np.float64)
+    pr = mbo.F32 if prec == "f32" else mbo.F32_F64FALLBACK
+    plan = mbo.Plan(grid, n, 1e-3, precision=pr)
+    for n_plus in (P // 4, P // 2, 3 * P // 4):
+        B, dE = plan.project_volume(dev(torch, A32, torch.float32), n_plus, want_dE=True)
+        check_step(A32, B.cpu().double().numpy(), dE.cpu().double().numpy(), n_plus,
+                   vtol=1e-5, dtol=1e-5, gmin=0.2, otol=2e-6)
+    plan.close()
+
+
+# ---------------------------------------------------------------------------
+# iterations
+# ---------------------------------------------------------------------------
+def oracle_trajectory(A0, tau, K, n_plus):
+    """Steps of the oracle with the Delta E margin at the threshold of each step."""
+    A = A0.copy()
+    out, margins = [], []
+    for _ in range(K):
+        At, _ = oracle.heat(A, tau, A.ndim - 2)
+        A, dE, _ = oracle.volume_project(At, n_plus)
+        srt = np.sort(dE.ravel())[::-1]
+        if 0 < n_plus < srt.size:
+            margins.append(srt[n_plus - 1] - srt[n_plus])
+        out.append(A.copy())
+    return out, (min(margins) if margins else np.inf)
+
+
+@pytest.mark.parametrize("n,grid,given", [(2, (32, 32), False), (3, (32, 32), True),
+                                          (3, (16, 64), False), (3, (8, 8, 16), False),
+                                          (4, (16, 16), True)])
+def test_iterate_volume_f64_matches_oracle(torch_cuda, n, grid, given):
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    K, tau = 10, 2e-3
+    note("iterate_volume f64 n=%d" % n, grid, "given" if given else "from A0")
+    A0 = inputs.haar_field(n, grid, 950 + n)
+    P = int(np.prod(grid))
+    n0 = int((oracle.det_sign(A0) > 0).sum())
+    n_plus = P // 3 if given else n0
+    traj, margin = oracle_trajectory(A0, tau, K, n_plus)
+    assert margin > 1e-8, "input has a near-tie at the threshold (margin %g)" % margin
+    ref = oracle.iterate_volume(A0, tau, K, n_plus)
+    assert np.abs(ref["A"] - traj[-1]).max() == 0.0
+    plan = mbo.Plan(grid, n, tau, precision=mbo.F64)
+    X = dev(torch, A0, torch.float64)
+    logs = plan.iterate_volume(X, K, n_plus if given else None)
+    assert int(logs["n_plus"][0]) == n_plus
+    err = float(np.abs(X.cpu().numpy().reshape(A0.shape) - ref["A"]).max())
+    note("max |A - A_oracle| = %.3g" % err)
+    assert err <= 1e-10
+    E = logs["energy"][0]
+    assert np.abs(E - ref["energy"]).max() <= 1e-9 * np.abs(ref["energy"]).max()
+    # flips: det sign changes between consecutive iterates (A_0 with sgn(0) = +1)
+    prev = oracle.det_sign(A0)
+    for s in range(K):
+        cur = oracle.det_sign(traj[s])
+        assert logs["flips"][0][s] == int((cur != prev).sum())
+        prev = cur
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32fb"])
+def test_iterate_volume_star_defect(torch_cuda, prec):
+    """The paper's example at 64^2: the SO(2) volume stays fixed and E^tau does
+    not increase (Proposition 7.3); the energies follow the oracle's."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    N, K = 64, 40
+    tau = 8.0 / N
+    A0 = inputs.star_defect_field((N, N))
+    n0 = int((oracle.det_sign(A0) > 0).sum())
+    pr, dt = (mbo.F64, torch.float64) if prec == "f64" else (mbo.F32_F64FALLBACK, torch.float32)
+    plan = mbo.Plan((N, N), 2, tau, precision=pr)
+    X = dev(torch, A0, dt)
+    logs = plan.iterate_volume(X, K)
+    assert int(logs["n_plus"][0]) == n0
+    B = X.cpu().double().numpy()
+    assert int((np.linalg.det(pm(B)) > 0).sum()) == n0
+    E = logs["energy"][0]
+    slack = 1e-12 if prec == "f64" else 1e-5
+    assert np.all(np.diff(E) <= slack * np.abs(E[:-1]))
+    ref = oracle.iterate_volume(A0, tau, K)
+    assert np.abs(E - ref["energy"]).max() <= 1e-3 * np.abs(ref["energy"]).max()
+    note(prec, "E_0 %.6g E_K %.6g (oracle %.6g)" % (E[0], E[-1], ref["energy"][-1]))
+    plan.close()
+
+
+def test_iterate_volume_graph_reuse(torch_cuda):
+    """The captured graph is re-used with new n_plus values and gives the same
+    result as a fresh plan."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    grid, n, K, tau = (32, 32), 3, 6, 2e-3
+    A0 = inputs.haar_field(n, grid, 960)
+    plan = mbo.Plan(grid, n, tau, precision=mbo.F64)
+    outs = []
+    for n_plus in (300, 600, 300):
+        X = dev(torch, A0, torch.float64)
+        plan.iterate_volume(X, K, n_plus)
+        outs.append(X.cpu().numpy())
+        assert int((np.linalg.det(pm(outs[-1])) > 0).sum()) == n_plus
+    assert np.array_equal(outs[0], outs[2])
+    fresh = mbo.Plan(grid, n, tau, precision=mbo.F64)
+    X = dev(torch, A0, torch.float64)
+    fresh.iterate_volume(X, K, 600)
+    assert np.array_equal(X.cpu().numpy(), outs[1])
+    plan.close()
+    fresh.close()
+
+
+# ---------------------------------------------------------------------------
+# the measured configurations, one step against the oracle
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("w", ["star_1024", "haar_512"])
+def test_full_size_one_step(torch_cuda, w):
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    wl = inputs.VOLUME_STAR_1024 if w == "star_1024" else inputs.VOLUME_HAAR_512
+    note("full size", wl.name)
+    A0 = wl.field().astype(np.float32).astype(np.float64)
+    P = wl.points
+    n0 = int((oracle.det_sign(A0) > 0).sum())
+    plan = mbo.Plan(wl.grid, wl.n, wl.tau, precision=mbo.F32_F64FALLBACK)
+    plan.autotune()
+    X = dev(torch, A0, torch.float32)
+    logs = plan.iterate_volume(X, 1)
+    assert int(logs["n_plus"][0]) == n0
+    At, _ = oracle.heat(A0, wl.tau, 2)
+    err = check_step(At, X.cpu().double().numpy().reshape(A0.shape), None, n0,
+                     vtol=1e-5, dtol=2e-6, gmin=0.2, otol=2e-6)
+    note("one-step max error on well-conditioned points %.3g" % float(err.max()))
+    plan.close()
+    assert P == A0[0, 0].size

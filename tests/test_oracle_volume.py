@@ -117,6 +117,19 @@ def test_n1_is_volume_constrained_thresholding():
         assert np.array_equal(dE, 2.0 * a)
 
 
+def test_volume_select_matches_python_sort():
+    rng = np.random.default_rng(745)
+    for vals in (rng.integers(-3, 4, 1000).astype(float), rng.standard_normal(999),
+                 np.array([0.0, -0.0, 0.0, -0.0, 1.0, -1.0])):
+        for n_plus in sorted({0, 1, 2, vals.size // 2, vals.size - 1, vals.size}):
+            order = sorted(range(vals.size), key=lambda i: (-vals[i], i))
+            want = np.zeros(vals.size, dtype=np.int8)
+            want[order[:n_plus]] = 1
+            assert np.array_equal(oracle.volume_select(vals, n_plus), want)
+    with pytest.raises(ValueError):
+        oracle.volume_select(np.array([1.0, np.nan]), 1)
+
+
 @pytest.mark.parametrize("n", [2, 3])
 def test_selection_count_and_order(n):
     rng = np.random.default_rng(740 + n)
