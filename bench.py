@@ -25,8 +25,15 @@ workload).  Beside the main line: a 2048^2 bandwidth control (the same
 kernels on a field 16x larger), the 3-D configuration (n = 3, 128^3, 100
 iterations, FP32 + fallback), the batched configuration (64 fields of mixed n,
 grid and tau, 50 iterations in one graph; FP32 autotuned, FP32 with the fixed
-launch rules, FP64) and the gradient of 50 unrolled steps (n = 3, 256^2, FP32 +
-fallback and FP64), forward and backward time.
+launch rules, FP64), the volume-preserving method of Section 7 (n = 3, 512^2
+Haar, 200 iterations; and the paper's example, the star-shaped defect with
+n = 2 on 1024^2, tau = 8 dx, 100 iterations; FP32 + fallback, the SO(n) volume
+of the initial field held fixed) and the gradient of 50 unrolled steps (n = 3,
+256^2, FP32 + fallback and FP64), forward and backward time.
+
+    python bench.py --volume-only [--steps K] [--warmup W]
+
+runs only the two volume-preserving legs (for profiling them).
 
     python bench.py --copy-calibration
 
@@ -184,6 +191,48 @@ def run_3d(steps, warmup):
             "ms_per_run": 1000.0 * sec / steps}
 
 
+def run_volume(w, steps, warmup):
+    """Volume-preserving MBO (Section 7) on workload w, FP32 + FP64 fallback,
+    through its captured graph, n_plus = the SO(n) points of A_0; beside it the
+    plain iteration of the same workload on the same plan."""
+    import numpy as np
+    import torch
+    from paper_1711_01365_amd import mbo
+    A0 = torch.tensor(w.field(), dtype=torch.float32, device="cuda")
+    A = A0.clone()
+    plan = mbo.Plan(w.grid, w.n, w.tau, precision=mbo.F32_F64FALLBACK)
+    plan.autotune()
+
+    def timed(fn):
+        for _ in range(warmup):
+            A.copy_(A0)
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            A.copy_(A0)
+            fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    logs = {}
+
+    def vol():
+        logs.update(plan.iterate_volume(A, w.iters))
+
+    sec = timed(vol)
+    n_plus = int(logs["n_plus"][0])
+    E = logs["energy"][0]
+    sec_plain = timed(lambda: plan.iterate(A, w.iters, logs=False))
+    plan.close()
+    return {"workload": w.name + "_tau%g_%dit_f32_f64fallback" % (w.tau, w.iters),
+            "value": w.points * w.iters * steps / sec, "unit": "point-iterations/s",
+            "us_per_iteration": 1e6 * sec / (steps * w.iters),
+            "plain_mbo_us_per_iteration": 1e6 * sec_plain / (steps * w.iters),
+            "n_plus": n_plus, "energy_first_last": [float(E[0]), float(E[-1])],
+            "energy_nonincreasing": bool(np.all(np.diff(E[1:]) <= 1e-5 * np.abs(E[1:-1])))}
+
+
 def run_adjoint(precision, reps):
     """Gradients of K = 50 unrolled steps (n = 3, 256^2, checkpoint every 10):
     forward and backward wall time of the autograd function."""
@@ -278,8 +327,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the 3-D and adjoint legs (reported beside the main line)")
+                    help="skip the legs reported beside the main line (2048^2 control, 3-D, "
+                         "batched, volume-preserving, adjoint)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--volume-only", action="store_true",
+                    help="only the volume-preserving legs (for profiling them)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -298,6 +350,12 @@ def main():
         return
 
     from paper_1711_01365_amd import inputs, mbo
+    if args.volume_only:
+        for wv in (inputs.VOLUME_HAAR_512, inputs.VOLUME_STAR_1024):
+            r = run_volume(wv, args.steps, args.warmup)
+            log("volume-preserving %s: %.3e point-iter/s, %.1f us/iteration (plain %.1f us)"
+                % (wv.name, r["value"], r["us_per_iteration"], r["plain_mbo_us_per_iteration"]))
+        return
     w = inputs.HAAR_512
     log("workload %s: n=%d grid=%s tau=%g iterations=%d" % (w.name, w.n, w.grid, w.tau, w.iters))
     main_run = run_gpu(w, mbo.F32_F64FALLBACK, args.steps, args.warmup, timing_steps=3)
@@ -355,6 +413,11 @@ def main():
         log("batched 64 fields: f32 tuned %.3e, f32 rules %.3e, f64 tuned %.3e point-iter/s"
             % (out["batched"]["f32_autotuned"]["value"], out["batched"]["f32_fixed_rules"]["value"],
                out["batched"]["f64_autotuned"]["value"]))
+        out["volume_preserving"] = {"n3_512x512_haar": run_volume(inputs.VOLUME_HAAR_512, 3, 1),
+                                    "n2_1024x1024_star": run_volume(inputs.VOLUME_STAR_1024, 3, 1)}
+        for k, r in out["volume_preserving"].items():
+            log("volume-preserving %s: %.3e point-iter/s, %.1f us/iteration (plain %.1f us)"
+                % (k, r["value"], r["us_per_iteration"], r["plain_mbo_us_per_iteration"]))
         out["adjoint"] = {"f32_f64fallback": run_adjoint(mbo.F32_F64FALLBACK, 2),
                           "f64": run_adjoint(mbo.F64, 2)}
         log("adjoint K=50 256^2: fp32+fb fwd %.1f ms bwd %.1f ms, fp64 fwd %.1f ms bwd %.1f ms"

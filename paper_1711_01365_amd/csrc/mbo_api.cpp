@@ -130,6 +130,7 @@ struct mbo_plan_s {
     unsigned* vhist = nullptr;    // [batch][1 << SEL_BITS]
     unsigned* vtcnt = nullptr;    // [batch][chunks]
     long long* vnplus = nullptr;  // [batch]
+    unsigned* vdone = nullptr;    // [batch] finished-workgroup counters of the tie count
     hipGraphExec_t vexec = nullptr;  // cached graph of mbo_iterate_volume
     void* vg_A = nullptr;
     int vg_K = -1;
@@ -222,6 +223,7 @@ void destroy(mbo_plan_t p)
     free_dev(p->vhist);
     free_dev(p->vtcnt);
     free_dev(p->vnplus);
+    free_dev(p->vdone);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     if (p->cap) (void)hipStreamDestroy(p->cap);
     delete p;
@@ -665,8 +667,10 @@ mbo_status ensure_volume(mbo_plan_t p)
     if (!p->vsel) HIP_TRY(p, hipMalloc((void**)&p->vsel, B * sizeof(VpSel)));
     if (!p->vhist) HIP_TRY(p, hipMalloc((void**)&p->vhist, B * ((size_t)1 << SEL_BITS) * sizeof(unsigned)));
     if (!p->vtcnt) HIP_TRY(p, hipMalloc((void**)&p->vtcnt, B * (size_t)sel_chunks(p) * sizeof(unsigned)));
+    if (!p->vdone) HIP_TRY(p, hipMalloc((void**)&p->vdone, B * sizeof(unsigned long long)));
     HIP_TRY(p, launch_fill_u64(reinterpret_cast<unsigned long long*>(p->vhist),
                                (int64_t)B * ((1 << SEL_BITS) / 2), 0ull, p->stream));
+    HIP_TRY(p, launch_fill_u64(reinterpret_cast<unsigned long long*>(p->vdone), (int64_t)B, 0ull, p->stream));
     RowArgs r = row_args(p);
     (void)launch_row_vp(p->pk, p->n, r.log2L, r, p->row_grid, p->row_block, p->lds_max, nullptr, true);
     (void)hipGetLastError();
@@ -685,6 +689,7 @@ SelArgs sel_args(mbo_plan_t p, const void* dE)
     a.hist = p->vhist;
     a.tcnt = p->vtcnt;
     a.chunks = sel_chunks(p);
+    a.done = p->vdone;
     return a;
 }
 

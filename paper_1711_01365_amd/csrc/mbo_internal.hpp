@@ -183,6 +183,7 @@ hipError_t launch_sum_rows(const double* part, int64_t m, int batch, double* out
 // (plan precision) of each field; keys are taken SEL_BITS bits at a time from
 // the top, the histograms of a pass built per chunk of SEL_CHUNK points.
 constexpr int SEL_CHUNK = 4096;
+constexpr int SEL_PER = SEL_CHUNK / 256;  // points per thread of a 256-thread workgroup
 constexpr int SEL_BITS = 11;
 struct SelArgs {
     const void* dE;          // [batch][npts]
@@ -192,6 +193,7 @@ struct SelArgs {
     unsigned* hist;          // [batch][1 << SEL_BITS], zero between passes
     unsigned* tcnt;          // [batch][chunks] points per chunk whose key is kstar
     int64_t chunks;          // ceil(npts / SEL_CHUNK)
+    unsigned* done;          // [batch] workgroups of the tie count finished, zero between uses
     uint8_t* mask;           // launch_sel_mark: 1 = selected [batch][npts]
 };
 hipError_t launch_select(int prec, const SelArgs& a, int batch, hipStream_t st);

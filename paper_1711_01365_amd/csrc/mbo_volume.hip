@@ -6,13 +6,14 @@
 // Radix search over order-preserving keys of Delta E (vp_key), SEL_BITS bits
 // per pass from the top: a pass histograms the next digit of the keys that
 // match the digits found so far (one workgroup per chunk of SEL_CHUNK points,
-// LDS histogram, non-zero bins added to the field's global histogram), and one
-// workgroup per field then finds the digit holding the n_plus-th largest key
-// and clears the histogram.  After the last digit the key kstar is known; when
-// only some of the points with key kstar are selected, per-chunk counts of
-// those points and a walk through the chunk holding the last selected one give
-// its index istar.  Every kernel reads the selection state first and returns
-// at once when its field needs no more work.
+// LDS histogram, non-zero bins added to the field's global
+// histogram), and one workgroup per field then finds the digit holding the
+// n_plus-th largest key and clears the histogram.  After the last digit the
+// key kstar is known; when only some of the points with key kstar are
+// selected, per-chunk counts of those points and a walk through the chunk
+// holding the last selected one give its index istar (sel_tie).  Every kernel
+// reads the selection state first and returns at once when its field needs no
+// more work.
 #include <climits>
 
 #include "mbo_kernels.hpp"
@@ -53,11 +54,18 @@ __global__ void __launch_bounds__(256) sel_hist(const SelArgs a, int shift, int 
     for (int i = threadIdx.x; i < nb; i += blockDim.x) h[i] = 0u;
     __syncthreads();
     const T* v = reinterpret_cast<const T*>(a.dE) + (size_t)b * a.npts;
-    const int64_t x0 = (int64_t)blockIdx.x * SEL_CHUNK;
-    const int64_t x1 = x0 + SEL_CHUNK < a.npts ? x0 + SEL_CHUNK : a.npts;
-    for (int64_t x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
-        const unsigned long long k = vp_key(v[x]);
-        if (top >= KB || (k >> top) == (pre >> top)) atomicAdd(&h[(k >> shift) & (unsigned)(nb - 1)], 1u);
+    const int64_t x0 = (int64_t)blockIdx.x * SEL_CHUNK + threadIdx.x;
+    T val[SEL_PER];
+#pragma unroll
+    for (int k = 0; k < SEL_PER; ++k) {  // every load in flight at once
+        const int64_t x = x0 + (int64_t)k * 256;
+        val[k] = x < a.npts ? v[x] : (T)0;
+    }
+#pragma unroll
+    for (int k = 0; k < SEL_PER; ++k) {
+        const unsigned long long key = vp_key(val[k]);
+        if (x0 + (int64_t)k * 256 < a.npts && (top >= KB || (key >> top) == (pre >> top)))
+            atomicAdd(&h[(key >> shift) & (unsigned)(nb - 1)], 1u);
     }
     __syncthreads();
     unsigned* g = a.hist + (size_t)b * (1 << SEL_BITS);
@@ -130,41 +138,62 @@ __global__ void __launch_bounds__(256) sel_pick(const SelArgs a, int shift, int 
     for (int i = tid; i < nb; i += 256) g[i] = 0u;
 }
 
+// Points whose key is kstar, per chunk; the workgroup of a field that finishes
+// last then finds the chunk holding the need-th of them (in index order) and
+// walks it for that point's index.  The per-chunk counts and the finished-
+// workgroup counter are only touched by device-scope atomics, performed at the
+// device's coherence point for workgroups on every XCD: a workgroup's count is
+// performed once its returned value is in (before the barrier that precedes
+// the counter), and the last workgroup's atomic reads come after the counter
+// told it every other workgroup had counted; no cache write-back is needed.
 template <typename T>
-__global__ void __launch_bounds__(256) sel_tie_count(const SelArgs a)
-{
-    __shared__ long long sh[4];
-    const int b = blockIdx.y;
-    if (a.st[b].mode != VS_TIES_PART) return;
-    const unsigned long long ks = a.st[b].kstar;
-    const T* v = reinterpret_cast<const T*>(a.dE) + (size_t)b * a.npts;
-    const int64_t x0 = (int64_t)blockIdx.x * SEL_CHUNK;
-    const int64_t x1 = x0 + SEL_CHUNK < a.npts ? x0 + SEL_CHUNK : a.npts;
-    long long cnt = 0;
-    for (int64_t x = x0 + threadIdx.x; x < x1; x += blockDim.x) cnt += vp_key(v[x]) == ks ? 1 : 0;
-    long long total;
-    (void)scan256(cnt, sh, total);
-    if (threadIdx.x == 0) a.tcnt[(size_t)b * a.chunks + blockIdx.x] = (unsigned)total;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) sel_tie_pick(const SelArgs a)
+__global__ void __launch_bounds__(256) sel_tie(const SelArgs a)
 {
     __shared__ long long sh[4];
     __shared__ long long s_chunk, s_rank;
-    const int b = blockIdx.x;
+    __shared__ int s_last;
+    const int b = blockIdx.y;
     const int tid = threadIdx.x;
     VpSel* st = a.st + b;
     if (st->mode != VS_TIES_PART) return;
     const unsigned long long ks = st->kstar;
-    const long long need = st->need;  // rank of the last selected tie, from 1
-    // the chunk holding it
-    const unsigned* tc = a.tcnt + (size_t)b * a.chunks;
+    const T* v = reinterpret_cast<const T*>(a.dE) + (size_t)b * a.npts;
+    unsigned* tc = a.tcnt + (size_t)b * a.chunks;
+    {
+        const int64_t x0 = (int64_t)blockIdx.x * SEL_CHUNK + tid;
+        T val[SEL_PER];
+#pragma unroll
+        for (int k = 0; k < SEL_PER; ++k) {
+            const int64_t x = x0 + (int64_t)k * 256;
+            val[k] = x < a.npts ? v[x] : (T)0;
+        }
+        long long cnt = 0;
+#pragma unroll
+        for (int k = 0; k < SEL_PER; ++k) cnt += (x0 + (int64_t)k * 256 < a.npts && vp_key(val[k]) == ks) ? 1 : 0;
+        long long total;
+        (void)scan256(cnt, sh, total);
+        unsigned seen = 0u;
+        if (tid == 0) seen = __hip_atomic_exchange(&tc[blockIdx.x], (unsigned)total, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (seen == 0xffffffffu) s_last = 2;  // consumes the returned value (overwritten below)
+        __syncthreads();
+        if (tid == 0)
+            s_last = __hip_atomic_fetch_add(a.done + b, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                             gridDim.x - 1
+                         ? 1
+                         : 0;
+        __syncthreads();
+        if (s_last != 1) return;  // uniform
+        if (tid == 0) (void)__hip_atomic_exchange(a.done + b, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // the last workgroup: the chunk holding the need-th tie ...
+    const long long need = st->need;
     const int64_t per = (a.chunks + 255) / 256;
     const int64_t c0 = (int64_t)tid * per;
     const int64_t c1 = c0 + per < a.chunks ? c0 + per : a.chunks;
     long long sum = 0;
-    for (int64_t c = c0; c < c1; ++c) sum += tc[c];
+    for (int64_t c = c0; c < c1; ++c)
+        sum += __hip_atomic_load(&tc[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (tid == 0) {
         s_chunk = -1;
         s_rank = 0;
@@ -175,19 +204,19 @@ __global__ void __launch_bounds__(256) sel_tie_pick(const SelArgs a)
     if (excl < need && need <= incl) {
         long long acc = excl;
         for (int64_t c = c0; c < c1; ++c) {
-            if (acc + (long long)tc[c] >= need) {
+            const long long k = __hip_atomic_load(&tc[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (acc + k >= need) {
                 s_chunk = c;
                 s_rank = need - acc;
                 break;
             }
-            acc += tc[c];
+            acc += k;
         }
     }
     __syncthreads();
     const long long chunk = s_chunk, rank = s_rank;
     if (chunk < 0) return;  // uniform
-    // walk the chunk in index order, 256 points at a time
-    const T* v = reinterpret_cast<const T*>(a.dE) + (size_t)b * a.npts;
+    // ... and the point: walk the chunk in index order
     const int64_t x0 = chunk * SEL_CHUNK;
     const int64_t x1 = x0 + SEL_CHUNK < a.npts ? x0 + SEL_CHUNK : a.npts;
     long long run = 0;
@@ -244,8 +273,7 @@ static hipError_t select_t(const SelArgs& a, int batch, hipStream_t st)
         hipLaunchKernelGGL((sel_hist<T>), gc, bl, 0, st, a, sh, bi, p);
         hipLaunchKernelGGL(sel_pick, gb, bl, 0, st, a, sh, bi, p, p == passes - 1 ? 1 : 0);
     }
-    hipLaunchKernelGGL((sel_tie_count<T>), gc, bl, 0, st, a);
-    hipLaunchKernelGGL((sel_tie_pick<T>), gb, bl, 0, st, a);
+    hipLaunchKernelGGL((sel_tie<T>), gc, bl, 0, st, a);
     return hipGetLastError();
 }
 
