@@ -149,6 +149,20 @@ mbo_status mbo_iterate(mbo_plan_t plan, void* A, int max_iter, double tol, int* 
  * E: host, [batch].  Synchronises the stream. */
 mbo_status mbo_energy(mbo_plan_t plan, const void* A, double* E);
 
+/* Index of an SO(2)-valued field (Section 6.1), a diagnostic of the flat-torus
+ * examples: for each field of an n = 2 plan on a 2-D grid, the winding of the
+ * first column (A_00, A_10) of the matrices -- the vector field the paper draws;
+ * a rotation and a reflection with the same angle share it -- along the loops
+ * that wrap once around the torus:
+ *   w_x[b][j]  along axis 0 (x) at column j, the class [gamma]_{1,0};  host [batch][N1];
+ *   w_y[b][i]  along axis 1 (y) at row i,    the class [gamma]_{0,1};  host [batch][N0].
+ * Each is (1/2 pi) times the sum, over consecutive samples with the last joined
+ * to the first, of the angle from one first column to the next in (-pi, pi]:
+ * an integer (to rounding) when neighbouring samples differ by less than pi.
+ * Either output may be NULL.  Other plans return MBO_ERR_UNSUPPORTED.
+ * Allocates a small device buffer per call; synchronises. */
+mbo_status mbo_so2_index(mbo_plan_t plan, const void* A, double* w_x, double* w_y);
+
 /* ---------------------------------------------------------------------------
  * Volume-preserving MBO (Section 7).  Step 2 of Algorithm 1 is replaced by a
  * reassignment that keeps the number of grid points in SO(n) fixed (the volume

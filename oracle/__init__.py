@@ -28,6 +28,11 @@ What each function follows (Osting & Wang, arXiv:1711.01365):
                   SO(n) (the n_plus largest Delta E, ties by point index).
   * ``volume_select``   the selection alone (n_plus largest, ties by index).
   * ``iterate_volume``  volume-preserving MBO: Algorithm 1 with that step 2.
+  * ``winding``   Section 6.1's index of an SO(2)-valued field along the loops
+                  that wrap once in x (axis 0) and once in y (axis 1), from
+                  the first column of each matrix (the field drawn in the
+                  paper's figures), by summing the principal angle between
+                  neighbouring samples.
   * ``dft_naive`` / ``fft``   the discrete Fourier transform by definition and
                   by radix-2 Cooley-Tukey (cross-checked against each other).
 """
@@ -324,3 +329,20 @@ def iterate_volume(A0: np.ndarray, tau: float, K: int, n_plus: int | None = None
                                   -1 if n_plus is None else int(n_plus), _ptr(en),
                                   _ptr(npos, _i64), _ptr(used, _i64)), "iterate_volume")
     return {"A": A, "energy": en, "n_pos": npos, "n_plus": int(used[0])}
+
+
+def winding(A: np.ndarray):
+    """Index of the first-column field of a 2-D O(2) field A (2, 2, N0, N1) along
+    the loops x -> (x, y_j) (one per column j: [gamma]_{1,0}) and y -> (x_i, y)
+    (one per row i: [gamma]_{0,1}): (1/2 pi) times the sum over consecutive
+    samples, the last joined to the first, of the angle from one first column to
+    the next in (-pi, pi].  Returns (w_x [N1], w_y [N0]) as floats."""
+    A = np.asarray(A, dtype=np.float64)
+    assert A.shape[:2] == (2, 2) and A.ndim == 4
+    u, v = A[0, 0], A[1, 0]
+    out = []
+    for axis in (0, 1):
+        un, vn = np.roll(u, -1, axis=axis), np.roll(v, -1, axis=axis)
+        step = np.arctan2(u * vn - v * un, u * un + v * vn)
+        out.append(step.sum(axis=axis) / (2.0 * np.pi))
+    return out[0], out[1]

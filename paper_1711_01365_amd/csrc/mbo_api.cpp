@@ -1572,6 +1572,29 @@ mbo_status mbo_iterate(mbo_plan_t p, void* A, int max_iter, double tol, int* ite
     return MBO_OK;
 }
 
+mbo_status mbo_so2_index(mbo_plan_t p, const void* A, double* w_x, double* w_y)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (p->group) return fail(p, MBO_ERR_UNSUPPORTED, "not available for a batched plan");
+    if (p->d != 2 || p->n != 2) return fail(p, MBO_ERR_UNSUPPORTED, "the index needs n = 2 on a 2-D grid");
+    if (!A) return fail(p, MBO_ERR_INVALID_ARG, "A is NULL");
+    HIP_TRY(p, hipSetDevice(p->device));
+    const int64_t N0 = p->N[0], N1 = p->N[1];
+    const size_t nx = (size_t)p->batch * (size_t)N1, ny = (size_t)p->batch * (size_t)N0;
+    double* d = nullptr;
+    HIP_TRY(p, hipMalloc((void**)&d, (nx + ny) * sizeof(double)));
+    hipError_t e = launch_so2_index(p->pk, A, N0, N1, (int)p->batch, 0, d, p->stream);
+    if (e == hipSuccess) e = launch_so2_index(p->pk, A, N0, N1, (int)p->batch, 1, d + nx, p->stream);
+    std::vector<double> h(nx + ny);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, h.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(p, MBO_ERR_HIP, "index: %s", hipGetErrorString(e));
+    if (w_x) std::memcpy(w_x, h.data(), nx * sizeof(double));
+    if (w_y) std::memcpy(w_y, h.data() + nx, ny * sizeof(double));
+    return MBO_OK;
+}
+
 mbo_status mbo_volume_select(mbo_plan_t p, const void* dE, const int64_t* n_plus, uint8_t* selected)
 {
     if (!p) return MBO_ERR_INVALID_ARG;

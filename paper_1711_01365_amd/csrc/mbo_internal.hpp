@@ -176,6 +176,10 @@ hipError_t launch_vjp(int prec, int n, const VjpArgs& a, int batch, hipStream_t 
 // count values uniform in [-1, 1) from a counter-based hash of (seed, index)
 hipError_t launch_fill_uniform(int prec, void* p, int64_t count, uint64_t seed, hipStream_t st);
 // out[b] = (accumulate ? out[b] : 0) + sum of part[b * m .. b * m + m - 1] in a fixed order
+// Index of the first-column field of a 2-D n = 2 field along every loop of
+// one axis: out[b][l], l < (axis == 0 ? N1 : N0)
+hipError_t launch_so2_index(int prec, const void* A, int64_t N0, int64_t N1, int batch, int axis, double* out,
+                            hipStream_t st);
 hipError_t launch_sum_rows(const double* part, int64_t m, int batch, double* out, hipStream_t st,
                            bool accumulate = false);
 

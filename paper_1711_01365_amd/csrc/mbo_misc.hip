@@ -99,6 +99,34 @@ __global__ void __launch_bounds__(256) sum_rows(const double* part, int64_t m, d
 // ---------------------------------------------------------------------------
 // Small utility kernels (graph-capture safe replacements for memset)
 // ---------------------------------------------------------------------------
+// Index of the first-column field of a 2-D O(2) field (Section 6.1): for loop
+// l (axis 0: column l, the loop wrapping once in x; axis 1: row l, once in y),
+// the sum over consecutive samples (the last joined to the first) of the angle
+// from one first column to the next in (-pi, pi], divided by 2 pi.  One
+// workgroup per loop and field; the FP64 sum runs in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(256) so2_index_kernel(const T* A, int64_t N0, int64_t N1, int axis, double* out)
+{
+    __shared__ double red_d[64];
+    const int b = blockIdx.y;
+    const int64_t loop = blockIdx.x;
+    const int64_t npts = N0 * N1;
+    const T* c0 = A + (size_t)b * 4 * npts;  // entry (0, 0)
+    const T* c1 = c0 + 2 * npts;             // entry (1, 0)
+    const int64_t L = axis == 0 ? N0 : N1;
+    const int64_t stride = axis == 0 ? N1 : 1;
+    const int64_t base = axis == 0 ? loop : loop * N1;
+    double acc = 0.0;
+    for (int64_t k = threadIdx.x; k < L; k += blockDim.x) {
+        const int64_t p = base + k * stride;
+        const int64_t q = base + (k + 1 == L ? 0 : k + 1) * stride;
+        const double u = (double)c0[p], v = (double)c1[p], un = (double)c0[q], vn = (double)c1[q];
+        acc += atan2(u * vn - v * un, u * un + v * vn);
+    }
+    acc = block_reduce<OpSum>(acc, red_d);
+    if (threadIdx.x == 0) out[(size_t)b * gridDim.x + loop] = acc / 6.283185307179586476925286766559;
+}
+
 __global__ void fill_u64(unsigned long long* p, int64_t count, unsigned long long v)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -199,6 +227,17 @@ static hipError_t vjp_dispatch(int n, const VjpArgs& a, int batch, hipStream_t s
 hipError_t launch_vjp(int prec, int n, const VjpArgs& a, int batch, hipStream_t st)
 {
     return prec == 0 ? vjp_dispatch<double>(n, a, batch, st) : vjp_dispatch<float>(n, a, batch, st);
+}
+
+hipError_t launch_so2_index(int prec, const void* A, int64_t N0, int64_t N1, int batch, int axis, double* out,
+                            hipStream_t st)
+{
+    const dim3 g((unsigned)(axis == 0 ? N1 : N0), (unsigned)batch), bl(256);
+    if (prec == 0)
+        hipLaunchKernelGGL((so2_index_kernel<double>), g, bl, 0, st, (const double*)A, N0, N1, axis, out);
+    else
+        hipLaunchKernelGGL((so2_index_kernel<float>), g, bl, 0, st, (const float*)A, N0, N1, axis, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_sum_rows(const double* part, int64_t m, int batch, double* out, hipStream_t st,

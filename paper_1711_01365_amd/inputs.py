@@ -69,6 +69,44 @@ def star_defect_field(grid: Tuple[int, int]) -> np.ndarray:
     return A
 
 
+def line_defect_field(grid: Tuple[int, int], winding: bool) -> np.ndarray:
+    """The two closed line defects of the paper's second and third flat-torus
+    examples (Section 6.1), n = 2.
+
+    Same sampling as star_defect_field.  The rotation by alpha where
+    x > 0.25 |sin(2.5 pi y)| + 0.2 or x < -0.25 |sin(2.5 pi y)| - 0.2, the
+    reflection [[cos a, sin a], [sin a, -cos a]] elsewhere, with
+    alpha = pi sin(2 pi y) (second example) or alpha = 2 pi y (third example,
+    winding = True: the angle turns once along every loop in y).
+    """
+    N0, N1 = grid
+    x = -0.5 + np.arange(N0) / N0
+    y = -0.5 + np.arange(N1) / N1
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    al = 2.0 * np.pi * Y if winding else np.pi * np.sin(2.0 * np.pi * Y)
+    w = 0.25 * np.abs(np.sin(2.5 * np.pi * Y)) + 0.2
+    rot = (X > w) | (X < -w)
+    c, s = np.cos(al), np.sin(al)
+    A = np.empty((2, 2, N0, N1))
+    A[0, 0] = c
+    A[0, 1] = np.where(rot, -s, s)
+    A[1, 0] = s
+    A[1, 1] = np.where(rot, c, -c)
+    return A
+
+
+def linear_angle_field(grid: Tuple[int, int], m: int, k: int) -> np.ndarray:
+    """SO(2) field with angle 2 pi (m x + k y) (x = i/N0, y = j/N1): its first
+    column turns m times along every loop in x and k times along every loop in y."""
+    N0, N1 = grid
+    x = np.arange(N0) / N0
+    y = np.arange(N1) / N1
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    al = 2.0 * np.pi * (m * X + k * Y)
+    c, s = np.cos(al), np.sin(al)
+    return np.stack([np.stack([c, -s]), np.stack([s, c])])
+
+
 @dataclass
 class Workload:
     """One measured configuration: field size, time step, iteration count."""
@@ -77,13 +115,15 @@ class Workload:
     grid: Tuple[int, ...]
     tau: float
     iters: int
-    init: str            # "uniform" | "haar" | "normal" | "star"
+    init: str            # "uniform" | "haar" | "normal" | "star" | "lines" | "lines_winding"
     seed: int
 
     def field(self) -> np.ndarray:
-        if self.init == "star":
+        if self.init in ("star", "lines", "lines_winding"):
             assert self.n == 2 and len(self.grid) == 2
-            return star_defect_field(self.grid)
+            if self.init == "star":
+                return star_defect_field(self.grid)
+            return line_defect_field(self.grid, self.init == "lines_winding")
         gen = {"uniform": uniform_field, "haar": haar_field, "normal": normal_field}[self.init]
         return gen(self.n, self.grid, self.seed)
 
@@ -103,10 +143,21 @@ ADJOINT_256 = Workload("n3_256x256_adjoint", 3, (256, 256), 1e-3, 50, "haar", 40
 ADJOINT_TARGET_SEED = 4002
 ADJOINT_TARGET_TAU = 1e-2
 ADJOINT_CHECKPOINT = 10
-# volume-preserving MBO (Section 7): the paper's example (star-shaped defect,
-# n = 2, 1024^2, tau = 8 dx), and the measured n = 3 configuration with the
-# volume of its initial SO(3) region held fixed
-VOLUME_STAR_1024 = Workload("n2_1024x1024_star_volume", 2, (1024, 1024), 8.0 / 1024, 100, "star", 0)
+# The paper's three flat-torus examples (Section 6.1), n = 2 on 1024^2.  The
+# printed steps (tau = 8 dx and 64 dx, dx = 1/1024) are read as the coefficient
+# of integer wavenumbers in the heat multiplier, exp(-tau |m|^2): on the unit
+# torus that is the diffusion time tau / (4 pi^2).  (Taken as the unit-torus
+# time itself, the second and third examples become uniform within two steps,
+# unlike the evolutions the paper describes.)
+PAPER_TAU_SCALE = 1.0 / (4.0 * np.pi ** 2)
+EXAMPLE_STAR = Workload("n2_1024x1024_star", 2, (1024, 1024), 8.0 / 1024 * PAPER_TAU_SCALE, 400, "star", 0)
+EXAMPLE_LINES = Workload("n2_1024x1024_lines", 2, (1024, 1024), 64.0 / 1024 * PAPER_TAU_SCALE, 200, "lines", 0)
+EXAMPLE_WINDING = Workload("n2_1024x1024_lines_winding", 2, (1024, 1024), 64.0 / 1024 * PAPER_TAU_SCALE, 200,
+                           "lines_winding", 0)
+# volume-preserving MBO (Section 7): the paper's example (the star-shaped
+# defect with the first example's step), and the measured n = 3 configuration
+# with the volume of its initial SO(3) region held fixed
+VOLUME_STAR_1024 = Workload("n2_1024x1024_star_volume", 2, (1024, 1024), EXAMPLE_STAR.tau, 100, "star", 0)
 VOLUME_HAAR_512 = Workload("n3_512x512_haar_volume", 3, (512, 512), 2e-4, 200, "haar", 1)
 
 

@@ -29,7 +29,8 @@ EXPORTS = ("mbo_plan", "mbo_plan_destroy", "mbo_plan_set_tau", "mbo_plan_set_str
            "mbo_plan_set_timing", "mbo_last_timing", "mbo_diffuse", "mbo_project", "mbo_iterate",
            "mbo_energy", "mbo_project_vjp", "mbo_diffuse_dtau", "mbo_plan_batched", "mbo_plan_tuning",
            "mbo_plan_autotune", "mbo_step", "mbo_step_vjp", "mbo_volume_select",
-           "mbo_project_volume", "mbo_iterate_volume", "mbo_status_string", "mbo_last_error")
+           "mbo_project_volume", "mbo_iterate_volume", "mbo_so2_index", "mbo_status_string",
+           "mbo_last_error")
 
 
 class FieldDesc(ctypes.Structure):
@@ -76,6 +77,7 @@ def load(path: str = LIB_PATH):
     lib.mbo_volume_select.argtypes = [vp, vp, i64p, vp]
     lib.mbo_project_volume.argtypes = [vp, vp, vp, i64p, vp]
     lib.mbo_iterate_volume.argtypes = [vp, vp, ctypes.c_int, i64p, i64p, dp, i64p, i64p]
+    lib.mbo_so2_index.argtypes = [vp, vp, dp, dp]
     for f in EXPORTS:
         if f not in ("mbo_status_string", "mbo_last_error"):
             getattr(lib, f).restype = ctypes.c_int
@@ -308,6 +310,17 @@ class Plan:
         if logs:
             out.update(energy=en, flips=fl[:, :K], fallbacks=fb[:, :K])
         return out
+
+    def so2_index(self, A):
+        """Section 6.1 index of the first-column field of an n = 2 field along the
+        loops in x (one per column) and in y (one per row): (w_x [batch, N1],
+        w_y [batch, N0]) as float64 numpy arrays."""
+        w_x = np.zeros((self.batch, self.grid[1]))
+        w_y = np.zeros((self.batch, self.grid[0]))
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(self._lib.mbo_so2_index(self._h, self._field(A), w_x.ctypes.data_as(dp),
+                                       w_y.ctypes.data_as(dp)), self._h)
+        return w_x, w_y
 
     def autotune(self):
         """Time candidate launch shapes on the device and keep the fastest."""

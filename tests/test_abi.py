@@ -132,3 +132,7 @@ def test_null_plan_is_rejected_by_volume_calls(lib):
     assert lib.mbo_volume_select(None, None, None, None) == 1
     assert lib.mbo_project_volume(None, None, None, None, None) == 1
     assert lib.mbo_iterate_volume(None, None, 1, None, None, None, None, None) == 1
+
+
+def test_null_plan_is_rejected_by_the_index(lib):
+    assert lib.mbo_so2_index(None, None, None, None) == 1
