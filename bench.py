@@ -29,7 +29,8 @@ launch rules, FP64), the volume-preserving method of Section 7 (n = 3, 512^2
 Haar, 200 iterations; and the paper's example, the star-shaped defect with
 n = 2 on 1024^2, tau = 8 dx, 100 iterations; FP32 + fallback, the SO(n) volume
 of the initial field held fixed) and the gradient of 50 unrolled steps (n = 3,
-256^2, FP32 + fallback and FP64), forward and backward time.
+256^2, FP32 + fallback and FP64), forward and backward time; and the paper's
+three flat-torus examples (n = 2, 1024^2, FP32 + fallback) with their end states.
 
     python bench.py --volume-only [--steps K] [--warmup W]
 
@@ -59,8 +60,8 @@ def log(*a):
 
 
 # sources that decide the row pass's code and launch shape (its traffic)
-ROW_PASS_SOURCES = ("mbo_device.hpp", "mbo_kernels.hpp", "mbo_internal.hpp", "mbo_row_f32.hip",
-                    "mbo_api.cpp")
+ROW_PASS_SOURCES = ("mbo_device.hpp", "mbo_kernels.hpp", "mbo_internal.hpp", "mbo_volume.hpp",
+                    "mbo_row_f32.hip", "mbo_api.cpp")
 
 
 def kernel_source_hash() -> str:
@@ -233,6 +234,42 @@ def run_volume(w, steps, warmup):
             "energy_nonincreasing": bool(np.all(np.diff(E[1:]) <= 1e-5 * np.abs(E[1:-1])))}
 
 
+def run_examples(steps):
+    """The paper's three flat-torus examples (n = 2, 1024^2, FP32 + FP64
+    fallback, their iteration counts) through the captured graph: rate and the
+    end state (points in SO(2), SO(2) index along x and y loops)."""
+    import numpy as np
+    import torch
+    from paper_1711_01365_amd import inputs, mbo
+    out = {}
+    for w in (inputs.EXAMPLE_STAR, inputs.EXAMPLE_LINES, inputs.EXAMPLE_WINDING):
+        A0 = torch.tensor(w.field(), dtype=torch.float32, device="cuda")
+        A = A0.clone()
+        plan = mbo.Plan(w.grid, w.n, w.tau, precision=mbo.F32_F64FALLBACK)
+        plan.autotune()
+        A.copy_(A0)
+        plan.iterate(A, w.iters)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            A.copy_(A0)
+            lg = plan.iterate(A, w.iters)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        wx, wy = plan.so2_index(A)
+        a = A.double().cpu().numpy()
+        det = a[0, 0] * a[1, 1] - a[0, 1] * a[1, 0]
+        plan.close()
+        out[w.name] = {"tau": w.tau, "iterations": w.iters,
+                       "value": w.points * w.iters * steps / sec, "unit": "point-iterations/s",
+                       "us_per_iteration": 1e6 * sec / (steps * w.iters),
+                       "so2_points_end": int((det > 0).sum()),
+                       "index_end": [sorted(set(np.rint(wx[0]).astype(int).tolist())),
+                                     sorted(set(np.rint(wy[0]).astype(int).tolist()))],
+                       "energy_first_last": [float(lg["energy"][0][0]), float(lg["energy"][0][-1])]}
+    return out
+
+
 def run_adjoint(precision, reps):
     """Gradients of K = 50 unrolled steps (n = 3, 256^2, checkpoint every 10):
     forward and backward wall time of the autograd function."""
@@ -328,7 +365,7 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the legs reported beside the main line (2048^2 control, 3-D, "
-                         "batched, volume-preserving, adjoint)")
+                         "batched, volume-preserving, paper examples, adjoint)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--volume-only", action="store_true",
                     help="only the volume-preserving legs (for profiling them)")
@@ -418,6 +455,10 @@ def main():
         for k, r in out["volume_preserving"].items():
             log("volume-preserving %s: %.3e point-iter/s, %.1f us/iteration (plain %.1f us)"
                 % (k, r["value"], r["us_per_iteration"], r["plain_mbo_us_per_iteration"]))
+        out["paper_examples"] = run_examples(3)
+        for k, r in out["paper_examples"].items():
+            log("paper example %s: %.3e point-iter/s, %.1f us/iteration, end: %d SO(2) points, index %s"
+                % (k, r["value"], r["us_per_iteration"], r["so2_points_end"], r["index_end"]))
         out["adjoint"] = {"f32_f64fallback": run_adjoint(mbo.F32_F64FALLBACK, 2),
                           "f64": run_adjoint(mbo.F64, 2)}
         log("adjoint K=50 256^2: fp32+fb fwd %.1f ms bwd %.1f ms, fp64 fwd %.1f ms bwd %.1f ms"
