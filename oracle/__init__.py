@@ -33,6 +33,10 @@ What each function follows (Osting & Wang, arXiv:1711.01365):
                   the first column of each matrix (the field drawn in the
                   paper's figures), by summing the principal angle between
                   neighbouring samples.
+  * ``relaxed_flow`` / ``relaxed_energy``  the gradient flows GD-1
+                  (reaction U (Sigma - I) V^t) and GD-3 (A (A^t A - I)) by an
+                  implicit diffusion step then an explicit reaction step, and
+                  the energies E_{1,eps}, E_{2,eps} they descend.
   * ``dft_naive`` / ``fft``   the discrete Fourier transform by definition and
                   by radix-2 Cooley-Tukey (cross-checked against each other).
 """
@@ -98,11 +102,15 @@ def _load():
                                        _i8]
     lib.orc_iterate_volume.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_double, _d,
                                        ctypes.c_int, ctypes.c_int64, _d, _i64, _i64]
+    lib.orc_relaxed_flow.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_double, _d, ctypes.c_int]
+    lib.orc_relaxed_energy.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                       _d, _d]
     lib.orc_num_threads.argtypes = []
     for f in ("orc_dft_naive", "orc_fft", "orc_heat", "orc_project", "orc_det_sign",
               "orc_energy", "orc_iterate", "orc_num_threads", "orc_heat_dtau", "orc_project_vjp",
               "orc_unroll_grad", "orc_volume_select", "orc_volume_project",
-              "orc_iterate_volume"):
+              "orc_iterate_volume", "orc_relaxed_flow", "orc_relaxed_energy"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -346,3 +354,27 @@ def winding(A: np.ndarray):
         step = np.arctan2(u * vn - v * un, u * un + v * vn)
         out.append(step.sum(axis=axis) / (2.0 * np.pi))
     return out[0], out[1]
+
+
+def relaxed_flow(A0: np.ndarray, kind: int, eps: float, dt: float, K: int) -> np.ndarray:
+    """K steps of GD-1 (kind 1) or GD-3 (kind 3): B = (I - dt Delta)^-1 A, then
+    A = B - (dt/eps^2) N(B).  A0 has shape (n, n, *grid); returns the last A."""
+    lib = _load()
+    A = np.ascontiguousarray(A0, dtype=np.float64).copy()
+    n = A.shape[0]
+    g, d = _grid(A.shape[2:])
+    _check(lib.orc_relaxed_flow(d, _ptr(g, _i64), n, int(kind), float(eps), float(dt), _ptr(A), int(K)),
+           "relaxed_flow")
+    return A
+
+
+def relaxed_energy(A: np.ndarray, kind: int, eps: float) -> float:
+    """E_{1,eps} (kind 1) or E_{2,eps} (kind 3) of A on the unit torus."""
+    lib = _load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    g, d = _grid(A.shape[2:])
+    E = np.zeros(1)
+    _check(lib.orc_relaxed_energy(d, _ptr(g, _i64), n, int(kind), float(eps), _ptr(A), _ptr(E)),
+           "relaxed_energy")
+    return float(E[0])

@@ -2,7 +2,8 @@
  * FP64 CPU oracle for the generalized MBO diffusion generated motion for
  * orthogonal matrix-valued fields on flat tori (Osting & Wang, arXiv:1711.01365:
  * Algorithm 1, Lemma 1.1, Section 4, Section 5.1; the volume-preserving
- * variant of Section 7: Lemmas 7.1, 7.2).
+ * variant of Section 7: Lemmas 7.1, 7.2; the relaxed gradient flows GD-1 and
+ * GD-3 of Section 1 with their energies).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call
  * this file: only the test suite, the smoke check and the CPU-baseline leg of
@@ -791,6 +792,131 @@ int orc_iterate_volume(int d, const int64_t* N, int n, double tau, double* A, in
     if (n_plus_used) *n_plus_used = n_plus;
     free(At); free(sg);
     return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Relaxed gradient flows (eqs. GD-1 and GD-3)                               */
+/* ------------------------------------------------------------------------ */
+
+/* The reaction term of one matrix: kind 1 (GD-1) U (Sigma - I) V^t, which by
+ * Lemma 1.1 is A - U V^t; kind 3 (GD-3) A (A^t A - I). */
+static void orc_relax_reaction(int n, int kind, const double* a, double* r)
+{
+    if (kind == 1) {
+        double q[16], sig[4];
+        orc_project_point(n, a, q, sig);
+        for (int e = 0; e < n * n; ++e) r[e] = a[e] - q[e];
+    } else {
+        double m[16];
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < n; ++k) s += a[k * n + i] * a[k * n + j];
+                m[i * n + j] = s - (i == j ? 1.0 : 0.0);
+            }
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < n; ++k) s += a[i * n + k] * m[k * n + j];
+                r[i * n + j] = s;
+            }
+    }
+}
+
+/* K steps of the semi-implicit scheme for dA/dt = Delta A - eps^-2 N(A) (GD-1
+ * or GD-3), in place: an implicit-Euler diffusion step B = (I - dt Delta)^{-1} A
+ * (Fourier symbol 1 / (1 + 4 pi^2 dt |k|^2)) followed by an explicit reaction
+ * step A = B - (dt / eps^2) N(B).  (The paper states the flows, not a scheme;
+ * the IMEX Euler step A <- (I - dt Delta)^{-1} (A - dt eps^-2 N(A)) gives the
+ * same sequence shifted by one reaction step.)  eps = +inf drops the
+ * reaction. */
+int orc_relaxed_flow(int d, const int64_t* N, int n, int kind, double eps, double dt, double* A, int K)
+{
+    if (n < 1 || n > 4 || (kind != 1 && kind != 3) || !(eps > 0.0) || !(dt > 0.0) || K < 0) return -1;
+    if (d < 1 || d > 3) return -1;
+    for (int a = 0; a < d; ++a)
+        if (!orc_is_pow2(N[a])) return -2;
+    const int64_t P = orc_npoints(d, N);
+    const int64_t nn = (int64_t)n * n;
+    const double c = isinf(eps) ? 0.0 : dt / (eps * eps);
+    double* re = (double*)malloc(sizeof(double) * (size_t)P);
+    double* im = (double*)malloc(sizeof(double) * (size_t)P);
+    double* B = (double*)malloc(sizeof(double) * (size_t)(P * nn));
+    for (int s = 0; s < K; ++s) {
+        for (int64_t pl = 0; pl < nn; ++pl) { /* diffusion step */
+            memcpy(re, A + pl * P, sizeof(double) * (size_t)P);
+            memset(im, 0, sizeof(double) * (size_t)P);
+            orc_fft(d, N, re, im, -1);
+            for (int64_t m = 0; m < P; ++m) {
+                const double g = 1.0 / (1.0 - dt * orc_laplace_symbol(d, N, m));
+                re[m] *= g;
+                im[m] *= g;
+            }
+            orc_fft(d, N, re, im, +1);
+            for (int64_t p = 0; p < P; ++p) B[pl * P + p] = re[p] / (double)P;
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t p = 0; p < P; ++p) { /* reaction step */
+            double b[16], r[16];
+            for (int e = 0; e < nn; ++e) b[e] = B[e * P + p];
+            orc_relax_reaction(n, kind, b, r);
+            for (int e = 0; e < nn; ++e) A[e * P + p] = b[e] - c * r[e];
+        }
+    }
+    free(re); free(im); free(B);
+    return 0;
+}
+
+/* The relaxed energies E_{1,eps} (kind 1) and E_{2,eps} (kind 3) on the unit
+ * torus: (1/2) int |grad A|_F^2, by Parseval (1/2) sum over entry planes and
+ * modes of 4 pi^2 |k|^2 |F(A)(k) / P|^2, plus the mean over points of the
+ * penalty, (1/(2 eps^2)) dist^2(O_n, A) = (1/(2 eps^2)) sum (sigma_i - 1)^2
+ * (Lemma 1.1, computed as |A - U V^t|_F^2) or (1/(4 eps^2)) |A^t A - I|_F^2. */
+int orc_relaxed_energy(int d, const int64_t* N, int n, int kind, double eps, const double* A, double* E)
+{
+    if (n < 1 || n > 4 || (kind != 1 && kind != 3) || !(eps > 0.0)) return -1;
+    if (d < 1 || d > 3) return -1;
+    for (int a = 0; a < d; ++a)
+        if (!orc_is_pow2(N[a])) return -2;
+    const int64_t P = orc_npoints(d, N);
+    const int64_t nn = (int64_t)n * n;
+    double* re = (double*)malloc(sizeof(double) * (size_t)P);
+    double* im = (double*)malloc(sizeof(double) * (size_t)P);
+    double* t = (double*)malloc(sizeof(double) * (size_t)P);
+    double dir = 0.0;
+    for (int64_t pl = 0; pl < nn; ++pl) {
+        memcpy(re, A + pl * P, sizeof(double) * (size_t)P);
+        memset(im, 0, sizeof(double) * (size_t)P);
+        orc_fft(d, N, re, im, -1);
+        for (int64_t m = 0; m < P; ++m)
+            t[m] = -orc_laplace_symbol(d, N, m) * (re[m] * re[m] + im[m] * im[m]);
+        dir += orc_pairwise_sum(t, P);
+    }
+    dir *= 0.5 / ((double)P * (double)P);
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < P; ++p) {
+        double a[16], r[16];
+        for (int e = 0; e < nn; ++e) a[e] = A[e * P + p];
+        double s = 0.0;
+        if (kind == 1) {
+            orc_relax_reaction(n, 1, a, r); /* A - U V^t */
+            for (int e = 0; e < nn; ++e) s += r[e] * r[e];
+            t[p] = 0.5 * s;
+        } else {
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    double m = 0.0;
+                    for (int k = 0; k < n; ++k) m += a[k * n + i] * a[k * n + j];
+                    m -= (i == j ? 1.0 : 0.0);
+                    s += m * m;
+                }
+            t[p] = 0.25 * s;
+        }
+    }
+    const double pen = isinf(eps) ? 0.0 : orc_pairwise_sum(t, P) / ((double)P * eps * eps);
+    *E = dir + pen;
+    free(re); free(im); free(t);
+    return 0;
 }
 
 /* Number of threads the OpenMP loops above use (1 without OpenMP). */
