@@ -149,6 +149,33 @@ mbo_status mbo_iterate(mbo_plan_t plan, void* A, int max_iter, double tol, int* 
  * E: host, [batch].  Synchronises the stream. */
 mbo_status mbo_energy(mbo_plan_t plan, const void* A, double* E);
 
+/* ---------------------------------------------------------------------------
+ * Relaxed gradient flows (Section 1), the comparison PDEs of the MBO method:
+ *   GD-1  dA/dt = Delta A - eps^-2 U (Sigma - I) V^t   (E_{1,eps}, penalty
+ *         dist^2(O_n, A) / (2 eps^2); U (Sigma - I) V^t = A - U V^t by Lemma 1.1)
+ *   GD-3  dA/dt = Delta A - eps^-2 A (A^t A - I)        (E_{2,eps}, penalty
+ *         |A^t A - I|_F^2 / (4 eps^2); the same flow as GD-2)
+ * The paper states the flows, not a scheme.  One step here is an implicit-Euler
+ * diffusion step B = (I - dt Delta)^{-1} A (Fourier symbol 1 / (1 + 4 pi^2 dt
+ * |k|^2)) followed by an explicit reaction step A = B - (dt / eps^2) N(B): first
+ * order in dt, energy-decreasing for small dt / eps^2.  eps = +inf drops the
+ * reaction (pure implicit heat steps).  GD-1 at a singular point uses the
+ * projection's convention (det +1 minimiser).  The plan's tau is not used.
+ * Batched plans return MBO_ERR_UNSUPPORTED.
+ * ------------------------------------------------------------------------- */
+typedef enum { MBO_GD1 = 1, MBO_GD3 = 3 } mbo_flow;
+
+/* `steps` steps of the flow `kind` (an mbo_flow) in place on A (device, plan
+ * layout).  dt > 0 finite, eps > 0.  Runs as one captured HIP graph (re-used
+ * while A, steps, kind, eps and dt stay the same); synchronises and returns
+ * MBO_ERR_NONFINITE if a NaN/Inf was met. */
+mbo_status mbo_relaxed_flow(mbo_plan_t plan, void* A, int steps, int kind, double eps, double dt);
+
+/* E_{1,eps} (kind MBO_GD1) or E_{2,eps} (MBO_GD3) of each field on the unit
+ * torus: (1/2) int |grad A|_F^2 (from the spectrum, Parseval) plus the mean
+ * over grid points of the penalty.  E: host [batch].  Synchronises. */
+mbo_status mbo_relaxed_energy(mbo_plan_t plan, const void* A, int kind, double eps, double* E);
+
 /* Index of an SO(2)-valued field (Section 6.1), a diagnostic of the flat-torus
  * examples: for each field of an n = 2 plan on a 2-D grid, the winding of the
  * first column (A_00, A_10) of the matrices -- the vector field the paper draws;

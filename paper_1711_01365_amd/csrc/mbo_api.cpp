@@ -131,6 +131,13 @@ struct mbo_plan_s {
     unsigned* vtcnt = nullptr;    // [batch][chunks]
     long long* vnplus = nullptr;  // [batch]
     unsigned* vdone = nullptr;    // [batch] finished-workgroup counters of the tie count
+    // relaxed flows: cached graph of mbo_relaxed_flow, penalty partials
+    hipGraphExec_t rexec = nullptr;
+    void* rg_A = nullptr;
+    int rg_K = -1, rg_kind = 0;
+    double rg_c = 0.0, rg_dt = 0.0;
+    double* pen = nullptr;       // [batch][ceil(npts / 256)]
+    double* pen_sum = nullptr;   // [batch]
     hipGraphExec_t vexec = nullptr;  // cached graph of mbo_iterate_volume
     void* vg_A = nullptr;
     int vg_K = -1;
@@ -177,6 +184,10 @@ void drop_graph(mbo_plan_t p)
     p->g_key = -1;
     if (p->vexec) (void)hipGraphExecDestroy(p->vexec);
     p->vexec = nullptr;
+    if (p->rexec) (void)hipGraphExecDestroy(p->rexec);
+    p->rexec = nullptr;
+    p->rg_A = nullptr;
+    p->rg_K = -1;
     p->vg_A = nullptr;
     p->vg_K = -1;
     p->vg_key = -1;
@@ -224,6 +235,8 @@ void destroy(mbo_plan_t p)
     free_dev(p->vtcnt);
     free_dev(p->vnplus);
     free_dev(p->vdone);
+    free_dev(p->pen);
+    free_dev(p->pen_sum);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     if (p->cap) (void)hipStreamDestroy(p->cap);
     delete p;
@@ -774,6 +787,58 @@ hipError_t enqueue_iterate_volume(mbo_plan_t p, void* A, int K, bool from_a0, bo
     }
     if (want_energy) return enqueue_final_energy(p, K, st);
     return hipSuccess;
+}
+
+// ---- relaxed gradient flows (GD-1, GD-3) -------------------------------------
+
+hipError_t run_row_relax(mbo_plan_t p, const RowArgs& a, hipStream_t st)
+{
+    return launch_row_relax(p->pk, p->n, a.log2L, a, p->row_grid, p->row_block, p->row_lds, st);
+}
+
+// K steps of B = (I - dt Delta)^{-1} A, A = B - c N(B) in place on A.
+hipError_t enqueue_relaxed_flow(mbo_plan_t p, void* A, int K, int kind, double c, double dt, hipStream_t st)
+{
+    const int64_t cs = (int64_t)p->batch * (K > 0 ? K : 1);
+    hipError_t e;
+    if ((e = launch_fill_u64(p->fallbacks, cs, 0ull, st)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(p->nonfinite, cs, 0ull, st)) != hipSuccess) return e;
+    if (K == 0) return hipSuccess;
+    if ((e = enqueue_forward(p, A, 0, false, st)) != hipSuccess) return e;
+    const int fb = p->prec == MBO_F32_F64FALLBACK ? RF_FALLBACK : 0;
+    for (int s = 1; s <= K; ++s) {
+        if (p->d == 3) {
+            ColArgs y = col_args(p, p->ypass);
+            if ((e = run_col(p, p->ypass, CM_FORWARD, y, st)) != hipSuccess) return e;
+        }
+        ColArgs h = col_args(p, p->heat);
+        h.rdt = dt;
+        h.rnorm = 1.0 / (double)p->npts;
+        if ((e = run_col(p, p->heat, CM_RESOLVENT, h, st)) != hipSuccess) return e;
+        if (p->d == 3) {
+            ColArgs y = col_args(p, p->ypass);
+            if ((e = run_col(p, p->ypass, CM_INVERSE, y, st)) != hipSuccess) return e;
+        }
+        RowArgs r = row_args(p);
+        r.Aout = A;
+        r.iter = s;
+        r.K = K;
+        r.fallbacks = p->fallbacks;
+        r.nonfinite = p->nonfinite;
+        r.relax_kind = kind;
+        r.relax_c = c;
+        r.flags = RF_INVERSE | RF_RELAX | fb | (s < K ? RF_FORWARD : 0) | (s == K ? RF_STORE_REAL : 0);
+        if ((e = run_row_relax(p, r, st)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+mbo_status check_relax_args(mbo_plan_t p, int kind, double eps)
+{
+    if (p->group) return fail(p, MBO_ERR_UNSUPPORTED, "not available for a batched plan");
+    if (kind != MBO_GD1 && kind != MBO_GD3) return fail(p, MBO_ERR_INVALID_ARG, "kind must be MBO_GD1 or MBO_GD3");
+    if (!(eps > 0.0)) return fail(p, MBO_ERR_INVALID_ARG, "eps must be > 0 (+inf drops the penalty)");
+    return MBO_OK;
 }
 
 // Shape checks shared by mbo_plan and mbo_plan_batched.
@@ -1569,6 +1634,91 @@ mbo_status mbo_iterate(mbo_plan_t p, void* A, int max_iter, double tol, int* ite
         return s;
     }
     if (bad) return fail(p, MBO_ERR_NONFINITE, "%llu projections met NaN/Inf input", bad);
+    return MBO_OK;
+}
+
+mbo_status mbo_relaxed_flow(mbo_plan_t p, void* A, int steps, int kind, double eps, double dt)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    mbo_status s;
+    if ((s = check_relax_args(p, kind, eps)) != MBO_OK) return s;
+    if (!A) return fail(p, MBO_ERR_INVALID_ARG, "A is NULL");
+    if (steps < 0) return fail(p, MBO_ERR_INVALID_ARG, "steps < 0");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, MBO_ERR_INVALID_ARG, "dt must be finite and > 0");
+    HIP_TRY(p, hipSetDevice(p->device));
+    if ((s = ensure_logs(p, steps)) != MBO_OK) return s;
+    (void)launch_row_relax(p->pk, p->n, ilog2((int)p->N[p->d - 1]), row_args(p), p->row_grid, p->row_block,
+                           p->lds_max, nullptr, true);
+    (void)hipGetLastError();
+    const double c = std::isinf(eps) ? 0.0 : dt / (eps * eps);
+    if (use_graphs()) {
+        if (!(p->rexec && p->rg_A == A && p->rg_K == steps && p->rg_kind == kind && p->rg_c == c &&
+              p->rg_dt == dt)) {
+            if (p->rexec) (void)hipGraphExecDestroy(p->rexec);
+            p->rexec = nullptr;
+            hipGraph_t g = nullptr;
+            HIP_TRY(p, hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+            hipError_t e = enqueue_relaxed_flow(p, A, steps, kind, c, dt, p->cap);
+            hipError_t e2 = hipStreamEndCapture(p->cap, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return fail(p, MBO_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+            }
+            hipError_t e3 = hipGraphInstantiate(&p->rexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e3 != hipSuccess) {
+                p->rexec = nullptr;
+                return fail(p, MBO_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e3));
+            }
+            p->rg_A = A;
+            p->rg_K = steps;
+            p->rg_kind = kind;
+            p->rg_c = c;
+            p->rg_dt = dt;
+        }
+        HIP_TRY(p, hipGraphLaunch(p->rexec, p->stream));
+    } else {
+        HIP_TRY(p, enqueue_relaxed_flow(p, A, steps, kind, c, dt, p->stream));
+    }
+    const size_t cs = (size_t)p->batch * (size_t)(steps > 0 ? steps : 1);
+    std::vector<unsigned long long> h(cs);
+    HIP_TRY(p, hipMemcpyAsync(h.data(), p->nonfinite, cs * 8, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    unsigned long long bad = 0;
+    for (unsigned long long v : h) bad += v;
+    if (bad) return fail(p, MBO_ERR_NONFINITE, "%llu points met NaN/Inf", bad);
+    return MBO_OK;
+}
+
+mbo_status mbo_relaxed_energy(mbo_plan_t p, const void* A, int kind, double eps, double* E)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    mbo_status s;
+    if ((s = check_relax_args(p, kind, eps)) != MBO_OK) return s;
+    if (!A || !E) return fail(p, MBO_ERR_INVALID_ARG, "A / E is NULL");
+    HIP_TRY(p, hipSetDevice(p->device));
+    if ((s = ensure_logs(p, 0)) != MBO_OK) return s;
+    const int64_t blocks = (p->npts + 255) / 256;
+    if (!p->pen) HIP_TRY(p, hipMalloc((void**)&p->pen, (size_t)p->batch * (size_t)blocks * sizeof(double)));
+    if (!p->pen_sum) HIP_TRY(p, hipMalloc((void**)&p->pen_sum, (size_t)p->batch * sizeof(double)));
+    // (1/2) int |grad A|^2 from the spectrum (Parseval), then the mean penalty
+    HIP_TRY(p, enqueue_forward(p, A, 0, true, p->stream));
+    ColArgs h = col_args(p, p->heat);
+    h.K = 0;
+    h.slot = 0;
+    h.epart = p->epart;
+    HIP_TRY(p, run_col(p, p->heat, CM_DIRICHLET, h, p->stream));
+    HIP_TRY(p, launch_sum_rows(p->epart, energy_partials(p), (int)p->batch, p->dsum, p->stream));
+    HIP_TRY(p, launch_penalty(p->pk, p->n, A, p->npts, (int)p->batch, kind, p->pen, p->stream));
+    HIP_TRY(p, launch_sum_rows(p->pen, blocks, (int)p->batch, p->pen_sum, p->stream));
+    std::vector<double> dir((size_t)p->batch), pen((size_t)p->batch);
+    HIP_TRY(p, hipMemcpyAsync(dir.data(), p->dsum, dir.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipMemcpyAsync(pen.data(), p->pen_sum, pen.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    const double P = (double)p->npts;
+    for (int64_t b = 0; b < p->batch; ++b)
+        E[b] = 0.5 * dir[(size_t)b] / (P * P) + (std::isinf(eps) ? 0.0 : pen[(size_t)b] / (P * eps * eps));
     return MBO_OK;
 }
 

@@ -1,4 +1,4 @@
-// Strided-axis kernels in double: forward / inverse / heat / energy / tau-derivative modes for
+// Strided-axis kernels in double: forward / inverse / heat / energy / tau-derivative / resolvent / Dirichlet modes for
 // transform lengths 2^3..2^11.
 #include <hip/hip_ext.h>
 
@@ -33,6 +33,8 @@ hipError_t launch_col_f64(int mode, int log2L, const ColArgs& a, dim3 g, dim3 bl
     case CM_HEAT: return col_m<CM_HEAT>(log2L, a, g, bl, lds, st, prepare, ev0, ev1);
     case CM_ENERGY: return col_m<CM_ENERGY>(log2L, a, g, bl, lds, st, prepare, ev0, ev1);
     case CM_DTAU: return col_m<CM_DTAU>(log2L, a, g, bl, lds, st, prepare, ev0, ev1);
+    case CM_RESOLVENT: return col_m<CM_RESOLVENT>(log2L, a, g, bl, lds, st, prepare, ev0, ev1);
+    case CM_DIRICHLET: return col_m<CM_DIRICHLET>(log2L, a, g, bl, lds, st, prepare, ev0, ev1);
     }
     return hipErrorInvalidValue;
 }

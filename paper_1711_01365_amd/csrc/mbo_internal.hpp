@@ -22,7 +22,12 @@ enum RowFlags : int {
     RF_DOT = 1 << 10,        // per-workgroup partials of <G, values after the inverse FFT>
     RF_VP_KEY = 1 << 11,     // volume-preserving step: Delta E of the loaded values into vde[]
     RF_VP_APPLY = 1 << 12,   // volume-preserving step: T+ / T- as the selection vsel[] says
+    RF_RELAX = 1 << 13,      // relaxed flow: explicit reaction step of GD-1 / GD-3
 };
+
+// Instances of the row pass: Algorithm 1, the volume-preserving step, the
+// reaction step of the relaxed gradient flows.
+enum RowMode : int { RM_MBO = 0, RM_VOLUME = 1, RM_RELAX = 2 };
 
 // Selection of the n_plus points with the largest Delta E of a field (the
 // volume-preserving step), found by a radix search over order-preserving keys
@@ -70,6 +75,8 @@ struct RowArgs {
                              // (default b * n*n * npts)
     void* vde;               // RF_VP_KEY / RF_VP_APPLY: Delta E per point [batch][npts]
     const VpSel* vsel;       // RF_VP_APPLY: finished selection of each field [batch]
+    int relax_kind;          // RF_RELAX: 1 = GD-1, 3 = GD-3
+    double relax_c;          // RF_RELAX: dt / eps^2
 };
 
 // Element offset of field b of a real-field buffer.
@@ -91,7 +98,13 @@ constexpr size_t row_fb_lds(int esz, int n, int log2L)
 }
 
 // Modes of the strided-axis pass.
-enum ColMode : int { CM_FORWARD = 0, CM_INVERSE = 1, CM_HEAT = 2, CM_ENERGY = 3, CM_DTAU = 4 };
+// CM_RESOLVENT multiplies by rnorm / (1 + 4 pi^2 rdt |k|^2) (the implicit
+// diffusion step of the relaxed flows); CM_DIRICHLET only sums
+// 4 pi^2 |k|^2 |Z|^2 into the energy partials.
+enum ColMode : int {
+    CM_FORWARD = 0, CM_INVERSE = 1, CM_HEAT = 2, CM_ENERGY = 3, CM_DTAU = 4, CM_RESOLVENT = 5,
+    CM_DIRICHLET = 6
+};
 
 struct ColArgs {
     int L, log2L;            // transform length along the axis
@@ -119,6 +132,8 @@ struct ColArgs {
     int* stop_iter;          // nullable
     const unsigned long long* delta_bits;  // nullable
     double tol;
+    double rdt;              // CM_RESOLVENT: the step dt
+    double rnorm;            // CM_RESOLVENT: 1 / prod(N) (the inverse transforms are unscaled)
 };
 
 struct ProjArgs {
@@ -220,6 +235,18 @@ hipError_t launch_col_f64(int mode, int log2L, const ColArgs& a, dim3 g, dim3 b,
                           hipStream_t st, bool prepare, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_row_vp_f32(int n, int log2L, const RowArgs& a, dim3 g, dim3 b, size_t lds,
                              hipStream_t st, bool prepare);
+hipError_t launch_row_relax_f32(int n, int log2L, const RowArgs& a, dim3 g, dim3 b, size_t lds,
+                                hipStream_t st, bool prepare);
+hipError_t launch_row_relax_f64(int n, int log2L, const RowArgs& a, dim3 g, dim3 b, size_t lds,
+                                hipStream_t st, bool prepare);
+// Row pass of the relaxed flows (flag RF_RELAX)
+hipError_t launch_row_relax(int prec, int n, int log2L, const RowArgs& a, dim3 grid, dim3 block,
+                            size_t lds, hipStream_t st, bool prepare = false);
+// Per-workgroup sums of the pointwise penalty of E_{1,eps} (kind 1:
+// |A - U V^t|^2 / 2) or E_{2,eps} (kind 3: |A^t A - I|^2 / 4), without the
+// 1 / eps^2: part[b][blocks], blocks = ceil(npts / 256)
+hipError_t launch_penalty(int prec, int n, const void* A, int64_t npts, int batch, int kind, double* part,
+                          hipStream_t st);
 hipError_t launch_row_vp_f64(int n, int log2L, const RowArgs& a, dim3 g, dim3 b, size_t lds,
                              hipStream_t st, bool prepare);
 

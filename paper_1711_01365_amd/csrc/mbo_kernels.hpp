@@ -129,17 +129,21 @@ __device__ __forceinline__ void line_stage(typename cx<T>::type* zline, T* lr, T
 // Waves per SIMD the row pass is compiled for: float rows of up to 512 points
 // and n <= 3 are held to 128 VGPRs, so that two 512-thread workgroups share a
 // compute unit.
-// The volume-preserving instance (VP) evaluates both candidates of a point and
-// is not held.
-template <typename T, int n, int LOG2L, bool VP = false>
-constexpr int row_waves_per_simd() { return (!VP && sizeof(T) == 4 && n <= 3 && LOG2L <= 9) ? 4 : 1; }
+// The volume-preserving and relaxed-flow instances are not held (the first
+// evaluates both candidates of a point, the second carries the projection's
+// double path inline).
+template <typename T, int n, int LOG2L, int RM = RM_MBO>
+constexpr int row_waves_per_simd() { return (RM == RM_MBO && sizeof(T) == 4 && n <= 3 && LOG2L <= 9) ? 4 : 1; }
 
-// VP = false: Algorithm 1 (flags RF_PROJECT ...); VP = true: the volume-
-// preserving step of Section 7 in two launches, RF_VP_KEY (Delta E of every
-// point) and, after the selection, RF_VP_APPLY (T+ or T- per point).
-template <typename T, int n, int LOG2L, bool VP = false>
-__global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L, VP>())) row_pass(const RowArgs a)
+// RM_MBO: Algorithm 1 (flags RF_PROJECT ...); RM_VOLUME: the volume-preserving
+// step of Section 7 in two launches, RF_VP_KEY (Delta E of every point) and,
+// after the selection, RF_VP_APPLY (T+ or T- per point); RM_RELAX: the explicit
+// reaction step of the relaxed gradient flows GD-1 / GD-3 (RF_RELAX).
+template <typename T, int n, int LOG2L, int RM = RM_MBO>
+__global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L, RM>())) row_pass(const RowArgs a)
 {
+    constexpr bool VP = RM == RM_VOLUME;
+    constexpr bool RELAX = RM == RM_RELAX;
     constexpr int NN = n * n;
     constexpr int PL = (NN + 1) / 2;
     typedef FftShape<LOG2L> F;
@@ -283,7 +287,7 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L, VP>())) 
     // loop nor runs once per wave that holds such a point.
     unsigned long long nflip = 0, nfb = 0, nbad = 0;
     double dmax = 0.0, dacc = 0.0;
-    if (flags & (RF_PROJECT | RF_SIGN_INIT | RF_STORE_REAL | RF_DOT | RF_VP_KEY | RF_VP_APPLY)) {
+    if (flags & (RF_PROJECT | RF_SIGN_INIT | RF_STORE_REAL | RF_DOT | RF_VP_KEY | RF_VP_APPLY | RF_RELAX)) {
         T* Aout = reinterpret_cast<T*>(a.Aout) + field_base(a.foff, b, NN * npts);
         int8_t* sgn = a.sgn + (size_t)b * npts;
         const bool defer = DEFER && (flags & RF_PROJECT) && (flags & RF_FALLBACK);
@@ -354,7 +358,45 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L, VP>())) 
                     }
                 }
             }
-            if (!VP && (flags & RF_PROJECT)) {
+            if constexpr (RELAX) {
+                // dA/dt = Delta A - eps^-2 N(A), reaction step A - c N(A), c = dt / eps^2:
+                // GD-1 N(A) = U (Sigma - I) V^t = A - U V^t, GD-3 N(A) = A (A^t A - I)
+                if (flags & RF_RELAX) {
+                    nbad += all_finite<T, NN>(av) ? 0ull : 1ull;
+                    const T c = (T)a.relax_c;
+                    T qv[NN];
+                    if (a.relax_kind == 1) {
+                        int ds;
+                        if (project_point_fb<T, n>(av, qv, ds, (flags & RF_FALLBACK) != 0, a.sigma_fb)) ++nfb;
+#pragma unroll
+                        for (int k = 0; k < NN; ++k) qv[k] = av[k] - c * (av[k] - qv[k]);
+                    } else {
+                        T m[NN];
+#pragma unroll
+                        for (int i = 0; i < n; ++i)
+#pragma unroll
+                            for (int j = 0; j < n; ++j) {
+                                T v = 0;
+#pragma unroll
+                                for (int k = 0; k < n; ++k) v += av[k * n + i] * av[k * n + j];
+                                m[i * n + j] = v - (i == j ? (T)1 : (T)0);
+                            }
+#pragma unroll
+                        for (int i = 0; i < n; ++i)
+#pragma unroll
+                            for (int j = 0; j < n; ++j) {
+                                T v = 0;
+#pragma unroll
+                                for (int k = 0; k < n; ++k) v += av[i * n + k] * m[k * n + j];
+                                qv[i * n + j] = av[i * n + j] - c * v;
+                            }
+                    }
+                    finish(x, lrr, lir, qv, 1, s_old);
+#pragma unroll
+                    for (int k = 0; k < NN; ++k) av[k] = qv[k];
+                }
+            }
+            if (RM == RM_MBO && (flags & RF_PROJECT)) {
                 nbad += all_finite<T, NN>(av) ? 0ull : 1ull;
                 T qv[NN];
                 int ds;
@@ -486,7 +528,7 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L, VP>())) 
         dacc = block_reduce<OpSum>(dacc, red_d);
         if (tid == 0) a.dpart[(int64_t)b * gridDim.x + blockIdx.x] = dacc;
     }
-    if (flags & (RF_PROJECT | RF_VP_APPLY)) {
+    if (flags & (RF_PROJECT | RF_VP_APPLY | RF_RELAX)) {
         // The three counts of a workgroup are below 2^21 each and travel packed;
         // each wave adds its sums to the workgroup's LDS counters, and the last
         // wave to finish (the release/acquire on the done counter orders every
@@ -533,6 +575,13 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L, VP>())) 
 template <typename T, int MODE, int LOG2L>
 __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) col_pass(const ColArgs a)
 {
+    // modes that weight the spectrum (SYM), that multiply it and transform back
+    // (APPLY), and that write it back (STORE)
+    constexpr bool SYM = MODE == CM_HEAT || MODE == CM_ENERGY || MODE == CM_DTAU || MODE == CM_RESOLVENT ||
+                         MODE == CM_DIRICHLET;
+    constexpr bool APPLY = MODE == CM_HEAT || MODE == CM_DTAU || MODE == CM_RESOLVENT;
+    constexpr bool STORE = MODE != CM_ENERGY && MODE != CM_DIRICHLET;
+    constexpr bool LAPLACE = MODE == CM_RESOLVENT || MODE == CM_DIRICHLET;
     typedef typename cx<T>::type C;
     typedef FftShape<LOG2L> F;
     constexpr int Tn = F::Tn;
@@ -598,7 +647,15 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
         T* li = lib + (size_t)c * pitch;
         // symbol values of this thread's 8 modes, loaded before the transform
         T lam[8];
-        if (MODE == CM_HEAT || MODE == CM_ENERGY || MODE == CM_DTAU) {
+        if constexpr (LAPLACE) {
+            // -4 pi^2 |k|^2 = mu_row + mu_inner
+            const T muin = reinterpret_cast<const T*>(a.mu_inner)[tile0 + c];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const T mu = reinterpret_cast<const T*>(a.mu_row)[tt + e * Tn] + muin;
+                lam[e] = MODE == CM_RESOLVENT ? (T)a.rnorm / ((T)1 - (T)a.rdt * mu) : -mu;
+            }
+        } else if (SYM) {
             const T* lrow = reinterpret_cast<const T*>(a.lam_row) + b * a.lam_row_stride;
             const T lin = reinterpret_cast<const T*>(a.lam_inner)[b * a.lam_inner_stride + tile0 + c];
             const T muin = MODE == CM_DTAU ? reinterpret_cast<const T*>(a.mu_inner)[tile0 + c] : (T)0;
@@ -616,14 +673,14 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
         }
         if (MODE == CM_INVERSE) fft_wave<T, +1, LOG2L>(r, im, lr, li, tt, tw, true);
         else fft_wave<T, -1, LOG2L>(r, im, lr, li, tt, tw, true);
-        if (MODE == CM_HEAT || MODE == CM_ENERGY || MODE == CM_DTAU) {
+        if (SYM) {
             double acc = 0.0;
             if (a.epart) {
 #pragma unroll
                 for (int e = 0; e < 8; ++e)
                     acc += (double)lam[e] * ((double)r[e] * (double)r[e] + (double)im[e] * (double)im[e]);
             }
-            if (MODE == CM_HEAT || MODE == CM_DTAU) {
+            if (APPLY) {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     r[e] *= lam[e];
@@ -643,8 +700,8 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
                 }
             }
         }
-        if (MODE == CM_HEAT || MODE == CM_DTAU) fft_wave<T, +1, LOG2L>(r, im, lr, li, tt, tw, true);
-        if (MODE != CM_ENERGY) {
+        if (APPLY) fft_wave<T, +1, LOG2L>(r, im, lr, li, tt, tw, true);
+        if (STORE) {
             wave_lds_sync();  // the line's last exchange has been read
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -668,7 +725,15 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
         T* lr = reinterpret_cast<T*>(smem_raw);
         T* li = lr + (size_t)a.lds_col * TX;
         T lam[8];
-        if (MODE == CM_HEAT || MODE == CM_ENERGY || MODE == CM_DTAU) {
+        if constexpr (LAPLACE) {
+            // -4 pi^2 |k|^2 = mu_row + mu_inner
+            const T muin = reinterpret_cast<const T*>(a.mu_inner)[tile0 + tx];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const T mu = reinterpret_cast<const T*>(a.mu_row)[t + e * Tn] + muin;
+                lam[e] = MODE == CM_RESOLVENT ? (T)a.rnorm / ((T)1 - (T)a.rdt * mu) : -mu;
+            }
+        } else if (SYM) {
             const T* lrow = reinterpret_cast<const T*>(a.lam_row) + b * a.lam_row_stride;
             const T lin = reinterpret_cast<const T*>(a.lam_inner)[b * a.lam_inner_stride + tile0 + tx];
             const T muin = MODE == CM_DTAU ? reinterpret_cast<const T*>(a.mu_inner)[tile0 + tx] : (T)0;
@@ -691,7 +756,7 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
             fft_lines<T, +1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
         else
             fft_lines<T, -1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
-        if (MODE == CM_HEAT || MODE == CM_ENERGY || MODE == CM_DTAU) {
+        if (SYM) {
             double acc = 0.0;
             if (a.epart) {
 #pragma unroll
@@ -699,7 +764,7 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
                     acc += (double)lam[e] * ((double)r[0][e] * (double)r[0][e] +
                                              (double)im[0][e] * (double)im[0][e]);
             }
-            if (MODE == CM_HEAT || MODE == CM_DTAU) {
+            if (APPLY) {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     r[0][e] *= lam[e];
@@ -719,8 +784,8 @@ __global__ void __launch_bounds__(512, (sizeof(T) == 4 && LOG2L <= 9 ? 4 : 1)) c
                 }
             }
         }
-        if (MODE == CM_HEAT || MODE == CM_DTAU) fft_lines<T, +1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
-        if (MODE != CM_ENERGY) {
+        if (APPLY) fft_lines<T, +1, 1, LOG2L>(r, im, lr, li, 0, TX, tx, t, tw);
+        if (STORE) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 C v;

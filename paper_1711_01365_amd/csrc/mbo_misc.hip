@@ -127,6 +127,45 @@ __global__ void __launch_bounds__(256) so2_index_kernel(const T* A, int64_t N0, 
     if (threadIdx.x == 0) out[(size_t)b * gridDim.x + loop] = acc / 6.283185307179586476925286766559;
 }
 
+// Pointwise penalty of the relaxed energies, summed per workgroup in double:
+// kind 1 |A - U V^t|_F^2 / 2 (= sum (sigma_i - 1)^2 / 2, Lemma 1.1), kind 3
+// |A^t A - I|_F^2 / 4.
+template <typename T, int n>
+__global__ void __launch_bounds__(256) penalty_kernel(const T* A, int64_t npts, int kind, double* part)
+{
+    __shared__ double red_d[64];
+    const int b = blockIdx.y;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (p < npts) {
+        double a[n * n];
+#pragma unroll
+        for (int k = 0; k < n * n; ++k) a[k] = (double)A[((size_t)b * n * n + k) * npts + p];
+        if (kind == 1) {
+            double q[n * n], smin;
+            int ds;
+            project_point<double, n>(a, q, ds, smin);
+#pragma unroll
+            for (int k = 0; k < n * n; ++k) s += (a[k] - q[k]) * (a[k] - q[k]);
+            s *= 0.5;
+        } else {
+#pragma unroll
+            for (int i = 0; i < n; ++i)
+#pragma unroll
+                for (int j = 0; j < n; ++j) {
+                    double m = 0.0;
+#pragma unroll
+                    for (int k = 0; k < n; ++k) m += a[k * n + i] * a[k * n + j];
+                    m -= (i == j ? 1.0 : 0.0);
+                    s += m * m;
+                }
+            s *= 0.25;
+        }
+    }
+    s = block_reduce<OpSum>(s, red_d);
+    if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = s;
+}
+
 __global__ void fill_u64(unsigned long long* p, int64_t count, unsigned long long v)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -227,6 +266,41 @@ static hipError_t vjp_dispatch(int n, const VjpArgs& a, int batch, hipStream_t s
 hipError_t launch_vjp(int prec, int n, const VjpArgs& a, int batch, hipStream_t st)
 {
     return prec == 0 ? vjp_dispatch<double>(n, a, batch, st) : vjp_dispatch<float>(n, a, batch, st);
+}
+
+hipError_t launch_penalty(int prec, int n, const void* A, int64_t npts, int batch, int kind, double* part,
+                          hipStream_t st)
+{
+    const dim3 g((unsigned)((npts + 255) / 256), (unsigned)batch), bl(256);
+#define MBO_PEN(T, N)                                                                          \
+    hipLaunchKernelGGL((penalty_kernel<T, N>), g, bl, 0, st, (const T*)A, npts, kind, part); \
+    break;
+    if (prec == 0) {
+        switch (n) {
+        case 1: MBO_PEN(double, 1)
+        case 2: MBO_PEN(double, 2)
+        case 3: MBO_PEN(double, 3)
+        case 4: MBO_PEN(double, 4)
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (n) {
+        case 1: MBO_PEN(float, 1)
+        case 2: MBO_PEN(float, 2)
+        case 3: MBO_PEN(float, 3)
+        case 4: MBO_PEN(float, 4)
+        default: return hipErrorInvalidValue;
+        }
+    }
+#undef MBO_PEN
+    return hipGetLastError();
+}
+
+hipError_t launch_row_relax(int prec, int n, int log2L, const RowArgs& a, dim3 grid, dim3 block, size_t lds,
+                            hipStream_t st, bool prepare)
+{
+    return prec == 0 ? launch_row_relax_f64(n, log2L, a, grid, block, lds, st, prepare)
+                     : launch_row_relax_f32(n, log2L, a, grid, block, lds, st, prepare);
 }
 
 hipError_t launch_so2_index(int prec, const void* A, int64_t N0, int64_t N1, int batch, int axis, double* out,

@@ -11,9 +11,9 @@ static hipError_t vprow_n(int log2L, const RowArgs& a, dim3 g, dim3 bl, size_t l
 #define MBO_VPROW_CASE(LG)                                                                           \
     {                                                                                                \
         if (prepare)                                                                                 \
-            return hipFuncSetAttribute(reinterpret_cast<const void*>(&row_pass<float, n, LG, true>),    \
+            return hipFuncSetAttribute(reinterpret_cast<const void*>(&row_pass<float, n, LG, RM_VOLUME>),    \
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);       \
-        hipLaunchKernelGGL((row_pass<float, n, LG, true>), g, bl, lds, st, a);                        \
+        hipLaunchKernelGGL((row_pass<float, n, LG, RM_VOLUME>), g, bl, lds, st, a);                        \
         return hipGetLastError();                                                                    \
     }
     MBO_LOG2L_SWITCH(log2L, MBO_VPROW_CASE)

@@ -20,6 +20,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmbo.so")
 
 F64, F32, F32_F64FALLBACK = 0, 1, 2
+GD1, GD3 = 1, 3
 _STATUS = {0: "MBO_OK", 1: "MBO_ERR_INVALID_ARG", 2: "MBO_ERR_UNSUPPORTED", 3: "MBO_ERR_ALLOC",
            4: "MBO_ERR_HIP", 5: "MBO_ERR_NONFINITE"}
 
@@ -29,8 +30,8 @@ EXPORTS = ("mbo_plan", "mbo_plan_destroy", "mbo_plan_set_tau", "mbo_plan_set_str
            "mbo_plan_set_timing", "mbo_last_timing", "mbo_diffuse", "mbo_project", "mbo_iterate",
            "mbo_energy", "mbo_project_vjp", "mbo_diffuse_dtau", "mbo_plan_batched", "mbo_plan_tuning",
            "mbo_plan_autotune", "mbo_step", "mbo_step_vjp", "mbo_volume_select",
-           "mbo_project_volume", "mbo_iterate_volume", "mbo_so2_index", "mbo_status_string",
-           "mbo_last_error")
+           "mbo_project_volume", "mbo_iterate_volume", "mbo_so2_index", "mbo_relaxed_flow",
+           "mbo_relaxed_energy", "mbo_status_string", "mbo_last_error")
 
 
 class FieldDesc(ctypes.Structure):
@@ -78,6 +79,8 @@ def load(path: str = LIB_PATH):
     lib.mbo_project_volume.argtypes = [vp, vp, vp, i64p, vp]
     lib.mbo_iterate_volume.argtypes = [vp, vp, ctypes.c_int, i64p, i64p, dp, i64p, i64p]
     lib.mbo_so2_index.argtypes = [vp, vp, dp, dp]
+    lib.mbo_relaxed_flow.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+    lib.mbo_relaxed_energy.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, dp]
     for f in EXPORTS:
         if f not in ("mbo_status_string", "mbo_last_error"):
             getattr(lib, f).restype = ctypes.c_int
@@ -310,6 +313,21 @@ class Plan:
         if logs:
             out.update(energy=en, flips=fl[:, :K], fallbacks=fb[:, :K])
         return out
+
+    # -- relaxed gradient flows GD-1 / GD-3 -------------------------------------
+    def relaxed_flow(self, A, steps: int, kind: int, eps: float, dt: float):
+        """In place: `steps` steps of GD-1 (kind GD1) or GD-3 (GD3), each an
+        implicit diffusion step then an explicit reaction step."""
+        _check(self._lib.mbo_relaxed_flow(self._h, self._field(A), int(steps), int(kind), float(eps),
+                                          float(dt)), self._h)
+        return A
+
+    def relaxed_energy(self, A, kind: int, eps: float):
+        """E_{1,eps} (GD1) or E_{2,eps} (GD3) per field."""
+        E = np.zeros(self.batch)
+        _check(self._lib.mbo_relaxed_energy(self._h, self._field(A), int(kind), float(eps),
+                                            E.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self._h)
+        return E if self.batch > 1 else float(E[0])
 
     def so2_index(self, A):
         """Section 6.1 index of the first-column field of an n = 2 field along the

@@ -136,3 +136,8 @@ def test_null_plan_is_rejected_by_volume_calls(lib):
 
 def test_null_plan_is_rejected_by_the_index(lib):
     assert lib.mbo_so2_index(None, None, None, None) == 1
+
+
+def test_null_plan_is_rejected_by_the_relaxed_flows(lib):
+    assert lib.mbo_relaxed_flow(None, None, 1, 1, 0.1, 1e-3) == 1
+    assert lib.mbo_relaxed_energy(None, None, 1, 0.1, None) == 1
