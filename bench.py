@@ -29,8 +29,9 @@ launch rules, FP64), the volume-preserving method of Section 7 (n = 3, 512^2
 Haar, 200 iterations; and the paper's example, the star-shaped defect with
 n = 2 on 1024^2, tau = 8 dx, 100 iterations; FP32 + fallback, the SO(n) volume
 of the initial field held fixed) and the gradient of 50 unrolled steps (n = 3,
-256^2, FP32 + fallback and FP64), forward and backward time; and the paper's
-three flat-torus examples (n = 2, 1024^2, FP32 + fallback) with their end states.
+256^2, FP32 + fallback and FP64), forward and backward time; the paper's three
+flat-torus examples (n = 2, 1024^2, FP32 + fallback) with their end states; and
+the relaxed gradient flows GD-1 / GD-3 (n = 3, 512^2, 200 steps).
 
     python bench.py --volume-only [--steps K] [--warmup W]
 
@@ -270,6 +271,39 @@ def run_examples(steps):
     return out
 
 
+def run_relaxed(steps):
+    """The relaxed gradient flows GD-1 and GD-3 (n = 3, 512^2 Haar field,
+    FP32 + FP64 fallback, eps = 4 dx, dt = 0.1 eps^2, 200 steps) through their
+    captured graph: step rate and the energy before / after."""
+    import torch
+    from paper_1711_01365_amd import inputs, mbo
+    w = inputs.HAAR_512
+    eps = 4.0 / w.grid[0]
+    dt = 0.1 * eps * eps
+    K = 200
+    A0 = torch.tensor(w.field(), dtype=torch.float32, device="cuda")
+    A = A0.clone()
+    plan = mbo.Plan(w.grid, w.n, w.tau, precision=mbo.F32_F64FALLBACK)
+    plan.autotune()
+    out = {}
+    for name, kind in (("gd1", mbo.GD1), ("gd3", mbo.GD3)):
+        A.copy_(A0)
+        plan.relaxed_flow(A, K, kind, eps, dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            A.copy_(A0)
+            plan.relaxed_flow(A, K, kind, eps, dt)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out[name] = {"workload": "n3_512x512_haar_eps%.4g_dt%.3g_%dsteps_f32_f64fallback" % (eps, dt, K),
+                     "value": w.points * K * steps / sec, "unit": "point-steps/s",
+                     "us_per_step": 1e6 * sec / (steps * K),
+                     "energy_first_last": [plan.relaxed_energy(A0, kind, eps), plan.relaxed_energy(A, kind, eps)]}
+    plan.close()
+    return out
+
+
 def run_adjoint(precision, reps):
     """Gradients of K = 50 unrolled steps (n = 3, 256^2, checkpoint every 10):
     forward and backward wall time of the autograd function."""
@@ -365,7 +399,7 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the legs reported beside the main line (2048^2 control, 3-D, "
-                         "batched, volume-preserving, paper examples, adjoint)")
+                         "batched, volume-preserving, paper examples, relaxed flows, adjoint)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--volume-only", action="store_true",
                     help="only the volume-preserving legs (for profiling them)")
@@ -459,6 +493,10 @@ def main():
         for k, r in out["paper_examples"].items():
             log("paper example %s: %.3e point-iter/s, %.1f us/iteration, end: %d SO(2) points, index %s"
                 % (k, r["value"], r["us_per_iteration"], r["so2_points_end"], r["index_end"]))
+        out["relaxed_flows"] = run_relaxed(3)
+        for k, r in out["relaxed_flows"].items():
+            log("relaxed flow %s: %.3e point-steps/s, %.1f us/step, E %.4g -> %.4g"
+                % (k, r["value"], r["us_per_step"], r["energy_first_last"][0], r["energy_first_last"][1]))
         out["adjoint"] = {"f32_f64fallback": run_adjoint(mbo.F32_F64FALLBACK, 2),
                           "f64": run_adjoint(mbo.F64, 2)}
         log("adjoint K=50 256^2: fp32+fb fwd %.1f ms bwd %.1f ms, fp64 fwd %.1f ms bwd %.1f ms"
