@@ -37,6 +37,14 @@ What each function follows (Osting & Wang, arXiv:1711.01365):
                   (reaction U (Sigma - I) V^t) and GD-3 (A (A^t A - I)) by an
                   implicit diffusion step then an explicit reaction step, and
                   the energies E_{1,eps}, E_{2,eps} they descend.
+  * ``band_T`` / ``band_width``  Theorem 5.2's tail mass T and the band width
+                  w_b with T(w_b / 2 sqrt(tau)) = eps.
+  * ``cheb_rule``  Chebyshev-point rule on [0, 1] (Fejer's first rule).
+  * ``sphere_band``  the closest-point sample set of a sphere (Algorithm 2,
+                  step 1): band cells, quadrature points, weights, closest points.
+  * ``surface_diffuse`` / ``surface_iterate``  the closest-point surface
+                  diffusion step by direct quadrature of the free-space heat
+                  kernel, and Algorithm 1 on the sphere with it.
   * ``dft_naive`` / ``fft``   the discrete Fourier transform by definition and
                   by radix-2 Cooley-Tukey (cross-checked against each other).
 """
@@ -106,11 +114,23 @@ def _load():
                                      ctypes.c_double, _d, ctypes.c_int]
     lib.orc_relaxed_energy.argtypes = [ctypes.c_int, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                        _d, _d]
+    lib.orc_band_T.argtypes = [ctypes.c_double]
+    lib.orc_band_T.restype = ctypes.c_double
+    lib.orc_band_width.argtypes = [ctypes.c_double, ctypes.c_double]
+    lib.orc_band_width.restype = ctypes.c_double
+    lib.orc_cheb_rule.argtypes = [ctypes.c_int, _d, _d]
+    lib.orc_cheb_rule.restype = None
+    lib.orc_sphere_band.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double, _i64,
+                                    _i64, _d, _d, _d]
+    lib.orc_surface_diffuse.argtypes = [ctypes.c_int64, _d, _d, _d, ctypes.c_int, ctypes.c_double, _d, _d]
+    lib.orc_surface_iterate.argtypes = [ctypes.c_int64, _d, _d, _d, ctypes.c_int, ctypes.c_double, _d,
+                                        ctypes.c_int, _i64]
     lib.orc_num_threads.argtypes = []
     for f in ("orc_dft_naive", "orc_fft", "orc_heat", "orc_project", "orc_det_sign",
               "orc_energy", "orc_iterate", "orc_num_threads", "orc_heat_dtau", "orc_project_vjp",
               "orc_unroll_grad", "orc_volume_select", "orc_volume_project",
-              "orc_iterate_volume", "orc_relaxed_flow", "orc_relaxed_energy"):
+              "orc_iterate_volume", "orc_relaxed_flow", "orc_relaxed_energy", "orc_sphere_band",
+              "orc_surface_diffuse", "orc_surface_iterate"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -378,3 +398,67 @@ def relaxed_energy(A: np.ndarray, kind: int, eps: float) -> float:
     _check(lib.orc_relaxed_energy(d, _ptr(g, _i64), n, int(kind), float(eps), _ptr(A), _ptr(E)),
            "relaxed_energy")
     return float(E[0])
+
+
+def band_T(x: float) -> float:
+    """T(x) of Theorem 5.2."""
+    return float(_load().orc_band_T(float(x)))
+
+
+def band_width(tau: float, eps: float) -> float:
+    """w_b with T(w_b / (2 sqrt(tau))) = eps (Theorem 5.2)."""
+    return float(_load().orc_band_width(float(tau), float(eps)))
+
+
+def cheb_rule(p: int):
+    """(nodes, weights) of the p-point Chebyshev-point rule on [0, 1]."""
+    x = np.zeros(p)
+    w = np.zeros(p)
+    _load().orc_cheb_rule(int(p), _ptr(x), _ptr(w))
+    return x, w
+
+
+def sphere_band(R: float, dx: float, p: int, tau: float, eps: float):
+    """Sample set of the sphere of radius R: dict with xq, xc ([3, m]), w ([m]),
+    cells (band cell count), wb (band width)."""
+    lib = _load()
+    wb = band_width(tau, eps)
+    cnt = np.zeros(1, dtype=np.int64)
+    cells = np.zeros(1, dtype=np.int64)
+    _check(lib.orc_sphere_band(float(R), float(dx), int(p), wb, _ptr(cnt, _i64), _ptr(cells, _i64), None,
+                               None, None), "sphere_band")
+    m = int(cnt[0])
+    xq = np.zeros((3, m))
+    xc = np.zeros((3, m))
+    w = np.zeros(m)
+    _check(lib.orc_sphere_band(float(R), float(dx), int(p), wb, _ptr(cnt, _i64), None, _ptr(xq), _ptr(xc),
+                               _ptr(w)), "sphere_band")
+    return {"xq": xq, "xc": xc, "w": w, "cells": int(cells[0]), "wb": wb}
+
+
+def surface_diffuse(band: dict, A: np.ndarray, tau: float) -> np.ndarray:
+    """Closest-point surface diffusion of A (n, n, m) over the band's samples."""
+    lib = _load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n, m = A.shape[0], A.shape[2]
+    out = np.empty_like(A)
+    xq = np.ascontiguousarray(band["xq"])
+    xc = np.ascontiguousarray(band["xc"])
+    w = np.ascontiguousarray(band["w"])
+    _check(lib.orc_surface_diffuse(m, _ptr(xq), _ptr(xc), _ptr(w), n, float(tau), _ptr(A), _ptr(out)),
+           "surface_diffuse")
+    return out
+
+
+def surface_iterate(band: dict, A0: np.ndarray, tau: float, K: int):
+    """K steps of Algorithm 1 on the sphere.  Returns (A, flips [K])."""
+    lib = _load()
+    A = np.ascontiguousarray(A0, dtype=np.float64).copy()
+    n, m = A.shape[0], A.shape[2]
+    fl = np.zeros(max(K, 1), dtype=np.int64)
+    xq = np.ascontiguousarray(band["xq"])
+    xc = np.ascontiguousarray(band["xc"])
+    w = np.ascontiguousarray(band["w"])
+    _check(lib.orc_surface_iterate(m, _ptr(xq), _ptr(xc), _ptr(w), n, float(tau), _ptr(A), int(K),
+                                   _ptr(fl, _i64)), "surface_iterate")
+    return A, fl[:K]

@@ -3,7 +3,8 @@
  * orthogonal matrix-valued fields on flat tori (Osting & Wang, arXiv:1711.01365:
  * Algorithm 1, Lemma 1.1, Section 4, Section 5.1; the volume-preserving
  * variant of Section 7: Lemmas 7.1, 7.2; the relaxed gradient flows GD-1 and
- * GD-3 of Section 1 with their energies).
+ * GD-3 of Section 1 with their energies; surface diffusion on a sphere by the
+ * closest point method of Section 5.2, Theorem 5.2).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call
  * this file: only the test suite, the smoke check and the CPU-baseline leg of
@@ -917,6 +918,141 @@ int orc_relaxed_energy(int d, const int64_t* N, int n, int kind, double eps, con
     *E = dir + pen;
     free(re); free(im); free(t);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Surface diffusion on a sphere by the closest point method (Section 5.2)   */
+/* ------------------------------------------------------------------------ */
+
+/* T(x) = (2x / sqrt(pi)) exp(-x^2) + erfc(x) of Theorem 5.2: the heat-kernel
+ * mass outside a ball of radius 2 x sqrt(tau). */
+double orc_band_T(double x) { return 2.0 * x / sqrt(ORC_PI) * exp(-x * x) + erfc(x); }
+
+/* The band width w_b with T(w_b / (2 sqrt(tau))) = eps (T decreases from 1 at
+ * 0), by bisection. */
+double orc_band_width(double tau, double eps)
+{
+    double lo = 0.0, hi = 40.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (orc_band_T(mid) > eps) lo = mid;
+        else hi = mid;
+    }
+    return 2.0 * sqrt(tau) * 0.5 * (lo + hi);
+}
+
+/* p-point rule on [0, 1] at the Chebyshev points (the zeros of T_p) with the
+ * weights that integrate every polynomial of degree < p exactly (Fejer's first
+ * rule), nodes in ascending order. */
+void orc_cheb_rule(int p, double* x, double* w)
+{
+    for (int k = 0; k < p; ++k) {
+        const double th = ORC_PI * (2.0 * (p - 1 - k) + 1.0) / (2.0 * p); /* ascending cos */
+        double s = 0.0;
+        for (int j = 1; j <= p / 2; ++j) s += cos(2.0 * j * th) / (4.0 * j * j - 1.0);
+        x[k] = 0.5 * (1.0 + cos(th));
+        w[k] = 0.5 * (2.0 / p) * (1.0 - 2.0 * s);
+    }
+}
+
+/* The closest-point sample set of a sphere of radius R centred at the origin
+ * (Algorithm 2, step 1): grid points x_g = dx (i, j, k) with | |x_g| - R | < w_b,
+ * in lexicographic (i, j, k) order; in each cell x_g + [0, dx]^3 the p^3
+ * points of the rule above (lexicographic, first coordinate slowest), their
+ * weights dx^3 w_a w_b w_c, and their closest points R x / |x| on the sphere
+ * ((R, 0, 0) for x = 0).  With xq == NULL only counts: *count receives the
+ * number of sample points (p^3 per band cell) and *cells the band cells. */
+int orc_sphere_band(double R, double dx, int p, double wb, int64_t* count, int64_t* cells, double* xq,
+                    double* xc, double* wq)
+{
+    if (!(R > 0.0) || !(dx > 0.0) || p < 1 || p > 8 || !(wb > 0.0)) return -1;
+    double nx[8], nw[8];
+    orc_cheb_rule(p, nx, nw);
+    const int64_t lim = (int64_t)ceil((R + wb) / dx) + 1;
+    int64_t c = 0, q = 0;
+    for (int64_t i = -lim; i <= lim; ++i)
+        for (int64_t j = -lim; j <= lim; ++j)
+            for (int64_t k = -lim; k <= lim; ++k) {
+                const double gx = dx * (double)i, gy = dx * (double)j, gz = dx * (double)k;
+                const double d = fabs(sqrt(gx * gx + gy * gy + gz * gz) - R);
+                if (!(d < wb)) continue;
+                ++c;
+                for (int a = 0; a < p; ++a)
+                    for (int b = 0; b < p; ++b)
+                        for (int e = 0; e < p; ++e) {
+                            if (xq) {
+                                const double x = gx + dx * nx[a], y = gy + dx * nx[b], z = gz + dx * nx[e];
+                                const double r = sqrt(x * x + y * y + z * z);
+                                xq[q] = x;
+                                xq[*count + q] = y;
+                                xq[2 * *count + q] = z;
+                                xc[q] = r > 0.0 ? R * x / r : R;
+                                xc[*count + q] = r > 0.0 ? R * y / r : 0.0;
+                                xc[2 * *count + q] = r > 0.0 ? R * z / r : 0.0;
+                                wq[q] = dx * dx * dx * nw[a] * nw[b] * nw[e];
+                            }
+                            ++q;
+                        }
+            }
+    if (!xq) {
+        *count = q;
+        if (cells) *cells = c;
+    }
+    return 0;
+}
+
+/* One step of surface diffusion by the closest point method (eqs.
+ * surface_diffusion_extended, freeSpace): the field A (entry-planar [n*n][m],
+ * its value at sample q being A(x_q^c), i.e. already the constant extension
+ * to x_q) is convolved with the free-space heat kernel
+ * G_tau(x) = (4 pi tau)^{-3/2} exp(-|x|^2 / (4 tau)) by the quadrature of the
+ * band, and the result is taken at the closest points:
+ *   out(c) = sum_q w_q G_tau(x_c^c - x_q) A(q).
+ * Direct sums, O(m^2). */
+int orc_surface_diffuse(int64_t m, const double* xq, const double* xc, const double* wq, int n, double tau,
+                        const double* A, double* out)
+{
+    if (m < 0 || n < 1 || n > 4 || !(tau > 0.0)) return -1;
+    const int nn = n * n;
+    const double norm = pow(4.0 * ORC_PI * tau, -1.5);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t c = 0; c < m; ++c) {
+        double acc[16] = {0.0};
+        const double cx = xc[c], cy = xc[m + c], cz = xc[2 * m + c];
+        for (int64_t q = 0; q < m; ++q) {
+            const double dx = cx - xq[q], dy = cy - xq[m + q], dz = cz - xq[2 * m + q];
+            const double g = wq[q] * exp(-(dx * dx + dy * dy + dz * dz) / (4.0 * tau));
+            for (int e = 0; e < nn; ++e) acc[e] += g * A[e * m + q];
+        }
+        for (int e = 0; e < nn; ++e) out[e * m + c] = norm * acc[e];
+    }
+    return 0;
+}
+
+/* The MBO iteration on the sphere (Algorithm 1 with the diffusion step above):
+ * K steps of A <- P(S_tau A), P the pointwise projection of Lemma 1.1.
+ * flips (nullable, [K]) counts the samples whose det sign changed. */
+int orc_surface_iterate(int64_t m, const double* xq, const double* xc, const double* wq, int n, double tau,
+                        double* A, int K, int64_t* flips)
+{
+    if (m < 0 || n < 1 || n > 4 || !(tau > 0.0) || K < 0) return -1;
+    const int64_t nn = (int64_t)n * n;
+    double* T = (double*)malloc(sizeof(double) * (size_t)(m * nn + 1));
+    int8_t* sp = (int8_t*)malloc((size_t)m + 1);
+    int8_t* sn = (int8_t*)malloc((size_t)m + 1);
+    orc_det_sign(m, n, A, sp);
+    int rc = 0;
+    for (int s = 0; s < K && rc == 0; ++s) {
+        rc = orc_surface_diffuse(m, xq, xc, wq, n, tau, A, T);
+        if (rc) break;
+        orc_project(m, n, T, A, sn, NULL, NULL);
+        int64_t f = 0;
+        for (int64_t i = 0; i < m; ++i) f += sn[i] != sp[i];
+        if (flips) flips[s] = f;
+        memcpy(sp, sn, (size_t)m);
+    }
+    free(T); free(sp); free(sn);
+    return rc;
 }
 
 /* Number of threads the OpenMP loops above use (1 without OpenMP). */
