@@ -125,12 +125,13 @@ def _load():
     lib.orc_surface_diffuse.argtypes = [ctypes.c_int64, _d, _d, _d, ctypes.c_int, ctypes.c_double, _d, _d]
     lib.orc_surface_iterate.argtypes = [ctypes.c_int64, _d, _d, _d, ctypes.c_int, ctypes.c_double, _d,
                                         ctypes.c_int, _i64]
+    lib.orc_heat_at.argtypes = [ctypes.c_int64, _d, _d, ctypes.c_int, ctypes.c_double, _d, ctypes.c_int64, _d, _d]
     lib.orc_num_threads.argtypes = []
     for f in ("orc_dft_naive", "orc_fft", "orc_heat", "orc_project", "orc_det_sign",
               "orc_energy", "orc_iterate", "orc_num_threads", "orc_heat_dtau", "orc_project_vjp",
               "orc_unroll_grad", "orc_volume_select", "orc_volume_project",
               "orc_iterate_volume", "orc_relaxed_flow", "orc_relaxed_energy", "orc_sphere_band",
-              "orc_surface_diffuse", "orc_surface_iterate"):
+              "orc_surface_diffuse", "orc_surface_iterate", "orc_heat_at"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -447,6 +448,20 @@ def surface_diffuse(band: dict, A: np.ndarray, tau: float) -> np.ndarray:
     w = np.ascontiguousarray(band["w"])
     _check(lib.orc_surface_diffuse(m, _ptr(xq), _ptr(xc), _ptr(w), n, float(tau), _ptr(A), _ptr(out)),
            "surface_diffuse")
+    return out
+
+
+def heat_at(band: dict, A: np.ndarray, tau: float, xt: np.ndarray) -> np.ndarray:
+    """The band's heat convolution of A (n, n, m) at target points xt [3, nt]:
+    (n, n, nt)."""
+    lib = _load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n, m = A.shape[0], A.shape[2]
+    xt = np.ascontiguousarray(xt, dtype=np.float64)
+    nt = xt.shape[1]
+    out = np.empty((n, n, nt))
+    _check(lib.orc_heat_at(m, _ptr(np.ascontiguousarray(band["xq"])), _ptr(np.ascontiguousarray(band["w"])), n,
+                           float(tau), _ptr(A), nt, _ptr(xt), _ptr(out)), "heat_at")
     return out
 
 

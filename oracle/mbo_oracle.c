@@ -1029,6 +1029,30 @@ int orc_surface_diffuse(int64_t m, const double* xq, const double* xc, const dou
     return 0;
 }
 
+/* The same convolution taken at nt arbitrary target points xt ([3][nt]):
+ *   out(t) = sum_q w_q G_tau(x_t - x_q) A(q),   out entry-planar [n*n][nt].
+ * At xt = the closest points this is orc_surface_diffuse restricted to the
+ * chosen targets (large bands, sampled outputs).  O(m nt). */
+int orc_heat_at(int64_t m, const double* xq, const double* wq, int n, double tau, const double* A, int64_t nt,
+                const double* xt, double* out)
+{
+    if (m < 0 || nt < 0 || n < 1 || n > 4 || !(tau > 0.0)) return -1;
+    const int nn = n * n;
+    const double norm = pow(4.0 * ORC_PI * tau, -1.5);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < nt; ++t) {
+        double acc[16] = {0.0};
+        const double cx = xt[t], cy = xt[nt + t], cz = xt[2 * nt + t];
+        for (int64_t q = 0; q < m; ++q) {
+            const double dx = cx - xq[q], dy = cy - xq[m + q], dz = cz - xq[2 * m + q];
+            const double g = wq[q] * exp(-(dx * dx + dy * dy + dz * dz) / (4.0 * tau));
+            for (int e = 0; e < nn; ++e) acc[e] += g * A[e * m + q];
+        }
+        for (int e = 0; e < nn; ++e) out[e * nt + t] = norm * acc[e];
+    }
+    return 0;
+}
+
 /* The MBO iteration on the sphere (Algorithm 1 with the diffusion step above):
  * K steps of A <- P(S_tau A), P the pointwise projection of Lemma 1.1.
  * flips (nullable, [K]) counts the samples whose det sign changed. */

@@ -152,3 +152,22 @@ def test_sphere_experiment_shrinks_the_octant():
     A, fl = oracle.surface_iterate(b, A0, tau, 6)
     n1 = int((oracle.det_sign(A) < 0).sum())
     assert n1 < n0 and fl.sum() == n0 - n1
+
+
+def test_heat_at_targets():
+    """The convolution at arbitrary targets: at the closest points it is the
+    surface diffusion step; for one source of weight 1 it is G_tau itself."""
+    tau = 0.01
+    b = oracle.sphere_band(1.0, 0.15, 1, tau, 1e-6)
+    m = b["w"].size
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((2, 2, m))
+    idx = rng.choice(m, 40, replace=False)
+    full = oracle.surface_diffuse(b, A, tau)
+    at = oracle.heat_at(b, A, tau, b["xc"][:, idx])
+    assert np.abs(at - full[:, :, idx]).max() < 1e-13 * np.abs(full).max()
+    one = {"xq": np.array([[0.1], [0.2], [-0.3]]), "w": np.array([1.0])}
+    xt = np.array([[0.0, 0.4], [0.0, -0.1], [0.0, 0.05]])
+    g = oracle.heat_at(one, np.ones((1, 1, 1)), tau, xt)[0, 0]
+    r2 = ((xt - one["xq"]) ** 2).sum(axis=0)
+    assert np.abs(g - (4 * np.pi * tau) ** -1.5 * np.exp(-r2 / (4 * tau))).max() < 1e-12 * g.max()
