@@ -304,6 +304,51 @@ def run_relaxed(steps):
     return out
 
 
+def run_surface(steps, precisions=None):
+    """The sphere experiment of Section 6.2 (unit sphere, dx = 0.05, p = 3,
+    tau = 0.005, eps = 1e-6, n = 3, 20 MBO steps from the printed matrices by
+    octant): sample-steps/s of the closest-point MBO iteration, the time of one
+    diffusion step, and the SO^-(3) sample count before / after."""
+    import numpy as np
+    import torch
+    from paper_1711_01365_amd import inputs, mbo
+    w = inputs.SPHERE_PAPER
+    out = {}
+    for name, prec in (precisions or (("f32_f64fallback", mbo.F32_F64FALLBACK), ("f64", mbo.F64))):
+        t0 = time.perf_counter()
+        s = mbo.SphereSurface(w.R, w.dx, w.p, w.tau, w.eps, w.n, precision=prec)
+        setup = time.perf_counter() - t0
+        xq, xc, wts = s.points()
+        dt = torch.float64 if prec == mbo.F64 else torch.float32
+        A0 = torch.tensor(inputs.sphere_octant_field(xc), dtype=dt, device="cuda")
+        A = A0.clone()
+        B = torch.empty_like(A)
+        s.iterate(A, 1)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            A.copy_(A0)
+            s.iterate(A, w.iters)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(5):
+            s.diffuse(A0, B)
+        ev1.record()
+        torch.cuda.synchronize()
+        det = np.linalg.det(np.moveaxis(A.double().cpu().numpy(), 2, 0))
+        x, y, z = xc
+        out[name] = {"workload": "%s_n3_%dit_%s" % (w.name, w.iters, name),
+                     "value": s.m * w.iters * steps / sec, "unit": "sample-steps/s",
+                     "samples": s.m, "band_cells": s.cells, "grid": s.grid,
+                     "us_per_step": 1e6 * sec / (steps * w.iters),
+                     "diffuse_us": 1e3 * ev0.elapsed_time(ev1) / 5, "setup_s": setup,
+                     "so3minus_samples_first_last": [int(((x < 0) & (y < 0) & (z > 0)).sum()), int((det < 0).sum())]}
+        s.close()
+    return out
+
+
 def run_adjoint(precision, reps):
     """Gradients of K = 50 unrolled steps (n = 3, 256^2, checkpoint every 10):
     forward and backward wall time of the autograd function."""
@@ -399,10 +444,12 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the legs reported beside the main line (2048^2 control, 3-D, "
-                         "batched, volume-preserving, paper examples, relaxed flows, adjoint)")
+                         "batched, volume-preserving, paper examples, relaxed flows, sphere, adjoint)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--volume-only", action="store_true",
                     help="only the volume-preserving legs (for profiling them)")
+    ap.add_argument("--surface-only", action="store_true",
+                    help="only the sphere leg, float surface (for profiling it)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -426,6 +473,11 @@ def main():
             r = run_volume(wv, args.steps, args.warmup)
             log("volume-preserving %s: %.3e point-iter/s, %.1f us/iteration (plain %.1f us)"
                 % (wv.name, r["value"], r["us_per_iteration"], r["plain_mbo_us_per_iteration"]))
+        return
+    if args.surface_only:
+        r = run_surface(args.steps, (("f32_f64fallback", mbo.F32_F64FALLBACK),))["f32_f64fallback"]
+        log("sphere %s: %.3e sample-steps/s, %.1f us/step, diffuse %.1f us, m=%d grid=%d^3"
+            % (r["workload"], r["value"], r["us_per_step"], r["diffuse_us"], r["samples"], r["grid"]))
         return
     w = inputs.HAAR_512
     log("workload %s: n=%d grid=%s tau=%g iterations=%d" % (w.name, w.n, w.grid, w.tau, w.iters))
@@ -497,6 +549,11 @@ def main():
         for k, r in out["relaxed_flows"].items():
             log("relaxed flow %s: %.3e point-steps/s, %.1f us/step, E %.4g -> %.4g"
                 % (k, r["value"], r["us_per_step"], r["energy_first_last"][0], r["energy_first_last"][1]))
+        out["sphere"] = run_surface(1)
+        for k, r in out["sphere"].items():
+            log("sphere %s: %.3e sample-steps/s, %.1f us/step, diffuse %.1f us, m=%d grid=%d^3, SO-(3) %s"
+                % (k, r["value"], r["us_per_step"], r["diffuse_us"], r["samples"], r["grid"],
+                   r["so3minus_samples_first_last"]))
         out["adjoint"] = {"f32_f64fallback": run_adjoint(mbo.F32_F64FALLBACK, 2),
                           "f64": run_adjoint(mbo.F64, 2)}
         log("adjoint K=50 256^2: fp32+fb fwd %.1f ms bwd %.1f ms, fp64 fwd %.1f ms bwd %.1f ms"

@@ -176,6 +176,72 @@ mbo_status mbo_relaxed_flow(mbo_plan_t plan, void* A, int steps, int kind, doubl
  * over grid points of the penalty.  E: host [batch].  Synchronises. */
 mbo_status mbo_relaxed_energy(mbo_plan_t plan, const void* A, int kind, double eps, double* E);
 
+/* ---------------------------------------------------------------------------
+ * Surface diffusion on a closed surface, the sphere of radius R centred at the
+ * origin, by the closest point method (Section 5.2): the diffusion step of
+ * Algorithm 1 on the surface is the free-space heat convolution of the field
+ * extended constant along normals, evaluated at the closest points,
+ *     (S_tau A)(c_j) = sum_q w_q G_tau(c_j - x_q) A(c(x_q)),
+ *     G_tau(r) = (4 pi tau)^{-3/2} exp(-|r|^2 / (4 tau)),
+ * over quadrature points x_q that fill a band of half width w_b around the
+ * surface (Theorem 5.2: w_b solves T(w_b / (2 sqrt tau)) = eps with
+ * T(x) = 2 x e^{-x^2} / sqrt(pi) + erfc(x)).  The band is the union of the
+ * grid cells [dx i, dx (i+1)) x ... whose corner dx (i, j, k) lies within w_b
+ * of the sphere; each cell holds p^3 points, the tensor product of p Chebyshev
+ * points (zeros of T_p mapped to [0, 1]) with the Fejer weights, times dx^3.
+ * Samples are in canonical order: cells lexicographic in (i, j, k), then the
+ * points of a cell lexicographic in their Chebyshev indices.  Every sample q is
+ * both a quadrature point x_q and, through its closest point c_q = R x_q / |x_q|,
+ * a target: fields live at the samples, entry-planar [n*n][m] (entry (i, j) of
+ * sample q at (i n + j) m + q), in the surface's precision.
+ *
+ * The sum is not formed directly: the samples are spread onto a periodic
+ * Cartesian grid (a power of two per axis, at most 512) with the
+ * "exponential of semicircle" kernel, the grid is transformed by the FFT of a
+ * 3-D plan, multiplied by the heat symbol divided by the kernel's transform,
+ * transformed back and interpolated at the closest points, with a gridding
+ * tolerance of max(eps / 10, 1e-11) (float surfaces: max(eps / 10, 1e-7)).
+ * The result then matches the sum to within about eps times the largest |A|
+ * entry (float surfaces: max(eps, 4e-6) times it).
+ * ------------------------------------------------------------------------- */
+typedef struct mbo_surface_s* mbo_surface_t;
+
+/* Build the sample set (host, FP64) and the device state of the sphere of
+ * radius R > 0 for band cells of size dx > 0, p in [1, 8] Chebyshev points per
+ * cell axis, diffusion time tau > 0, band tolerance eps in (0, 0.5), matrices
+ * of size n in [1, 4] and precision prec (MBO_F32_F64FALLBACK: float surface
+ * whose projection falls back to double near singular points).  hip_stream
+ * (hipStream_t, nullable) carries every later call.  MBO_ERR_UNSUPPORTED when
+ * the grid would need more than 512 points per axis (tau too small for the
+ * radius).  On error *out is NULL and mbo_surface_last_error(NULL) explains. */
+mbo_status mbo_surface_sphere(mbo_surface_t* out, double R, double dx, int p, double tau, double eps, int n,
+                              mbo_precision prec, void* hip_stream);
+
+/* Free the surface (synchronises its stream).  NULL is a no-op. */
+mbo_status mbo_surface_destroy(mbo_surface_t s);
+
+/* Sample count m, band cell count, grid points per axis, band half width w_b
+ * (each output nullable). */
+mbo_status mbo_surface_info(mbo_surface_t s, int64_t* samples, int64_t* cells, int* grid, double* band_width);
+
+/* Copy the sample set to host buffers (each nullable): quadrature points xq
+ * [3][m], closest points xc [3][m], weights w [m], FP64, canonical order. */
+mbo_status mbo_surface_points(mbo_surface_t s, double* xq, double* xc, double* w);
+
+/* A_out = S_tau A_in (device buffers [n*n][m], which must not alias).
+ * Asynchronous on the surface's stream; no NaN check. */
+mbo_status mbo_surface_diffuse(mbo_surface_t s, const void* A_in, void* A_out);
+
+/* K steps of Algorithm 1 on the surface in place on A (device [n*n][m]):
+ * A <- P(S_tau A), P the projection of Lemma 1.1 per sample.  flips (host,
+ * nullable, [K]): per step, the samples whose det sign changed.  Synchronises;
+ * MBO_ERR_NONFINITE when a NaN/Inf was met. */
+mbo_status mbo_surface_iterate(mbo_surface_t s, void* A, int K, int64_t* flips);
+
+/* Description of the last error on this surface (or of the last failed
+ * mbo_surface_sphere call when s is NULL). */
+const char* mbo_surface_last_error(mbo_surface_t s);
+
 /* Index of an SO(2)-valued field (Section 6.1), a diagnostic of the flat-torus
  * examples: for each field of an n = 2 plan on a 2-D grid, the winding of the
  * first column (A_00, A_10) of the matrices -- the vector field the paper draws;

@@ -6,6 +6,8 @@
 // iteration.  All device work goes to the plan's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1175,6 +1177,329 @@ bool use_graphs()
     return !(v && v[0] == '1');
 }
 
+
+// ---- surface diffusion on a sphere (closest point method) -------------------
+
+// T(x) of the band-width estimate: the heat-kernel mass outside the ball of
+// radius 2 x sqrt(tau) (Theorem 5.2).
+double band_tail(double x) { return 2.0 * x / std::sqrt(3.14159265358979323846) * std::exp(-x * x) + std::erfc(x); }
+
+// w_b with T(w_b / (2 sqrt(tau))) = eps (T falls from 1 at 0), by bisection.
+double band_width_of(double tau, double eps)
+{
+    double lo = 0.0, hi = 40.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        (band_tail(mid) > eps ? lo : hi) = mid;
+    }
+    return std::sqrt(tau) * (lo + hi);
+}
+
+// p Chebyshev points on [0, 1] (zeros of T_p, ascending) and the weights that
+// integrate polynomials of degree < p exactly (Fejer's first rule).
+void chebyshev_rule(int p, double* x, double* w)
+{
+    const double pi = 3.14159265358979323846;
+    for (int k = 0; k < p; ++k) {
+        const double th = pi * (2.0 * (p - 1 - k) + 1.0) / (2.0 * p);
+        double s = 0.0;
+        for (int j = 1; j <= p / 2; ++j) s += std::cos(2.0 * j * th) / (4.0 * j * j - 1.0);
+        x[k] = 0.5 * (1.0 + std::cos(th));
+        w[k] = (1.0 - 2.0 * s) / p;
+    }
+}
+
+// Gauss-Legendre rule on [-1, 1] by Newton's method on P_q.
+void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w)
+{
+    const double pi = 3.14159265358979323846;
+    x.assign((size_t)q, 0.0);
+    w.assign((size_t)q, 0.0);
+    for (int i = 0; i < q; ++i) {
+        double z = std::cos(pi * (i + 0.75) / (q + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= q; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = q * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[(size_t)i] = z;
+        w[(size_t)i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+}  // namespace
+
+struct mbo_surface_s {
+    mbo_plan_t grid = nullptr;  // 3-D plan of the periodic grid: workspace Z, passes, tables
+    int n = 3, p = 1, w = 6, Ng = 8, pk = 0;
+    mbo_precision prec = MBO_F64;
+    size_t esz = 8;
+    hipStream_t stream = nullptr;
+    double R = 1.0, dx = 0.1, tau = 0.01, eps = 1e-6, wb = 0.0, beta = 0.0, h = 0.0, y0 = 0.0;
+    int64_t m = 0, cells = 0;
+    std::vector<double> xq, xc, wq;  // canonical order, host
+    struct Bins {
+        void* pos = nullptr;
+        void* wts = nullptr;
+        int64_t* perm = nullptr;
+        int64_t* start = nullptr;
+        int* bin = nullptr;
+        int nbins = 0;
+    } spread, interp, cellbins;
+    // cell spreading (the default): nodes dx n_a and weight factors dx w_a per
+    // axis, union stencil width U, waves per workgroup (0: spread sample by
+    // sample instead)
+    void* nodes = nullptr;
+    void* nwts = nullptr;
+    int U = 0, cell_waves = 0;
+    void* tmp = nullptr;        // [n*n][m]
+    int8_t* sgn = nullptr;      // [m]
+    unsigned long long* counters = nullptr;
+    std::string err;
+};
+
+namespace {
+
+mbo_status sfail(mbo_surface_t s, mbo_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (s) s->err = buf;
+    else g_plan_error = buf;
+    return st;
+}
+
+#define SHIP(surf, expr)                                                                      \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return sfail(surf, e_ == hipErrorOutOfMemory ? MBO_ERR_ALLOC : MBO_ERR_HIP,       \
+                         "%s failed: %s", #expr, hipGetErrorString(e_));                      \
+    } while (0)
+
+void surface_free(mbo_surface_t s)
+{
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    free_dev(s->nodes);
+    free_dev(s->nwts);
+    for (auto* b : {&s->spread, &s->interp, &s->cellbins}) {
+        free_dev(b->pos);
+        free_dev(b->wts);
+        free_dev(b->perm);
+        free_dev(b->start);
+        free_dev(b->bin);
+    }
+    free_dev(s->tmp);
+    free_dev(s->sgn);
+    free_dev(s->counters);
+    if (s->grid) destroy(s->grid);
+    delete s;
+}
+
+// Upload T-typed copies of host doubles.
+mbo_status upload_as(mbo_surface_t s, void** dst, const std::vector<double>& h)
+{
+    SHIP(s, hipMalloc(dst, h.size() * s->esz + 8));
+    if (s->esz == 8) {
+        SHIP(s, hipMemcpy(*dst, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> f(h.size());
+        for (size_t i = 0; i < h.size(); ++i) f[i] = (float)h[i];
+        SHIP(s, hipMemcpy(*dst, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+    }
+    return MBO_OK;
+}
+
+// Sort the points pts ([3][m], canonical order) by their SURF_BIN^3 bin of the
+// grid and upload positions, weights (nullable), permutation, bin starts and
+// the coordinates of the non-empty bins.  The grid coordinate of a point is
+// computed here exactly as the kernels compute it (in T from the T-rounded
+// position), so that every stencil lies in its bin's tile.
+template <typename T>
+mbo_status build_bins_t(mbo_surface_t s, const std::vector<double>& pts, const std::vector<double>* wts,
+                        mbo_surface_s::Bins& B)
+{
+    const int64_t m = s->m;
+    const int nb = (s->Ng + SURF_BIN - 1) / SURF_BIN;
+    const T y0 = (T)s->y0, invh = (T)(1.0 / s->h);
+    std::vector<std::pair<int64_t, int64_t>> key((size_t)m);
+    for (int64_t q = 0; q < m; ++q) {
+        int64_t id = 0;
+        for (int a = 0; a < 3; ++a) {
+            const T u = ((T)pts[(size_t)(a * m + q)] - y0) * invh;
+            if (!(u >= (T)1 && u < (T)(s->Ng - 1)))
+                return sfail(s, MBO_ERR_INVALID_ARG, "sample %lld lies outside the grid", (long long)q);
+            const int bi = (int)std::floor(u / (T)SURF_BIN);
+            id = id * nb + bi;
+        }
+        key[(size_t)q] = {id, q};
+    }
+    std::stable_sort(key.begin(), key.end());
+    std::vector<int64_t> perm((size_t)m), start;
+    std::vector<int> bins;
+    std::vector<double> pos((size_t)(3 * m)), w;
+    if (wts) w.resize((size_t)m);
+    for (int64_t i = 0; i < m; ++i) {
+        const int64_t q = key[(size_t)i].second;
+        perm[(size_t)i] = q;
+        for (int a = 0; a < 3; ++a) pos[(size_t)(a * m + i)] = pts[(size_t)(a * m + q)];
+        if (wts) w[(size_t)i] = (*wts)[(size_t)q];
+        if (i == 0 || key[(size_t)i].first != key[(size_t)i - 1].first) {
+            start.push_back(i);
+            const int64_t id = key[(size_t)i].first;
+            bins.push_back((int)(id / ((int64_t)nb * nb)));
+            bins.push_back((int)((id / nb) % nb));
+            bins.push_back((int)(id % nb));
+        }
+    }
+    start.push_back(m);
+    B.nbins = (int)(start.size() - 1);
+    mbo_status st;
+    if ((st = upload_as(s, &B.pos, pos)) != MBO_OK) return st;
+    if (wts && (st = upload_as(s, &B.wts, w)) != MBO_OK) return st;
+    SHIP(s, hipMalloc((void**)&B.perm, (size_t)m * 8 + 8));
+    SHIP(s, hipMemcpy(B.perm, perm.data(), (size_t)m * 8, hipMemcpyHostToDevice));
+    SHIP(s, hipMalloc((void**)&B.start, start.size() * 8));
+    SHIP(s, hipMemcpy(B.start, start.data(), start.size() * 8, hipMemcpyHostToDevice));
+    SHIP(s, hipMalloc((void**)&B.bin, bins.size() * sizeof(int) + 4));
+    SHIP(s, hipMemcpy(B.bin, bins.data(), bins.size() * sizeof(int), hipMemcpyHostToDevice));
+    return MBO_OK;
+}
+
+mbo_status build_bins(mbo_surface_t s, const std::vector<double>& pts, const std::vector<double>* wts,
+                      mbo_surface_s::Bins& B)
+{
+    return s->esz == 8 ? build_bins_t<double>(s, pts, wts, B) : build_bins_t<float>(s, pts, wts, B);
+}
+
+// Bin the band cells (corners [3][cells], canonical order) by the grid
+// coordinate of their first node, computed as the cell kernel computes it, and
+// upload corners (sorted), cell indices, bin starts and bin coordinates.
+template <typename T>
+mbo_status build_cell_bins_t(mbo_surface_t s, const std::vector<double>& corners, double node0)
+{
+    const int64_t nc = s->cells;
+    const int nb = (s->Ng + SURF_BIN - 1) / SURF_BIN;
+    const T y0 = (T)s->y0, invh = (T)(1.0 / s->h), n0 = (T)node0;
+    std::vector<std::pair<int64_t, int64_t>> key((size_t)nc);
+    for (int64_t c = 0; c < nc; ++c) {
+        int64_t id = 0;
+        for (int a = 0; a < 3; ++a) {
+            const T u = ((T)corners[(size_t)(a * nc + c)] + n0 - y0) * invh;
+            if (!(u >= (T)1 && u < (T)(s->Ng - 1)))
+                return sfail(s, MBO_ERR_INVALID_ARG, "cell %lld lies outside the grid", (long long)c);
+            id = id * nb + (int)std::floor(u / (T)SURF_BIN);
+        }
+        key[(size_t)c] = {id, c};
+    }
+    std::stable_sort(key.begin(), key.end());
+    std::vector<int64_t> perm((size_t)nc), start;
+    std::vector<int> bins;
+    std::vector<double> pos((size_t)(3 * nc));
+    for (int64_t i = 0; i < nc; ++i) {
+        const int64_t c = key[(size_t)i].second;
+        perm[(size_t)i] = c;
+        for (int a = 0; a < 3; ++a) pos[(size_t)(a * nc + i)] = corners[(size_t)(a * nc + c)];
+        if (i == 0 || key[(size_t)i].first != key[(size_t)i - 1].first) {
+            start.push_back(i);
+            const int64_t id = key[(size_t)i].first;
+            bins.push_back((int)(id / ((int64_t)nb * nb)));
+            bins.push_back((int)((id / nb) % nb));
+            bins.push_back((int)(id % nb));
+        }
+    }
+    start.push_back(nc);
+    mbo_surface_s::Bins& B = s->cellbins;
+    B.nbins = (int)(start.size() - 1);
+    mbo_status st;
+    if ((st = upload_as(s, &B.pos, pos)) != MBO_OK) return st;
+    SHIP(s, hipMalloc((void**)&B.perm, (size_t)nc * 8 + 8));
+    SHIP(s, hipMemcpy(B.perm, perm.data(), (size_t)nc * 8, hipMemcpyHostToDevice));
+    SHIP(s, hipMalloc((void**)&B.start, start.size() * 8));
+    SHIP(s, hipMemcpy(B.start, start.data(), start.size() * 8, hipMemcpyHostToDevice));
+    SHIP(s, hipMalloc((void**)&B.bin, bins.size() * sizeof(int) + 4));
+    SHIP(s, hipMemcpy(B.bin, bins.data(), bins.size() * sizeof(int), hipMemcpyHostToDevice));
+    return MBO_OK;
+}
+
+SurfArgs surf_args(mbo_surface_t s, const mbo_surface_s::Bins& B)
+{
+    SurfArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.m = s->m;
+    a.n = s->n;
+    a.PL = s->grid->PL;
+    a.Ng = s->Ng;
+    a.w = s->w;
+    a.beta = s->beta;
+    a.y0 = s->y0;
+    a.h = s->h;
+    a.pos = B.pos;
+    a.wts = B.wts;
+    a.perm = B.perm;
+    a.start = B.start;
+    a.bin = B.bin;
+    a.nbins = B.nbins;
+    a.Z = s->grid->Z;
+    return a;
+}
+
+// out = S_tau in at the closest points: spread, forward FFT, symbol, inverse
+// FFT, interpolate.
+hipError_t enqueue_surface_diffuse(mbo_surface_t s, const void* in, void* out, hipStream_t st)
+{
+    mbo_plan_t g = s->grid;
+    const int64_t zwords = (int64_t)g->PL * g->npts * 2 * (int64_t)s->esz / 8;
+    hipError_t e = launch_fill_u64(reinterpret_cast<unsigned long long*>(g->Z), zwords, 0ull, st);
+    if (e != hipSuccess) return e;
+    const int PL = g->PL;
+    if (s->cell_waves > 0) {
+        SurfArgs a = surf_args(s, s->cellbins);
+        a.A = in;
+        a.p = s->p;
+        a.U = s->U;
+        a.TE = SURF_BIN + s->U;
+        a.nodes = s->nodes;
+        a.nwts = s->nwts;
+        a.pl0 = 0;
+        a.pl1 = PL;
+        if ((e = launch_surface_spread_cells(s->pk, a, s->cell_waves, st)) != hipSuccess) return e;
+    } else {
+        SurfArgs a = surf_args(s, s->spread);
+        a.A = in;
+        a.pl0 = 0;
+        a.pl1 = PL;
+        if ((e = launch_surface_spread(s->pk, a, st)) != hipSuccess) return e;
+    }
+    RowArgs r = row_args(g);
+    r.flags = RF_FORWARD;
+    if ((e = run_row_relax(g, r, st)) != hipSuccess) return e;
+    ColArgs y = col_args(g, g->ypass);
+    if ((e = run_col(g, g->ypass, CM_FORWARD, y, st)) != hipSuccess) return e;
+    ColArgs hh = col_args(g, g->heat);
+    if ((e = run_col(g, g->heat, CM_HEAT, hh, st)) != hipSuccess) return e;
+    if ((e = run_col(g, g->ypass, CM_INVERSE, y, st)) != hipSuccess) return e;
+    r.flags = RF_INVERSE | RF_STORE_Z;
+    if ((e = run_row_relax(g, r, st)) != hipSuccess) return e;
+    SurfArgs a = surf_args(s, s->interp);
+    a.out = out;
+    a.pl0 = 0;
+    a.pl1 = PL;
+    if ((e = launch_surface_interp(s->pk, a, st)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1842,6 +2167,247 @@ mbo_status mbo_iterate_volume(mbo_plan_t p, void* A, int max_iter, const int64_t
     if (n_plus_used)
         for (int64_t b = 0; b < p->batch; ++b) n_plus_used[b] = (int64_t)used[(size_t)b];
     if (bad) return fail(p, MBO_ERR_NONFINITE, "%llu projections met NaN/Inf input", bad);
+    return MBO_OK;
+}
+
+mbo_status mbo_surface_sphere(mbo_surface_t* out, double radius, double dx, int p, double tau, double eps, int n,
+                              mbo_precision prec, void* hip_stream)
+{
+    g_plan_error.clear();
+    if (!out) return sfail(nullptr, MBO_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!(radius > 0.0) || !(dx > 0.0) || !(tau > 0.0) || !(eps > 0.0 && eps < 0.5) || !std::isfinite(radius) ||
+        !std::isfinite(dx) || !std::isfinite(tau))
+        return sfail(nullptr, MBO_ERR_INVALID_ARG, "radius, dx, tau must be finite and > 0, eps in (0, 0.5)");
+    if (p < 1 || p > 8) return sfail(nullptr, MBO_ERR_INVALID_ARG, "p must be in [1, 8]");
+    if (n < 1 || n > 4) return sfail(nullptr, MBO_ERR_INVALID_ARG, "n must be in [1, 4]");
+    if (prec != MBO_F64 && prec != MBO_F32 && prec != MBO_F32_F64FALLBACK)
+        return sfail(nullptr, MBO_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
+    mbo_surface_t s = new mbo_surface_s();
+    auto bail = [&](mbo_status st) {
+        g_plan_error = s->err;
+        surface_free(s);
+        return st;
+    };
+    s->R = radius;
+    s->dx = dx;
+    s->p = p;
+    s->tau = tau;
+    s->eps = eps;
+    s->n = n;
+    s->prec = prec;
+    s->pk = prec == MBO_F64 ? 0 : 1;
+    s->esz = prec == MBO_F64 ? 8 : 4;
+    s->stream = (hipStream_t)hip_stream;
+    // Algorithm 2, step 1: band width, band cells, quadrature points, closest points
+    s->wb = band_width_of(tau, eps);
+    double nx[8], nw[8];
+    chebyshev_rule(p, nx, nw);
+    const int64_t lim = (int64_t)std::ceil((radius + s->wb) / dx) + 1;
+    std::vector<std::array<double, 3>> corners;
+    for (int64_t i = -lim; i <= lim; ++i)
+        for (int64_t j = -lim; j <= lim; ++j)
+            for (int64_t k = -lim; k <= lim; ++k) {
+                const double gx = dx * (double)i, gy = dx * (double)j, gz = dx * (double)k;
+                if (std::fabs(std::sqrt(gx * gx + gy * gy + gz * gz) - radius) < s->wb) corners.push_back({gx, gy, gz});
+            }
+    s->cells = (int64_t)corners.size();
+    const int64_t m = s->cells * p * p * p;
+    s->m = m;
+    if (m == 0) return bail(sfail(s, MBO_ERR_INVALID_ARG, "the band holds no grid point"));
+    s->xq.assign((size_t)(3 * m), 0.0);
+    s->xc.assign((size_t)(3 * m), 0.0);
+    s->wq.assign((size_t)m, 0.0);
+    int64_t q = 0;
+    for (const auto& c : corners)
+        for (int a = 0; a < p; ++a)
+            for (int b = 0; b < p; ++b)
+                for (int e = 0; e < p; ++e, ++q) {
+                    const double x = c[0] + dx * nx[a], y = c[1] + dx * nx[b], z = c[2] + dx * nx[e];
+                    const double r = std::sqrt(x * x + y * y + z * z);
+                    s->xq[(size_t)q] = x;
+                    s->xq[(size_t)(m + q)] = y;
+                    s->xq[(size_t)(2 * m + q)] = z;
+                    s->xc[(size_t)q] = r > 0.0 ? radius * x / r : radius;
+                    s->xc[(size_t)(m + q)] = r > 0.0 ? radius * y / r : 0.0;
+                    s->xc[(size_t)(2 * m + q)] = r > 0.0 ? radius * z / r : 0.0;
+                    s->wq[(size_t)q] = dx * dx * dx * nw[a] * nw[b] * nw[e];
+                }
+    // the periodic grid.  Gridding tolerance eg = eps / 10 (the gridding error
+    // at a target grows with the strength of the sources within reach, about
+    // (4 pi tau)^{-3/2} times the band volume, so it gets a tenth of the band's
+    // tolerance), kernel width w for eg, spacing at most that of a 2x
+    // oversampled band limit of the heat kernel (exp(-tau k^2) = eg at half
+    // the Nyquist wavenumber), box wide enough that (a) no periodic image of
+    // G_tau reaches a target (its tail mass beyond band_width_of(tau, eg) is eg)
+    // and (b) every sample lies inside the box with a grid point to spare
+    const double pi = 3.14159265358979323846;
+    const double eg = std::max(0.1 * eps, prec == MBO_F64 ? 1e-11 : 1e-7);
+    s->w = std::max(3, std::min(12, (int)std::ceil(std::log10(1.0 / eg)) + 1));
+    s->beta = 2.30 * s->w;
+    const double L = std::log(1.0 / eg);
+    const double hmax = pi / (2.0 * std::sqrt(L / tau));
+    const double reach = radius + s->wb + dx * std::sqrt(3.0);  // max |x_q|
+    const double need = std::max(radius + reach + band_width_of(tau, eg), 2.0 * reach + 4.0 * hmax);
+    int Ng = 8;
+    while (Ng * hmax < need) Ng *= 2;
+    if (Ng > 512)
+        return bail(sfail(s, MBO_ERR_UNSUPPORTED, "the grid would need %d > 512 points per axis", Ng));
+    s->Ng = Ng;
+    s->h = need / Ng;  // the whole power-of-two grid oversamples further
+    s->y0 = -0.5 * need;
+    const int64_t N3[3] = {Ng, Ng, Ng};
+    mbo_status st = mbo_plan(&s->grid, 3, N3, n, 1, tau, prec, 0.0, hip_stream);
+    if (st != MBO_OK) {
+        s->err = g_plan_error;
+        return bail(st);
+    }
+    mbo_plan_t g = s->grid;
+    // symbol per axis: exp(-tau k^2) / (Ng h psihat(k h)^2), k = 2 pi m' / (Ng h);
+    // psihat(xi) = int_{-W}^{W} psi(z) cos(xi z) dz by Gauss-Legendre
+    std::vector<double> gx, gw;
+    gauss_legendre(200, gx, gw);
+    const double W = 0.5 * s->w;
+    std::vector<double> f((size_t)Ng);
+    for (int mm = 0; mm < Ng; ++mm) {
+        const int mw = 2 * mm < Ng ? mm : mm - Ng;
+        const double k = 2.0 * pi * mw / (Ng * s->h);
+        double ph = 0.0;
+        for (size_t i = 0; i < gx.size(); ++i) {
+            const double z = W * gx[i];
+            const double r = gx[i];
+            ph += W * gw[i] * std::exp(s->beta * (std::sqrt(std::max(0.0, 1.0 - r * r)) - 1.0)) * std::cos(k * s->h * z);
+        }
+        f[(size_t)mm] = tau * k * k > 3.0 * L ? 0.0 : std::exp(-tau * k * k) / (Ng * s->h * ph * ph);
+    }
+    std::vector<double> inner((size_t)Ng * Ng);
+    for (int a = 0; a < Ng; ++a)
+        for (int b = 0; b < Ng; ++b) inner[(size_t)a * Ng + b] = f[(size_t)a] * f[(size_t)b];
+    if ((st = upload(g, g->lam_row, f)) != MBO_OK || (st = upload(g, g->lam_inner, inner)) != MBO_OK) {
+        s->err = g->err;
+        return bail(st);
+    }
+    (void)launch_row_relax(g->pk, n, ilog2(Ng), row_args(g), g->row_grid, g->row_block, g->lds_max, nullptr, true);
+    (void)hipGetLastError();
+    // spreading: whole cells when the cell kernel's LDS (tile plus per-wave
+    // scratch) fits with at least one wave, else sample by sample
+    s->U = s->w + (int)std::ceil(dx * (nx[p - 1] - nx[0]) / s->h * (1.0 + 1e-4) + 1e-4);
+    s->cell_waves = 0;
+    for (int wv = 4; wv >= 1 && !s->cell_waves; wv /= 2)
+        if (surface_cell_lds(p, s->U, wv, s->esz) <= g->lds_max) s->cell_waves = wv;
+    if (s->cell_waves) {
+        std::vector<double> cflat((size_t)(3 * s->cells)), nd((size_t)p), nwv((size_t)p);
+        for (int64_t c = 0; c < s->cells; ++c)
+            for (int a = 0; a < 3; ++a) cflat[(size_t)(a * s->cells + c)] = corners[(size_t)c][(size_t)a];
+        for (int a = 0; a < p; ++a) {
+            nd[(size_t)a] = dx * nx[a];
+            nwv[(size_t)a] = dx * nw[a];
+        }
+        st = s->esz == 8 ? build_cell_bins_t<double>(s, cflat, nd[0]) : build_cell_bins_t<float>(s, cflat, nd[0]);
+        if (st != MBO_OK) return bail(st);
+        if ((st = upload_as(s, &s->nodes, nd)) != MBO_OK || (st = upload_as(s, &s->nwts, nwv)) != MBO_OK)
+            return bail(st);
+    } else if ((st = build_bins(s, s->xq, &s->wq, s->spread)) != MBO_OK) {
+        return bail(st);
+    }
+    if ((st = build_bins(s, s->xc, nullptr, s->interp)) != MBO_OK) return bail(st);
+    const size_t te = (size_t)(SURF_BIN + s->w);
+    if (2 * te * te * (te | 1) * s->esz > g->lds_max)
+        return bail(sfail(s, MBO_ERR_UNSUPPORTED, "kernel width %d needs more LDS than the device has", s->w));
+    if (hipMalloc(&s->tmp, (size_t)(n * n) * (size_t)m * s->esz) != hipSuccess ||
+        hipMalloc((void**)&s->sgn, (size_t)m) != hipSuccess ||
+        hipMalloc((void**)&s->counters, 4 * sizeof(unsigned long long)) != hipSuccess)
+        return bail(sfail(s, MBO_ERR_ALLOC, "device allocation failed"));
+    *out = s;
+    return MBO_OK;
+}
+
+mbo_status mbo_surface_destroy(mbo_surface_t s)
+{
+    surface_free(s);
+    return MBO_OK;
+}
+
+const char* mbo_surface_last_error(mbo_surface_t s) { return s ? s->err.c_str() : g_plan_error.c_str(); }
+
+mbo_status mbo_surface_info(mbo_surface_t s, int64_t* samples, int64_t* cells, int* grid, double* band_width)
+{
+    if (!s) return MBO_ERR_INVALID_ARG;
+    if (samples) *samples = s->m;
+    if (cells) *cells = s->cells;
+    if (grid) *grid = s->Ng;
+    if (band_width) *band_width = s->wb;
+    return MBO_OK;
+}
+
+mbo_status mbo_surface_points(mbo_surface_t s, double* xq, double* xc, double* w)
+{
+    if (!s) return MBO_ERR_INVALID_ARG;
+    if (xq) std::memcpy(xq, s->xq.data(), s->xq.size() * sizeof(double));
+    if (xc) std::memcpy(xc, s->xc.data(), s->xc.size() * sizeof(double));
+    if (w) std::memcpy(w, s->wq.data(), s->wq.size() * sizeof(double));
+    return MBO_OK;
+}
+
+mbo_status mbo_surface_diffuse(mbo_surface_t s, const void* A_in, void* A_out)
+{
+    if (!s) return MBO_ERR_INVALID_ARG;
+    if (!A_in || !A_out) return sfail(s, MBO_ERR_INVALID_ARG, "A_in / A_out is NULL");
+    if (A_in == A_out) return sfail(s, MBO_ERR_INVALID_ARG, "A_out must not alias A_in");
+    SHIP(s, hipSetDevice(s->grid->device));
+    SHIP(s, enqueue_surface_diffuse(s, A_in, A_out, s->stream));
+    return MBO_OK;
+}
+
+mbo_status mbo_surface_iterate(mbo_surface_t s, void* A, int K, int64_t* flips)
+{
+    if (!s) return MBO_ERR_INVALID_ARG;
+    if (!A) return sfail(s, MBO_ERR_INVALID_ARG, "A is NULL");
+    if (K < 0) return sfail(s, MBO_ERR_INVALID_ARG, "K < 0");
+    SHIP(s, hipSetDevice(s->grid->device));
+    std::vector<int8_t> prev, cur;
+    if (flips && K > 0) {
+        ProjArgs a0;
+        std::memset(&a0, 0, sizeof a0);
+        a0.npts = s->m;
+        a0.A = A;
+        a0.Q = s->tmp;
+        a0.dsign = s->sgn;
+        a0.nonfinite = s->counters;
+        a0.fallbacks = s->counters + 1;
+        SHIP(s, launch_project(s->pk, s->n, a0, 1, s->stream));  // det signs of A_0 (projection discarded)
+        prev.resize((size_t)s->m);
+        SHIP(s, hipMemcpyAsync(prev.data(), s->sgn, (size_t)s->m, hipMemcpyDeviceToHost, s->stream));
+        SHIP(s, hipStreamSynchronize(s->stream));
+    }
+    SHIP(s, launch_fill_u64(s->counters, 4, 0ull, s->stream));
+    for (int it = 0; it < K; ++it) {
+        SHIP(s, enqueue_surface_diffuse(s, A, s->tmp, s->stream));
+        ProjArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.npts = s->m;
+        a.A = s->tmp;
+        a.Q = A;
+        a.dsign = flips ? s->sgn : nullptr;
+        a.nonfinite = s->counters;
+        a.fallbacks = s->counters + 1;
+        a.fallback = s->prec == MBO_F32_F64FALLBACK;
+        a.sigma_fb = 1e-3;
+        SHIP(s, launch_project(s->pk, s->n, a, 1, s->stream));
+        if (flips) {
+            cur.resize((size_t)s->m);
+            SHIP(s, hipMemcpyAsync(cur.data(), s->sgn, (size_t)s->m, hipMemcpyDeviceToHost, s->stream));
+            SHIP(s, hipStreamSynchronize(s->stream));
+            int64_t f = 0;
+            for (int64_t i = 0; i < s->m; ++i) f += cur[(size_t)i] != prev[(size_t)i];
+            flips[it] = f;
+            prev.swap(cur);
+        }
+    }
+    unsigned long long h[4];
+    SHIP(s, hipMemcpyAsync(h, s->counters, sizeof h, hipMemcpyDeviceToHost, s->stream));
+    SHIP(s, hipStreamSynchronize(s->stream));
+    if (h[0]) return sfail(s, MBO_ERR_NONFINITE, "%llu points with NaN/Inf input", h[0]);
     return MBO_OK;
 }
 

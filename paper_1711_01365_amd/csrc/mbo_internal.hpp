@@ -23,6 +23,7 @@ enum RowFlags : int {
     RF_VP_KEY = 1 << 11,     // volume-preserving step: Delta E of the loaded values into vde[]
     RF_VP_APPLY = 1 << 12,   // volume-preserving step: T+ / T- as the selection vsel[] says
     RF_RELAX = 1 << 13,      // relaxed flow: explicit reaction step of GD-1 / GD-3
+    RF_STORE_Z = 1 << 14,    // store the lines back to Z as they are (no forward FFT)
 };
 
 // Instances of the row pass: Algorithm 1, the volume-preserving step, the
@@ -223,6 +224,62 @@ hipError_t launch_count_pos(const int8_t* sgn, int64_t npts, int batch, long lon
 // Row pass of the volume-preserving step (flags RF_VP_KEY / RF_VP_APPLY)
 hipError_t launch_row_vp(int prec, int n, int log2L, const RowArgs& a, dim3 grid, dim3 block,
                          size_t lds, hipStream_t st, bool prepare = false);
+
+// Surface diffusion by the closest point method: the spreading / interpolation
+// of the samples onto / from a periodic Cartesian grid (the complex planes Z of
+// a 3-D plan, PL planes, Ng^3 points, axis 0 slowest) with the "exponential of
+// semicircle" kernel psi(z) = exp(beta (sqrt(1 - (z / W)^2) - 1)), |z| < W = w / 2
+// grid units.  Work is split in bins of SURF_BIN^3 grid points; the workgroup of
+// a (bin, plane) accumulates into, or reads from, an LDS tile of the grid
+// around its bin.
+//   Cell spreading: the samples of a band cell are the tensor product of p
+//   nodes per axis with separable weights; the cell is listed in the bin of its
+//   first sample and spread as a whole (U grid points per axis cover the
+//   stencils of all its samples; tile edge TE = SURF_BIN + U).
+//   Sample spreading / interpolation: one sample at a time (tile edge
+//   SURF_BIN + w).
+constexpr int SURF_BIN = 8;
+struct SurfArgs {
+    int64_t m;               // samples
+    int n, PL;               // matrix size, packed complex planes
+    int Ng;                  // grid points per axis
+    int w;                   // kernel width in grid points
+    double beta;             // kernel shape
+    double y0, h;            // grid: y_g = y0 + g h
+    const void* pos;         // samples: [3][m] positions sorted by bin; cells: [3][cells] corners sorted by bin
+    const void* wts;         // sample spreading: [m] weights sorted by bin (nullable: 1)
+    const int64_t* perm;     // sorted index -> sample (cell) index of the canonical order
+    const int64_t* start;    // [bins + 1] first sorted index of each listed bin
+    const int* bin;          // [bins][3] bin coordinates
+    int nbins;
+    int p, U, TE;            // cells: nodes per axis, union stencil width, tile edge
+    const void* nodes;       // cells: [p] node offsets dx n_a (ascending)
+    const void* nwts;        // cells: [p] per-axis weight factors dx w_a
+    const void* A;           // spread: entry-planar [n*n][m] field
+    void* out;               // interpolate: entry-planar [n*n][m] field
+    void* Z;                 // grid: [PL][Ng^3] complex
+    int pl0, pl1;            // planes of this launch (one workgroup row per plane)
+};
+hipError_t launch_surface_spread(int prec, const SurfArgs& a, hipStream_t st);
+hipError_t launch_surface_spread_cells(int prec, const SurfArgs& a, int waves, hipStream_t st);
+hipError_t launch_surface_interp(int prec, const SurfArgs& a, hipStream_t st);
+// LDS bytes of the sample kernels' tile (one complex plane) for kernel width w
+inline size_t surface_tile_bytes(int w, size_t esz)
+{
+    const size_t te = (size_t)(SURF_BIN + w);
+    return te * te * te * 2 * esz;
+}
+// LDS of the cell kernel: tile (re and im, z pitch TE | 1) plus a scratch
+// per wave (weights 3 p U, values 2 p^3, partial sums 2 p^2 U and 2 p U^2)
+__host__ __device__ inline size_t surface_cell_scratch(int p, int U)
+{
+    return (size_t)(3 * p * U + 2 * p * p * p + 2 * p * p * U + 2 * p * U * U);
+}
+inline size_t surface_cell_lds(int p, int U, int waves, size_t esz)
+{
+    const size_t te = (size_t)(SURF_BIN + U);
+    return (2 * te * te * (te | 1) + (size_t)waves * surface_cell_scratch(p, U)) * esz;
+}
 
 // per-translation-unit launchers behind launch_row / launch_col
 hipError_t launch_row_f32(int n, int log2L, const RowArgs& a, dim3 g, dim3 b, size_t lds,

@@ -471,6 +471,29 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L, RM>())) 
         }
     }
 
+    if constexpr (RELAX) {
+        if (flags & RF_STORE_Z) {
+            // the lines as they stand in LDS (after the inverse transform) back to Z
+            __syncthreads();
+            for (int rd = 0; rd < rounds; ++rd) {
+                const int j = rd * G + g;
+                const int rloc = j / PL, pl = j - (j / PL) * PL;
+                if (j < nlines && row0 + rloc < a.rows) {
+                    const T* lrj = lr + (size_t)j * lp;
+                    const T* lij = li + (size_t)j * lp;
+                    C* Z = reinterpret_cast<C*>(a.Z) + ((size_t)b * PL + pl) * npts + (row0 + rloc) * L;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        C v;
+                        v.x = lrj[lds_pad_at<Tn>(t, lds_pad(t), e)];
+                        v.y = lij[lds_pad_at<Tn>(t, lds_pad(t), e)];
+                        Z[t + e * Tn] = v;
+                    }
+                }
+            }
+        }
+    }
+
     // ---- phase 3: forward FFT of the lines, store the spectra
     if (flags & RF_FORWARD) {
         // twiddles are (re)loaded here rather than kept in registers through

@@ -184,3 +184,37 @@ class BatchedWorkload:
     @property
     def points(self) -> int:
         return sum(m.points for m in self.members)
+
+
+# The sphere experiment (Section 6.2): unit sphere, band cells dx = 0.05 with
+# p = 3 Chebyshev points per axis, tau = 0.005, eps = 1e-6, n = 3; the initial
+# field takes the first printed matrix in the octant x < 0, y < 0, z > 0 and the
+# second one elsewhere.  As printed the matrices are not orthogonal (raw inputs of
+# the first projection); the first has det < 0, the second det > 0.
+@dataclass
+class SphereWorkload:
+    name: str
+    R: float
+    dx: float
+    p: int
+    tau: float
+    eps: float
+    n: int
+    iters: int
+
+
+SPHERE_MATRICES = np.array([[[0.392227, 0.706046, 0.046171],
+                             [0.655478, 0.031833, 0.097132],
+                             [0.171187, 0.276923, 0.82346]],
+                            [[0.699077, 0.547216, 0.257508],
+                             [0.890903, 0.138624, 0.840717],
+                             [0.959291, 0.149294, 0.254282]]])
+SPHERE_PAPER = SphereWorkload("sphere_R1_dx0.05_p3_tau0.005", 1.0, 0.05, 3, 0.005, 1e-6, 3, 20)
+
+
+def sphere_octant_field(xc: np.ndarray) -> np.ndarray:
+    """(3, 3, m) field over samples with closest points xc [3, m]: the first
+    printed matrix where x < 0, y < 0, z > 0, the second elsewhere."""
+    x, y, z = xc
+    inside = (x < 0) & (y < 0) & (z > 0)
+    return np.where(inside[None, None, :], SPHERE_MATRICES[0][:, :, None], SPHERE_MATRICES[1][:, :, None])

@@ -31,7 +31,9 @@ EXPORTS = ("mbo_plan", "mbo_plan_destroy", "mbo_plan_set_tau", "mbo_plan_set_str
            "mbo_energy", "mbo_project_vjp", "mbo_diffuse_dtau", "mbo_plan_batched", "mbo_plan_tuning",
            "mbo_plan_autotune", "mbo_step", "mbo_step_vjp", "mbo_volume_select",
            "mbo_project_volume", "mbo_iterate_volume", "mbo_so2_index", "mbo_relaxed_flow",
-           "mbo_relaxed_energy", "mbo_status_string", "mbo_last_error")
+           "mbo_relaxed_energy", "mbo_surface_sphere", "mbo_surface_destroy", "mbo_surface_info",
+           "mbo_surface_points", "mbo_surface_diffuse", "mbo_surface_iterate", "mbo_surface_last_error",
+           "mbo_status_string", "mbo_last_error")
 
 
 class FieldDesc(ctypes.Structure):
@@ -81,8 +83,17 @@ def load(path: str = LIB_PATH):
     lib.mbo_so2_index.argtypes = [vp, vp, dp, dp]
     lib.mbo_relaxed_flow.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double]
     lib.mbo_relaxed_energy.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, dp]
+    lib.mbo_surface_sphere.argtypes = [ctypes.POINTER(vp), ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, vp]
+    lib.mbo_surface_destroy.argtypes = [vp]
+    lib.mbo_surface_info.argtypes = [vp, i64p, i64p, ip, dp]
+    lib.mbo_surface_points.argtypes = [vp, dp, dp, dp]
+    lib.mbo_surface_diffuse.argtypes = [vp, vp, vp]
+    lib.mbo_surface_iterate.argtypes = [vp, vp, ctypes.c_int, i64p]
+    lib.mbo_surface_last_error.argtypes = [vp]
+    lib.mbo_surface_last_error.restype = ctypes.c_char_p
     for f in EXPORTS:
-        if f not in ("mbo_status_string", "mbo_last_error"):
+        if f not in ("mbo_status_string", "mbo_last_error", "mbo_surface_last_error"):
             getattr(lib, f).restype = ctypes.c_int
     lib.mbo_status_string.argtypes = [ctypes.c_int]
     lib.mbo_status_string.restype = ctypes.c_char_p
@@ -356,6 +367,97 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             self._lib.mbo_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class SphereSurface:
+    """Owns an ``mbo_surface_t`` (mbo_surface_sphere): closest-point diffusion
+    and the MBO iteration on the sphere of radius R.  Fields are ``(n, n, m)``
+    tensors over the m samples (canonical order), float64 for ``F64`` surfaces
+    and float32 otherwise."""
+
+    def __init__(self, R: float, dx: float, p: int, tau: float, eps: float, n: int,
+                 precision: int = F64, stream=None):
+        lib = load()
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: libmbo runs on the GPU only")
+        h = ctypes.c_void_p()
+        rc = lib.mbo_surface_sphere(ctypes.byref(h), float(R), float(dx), int(p), float(tau), float(eps),
+                                    int(n), int(precision), _stream_ptr(stream))
+        if rc != 0:
+            msg = lib.mbo_surface_last_error(None)
+            raise MboError(rc, msg.decode() if msg else "")
+        self._h, self._lib = h, lib
+        self.R, self.dx, self.p, self.tau, self.eps = float(R), float(dx), int(p), float(tau), float(eps)
+        self.n, self.precision = int(n), int(precision)
+        self.dtype = torch.float64 if precision == F64 else torch.float32
+        m, cells, g, wb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int(), ctypes.c_double()
+        self._check(lib.mbo_surface_info(h, ctypes.byref(m), ctypes.byref(cells), ctypes.byref(g),
+                                         ctypes.byref(wb)))
+        self.m, self.cells, self.grid, self.band_width = m.value, cells.value, g.value, wb.value
+
+    def _check(self, rc):
+        if rc != 0:
+            msg = self._lib.mbo_surface_last_error(self._h)
+            raise MboError(rc, msg.decode() if msg else "")
+
+    @property
+    def shape(self):
+        return (self.n, self.n, self.m)
+
+    def _field(self, A, name="A"):
+        import torch
+        if not isinstance(A, torch.Tensor) or not A.is_cuda:
+            raise TypeError("%s must be a CUDA/HIP tensor" % name)
+        if A.dtype != self.dtype:
+            raise TypeError("%s must be %s" % (name, self.dtype))
+        if tuple(A.shape) != self.shape:
+            raise ValueError("%s has shape %s, surface expects %s" % (name, tuple(A.shape), self.shape))
+        if not A.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        return ctypes.c_void_p(A.data_ptr())
+
+    def points(self):
+        """(xq [3, m], xc [3, m], w [m]) as float64 numpy arrays."""
+        xq, xc, w = np.zeros((3, self.m)), np.zeros((3, self.m)), np.zeros(self.m)
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._check(self._lib.mbo_surface_points(self._h, xq.ctypes.data_as(dp), xc.ctypes.data_as(dp),
+                                                 w.ctypes.data_as(dp)))
+        return xq, xc, w
+
+    def diffuse(self, A_in, A_out=None):
+        import torch
+        if A_out is None:
+            A_out = torch.empty_like(A_in)
+        self._check(self._lib.mbo_surface_diffuse(self._h, self._field(A_in, "A_in"),
+                                                  self._field(A_out, "A_out")))
+        return A_out
+
+    def iterate(self, A, K: int, flips: bool = False):
+        """K MBO steps in place on A; returns the per-step flip counts (numpy
+        int64 [K]) when flips is set, else None."""
+        fl = np.zeros(max(int(K), 1), dtype=np.int64) if flips else None
+        self._check(self._lib.mbo_surface_iterate(
+            self._h, self._field(A), int(K),
+            fl.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if fl is not None else None))
+        return fl[:K] if fl is not None else None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mbo_surface_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -141,3 +141,25 @@ def test_null_plan_is_rejected_by_the_index(lib):
 def test_null_plan_is_rejected_by_the_relaxed_flows(lib):
     assert lib.mbo_relaxed_flow(None, None, 1, 1, 0.1, 1e-3) == 1
     assert lib.mbo_relaxed_energy(None, None, 1, 0.1, None) == 1
+
+
+def test_surface_calls_validate_before_touching_the_device(lib):
+    assert lib.mbo_surface_info(None, None, None, None, None) == 1
+    assert lib.mbo_surface_points(None, None, None, None) == 1
+    assert lib.mbo_surface_diffuse(None, None, None) == 1
+    assert lib.mbo_surface_iterate(None, None, 1, None) == 1
+    assert lib.mbo_surface_destroy(None) == 0
+    h = ctypes.c_void_p()
+    assert lib.mbo_surface_sphere(None, 1.0, 0.1, 1, 0.01, 1e-6, 3, 0, None) == 1
+    for bad in [(-1.0, 0.1, 1, 0.01, 1e-6, 3, 0), (1.0, 0.0, 1, 0.01, 1e-6, 3, 0),
+                (1.0, 0.1, 0, 0.01, 1e-6, 3, 0), (1.0, 0.1, 9, 0.01, 1e-6, 3, 0),
+                (1.0, 0.1, 1, 0.0, 1e-6, 3, 0), (1.0, 0.1, 1, float("nan"), 1e-6, 3, 0),
+                (1.0, 0.1, 1, 0.01, 0.0, 3, 0), (1.0, 0.1, 1, 0.01, 0.6, 3, 0),
+                (1.0, 0.1, 1, 0.01, 1e-6, 0, 0), (1.0, 0.1, 1, 0.01, 1e-6, 5, 0),
+                (1.0, 0.1, 1, 0.01, 1e-6, 3, 7)]:
+        assert lib.mbo_surface_sphere(ctypes.byref(h), *bad, None) == 1, bad
+        assert not h.value
+        assert lib.mbo_surface_last_error(None)
+    # a grid finer than 512 points per axis is refused before any device work
+    assert lib.mbo_surface_sphere(ctypes.byref(h), 10.0, 0.5, 1, 1e-3, 1e-6, 3, 0, None) == 2
+    assert b"512" in lib.mbo_surface_last_error(None)
