@@ -1258,7 +1258,12 @@ struct mbo_surface_s {
     // sample instead)
     void* nodes = nullptr;
     void* nwts = nullptr;
-    int U = 0, cell_waves = 0;
+    int U = 0, cell_waves = 0, cell_chunk = 1;
+    bool cell_lines = false;
+    // spreading tiles of every (listed bin, plane) and the bin -> listed index map
+    void* tiles = nullptr;
+    int* binmap = nullptr;
+    int tile_edge = 0;
     void* tmp = nullptr;        // [n*n][m]
     int8_t* sgn = nullptr;      // [m]
     unsigned long long* counters = nullptr;
@@ -1293,6 +1298,8 @@ void surface_free(mbo_surface_t s)
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     free_dev(s->nodes);
     free_dev(s->nwts);
+    free_dev(s->tiles);
+    free_dev(s->binmap);
     for (auto* b : {&s->spread, &s->interp, &s->cellbins}) {
         free_dev(b->pos);
         free_dev(b->wts);
@@ -1326,6 +1333,9 @@ mbo_status upload_as(mbo_surface_t s, void** dst, const std::vector<double>& h)
 // the coordinates of the non-empty bins.  The grid coordinate of a point is
 // computed here exactly as the kernels compute it (in T from the T-rounded
 // position), so that every stencil lies in its bin's tile.
+// Within a bin the points are ordered by their stencil start (x, then y, then
+// z): the lanes of a wave then read the same few z-lines of the tile, as LDS
+// broadcasts or consecutive banks.
 template <typename T>
 mbo_status build_bins_t(mbo_surface_t s, const std::vector<double>& pts, const std::vector<double>* wts,
                         mbo_surface_s::Bins& B)
@@ -1334,18 +1344,26 @@ mbo_status build_bins_t(mbo_surface_t s, const std::vector<double>& pts, const s
     const int nb = (s->Ng + SURF_BIN - 1) / SURF_BIN;
     const T y0 = (T)s->y0, invh = (T)(1.0 / s->h);
     std::vector<std::pair<int64_t, int64_t>> key((size_t)m);
+    std::vector<int64_t> sub((size_t)m);
+    const T half = (T)s->w * (T)0.5;
     for (int64_t q = 0; q < m; ++q) {
-        int64_t id = 0;
+        int64_t id = 0, st = 0;
         for (int a = 0; a < 3; ++a) {
             const T u = ((T)pts[(size_t)(a * m + q)] - y0) * invh;
             if (!(u >= (T)1 && u < (T)(s->Ng - 1)))
                 return sfail(s, MBO_ERR_INVALID_ARG, "sample %lld lies outside the grid", (long long)q);
             const int bi = (int)std::floor(u / (T)SURF_BIN);
             id = id * nb + bi;
+            st = st * (s->Ng + 64) + ((int64_t)std::ceil(u - half) + 32);
         }
         key[(size_t)q] = {id, q};
+        sub[(size_t)q] = st;
     }
-    std::stable_sort(key.begin(), key.end());
+    std::sort(key.begin(), key.end(), [&](const std::pair<int64_t, int64_t>& x, const std::pair<int64_t, int64_t>& y) {
+        if (x.first != y.first) return x.first < y.first;
+        const int64_t sx = sub[(size_t)x.second], sy = sub[(size_t)y.second];
+        return sx != sy ? sx < sy : x.second < y.second;
+    });
     std::vector<int64_t> perm((size_t)m), start;
     std::vector<int> bins;
     std::vector<double> pos((size_t)(3 * m)), w;
@@ -1460,28 +1478,29 @@ SurfArgs surf_args(mbo_surface_t s, const mbo_surface_s::Bins& B)
 hipError_t enqueue_surface_diffuse(mbo_surface_t s, const void* in, void* out, hipStream_t st)
 {
     mbo_plan_t g = s->grid;
-    const int64_t zwords = (int64_t)g->PL * g->npts * 2 * (int64_t)s->esz / 8;
-    hipError_t e = launch_fill_u64(reinterpret_cast<unsigned long long*>(g->Z), zwords, 0ull, st);
-    if (e != hipSuccess) return e;
+    hipError_t e;
     const int PL = g->PL;
-    if (s->cell_waves > 0) {
-        SurfArgs a = surf_args(s, s->cellbins);
-        a.A = in;
+    const bool cells = s->cell_waves > 0 || s->cell_lines;
+    const mbo_surface_s::Bins& sb = cells ? s->cellbins : s->spread;
+    SurfArgs a = surf_args(s, sb);
+    a.A = in;
+    a.pl0 = 0;
+    a.pl1 = PL;
+    a.tiles = s->tiles;
+    a.binmap = s->binmap;
+    if (cells) {
         a.p = s->p;
         a.U = s->U;
         a.TE = SURF_BIN + s->U;
         a.nodes = s->nodes;
         a.nwts = s->nwts;
-        a.pl0 = 0;
-        a.pl1 = PL;
-        if ((e = launch_surface_spread_cells(s->pk, a, s->cell_waves, st)) != hipSuccess) return e;
-    } else {
-        SurfArgs a = surf_args(s, s->spread);
-        a.A = in;
-        a.pl0 = 0;
-        a.pl1 = PL;
-        if ((e = launch_surface_spread(s->pk, a, st)) != hipSuccess) return e;
+        a.chunk = s->cell_chunk;
+        if ((e = launch_surface_spread_cells(s->pk, a, s->cell_lines ? 0 : s->cell_waves, st)) != hipSuccess)
+            return e;
+    } else if ((e = launch_surface_spread(s->pk, a, st)) != hipSuccess) {
+        return e;
     }
+    if ((e = launch_surface_gather(s->pk, a, s->tile_edge, st)) != hipSuccess) return e;
     RowArgs r = row_args(g);
     r.flags = RF_FORWARD;
     if ((e = run_row_relax(g, r, st)) != hipSuccess) return e;
@@ -1492,11 +1511,11 @@ hipError_t enqueue_surface_diffuse(mbo_surface_t s, const void* in, void* out, h
     if ((e = run_col(g, g->ypass, CM_INVERSE, y, st)) != hipSuccess) return e;
     r.flags = RF_INVERSE | RF_STORE_Z;
     if ((e = run_row_relax(g, r, st)) != hipSuccess) return e;
-    SurfArgs a = surf_args(s, s->interp);
-    a.out = out;
-    a.pl0 = 0;
-    a.pl1 = PL;
-    if ((e = launch_surface_interp(s->pk, a, st)) != hipSuccess) return e;
+    SurfArgs ia = surf_args(s, s->interp);
+    ia.out = out;
+    ia.pl0 = 0;
+    ia.pl1 = PL;
+    if ((e = launch_surface_interp(s->pk, ia, st)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -2249,7 +2268,7 @@ mbo_status mbo_surface_sphere(mbo_surface_t* out, double radius, double dx, int 
     const double hmax = pi / (2.0 * std::sqrt(L / tau));
     const double reach = radius + s->wb + dx * std::sqrt(3.0);  // max |x_q|
     const double need = std::max(radius + reach + band_width_of(tau, eg), 2.0 * reach + 4.0 * hmax);
-    int Ng = 8;
+    int Ng = 64;  // at least the spreading tiles plus a bin
     while (Ng * hmax < need) Ng *= 2;
     if (Ng > 512)
         return bail(sfail(s, MBO_ERR_UNSUPPORTED, "the grid would need %d > 512 points per axis", Ng));
@@ -2292,10 +2311,22 @@ mbo_status mbo_surface_sphere(mbo_surface_t* out, double radius, double dx, int 
     // spreading: whole cells when the cell kernel's LDS (tile plus per-wave
     // scratch) fits with at least one wave, else sample by sample
     s->U = s->w + (int)std::ceil(dx * (nx[p - 1] - nx[0]) / s->h * (1.0 + 1e-4) + 1e-4);
+    // the line-owner variant (no LDS atomics) when its tile fits in the
+    // registers of a 512-thread workgroup, else one wave per cell
     s->cell_waves = 0;
-    for (int wv = 4; wv >= 1 && !s->cell_waves; wv /= 2)
-        if (surface_cell_lds(p, s->U, wv, s->esz) <= g->lds_max) s->cell_waves = wv;
-    if (s->cell_waves) {
+    s->cell_lines = p <= 4 && SURF_BIN + s->U <= 22 &&
+                    surface_lines_lds(p, s->U, 64, s->esz) <= g->lds_max;
+    if (s->cell_lines) s->cell_chunk = 64;
+    for (int wv = 4; wv >= 1 && !s->cell_waves && !s->cell_lines && SURF_BIN + s->U <= 4 * SURF_BIN; wv /= 2) {
+        const size_t fixed = surface_cell_lds(p, s->U, wv, 0, s->esz);
+        const size_t per_cell = (size_t)(3 + 2 * p * p * p) * s->esz + 8;
+        const size_t ch = fixed < g->lds_max ? (g->lds_max - fixed) / per_cell : 0;
+        if (ch >= (size_t)wv) {
+            s->cell_waves = wv;
+            s->cell_chunk = (int)std::min<size_t>(ch, 64);
+        }
+    }
+    if (s->cell_waves || s->cell_lines) {
         std::vector<double> cflat((size_t)(3 * s->cells)), nd((size_t)p), nwv((size_t)p);
         for (int64_t c = 0; c < s->cells; ++c)
             for (int a = 0; a < 3; ++a) cflat[(size_t)(a * s->cells + c)] = corners[(size_t)c][(size_t)a];
@@ -2311,6 +2342,23 @@ mbo_status mbo_surface_sphere(mbo_surface_t* out, double radius, double dx, int 
         return bail(st);
     }
     if ((st = build_bins(s, s->xc, nullptr, s->interp)) != MBO_OK) return bail(st);
+    {
+        // spreading tiles and the map from bin to listed index (the gather's lookup)
+        const bool cells = s->cell_waves || s->cell_lines;
+        const mbo_surface_s::Bins& sb = cells ? s->cellbins : s->spread;
+        s->tile_edge = SURF_BIN + (cells ? s->U : s->w);
+        const int nbx = Ng / SURF_BIN;
+        std::vector<int> coords((size_t)(3 * sb.nbins)), map((size_t)nbx * nbx * nbx, -1);
+        if (sb.nbins > 0)
+            SHIP(s, hipMemcpy(coords.data(), sb.bin, coords.size() * sizeof(int), hipMemcpyDeviceToHost));
+        for (int b = 0; b < sb.nbins; ++b)
+            map[((size_t)coords[(size_t)(3 * b)] * nbx + coords[(size_t)(3 * b + 1)]) * nbx +
+                coords[(size_t)(3 * b + 2)]] = b;
+        const size_t te3 = (size_t)s->tile_edge * s->tile_edge * s->tile_edge;
+        SHIP(s, hipMalloc(&s->tiles, (size_t)sb.nbins * g->PL * te3 * 2 * s->esz + 16));
+        SHIP(s, hipMalloc((void**)&s->binmap, map.size() * sizeof(int)));
+        SHIP(s, hipMemcpy(s->binmap, map.data(), map.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
     const size_t te = (size_t)(SURF_BIN + s->w);
     if (2 * te * te * (te | 1) * s->esz > g->lds_max)
         return bail(sfail(s, MBO_ERR_UNSUPPORTED, "kernel width %d needs more LDS than the device has", s->w));

@@ -253,32 +253,51 @@ struct SurfArgs {
     const int* bin;          // [bins][3] bin coordinates
     int nbins;
     int p, U, TE;            // cells: nodes per axis, union stencil width, tile edge
+    int chunk;               // cells: cells staged in LDS at a time
     const void* nodes;       // cells: [p] node offsets dx n_a (ascending)
     const void* nwts;        // cells: [p] per-axis weight factors dx w_a
     const void* A;           // spread: entry-planar [n*n][m] field
     void* out;               // interpolate: entry-planar [n*n][m] field
     void* Z;                 // grid: [PL][Ng^3] complex
     int pl0, pl1;            // planes of this launch (one workgroup row per plane)
+    void* tiles;             // spreading: [bins][PL][TE^3] complex, each workgroup's tile
+    const int* binmap;       // [(Ng / SURF_BIN)^3] listed index of each bin, -1 when empty
 };
 hipError_t launch_surface_spread(int prec, const SurfArgs& a, hipStream_t st);
+// waves = 0: the line-owner variant without atomics (p <= 4, TE <= 22), else
+// the cell-per-wave variant with that many waves per workgroup
 hipError_t launch_surface_spread_cells(int prec, const SurfArgs& a, int waves, hipStream_t st);
 hipError_t launch_surface_interp(int prec, const SurfArgs& a, hipStream_t st);
+// Z = sum of the spreading tiles over every grid point (tile edge TE; the
+// tiles of bin b start at grid point SURF_BIN b - w / 2 per axis, wrapping).
+// Needs Ng >= TE + SURF_BIN.
+hipError_t launch_surface_gather(int prec, const SurfArgs& a, int TE, hipStream_t st);
 // LDS bytes of the sample kernels' tile (one complex plane) for kernel width w
 inline size_t surface_tile_bytes(int w, size_t esz)
 {
     const size_t te = (size_t)(SURF_BIN + w);
     return te * te * te * 2 * esz;
 }
-// LDS of the cell kernel: tile (re and im, z pitch TE | 1) plus a scratch
-// per wave (weights 3 p U, values 2 p^3, partial sums 2 p^2 U and 2 p U^2)
+// LDS of the cell kernel: tile (re and im, z pitch TE | 1), the staged cells
+// of a chunk (corner and the values of one complex plane: 3 + 2 p^3 each, and
+// an int64 first-sample index) and a scratch per wave (weights 3 p U, partial
+// sums 2 p^2 U and 2 p U^2)
 __host__ __device__ inline size_t surface_cell_scratch(int p, int U)
 {
-    return (size_t)(3 * p * U + 2 * p * p * p + 2 * p * p * U + 2 * p * U * U);
+    return (size_t)(3 * p * U + 2 * p * p * U + 2 * p * U * U);
 }
-inline size_t surface_cell_lds(int p, int U, int waves, size_t esz)
+// LDS of the line-owner variant: chunk ids and staged cells, weights, T1 and
+// the padded T2 (k pitch SURF_BIN + 22 + 3)
+inline size_t surface_lines_lds(int p, int U, int chunk, size_t esz)
+{
+    return (size_t)chunk * 8 +
+           ((size_t)chunk * (3 + 2 * p * p * p) + 3 * p * U + 2 * p * p * U + 2 * p * U * (SURF_BIN + 22 + 3)) * esz;
+}
+inline size_t surface_cell_lds(int p, int U, int waves, int chunk, size_t esz)
 {
     const size_t te = (size_t)(SURF_BIN + U);
-    return (2 * te * te * (te | 1) + (size_t)waves * surface_cell_scratch(p, U)) * esz;
+    return (2 * te * te * (te | 1) + (size_t)chunk * (3 + 2 * p * p * p) +
+            (size_t)waves * surface_cell_scratch(p, U)) * esz + (size_t)chunk * 8;
 }
 
 // per-translation-unit launchers behind launch_row / launch_col

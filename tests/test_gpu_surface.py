@@ -145,6 +145,29 @@ def test_diffuse_wide_cells(torch_cuda, prec_name, eps):
     s.close()
 
 
+@pytest.mark.parametrize("prec_name", ["F64", "F32"])
+def test_diffuse_five_nodes_sampled(torch_cuda, prec_name):
+    """p = 5 nodes per cell axis (one wave per cell with LDS accumulation; the
+    register-line variant takes p <= 4): 1.9 M samples, outputs sampled against
+    the oracle's convolution at their closest points."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    prec = getattr(mbo, prec_name)
+    R, dx, p, tau, eps = 1.0, 0.1, 5, 0.01, 1e-4
+    note("five nodes", prec_name)
+    s = surface(R, dx, p, tau, eps, 2, prec)
+    b = band_of(s)
+    A = inputs.uniform_field(2, (s.m,), 930)
+    dt = torch.float64 if prec == mbo.F64 else torch.float32
+    Y = s.diffuse(dev(torch, A, dt)).double().cpu().numpy()
+    idx = np.random.default_rng(8).choice(s.m, 48, replace=False)
+    ref = oracle.heat_at(b, A, tau, b["xc"][:, idx])
+    err = np.abs(Y[:, :, idx] - ref).max() / np.abs(A).max()
+    note("  m", s.m, "grid", s.grid, "sampled err/max|A|", err)
+    assert err <= _tol(prec, eps), err
+    s.close()
+
+
 def test_diffuse_rejects_aliasing_and_bad_shapes(torch_cuda):
     torch = torch_cuda
     from paper_1711_01365_amd import mbo
