@@ -126,12 +126,16 @@ def _load():
     lib.orc_surface_iterate.argtypes = [ctypes.c_int64, _d, _d, _d, ctypes.c_int, ctypes.c_double, _d,
                                         ctypes.c_int, _i64]
     lib.orc_heat_at.argtypes = [ctypes.c_int64, _d, _d, ctypes.c_int, ctypes.c_double, _d, ctypes.c_int64, _d, _d]
+    lib.orc_weighted_select.argtypes = [ctypes.c_int64, _d, _i64, ctypes.c_int64, _i8]
+    lib.orc_surface_iterate_volume.argtypes = [ctypes.c_int64, _d, _d, _d, _i64, ctypes.c_int, ctypes.c_double, _d,
+                                               ctypes.c_int, _i64, _i64, _i64]
     lib.orc_num_threads.argtypes = []
     for f in ("orc_dft_naive", "orc_fft", "orc_heat", "orc_project", "orc_det_sign",
               "orc_energy", "orc_iterate", "orc_num_threads", "orc_heat_dtau", "orc_project_vjp",
               "orc_unroll_grad", "orc_volume_select", "orc_volume_project",
               "orc_iterate_volume", "orc_relaxed_flow", "orc_relaxed_energy", "orc_sphere_band",
-              "orc_surface_diffuse", "orc_surface_iterate", "orc_heat_at"):
+              "orc_surface_diffuse", "orc_surface_iterate", "orc_heat_at", "orc_weighted_select",
+              "orc_surface_iterate_volume"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -463,6 +467,40 @@ def heat_at(band: dict, A: np.ndarray, tau: float, xt: np.ndarray) -> np.ndarray
     _check(lib.orc_heat_at(m, _ptr(np.ascontiguousarray(band["xq"])), _ptr(np.ascontiguousarray(band["w"])), n,
                            float(tau), _ptr(A), nt, _ptr(xt), _ptr(out)), "heat_at")
     return out
+
+
+def surface_weights(band: dict, dx: float) -> np.ndarray:
+    """Integer volume weights of the samples: the quadrature weight in units of
+    2^-30 dx^3, rounded (sums of them are exact)."""
+    return np.rint(np.asarray(band["w"]) / dx ** 3 * 2.0 ** 30).astype(np.int64)
+
+
+def weighted_select(dE: np.ndarray, W: np.ndarray, V: int) -> np.ndarray:
+    """int8 mask of Algorithm 3's selection: dE in descending order (ties by
+    ascending index) while the weight taken is below V."""
+    lib = _load()
+    v = np.ascontiguousarray(dE, dtype=np.float64).ravel()
+    w = np.ascontiguousarray(W, dtype=np.int64).ravel()
+    sel = np.empty(v.size, dtype=np.int8)
+    _check(lib.orc_weighted_select(int(v.size), _ptr(v), _ptr(w, _i64), int(V), _ptr(sel, _i8)), "weighted_select")
+    return sel
+
+
+def surface_iterate_volume(band: dict, W: np.ndarray, A0: np.ndarray, tau: float, K: int, V=None):
+    """K steps of volume-preserving MBO on the sphere (Algorithm 3 selection).
+    Returns (A, flips [K], V used)."""
+    lib = _load()
+    A = np.ascontiguousarray(A0, dtype=np.float64).copy()
+    n, m = A.shape[0], A.shape[2]
+    fl = np.zeros(max(K, 1), dtype=np.int64)
+    vu = np.zeros(1, dtype=np.int64)
+    vin = None if V is None else np.array([int(V)], dtype=np.int64)
+    w = np.ascontiguousarray(W, dtype=np.int64)
+    _check(lib.orc_surface_iterate_volume(m, _ptr(np.ascontiguousarray(band["xq"])), _ptr(np.ascontiguousarray(band["xc"])),
+                                          _ptr(np.ascontiguousarray(band["w"])), _ptr(w, _i64), n, float(tau), _ptr(A),
+                                          int(K), None if vin is None else _ptr(vin, _i64), _ptr(vu, _i64),
+                                          _ptr(fl, _i64)), "surface_iterate_volume")
+    return A, fl[:K], int(vu[0])
 
 
 def surface_iterate(band: dict, A0: np.ndarray, tau: float, K: int):

@@ -1079,6 +1079,92 @@ int orc_surface_iterate(int64_t m, const double* xq, const double* xc, const dou
     return rc;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Volume-preserving MBO on a surface (Section 7, Algorithm 3)               */
+/* ------------------------------------------------------------------------ */
+
+/* Algorithm 3: sort Delta E in descending order (equal values in ascending
+ * sample index, as on the flat torus), then take the samples in that order,
+ * adding their volume weights W, while the sum is below V.  sel[q] = 1 for the
+ * taken samples: V <= 0 takes none, V above the total takes all.  The weights
+ * are integers (the sample's quadrature weight in units of 2^-30 dx^3), so the
+ * cut does not depend on the order of summation.  Returns -1 on bad
+ * arguments, -2 when a value is not finite. */
+int orc_weighted_select(int64_t m, const double* dE, const int64_t* W, int64_t V, int8_t* sel)
+{
+    if (m < 0) return -1;
+    for (int64_t q = 0; q < m; ++q) {
+        if (!isfinite(dE[q])) return -2;
+        if (W[q] < 0) return -1;
+    }
+    orc_rank_t* rk = (orc_rank_t*)malloc(sizeof(orc_rank_t) * (size_t)(m + 1));
+    for (int64_t q = 0; q < m; ++q) {
+        rk[q].de = dE[q];
+        rk[q].idx = q;
+    }
+    qsort(rk, (size_t)m, sizeof(orc_rank_t), orc_rank_cmp);
+    memset(sel, 0, (size_t)m);
+    int64_t acc = 0;
+    for (int64_t r = 0; r < m && acc < V; ++r) {
+        sel[rk[r].idx] = 1;
+        acc += W[rk[r].idx];
+    }
+    free(rk);
+    return 0;
+}
+
+/* Volume-preserving MBO on the sphere: K steps of diffusion (the direct band
+ * quadrature above) followed by the reassignment of Lemma 7.2 with the
+ * selection of Algorithm 3: T+ on the selected samples, T- elsewhere.
+ * V (nullable): the volume to keep in SO(n), in weight units; NULL takes the
+ * weight of the samples of A with det >= 0.  V_used (nullable) receives it.
+ * flips (nullable, [K]) counts the samples whose det sign changed. */
+int orc_surface_iterate_volume(int64_t m, const double* xq, const double* xc, const double* wq,
+                               const int64_t* W, int n, double tau, double* A, int K, const int64_t* V,
+                               int64_t* V_used, int64_t* flips)
+{
+    if (m < 0 || n < 1 || n > 4 || !(tau > 0.0) || K < 0) return -1;
+    const int64_t nn = (int64_t)n * n;
+    int8_t* sp = (int8_t*)malloc((size_t)m + 1);
+    int8_t* sel = (int8_t*)malloc((size_t)m + 1);
+    double* T = (double*)malloc(sizeof(double) * (size_t)(m * nn + 1));
+    double* tp = (double*)malloc(sizeof(double) * (size_t)(m * nn + 1));
+    double* tm = (double*)malloc(sizeof(double) * (size_t)(m * nn + 1));
+    double* de = (double*)malloc(sizeof(double) * (size_t)(m + 1));
+    orc_det_sign(m, n, A, sp);
+    int64_t vol = 0;
+    if (V) {
+        vol = *V;
+    } else {
+        for (int64_t q = 0; q < m; ++q) vol += sp[q] > 0 ? W[q] : 0;
+    }
+    if (V_used) *V_used = vol;
+    int rc = 0;
+    for (int s = 0; s < K && rc == 0; ++s) {
+        rc = orc_surface_diffuse(m, xq, xc, wq, n, tau, A, T);
+        if (rc) break;
+#pragma omp parallel for schedule(static)
+        for (int64_t q = 0; q < m; ++q) {
+            double a[16];
+            for (int e = 0; e < nn; ++e) a[e] = T[e * m + q];
+            de[q] = orc_vp_point(n, a, tp + q * nn, tm + q * nn);
+        }
+        rc = orc_weighted_select(m, de, W, vol, sel);
+        if (rc) break;
+        int64_t f = 0;
+        for (int64_t q = 0; q < m; ++q) {
+            const double* t = sel[q] ? tp + q * nn : tm + q * nn;
+            for (int e = 0; e < nn; ++e) A[e * m + q] = t[e];
+            const int8_t sn = sel[q] ? 1 : -1;
+            f += sn != sp[q];
+            sp[q] = sn;
+        }
+        if (flips) flips[s] = f;
+    }
+    free(sp); free(sel); free(T); free(tp); free(tm); free(de);
+    return rc;
+}
+
 /* Number of threads the OpenMP loops above use (1 without OpenMP). */
 #ifdef _OPENMP
 #include <omp.h>
