@@ -349,6 +349,38 @@ def run_surface(steps, precisions=None):
     return out
 
 
+def run_surface_volume(steps):
+    """Volume-preserving MBO on the sphere of Section 7 (dx = 0.05, p = 3,
+    tau = 0.01, eps = 1e-6, n = 3, FP32 + fallback, 20 steps from the printed
+    matrices by octant, V = the initial SO(3) volume): sample-steps/s and the
+    volume kept."""
+    import numpy as np
+    import torch
+    from paper_1711_01365_amd import inputs, mbo
+    w = inputs.SPHERE_VOLUME_PAPER
+    s = mbo.SphereSurface(w.R, w.dx, w.p, w.tau, w.eps, w.n, precision=mbo.F32_F64FALLBACK)
+    xq, xc, wts = s.points()
+    W = s.volume_weights()
+    A0 = torch.tensor(inputs.sphere_octant_field(xc), dtype=torch.float32, device="cuda")
+    A = A0.clone()
+    V, _ = s.iterate_volume(A, 1)  # warm-up; V = weight of the samples with det >= 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        A.copy_(A0)
+        s.iterate_volume(A, w.iters, V)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    det = np.linalg.det(np.moveaxis(A.double().cpu().numpy(), 2, 0))
+    kept = int(W[det > 0].sum())
+    out = {"workload": "%s_n3_%dit_f32_f64fallback" % (w.name, w.iters),
+           "value": s.m * w.iters * steps / sec, "unit": "sample-steps/s", "samples": s.m, "grid": s.grid,
+           "us_per_step": 1e6 * sec / (steps * w.iters), "volume_target": V, "volume_end": kept,
+           "volume_within_one_sample": bool(V <= kept < V + int(W.max()))}
+    s.close()
+    return out
+
+
 def run_adjoint(precision, reps):
     """Gradients of K = 50 unrolled steps (n = 3, 256^2, checkpoint every 10):
     forward and backward wall time of the autograd function."""
@@ -444,12 +476,13 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the legs reported beside the main line (2048^2 control, 3-D, "
-                         "batched, volume-preserving, paper examples, relaxed flows, sphere, adjoint)")
+                         "batched, volume-preserving, paper examples, relaxed flows, sphere, "
+                         "volume-preserving sphere, adjoint)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--volume-only", action="store_true",
                     help="only the volume-preserving legs (for profiling them)")
     ap.add_argument("--surface-only", action="store_true",
-                    help="only the sphere leg, float surface (for profiling it)")
+                    help="only the sphere legs, float surfaces (for profiling them)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -478,6 +511,9 @@ def main():
         r = run_surface(args.steps, (("f32_f64fallback", mbo.F32_F64FALLBACK),))["f32_f64fallback"]
         log("sphere %s: %.3e sample-steps/s, %.1f us/step, diffuse %.1f us, m=%d grid=%d^3"
             % (r["workload"], r["value"], r["us_per_step"], r["diffuse_us"], r["samples"], r["grid"]))
+        r = run_surface_volume(args.steps)
+        log("volume-preserving sphere %s: %.3e sample-steps/s, %.1f us/step, m=%d, volume %d -> %d"
+            % (r["workload"], r["value"], r["us_per_step"], r["samples"], r["volume_target"], r["volume_end"]))
         return
     w = inputs.HAAR_512
     log("workload %s: n=%d grid=%s tau=%g iterations=%d" % (w.name, w.n, w.grid, w.tau, w.iters))
@@ -554,6 +590,10 @@ def main():
             log("sphere %s: %.3e sample-steps/s, %.1f us/step, diffuse %.1f us, m=%d grid=%d^3, SO-(3) %s"
                 % (k, r["value"], r["us_per_step"], r["diffuse_us"], r["samples"], r["grid"],
                    r["so3minus_samples_first_last"]))
+        out["sphere_volume_preserving"] = run_surface_volume(1)
+        r = out["sphere_volume_preserving"]
+        log("volume-preserving sphere: %.3e sample-steps/s, %.1f us/step, m=%d, volume %d -> %d"
+            % (r["value"], r["us_per_step"], r["samples"], r["volume_target"], r["volume_end"]))
         out["adjoint"] = {"f32_f64fallback": run_adjoint(mbo.F32_F64FALLBACK, 2),
                           "f64": run_adjoint(mbo.F64, 2)}
         log("adjoint K=50 256^2: fp32+fb fwd %.1f ms bwd %.1f ms, fp64 fwd %.1f ms bwd %.1f ms"

@@ -238,6 +238,33 @@ mbo_status mbo_surface_diffuse(mbo_surface_t s, const void* A_in, void* A_out);
  * MBO_ERR_NONFINITE when a NaN/Inf was met. */
 mbo_status mbo_surface_iterate(mbo_surface_t s, void* A, int K, int64_t* flips);
 
+/* Volume-preserving MBO on the surface (Section 7, Algorithm 3).  Each sample
+ * carries an integer volume weight W_q: its quadrature weight in units of
+ * 2^-30 dx^3, rounded, so that sums of weights are exact and the selection does
+ * not depend on the order of summation.  After the diffusion, Delta E =
+ * 2 sgn(det) sigma_min per sample (as on the flat torus); the samples are taken
+ * in descending Delta E (equal values in ascending sample index) while the
+ * weight taken is below V; the taken samples receive T+ (closest point of
+ * SO(n)), all others T- (Lemma 7.2).  V <= 0 takes none, V above the total
+ * weight takes all.  MBO_F32_F64FALLBACK surfaces re-evaluate a sample in
+ * double when its float sigma_min is below 1e-3. */
+
+/* The weights W_q, host int64 [m], canonical order. */
+mbo_status mbo_surface_volume_weights(mbo_surface_t s, int64_t* W);
+
+/* Selection alone: selected[q] = 1 for the samples Algorithm 3 takes for the
+ * values dE (device [m], the surface's element type, finite) and the volume V
+ * (weight units), 0 elsewhere (device uint8 [m]).  Synchronises. */
+mbo_status mbo_surface_volume_select(mbo_surface_t s, const void* dE, int64_t V, uint8_t* selected);
+
+/* K volume-preserving steps in place on A (device [n*n][m]).  V: host, the
+ * volume to keep in SO(n) in weight units, or NULL for the weight of the
+ * samples of A with det >= 0; V_used (host, nullable) receives it.  flips
+ * (host, nullable, [K]): per step, the samples whose det sign changed.
+ * Synchronises; MBO_ERR_NONFINITE when a NaN/Inf was met. */
+mbo_status mbo_surface_iterate_volume(mbo_surface_t s, void* A, int K, const int64_t* V, int64_t* V_used,
+                                      int64_t* flips);
+
 /* Description of the last error on this surface (or of the last failed
  * mbo_surface_sphere call when s is NULL). */
 const char* mbo_surface_last_error(mbo_surface_t s);

@@ -1267,6 +1267,15 @@ struct mbo_surface_s {
     void* tmp = nullptr;        // [n*n][m]
     int8_t* sgn = nullptr;      // [m]
     unsigned long long* counters = nullptr;
+    // volume-preserving step: integer volume weights (host and device), their
+    // total, Delta E, the selection state, digit histogram and tie chunk sums
+    std::vector<int64_t> Wh;
+    int64_t Wtotal = 0;
+    int64_t* Wd = nullptr;
+    void* de = nullptr;
+    WSelState* wsel = nullptr;
+    unsigned long long* whist = nullptr;
+    long long* wcsum = nullptr;
     std::string err;
 };
 
@@ -1300,6 +1309,11 @@ void surface_free(mbo_surface_t s)
     free_dev(s->nwts);
     free_dev(s->tiles);
     free_dev(s->binmap);
+    free_dev(s->Wd);
+    free_dev(s->de);
+    free_dev(s->wsel);
+    free_dev(s->whist);
+    free_dev(s->wcsum);
     for (auto* b : {&s->spread, &s->interp, &s->cellbins}) {
         free_dev(b->pos);
         free_dev(b->wts);
@@ -1470,6 +1484,38 @@ SurfArgs surf_args(mbo_surface_t s, const mbo_surface_s::Bins& B)
     a.bin = B.bin;
     a.nbins = B.nbins;
     a.Z = s->grid->Z;
+    return a;
+}
+
+// Device state of the volume-preserving step, allocated on first use.
+mbo_status ensure_surface_volume(mbo_surface_t s)
+{
+    if (s->wsel) return MBO_OK;
+    const int64_t nch = (s->m + WSEL_CHUNK - 1) / WSEL_CHUNK;
+    SHIP(s, hipMalloc((void**)&s->Wd, (size_t)s->m * 8 + 8));
+    SHIP(s, hipMemcpy(s->Wd, s->Wh.data(), (size_t)s->m * 8, hipMemcpyHostToDevice));
+    SHIP(s, hipMalloc(&s->de, (size_t)s->m * s->esz + 8));
+    SHIP(s, hipMalloc((void**)&s->whist, 256 * sizeof(unsigned long long)));
+    SHIP(s, hipMemset(s->whist, 0, 256 * sizeof(unsigned long long)));
+    SHIP(s, hipMalloc((void**)&s->wcsum, (size_t)nch * 8 + 8));
+    SHIP(s, hipMalloc((void**)&s->wsel, sizeof(WSelState)));
+    return MBO_OK;
+}
+
+SurfVolArgs surf_vol_args(mbo_surface_t s)
+{
+    SurfVolArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.m = s->m;
+    a.D = s->tmp;
+    a.de = s->de;
+    a.W = s->Wd;
+    a.sel = s->wsel;
+    a.hist = s->whist;
+    a.csum = s->wcsum;
+    a.nonfinite = s->counters;
+    a.fallback = s->prec == MBO_F32_F64FALLBACK;
+    a.sigma_fb = 1e-3;
     return a;
 }
 
@@ -2252,6 +2298,14 @@ mbo_status mbo_surface_sphere(mbo_surface_t* out, double radius, double dx, int 
                     s->xc[(size_t)(2 * m + q)] = r > 0.0 ? radius * z / r : 0.0;
                     s->wq[(size_t)q] = dx * dx * dx * nw[a] * nw[b] * nw[e];
                 }
+    // integer volume weights (Algorithm 3): the quadrature weight in units of
+    // 2^-30 dx^3, so that sums of them are exact
+    s->Wh.resize((size_t)m);
+    s->Wtotal = 0;
+    for (int64_t q = 0; q < m; ++q) {
+        s->Wh[(size_t)q] = (int64_t)std::llround(s->wq[(size_t)q] / (dx * dx * dx) * 1073741824.0);
+        s->Wtotal += s->Wh[(size_t)q];
+    }
     // the periodic grid.  Gridding tolerance eg = eps / 10 (the gridding error
     // at a target grows with the strength of the sources within reach, about
     // (4 pi tau)^{-3/2} times the band volume, so it gets a tenth of the band's
@@ -2404,6 +2458,86 @@ mbo_status mbo_surface_diffuse(mbo_surface_t s, const void* A_in, void* A_out)
     if (A_in == A_out) return sfail(s, MBO_ERR_INVALID_ARG, "A_out must not alias A_in");
     SHIP(s, hipSetDevice(s->grid->device));
     SHIP(s, enqueue_surface_diffuse(s, A_in, A_out, s->stream));
+    return MBO_OK;
+}
+
+mbo_status mbo_surface_volume_weights(mbo_surface_t s, int64_t* W)
+{
+    if (!s || !W) return MBO_ERR_INVALID_ARG;
+    std::memcpy(W, s->Wh.data(), s->Wh.size() * sizeof(int64_t));
+    return MBO_OK;
+}
+
+mbo_status mbo_surface_volume_select(mbo_surface_t s, const void* dE, int64_t V, uint8_t* selected)
+{
+    if (!s) return MBO_ERR_INVALID_ARG;
+    if (!dE || !selected) return sfail(s, MBO_ERR_INVALID_ARG, "dE / selected is NULL");
+    SHIP(s, hipSetDevice(s->grid->device));
+    mbo_status st = ensure_surface_volume(s);
+    if (st != MBO_OK) return st;
+    SurfVolArgs a = surf_vol_args(s);
+    a.de = const_cast<void*>(dE);
+    a.selected = selected;
+    SHIP(s, launch_wsel(s->pk, a, (long long)V, (long long)s->Wtotal, s->stream));
+    SHIP(s, launch_wsel_mark(s->pk, a, s->stream));
+    SHIP(s, hipStreamSynchronize(s->stream));
+    return MBO_OK;
+}
+
+mbo_status mbo_surface_iterate_volume(mbo_surface_t s, void* A, int K, const int64_t* V, int64_t* V_used,
+                                      int64_t* flips)
+{
+    if (!s) return MBO_ERR_INVALID_ARG;
+    if (!A) return sfail(s, MBO_ERR_INVALID_ARG, "A is NULL");
+    if (K < 0) return sfail(s, MBO_ERR_INVALID_ARG, "K < 0");
+    SHIP(s, hipSetDevice(s->grid->device));
+    mbo_status st = ensure_surface_volume(s);
+    if (st != MBO_OK) return st;
+    SHIP(s, launch_fill_u64(s->counters, 4, 0ull, s->stream));
+    std::vector<int8_t> prev, cur;
+    int64_t vol = V ? *V : 0;
+    if (!V || flips) {
+        // det signs of A_0 (its projection into tmp is discarded)
+        ProjArgs a0;
+        std::memset(&a0, 0, sizeof a0);
+        a0.npts = s->m;
+        a0.A = A;
+        a0.Q = s->tmp;
+        a0.dsign = s->sgn;
+        a0.nonfinite = s->counters + 2;
+        a0.fallbacks = s->counters + 3;
+        SHIP(s, launch_project(s->pk, s->n, a0, 1, s->stream));
+        prev.resize((size_t)s->m);
+        SHIP(s, hipMemcpyAsync(prev.data(), s->sgn, (size_t)s->m, hipMemcpyDeviceToHost, s->stream));
+        SHIP(s, hipStreamSynchronize(s->stream));
+        if (!V) {
+            vol = 0;
+            for (int64_t q = 0; q < s->m; ++q) vol += prev[(size_t)q] > 0 ? s->Wh[(size_t)q] : 0;
+        }
+    }
+    if (V_used) *V_used = vol;
+    for (int it = 0; it < K; ++it) {
+        SHIP(s, enqueue_surface_diffuse(s, A, s->tmp, s->stream));
+        SurfVolArgs a = surf_vol_args(s);
+        a.A = A;
+        a.sgn = s->sgn;
+        SHIP(s, launch_surf_vp_key(s->pk, s->n, a, s->stream));
+        SHIP(s, launch_wsel(s->pk, a, (long long)vol, (long long)s->Wtotal, s->stream));
+        SHIP(s, launch_surf_vp_apply(s->pk, s->n, a, s->stream));
+        if (flips) {
+            cur.resize((size_t)s->m);
+            SHIP(s, hipMemcpyAsync(cur.data(), s->sgn, (size_t)s->m, hipMemcpyDeviceToHost, s->stream));
+            SHIP(s, hipStreamSynchronize(s->stream));
+            int64_t f = 0;
+            for (int64_t i = 0; i < s->m; ++i) f += cur[(size_t)i] != prev[(size_t)i];
+            flips[it] = f;
+            prev.swap(cur);
+        }
+    }
+    unsigned long long h[4];
+    SHIP(s, hipMemcpyAsync(h, s->counters, sizeof h, hipMemcpyDeviceToHost, s->stream));
+    SHIP(s, hipStreamSynchronize(s->stream));
+    if (h[0]) return sfail(s, MBO_ERR_NONFINITE, "%llu samples with NaN/Inf values", h[0]);
     return MBO_OK;
 }
 

@@ -300,6 +300,38 @@ inline size_t surface_cell_lds(int p, int U, int waves, int chunk, size_t esz)
             (size_t)waves * surface_cell_scratch(p, U)) * esz + (size_t)chunk * 8;
 }
 
+// Volume-preserving MBO on a surface: the weighted selection of Algorithm 3
+// (samples in descending Delta E order, ties by ascending index, taken while
+// their integer volume weights sum below V) and the reassignment of Lemma 7.2.
+constexpr int WSEL_CHUNK = 4096;  // samples per workgroup of the tie scan
+struct WSelState {
+    unsigned long long prefix;  // digits of kstar found so far
+    unsigned long long kstar;   // key of the last sample taken
+    long long vrem;             // weight still needed among the keys matching prefix
+    long long istar;            // the last sample taken among those with key kstar
+    int mode;                   // VpMode: VS_SEARCH until the tie scan ends, VS_NONE, VS_ALL, VS_TIES_PART
+    int pad;
+};
+struct SurfVolArgs {
+    int64_t m;                 // samples
+    const void* D;             // diffused field, entry-planar [n*n][m] (plan precision)
+    void* A;                   // reassigned field, entry-planar [n*n][m]
+    void* de;                  // [m] Delta E
+    const int64_t* W;          // [m] volume weights
+    WSelState* sel;
+    unsigned long long* hist;  // [256] weights per digit (zero between passes)
+    long long* csum;           // [chunks] tie weight per chunk
+    int8_t* sgn;               // [m] nullable: +1 where T+ was taken, -1 elsewhere
+    uint8_t* selected;         // [m] selection mask (mark only)
+    unsigned long long* nonfinite;
+    int fallback;
+    double sigma_fb;
+};
+hipError_t launch_surf_vp_key(int prec, int n, const SurfVolArgs& a, hipStream_t st);
+hipError_t launch_wsel(int prec, const SurfVolArgs& a, long long V, long long total, hipStream_t st);
+hipError_t launch_wsel_mark(int prec, const SurfVolArgs& a, hipStream_t st);
+hipError_t launch_surf_vp_apply(int prec, int n, const SurfVolArgs& a, hipStream_t st);
+
 // per-translation-unit launchers behind launch_row / launch_col
 hipError_t launch_row_f32(int n, int log2L, const RowArgs& a, dim3 g, dim3 b, size_t lds,
                           hipStream_t st, bool prepare, hipEvent_t ev0, hipEvent_t ev1);

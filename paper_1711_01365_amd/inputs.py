@@ -210,6 +210,8 @@ SPHERE_MATRICES = np.array([[[0.392227, 0.706046, 0.046171],
                              [0.890903, 0.138624, 0.840717],
                              [0.959291, 0.149294, 0.254282]]])
 SPHERE_PAPER = SphereWorkload("sphere_R1_dx0.05_p3_tau0.005", 1.0, 0.05, 3, 0.005, 1e-6, 3, 20)
+# the volume-preserving sphere of Section 7 (same band construction, tau = 0.01)
+SPHERE_VOLUME_PAPER = SphereWorkload("sphere_volume_R1_dx0.05_p3_tau0.01", 1.0, 0.05, 3, 0.01, 1e-6, 3, 20)
 
 
 def sphere_octant_field(xc: np.ndarray) -> np.ndarray:

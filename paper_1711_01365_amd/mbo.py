@@ -33,6 +33,7 @@ EXPORTS = ("mbo_plan", "mbo_plan_destroy", "mbo_plan_set_tau", "mbo_plan_set_str
            "mbo_project_volume", "mbo_iterate_volume", "mbo_so2_index", "mbo_relaxed_flow",
            "mbo_relaxed_energy", "mbo_surface_sphere", "mbo_surface_destroy", "mbo_surface_info",
            "mbo_surface_points", "mbo_surface_diffuse", "mbo_surface_iterate", "mbo_surface_last_error",
+           "mbo_surface_volume_weights", "mbo_surface_volume_select", "mbo_surface_iterate_volume",
            "mbo_status_string", "mbo_last_error")
 
 
@@ -90,6 +91,9 @@ def load(path: str = LIB_PATH):
     lib.mbo_surface_points.argtypes = [vp, dp, dp, dp]
     lib.mbo_surface_diffuse.argtypes = [vp, vp, vp]
     lib.mbo_surface_iterate.argtypes = [vp, vp, ctypes.c_int, i64p]
+    lib.mbo_surface_volume_weights.argtypes = [vp, i64p]
+    lib.mbo_surface_volume_select.argtypes = [vp, vp, ctypes.c_int64, vp]
+    lib.mbo_surface_iterate_volume.argtypes = [vp, vp, ctypes.c_int, i64p, i64p, i64p]
     lib.mbo_surface_last_error.argtypes = [vp]
     lib.mbo_surface_last_error.restype = ctypes.c_char_p
     for f in EXPORTS:
@@ -454,6 +458,34 @@ class SphereSurface:
             self._h, self._field(A), int(K),
             fl.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if fl is not None else None))
         return fl[:K] if fl is not None else None
+
+    def volume_weights(self):
+        """Integer volume weights of the samples (numpy int64 [m])."""
+        W = np.zeros(self.m, dtype=np.int64)
+        self._check(self._lib.mbo_surface_volume_weights(self._h, W.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return W
+
+    def volume_select(self, dE, V: int):
+        """uint8 device mask of Algorithm 3's selection for the values dE."""
+        import torch
+        if not isinstance(dE, torch.Tensor) or not dE.is_cuda or dE.dtype != self.dtype \
+                or tuple(dE.shape) != (self.m,) or not dE.is_contiguous():
+            raise ValueError("dE must be a contiguous %s device tensor of shape (%d,)" % (self.dtype, self.m))
+        sel = torch.empty(self.m, dtype=torch.uint8, device=dE.device)
+        self._check(self._lib.mbo_surface_volume_select(self._h, ctypes.c_void_p(dE.data_ptr()), int(V),
+                                                        ctypes.c_void_p(sel.data_ptr())))
+        return sel
+
+    def iterate_volume(self, A, K: int, V=None, flips: bool = False):
+        """K volume-preserving steps in place on A; returns (V used, flips or None)."""
+        i64 = ctypes.POINTER(ctypes.c_int64)
+        vin = None if V is None else np.array([int(V)], dtype=np.int64)
+        vu = np.zeros(1, dtype=np.int64)
+        fl = np.zeros(max(int(K), 1), dtype=np.int64) if flips else None
+        self._check(self._lib.mbo_surface_iterate_volume(
+            self._h, self._field(A), int(K), None if vin is None else vin.ctypes.data_as(i64), vu.ctypes.data_as(i64),
+            fl.ctypes.data_as(i64) if fl is not None else None))
+        return int(vu[0]), (fl[:K] if fl is not None else None)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -149,6 +149,9 @@ def test_surface_calls_validate_before_touching_the_device(lib):
     assert lib.mbo_surface_diffuse(None, None, None) == 1
     assert lib.mbo_surface_iterate(None, None, 1, None) == 1
     assert lib.mbo_surface_destroy(None) == 0
+    assert lib.mbo_surface_volume_weights(None, None) == 1
+    assert lib.mbo_surface_volume_select(None, None, 1, None) == 1
+    assert lib.mbo_surface_iterate_volume(None, None, 1, None, None, None) == 1
     h = ctypes.c_void_p()
     assert lib.mbo_surface_sphere(None, 1.0, 0.1, 1, 0.01, 1e-6, 3, 0, None) == 1
     for bad in [(-1.0, 0.1, 1, 0.01, 1e-6, 3, 0), (1.0, 0.0, 1, 0.01, 1e-6, 3, 0),

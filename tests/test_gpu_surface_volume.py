@@ -1,0 +1,197 @@
+"""GPU parity of volume-preserving MBO on the sphere (Section 7, Algorithm 3 with
+the reassignment of Lemma 7.2) through the C ABI, against the FP64 oracle.
+
+Bars:
+  * volume weights: identical integers;
+  * the selection alone: bit-exact masks for the same Delta E values (FP64 and
+    float values with many ties and signed zeros, V from none to all), also at
+    the 5.1 M samples of the paper's volume-preserving sphere;
+  * one step from the same field, FP64, wherever Delta E is not within 1e-5 of
+    the cut value (samples deep inside a uniform region have Delta E within
+    ~1e-9 of each other, and their order follows the diffusion's last digits):
+    the same component for every sample, the same distance to the diffused
+    matrix (to 1e-9), the same matrix where the minimiser is unique (to 1e-9
+    for T+, and 1e-9 + 1e-10 / gap for T-, whose sensitivity grows as the
+    smallest singular value nears the next; T- is not unique when they
+    coincide), and the kept volume in [V, V + max w) exactly;
+  * the paper's configuration (dx = 0.05, p = 3, tau = 0.01, FP32): the volume
+    stays in [V, V + max w) at every step while the interface moves.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_01365_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*a):
+    print("[gpu-surface-volume]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1711_01365_amd import mbo
+    mbo.load()
+    return torch
+
+
+def surface(R, dx, p, tau, eps, n, prec):
+    from paper_1711_01365_amd import mbo
+    return mbo.SphereSurface(R, dx, p, tau, eps, n, precision=prec)
+
+
+def band_of(s):
+    xq, xc, w = s.points()
+    return {"xq": xq, "xc": xc, "w": w, "cells": s.cells, "wb": s.band_width}
+
+
+def octant_start(b):
+    M = inputs.SPHERE_MATRICES
+    Q = oracle.project(np.stack([M[0], M[1]], axis=-1).reshape(3, 3, 2))[0]
+    x, y, z = b["xc"]
+    inside = (x < 0) & (y < 0) & (z > 0)
+    return np.where(inside[None, None, :], Q[:, :, 0:1], Q[:, :, 1:2])
+
+
+def test_weights_match_oracle(torch_cuda):
+    from paper_1711_01365_amd import mbo
+    for dx, p in ((0.15, 1), (0.2, 3)):
+        s = surface(1.0, dx, p, 0.01, 1e-6, 3, mbo.F64)
+        W = s.volume_weights()
+        assert np.array_equal(W, oracle.surface_weights(band_of(s), dx))
+        s.close()
+
+
+@pytest.mark.parametrize("prec_name", ["F64", "F32"])
+def test_selection_is_bit_exact(torch_cuda, prec_name):
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    prec = getattr(mbo, prec_name)
+    s = surface(1.0, 0.15, 3, 0.01, 1e-6, 3, prec)
+    W = s.volume_weights()
+    total = int(W.sum())
+    rng = np.random.default_rng(1400)
+    dt = torch.float64 if prec == mbo.F64 else torch.float32
+    npdt = np.float64 if prec == mbo.F64 else np.float32
+    for trial in range(3):
+        if trial == 0:
+            dE = (rng.integers(-40, 40, s.m) / 8.0).astype(npdt)  # heavy ties
+            dE[rng.integers(0, s.m, 50)] = -0.0
+        elif trial == 1:
+            dE = rng.standard_normal(s.m).astype(npdt)
+        else:
+            dE = np.zeros(s.m, dtype=npdt)  # one tie class
+        d = torch.tensor(dE, dtype=dt, device="cuda")
+        for V in (-3, 0, 1, total // 7, total // 2, total - 1, total, total + 5):
+            got = s.volume_select(d, V).cpu().numpy()
+            want = oracle.weighted_select(dE.astype(np.float64), W, V)
+            assert np.array_equal(got, want.astype(np.uint8)), (prec_name, trial, V)
+    note("selection", prec_name, "m", s.m)
+    s.close()
+
+
+def test_selection_at_the_paper_size(torch_cuda):
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    w = inputs.SPHERE_VOLUME_PAPER
+    s = surface(w.R, w.dx, w.p, w.tau, w.eps, w.n, mbo.F32_F64FALLBACK)
+    W = s.volume_weights()
+    rng = np.random.default_rng(1401)
+    dE = (rng.integers(-3000, 3000, s.m) / 64.0).astype(np.float32)
+    d = torch.tensor(dE, device="cuda")
+    for V in (int(W.sum()) // 5, int(W.sum()) // 2 + 12345):
+        got = s.volume_select(d, V).cpu().numpy()
+        want = oracle.weighted_select(dE.astype(np.float64), W, V)
+        assert np.array_equal(got, want.astype(np.uint8))
+    note("selection at", s.m, "samples")
+    s.close()
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_one_step_matches_oracle(torch_cuda, p):
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    tau, dx, eps = 0.01, 0.15 if p == 1 else 0.2, 1e-9
+    s = surface(1.0, dx, p, tau, eps, 3, mbo.F64)
+    b = band_of(s)
+    W = s.volume_weights()
+    A0 = octant_start(b)
+    for V in (None, int(W.sum()) // 3):
+        ref, fl_ref, v_ref = oracle.surface_iterate_volume(b, W, A0, tau, 1, V)
+        X = torch.tensor(A0, device="cuda")
+        v_got, fl = s.iterate_volume(X, 1, V, flips=True)
+        got = X.cpu().numpy()
+        assert v_got == v_ref
+        D = oracle.surface_diffuse(b, A0, tau)
+        _, dE, _ = oracle.volume_project(D, 0)
+        sel = oracle.weighted_select(dE, W, v_ref).astype(bool)
+        order = np.lexsort((np.arange(s.m), -dE))
+        k = int(sel.sum())
+        cut = dE[order[k - 1]] if k > 0 else np.inf
+        clear = np.abs(dE - cut) > 1e-5
+        Dm = np.moveaxis(D, 2, 0)
+        sv = np.linalg.svd(Dm, compute_uv=False)
+        unique = (sv[:, -2] - sv[:, -1]) > 1e-6 * sv[:, 0]
+        det = np.linalg.det(np.moveaxis(got, 2, 0))
+        det_ref = np.linalg.det(np.moveaxis(ref, 2, 0))
+        assert np.array_equal(np.sign(det[clear]), np.sign(det_ref[clear]))
+        dist = np.linalg.norm(np.moveaxis(got, 2, 0) - Dm, axis=(1, 2))
+        dist_ref = np.linalg.norm(np.moveaxis(ref, 2, 0) - Dm, axis=(1, 2))
+        derr = np.abs(dist - dist_ref)[clear].max()
+        # T+ = U V^t is well conditioned; T- moves by about |dD| / gap under a
+        # perturbation dD of the diffused matrix (gap: the distance of sigma_min
+        # to the next singular value), and is not unique when the gap is zero
+        gap = np.maximum(sv[:, -2] - sv[:, -1], 1e-300)
+        allow = np.where(det > 0, 1e-9, 1e-9 + 1e-10 / gap)
+        sel_cmp = clear & (unique | (det > 0))
+        err = (np.abs(got - ref).max(axis=(0, 1)) / allow)[sel_cmp].max() * 1e-9
+        vol = int(W[det > 0].sum())
+        note("p", p, "V", v_ref, "m", s.m, "near the cut", int((~clear).sum()), "repeated sigma_min",
+             int((~unique).sum()), "err", err, "dist err", derr, "flips", fl, fl_ref)
+        assert err <= 1e-9 and derr <= 1e-9
+        assert v_ref <= vol < v_ref + W.max()
+    s.close()
+
+
+def test_zero_and_full_volume(torch_cuda):
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    s = surface(1.0, 0.2, 1, 0.01, 1e-6, 3, mbo.F64)
+    A0 = octant_start(band_of(s))
+    X = torch.tensor(A0, device="cuda")
+    s.iterate_volume(X, 1, 0)
+    assert (np.linalg.det(np.moveaxis(X.cpu().numpy(), 2, 0)) < 0).all()
+    X = torch.tensor(A0, device="cuda")
+    s.iterate_volume(X, 1, 1 << 62)
+    assert (np.linalg.det(np.moveaxis(X.cpu().numpy(), 2, 0)) > 0).all()
+    s.close()
+
+
+def test_paper_configuration_keeps_the_volume(torch_cuda):
+    """Section 7's sphere (dx = 0.05, p = 3, tau = 0.01, eps = 1e-6), float:
+    V defaults to the initial SO(3) volume, which every step keeps within one
+    sample's weight while the interface moves."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    w = inputs.SPHERE_VOLUME_PAPER
+    s = surface(w.R, w.dx, w.p, w.tau, w.eps, w.n, mbo.F32_F64FALLBACK)
+    b = band_of(s)
+    W = s.volume_weights()
+    A0 = inputs.sphere_octant_field(b["xc"])
+    V0 = int(W[np.linalg.det(np.moveaxis(A0, 2, 0)) >= 0].sum())
+    X = torch.tensor(A0, dtype=torch.float32, device="cuda")
+    for step in range(4):
+        vu, fl = s.iterate_volume(X, 1, V0 if step else None, flips=True)
+        assert vu == V0
+        det = np.linalg.det(np.moveaxis(X.double().cpu().numpy(), 2, 0))
+        vol = int(W[det > 0].sum())
+        note("step", step, "m", s.m, "flips", int(fl[0]), "volume", vol, "V", V0)
+        assert V0 <= vol < V0 + W.max() and fl[0] > 0
+    s.close()
