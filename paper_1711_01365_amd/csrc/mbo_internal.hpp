@@ -286,12 +286,14 @@ __host__ __device__ inline size_t surface_cell_scratch(int p, int U)
 {
     return (size_t)(3 * p * U + 2 * p * p * U + 2 * p * U * U);
 }
-// LDS of the line-owner variant: chunk ids and staged cells, weights, T1 and
-// the padded T2 (k pitch SURF_BIN + 22 + 3)
+// LDS of the line-owner variant: chunk ids and staged cells, and per cell of a
+// round the weights, T1 and the padded T2 (k pitch SURF_BIN + 22 + 3)
+constexpr int SURF_LINE_CB = 4;  // cells contracted per round of workgroup barriers
 inline size_t surface_lines_lds(int p, int U, int chunk, size_t esz)
 {
     return (size_t)chunk * 8 +
-           ((size_t)chunk * (3 + 2 * p * p * p) + 3 * p * U + 2 * p * p * U + 2 * p * U * (SURF_BIN + 22 + 3)) * esz;
+           ((size_t)chunk * (3 + 2 * p * p * p) +
+            (size_t)SURF_LINE_CB * (3 * p * U + 2 * p * p * U + 2 * p * U * (SURF_BIN + 22 + 3))) * esz;
 }
 inline size_t surface_cell_lds(int p, int U, int waves, int chunk, size_t esz)
 {

@@ -299,32 +299,36 @@ __global__ void __launch_bounds__(256) surface_spread_cells(const SurfArgs a, un
 
 // The same spreading without LDS atomics (LDS float atomics run at a small
 // fraction of the LDS rate): each thread owns one z-line (x, y) of the bin's
-// tile in registers, TE <= SURF_LINE_MAX.  Cells are taken one at a time by the whole
-// workgroup: weights, T1 and T2 as above (T2 with its k axis zero-padded by
-// SURF_BIN on the low side and odd pitch SURF_LINE_KP, so that a line reads
-// T2[a][y - y0][z - z0] for every z without bounds tests), then every line
-// inside the cell's block adds sum_a Wx[a][x - x0] T2[a][y - y0][.] to its
-// registers.  Lanes of a wave share x rarely and y often, so most T2 reads are
-// broadcasts.
-constexpr int SURF_LINE_MAX = 22;                    // tile edge limit (TE^2 <= 512 lines)
+// tile in registers, TE <= SURF_LINE_MAX.  Cells are taken SURF_LINE_CB at a
+// time by the whole workgroup: weights, T1 and T2 of every cell of the round
+// as above (T2 with its k axis zero-padded by SURF_BIN on the low side and odd
+// pitch SURF_LINE_KP, so that a line reads T2[a][y - y0][z - z0] for every z
+// without bounds tests), then every line inside a cell's block adds
+// sum_a Wx[a][x - x0] T2[a][y - y0][.] to its registers.  Lanes of a wave share
+// x rarely and y often, so most T2 reads are broadcasts.
+constexpr int SURF_LINE_MAX = 22;                           // tile edge limit (TE^2 <= 512 lines)
 constexpr int SURF_LINE_KP = SURF_BIN + SURF_LINE_MAX + 3;  // padded k pitch (odd)
 
+// Reciprocals for fdiv of the line kernel's index splits.
+struct LineRecip {
+    unsigned p3, U, pU, UU, pU3, ppU, pUU;
+};
+
 template <typename T, int P>
-__global__ void __launch_bounds__(512) surface_spread_lines(const SurfArgs a, unsigned Mp3, unsigned MU,
-                                                            unsigned MpU, unsigned MUU)
+__global__ void __launch_bounds__(512) surface_spread_lines(const SurfArgs a, const LineRecip M)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    constexpr int p = P, p3 = P * P * P;
+    constexpr int p = P, p3 = P * P * P, CB = SURF_LINE_CB;
     const int TE = a.TE;
     const int U = a.U, pU = p * U, ppU = p * p * U, pUU = p * U * U, UU = U * U;
     const int CH = a.chunk, cst = 3 + 2 * p3;
     const int tid = threadIdx.x, NT = blockDim.x;
+    const int t2p = p * U * SURF_LINE_KP;
     int64_t* ids = reinterpret_cast<int64_t*>(smem_raw);  // [CH]
     T* stage = reinterpret_cast<T*>(ids + CH);           // [CH][3 + 2 p^3]
-    T* Ws = stage + (size_t)CH * cst;                    // [3][p][U]
-    T* T1 = Ws + 3 * pU;                                 // [2][p^2][U]
-    T* T2 = T1 + 2 * ppU;                                // [2][p][U][SURF_LINE_KP]
-    const int t2p = p * U * SURF_LINE_KP;
+    T* Ws = stage + (size_t)CH * cst;                    // [CB][3][p][U]
+    T* T1 = Ws + CB * 3 * pU;                            // [CB][2][p^2][U]
+    T* T2 = T1 + CB * 2 * ppU;                           // [CB][2][p][U][SURF_LINE_KP]
 
     const int nb = blockIdx.x, pl = a.pl0 + (int)blockIdx.y;
     const int nn = a.n * a.n, e0 = 2 * pl, e1 = e0 + 1;
@@ -345,6 +349,13 @@ __global__ void __launch_bounds__(512) surface_spread_lines(const SurfArgs a, un
         nd[an] = reinterpret_cast<const T*>(a.nodes)[an];
         nwt[an] = reinterpret_cast<const T*>(a.nwts)[an];
     }
+    // union start of a staged cell along axis d, relative to the tile (0 ..
+    // SURF_BIN for a cell listed in this bin; clamped: see the atomic variant)
+    auto start_of = [&](const T* cs, int d) {
+        const T u0 = (cs[d] + nd[0] - y0) * invh;
+        const int rr = (int)ceil(u0 - W) - o[d];
+        return rr < 0 ? 0 : (rr > TE - U ? TE - U : rr);
+    };
     // this thread's line: x = tid / TE, y = tid % TE (y fastest)
     const bool owns = tid < TE * TE;
     const int lx = owns ? tid / TE : 0, ly = owns ? tid - (tid / TE) * TE : 0;
@@ -354,7 +365,7 @@ __global__ void __launch_bounds__(512) surface_spread_lines(const SurfArgs a, un
         accr[z] = (T)0;
         acci[z] = (T)0;
     }
-    for (int i = tid; i < 2 * t2p; i += NT) T2[i] = (T)0;  // the padding stays zero
+    for (int i = tid; i < CB * 2 * t2p; i += NT) T2[i] = (T)0;  // the padding stays zero
 
     for (int64_t cb = c0; cb < c1; cb += CH) {
         const int nch = (int)(c1 - cb < CH ? c1 - cb : CH);
@@ -373,7 +384,7 @@ __global__ void __launch_bounds__(512) surface_spread_lines(const SurfArgs a, un
             for (int u = 0; u < 4; ++u) {
                 const int i = i0 + u * NT;
                 const int ii = i < tot ? i : tot - 1;
-                const int c = fdiv(ii, Mp3), e = ii - c * p3;
+                const int c = fdiv(ii, M.p3), e = ii - c * p3;
                 const int64_t q = ids[c] + e;
                 vr[u] = Are[q];
                 vi[u] = Aim[q];
@@ -387,22 +398,13 @@ __global__ void __launch_bounds__(512) surface_spread_lines(const SurfArgs a, un
                 }
             }
         }
-        for (int c = 0; c < nch; ++c) {
-            __syncthreads();  // staged values visible; the previous cell's scratch is read
-            const T* cs = stage + c * cst;
-            const T* Vr = cs + 3;
-            const T* Vi = cs + 3 + p3;
-            // union start per axis relative to the tile (clamped: see the
-            // atomic variant above)
-            int r0[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const T u0 = (cs[d] + nd[0] - y0) * invh;
-                const int rr = (int)ceil(u0 - W) - o[d];
-                r0[d] = rr < 0 ? 0 : (rr > TE - U ? TE - U : rr);
-            }
-            for (int e = tid; e < 3 * pU; e += NT) {
-                const int d = fdiv(e, MpU), r = e - d * pU, an = fdiv(r, MU), i = r - an * U;
+        for (int cr = 0; cr < nch; cr += CB) {
+            const int nr = nch - cr < CB ? nch - cr : CB;  // cells of this round
+            __syncthreads();  // staged values visible; the previous round's scratch is read
+            for (int e = tid; e < nr * 3 * pU; e += NT) {
+                const int c = fdiv(e, M.pU3), r3 = e - c * 3 * pU;
+                const int d = fdiv(r3, M.pU), r = r3 - d * pU, an = fdiv(r, M.U), i = r - an * U;
+                const T* cs = stage + (cr + c) * cst;
                 T ndv = nd[0], nwv_ = nwt[0];
 #pragma unroll
                 for (int k = 1; k < P; ++k) {
@@ -410,51 +412,62 @@ __global__ void __launch_bounds__(512) surface_spread_lines(const SurfArgs a, un
                     nwv_ = an == k ? nwt[k] : nwv_;
                 }
                 const T u = (cs[d] + ndv - y0) * invh;
-                Ws[e] = nwv_ * es_kernel<T>((T)(o[d] + r0[d] + i) - u, invW, beta);
+                Ws[e] = nwv_ * es_kernel<T>((T)(o[d] + start_of(cs, d) + i) - u, invW, beta);
             }
             __syncthreads();
-            for (int e = tid; e < ppU; e += NT) {
-                const int ab = fdiv(e, MU), k = e - ab * U;
+            for (int e = tid; e < nr * ppU; e += NT) {
+                const int c = fdiv(e, M.ppU), r = e - c * ppU, ab = fdiv(r, M.U), k = r - ab * U;
+                const T* cs = stage + (cr + c) * cst;
+                const T* W3 = Ws + c * 3 * pU;
                 T s0 = 0, s1 = 0;
 #pragma unroll
                 for (int c3 = 0; c3 < P; ++c3) {
-                    const T wz = Ws[(2 * p + c3) * U + k];
-                    s0 += wz * Vr[ab * p + c3];
-                    s1 += wz * Vi[ab * p + c3];
+                    const T wz = W3[(2 * p + c3) * U + k];
+                    s0 += wz * cs[3 + ab * p + c3];
+                    s1 += wz * cs[3 + p3 + ab * p + c3];
                 }
-                T1[e] = s0;
-                T1[ppU + e] = s1;
+                T1[c * 2 * ppU + r] = s0;
+                T1[c * 2 * ppU + ppU + r] = s1;
             }
             __syncthreads();
-            for (int e = tid; e < pUU; e += NT) {
-                const int an = fdiv(e, MUU), r = e - an * UU, j = fdiv(r, MU), k = r - j * U;
+            for (int e = tid; e < nr * pUU; e += NT) {
+                const int c = fdiv(e, M.pUU), r = e - c * pUU;
+                const int an = fdiv(r, M.UU), r2 = r - an * UU, j = fdiv(r2, M.U), k = r2 - j * U;
+                const T* W3 = Ws + c * 3 * pU;
+                const T* t1 = T1 + c * 2 * ppU;
                 T s0 = 0, s1 = 0;
 #pragma unroll
                 for (int b = 0; b < P; ++b) {
-                    const T wy = Ws[(p + b) * U + j];
-                    s0 += wy * T1[(an * p + b) * U + k];
-                    s1 += wy * T1[ppU + (an * p + b) * U + k];
+                    const T wy = W3[(p + b) * U + j];
+                    s0 += wy * t1[(an * p + b) * U + k];
+                    s1 += wy * t1[ppU + (an * p + b) * U + k];
                 }
-                const int dst = (an * U + j) * SURF_LINE_KP + SURF_BIN + k;
+                const int dst = c * 2 * t2p + (an * U + j) * SURF_LINE_KP + SURF_BIN + k;
                 T2[dst] = s0;
                 T2[t2p + dst] = s1;
             }
             __syncthreads();
-            const int ii = lx - r0[0], jj = ly - r0[1];
-            if (owns && ii >= 0 && ii < U && jj >= 0 && jj < U) {
-                T wx[P];
+            if (owns) {
+                for (int c = 0; c < nr; ++c) {
+                    const T* cs = stage + (cr + c) * cst;
+                    const int ii = lx - start_of(cs, 0), jj = ly - start_of(cs, 1);
+                    if (ii >= 0 && ii < U && jj >= 0 && jj < U) {
+                        const T* W3 = Ws + c * 3 * pU;
+                        T wx[P];
 #pragma unroll
-                for (int an = 0; an < P; ++an) wx[an] = Ws[an * U + ii];
-                // element z of the line reads T2[.][jj][z - r0z] at padded index
-                // SURF_BIN + z - r0z in [0, SURF_BIN + SURF_LINE_MAX)
-                const T* br = T2 + jj * SURF_LINE_KP + SURF_BIN - r0[2];
-                const T* bi = br + t2p;
+                        for (int an = 0; an < P; ++an) wx[an] = W3[an * U + ii];
+                        // element z of the line reads T2[.][jj][z - z0] at padded
+                        // index SURF_BIN + z - z0 in [0, SURF_BIN + SURF_LINE_MAX)
+                        const T* br = T2 + c * 2 * t2p + jj * SURF_LINE_KP + SURF_BIN - start_of(cs, 2);
+                        const T* bi = br + t2p;
 #pragma unroll
-                for (int z = 0; z < SURF_LINE_MAX; ++z) {
+                        for (int z = 0; z < SURF_LINE_MAX; ++z) {
 #pragma unroll
-                    for (int an = 0; an < P; ++an) {
-                        accr[z] += wx[an] * br[an * U * SURF_LINE_KP + z];
-                        acci[z] += wx[an] * bi[an * U * SURF_LINE_KP + z];
+                            for (int an = 0; an < P; ++an) {
+                                accr[z] += wx[an] * br[an * U * SURF_LINE_KP + z];
+                                acci[z] += wx[an] * bi[an * U * SURF_LINE_KP + z];
+                            }
+                        }
                     }
                 }
             }
@@ -637,8 +650,16 @@ static hipError_t surf_lines_p(const SurfArgs& a, hipStream_t st)
     const void* f = reinterpret_cast<const void*>(&surface_spread_lines<T, P>);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    LineRecip M;
+    M.p3 = recip32(P * P * P);
+    M.U = recip32(a.U);
+    M.pU = recip32(P * a.U);
+    M.UU = recip32(a.U * a.U);
+    M.pU3 = recip32(3 * P * a.U);
+    M.ppU = recip32(P * P * a.U);
+    M.pUU = recip32(P * a.U * a.U);
     hipLaunchKernelGGL((surface_spread_lines<T, P>), dim3((unsigned)a.nbins, (unsigned)(a.pl1 - a.pl0)), dim3(512),
-                       lds, st, a, recip32(P * P * P), recip32(a.U), recip32(P * a.U), recip32(a.U * a.U));
+                       lds, st, a, M);
     return hipGetLastError();
 }
 
