@@ -328,3 +328,40 @@ def test_paper_sphere_octant_shrinks(torch_cuda, paper_sphere):
     n0 = int(((x < 0) & (y < 0) & (z > 0)).sum())
     note("octant", n0, "->", n1, "->", n9, "flips", fl1.tolist(), fl.tolist())
     assert 0 < n9 < n1 and fl.min() > 0
+
+
+def _random_config(seed):
+    rng = np.random.default_rng(2000 + seed)
+    R = float(rng.uniform(0.6, 1.2))
+    p = int(rng.integers(1, 7))
+    tau = float(10 ** rng.uniform(-2.3, -1.8))
+    eps = float(10 ** rng.uniform(-9, -3))
+    n = int(rng.integers(1, 5))
+    dx = float(rng.uniform(0.12, 0.25)) * (1 + 0.4 * (p - 1))
+    return R, dx, p, tau, eps, n
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_configurations(torch_cuda, seed):
+    """Random radius, cell size, nodes per cell (1-6: every spreading variant),
+    tau, eps and n, both precisions, against the oracle's direct sums (all
+    outputs when the band is small, 64 sampled outputs otherwise)."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    R, dx, p, tau, eps, n = _random_config(seed)
+    for prec in (mbo.F64, mbo.F32):
+        s = surface(R, dx, p, tau, eps, n, prec)
+        b = band_of(s)
+        A = inputs.uniform_field(n, (s.m,), 940 + seed)
+        dt = torch.float64 if prec == mbo.F64 else torch.float32
+        Y = s.diffuse(dev(torch, A, dt)).double().cpu().numpy()
+        if s.m <= 20000:
+            ref, got = oracle.surface_diffuse(b, A, tau), Y
+        else:
+            idx = np.random.default_rng(seed).choice(s.m, 64, replace=False)
+            ref, got = oracle.heat_at(b, A, tau, b["xc"][:, idx]), Y[:, :, idx]
+        err = np.abs(got - ref).max() / np.abs(A).max()
+        note("random", seed, "R %.3f dx %.3f p %d tau %.4f eps %.1e n %d" % (R, dx, p, tau, eps, n),
+             "prec", prec, "m", s.m, "grid", s.grid, "err", err)
+        assert err <= _tol(prec, eps), err
+        s.close()
