@@ -213,7 +213,9 @@ typedef struct mbo_surface_s* mbo_surface_t;
  * whose projection falls back to double near singular points).  hip_stream
  * (hipStream_t, nullable) carries every later call.  MBO_ERR_UNSUPPORTED when
  * the grid would need more than 512 points per axis (tau too small for the
- * radius).  On error *out is NULL and mbo_surface_last_error(NULL) explains. */
+ * radius), when the lattice to scan has more than 1501 points per half axis
+ * ((R + w_b) / dx too large) or when the band holds 2^31 samples or more.  On
+ * error *out is NULL and mbo_surface_last_error(NULL) explains. */
 mbo_status mbo_surface_sphere(mbo_surface_t* out, double R, double dx, int p, double tau, double eps, int n,
                               mbo_precision prec, void* hip_stream);
 

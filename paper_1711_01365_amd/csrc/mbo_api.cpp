@@ -2268,7 +2268,11 @@ mbo_status mbo_surface_sphere(mbo_surface_t* out, double radius, double dx, int 
     s->wb = band_width_of(tau, eps);
     double nx[8], nw[8];
     chebyshev_rule(p, nx, nw);
-    const int64_t lim = (int64_t)std::ceil((radius + s->wb) / dx) + 1;
+    const double lim_d = std::ceil((radius + s->wb) / dx) + 1.0;
+    if (lim_d > 1500.0)  // about 2.7e10 lattice points to test
+        return bail(sfail(s, MBO_ERR_UNSUPPORTED, "dx = %g is too small for a band of outer radius %g", dx,
+                          radius + s->wb));
+    const int64_t lim = (int64_t)lim_d;
     std::vector<std::array<double, 3>> corners;
     for (int64_t i = -lim; i <= lim; ++i)
         for (int64_t j = -lim; j <= lim; ++j)
@@ -2280,6 +2284,8 @@ mbo_status mbo_surface_sphere(mbo_surface_t* out, double radius, double dx, int 
     const int64_t m = s->cells * p * p * p;
     s->m = m;
     if (m == 0) return bail(sfail(s, MBO_ERR_INVALID_ARG, "the band holds no grid point"));
+    if (m > ((int64_t)1 << 31) - 1)
+        return bail(sfail(s, MBO_ERR_UNSUPPORTED, "%lld samples: at most 2^31 - 1", (long long)m));
     s->xq.assign((size_t)(3 * m), 0.0);
     s->xc.assign((size_t)(3 * m), 0.0);
     s->wq.assign((size_t)m, 0.0);

@@ -166,3 +166,6 @@ def test_surface_calls_validate_before_touching_the_device(lib):
     # a grid finer than 512 points per axis is refused before any device work
     assert lib.mbo_surface_sphere(ctypes.byref(h), 10.0, 0.5, 1, 1e-3, 1e-6, 3, 0, None) == 2
     assert b"512" in lib.mbo_surface_last_error(None)
+    # a lattice too fine to scan is refused before any work
+    assert lib.mbo_surface_sphere(ctypes.byref(h), 1.0, 1e-4, 1, 0.01, 1e-6, 3, 0, None) == 2
+    assert b"too small" in lib.mbo_surface_last_error(None)
