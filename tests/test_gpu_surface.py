@@ -13,7 +13,9 @@ Bars:
     1e-9 (FP64) / 2e-4 (float) away from near-singular diffused matrices;
   * at the sphere experiment's size (3.3 M samples): sampled outputs against
     the oracle, constants kept, the degree-1 harmonic damped by 1 - 2 tau, and
-    the SO^-(3) octant shrinking.
+    the SO^-(3) octant shrinking;
+  * ten random configurations (radius, cell size, 1-6 nodes per cell, tau, eps,
+    n, both precisions) to the same bars, covering every spreading variant.
 """
 import sys
 
