@@ -129,13 +129,18 @@ def _load():
     lib.orc_weighted_select.argtypes = [ctypes.c_int64, _d, _i64, ctypes.c_int64, _i8]
     lib.orc_surface_iterate_volume.argtypes = [ctypes.c_int64, _d, _d, _d, _i64, ctypes.c_int, ctypes.c_double, _d,
                                                ctypes.c_int, _i64, _i64, _i64]
+    lib.orc_revolution_cp.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, _d]
+    lib.orc_revolution_cp.restype = ctypes.c_double
+    lib.orc_revolution_band.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                        _i64, _i64, _d, _d, _d]
     lib.orc_num_threads.argtypes = []
     for f in ("orc_dft_naive", "orc_fft", "orc_heat", "orc_project", "orc_det_sign",
               "orc_energy", "orc_iterate", "orc_num_threads", "orc_heat_dtau", "orc_project_vjp",
               "orc_unroll_grad", "orc_volume_select", "orc_volume_project",
               "orc_iterate_volume", "orc_relaxed_flow", "orc_relaxed_energy", "orc_sphere_band",
               "orc_surface_diffuse", "orc_surface_iterate", "orc_heat_at", "orc_weighted_select",
-              "orc_surface_iterate_volume"):
+              "orc_surface_iterate_volume", "orc_revolution_band"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -438,6 +443,41 @@ def sphere_band(R: float, dx: float, p: int, tau: float, eps: float):
     w = np.zeros(m)
     _check(lib.orc_sphere_band(float(R), float(dx), int(p), wb, _ptr(cnt, _i64), None, _ptr(xq), _ptr(xc),
                                _ptr(w)), "sphere_band")
+    return {"xq": xq, "xc": xc, "w": w, "cells": int(cells[0]), "wb": wb}
+
+
+REV_SPHERE, REV_PEANUT = 0, 1
+
+
+def revolution_cp(kind: int, pts: np.ndarray, R: float = 1.0):
+    """Closest points [3, k] and distances [k] of points pts [3, k] on a surface
+    of revolution (REV_SPHERE of radius R, or REV_PEANUT)."""
+    lib = _load()
+    pts = np.asarray(pts, dtype=np.float64)
+    out = np.zeros_like(pts)
+    dist = np.zeros(pts.shape[1])
+    c = np.zeros(3)
+    for q in range(pts.shape[1]):
+        dist[q] = lib.orc_revolution_cp(int(kind), float(R), float(pts[0, q]), float(pts[1, q]), float(pts[2, q]),
+                                        _ptr(c))
+        out[:, q] = c
+    return out, dist
+
+
+def revolution_band(kind: int, dx: float, p: int, tau: float, eps: float, R: float = 1.0):
+    """Sample set of a surface of revolution, as sphere_band."""
+    lib = _load()
+    wb = band_width(tau, eps)
+    cnt = np.zeros(1, dtype=np.int64)
+    cells = np.zeros(1, dtype=np.int64)
+    _check(lib.orc_revolution_band(int(kind), float(R), float(dx), int(p), wb, _ptr(cnt, _i64), _ptr(cells, _i64),
+                                   None, None, None), "revolution_band")
+    m = int(cnt[0])
+    xq = np.zeros((3, m))
+    xc = np.zeros((3, m))
+    w = np.zeros(m)
+    _check(lib.orc_revolution_band(int(kind), float(R), float(dx), int(p), wb, _ptr(cnt, _i64), None, _ptr(xq),
+                                   _ptr(xc), _ptr(w)), "revolution_band")
     return {"xq": xq, "xc": xc, "w": w, "cells": int(cells[0]), "wb": wb}
 
 

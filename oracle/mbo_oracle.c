@@ -1001,6 +1001,155 @@ int orc_sphere_band(double R, double dx, int p, double wb, int64_t* count, int64
     return 0;
 }
 
+/* Surfaces of revolution about the x axis (Section 6.3): a meridian
+ * (X(s), rho(s)), s in [s0, s1], rho >= 0, rotated about the x axis.
+ *   kind 0: the sphere of radius R, X = -R cos(pi s), rho = R sin(pi s), s in [0, 1];
+ *   kind 1: the peanut, X = 3 t - t^3, rho = (1/2) sqrt((1 + X^2)(4 - X^2)),
+ *           t in [-1, 1], with 4 - X^2 = (1 - t^2)^2 (4 - t^2) so that rho is
+ *           a smooth function of t. */
+static void orc_meridian(int kind, double R, double s, double* X, double* rho)
+{
+    if (kind == 0) {
+        *X = -R * cos(ORC_PI * s);
+        *rho = R * sin(ORC_PI * s);
+    } else {
+        const double x = 3.0 * s - s * s * s;
+        *X = x;
+        *rho = 0.5 * (1.0 - s * s) * sqrt((1.0 + x * x) * (4.0 - s * s));
+    }
+}
+
+/* First and second derivatives of the meridian in its parameter. */
+static void orc_meridian_d(int kind, double R, double s, double* X1, double* X2, double* r1, double* r2)
+{
+    if (kind == 0) {
+        *X1 = R * ORC_PI * sin(ORC_PI * s);
+        *X2 = R * ORC_PI * ORC_PI * cos(ORC_PI * s);
+        *r1 = R * ORC_PI * cos(ORC_PI * s);
+        *r2 = -R * ORC_PI * ORC_PI * sin(ORC_PI * s);
+    } else {
+        /* rho = a sqrt(h) / 2, a = 1 - t^2, h = u v, u = 1 + X^2, v = 4 - t^2 */
+        const double t = s, X = 3.0 * t - t * t * t, Xp = 3.0 - 3.0 * t * t, Xpp = -6.0 * t;
+        const double u = 1.0 + X * X, up = 2.0 * X * Xp, upp = 2.0 * (Xp * Xp + X * Xpp);
+        const double v = 4.0 - t * t, vp = -2.0 * t, vpp = -2.0;
+        const double h = u * v, hp = up * v + u * vp, hpp = upp * v + 2.0 * up * vp + u * vpp;
+        const double a = 1.0 - t * t, ap = -2.0 * t, app = -2.0;
+        const double sh = sqrt(h);
+        *X1 = Xp;
+        *X2 = Xpp;
+        *r1 = 0.5 * (ap * sh + a * hp / (2.0 * sh));
+        *r2 = 0.5 * (app * sh + ap * hp / sh + a * (hpp / (2.0 * sh) - hp * hp / (4.0 * h * sh)));
+    }
+}
+
+static void orc_meridian_range(int kind, double* s0, double* s1)
+{
+    *s0 = kind == 0 ? 0.0 : -1.0;
+    *s1 = 1.0;
+}
+
+/* Closest point on the surface of revolution to p = (x, y, z): the closest
+ * point (X(s), rho(s)) of the meridian to (x, r), r = |(y, z)|, rotated into the
+ * half plane of p ((y, z) = (r, 0) taken when r = 0, where it is not unique).
+ * The meridian is scanned at 8193 parameter values, and the best one refined
+ * by golden-section search between its neighbours.  Returns the distance. */
+double orc_revolution_cp(int kind, double R, double x, double y, double z, double* c)
+{
+    const double r = sqrt(y * y + z * z);
+    double s0, s1;
+    orc_meridian_range(kind, &s0, &s1);
+    const int N = 8192;
+    int best = 0;
+    double bd = INFINITY;
+    for (int k = 0; k <= N; ++k) {
+        double X, rho;
+        orc_meridian(kind, R, s0 + (s1 - s0) * k / N, &X, &rho);
+        const double d = (X - x) * (X - x) + (rho - r) * (rho - r);
+        if (d < bd) {
+            bd = d;
+            best = k;
+        }
+    }
+    double a = s0 + (s1 - s0) * (best > 0 ? best - 1 : 0) / N;
+    double b = s0 + (s1 - s0) * (best < N ? best + 1 : N) / N;
+    const double g = 0.5 * (sqrt(5.0) - 1.0);
+    for (int it = 0; it < 200 && b - a > 1e-16; ++it) {
+        const double u = b - g * (b - a), v = a + g * (b - a);
+        double Xu, ru, Xv, rv;
+        orc_meridian(kind, R, u, &Xu, &ru);
+        orc_meridian(kind, R, v, &Xv, &rv);
+        const double du = (Xu - x) * (Xu - x) + (ru - r) * (ru - r);
+        const double dv = (Xv - x) * (Xv - x) + (rv - r) * (rv - r);
+        if (du <= dv) b = v;
+        else a = u;
+    }
+    /* Newton on the derivative of the squared distance polishes the golden-
+     * section bracket (whose width is limited by the flat minimum to about the
+     * square root of the rounding) to full precision */
+    double t = 0.5 * (a + b);
+    for (int it = 0; it < 4; ++it) {
+        double X, rho, X1, X2, r1, r2;
+        orc_meridian(kind, R, t, &X, &rho);
+        orc_meridian_d(kind, R, t, &X1, &X2, &r1, &r2);
+        const double g = (X - x) * X1 + (rho - r) * r1;
+        const double H = X1 * X1 + (X - x) * X2 + r1 * r1 + (rho - r) * r2;
+        if (!(H > 0.0)) break;
+        const double tn = t - g / H;
+        if (!(tn >= a - 1e-6 && tn <= b + 1e-6) || tn < s0 || tn > s1) break;
+        t = tn;
+    }
+    double X, rho;
+    orc_meridian(kind, R, t, &X, &rho);
+    c[0] = X;
+    c[1] = r > 0.0 ? rho * y / r : rho;
+    c[2] = r > 0.0 ? rho * z / r : 0.0;
+    return sqrt((c[0] - x) * (c[0] - x) + (c[1] - y) * (c[1] - y) + (c[2] - z) * (c[2] - z));
+}
+
+/* The closest-point sample set of a surface of revolution (as orc_sphere_band,
+ * with the distance and closest points of orc_revolution_cp): grid points
+ * x_g = dx (i, j, k) within w_b of the surface over the box that holds the
+ * surface grown by w_b, lexicographic; p^3 Chebyshev points per cell. */
+int orc_revolution_band(int kind, double R, double dx, int p, double wb, int64_t* count, int64_t* cells,
+                        double* xq, double* xc, double* wq)
+{
+    if (kind < 0 || kind > 1 || !(R > 0.0) || !(dx > 0.0) || p < 1 || p > 8 || !(wb > 0.0)) return -1;
+    double nx[8], nw[8];
+    orc_cheb_rule(p, nx, nw);
+    const double xext = kind == 0 ? R : 2.0, rext = kind == 0 ? R : 1.25;
+    const int64_t lx = (int64_t)ceil((xext + wb) / dx) + 1, lr = (int64_t)ceil((rext + wb) / dx) + 1;
+    int64_t c = 0, q = 0;
+    for (int64_t i = -lx; i <= lx; ++i)
+        for (int64_t j = -lr; j <= lr; ++j)
+            for (int64_t k = -lr; k <= lr; ++k) {
+                const double gx = dx * (double)i, gy = dx * (double)j, gz = dx * (double)k;
+                double cc[3];
+                if (!(orc_revolution_cp(kind, R, gx, gy, gz, cc) < wb)) continue;
+                ++c;
+                for (int a = 0; a < p; ++a)
+                    for (int b = 0; b < p; ++b)
+                        for (int e = 0; e < p; ++e) {
+                            if (xq) {
+                                const double x = gx + dx * nx[a], y = gy + dx * nx[b], z = gz + dx * nx[e];
+                                xq[q] = x;
+                                xq[*count + q] = y;
+                                xq[2 * *count + q] = z;
+                                orc_revolution_cp(kind, R, x, y, z, cc);
+                                xc[q] = cc[0];
+                                xc[*count + q] = cc[1];
+                                xc[2 * *count + q] = cc[2];
+                                wq[q] = dx * dx * dx * nw[a] * nw[b] * nw[e];
+                            }
+                            ++q;
+                        }
+            }
+    if (!xq) {
+        *count = q;
+        if (cells) *cells = c;
+    }
+    return 0;
+}
+
 /* One step of surface diffusion by the closest point method (eqs.
  * surface_diffusion_extended, freeSpace): the field A (entry-planar [n*n][m],
  * its value at sample q being A(x_q^c), i.e. already the constant extension
