@@ -219,6 +219,15 @@ typedef struct mbo_surface_s* mbo_surface_t;
 mbo_status mbo_surface_sphere(mbo_surface_t* out, double R, double dx, int p, double tau, double eps, int n,
                               mbo_precision prec, void* hip_stream);
 
+/* The same for the peanut of Section 6.3: the meridian X(t) = 3t - t^3,
+ * rho(t) = sqrt((1 + X^2)(4 - X^2)) / 2, t in [-1, 1], rotated about the x axis
+ * (tips at x = +-2, waist radius 1, largest radius 1.25).  Closest points are
+ * the closest points of the meridian to (x, |(y, z)|) turned into the half plane
+ * of the point ((y, z) = (rho, 0) on the axis, where they are not unique);
+ * the band, cells, weights, diffusion and steps are as for the sphere. */
+mbo_status mbo_surface_peanut(mbo_surface_t* out, double dx, int p, double tau, double eps, int n,
+                              mbo_precision prec, void* hip_stream);
+
 /* Free the surface (synchronises its stream).  NULL is a no-op. */
 mbo_status mbo_surface_destroy(mbo_surface_t s);
 

@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "mbo.h"
@@ -1210,6 +1211,122 @@ void chebyshev_rule(int p, double* x, double* w)
 }
 
 // Gauss-Legendre rule on [-1, 1] by Newton's method on P_q.
+// The peanut of Section 6.3: the meridian X(t) = 3t - t^3,
+// rho(t) = sqrt((1 + X^2)(4 - X^2)) / 2 = (1 - t^2) sqrt((1 + X^2)(4 - t^2)) / 2,
+// t in [-1, 1] (the second form is smooth at the tips), rotated about the x
+// axis.  The closest point of p = (x, y, z) is the closest point (X(t), rho(t))
+// of the meridian to (x, |(y, z)|), turned into the half plane of p.
+void peanut_eval(double t, double& X, double& r)
+{
+    X = 3.0 * t - t * t * t;
+    r = 0.5 * (1.0 - t * t) * std::sqrt((1.0 + X * X) * (4.0 - t * t));
+}
+
+// d/dt and d^2/dt^2 of X and rho
+void peanut_deriv(double t, double& X1, double& X2, double& r1, double& r2)
+{
+    const double X = 3.0 * t - t * t * t, Xp = 3.0 - 3.0 * t * t, Xpp = -6.0 * t;
+    const double u = 1.0 + X * X, up = 2.0 * X * Xp, upp = 2.0 * (Xp * Xp + X * Xpp);
+    const double v = 4.0 - t * t, vp = -2.0 * t;
+    const double h = u * v, hp = up * v + u * vp, hpp = upp * v + 2.0 * up * vp - 2.0 * u;
+    const double a = 1.0 - t * t, ap = -2.0 * t;
+    const double sh = std::sqrt(h);
+    X1 = Xp;
+    X2 = Xpp;
+    r1 = 0.5 * (ap * sh + a * hp / (2.0 * sh));
+    r2 = 0.5 * (-2.0 * sh + ap * hp / sh + a * (hpp / (2.0 * sh) - hp * hp / (4.0 * h * sh)));
+}
+
+double peanut_d2(double t, double x, double rr)
+{
+    double X, r;
+    peanut_eval(t, X, r);
+    return (X - x) * (X - x) + (r - rr) * (r - rr);
+}
+
+// Minimise the squared meridian distance over [a, b]: golden section, then
+// Newton on its derivative (the flat minimum limits the golden bracket to about
+// the square root of the rounding).  Returns the minimiser.
+double peanut_refine(double x, double rr, double a, double b)
+{
+    const double g = 0.5 * (std::sqrt(5.0) - 1.0);
+    for (int it = 0; it < 120 && b - a > 1e-15; ++it) {
+        const double u = b - g * (b - a), v = a + g * (b - a);
+        if (peanut_d2(u, x, rr) <= peanut_d2(v, x, rr)) b = v;
+        else a = u;
+    }
+    double t = 0.5 * (a + b);
+    for (int it = 0; it < 4; ++it) {
+        double X, r, X1, X2, r1, r2;
+        peanut_eval(t, X, r);
+        peanut_deriv(t, X1, X2, r1, r2);
+        const double gr = (X - x) * X1 + (r - rr) * r1;
+        const double H = X1 * X1 + (X - x) * X2 + r1 * r1 + (r - rr) * r2;
+        if (!(H > 0.0)) break;
+        const double tn = t - gr / H;
+        if (!(tn >= a - 1e-6 && tn <= b + 1e-6) || tn < -1.0 || tn > 1.0) break;
+        t = tn;
+    }
+    return t;
+}
+
+// Closest point of (x, y, z) on the peanut: the meridian distance scanned at
+// 257 parameters, its two best local minima refined, the better one turned into
+// the half plane of the point.  Returns the distance.
+double peanut_cp(double x, double y, double z, double c[3])
+{
+    const int N = 256;
+    const double rr = std::sqrt(y * y + z * z);
+    double d[N + 1];
+    for (int k = 0; k <= N; ++k) d[k] = peanut_d2(-1.0 + 2.0 * k / N, x, rr);
+    int b1 = -1, b2 = -1;
+    for (int k = 0; k <= N; ++k) {
+        const bool lmin = (k == 0 || d[k] <= d[k - 1]) && (k == N || d[k] <= d[k + 1]);
+        if (!lmin) continue;
+        if (b1 < 0 || d[k] < d[b1]) {
+            b2 = b1;
+            b1 = k;
+        } else if (b2 < 0 || d[k] < d[b2]) {
+            b2 = k;
+        }
+    }
+    double best = 0.0, bd = INFINITY;
+    for (int i = 0; i < 2; ++i) {
+        const int k = i == 0 ? b1 : b2;
+        if (k < 0) continue;
+        const double t = peanut_refine(x, rr, -1.0 + 2.0 * std::max(k - 1, 0) / N, -1.0 + 2.0 * std::min(k + 1, N) / N);
+        const double dd = peanut_d2(t, x, rr);
+        if (dd < bd) {
+            bd = dd;
+            best = t;
+        }
+    }
+    double X, r;
+    peanut_eval(best, X, r);
+    c[0] = X;
+    c[1] = rr > 0.0 ? r * y / rr : r;
+    c[2] = rr > 0.0 ? r * z / rr : 0.0;
+    return std::sqrt((c[0] - x) * (c[0] - x) + (c[1] - y) * (c[1] - y) + (c[2] - z) * (c[2] - z));
+}
+
+// Run f(i) for i in [0, count) on the host's cores (at most 16 threads).
+template <typename F>
+void parallel_for(int64_t count, F f)
+{
+    unsigned nt = std::thread::hardware_concurrency();
+    nt = nt == 0 ? 1 : (nt > 16 ? 16 : nt);
+    if (count < 64 || nt == 1) {
+        for (int64_t i = 0; i < count; ++i) f(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (unsigned w = 0; w < nt; ++w)
+        th.emplace_back([&, w]() {
+            for (int64_t i = w; i < count; i += nt) f(i);
+        });
+    for (auto& t : th) t.join();
+}
+
 void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w)
 {
     const double pi = 3.14159265358979323846;
@@ -2235,8 +2352,16 @@ mbo_status mbo_iterate_volume(mbo_plan_t p, void* A, int max_iter, const int64_t
     return MBO_OK;
 }
 
-mbo_status mbo_surface_sphere(mbo_surface_t* out, double radius, double dx, int p, double tau, double eps, int n,
-                              mbo_precision prec, void* hip_stream)
+}  // extern "C"
+
+namespace {
+
+enum SurfaceKind { SURF_SPHERE = 0, SURF_PEANUT = 1 };
+
+// The surface object of either kind: sample set on the host, then the grid
+// plan, symbol tables, bins and buffers.
+mbo_status surface_create(mbo_surface_t* out, int kind, double radius, double dx, int p, double tau, double eps,
+                          int n, mbo_precision prec, void* hip_stream)
 {
     g_plan_error.clear();
     if (!out) return sfail(nullptr, MBO_ERR_INVALID_ARG, "out is NULL");
@@ -2268,18 +2393,41 @@ mbo_status mbo_surface_sphere(mbo_surface_t* out, double radius, double dx, int 
     s->wb = band_width_of(tau, eps);
     double nx[8], nw[8];
     chebyshev_rule(p, nx, nw);
-    const double lim_d = std::ceil((radius + s->wb) / dx) + 1.0;
-    if (lim_d > 1500.0)  // about 2.7e10 lattice points to test
-        return bail(sfail(s, MBO_ERR_UNSUPPORTED, "dx = %g is too small for a band of outer radius %g", dx,
-                          radius + s->wb));
-    const int64_t lim = (int64_t)lim_d;
+    // half extents of the surface per axis (the sphere: R; the peanut: tips at
+    // x = +-2, largest radius 1.25)
+    const double ext[3] = {kind == SURF_SPHERE ? radius : 2.0, kind == SURF_SPHERE ? radius : 1.25,
+                           kind == SURF_SPHERE ? radius : 1.25};
+    const double lim_x = std::ceil((ext[0] + s->wb) / dx) + 1.0, lim_r = std::ceil((ext[1] + s->wb) / dx) + 1.0;
+    if (lim_x > 1500.0 || lim_r > 1500.0)  // about 2.7e10 lattice points to test
+        return bail(sfail(s, MBO_ERR_UNSUPPORTED, "dx = %g is too small for a band of outer extent %g", dx,
+                          ext[0] + s->wb));
+    const int64_t lx = (int64_t)lim_x, lr = (int64_t)lim_r;
     std::vector<std::array<double, 3>> corners;
-    for (int64_t i = -lim; i <= lim; ++i)
-        for (int64_t j = -lim; j <= lim; ++j)
-            for (int64_t k = -lim; k <= lim; ++k) {
-                const double gx = dx * (double)i, gy = dx * (double)j, gz = dx * (double)k;
-                if (std::fabs(std::sqrt(gx * gx + gy * gy + gz * gz) - radius) < s->wb) corners.push_back({gx, gy, gz});
-            }
+    if (kind == SURF_SPHERE) {
+        for (int64_t i = -lx; i <= lx; ++i)
+            for (int64_t j = -lr; j <= lr; ++j)
+                for (int64_t k = -lr; k <= lr; ++k) {
+                    const double gx = dx * (double)i, gy = dx * (double)j, gz = dx * (double)k;
+                    if (std::fabs(std::sqrt(gx * gx + gy * gy + gz * gz) - radius) < s->wb)
+                        corners.push_back({gx, gy, gz});
+                }
+    } else {
+        // one slab of constant i per task, lexicographic order kept by slab
+        const int64_t ni = 2 * lx + 1;
+        std::vector<std::vector<std::array<double, 3>>> slab_c((size_t)ni);
+        const double wb = s->wb;
+        parallel_for(ni, [&](int64_t ii) {
+            const int64_t i = ii - lx;
+            for (int64_t j = -lr; j <= lr; ++j)
+                for (int64_t k = -lr; k <= lr; ++k) {
+                    const double gx = dx * (double)i, gy = dx * (double)j, gz = dx * (double)k;
+                    double c[3];
+                    if (peanut_cp(gx, gy, gz, c) < wb) slab_c[(size_t)ii].push_back({gx, gy, gz});
+                }
+        });
+        for (int64_t ii = 0; ii < ni; ++ii)
+            corners.insert(corners.end(), slab_c[(size_t)ii].begin(), slab_c[(size_t)ii].end());
+    }
     s->cells = (int64_t)corners.size();
     const int64_t m = s->cells * p * p * p;
     s->m = m;
@@ -2289,21 +2437,32 @@ mbo_status mbo_surface_sphere(mbo_surface_t* out, double radius, double dx, int 
     s->xq.assign((size_t)(3 * m), 0.0);
     s->xc.assign((size_t)(3 * m), 0.0);
     s->wq.assign((size_t)m, 0.0);
-    int64_t q = 0;
-    for (const auto& c : corners)
+    const int p3 = p * p * p;
+    parallel_for(s->cells, [&](int64_t ci) {
+        const auto& c = corners[(size_t)ci];
+        int64_t q = ci * p3;
         for (int a = 0; a < p; ++a)
             for (int b = 0; b < p; ++b)
                 for (int e = 0; e < p; ++e, ++q) {
                     const double x = c[0] + dx * nx[a], y = c[1] + dx * nx[b], z = c[2] + dx * nx[e];
-                    const double r = std::sqrt(x * x + y * y + z * z);
+                    double cp[3];
+                    if (kind == SURF_SPHERE) {
+                        const double r = std::sqrt(x * x + y * y + z * z);
+                        cp[0] = r > 0.0 ? radius * x / r : radius;
+                        cp[1] = r > 0.0 ? radius * y / r : 0.0;
+                        cp[2] = r > 0.0 ? radius * z / r : 0.0;
+                    } else {
+                        peanut_cp(x, y, z, cp);
+                    }
                     s->xq[(size_t)q] = x;
                     s->xq[(size_t)(m + q)] = y;
                     s->xq[(size_t)(2 * m + q)] = z;
-                    s->xc[(size_t)q] = r > 0.0 ? radius * x / r : radius;
-                    s->xc[(size_t)(m + q)] = r > 0.0 ? radius * y / r : 0.0;
-                    s->xc[(size_t)(2 * m + q)] = r > 0.0 ? radius * z / r : 0.0;
+                    s->xc[(size_t)q] = cp[0];
+                    s->xc[(size_t)(m + q)] = cp[1];
+                    s->xc[(size_t)(2 * m + q)] = cp[2];
                     s->wq[(size_t)q] = dx * dx * dx * nw[a] * nw[b] * nw[e];
                 }
+    });
     // integer volume weights (Algorithm 3): the quadrature weight in units of
     // 2^-30 dx^3, so that sums of them are exact
     s->Wh.resize((size_t)m);
@@ -2326,8 +2485,14 @@ mbo_status mbo_surface_sphere(mbo_surface_t* out, double radius, double dx, int 
     s->beta = 2.30 * s->w;
     const double L = std::log(1.0 / eg);
     const double hmax = pi / (2.0 * std::sqrt(L / tau));
-    const double reach = radius + s->wb + dx * std::sqrt(3.0);  // max |x_q|
-    const double need = std::max(radius + reach + band_width_of(tau, eg), 2.0 * reach + 4.0 * hmax);
+    // per axis: sources reach ext + w_b + sqrt(3) dx, targets ext
+    double span = 0.0, reach = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double ra = ext[a] + s->wb + dx * std::sqrt(3.0);
+        span = std::max(span, ext[a] + ra);
+        reach = std::max(reach, ra);
+    }
+    const double need = std::max(span + band_width_of(tau, eg), 2.0 * reach + 4.0 * hmax);
     int Ng = 64;  // at least the spreading tiles plus a bin
     while (Ng * hmax < need) Ng *= 2;
     if (Ng > 512)
@@ -2428,6 +2593,22 @@ mbo_status mbo_surface_sphere(mbo_surface_t* out, double radius, double dx, int 
         return bail(sfail(s, MBO_ERR_ALLOC, "device allocation failed"));
     *out = s;
     return MBO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mbo_status mbo_surface_sphere(mbo_surface_t* out, double radius, double dx, int p, double tau, double eps, int n,
+                              mbo_precision prec, void* hip_stream)
+{
+    return surface_create(out, SURF_SPHERE, radius, dx, p, tau, eps, n, prec, hip_stream);
+}
+
+mbo_status mbo_surface_peanut(mbo_surface_t* out, double dx, int p, double tau, double eps, int n,
+                              mbo_precision prec, void* hip_stream)
+{
+    return surface_create(out, SURF_PEANUT, 1.0, dx, p, tau, eps, n, prec, hip_stream);
 }
 
 mbo_status mbo_surface_destroy(mbo_surface_t s)

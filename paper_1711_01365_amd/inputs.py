@@ -220,3 +220,17 @@ def sphere_octant_field(xc: np.ndarray) -> np.ndarray:
     x, y, z = xc
     inside = (x < 0) & (y < 0) & (z > 0)
     return np.where(inside[None, None, :], SPHERE_MATRICES[0][:, :, None], SPHERE_MATRICES[1][:, :, None])
+
+
+# The peanut experiment (Section 6.3): dx = 0.04, p = 4, tau = 0.032,
+# eps = 1e-6, n = 3; the first printed matrix where x > sqrt((y^2 + z^2)(y^2 + 0.1) / 1.5),
+# the second elsewhere (the sphere's matrices, raw).
+PEANUT_PAPER = SphereWorkload("peanut_dx0.04_p4_tau0.032", 1.0, 0.04, 4, 0.032, 1e-6, 3, 10)
+
+
+def peanut_field(xc: np.ndarray) -> np.ndarray:
+    """(3, 3, m) field over samples with closest points xc [3, m]: the paper's
+    peanut initial condition."""
+    x, y, z = xc
+    first = x > np.sqrt((y * y + z * z) * (y * y + 0.1) / 1.5)
+    return np.where(first[None, None, :], SPHERE_MATRICES[0][:, :, None], SPHERE_MATRICES[1][:, :, None])

@@ -31,7 +31,8 @@ EXPORTS = ("mbo_plan", "mbo_plan_destroy", "mbo_plan_set_tau", "mbo_plan_set_str
            "mbo_energy", "mbo_project_vjp", "mbo_diffuse_dtau", "mbo_plan_batched", "mbo_plan_tuning",
            "mbo_plan_autotune", "mbo_step", "mbo_step_vjp", "mbo_volume_select",
            "mbo_project_volume", "mbo_iterate_volume", "mbo_so2_index", "mbo_relaxed_flow",
-           "mbo_relaxed_energy", "mbo_surface_sphere", "mbo_surface_destroy", "mbo_surface_info",
+           "mbo_relaxed_energy", "mbo_surface_sphere", "mbo_surface_peanut", "mbo_surface_destroy",
+           "mbo_surface_info",
            "mbo_surface_points", "mbo_surface_diffuse", "mbo_surface_iterate", "mbo_surface_last_error",
            "mbo_surface_volume_weights", "mbo_surface_volume_select", "mbo_surface_iterate_volume",
            "mbo_status_string", "mbo_last_error")
@@ -86,6 +87,8 @@ def load(path: str = LIB_PATH):
     lib.mbo_relaxed_energy.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, dp]
     lib.mbo_surface_sphere.argtypes = [ctypes.POINTER(vp), ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, vp]
+    lib.mbo_surface_peanut.argtypes = [ctypes.POINTER(vp), ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int, ctypes.c_int, vp]
     lib.mbo_surface_destroy.argtypes = [vp]
     lib.mbo_surface_info.argtypes = [vp, i64p, i64p, ip, dp]
     lib.mbo_surface_points.argtypes = [vp, dp, dp, dp]
@@ -399,8 +402,8 @@ class SphereSurface:
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: libmbo runs on the GPU only")
         h = ctypes.c_void_p()
-        rc = lib.mbo_surface_sphere(ctypes.byref(h), float(R), float(dx), int(p), float(tau), float(eps),
-                                    int(n), int(precision), _stream_ptr(stream))
+        rc = self._create(lib, h, float(R), float(dx), int(p), float(tau), float(eps), int(n), int(precision),
+                          _stream_ptr(stream))
         if rc != 0:
             msg = lib.mbo_surface_last_error(None)
             raise MboError(rc, msg.decode() if msg else "")
@@ -412,6 +415,10 @@ class SphereSurface:
         self._check(lib.mbo_surface_info(h, ctypes.byref(m), ctypes.byref(cells), ctypes.byref(g),
                                          ctypes.byref(wb)))
         self.m, self.cells, self.grid, self.band_width = m.value, cells.value, g.value, wb.value
+
+    @staticmethod
+    def _create(lib, h, R, dx, p, tau, eps, n, precision, stream):
+        return lib.mbo_surface_sphere(ctypes.byref(h), R, dx, p, tau, eps, n, precision, stream)
 
     def _check(self, rc):
         if rc != 0:
@@ -503,6 +510,18 @@ class SphereSurface:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class PeanutSurface(SphereSurface):
+    """Owns an ``mbo_surface_t`` of the peanut (mbo_surface_peanut); the same
+    calls as SphereSurface."""
+
+    def __init__(self, dx: float, p: int, tau: float, eps: float, n: int, precision: int = F64, stream=None):
+        super().__init__(1.0, dx, p, tau, eps, n, precision, stream)
+
+    @staticmethod
+    def _create(lib, h, R, dx, p, tau, eps, n, precision, stream):
+        return lib.mbo_surface_peanut(ctypes.byref(h), dx, p, tau, eps, n, precision, stream)
 
 
 def status_string(code: int) -> str:

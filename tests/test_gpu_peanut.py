@@ -1,0 +1,97 @@
+"""GPU parity of closest-point diffusion and MBO on the peanut (Section 6.3)
+through the C ABI, against the FP64 oracle.
+
+Bars:
+  * the sample set: the same cells, samples and weights as the oracle's band
+    (rounding), closest points at the same distance (1e-12) and equal (1e-9)
+    except where the meridian has two equally close points;
+  * the diffusion step over the library's own sample set: the oracle's direct
+    sums to max(eps, 1e-11) (FP64) / max(eps, 4e-6) (FP32) relative to max |A|;
+  * a larger band (dx = 0.08, p = 2, the paper's tau and eps): sampled outputs,
+    constants kept, and the paper's initial field moving under the iteration.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_01365_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*a):
+    print("[gpu-peanut]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1711_01365_amd import mbo
+    mbo.load()
+    return torch
+
+
+def band_of(s):
+    xq, xc, w = s.points()
+    return {"xq": xq, "xc": xc, "w": w, "cells": s.cells, "wb": s.band_width}
+
+
+@pytest.mark.parametrize("dx,p", [(0.3, 1), (0.25, 2)])
+def test_sample_set_matches_oracle(torch_cuda, dx, p):
+    from paper_1711_01365_amd import mbo
+    tau, eps = 0.01, 1e-6
+    s = mbo.PeanutSurface(dx, p, tau, eps, 3, precision=mbo.F64)
+    ref = oracle.revolution_band(oracle.REV_PEANUT, dx, p, tau, eps)
+    xq, xc, w = s.points()
+    assert s.cells == ref["cells"] and s.m == ref["w"].size
+    assert np.abs(xq - ref["xq"]).max() < 1e-14 and np.abs(w - ref["w"]).max() < 1e-16
+    d_got = np.linalg.norm(xc - xq, axis=0)
+    d_ref = np.linalg.norm(ref["xc"] - ref["xq"], axis=0)
+    assert np.abs(d_got - d_ref).max() < 1e-12
+    diff = np.abs(xc - ref["xc"]).max(axis=0)
+    ties = int((diff > 1e-9).sum())
+    note("dx", dx, "p", p, "m", s.m, "cp err", float(np.sort(diff)[-ties - 1] if ties < s.m else 0), "ties", ties)
+    assert ties <= max(2, s.m // 1000)
+    s.close()
+
+
+@pytest.mark.parametrize("prec_name", ["F64", "F32"])
+def test_diffuse_matches_oracle(torch_cuda, prec_name):
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    prec = getattr(mbo, prec_name)
+    tau, eps = 0.01, 1e-6
+    s = mbo.PeanutSurface(0.25, 2, tau, eps, 2, precision=prec)
+    b = band_of(s)
+    A = inputs.uniform_field(2, (s.m,), 950)
+    ref = oracle.surface_diffuse(b, A, tau)
+    dt = torch.float64 if prec == mbo.F64 else torch.float32
+    Y = s.diffuse(torch.tensor(A, dtype=dt, device="cuda")).double().cpu().numpy()
+    err = np.abs(Y - ref).max() / np.abs(A).max()
+    note("diffuse", prec_name, "m", s.m, "grid", s.grid, "err", err)
+    assert err <= (max(eps, 1e-11) if prec == mbo.F64 else max(eps, 4e-6))
+    s.close()
+
+
+def test_larger_band(torch_cuda):
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    w = inputs.PEANUT_PAPER
+    s = mbo.PeanutSurface(0.08, 2, w.tau, w.eps, 3, precision=mbo.F32_F64FALLBACK)
+    b = band_of(s)
+    A = inputs.peanut_field(b["xc"])
+    X = torch.tensor(A, dtype=torch.float32, device="cuda")
+    Y = s.diffuse(X).double().cpu().numpy()
+    idx = np.random.default_rng(9).choice(s.m, 48, replace=False)
+    ref = oracle.heat_at(b, A, w.tau, b["xc"][:, idx])
+    err = np.abs(Y[:, :, idx] - ref).max() / np.abs(A).max()
+    ones = s.diffuse(torch.ones((3, 3, s.m), dtype=torch.float32, device="cuda"))
+    e1 = (ones - 1).abs().max().item()
+    fl = s.iterate(X, 3, flips=True)
+    note("larger band m", s.m, "grid", s.grid, "sampled err", err, "|S1 - 1|", e1, "flips", fl.tolist())
+    assert err <= 4e-6 and e1 <= 1e-5 and fl[1:].min() > 0
+    s.close()
