@@ -381,6 +381,38 @@ def run_surface_volume(steps):
     return out
 
 
+def run_peanut(steps):
+    """The peanut experiment of Section 6.3 (dx = 0.04, p = 4, tau = 0.032,
+    eps = 1e-6, n = 3, FP32 + fallback, 10 MBO steps from the printed matrices):
+    sample-steps/s, the host time of the sample set, and the flips per step."""
+    import torch
+    from paper_1711_01365_amd import inputs, mbo
+    w = inputs.PEANUT_PAPER
+    t0 = time.perf_counter()
+    s = mbo.PeanutSurface(w.dx, w.p, w.tau, w.eps, w.n, precision=mbo.F32_F64FALLBACK)
+    setup = time.perf_counter() - t0
+    xq, xc, wts = s.points()
+    del xq, wts
+    A0 = torch.tensor(inputs.peanut_field(xc), dtype=torch.float32, device="cuda")
+    A = A0.clone()
+    s.iterate(A, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        A.copy_(A0)
+        s.iterate(A, w.iters)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    A.copy_(A0)
+    fl = s.iterate(A, 3, flips=True)
+    out = {"workload": "%s_n3_%dit_f32_f64fallback" % (w.name, w.iters),
+           "value": s.m * w.iters * steps / sec, "unit": "sample-steps/s", "samples": s.m, "band_cells": s.cells,
+           "grid": s.grid, "us_per_step": 1e6 * sec / (steps * w.iters), "setup_s": setup,
+           "flips_first_steps": [int(f) for f in fl]}
+    s.close()
+    return out
+
+
 def run_adjoint(precision, reps):
     """Gradients of K = 50 unrolled steps (n = 3, 256^2, checkpoint every 10):
     forward and backward wall time of the autograd function."""
@@ -481,6 +513,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--volume-only", action="store_true",
                     help="only the volume-preserving legs (for profiling them)")
+    ap.add_argument("--peanut", action="store_true",
+                    help="also run the peanut of Section 6.3 (133 M samples; about a minute of host set-up)")
     ap.add_argument("--surface-only", action="store_true",
                     help="only the sphere legs, float surfaces (for profiling them)")
     args = ap.parse_args()
@@ -514,6 +548,11 @@ def main():
         r = run_surface_volume(args.steps)
         log("volume-preserving sphere %s: %.3e sample-steps/s, %.1f us/step, m=%d, volume %d -> %d"
             % (r["workload"], r["value"], r["us_per_step"], r["samples"], r["volume_target"], r["volume_end"]))
+        if args.peanut:
+            r = run_peanut(args.steps)
+            log("peanut %s: %.3e sample-steps/s, %.1f us/step, m=%d, grid=%d^3, set-up %.1f s, flips %s"
+                % (r["workload"], r["value"], r["us_per_step"], r["samples"], r["grid"], r["setup_s"],
+                   r["flips_first_steps"]))
         return
     w = inputs.HAAR_512
     log("workload %s: n=%d grid=%s tau=%g iterations=%d" % (w.name, w.n, w.grid, w.tau, w.iters))
@@ -594,6 +633,11 @@ def main():
         r = out["sphere_volume_preserving"]
         log("volume-preserving sphere: %.3e sample-steps/s, %.1f us/step, m=%d, volume %d -> %d"
             % (r["value"], r["us_per_step"], r["samples"], r["volume_target"], r["volume_end"]))
+        if args.peanut:
+            out["peanut"] = run_peanut(1)
+            r = out["peanut"]
+            log("peanut: %.3e sample-steps/s, %.1f us/step, m=%d, set-up %.1f s"
+                % (r["value"], r["us_per_step"], r["samples"], r["setup_s"]))
         out["adjoint"] = {"f32_f64fallback": run_adjoint(mbo.F32_F64FALLBACK, 2),
                           "f64": run_adjoint(mbo.F64, 2)}
         log("adjoint K=50 256^2: fp32+fb fwd %.1f ms bwd %.1f ms, fp64 fwd %.1f ms bwd %.1f ms"
