@@ -95,3 +95,35 @@ def test_larger_band(torch_cuda):
     note("larger band m", s.m, "grid", s.grid, "sampled err", err, "|S1 - 1|", e1, "flips", fl.tolist())
     assert err <= 4e-6 and e1 <= 1e-5 and fl[1:].min() > 0
     s.close()
+
+
+def test_volume_step_on_the_peanut(torch_cuda):
+    """Algorithm 3 on the peanut: one step against the oracle's selection on the
+    library's own sample set (same component for every sample away from the
+    cut), and the volume kept within one sample over several steps."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    tau, eps = 0.01, 1e-9
+    s = mbo.PeanutSurface(0.25, 2, tau, eps, 3, precision=mbo.F64)
+    b = band_of(s)
+    W = s.volume_weights()
+    A0 = oracle.project(inputs.peanut_field(b["xc"]))[0]
+    ref, _, v_ref = oracle.surface_iterate_volume(b, W, A0, tau, 1)
+    X = torch.tensor(A0, device="cuda")
+    v_got, _ = s.iterate_volume(X, 1)
+    assert v_got == v_ref
+    D = oracle.surface_diffuse(b, A0, tau)
+    _, dE, _ = oracle.volume_project(D, 0)
+    sel = oracle.weighted_select(dE, W, v_ref).astype(bool)
+    order = np.lexsort((np.arange(s.m), -dE))
+    k = int(sel.sum())
+    clear = np.abs(dE - dE[order[k - 1]]) > 1e-5
+    det = np.linalg.det(np.moveaxis(X.cpu().numpy(), 2, 0))
+    det_ref = np.linalg.det(np.moveaxis(ref, 2, 0))
+    assert np.array_equal(np.sign(det[clear]), np.sign(det_ref[clear]))
+    for _ in range(3):
+        vu, fl = s.iterate_volume(X, 1, v_ref, flips=True)
+        vol = int(W[np.linalg.det(np.moveaxis(X.cpu().numpy(), 2, 0)) > 0].sum())
+        note("volume step m", s.m, "V", v_ref, "volume", vol, "flips", fl.tolist())
+        assert v_ref <= vol < v_ref + W.max()
+    s.close()
