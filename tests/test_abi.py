@@ -169,3 +169,14 @@ def test_surface_calls_validate_before_touching_the_device(lib):
     # a lattice too fine to scan is refused before any work
     assert lib.mbo_surface_sphere(ctypes.byref(h), 1.0, 1e-4, 1, 0.01, 1e-6, 3, 0, None) == 2
     assert b"too small" in lib.mbo_surface_last_error(None)
+
+
+def test_peanut_surface_validates_before_touching_the_device(lib):
+    h = ctypes.c_void_p()
+    assert lib.mbo_surface_peanut(None, 0.1, 1, 0.01, 1e-6, 3, 0, None) == 1
+    for bad in [(0.0, 1, 0.01, 1e-6, 3, 0), (0.1, 0, 0.01, 1e-6, 3, 0), (0.1, 1, -1.0, 1e-6, 3, 0),
+                (0.1, 1, 0.01, 0.7, 3, 0), (0.1, 1, 0.01, 1e-6, 0, 0), (0.1, 1, 0.01, 1e-6, 3, 9)]:
+        assert lib.mbo_surface_peanut(ctypes.byref(h), *bad, None) == 1, bad
+        assert not h.value
+    assert lib.mbo_surface_peanut(ctypes.byref(h), 1e-4, 1, 0.01, 1e-6, 3, 0, None) == 2
+    assert b"too small" in lib.mbo_surface_last_error(None)
