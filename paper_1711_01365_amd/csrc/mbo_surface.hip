@@ -314,9 +314,10 @@ struct LineRecip {
     unsigned p3, U, pU, UU, pU3, ppU, pUU;
 };
 
-template <typename T, int P>
+template <typename T, int P, int LM>
 __global__ void __launch_bounds__(512) surface_spread_lines(const SurfArgs a, const LineRecip M)
 {
+    static_assert(LM <= SURF_LINE_MAX, "line length");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int p = P, p3 = P * P * P, CB = SURF_LINE_CB;
     const int TE = a.TE;
@@ -359,9 +360,9 @@ __global__ void __launch_bounds__(512) surface_spread_lines(const SurfArgs a, co
     // this thread's line: x = tid / TE, y = tid % TE (y fastest)
     const bool owns = tid < TE * TE;
     const int lx = owns ? tid / TE : 0, ly = owns ? tid - (tid / TE) * TE : 0;
-    T accr[SURF_LINE_MAX], acci[SURF_LINE_MAX];
+    T accr[LM], acci[LM];
 #pragma unroll
-    for (int z = 0; z < SURF_LINE_MAX; ++z) {
+    for (int z = 0; z < LM; ++z) {
         accr[z] = (T)0;
         acci[z] = (T)0;
     }
@@ -461,7 +462,7 @@ __global__ void __launch_bounds__(512) surface_spread_lines(const SurfArgs a, co
                         const T* br = T2 + c * 2 * t2p + jj * SURF_LINE_KP + SURF_BIN - start_of(cs, 2);
                         const T* bi = br + t2p;
 #pragma unroll
-                        for (int z = 0; z < SURF_LINE_MAX; ++z) {
+                        for (int z = 0; z < LM; ++z) {
 #pragma unroll
                             for (int an = 0; an < P; ++an) {
                                 accr[z] += wx[an] * br[an * U * SURF_LINE_KP + z];
@@ -478,7 +479,7 @@ __global__ void __launch_bounds__(512) surface_spread_lines(const SurfArgs a, co
         typedef typename cx<T>::type C;
         C* dst = reinterpret_cast<C*>(a.tiles) + ((size_t)nb * a.PL + pl) * TE * TE * TE + (size_t)(lx * TE + ly) * TE;
 #pragma unroll
-        for (int z = 0; z < SURF_LINE_MAX; ++z) {
+        for (int z = 0; z < LM; ++z) {
             if (z < TE) {
                 C v;
                 v.x = accr[z];
@@ -649,11 +650,11 @@ static hipError_t surf_cells_p(const SurfArgs& a, int waves, hipStream_t st)
     return hipGetLastError();
 }
 
-template <typename T, int P>
+template <typename T, int P, int LM>
 static hipError_t surf_lines_p(const SurfArgs& a, hipStream_t st)
 {
     const size_t lds = surface_lines_lds(P, a.U, a.chunk, sizeof(T));
-    const void* f = reinterpret_cast<const void*>(&surface_spread_lines<T, P>);
+    const void* f = reinterpret_cast<const void*>(&surface_spread_lines<T, P, LM>);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     LineRecip M;
@@ -664,8 +665,8 @@ static hipError_t surf_lines_p(const SurfArgs& a, hipStream_t st)
     M.pU3 = recip32(3 * P * a.U);
     M.ppU = recip32(P * P * a.U);
     M.pUU = recip32(P * a.U * a.U);
-    hipLaunchKernelGGL((surface_spread_lines<T, P>), dim3((unsigned)a.nbins, (unsigned)(a.pl1 - a.pl0)), dim3(512),
-                       lds, st, a, M);
+    hipLaunchKernelGGL((surface_spread_lines<T, P, LM>), dim3((unsigned)a.nbins, (unsigned)(a.pl1 - a.pl0)),
+                       dim3(512), lds, st, a, M);
     return hipGetLastError();
 }
 
@@ -675,12 +676,22 @@ static hipError_t surf_lines(const SurfArgs& a, hipStream_t st)
     if (a.p < 1 || a.p > 4 || a.U < 2 || a.TE != SURF_BIN + a.U || a.TE > SURF_LINE_MAX || a.chunk < 1)
         return hipErrorInvalidValue;
     static_assert(SURF_LINE_KP % 2 == 1 && SURF_LINE_KP >= SURF_BIN + SURF_LINE_MAX, "padded pitch");
-    switch (a.p) {
-    case 1: return surf_lines_p<T, 1>(a, st);
-    case 2: return surf_lines_p<T, 2>(a, st);
-    case 3: return surf_lines_p<T, 3>(a, st);
-    default: return surf_lines_p<T, 4>(a, st);
+    // registers per line: the smallest of 16, 18, 20, 22 slots that holds the tile edge
+    const int lm = a.TE <= 16 ? 16 : (a.TE <= 18 ? 18 : (a.TE <= 20 ? 20 : 22));
+#define MBO_LINES_P(PP)                                                  \
+    switch (lm) {                                                        \
+    case 16: return surf_lines_p<T, PP, 16>(a, st);                      \
+    case 18: return surf_lines_p<T, PP, 18>(a, st);                      \
+    case 20: return surf_lines_p<T, PP, 20>(a, st);                      \
+    default: return surf_lines_p<T, PP, 22>(a, st);                      \
     }
+    switch (a.p) {
+    case 1: MBO_LINES_P(1)
+    case 2: MBO_LINES_P(2)
+    case 3: MBO_LINES_P(3)
+    default: MBO_LINES_P(4)
+    }
+#undef MBO_LINES_P
 }
 
 template <typename T>
