@@ -577,25 +577,43 @@ __global__ void __launch_bounds__(256) surface_interp(const SurfArgs a)
         const int ix = tile_off(es_weights<T, W2>((pos[s] - y0) * invh, beta, wx) - ox);
         const int iy = tile_off(es_weights<T, W2>((pos[a.m + s] - y0) * invh, beta, wy) - oy);
         const int iz = tile_off(es_weights<T, W2>((pos[2 * a.m + s] - y0) * invh, beta, wz) - oz);
-        // separable: a z sum per (i, j) column, then its x-y weight
+        // float: separable (a z sum per (i, j) column, then its x-y weight),
+        // fewer VALU operations; double: the product weight per point, which
+        // measured faster there
         T sr = 0, si = 0;
+        if constexpr (sizeof(T) == 4) {
 #pragma unroll 1
-        for (int i = 0; i < W2; ++i) {
-            T xr = 0, xi = 0;
+            for (int i = 0; i < W2; ++i) {
+                T xr = 0, xi = 0;
 #pragma unroll
-            for (int j = 0; j < W2; ++j) {
-                const int base = ((ix + i) * TE + (iy + j)) * TE + iz;
-                T zr = 0, zi = 0;
+                for (int j = 0; j < W2; ++j) {
+                    const int base = ((ix + i) * TE + (iy + j)) * TE + iz;
+                    T zr = 0, zi = 0;
 #pragma unroll
-                for (int k = 0; k < W2; ++k) {
-                    zr += wz[k] * tile[2 * (base + k)];
-                    zi += wz[k] * tile[2 * (base + k) + 1];
+                    for (int k = 0; k < W2; ++k) {
+                        zr += wz[k] * tile[2 * (base + k)];
+                        zi += wz[k] * tile[2 * (base + k) + 1];
+                    }
+                    xr += wy[j] * zr;
+                    xi += wy[j] * zi;
                 }
-                xr += wy[j] * zr;
-                xi += wy[j] * zi;
+                sr += wx[i] * xr;
+                si += wx[i] * xi;
             }
-            sr += wx[i] * xr;
-            si += wx[i] * xi;
+        } else {
+#pragma unroll 1
+            for (int i = 0; i < W2; ++i)
+#pragma unroll
+                for (int j = 0; j < W2; ++j) {
+                    const T wij = wx[i] * wy[j];
+                    const int base = ((ix + i) * TE + (iy + j)) * TE + iz;
+#pragma unroll
+                    for (int k = 0; k < W2; ++k) {
+                        const T wt = wij * wz[k];
+                        sr += wt * tile[2 * (base + k)];
+                        si += wt * tile[2 * (base + k) + 1];
+                    }
+                }
         }
         const int e0 = 2 * pl, e1 = e0 + 1;
         out[(size_t)e0 * a.m + q] = sr;
