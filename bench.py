@@ -30,12 +30,20 @@ Haar, 200 iterations; and the paper's example, the star-shaped defect with
 n = 2 on 1024^2, tau = 8 dx, 100 iterations; FP32 + fallback, the SO(n) volume
 of the initial field held fixed) and the gradient of 50 unrolled steps (n = 3,
 256^2, FP32 + fallback and FP64), forward and backward time; the paper's three
-flat-torus examples (n = 2, 1024^2, FP32 + fallback) with their end states; and
-the relaxed gradient flows GD-1 / GD-3 (n = 3, 512^2, 200 steps).
+flat-torus examples (n = 2, 1024^2, FP32 + fallback) with their end states;
+the relaxed gradient flows GD-1 / GD-3 (n = 3, 512^2, 200 steps); the sphere of
+Section 6.2 (closest-point band, dx = 0.05, p = 3, tau = 0.005, 3.3 M samples,
+20 MBO steps, FP32 + fallback and FP64, in sample-steps per second); and the
+volume-preserving sphere of Section 7 (tau = 0.01, 5.1 M samples, 20 steps).
+With --peanut, the peanut of Section 6.3 (116.5 M samples, 10 steps) is added.
 
     python bench.py --volume-only [--steps K] [--warmup W]
 
-runs only the two volume-preserving legs (for profiling them).
+runs only the two volume-preserving legs (for profiling them), and
+
+    python bench.py --surface-only [--peanut] [--steps K]
+
+only the surface legs.
 
     python bench.py --copy-calibration
 
