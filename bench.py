@@ -529,8 +529,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the iteration would shard); run with --gpus 1",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(a large field would be slab-decomposed by rows, with an all-to-all "
+              "transpose each way per iteration); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

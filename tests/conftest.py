@@ -14,8 +14,7 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests run on the GPU machine only; elsewhere they are collected but skipped
-    # unless a device is present.
+    # GPU tests need a GPU: without one they are collected but skipped.
     try:
         import torch
         have_gpu = torch.cuda.is_available()
