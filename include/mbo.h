@@ -69,7 +69,10 @@ typedef enum {
     MBO_OK = 0,
     MBO_ERR_INVALID_ARG = 1,  /* null pointer, d not in {2,3}, n not in [1,4],
                                  tau not finite and > 0, batch < 1, bad precision */
-    MBO_ERR_UNSUPPORTED = 2,  /* some N[a] not a power of two in [8, 2048] */
+    MBO_ERR_UNSUPPORTED = 2,  /* some N[a] not a power of two in [8, 2048], or a
+                                 row (last axis) whose packed planes do not fit
+                                 in LDS: in MBO_F64, a last axis of 2048 with
+                                 n >= 3 */
     MBO_ERR_ALLOC = 3,        /* device allocation failed */
     MBO_ERR_HIP = 4,          /* a HIP runtime call failed (see mbo_last_error) */
     MBO_ERR_NONFINITE = 5     /* NaN or Inf met in the input of a projection */

@@ -272,6 +272,88 @@ def test_iterate_parity_f64(torch_cuda, n, grid):
     compare_runs(r, ro, K, 1e-12)
 
 
+LONG_AXES = [(8, 2048), (2048, 8), (16, 1024), (1024, 16), (8, 16, 2048), (2048, 16, 8)]
+
+
+def long_axes_n(grid):
+    """n = 3, except n = 2 for double rows of 2048 points: a double row pass keeps
+    every packed plane of its row in LDS, and five planes of 2048 doubles do not
+    fit (the plan refuses them, see test_long_double_rows_refused)."""
+    return 2 if grid[-1] == 2048 else 3
+
+
+@pytest.mark.parametrize("grid", LONG_AXES)
+def test_diffuse_long_axes_f64(torch_cuda, grid):
+    """Axes of 1024 and 2048 points, the longest a plan accepts: the row
+    transforms that exchange through workgroup barriers (lines longer than one
+    wave holds) and the strided passes at their largest tile."""
+    torch = torch_cuda
+    tau = 2e-4
+    n = long_axes_n(grid)
+    A = inputs.uniform_field(n, grid, 17)
+    note("diffuse f64 long axes grid=%s n=%d" % (grid, n))
+    P = plan(grid, n, tau, F64)
+    H = P.diffuse(to_dev(torch, A, torch.float64)).cpu().numpy()
+    Ho, _ = oracle.heat(A, tau, len(grid))
+    assert np.abs(H - Ho).max() <= 1e-13
+
+
+@pytest.mark.parametrize("grid", LONG_AXES)
+def test_iterate_long_axes_f64(torch_cuda, grid):
+    """Three MBO steps with rows of up to 2048 points (the projection and the
+    fallback queue sized by the row), against the oracle: entries to 1e-12,
+    flips and energies as in the other FP64 runs."""
+    torch = torch_cuda
+    tau, K = 2e-4, 3
+    n = long_axes_n(grid)
+    A0 = inputs.uniform_field(n, grid, 18)
+    note("iterate f64 long axes grid=%s n=%d" % (grid, n))
+    P = plan(grid, n, tau, F64)
+    t = to_dev(torch, A0, torch.float64)
+    r = P.iterate(t, K)
+    ro = oracle.iterate(A0, tau, K)
+    assert np.abs(t.cpu().numpy() - ro["A"]).max() <= 1e-12
+    compare_runs(r, ro, K, 1e-12)
+
+
+def test_long_double_rows_refused(torch_cuda):
+    """The largest shapes at the LDS limit: double rows of 2048 points with n >= 3
+    are refused (MBO_ERR_UNSUPPORTED); float rows of 2048 with
+    n = 4 and double rows of 1024 with n = 4 are accepted."""
+    from paper_1711_01365_amd import mbo
+    for n in (3, 4):
+        with pytest.raises(mbo.MboError) as ei:
+            plan((8, 2048), n, 1e-3, F64)
+        assert ei.value.status == 2
+    plan((8, 2048), 4, 1e-3, FB).close()
+    plan((8, 1024), 4, 1e-3, F64).close()
+    plan((2048, 8), 4, 1e-3, F64).close()
+
+
+@pytest.mark.parametrize("grid", [(8, 2048), (2048, 8), (8, 16, 2048)])
+def test_iterate_long_axes_fp32_fallback(torch_cuda, grid):
+    """One FP32 + FP64-fallback step with rows of 2048 points (a queue of 2048
+    entries per workgroup) against the FP64 oracle, to the FP32 bar."""
+    torch = torch_cuda
+    tau = 2e-4
+    A0 = inputs.uniform_field(3, grid, 19).astype(np.float32)
+    A64 = A0.astype(np.float64)
+    note("one step f32+fb long axes grid=%s" % (grid,))
+    P = plan(grid, 3, tau, FB)
+    Ht, _ = oracle.heat(A64, tau, len(grid))
+    Hg = P.diffuse(to_dev(torch, A0, torch.float32)).cpu().numpy()
+    e_heat = float(np.abs(Hg - Ht).max())
+    t = to_dev(torch, A0, torch.float32)
+    r = P.iterate(t, 1)
+    ro = oracle.iterate(A64, tau, 1)
+    gap = sigma_gap(Ht)
+    err = np.abs(point_major(t.cpu().numpy() - ro["A"])).max(axis=(1, 2))
+    note("long axes f32+fb: diffusion err %.3g, step err max %.3g, fallbacks %d"
+         % (e_heat, err.max(), r["fallbacks"][0][0]))
+    assert e_heat <= 2e-6
+    assert fp32_step_ok(err, gap, e_heat)
+
+
 def test_iterate_tolerance_stop_matches_oracle(torch_cuda):
     torch = torch_cuda
     tau = 2e-3
