@@ -9,8 +9,9 @@
 // points i0 .. i0 + w - 1 per axis, i0 = ceil(u - W).  Work comes sorted by bin
 // (SURF_BIN^3 grid points); the workgroup of a (bin, plane) accumulates into,
 // or reads from, an LDS tile that covers every stencil of its bin's work.
-// Spreading adds the tiles to the grid with atomics (tiles of neighbouring bins
-// overlap).
+// Spreading stores each (bin, plane) tile in a buffer of its own, and a gather
+// kernel sums the overlapping tiles of neighbouring bins into the grid (no
+// atomics on the grid).
 #include "mbo_kernels.hpp"
 
 namespace mbo {
@@ -21,6 +22,20 @@ __device__ __forceinline__ T es_kernel(T z, T invW, T beta)
     const T r = z * invW;
     const T s = (T)1 - r * r;
     return s > (T)0 ? exp(beta * (sqrt(s) - (T)1)) : (T)0;
+}
+
+// Float: the hardware square root and power of two (about 1 ulp each), with
+// exp(x) = 2^(x log2 e).  The exponent lies in [-beta log2 e, 0] (beta <= 28),
+// where 2^x is a normal float; the weights' relative error stays near 1e-7,
+// the size of the float gridding tolerance, at a third of the operations of
+// the correctly rounded library calls.
+template <>
+__device__ __forceinline__ float es_kernel<float>(float z, float invW, float beta)
+{
+    const float r = z * invW;
+    const float s = 1.0f - r * r;
+    const float b2 = beta * 1.4426950408889634f;  // beta log2(e)
+    return s > 0.0f ? __builtin_amdgcn_exp2f(b2 * __builtin_amdgcn_sqrtf(s) - b2) : 0.0f;
 }
 
 // Stencil start i0 and the w weights of one axis for grid coordinate u.
