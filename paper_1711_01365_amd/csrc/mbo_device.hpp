@@ -778,8 +778,9 @@ __device__ __forceinline__ void cofactor3(const float* x, float* c)
 // every singular value s to (zeta s + 1/(zeta s)) / 2 and keeps U, V and the
 // sign of det, so the limit is U V^t; convergence is quadratic, and a step
 // below 3e-4 leaves an error below the float rounding of the result.  Returns
-// false (q unset) when 1/|A^{-1}|_F < thr, i.e. possibly sigma_min < sqrt(3) thr;
-// then sigma_min is decided by the Jacobi route.  Otherwise sigma_min >= thr.
+// false (q unset) when 1/|A^{-1}|_F <= thr, i.e. possibly
+// sigma_min <= sqrt(3) thr, or A is singular; then sigma_min is decided by the
+// Jacobi route.  Otherwise sigma_min > thr.
 __device__ __forceinline__ bool polar_newton3(const float* a, float* q, int& dsign, float thr)
 {
     float X[9], C[9];
@@ -791,7 +792,9 @@ __device__ __forceinline__ bool polar_newton3(const float* a, float* q, int& dsi
 #pragma unroll
     for (int k = 0; k < 9; ++k) cf2 += C[k] * C[k];
     const float adet = det < 0.f ? -det : det;
-    if (!(adet >= thr * num<float>::sqrt_(cf2))) return false;  // also NaN input
+    // strict: det = 0 with a zero cofactor matrix (rank <= 1, the zero matrix)
+    // takes the Jacobi route too; also NaN input
+    if (!(adet > thr * num<float>::sqrt_(cf2))) return false;
     dsign = det >= 0.f ? 1 : -1;
     bool scaled = true;
 #pragma unroll 1

@@ -130,6 +130,36 @@ def test_project_singular_and_special_inputs(torch_cuda):
         assert np.abs(q.T @ q - np.eye(3)).max() < 1e-14
 
 
+@pytest.mark.parametrize("prec", [F32, FB])
+def test_project_singular_and_special_inputs_fp32(torch_cuda, prec):
+    """The same special matrices through the float projections: the zero matrix
+    gives I, rank-deficient inputs the oracle's factor (det Q = +1 at a tie), no
+    NaN from the Newton route."""
+    torch = torch_cuda
+    mats = [np.zeros((3, 3)), np.diag([1.0, 1.0, 0.0]), np.diag([2.0, 0.0, 0.5]),
+            np.array([[1.0, 0, 0], [0, -1.0, 0], [0, 0, 0]]), np.eye(3), -np.eye(3),
+            np.diag([3.0, 2.0, -1.0]), np.outer([1.0, 2.0, 0.5], [0.3, -1.0, 2.0])]
+    A = np.zeros((3, 3, 8, 8))
+    for k, M in enumerate(mats):
+        A[:, :, 0, k] = M
+    A[:, :, 1:, :] = inputs.uniform_field(3, (7, 8), 5)
+    A32 = A.astype(np.float32)
+    note("special inputs f32 prec=%d" % prec)
+    P = plan((8, 8), 3, 1e-3, prec)
+    Q = P.project(to_dev(torch, A32, torch.float32)).cpu().numpy().astype(np.float64)
+    assert np.isfinite(Q).all()
+    Qo = oracle.project(A32.astype(np.float64))[0]
+    for k in range(len(mats)):
+        q = Q[:, :, 0, k]
+        assert np.abs(q.T @ q - np.eye(3)).max() < 1e-6, k
+        if k < 7:  # rank >= 2 or zero: unique (ties to det +1)
+            assert np.abs(q - Qo[:, :, 0, k]).max() < 1e-6, k
+    assert np.abs(Q[:, :, 0, 0] - np.eye(3)).max() == 0.0
+    ok = cond_mask(A32[:, :, 1:, :].astype(np.float64))
+    err = np.abs(point_major(Q[:, :, 1:, :] - Qo[:, :, 1:, :])).max(axis=(1, 2))
+    assert err[ok].max() <= 1e-5
+
+
 def test_project_nonfinite_is_reported(torch_cuda):
     torch = torch_cuda
     from paper_1711_01365_amd import mbo
