@@ -384,6 +384,33 @@ def test_iterate_long_axes_fp32_fallback(torch_cuda, grid):
     assert fp32_step_ok(err, gap, e_heat)
 
 
+@pytest.mark.parametrize("prec", [F64, F32, FB])
+def test_iterate_zero_and_rank_one_fields(torch_cuda, prec):
+    """Degenerate fields: the zero field diffuses to itself and every point
+    projects to I (A = 0 gives Q = I), after which I is a fixed point; a field
+    of one rank-1 matrix everywhere (diffusion keeps a constant field) projects
+    to an orthogonal matrix with det +1 at the tie and then stays there.  No
+    NaN, no non-finite report, no flips."""
+    torch = torch_cuda
+    grid, tau = (16, 32), 1e-3
+    dt = torch.float64 if prec == F64 else torch.float32
+    M = np.outer([1.0, 2.0, 0.5], [0.3, -1.0, 2.0])
+    for name, A0 in (("zero", np.zeros((3, 3) + grid)),
+                     ("rank one", np.broadcast_to(M[:, :, None, None], (3, 3) + grid).copy())):
+        note("degenerate field %s prec=%d" % (name, prec))
+        P = plan(grid, 3, tau, prec)
+        t = to_dev(torch, A0, dt)
+        r = P.iterate(t, 3)
+        A = t.cpu().numpy().astype(np.float64)
+        assert np.isfinite(A).all(), name
+        Q0 = oracle.project(A0[:, :, :1, :1].copy())[0][:, :, 0, 0]
+        assert abs(np.linalg.det(Q0) - 1.0) < 1e-12
+        tol = 1e-12 if prec == F64 else 1e-6
+        assert np.abs(A - Q0[:, :, None, None]).max() <= tol, name
+        assert int(np.sum(r["flips"][0])) == 0, name
+        P.close()
+
+
 def test_iterate_tolerance_stop_matches_oracle(torch_cuda):
     torch = torch_cuda
     tau = 2e-3
