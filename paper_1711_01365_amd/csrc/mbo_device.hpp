@@ -379,13 +379,37 @@ __device__ __forceinline__ T det_n(const T* m)
     }
 }
 
+// Largest |entry| as a power of two 2^ex (ex = 0 for a zero or non-finite
+// matrix): scaling by 2^-ex is exact and keeps every square representable.
+template <typename T, int n>
+__device__ __forceinline__ int scale_exponent(const T* a)
+{
+    T amax = 0;
+#pragma unroll
+    for (int i = 0; i < n * n; ++i) {
+        const T v = a[i] < (T)0 ? -a[i] : a[i];
+        amax = v > amax ? v : amax;
+    }
+    int ex = 0;
+    if (amax > (T)0 && amax - amax == (T)0) (void)frexp(amax, &ex);
+    return ex;
+}
+
 // n = 2 closed form.  The closest rotation [[c,-s],[s,c]] maximises
 // c (a00 + a11) + s (a10 - a01); the closest reflection [[c,s],[s,-c]] maximises
 // c (a00 - a11) + s (a01 + a10).  Lemma 1.1 keeps the sign of det A, with the
 // rotation taken when det A = 0.  Also returns sigma_min for the fallback test.
+// The matrix is first scaled by a power of two (exact; for matrices of
+// moderate magnitude, whose products are normal numbers either way, the result
+// is unchanged), so that no square or product under- or overflows whatever the
+// magnitude.
 template <typename T>
-__device__ __forceinline__ void polar2(const T* a, T* q, int& dsign, T& smin)
+__device__ __forceinline__ void polar2(const T* a_in, T* q, int& dsign, T& smin)
 {
+    const int ex = scale_exponent<T, 2>(a_in);
+    T a[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] = ldexp(a_in[k], -ex);
     const T det = a[0] * a[3] - a[1] * a[2];
     const bool rot = det >= (T)0;
     const T p = rot ? a[0] + a[3] : a[0] - a[3];
@@ -408,7 +432,7 @@ __device__ __forceinline__ void polar2(const T* a, T* q, int& dsign, T& smin)
     const T ad = det < (T)0 ? -det : det;
     const T lo = f2 - 2 * ad;
     const T smax = (T)0.5 * (num<T>::sqrt_(f2 + 2 * ad) + num<T>::sqrt_(lo > (T)0 ? lo : (T)0));
-    smin = smax > (T)0 ? ad * num<T>::rcp(smax) : (T)0;
+    smin = ldexp(smax > (T)0 ? ad * num<T>::rcp(smax) : (T)0, ex);
 }
 
 // One-sided (Hestenes) Jacobi: rotate pairs of columns of W = A until they are
@@ -470,22 +494,6 @@ __device__ __forceinline__ void jacobi_sweeps(T (&W)[n][n], T (&V)[n][n])
         }
         if (!rotated || smax < sdone) break;
     }
-}
-
-// Largest |entry| as a power of two 2^ex (ex = 0 for a zero or non-finite
-// matrix): scaling by 2^-ex is exact and keeps every square representable.
-template <typename T, int n>
-__device__ __forceinline__ int scale_exponent(const T* a)
-{
-    T amax = 0;
-#pragma unroll
-    for (int i = 0; i < n * n; ++i) {
-        const T v = a[i] < (T)0 ? -a[i] : a[i];
-        amax = v > amax ? v : amax;
-    }
-    int ex = 0;
-    if (amax > (T)0 && amax - amax == (T)0) (void)frexp(amax, &ex);
-    return ex;
 }
 
 // Q = U V^t from the orthogonalised columns W = U Sigma (scaled by 2^-ex).  On
@@ -793,8 +801,10 @@ __device__ __forceinline__ bool polar_newton3(const float* a, float* q, int& dsi
     for (int k = 0; k < 9; ++k) cf2 += C[k] * C[k];
     const float adet = det < 0.f ? -det : det;
     // strict: det = 0 with a zero cofactor matrix (rank <= 1, the zero matrix)
-    // takes the Jacobi route too; also NaN input
-    if (!(adet > thr * num<float>::sqrt_(cf2))) return false;
+    // takes the Jacobi route too, and so does a matrix whose squared cofactor
+    // norm is not a normal float with room (|A| below ~1e-9: the first step's
+    // products would underflow; Jacobi rescales by a power of two); also NaN
+    if (!(cf2 >= 1e-36f) || !(adet > thr * num<float>::sqrt_(cf2))) return false;
     dsign = det >= 0.f ? 1 : -1;
     bool scaled = true;
 #pragma unroll 1

@@ -52,13 +52,20 @@ __device__ __forceinline__ bool vp_member(const VpSel& s, unsigned long long key
 //     U D V^t reverses that direction (Lemma 7.1).  The one of Q, Q' with
 //     det +1 is T+, and Delta E = 2 sgn(det Q) sigma_min.
 template <typename T, int n>
-__device__ __forceinline__ T vp_candidates(const T* a, T* tp, T* tm)
+__device__ __forceinline__ T vp_candidates(const T* a_in, T* tp, T* tm)
 {
+    const T* a = a_in;
     if constexpr (n == 1) {
         tp[0] = (T)1;
         tm[0] = (T)-1;
         return a[0] + a[0];
     } else if constexpr (n == 2) {
+        // scaled by a power of two first (exact), as in polar2: no square or
+        // product under- or overflows; Delta E scales back by the same power
+        const int ex = scale_exponent<T, 2>(a_in);
+        T a[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[k] = ldexp(a_in[k], -ex);
         const T p1 = a[0] + a[3], s1 = a[2] - a[1];
         const T p2 = a[0] - a[3], s2 = a[1] + a[2];
         const T q1 = p1 * p1 + s1 * s1, q2 = p2 * p2 + s2 * s2;
@@ -70,7 +77,7 @@ __device__ __forceinline__ T vp_candidates(const T* a, T* tp, T* tm)
         tm[0] = c2; tm[1] = n2; tm[2] = n2; tm[3] = -c2;
         const T r = q1 * i1 + q2 * i2;  // r+ + r-
         const T det = a[0] * a[3] - a[1] * a[2];
-        return r > (T)0 ? (T)4 * det / r : (T)0;
+        return r > (T)0 ? ldexp((T)4 * det / r, ex) : (T)0;
     } else {
         const int ex = scale_exponent<T, n>(a);
         T W[n][n], V[n][n];

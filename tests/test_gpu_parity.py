@@ -160,6 +160,29 @@ def test_project_singular_and_special_inputs_fp32(torch_cuda, prec):
     assert err[ok].max() <= 1e-5
 
 
+@pytest.mark.parametrize("n", [2, 3, 4])
+@pytest.mark.parametrize("prec", [F64, F32, FB])
+def test_project_scaled_orthogonal_inputs(torch_cuda, prec, n):
+    """s R with R orthogonal projects to R for every scale the precision holds
+    with room (|det| = s^n and the squares or cofactors representable or not):
+    no NaN and no wrong factor from under- or overflowing intermediate
+    products."""
+    torch = torch_cuda
+    Rs = oracle.project(inputs.normal_field(n, (8, 8), 77))[0]
+    scales = ([1e-30, 1e-25, 1e-13, 1e-12, 1e-11, 3e-10, 1e-9, 3e-9, 1e-6, 1.0, 1e6, 1e9, 3e9,
+               1e10, 1e12, 1e13, 1e19, 1e25]
+              if prec != F64 else [1e-150, 1e-100, 1e-60, 1e-12, 1.0, 1e12, 1e60, 1e100, 1e150])
+    dt = torch.float64 if prec == F64 else torch.float32
+    P = plan((8, 8), n, 1e-3, prec)
+    for sc in scales:
+        A = (sc * Rs).astype(np.float64 if prec == F64 else np.float32)
+        R = oracle.project(A.astype(np.float64))[0]
+        Q = P.project(to_dev(torch, A, dt)).cpu().numpy().astype(np.float64)
+        assert np.isfinite(Q).all(), sc
+        tol = 1e-12 if prec == F64 else 1e-5
+        assert np.abs(Q - R).max() <= tol, (sc, np.abs(Q - R).max())
+
+
 def test_project_nonfinite_is_reported(torch_cuda):
     torch = torch_cuda
     from paper_1711_01365_amd import mbo

@@ -210,6 +210,34 @@ def test_project_volume_fp32(torch_cuda, prec, n):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", [2, 3])
+def test_project_volume_scale_invariant(torch_cuda, prec, n):
+    """T+ and T- do not change when the field is scaled by s > 0, and Delta E
+    scales by s, so its order does not change either: the volume projection of
+    s A equals that of A (same selection, same matrices) across the magnitudes
+    the precision holds; Delta E of s A is s times that of A."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    grid = (32, 16)
+    A = inputs.uniform_field(n, grid, 960 + n)
+    f64 = prec == "f64"
+    dt, npdt = (torch.float64, np.float64) if f64 else (torch.float32, np.float32)
+    plan = mbo.Plan(grid, n, 1e-3, precision=mbo.F64 if f64 else mbo.F32)
+    n_plus = 200
+    B1, d1 = plan.project_volume(dev(torch, A.astype(npdt), dt), n_plus, want_dE=True)
+    B1, d1 = B1.cpu().double().numpy(), d1.cpu().double().numpy()
+    scales = [2.0 ** -500, 2.0 ** -200, 2.0 ** 200, 2.0 ** 500] if f64 else [2.0 ** -70, 2.0 ** -40, 2.0 ** 40, 2.0 ** 70]
+    for sc in scales:
+        note("project_volume scale %g %s n=%d" % (sc, prec, n))
+        Bs, ds = plan.project_volume(dev(torch, (A * sc).astype(npdt), dt), n_plus, want_dE=True)
+        Bs, ds = Bs.cpu().double().numpy(), ds.cpu().double().numpy()
+        assert np.isfinite(Bs).all(), sc
+        assert np.array_equal(Bs, B1), sc
+        assert np.array_equal(ds, d1 * sc), sc
+    plan.close()
+
+
 # ---------------------------------------------------------------------------
 # iterations
 # ---------------------------------------------------------------------------
