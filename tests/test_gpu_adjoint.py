@@ -109,6 +109,43 @@ def test_project_vjp_f32(torch_cuda, prec):
     assert vjp_ok(got.cpu().numpy().astype(np.float64), ref, G32, At32, 2.0 ** -24)
 
 
+@pytest.mark.parametrize("prec", [F64, F32])
+def test_project_vjp_special_and_scaled(torch_cuda, prec):
+    """Special matrices (zero: every pair has sigma_i + sigma_j = 0, so the
+    cotangent is 0; rank 2; identity; a reflection) against the oracle, a rank-1
+    matrix finite only (its factor is not unique), and the scaling law
+    VJP(s A, G) = VJP(A, G) / s over magnitudes the precision holds (Q is
+    invariant under s > 0)."""
+    torch = torch_cuda
+    f64 = prec == F64
+    dt, npdt = (torch.float64, np.float64) if f64 else (torch.float32, np.float32)
+    mats = [np.zeros((3, 3)), np.diag([1.0, 1.0, 0.0]), np.diag([2.0, 0.0, 0.5]), np.eye(3),
+            np.diag([3.0, 2.0, -1.0]), np.outer([1.0, 2.0, 0.5], [0.3, -1.0, 2.0])]
+    A = np.zeros((3, 3, 8, 8))
+    for k, M in enumerate(mats):
+        A[:, :, 0, k] = M
+    A[:, :, 1:, :] = diffused(3, (8, 8), 2e-3, 90, "uniform")[:, :, 1:, :]
+    A = A.astype(npdt).astype(np.float64)
+    G = inputs.normal_field(3, (8, 8), 91).astype(npdt).astype(np.float64)
+    p = plan((8, 8), 3, 2e-3, prec)
+    note("vjp special/scaled prec=%d" % prec)
+    got = p.project_vjp(to_dev(torch, A, dt), to_dev(torch, G, dt)).cpu().numpy().astype(np.float64)
+    ref = oracle.project_vjp(A, G)
+    assert np.isfinite(got).all()
+    tol = 1e-12 if f64 else 1e-5
+    assert np.abs(got[:, :, 0, 0]).max() == 0.0
+    assert np.abs(got[:, :, 0, :5] - ref[:, :, 0, :5]).max() <= tol * (1 + np.abs(ref[:, :, 0, :5]).max())
+    assert vjp_ok(got[:, :, 1:, :], ref[:, :, 1:, :], G[:, :, 1:, :], A[:, :, 1:, :],
+                  2.0 ** -53 if f64 else 2.0 ** -24)
+    base = got[:, :, 1:, :]
+    for k in ((-300, -100, 100, 300) if f64 else (-40, -20, 20, 40)):
+        sc = 2.0 ** k
+        gs = p.project_vjp(to_dev(torch, A * sc, dt), to_dev(torch, G, dt)).cpu().numpy().astype(np.float64)
+        assert np.isfinite(gs).all(), k
+        rel = np.abs(gs[:, :, 1:, :] * sc - base).max() / np.abs(base).max()
+        assert rel <= (1e-13 if f64 else 1e-6), (k, rel)
+
+
 def test_project_vjp_n1_zero(torch_cuda):
     torch = torch_cuda
     A = inputs.uniform_field(1, (32, 32), 5)
