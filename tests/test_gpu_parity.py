@@ -465,6 +465,42 @@ def test_iterate_graph_replay_is_stable(torch_cuda):
     assert np.abs(t.cpu().numpy() - ro["A"]).max() <= 1e-12
 
 
+def test_plan_on_a_side_stream(torch_cuda):
+    """A plan created on a side stream (default priority) enqueues everything
+    there: the iteration through its captured graph, diffusion and projection
+    give the same bits as a plan on the default stream; set_stream moves it
+    back."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    grid, n, tau, K = (64, 32), 3, 2e-3, 4
+    A0 = inputs.uniform_field(n, grid, 123)
+    P0 = plan(grid, n, tau, F64)
+    t0 = to_dev(torch, A0, torch.float64)
+    r0 = P0.iterate(t0, K)
+    H0 = P0.diffuse(to_dev(torch, A0, torch.float64)).cpu().numpy()
+    Q0 = P0.project(t0).cpu().numpy()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        t1 = to_dev(torch, A0, torch.float64)
+        P1 = mbo.Plan(grid, n, tau, precision=F64, stream=s)
+        r1 = P1.iterate(t1, K)
+        H1 = P1.diffuse(to_dev(torch, A0, torch.float64))
+        Q1 = P1.project(t1)
+    s.synchronize()
+    assert np.array_equal(t1.cpu().numpy(), t0.cpu().numpy())
+    assert np.array_equal(H1.cpu().numpy(), H0)
+    assert np.array_equal(Q1.cpu().numpy(), Q0)
+    assert np.array_equal(r1["flips"][0], r0["flips"][0])
+    assert np.array_equal(r1["energy"][0], r0["energy"][0])
+    P1.set_stream(None)
+    t2 = to_dev(torch, A0, torch.float64)
+    P1.iterate(t2, K)
+    assert np.array_equal(t2.cpu().numpy(), t0.cpu().numpy())
+    P0.close()
+    P1.close()
+
+
 def test_iterate_batched_fields_match_single(torch_cuda):
     torch = torch_cuda
     A = np.stack([inputs.uniform_field(2, (32, 64), s) for s in (4, 5)])
