@@ -241,6 +241,33 @@ def test_iterate_steps_match_oracle(torch_cuda, prec_name):
     s.close()
 
 
+def test_surface_on_a_side_stream(torch_cuda):
+    """A surface created on a side stream (default priority) runs there: its
+    diffusion and three MBO steps give the same bits as on the default stream."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    tau, eps = 0.01, 1e-9
+    s0 = surface(1.0, 0.2, 2, tau, eps, 3, mbo.F64)
+    A = _octant_start(band_of(s0))
+    H0 = s0.diffuse(dev(torch, A, torch.float64)).cpu().numpy()
+    X0 = dev(torch, A, torch.float64)
+    f0 = s0.iterate(X0, 3, flips=True)
+    torch.cuda.synchronize()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        s1 = mbo.SphereSurface(1.0, 0.2, 2, tau, eps, 3, precision=mbo.F64, stream=st)
+        H1 = s1.diffuse(dev(torch, A, torch.float64))
+        X1 = dev(torch, A, torch.float64)
+        f1 = s1.iterate(X1, 3, flips=True)
+    st.synchronize()
+    note("side stream: m", s1.m, "flips", list(f1))
+    assert np.array_equal(H1.cpu().numpy(), H0)
+    assert np.array_equal(X1.cpu().numpy(), X0.cpu().numpy())
+    assert np.array_equal(np.asarray(f1), np.asarray(f0))
+    s0.close()
+    s1.close()
+
+
 def test_iterate_zero_steps_and_flip_totals(torch_cuda):
     torch = torch_cuda
     from paper_1711_01365_amd import mbo
