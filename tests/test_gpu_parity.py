@@ -501,6 +501,40 @@ def test_plan_on_a_side_stream(torch_cuda):
     P1.close()
 
 
+def test_two_plans_on_two_streams_concurrently(torch_cuda):
+    """Two plans (different shapes and precisions) iterating at the same time
+    on two side streams share no state: each ends as it does when run alone."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    cfg = [((64, 32), 3, 2e-3, F64, 124), ((32, 64), 2, 1e-3, FB, 125)]
+    alone = []
+    for grid, n, tau, prec, seed in cfg:
+        P = plan(grid, n, tau, prec)
+        t = to_dev(torch, inputs.uniform_field(n, grid, seed), torch.float64 if prec == F64 else torch.float32)
+        P.iterate(t, 6)
+        alone.append(t.cpu().numpy())
+        P.close()
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    plans, fields = [], []
+    for (grid, n, tau, prec, seed), st in zip(cfg, streams):
+        with torch.cuda.stream(st):
+            plans.append(mbo.Plan(grid, n, tau, precision=prec, stream=st))
+            fields.append(to_dev(torch, inputs.uniform_field(n, grid, seed),
+                                 torch.float64 if prec == F64 else torch.float32))
+    for st in streams:
+        st.synchronize()
+    for rep in range(3):  # interleaved launches on both streams
+        for P, t, st in zip(plans, fields, streams):
+            with torch.cuda.stream(st):
+                P.iterate(t, 2, logs=False)
+    torch.cuda.synchronize()
+    for t, ref in zip(fields, alone):
+        assert np.array_equal(t.cpu().numpy(), ref)
+    for P in plans:
+        P.close()
+
+
 def test_iterate_batched_fields_match_single(torch_cuda):
     torch = torch_cuda
     A = np.stack([inputs.uniform_field(2, (32, 64), s) for s in (4, 5)])
