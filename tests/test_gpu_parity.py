@@ -465,6 +465,29 @@ def test_iterate_graph_replay_is_stable(torch_cuda):
     assert np.abs(t.cpu().numpy() - ro["A"]).max() <= 1e-12
 
 
+def test_iterate_graph_follows_changing_buffers(torch_cuda):
+    """The graph is keyed by the buffer it was captured with: alternating calls
+    on two buffers (and a changed iteration count) each continue their own
+    iteration, as the oracle does, with no result written into the other
+    buffer."""
+    torch = torch_cuda
+    A0 = inputs.uniform_field(3, (32, 32), 78)
+    B0 = inputs.uniform_field(3, (32, 32), 79)
+    P = plan((32, 32), 3, 1e-3, F64)
+    a = to_dev(torch, A0, torch.float64)
+    b = to_dev(torch, B0, torch.float64)
+    P.iterate(a, 2)
+    P.iterate(b, 2)
+    P.iterate(a, 3)
+    P.iterate(b, 1)
+    P.iterate(a, 1)
+    ra = oracle.iterate(A0, 1e-3, 6)
+    rb = oracle.iterate(B0, 1e-3, 3)
+    assert np.abs(a.cpu().numpy() - ra["A"]).max() <= 1e-12
+    assert np.abs(b.cpu().numpy() - rb["A"]).max() <= 1e-12
+    P.close()
+
+
 def test_plan_on_a_side_stream(torch_cuda):
     """A plan created on a side stream (default priority) enqueues everything
     there: the iteration through its captured graph, diffusion and projection
