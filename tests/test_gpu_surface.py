@@ -52,8 +52,15 @@ def surface(R, dx, p, tau, eps, n, prec):
 
 
 def band_of(s):
+    """The oracle's own sample set for the surface's parameters (the oracle takes
+    no input from the library), checked equal to the library's."""
+    ref = oracle.sphere_band(s.R, s.dx, s.p, s.tau, s.eps)
     xq, xc, w = s.points()
-    return {"xq": xq, "xc": xc, "w": w, "cells": s.cells, "wb": s.band_width}
+    assert s.cells == ref["cells"] and s.m == ref["w"].size
+    assert np.abs(xq - ref["xq"]).max() <= 1e-15 * (s.R + 1)
+    assert np.abs(xc - ref["xc"]).max() <= 1e-15 * (s.R + 1)
+    assert np.abs(w - ref["w"]).max() <= 1e-15 * ref["w"].max()
+    return ref
 
 
 @pytest.mark.parametrize("R,dx,p,tau,eps", [(1.0, 0.12, 1, 0.01, 1e-6), (0.7, 0.1, 2, 0.005, 1e-4),
@@ -368,6 +375,42 @@ def _random_config(seed):
     n = int(rng.integers(1, 5))
     dx = float(rng.uniform(0.12, 0.25)) * (1 + 0.4 * (p - 1))
     return R, dx, p, tau, eps, n
+
+
+# Corners of the parameter space: a small sphere with a fine lattice, a large
+# one with a coarse lattice, a short time step (a wide grid), a long one (a
+# wide band); each either builds and meets the tolerance against the oracle, or
+# is refused as unsupported (a grid beyond 512 per axis).
+EXTREME_CONFIGS = [(0.15, 0.03, 2, 2e-3, 1e-6, 2), (4.0, 0.6, 2, 0.4, 1e-6, 2),
+                   (1.0, 0.1, 3, 1e-3, 1e-6, 1), (1.0, 0.3, 2, 0.1, 1e-9, 3)]
+
+
+@pytest.mark.parametrize("cfg", range(len(EXTREME_CONFIGS)))
+def test_extreme_configurations(torch_cuda, cfg):
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    R, dx, p, tau, eps, n = EXTREME_CONFIGS[cfg]
+    for prec in (mbo.F64, mbo.F32):
+        try:
+            s = surface(R, dx, p, tau, eps, n, prec)
+        except mbo.MboError as e:
+            note("extreme", cfg, "refused:", str(e))
+            assert e.status == 2
+            continue
+        b = band_of(s)
+        A = inputs.uniform_field(n, (s.m,), 970 + cfg)
+        dt = torch.float64 if prec == mbo.F64 else torch.float32
+        Y = s.diffuse(dev(torch, A, dt)).double().cpu().numpy()
+        if s.m <= 20000:
+            ref, got = oracle.surface_diffuse(b, A, tau), Y
+        else:
+            idx = np.random.default_rng(cfg).choice(s.m, 64, replace=False)
+            ref, got = oracle.heat_at(b, A, tau, b["xc"][:, idx]), Y[:, :, idx]
+        err = np.abs(got - ref).max() / np.abs(A).max()
+        note("extreme", cfg, "R %.3f dx %.3f p %d tau %.4f eps %.1e n %d" % (R, dx, p, tau, eps, n),
+             "prec", prec, "m", s.m, "grid", s.grid, "err", err)
+        assert err <= _tol(prec, eps), err
+        s.close()
 
 
 @pytest.mark.parametrize("seed", range(10))

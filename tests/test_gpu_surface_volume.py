@@ -48,8 +48,23 @@ def surface(R, dx, p, tau, eps, n, prec):
 
 
 def band_of(s):
+    """The oracle's own sample set for the surface's parameters (the oracle takes
+    no input from the library), checked equal to the library's."""
+    ref = oracle.sphere_band(s.R, s.dx, s.p, s.tau, s.eps)
     xq, xc, w = s.points()
-    return {"xq": xq, "xc": xc, "w": w, "cells": s.cells, "wb": s.band_width}
+    assert s.cells == ref["cells"] and s.m == ref["w"].size
+    assert np.abs(xq - ref["xq"]).max() <= 1e-15 * (s.R + 1)
+    assert np.abs(xc - ref["xc"]).max() <= 1e-15 * (s.R + 1)
+    assert np.abs(w - ref["w"]).max() <= 1e-15 * ref["w"].max()
+    return ref
+
+
+def weights_of(s, b):
+    """The oracle's integer volume weights of sample set b, checked equal to the
+    library's."""
+    W = oracle.surface_weights(b, s.dx)
+    assert np.array_equal(s.volume_weights(), W)
+    return W
 
 
 def octant_start(b):
@@ -75,7 +90,7 @@ def test_selection_is_bit_exact(torch_cuda, prec_name):
     from paper_1711_01365_amd import mbo
     prec = getattr(mbo, prec_name)
     s = surface(1.0, 0.15, 3, 0.01, 1e-6, 3, prec)
-    W = s.volume_weights()
+    W = weights_of(s, band_of(s))
     total = int(W.sum())
     rng = np.random.default_rng(1400)
     dt = torch.float64 if prec == mbo.F64 else torch.float32
@@ -102,7 +117,7 @@ def test_selection_at_the_paper_size(torch_cuda):
     from paper_1711_01365_amd import mbo
     w = inputs.SPHERE_VOLUME_PAPER
     s = surface(w.R, w.dx, w.p, w.tau, w.eps, w.n, mbo.F32_F64FALLBACK)
-    W = s.volume_weights()
+    W = weights_of(s, band_of(s))
     rng = np.random.default_rng(1401)
     dE = (rng.integers(-3000, 3000, s.m) / 64.0).astype(np.float32)
     d = torch.tensor(dE, device="cuda")
@@ -121,7 +136,7 @@ def test_one_step_matches_oracle(torch_cuda, p):
     tau, dx, eps = 0.01, 0.15 if p == 1 else 0.2, 1e-9
     s = surface(1.0, dx, p, tau, eps, 3, mbo.F64)
     b = band_of(s)
-    W = s.volume_weights()
+    W = weights_of(s, b)
     A0 = octant_start(b)
     for V in (None, int(W.sum()) // 3):
         ref, fl_ref, v_ref = oracle.surface_iterate_volume(b, W, A0, tau, 1, V)
@@ -183,7 +198,7 @@ def test_paper_configuration_keeps_the_volume(torch_cuda):
     w = inputs.SPHERE_VOLUME_PAPER
     s = surface(w.R, w.dx, w.p, w.tau, w.eps, w.n, mbo.F32_F64FALLBACK)
     b = band_of(s)
-    W = s.volume_weights()
+    W = weights_of(s, b)
     A0 = inputs.sphere_octant_field(b["xc"])
     V0 = int(W[np.linalg.det(np.moveaxis(A0, 2, 0)) >= 0].sum())
     X = torch.tensor(A0, dtype=torch.float32, device="cuda")
