@@ -751,5 +751,8 @@ def test_autotune_keeps_results(torch_cuda, grid, n, prec):
     assert np.array_equal(r0["flips"], r1["flips"])
     assert np.allclose(r0["energy"], r1["energy"], rtol=1e-12 if prec == F64 else 1e-5, atol=0)
     if prec == F64:
-        Eo = oracle.energy(t1.cpu().numpy(), 2e-3)
-        assert abs(r1["energy"][0][-1] - Eo) <= 1e-11 * max(1.0, abs(Eo))
+        # against the oracle's own iterate (the states agree to 1e-12, and the
+        # energy moves by at most 2 / tau times that per unit of |dA|)
+        ro = oracle.iterate(A, 2e-3, 6)
+        Eo = ro["energy"][-1]
+        assert abs(r1["energy"][0][-1] - Eo) <= 1e-9 * max(1.0, abs(Eo))
