@@ -638,34 +638,38 @@ def test_iterate_full_size_512_f64_two_steps(torch_cuda):
 
 def test_bench_configuration_properties(torch_cuda):
     """The measured configuration (n = 3, 512^2, 200 FP32+fallback iterations) at
-    full size: every point orthogonal, energy non-increasing from s = 1 (within
-    FP32 rounding), the logged final energy equal to the oracle's energy of the
-    returned field, and the last step equal to one oracle step from iterate 199."""
+    full size: every point orthogonal and the energy non-increasing from s = 1
+    (within FP32 rounding) along the library's own run; and the 200th step at
+    full size from the oracle's own iterate 199 (rounded to float, the input of
+    both): the step within the FP32 bound of the oracle's and its logged energy
+    equal to the oracle's."""
     torch = torch_cuda
     w = inputs.HAAR_512
     A0 = w.field().astype(np.float32)
-    note("bench configuration %s, 199 + 1 iterations" % w.name)
+    note("bench configuration %s, 200 iterations" % w.name)
     P = plan(w.grid, w.n, w.tau, FB)
     t = to_dev(torch, A0, torch.float32)
-    r = P.iterate(t, w.iters - 1)
-    A199 = t.cpu().numpy()
-    r2 = P.iterate(t, 1)
-    A200 = t.cpu().numpy()
-    M = point_major(A200).astype(np.float64)
+    r = P.iterate(t, w.iters)
+    M = point_major(t.cpu().numpy()).astype(np.float64)
     assert np.abs(M.transpose(0, 2, 1) @ M - np.eye(3)).max() < 1e-5
-    E = np.concatenate([r["energy"][0], r2["energy"][0][1:]])
+    E = r["energy"][0]
     assert np.all(np.diff(E[1:]) <= 1e-5 * E[1])
-    assert abs(E[-1] - oracle.energy(A200.astype(np.float64), w.tau)) <= 1e-5 * E[-1]
-    ro = oracle.iterate(A199.astype(np.float64), w.tau, 1)
-    Ht, _ = oracle.heat(A199.astype(np.float64), w.tau, 2)
+    note("oracle trajectory to iterate %d" % (w.iters - 1))
+    A199 = oracle.iterate(w.field(), w.tau, w.iters - 1)["A"].astype(np.float32)
+    A64 = A199.astype(np.float64)
+    ro = oracle.iterate(A64, w.tau, 1)
+    Ht, _ = oracle.heat(A64, w.tau, 2)
     Hg = P.diffuse(to_dev(torch, A199, torch.float32)).cpu().numpy()
     e_heat = float(np.abs(Hg - Ht).max())
+    t = to_dev(torch, A199, torch.float32)
+    r2 = P.iterate(t, 1)
     gap = sigma_gap(Ht)
-    err = np.abs(point_major(A200 - ro["A"])).max(axis=(1, 2))
-    note("bench config last step: diffusion err %.3g, step err max %.3g, well-cond (%d pts) %.3g"
+    err = np.abs(point_major(t.cpu().numpy() - ro["A"])).max(axis=(1, 2))
+    note("bench config step 200: diffusion err %.3g, step err max %.3g, well-cond (%d pts) %.3g"
          % (e_heat, err.max(), int((gap >= 0.1).sum()), err[gap >= 0.1].max() if (gap >= 0.1).any() else 0))
     assert fp32_step_ok(err, gap, e_heat)
-    assert r2["flips"][0][0] == ro["flips"][0] or abs(int(r2["flips"][0][0]) - int(ro["flips"][0])) <= 2
+    assert abs(int(r2["flips"][0][0]) - int(ro["flips"][0])) <= 2
+    assert abs(r2["energy"][0][1] - ro["energy"][1]) <= 1e-5 * abs(ro["energy"][1])
 
 
 def test_iterate_full_size_128cube_f64_two_steps(torch_cuda):
@@ -688,49 +692,46 @@ def test_iterate_full_size_128cube_f64_two_steps(torch_cuda):
 
 def test_3d_configuration_properties(torch_cuda):
     """The 3-D configuration at full size (n = 3, 128^3, 100 FP32+fallback
-    iterations): one FP32 step from A_0 within the FP32 bound of the oracle step,
-    every point of the result orthogonal, energy non-increasing from s = 1 within
-    FP32 rounding, the final logged energy equal to the oracle's energy of the
-    returned field, and the last step equal to one oracle step from iterate 99."""
+    iterations): one FP32 step from A_0 within the FP32 bound of the oracle step;
+    along the library's own run every point of the result orthogonal and the
+    energy non-increasing from s = 1 within FP32 rounding; and a later step from
+    the oracle's own iterate 9 (rounded to float, the input of both) within the
+    FP32 bound, with the oracle's energy."""
     torch = torch_cuda
     w = inputs.NORMAL_128_3D
     A0 = w.field().astype(np.float32)
     note("3-D configuration %s" % w.name)
     P = plan(w.grid, w.n, w.tau, FB)
-    # one step from A_0
-    A64 = A0.astype(np.float64)
-    Ht, _ = oracle.heat(A64.reshape((9,) + w.grid), w.tau, 3)
-    Ht = Ht.reshape(A64.shape)
-    Hg = P.diffuse(to_dev(torch, A0, torch.float32)).cpu().numpy()
-    e_heat = float(np.abs(Hg - Ht).max())
+
+    def step_from(Ain, label):
+        A64 = Ain.astype(np.float64)
+        Ht, _ = oracle.heat(A64.reshape((9,) + w.grid), w.tau, 3)
+        Ht = Ht.reshape(A64.shape)
+        Hg = P.diffuse(to_dev(torch, Ain, torch.float32)).cpu().numpy()
+        e_heat = float(np.abs(Hg - Ht).max())
+        t = to_dev(torch, Ain, torch.float32)
+        r1 = P.iterate(t, 1)
+        ro = oracle.iterate(A64, w.tau, 1)
+        gap = sigma_gap(Ht)
+        err = np.abs(point_major(t.cpu().numpy() - ro["A"])).max(axis=(1, 2))
+        note("  %s: diffusion err %.3g, step err max %.3g, fallbacks %d"
+             % (label, e_heat, err.max(), r1["fallbacks"][0][0]))
+        assert e_heat <= 2e-6
+        assert fp32_step_ok(err, gap, e_heat)
+        return r1, ro
+
+    step_from(A0, "step 1")
+    # the library's own run
     t = to_dev(torch, A0, torch.float32)
-    r1 = P.iterate(t, 1)
-    ro = oracle.iterate(A64, w.tau, 1)
-    gap = sigma_gap(Ht)
-    err = np.abs(point_major(t.cpu().numpy() - ro["A"])).max(axis=(1, 2))
-    note("  step 1: diffusion err %.3g, step err max %.3g, fallbacks %d"
-         % (e_heat, err.max(), r1["fallbacks"][0][0]))
-    assert e_heat <= 2e-6
-    assert fp32_step_ok(err, gap, e_heat)
-    # the rest of the run
-    r = P.iterate(t, w.iters - 2)
-    A99 = t.cpu().numpy()
-    r2 = P.iterate(t, 1)
-    A100 = t.cpu().numpy()
-    M = point_major(A100).astype(np.float64)
+    r = P.iterate(t, w.iters)
+    M = point_major(t.cpu().numpy()).astype(np.float64)
     assert np.abs(M.transpose(0, 2, 1) @ M - np.eye(3)).max() < 1e-5
-    E = np.concatenate([r1["energy"][0][1:], r["energy"][0][1:], r2["energy"][0][1:]])
+    E = r["energy"][0][1:]
     assert np.all(np.diff(E) <= 1e-5 * E[0])
-    assert abs(E[-1] - oracle.energy(A100.astype(np.float64), w.tau)) <= 1e-5 * E[-1]
-    Ht, _ = oracle.heat(A99.astype(np.float64).reshape((9,) + w.grid), w.tau, 3)
-    Ht = Ht.reshape(A99.shape)
-    ro = oracle.iterate(A99.astype(np.float64), w.tau, 1)
-    Hg = P.diffuse(to_dev(torch, A99, torch.float32)).cpu().numpy()
-    e_heat = float(np.abs(Hg - Ht).max())
-    gap = sigma_gap(Ht)
-    err = np.abs(point_major(A100 - ro["A"])).max(axis=(1, 2))
-    note("  last step: diffusion err %.3g, step err max %.3g" % (e_heat, err.max()))
-    assert fp32_step_ok(err, gap, e_heat)
+    # a later step from the oracle's own trajectory
+    A9 = oracle.iterate(w.field(), w.tau, 9)["A"].astype(np.float32)
+    r1, ro = step_from(A9, "step 10")
+    assert abs(r1["energy"][0][1] - ro["energy"][1]) <= 1e-5 * abs(ro["energy"][1])
 
 
 @pytest.mark.parametrize("grid,n,prec", [((64, 64), 3, F64), ((8, 32), 2, F64), ((16, 8, 16), 3, FB),
