@@ -84,6 +84,25 @@ typedef enum {
     MBO_F32_F64FALLBACK = 2
 } mbo_precision;
 
+/* Kernels that mbo_iterate runs (Algorithm 1 with the diffusion of Section 5.1).
+ * MBO_PATH_BANDED (the default) keeps, in 2-D, only the row modes |kx| <= c of
+ * every row spectrum between the two passes of an iteration: c is the smallest
+ * half-width for which the heat symbol summed over every dropped mode,
+ * sum exp(-4 pi^2 tau |k|^2), is at most eta = 1e-12 (float plans) or 1e-20
+ * (MBO_F64).  Since every Fourier coefficient of a field is at most
+ * prod(N) max|A| in modulus, dropping those modes moves each diffused value by
+ * at most eta max|A|, far below the rounding of the transforms.  A plan whose
+ * tau and grid leave nothing to drop runs the same kernels with every mode kept.
+ * MBO_PATH_FULL runs the same kernels with every mode kept; MBO_PATH_GENERIC the
+ * general kernels (any d, any row length), which the other calls always use.
+ * The band-limited kernels serve d = 2 with a last axis of at most 512 points
+ * and a first axis of at least 64; other shapes run the general kernels. */
+typedef enum {
+    MBO_PATH_GENERIC = 0,
+    MBO_PATH_FULL = 1,
+    MBO_PATH_BANDED = 2
+} mbo_path;
+
 /* Create a plan for `batch` fields of n x n matrices on the grid N[0..d-1].
  * tau: diffusion time of one step (Algorithm 1, step 1).
  * sigma_fallback: threshold of MBO_F32_F64FALLBACK (ignored otherwise); a value
@@ -99,6 +118,19 @@ mbo_status mbo_plan_destroy(mbo_plan_t plan);
 
 /* Change the diffusion time; the heat-symbol tables are rebuilt. */
 mbo_status mbo_plan_set_tau(mbo_plan_t plan, double tau);
+
+/* Choose the kernels of mbo_iterate (see mbo_path; a batched plan applies the
+ * choice to every field class).  Synchronises the plan's stream; a captured
+ * iteration graph is rebuilt on the next mbo_iterate.  MBO_ERR_INVALID_ARG for an
+ * unknown path. */
+mbo_status mbo_plan_set_path(mbo_plan_t plan, mbo_path path);
+
+/* The kernels mbo_iterate runs for `field` (0 <= field < count, or < batch for
+ * a plain plan): *path (MBO_PATH_GENERIC when the shape has no band-limited
+ * kernels), the kept half-width *band_half_width along the last axis and the
+ * modes *stored_modes kept per row between the passes (the axis length when
+ * every mode is kept).  All outputs nullable. */
+mbo_status mbo_plan_path(mbo_plan_t plan, int field, int* path, int* band_half_width, int* stored_modes);
 
 /* Change the stream subsequent calls are enqueued on. */
 mbo_status mbo_plan_set_stream(mbo_plan_t plan, void* hip_stream);

@@ -119,6 +119,18 @@ struct mbo_plan_s {
     double t_row_us = 0.0, t_col_us = 0.0;
     int t_launches = 0;
 
+    // band-limited passes of mbo_iterate (2-D, rows of at most 512 points,
+    // columns of at least 64): path chosen by the caller (mbo_plan_set_path),
+    // whether this plan runs them, the kept half-width along the rows and the
+    // stored modes per row, the heat tile width, the symbol of the stored
+    // columns [nt][W]
+    int path = MBO_PATH_BANDED;
+    bool fast = false;
+    int band_c = 0, band_W = 0;
+    int fast_tx = 0, tune_fast_tx = 0;
+    void* lam_col = nullptr;
+    unsigned long long* cnt_part = nullptr;  // row-pass counts per workgroup [batch][log_K][workgroups]
+
     // cached iteration graph
     hipGraphExec_t gexec = nullptr;
     void* g_A = nullptr;
@@ -216,6 +228,7 @@ void destroy(mbo_plan_t p)
     }
     free_dev(p->lam_row);
     free_dev(p->lam_inner);
+    free_dev(p->lam_col);
     free_dev(p->mu_row);
     free_dev(p->mu_inner);
     free_dev(p->dpart);
@@ -326,6 +339,101 @@ mbo_status build_laplace_tables(mbo_plan_t p)
     mbo_status s = upload(p, p->mu_row, row);
     if (s != MBO_OK) return s;
     return upload(p, p->mu_inner, inner);
+}
+
+// Kept half-width of the row axis for the band-limited passes (2-D).  The
+// heat symbol is exp(-4 pi^2 tau ky^2) exp(-4 pi^2 tau kx^2); dropping the
+// modes with |kx| > c changes a diffused value by at most
+// max|A| * S_y(tau) * sum_{|kx| > c} exp(-4 pi^2 tau kx^2), S_y the sum of the
+// column axis's factor over all its modes (|A^(k)| <= N0 N1 max|A|).  c is the
+// smallest half-width that keeps this below eta for every tau of the plan;
+// c = N1/2 keeps every mode.
+int band_halfwidth(int64_t N0, int64_t N1, const std::vector<double>& taus, double eta)
+{
+    const double pi = 3.14159265358979323846;
+    int cmax = 0;
+    for (double tau : taus) {
+        double sy = 0.0;
+        for (int64_t m = 0; m < N0; ++m) {
+            const double k = (2 * m < N0) ? (double)m : (double)(m - N0);
+            sy += std::exp(-4.0 * pi * pi * tau * k * k);
+        }
+        // tail[c] = sum over the wrapped kx with |kx| > c, accumulated from the top
+        const int64_t h = N1 / 2;
+        std::vector<double> tail((size_t)h + 1, 0.0);
+        for (int64_t c = h - 1; c >= 0; --c) {
+            const double k = (double)(c + 1);
+            const double term = std::exp(-4.0 * pi * pi * tau * k * k);
+            // |kx| = c + 1 occurs twice, except the Nyquist mode N1/2 (once)
+            tail[(size_t)c] = tail[(size_t)c + 1] + (c + 1 == h ? 1.0 : 2.0) * term;
+        }
+        int c = 0;
+        while (c < h && sy * tail[(size_t)c] > eta) ++c;
+        cmax = c > cmax ? c : cmax;
+    }
+    return cmax;
+}
+
+// Whether mbo_iterate runs the band-limited passes, and their layout: kept
+// half-width c and stored modes W per row (a multiple of 16, at least 2c + 1;
+// W = N1 when nothing would be saved), the heat tile width.
+void config_fast(mbo_plan_t p)
+{
+    p->fast = false;
+    p->band_c = (int)(p->N[p->d - 1] / 2);
+    p->band_W = (int)p->N[p->d - 1];
+    if (p->path == MBO_PATH_GENERIC || p->d != 2) return;
+    const int64_t N0 = p->N[0], N1 = p->N[1];
+    if (N1 > 512 || N0 < 64 || N0 > 2048) return;
+    if (p->path == MBO_PATH_BANDED) {
+        std::vector<double> taus = p->per_field_tau ? p->taus : std::vector<double>(1, p->tau);
+        const double eta = p->pk == 1 ? 1e-12 : 1e-20;
+        const int c = band_halfwidth(N0, N1, taus, eta);
+        const int W = ((2 * c + 1) + 15) / 16 * 16;
+        if (W < N1) {
+            p->band_c = c;
+            p->band_W = W;
+        }
+    }
+    // heat tile: TX columns of 2^k with 64..1024 threads and TX | W
+    const int Tn = (int)(N0 / 8);
+    int tx = p->tune_fast_tx ? p->tune_fast_tx : 2;
+    while (tx * Tn < 64) tx *= 2;
+    while (tx > 1 && (tx * Tn > 1024 || p->band_W % tx)) tx /= 2;
+    if (tx * Tn < 64 || tx * Tn > 1024 || p->band_W % tx) return;
+    p->fast_tx = tx;
+    p->fast = true;
+}
+
+// Symbol of the stored columns of the band-limited layout, per field when the
+// fields have their own tau: slot w holds kx = w (w <= c) or kx = w - W
+// (w >= W - c), exp(-4 pi^2 tau kx^2) / N1; 0 in the unused slots.
+mbo_status build_fast_tables(mbo_plan_t p)
+{
+    free_dev(p->lam_col);
+    if (!p->fast) return MBO_OK;
+    const int W = p->band_W, c = p->band_c;
+    const int64_t N1 = p->N[1];
+    const int64_t nt = p->per_field_tau ? p->batch : 1;
+    const double pi = 3.14159265358979323846;
+    std::vector<double> v;
+    v.reserve((size_t)(nt * W));
+    for (int64_t b = 0; b < nt; ++b) {
+        const double tau = p->per_field_tau ? p->taus[(size_t)b] : p->tau;
+        for (int w = 0; w < W; ++w) {
+            double k;
+            if (W == N1) k = (2 * w < N1) ? (double)w : (double)(w - N1);
+            else if (w <= c) k = (double)w;
+            else if (w >= W - c) k = (double)(w - W);
+            else {
+                v.push_back(0.0);
+                continue;
+            }
+            v.push_back(std::exp(-4.0 * pi * pi * tau * k * k) / (double)N1);
+        }
+    }
+    HIP_TRY(p, hipMalloc(&p->lam_col, v.size() * p->esz));
+    return upload(p, p->lam_col, v);
 }
 
 // Twiddles exp(-2 pi i m / L), m < L, interleaved (re, im).
@@ -514,11 +622,43 @@ void prepare_plan_kernels(mbo_plan_t p)
     (void)hipGetLastError();
 }
 
+// Dynamic-LDS limits of the band-limited kernels of this plan (every tile width
+// the autotuner may pick).  Advisory, as above.
+void prepare_fast_kernels(mbo_plan_t p)
+{
+    if (!p->fast) return;
+    FastRowArgs r;
+    std::memset(&r, 0, sizeof r);
+    (void)launch_row_fast(p->pk, p->n, ilog2((int)p->N[1]), r, dim3(1), nullptr, true);
+    FastColArgs h;
+    std::memset(&h, 0, sizeof h);
+    for (int tx = 1; tx <= 16; tx *= 2)
+        (void)launch_heat_fast(p->pk, ilog2((int)p->N[0]), tx, h, dim3(1), nullptr, true);
+    (void)hipGetLastError();
+}
+
 // Energy partials per field and iterate: one per wave of the heat pass.
 int energy_partials(mbo_plan_t p)
 {
     const unsigned bx = p->heat.block.x;
     return (int)(p->heat.grid.x * ((bx % 64) ? 1 : bx / 64));  // = col_args(p, p->heat).nwg
+}
+
+// Workgroups of the band-limited row pass per field (512 points each).
+int fast_row_groups(mbo_plan_t p) { return (int)((p->npts + 511) / 512); }
+
+// Grid of the band-limited heat pass and its energy partials per field and
+// iterate (one per wave).
+dim3 fast_heat_grid(mbo_plan_t p)
+{
+    return dim3((unsigned)((int64_t)p->PL * (p->band_W / p->fast_tx)), (unsigned)p->batch);
+}
+
+int fast_energy_partials(mbo_plan_t p)
+{
+    if (!p->fast) return 0;
+    const int nt = p->fast_tx * (int)(p->N[0] / 8);
+    return (int)fast_heat_grid(p).x * (nt / 64);
 }
 
 // Free the device logs; the next ensure_logs reallocates them (their energy
@@ -533,6 +673,7 @@ void drop_logs(mbo_plan_t p)
     free_dev(p->nonfinite);
     free_dev(p->delta_bits);
     free_dev(p->stop_iter);
+    free_dev(p->cnt_part);
     p->log_K = -1;
 }
 
@@ -541,7 +682,9 @@ mbo_status ensure_logs(mbo_plan_t p, int K)
     if (K <= p->log_K) return MBO_OK;
     drop_logs(p);
     const size_t slots = (size_t)p->batch * (size_t)(K + 1);
-    const int nwg = energy_partials(p);
+    // room for the partials of either heat pass (the band-limited one when
+    // mbo_iterate runs it, the generic one for the other calls)
+    const int nwg = std::max(energy_partials(p), fast_energy_partials(p));
     HIP_TRY(p, hipMalloc((void**)&p->epart, slots * (size_t)nwg * sizeof(double)));
     HIP_TRY(p, hipMalloc((void**)&p->energy, slots * sizeof(double)));
     const size_t cslots = (size_t)p->batch * (size_t)(K > 0 ? K : 1);
@@ -550,6 +693,8 @@ mbo_status ensure_logs(mbo_plan_t p, int K)
     HIP_TRY(p, hipMalloc((void**)&p->nonfinite, cslots * sizeof(unsigned long long)));
     HIP_TRY(p, hipMalloc((void**)&p->delta_bits, cslots * sizeof(unsigned long long)));
     HIP_TRY(p, hipMalloc((void**)&p->stop_iter, (size_t)p->batch * sizeof(int)));
+    if (p->fast)
+        HIP_TRY(p, hipMalloc((void**)&p->cnt_part, cslots * (size_t)fast_row_groups(p) * sizeof(unsigned long long)));
     p->log_K = K;
     return MBO_OK;
 }
@@ -599,9 +744,137 @@ hipError_t enqueue_final_energy(mbo_plan_t p, int K, hipStream_t st)
     return launch_reduce(ra, st);
 }
 
+FastRowArgs fast_row_args(mbo_plan_t p)
+{
+    FastRowArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.L = (int)p->N[1];
+    a.band = p->band_c;
+    a.W = p->band_W;
+    a.rows = p->N[0];
+    a.npts = p->npts;
+    a.tw = p->tw[1];
+    a.Z = p->Z;
+    a.sgn = p->sgn;
+    a.sigma_fb = p->sigma_fb;
+    a.K = 1;
+    a.foff = p->foff_dev;
+    return a;
+}
+
+FastColArgs fast_col_args(mbo_plan_t p)
+{
+    FastColArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.L = (int)p->N[0];
+    a.W = p->band_W;
+    a.tiles = p->band_W / p->fast_tx;
+    a.field_elems = (int64_t)p->PL * p->N[0] * p->band_W;
+    a.tw = p->tw[0];
+    a.Z = p->Z;
+    a.lam_row = p->lam_row;
+    a.lam_col = p->lam_col;
+    a.lam_row_stride = p->per_field_tau ? p->N[0] : 0;
+    a.lam_col_stride = p->per_field_tau ? p->band_W : 0;
+    a.xcd_remap = p->xcd_remap;
+    a.nwg = fast_energy_partials(p);
+    a.apply = 1;
+    return a;
+}
+
+hipError_t run_row_fast(mbo_plan_t p, const FastRowArgs& a, hipStream_t st, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr)
+{
+    const dim3 g((unsigned)fast_row_groups(p), (unsigned)p->batch);
+    return launch_row_fast(p->pk, p->n, ilog2((int)p->N[1]), a, g, st, false, ev0, ev1);
+}
+
+hipError_t run_heat_fast(mbo_plan_t p, const FastColArgs& a, hipStream_t st, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr)
+{
+    return launch_heat_fast(p->pk, ilog2((int)p->N[0]), p->fast_tx, a, fast_heat_grid(p), st, false, ev0, ev1);
+}
+
+// mbo_iterate through the band-limited passes: the row pass of A_0 (forward
+// row FFT, det signs), then per iteration the heat pass over the stored columns
+// and the row pass (inverse row FFT, projection, forward row FFT).
+hipError_t enqueue_iterate_fast(mbo_plan_t p, void* A, int K, double tol, bool want_energy, hipStream_t st)
+{
+    const bool track = tol > 0.0;
+    const bool fallback = p->prec == MBO_F32_F64FALLBACK;
+    const int64_t cs = (int64_t)p->batch * (K > 0 ? K : 1);
+    hipError_t e;
+    if ((e = launch_fill_u64(p->flips, cs, 0ull, st)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(p->fallbacks, cs, 0ull, st)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(p->nonfinite, cs, 0ull, st)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(p->delta_bits, cs, 0ull, st)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(p->stop_iter, p->batch, K, st)) != hipSuccess) return e;
+    FastRowArgs r0 = fast_row_args(p);
+    r0.Ain = A;
+    r0.flags = RF_LOAD_REAL | RF_FORWARD | RF_SIGN_INIT;
+    if ((e = run_row_fast(p, r0, st)) != hipSuccess) return e;
+    for (int s = 1; s <= K; ++s) {
+        FastColArgs h = fast_col_args(p);
+        h.iter = s;
+        h.K = K;
+        h.stop_iter = track ? p->stop_iter : nullptr;
+        h.delta_bits = track ? p->delta_bits : nullptr;
+        h.tol = tol;
+        h.slot = s - 1;
+        h.epart = want_energy ? p->epart : nullptr;
+        hipEvent_t hs = p->timing ? p->ev[4 * (s - 1) + 2] : nullptr;
+        hipEvent_t he = p->timing ? p->ev[4 * (s - 1) + 3] : nullptr;
+        if ((e = run_heat_fast(p, h, st, hs, he)) != hipSuccess) return e;
+        FastRowArgs r = fast_row_args(p);
+        r.Aout = A;
+        r.iter = s;
+        r.K = K;
+        r.delta_bits = p->delta_bits;
+        r.cnt_part = p->cnt_part;
+        r.flags = RF_INVERSE | RF_PROJECT | RF_SIGN;
+        if (track) {
+            // only a tolerance can stop a field before the last iteration
+            r.stop_iter = p->stop_iter;
+            r.flags |= RF_CHECK_STOP;
+        }
+        if (s < K || want_energy) r.flags |= RF_FORWARD;
+        if (s == K || track) r.flags |= RF_STORE_REAL;
+        if (track) r.flags |= RF_TRACK;
+        if (fallback) r.flags |= RF_FALLBACK;
+        hipEvent_t rs = p->timing ? p->ev[4 * (s - 1)] : nullptr;
+        hipEvent_t re = p->timing ? p->ev[4 * (s - 1) + 1] : nullptr;
+        if ((e = run_row_fast(p, r, st, rs, re)) != hipSuccess) return e;
+    }
+    if ((e = launch_sum_counts(p->cnt_part, fast_row_groups(p), K, (int)p->batch, p->flips, p->fallbacks,
+                               p->nonfinite, st)) != hipSuccess)
+        return e;
+    if (!want_energy) return hipSuccess;
+    // E(A_final) into slot stop_iter[b], then every energy from its partials
+    FastColArgs h = fast_col_args(p);
+    h.K = K;
+    h.slot = -1;
+    h.stop_iter = p->stop_iter;
+    h.epart = p->epart;
+    h.apply = 0;
+    if ((e = run_heat_fast(p, h, st)) != hipSuccess) return e;
+    ReduceArgs ra;
+    ra.epart = p->epart;
+    ra.nwg = fast_energy_partials(p);
+    ra.K = K;
+    ra.batch = (int)p->batch;
+    ra.n = p->n;
+    ra.npts = p->npts;
+    ra.tau = p->tau;
+    ra.taus = p->taus_dev;
+    ra.stop_iter = p->stop_iter;
+    ra.energy = p->energy;
+    return launch_reduce(ra, st);
+}
+
 // Enqueue the whole of mbo_iterate on stream st (captured into a graph by the caller).
 hipError_t enqueue_iterate(mbo_plan_t p, void* A, int K, double tol, bool want_energy, hipStream_t st)
 {
+    if (p->fast) return enqueue_iterate_fast(p, A, K, tol, want_energy, st);
     const bool track = tol > 0.0;
     const bool fallback = p->prec == MBO_F32_F64FALLBACK;
     const int64_t cs = (int64_t)p->batch * (K > 0 ? K : 1);
@@ -911,6 +1184,9 @@ mbo_status plan_init(mbo_plan_t p, const int64_t* foff_host)
     HIP_TRY(p, hipMalloc(&p->lam_row, nt * (size_t)p->N[0] * p->esz));
     HIP_TRY(p, hipMalloc(&p->lam_inner, nt * (size_t)(p->npts / p->N[0]) * p->esz));
     if ((s = build_symbol_tables(p)) != MBO_OK) return s;
+    config_fast(p);
+    if ((s = build_fast_tables(p)) != MBO_OK) return s;
+    prepare_fast_kernels(p);
     HIP_TRY(p, hipMalloc(&p->mu_row, (size_t)p->N[0] * p->esz));
     HIP_TRY(p, hipMalloc(&p->mu_inner, (size_t)(p->npts / p->N[0]) * p->esz));
     if ((s = build_laplace_tables(p)) != MBO_OK) return s;
@@ -1043,6 +1319,34 @@ mbo_status autotune_plan(mbo_plan_t p)
     if (he != hipSuccess) return done(fail(p, MBO_ERR_HIP, "hipEventCreate: %s", hipGetErrorString(he)));
     double best = 0.0, t = 0.0;
     if ((s = time_iterations(p, A, reps, e0, e1, &best)) != MBO_OK) return done(s);
+    if (p->fast) {
+        // band-limited passes: the heat tile width and the XCD-aware tile order
+        int best_tx = p->fast_tx;
+        for (int tx = 1; tx <= 16; tx *= 2) {
+            if (tx == best_tx) continue;
+            p->tune_fast_tx = tx;
+            config_fast(p);
+            if (!p->fast || p->fast_tx != tx) continue;  // not a valid width here
+            drop_logs(p);
+            if ((s = ensure_logs(p, reps)) != MBO_OK) return done(s);
+            if ((s = time_iterations(p, A, reps, e0, e1, &t)) != MBO_OK) return done(s);
+            if (t < best) {
+                best = t;
+                best_tx = tx;
+            }
+        }
+        p->tune_fast_tx = best_tx;
+        config_fast(p);
+        drop_logs(p);
+        if ((s = ensure_logs(p, reps)) != MBO_OK) return done(s);
+        p->xcd_remap = 0;
+        if ((s = time_iterations(p, A, reps, e0, e1, &t)) != MBO_OK) return done(s);
+        if (t < best) best = t;
+        else p->xcd_remap = 1;
+        p->err.clear();
+        p->tuned = true;
+        return done(MBO_OK);
+    }
     // strided passes: tile width, from one line up to what the rule allows
     for (int axis = 0; axis < (p->d == 3 ? 2 : 1); ++axis) {
         ColCfg& c = axis == 0 ? p->heat : p->ypass;
@@ -1833,7 +2137,7 @@ mbo_status mbo_plan_tuning(mbo_plan_t p, int field, int* rows_per_group, int* ro
     mbo_plan_t m = p->group ? p->members[(size_t)p->f_member[(size_t)field]] : p;
     if (rows_per_group) *rows_per_group = m->row_rpw;
     if (row_threads) *row_threads = (int)m->row_block.x;
-    if (heat_lines_per_group) *heat_lines_per_group = m->heat.TX;
+    if (heat_lines_per_group) *heat_lines_per_group = m->fast ? m->fast_tx : m->heat.TX;
     if (xcd_order) *xcd_order = m->xcd_remap;
     return MBO_OK;
 }
@@ -1853,7 +2157,45 @@ mbo_status mbo_plan_set_tau(mbo_plan_t p, double tau)
     HIP_TRY(p, hipStreamSynchronize(p->stream));  // tables may be in use by queued work
     p->tau = tau;
     drop_graph(p);  // the energy reduction bakes tau into its arguments
-    return build_symbol_tables(p);
+    mbo_status s = build_symbol_tables(p);
+    if (s != MBO_OK) return s;
+    // the kept modes depend on tau (the logs' partial count may change with them)
+    drop_logs(p);
+    config_fast(p);
+    if ((s = build_fast_tables(p)) != MBO_OK) return s;
+    prepare_fast_kernels(p);
+    return MBO_OK;
+}
+
+mbo_status mbo_plan_set_path(mbo_plan_t p, mbo_path path)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (path != MBO_PATH_GENERIC && path != MBO_PATH_FULL && path != MBO_PATH_BANDED)
+        return fail(p, MBO_ERR_INVALID_ARG, "unknown path %d", (int)path);
+    HIP_TRY(p, hipSetDevice(p->device));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    drop_graph(p);
+    std::vector<mbo_plan_t> plans = p->group ? p->members : std::vector<mbo_plan_t>(1, p);
+    for (mbo_plan_t m : plans) {
+        m->path = (int)path;
+        drop_logs(m);  // the heat pass's partial count may change
+        config_fast(m);
+        const mbo_status s = build_fast_tables(m);
+        if (s != MBO_OK) return p == m ? s : fail(p, s, "%s", m->err.c_str());
+        prepare_fast_kernels(m);
+    }
+    return MBO_OK;
+}
+
+mbo_status mbo_plan_path(mbo_plan_t p, int field, int* path, int* band_half_width, int* stored_modes)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    if (field < 0 || field >= (int)p->batch) return fail(p, MBO_ERR_INVALID_ARG, "field out of range");
+    mbo_plan_t m = p->group ? p->members[(size_t)p->f_member[(size_t)field]] : p;
+    if (path) *path = !m->fast ? MBO_PATH_GENERIC : (m->band_W < m->N[m->d - 1] ? MBO_PATH_BANDED : MBO_PATH_FULL);
+    if (band_half_width) *band_half_width = m->band_c;
+    if (stored_modes) *stored_modes = m->band_W;
+    return MBO_OK;
 }
 
 mbo_status mbo_plan_set_timing(mbo_plan_t p, int enable)
@@ -2001,6 +2343,21 @@ mbo_status mbo_step(mbo_plan_t p, const void* A_prev, void* A_next)
     if (!A_prev || !A_next) return fail(p, MBO_ERR_INVALID_ARG, "A_prev / A_next is NULL");
     if (A_prev == A_next) return fail(p, MBO_ERR_INVALID_ARG, "A_next must not alias A_prev");
     HIP_TRY(p, hipSetDevice(p->device));
+    if (p->fast) {
+        // the kernels of mbo_iterate, so that a step reproduces its iterate
+        FastRowArgs r0 = fast_row_args(p);
+        r0.Ain = A_prev;
+        r0.flags = RF_LOAD_REAL | RF_FORWARD;
+        HIP_TRY(p, run_row_fast(p, r0, p->stream));
+        FastColArgs hf = fast_col_args(p);
+        HIP_TRY(p, run_heat_fast(p, hf, p->stream));
+        FastRowArgs r1 = fast_row_args(p);
+        r1.Aout = A_next;
+        r1.flags = RF_INVERSE | RF_PROJECT | RF_STORE_REAL;
+        if (p->prec == MBO_F32_F64FALLBACK) r1.flags |= RF_FALLBACK;
+        HIP_TRY(p, run_row_fast(p, r1, p->stream));
+        return MBO_OK;
+    }
     HIP_TRY(p, enqueue_forward(p, A_prev, 0, true, p->stream));
     ColArgs h = col_args(p, p->heat);
     HIP_TRY(p, run_col(p, p->heat, CM_HEAT, h, p->stream));

@@ -1,0 +1,478 @@
+// Band-limited passes of Algorithm 1 on the 2-D flat torus for gfx950: the
+// diffusion step of Section 5.1 (FFT, multiply by exp(-4 pi^2 tau |k|^2),
+// inverse FFT) and the projection of Lemma 1.1, in two kernels per iteration.
+//
+// Kept modes.  The heat symbol is a product over the axes of
+// exp(-4 pi^2 tau k^2); along an axis of length N the host keeps |k| <= c,
+// with c the smallest half-width whose discarded symbol mass
+// sum_{k outside the kept box} exp(-4 pi^2 tau |k|^2) is at most eta.  A value
+// of the diffused field then moves by at most eta * max|A| when those modes
+// are dropped (|A^(k)| <= N^d max|A| for every mode), far below the rounding of
+// the transforms themselves (eta = 1e-12 for float plans, 1e-20 for double
+// plans).  The row pass therefore stores, for every row, only the row spectrum
+// at kx = 0..c and kx = N-c..N-1, in W slots per row (slot w holds kx = w for
+// w <= c and kx = N - W + w for w >= W - c; the slots between hold zeros), and
+// the column pass transforms only those W columns.  With c >= N/2 nothing is
+// dropped and W = N.
+//
+//   row_fast   one workgroup owns 512 points (512/L whole rows, L <= 512): the
+//              line groups of its packed planes load their kept modes straight
+//              into the FFT register layout (lane t holds x[t + e L/8]),
+//              inverse-FFT inside one wave and leave the lines in LDS; one
+//              thread per point projects (Lemma 1.1) with the det-sign,
+//              fallback, non-finite and change diagnostics; the line groups
+//              forward-FFT and store the kept modes.  Float plans with n = 3
+//              run the Newton polar iteration on every point that is certainly
+//              well conditioned (1/|A^{-1}|_F > sigma_fb) and hand the others
+//              to one extra wave, raised in priority, that projects them by
+//              Jacobi (and in double when sigma_min < sigma_fb) while the other
+//              waves iterate, so the double work is off the row's critical
+//              path.
+//   heat_fast  a tile of TX stored columns of one packed plane: thread (t, cc)
+//              loads rows t + e L/8 of column cc (TX-wide coalesced segments),
+//              forward FFT along the column with workgroup exchanges, Lyapunov
+//              partial sum_k symbol |Z|^2 (Section 4), symbol multiply, inverse
+//              FFT, store in place.
+#pragma once
+
+#include "mbo_kernels.hpp"
+
+namespace mbo {
+
+// Stored slot of row mode kx, or -1 when the mode is not kept.
+__device__ __forceinline__ int band_slot(int kx, int L, int c, int W)
+{
+    if (kx <= c) return kx;
+    if (kx >= L - c) return W - (L - kx);
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// Float n = 3 Newton polar iteration, split so that the workgroup can decide
+// which points it runs before iterating (same arithmetic as polar_newton3).
+// ---------------------------------------------------------------------------
+struct Newton3 {
+    float X[9], C[9];
+    float det, cf2;
+};
+
+// True when 1/|A^{-1}|_F > thr (then sigma_min > thr) and the cofactor norm is
+// a normal float with room; otherwise the point goes to the Jacobi route.
+__device__ __forceinline__ bool newton3_init(const float* a, Newton3& s, float thr)
+{
+#pragma unroll
+    for (int k = 0; k < 9; ++k) s.X[k] = a[k];
+    cofactor3(s.X, s.C);
+    s.det = s.X[0] * s.C[0] + s.X[1] * s.C[1] + s.X[2] * s.C[2];
+    s.cf2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) s.cf2 += s.C[k] * s.C[k];
+    const float adet = s.det < 0.f ? -s.det : s.det;
+    return (s.cf2 >= 1e-36f) && (adet > thr * num<float>::sqrt_(s.cf2));
+}
+
+__device__ __forceinline__ void newton3_run(Newton3& s, float* q, int& dsign)
+{
+    dsign = s.det >= 0.f ? 1 : -1;
+    bool scaled = true;
+#pragma unroll 1
+    for (int it = 0; it < 16; ++it) {
+        if (it > 0) {
+            cofactor3(s.X, s.C);
+            s.det = s.X[0] * s.C[0] + s.X[1] * s.C[1] + s.X[2] * s.C[2];
+            s.cf2 = 0.f;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) s.cf2 += s.C[k] * s.C[k];
+        }
+        float xf2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) xf2 += s.X[k] * s.X[k];
+        const float idet = 1.0f / s.det;
+        const float zeta = scaled ? num<float>::sqrt_(num<float>::sqrt_(s.cf2) * (idet < 0.f ? -idet : idet) *
+                                                      num<float>::rsq(xf2))
+                                  : 1.0f;
+        const float cx = 0.5f * zeta, cc = 0.5f * idet / zeta;
+        float diff = 0.f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const float xn = cx * s.X[k] + cc * s.C[k];
+            const float dv = xn - s.X[k];
+            diff = fmaxf(diff, dv < 0.f ? -dv : dv);
+            s.X[k] = xn;
+        }
+        if (diff < 1e-2f) scaled = false;
+        if (diff < 3e-4f) break;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) q[k] = s.X[k];
+}
+
+// ---------------------------------------------------------------------------
+// Row pass
+// ---------------------------------------------------------------------------
+
+constexpr int FAST_POINTS = 512;  // points per row-pass workgroup
+
+template <typename T, int n>
+constexpr bool row_fast_helper() { return sizeof(T) == 4 && n == 3; }
+
+template <typename T, int n>
+constexpr int row_fast_threads() { return FAST_POINTS + (row_fast_helper<T, n>() ? 64 : 0); }
+
+// LDS bytes of a row-pass workgroup: every packed line of its rows, re and im.
+template <typename T, int n, int LOG2L>
+constexpr size_t row_fast_lds()
+{
+    return (size_t)((n * n + 1) / 2) * (FAST_POINTS >> LOG2L) * ((1 << LOG2L) + (1 << LOG2L) / 8) * 2 * sizeof(T);
+}
+
+// waves per SIMD the instance is compiled for (two workgroups per CU)
+template <typename T, int n>
+constexpr int row_fast_waves() { return row_fast_helper<T, n>() ? 5 : 4; }
+
+template <typename T, int n, int LOG2L>
+__global__ void __launch_bounds__((row_fast_threads<T, n>()), (row_fast_waves<T, n>())) row_fast(const FastRowArgs a)
+{
+    constexpr int NN = n * n;
+    constexpr int PL = (NN + 1) / 2;
+    constexpr int L = 1 << LOG2L;
+    constexpr int Tn = L / 8;
+    constexpr int RPW = FAST_POINTS / L;  // rows per workgroup (L <= 512)
+    constexpr int LINES = RPW * PL;
+    constexpr int NFFT = LINES * Tn;      // threads of the line groups
+    constexpr int LP = L + L / 8;         // padded line length
+    constexpr bool HELPER = row_fast_helper<T, n>();
+    static_assert(LOG2L <= 9, "a line must fit in one wave");
+    typedef typename cx<T>::type C;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lr = reinterpret_cast<T*>(smem_raw);
+    T* li = lr + (size_t)LINES * LP;
+    __shared__ unsigned short fq[HELPER ? FAST_POINTS : 1];
+    __shared__ int fq_n;
+    __shared__ unsigned long long wg_cnt[2];
+
+    const int flags = a.flags;
+    const int b = blockIdx.y;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        fq_n = 0;
+        wg_cnt[0] = 0;
+        wg_cnt[1] = 0;
+    }
+    const int64_t row0 = (int64_t)blockIdx.x * RPW;
+    const int64_t npts = a.npts;
+    const int W = a.W, c = a.band;
+    C* Zb = reinterpret_cast<C*>(a.Z) + (size_t)b * PL * a.rows * W;
+
+    // Every global load that does not depend on another is issued first (the
+    // kept modes, the twiddles, the previous det signs, the stop mark): at the
+    // start of a launch each round trip to memory is a cold miss, and none of
+    // them waits for another.
+    const int j = tid / Tn, t = tid - (tid / Tn) * Tn;
+    const int pt = lds_pad(t);
+    const bool fft_thread = tid < NFFT;
+    T r[8], im[8];
+    Twiddles<T, LOG2L> tw;
+    if ((flags & RF_INVERSE) && fft_thread) {
+        const int rloc = j / PL, pl = j - (j / PL) * PL;
+        const bool live = row0 + rloc < a.rows;
+        const C* zr = Zb + ((size_t)pl * a.rows + (live ? row0 + rloc : 0)) * W;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int w = band_slot(t + e * Tn, L, c, W);
+            C v;
+            if (live && w >= 0) v = zr[w];
+            else { v.x = 0; v.y = 0; }
+            r[e] = v.x;
+            im[e] = v.y;
+        }
+    }
+    if (fft_thread && (flags & (RF_INVERSE | RF_FORWARD)))
+        load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
+    const bool pthread = tid < FAST_POINTS;
+    const int rloc = tid >> LOG2L, xc = tid & (L - 1);
+    const bool plive = pthread && row0 + rloc < a.rows;
+    const int64_t x = (row0 + rloc) * L + xc;
+    int8_t* sgn = a.sgn + (size_t)b * npts;
+    const int8_t s_old = (plive && (flags & RF_SIGN)) ? sgn[x] : (int8_t)0;
+    const int stop = (flags & RF_CHECK_STOP) ? a.stop_iter[b] : a.iter;
+
+    // ---- phase 1: inverse FFT of each line, natural order into LDS
+    if ((flags & RF_INVERSE) && fft_thread) {
+        T* lrj = lr + (size_t)j * LP;
+        T* lij = li + (size_t)j * LP;
+        fft_wave<T, +1, LOG2L>(r, im, lrj, lij, t, tw, true);
+        wave_lds_sync();  // the line's last exchange has been read
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            lrj[lds_pad_at<Tn>(t, pt, e)] = r[e];
+            lij[lds_pad_at<Tn>(t, pt, e)] = im[e];
+        }
+    }
+    // a field that already stopped is left alone (uniform per workgroup; the
+    // loads above only read)
+    if (stop < a.iter) return;
+
+    // ---- phase 2: one point per thread
+    T* Aout = reinterpret_cast<T*>(a.Aout) + field_base(a.foff, b, NN * npts);
+    T* lrp = lr + (size_t)rloc * PL * LP + lds_pad(xc);
+    T* lip = li + (size_t)rloc * PL * LP + lds_pad(xc);
+    unsigned long long nflip = 0, nfb = 0, nbad = 0;
+    double dmax = 0.0;
+    const bool fallback = (flags & RF_FALLBACK) != 0;
+
+    // diagnostics and write-back of a projected point (LDS slot at lrq/liq)
+    auto finish = [&](int64_t xp, T* lrq, T* liq, const T (&qv)[NN], int ds, int8_t so) {
+        if (flags & RF_SIGN) {
+            nflip += (so != (int8_t)ds) ? 1ull : 0ull;
+            sgn[xp] = (int8_t)ds;
+        }
+        if (flags & RF_TRACK) {
+#pragma unroll
+            for (int k = 0; k < NN; ++k) {
+                const double dv = fabs((double)qv[k] - (double)Aout[(int64_t)k * npts + xp]);
+                dmax = dv > dmax ? dv : dmax;
+            }
+        }
+        if (flags & RF_STORE_REAL) {
+#pragma unroll
+            for (int k = 0; k < NN; ++k) Aout[(int64_t)k * npts + xp] = qv[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NN; ++k) {
+            if (k & 1) liq[(k >> 1) * LP] = qv[k];
+            else lrq[(k >> 1) * LP] = qv[k];
+        }
+        if (NN & 1) liq[(NN >> 1) * LP] = (T)0;
+    };
+
+    if (flags & RF_LOAD_REAL) {
+        // forward transform of a real field: the point's entries from A
+        if (plive) {
+            const T* A = reinterpret_cast<const T*>(a.Ain) + field_base(a.foff, b, NN * npts);
+            T av[NN];
+#pragma unroll
+            for (int k = 0; k < NN; ++k) av[k] = A[(int64_t)k * npts + x];
+            if (flags & RF_SIGN_INIT) sgn[x] = det_n<T, n>(av) >= (T)0 ? 1 : -1;
+#pragma unroll
+            for (int k = 0; k < NN; ++k) {
+                if (k & 1) lip[(k >> 1) * LP] = av[k];
+                else lrp[(k >> 1) * LP] = av[k];
+            }
+            if (NN & 1) lip[(NN >> 1) * LP] = (T)0;
+        }
+    }
+    __syncthreads();
+
+    if (flags & RF_PROJECT) {
+        T av[NN];
+        if (plive) {
+#pragma unroll
+            for (int k = 0; k < NN; ++k) av[k] = (k & 1) ? lip[(k >> 1) * LP] : lrp[(k >> 1) * LP];
+            nbad += all_finite<T, NN>(av) ? 0ull : 1ull;
+        }
+        if constexpr (HELPER) {
+            // which points are certainly well conditioned: the Newton iteration;
+            // the others are queued for the helper wave
+            Newton3 ns;
+            bool ok = false;
+            if (plive) {
+                ok = newton3_init(av, ns, (float)a.sigma_fb);
+                if (!ok) fq[atomicAdd(&fq_n, 1)] = (unsigned short)tid;
+            }
+            __syncthreads();
+            if (pthread) {
+                if (ok) {
+                    T qv[NN];
+                    int ds;
+                    newton3_run(ns, qv, ds);
+                    finish(x, lrp, lip, qv, ds, s_old);
+                }
+            } else {
+                // the helper wave: Jacobi in float, and in double (warm-started
+                // from the float right singular vectors) when sigma_min < sigma_fb
+                __builtin_amdgcn_s_setprio(3);
+                const int nq = fq_n;
+                const int lane = tid & 63;
+#pragma unroll 1
+                for (int qi = lane; qi < nq; qi += 64) {
+                    const int pi = fq[qi];
+                    const int rq = pi >> LOG2L, xq = pi & (L - 1);
+                    const int64_t xp = (row0 + rq) * L + xq;
+                    T* lrq = lr + (size_t)rq * PL * LP + lds_pad(xq);
+                    T* liq = li + (size_t)rq * PL * LP + lds_pad(xq);
+                    float aq[NN], qv[NN];
+#pragma unroll
+                    for (int k = 0; k < NN; ++k) aq[k] = (k & 1) ? liq[(k >> 1) * LP] : lrq[(k >> 1) * LP];
+                    int ds;
+                    if (fallback) {
+                        float V[n][n];
+                        if (polar_jacobi_f32_fb<n>(aq, qv, ds, V, a.sigma_fb)) {
+                            double ad[NN], qd[NN], smd;
+#pragma unroll
+                            for (int k = 0; k < NN; ++k) ad[k] = (double)aq[k];
+                            polar_jacobi_warm<n>(ad, V, qd, ds, smd);
+#pragma unroll
+                            for (int k = 0; k < NN; ++k) qv[k] = (float)qd[k];
+                            ++nfb;
+                        }
+                    } else {
+                        float smin;
+                        polar_jacobi<float, n>(aq, qv, ds, smin);
+                    }
+                    finish(xp, lrq, liq, qv, ds, (flags & RF_SIGN) ? sgn[xp] : (int8_t)0);
+                }
+                __builtin_amdgcn_s_setprio(0);
+            }
+        } else {
+            if (plive) {
+                T qv[NN];
+                int ds;
+                if (project_point_fb<T, n>(av, qv, ds, fallback, a.sigma_fb)) ++nfb;
+                finish(x, lrp, lip, qv, ds, s_old);
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- phase 3: forward FFT of the lines, store the kept modes
+    if ((flags & RF_FORWARD) && fft_thread) {
+        const int rl = j / PL, pl = j - (j / PL) * PL;
+        T* lrj = lr + (size_t)j * LP;
+        T* lij = li + (size_t)j * LP;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            r[e] = lrj[lds_pad_at<Tn>(t, pt, e)];
+            im[e] = lij[lds_pad_at<Tn>(t, pt, e)];
+        }
+        wave_lds_sync();  // every lane has read its elements before the exchanges
+        fft_wave<T, -1, LOG2L>(r, im, lrj, lij, t, tw, true);
+        if (row0 + rl < a.rows) {
+            C* zr = Zb + ((size_t)pl * a.rows + row0 + rl) * W;
+            // slots w < W - c take mode w (zero when w > c); slots w >= W - c
+            // take mode L - W + w
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int kx = t + e * Tn;
+                C v;
+                v.x = r[e];
+                v.y = im[e];
+                if (kx < W - c) {
+                    if (kx > c) { v.x = 0; v.y = 0; }
+                    zr[kx] = v;
+                } else if (kx >= L - c) {
+                    zr[W - L + kx] = v;
+                }
+            }
+        }
+    }
+
+    if (flags & (RF_PROJECT | RF_TRACK)) {
+        // counts of the workgroup: packed 21 bits each (at most 512 per workgroup)
+        unsigned long long packed = wave_sum(nflip | (nfb << 21) | (nbad << 42));
+        unsigned long long dbits = (unsigned long long)__double_as_longlong(dmax);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long ob = (unsigned long long)__shfl_xor((long long)dbits, o, 64);
+            dbits = ob > dbits ? ob : dbits;
+        }
+        if ((tid & 63) == 0) {
+            if (packed) atomicAdd(&wg_cnt[0], packed);
+            if (dbits) atomicMax(&wg_cnt[1], dbits);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            // the workgroup's packed counts into its own slot (summed per
+            // iteration after the loop: no same-address atomics from every
+            // workgroup at the end of the pass); the largest change by atomic max
+            if (a.cnt_part)
+                a.cnt_part[((int64_t)b * a.K + (a.iter - 1)) * gridDim.x + blockIdx.x] = wg_cnt[0];
+            if ((flags & RF_TRACK) && a.delta_bits && wg_cnt[1])
+                atomicMax(a.delta_bits + (int64_t)b * a.K + (a.iter - 1), wg_cnt[1]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass over the stored columns
+// ---------------------------------------------------------------------------
+
+template <typename T, int LOG2L, int TX>
+__global__ void __launch_bounds__(TX * (1 << LOG2L) / 8) heat_fast(const FastColArgs a)
+{
+    typedef typename cx<T>::type C;
+    typedef FftShape<LOG2L> F;
+    constexpr int L = F::L, Tn = F::Tn;
+    constexpr int LP = L + L / 8;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lr = reinterpret_cast<T*>(smem_raw);
+    T* li = lr + (size_t)TX * LP;
+
+    const int b = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int cc = tid % TX, t = tid / TX;
+    // XCD-aware order: the eight XCDs (own L2 each) get contiguous runs of tiles
+    const int64_t nwgx = gridDim.x;
+    const int64_t wg = ((nwgx & 7) || !a.xcd_remap) ? (int64_t)blockIdx.x
+                                                    : (int64_t)(blockIdx.x & 7) * (nwgx >> 3) + (blockIdx.x >> 3);
+    const int64_t o = wg / a.tiles;
+    const int col = (int)(wg - o * a.tiles) * TX + cc;
+    C* Zc = reinterpret_cast<C*>(a.Z) + (size_t)b * a.field_elems + o * (int64_t)L * a.W + col;
+    // every independent global load first (column data, symbol, twiddles, the
+    // stop marks): at the start of a launch each round trip is a cold miss
+    T r[1][8], im[1][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const C v = Zc[(int64_t)(t + e * Tn) * a.W];
+        r[0][e] = v.x;
+        im[0][e] = v.y;
+    }
+    const T* lrow = reinterpret_cast<const T*>(a.lam_row) + b * a.lam_row_stride;
+    const T lcol = reinterpret_cast<const T*>(a.lam_col)[b * a.lam_col_stride + col];
+    T lam[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) lam[e] = lrow[t + e * Tn];
+    Twiddles<T, LOG2L> tw;
+    load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
+    const bool marks = a.iter > 0 && a.stop_iter;
+    const int stop = marks ? a.stop_iter[b] : a.iter;
+    const bool check_tol = marks && a.delta_bits && a.tol > 0.0 && a.iter >= 2;
+    const unsigned long long dbits = check_tol ? a.delta_bits[(int64_t)b * a.K + (a.iter - 2)] : 0ull;
+    if (marks) {
+        if (stop < a.iter) return;  // uniform per workgroup
+        // the first pass of iteration s stops field b when s-1 changed it by <= tol
+        if (check_tol && __longlong_as_double((long long)dbits) <= a.tol) {
+            if (blockIdx.x == 0 && tid == 0) atomicMin(a.stop_iter + b, a.iter - 1);
+            return;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) lam[e] *= lcol;
+    fft_lines<T, -1, 1, LOG2L>(r, im, lr, li, 0, TX, cc, t, tw);
+    if (a.epart) {
+        // this thread's eight terms in the plan's precision, the wave's sum in double
+        T acc = 0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc += lam[e] * (r[0][e] * r[0][e] + im[0][e] * im[0][e]);
+        const double s = wave_sum((double)acc);
+        const int slot = a.slot >= 0 ? a.slot : a.stop_iter[b];
+        if ((tid & 63) == 0)
+            a.epart[((int64_t)b * (a.K + 1) + slot) * a.nwg + wg * (blockDim.x >> 6) + (tid >> 6)] = s;
+    }
+    if (!a.apply) return;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        r[0][e] *= lam[e];
+        im[0][e] *= lam[e];
+    }
+    fft_lines<T, +1, 1, LOG2L>(r, im, lr, li, 0, TX, cc, t, tw);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        C v;
+        v.x = r[0][e];
+        v.y = im[0][e];
+        Zc[(int64_t)(t + e * Tn) * a.W] = v;
+    }
+}
+
+}  // namespace mbo

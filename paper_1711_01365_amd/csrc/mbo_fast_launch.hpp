@@ -1,0 +1,100 @@
+// Launchers of the band-limited passes (mbo_fast.hpp) for one precision T:
+// row_fast for n = 1..4 and row lengths 2^3..2^9, heat_fast for column lengths
+// 2^6..2^11 and tiles of TX = 1..16 columns with 64..1024 threads.
+#pragma once
+
+#include <hip/hip_ext.h>
+
+#include "mbo_fast.hpp"
+
+namespace mbo {
+
+template <typename T, int n, int LG>
+static hipError_t row_fast_go(const FastRowArgs& a, dim3 g, hipStream_t st, bool prepare, hipEvent_t ev0,
+                              hipEvent_t ev1)
+{
+    const size_t lds = row_fast_lds<T, n, LG>();
+    const void* f = reinterpret_cast<const void*>(&row_fast<T, n, LG>);
+    if (prepare) return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const dim3 bl(row_fast_threads<T, n>());
+    if (ev0) hipExtLaunchKernelGGL((row_fast<T, n, LG>), g, bl, lds, st, ev0, ev1, 0, a);
+    else hipLaunchKernelGGL((row_fast<T, n, LG>), g, bl, lds, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int n>
+static hipError_t row_fast_n(int log2L, const FastRowArgs& a, dim3 g, hipStream_t st, bool prepare,
+                             hipEvent_t ev0, hipEvent_t ev1)
+{
+    switch (log2L) {
+    case 3: return row_fast_go<T, n, 3>(a, g, st, prepare, ev0, ev1);
+    case 4: return row_fast_go<T, n, 4>(a, g, st, prepare, ev0, ev1);
+    case 5: return row_fast_go<T, n, 5>(a, g, st, prepare, ev0, ev1);
+    case 6: return row_fast_go<T, n, 6>(a, g, st, prepare, ev0, ev1);
+    case 7: return row_fast_go<T, n, 7>(a, g, st, prepare, ev0, ev1);
+    case 8: return row_fast_go<T, n, 8>(a, g, st, prepare, ev0, ev1);
+    case 9: return row_fast_go<T, n, 9>(a, g, st, prepare, ev0, ev1);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t row_fast_t(int n, int log2L, const FastRowArgs& a, dim3 g, hipStream_t st, bool prepare,
+                             hipEvent_t ev0, hipEvent_t ev1)
+{
+    switch (n) {
+    case 1: return row_fast_n<T, 1>(log2L, a, g, st, prepare, ev0, ev1);
+    case 2: return row_fast_n<T, 2>(log2L, a, g, st, prepare, ev0, ev1);
+    case 3: return row_fast_n<T, 3>(log2L, a, g, st, prepare, ev0, ev1);
+    case 4: return row_fast_n<T, 4>(log2L, a, g, st, prepare, ev0, ev1);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int LG, int TX>
+static hipError_t heat_fast_go(const FastColArgs& a, dim3 g, hipStream_t st, bool prepare, hipEvent_t ev0,
+                               hipEvent_t ev1)
+{
+    constexpr int NT = TX * (1 << LG) / 8;
+    if constexpr (NT < 64 || NT > 1024) {
+        return hipErrorInvalidValue;
+    } else {
+        const size_t lds = (size_t)TX * ((1 << LG) + (1 << LG) / 8) * 2 * sizeof(T);
+        const void* f = reinterpret_cast<const void*>(&heat_fast<T, LG, TX>);
+        if (prepare) return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (ev0) hipExtLaunchKernelGGL((heat_fast<T, LG, TX>), g, dim3(NT), lds, st, ev0, ev1, 0, a);
+        else hipLaunchKernelGGL((heat_fast<T, LG, TX>), g, dim3(NT), lds, st, a);
+        return hipGetLastError();
+    }
+}
+
+template <typename T, int LG>
+static hipError_t heat_fast_l(int TX, const FastColArgs& a, dim3 g, hipStream_t st, bool prepare, hipEvent_t ev0,
+                              hipEvent_t ev1)
+{
+    switch (TX) {
+    case 1: return heat_fast_go<T, LG, 1>(a, g, st, prepare, ev0, ev1);
+    case 2: return heat_fast_go<T, LG, 2>(a, g, st, prepare, ev0, ev1);
+    case 4: return heat_fast_go<T, LG, 4>(a, g, st, prepare, ev0, ev1);
+    case 8: return heat_fast_go<T, LG, 8>(a, g, st, prepare, ev0, ev1);
+    case 16: return heat_fast_go<T, LG, 16>(a, g, st, prepare, ev0, ev1);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t heat_fast_t(int log2L, int TX, const FastColArgs& a, dim3 g, hipStream_t st, bool prepare,
+                              hipEvent_t ev0, hipEvent_t ev1)
+{
+    switch (log2L) {
+    case 6: return heat_fast_l<T, 6>(TX, a, g, st, prepare, ev0, ev1);
+    case 7: return heat_fast_l<T, 7>(TX, a, g, st, prepare, ev0, ev1);
+    case 8: return heat_fast_l<T, 8>(TX, a, g, st, prepare, ev0, ev1);
+    case 9: return heat_fast_l<T, 9>(TX, a, g, st, prepare, ev0, ev1);
+    case 10: return heat_fast_l<T, 10>(TX, a, g, st, prepare, ev0, ev1);
+    case 11: return heat_fast_l<T, 11>(TX, a, g, st, prepare, ev0, ev1);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace mbo

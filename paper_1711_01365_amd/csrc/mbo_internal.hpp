@@ -360,4 +360,62 @@ hipError_t launch_penalty(int prec, int n, const void* A, int64_t npts, int batc
 hipError_t launch_row_vp_f64(int n, int log2L, const RowArgs& a, dim3 g, dim3 b, size_t lds,
                              hipStream_t st, bool prepare);
 
+
+// Band-limited passes of the 2-D iteration (mbo_fast.hpp): the row spectra
+// keep only the modes kx <= band and kx >= L - band, W slots per row.
+struct FastRowArgs {
+    int L;                   // row length (last grid axis)
+    int band;                // kept half-width c along the row axis
+    int W;                   // stored modes per row
+    int64_t rows;            // rows per field plane
+    int64_t npts;            // points per field
+    const void* tw;          // twiddles exp(-2 pi i m / L)
+    void* Z;                 // kept row spectra [batch][PL][rows][W] complex
+    const void* Ain;         // RF_LOAD_REAL: real field [batch][n*n][npts]
+    void* Aout;              // RF_STORE_REAL / RF_TRACK: real field
+    int8_t* sgn;             // det signs [batch][npts]
+    unsigned long long* delta_bits;  // [batch][K] max |A_s - A_{s-1}| (double bits)
+    int* stop_iter;          // [batch]
+    int iter, K, flags;
+    double sigma_fb;
+    const int64_t* foff;     // nullable field offsets of the real fields
+    unsigned long long* cnt_part;  // nullable: packed flips | fallbacks << 21 | non-finite << 42
+                                   // per workgroup [batch][K][gridDim.x]
+};
+
+struct FastColArgs {
+    int L;                   // column length (grid axis 0)
+    int W;                   // stored columns per plane (row stride of the layout)
+    int64_t tiles;           // W / TX
+    int64_t field_elems;     // PL * L * W complex elements per field
+    const void* tw;          // twiddles exp(-2 pi i m / L)
+    void* Z;
+    const void* lam_row;     // [L] exp(-4 pi^2 tau ky^2) / L
+    const void* lam_col;     // [W] exp(-4 pi^2 tau kx^2) / N1 of the stored column (0 in unused slots)
+    int64_t lam_row_stride;  // per-field tables (0: shared)
+    int64_t lam_col_stride;
+    int xcd_remap;
+    double* epart;           // energy partials [batch][K+1][nwg]
+    int nwg;
+    int slot;                // energy slot; -1: stop_iter[b]
+    int iter, K;
+    int* stop_iter;          // nullable
+    const unsigned long long* delta_bits;  // nullable
+    double tol;
+    int apply;               // 1: multiply and transform back (heat step); 0: energy only
+};
+
+hipError_t launch_row_fast(int prec, int n, int log2L, const FastRowArgs& a, dim3 grid, hipStream_t st,
+                           bool prepare = false, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+hipError_t launch_heat_fast(int prec, int log2L, int TX, const FastColArgs& a, dim3 grid, hipStream_t st,
+                            bool prepare = false, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// threads and LDS bytes of a row_fast workgroup, LDS bytes of a heat_fast workgroup
+int row_fast_block(int prec, int n);
+// flips / fallbacks / non-finite of every iteration and field from the row
+// pass's per-workgroup packed counts [batch][K][nwg]
+hipError_t launch_sum_counts(const unsigned long long* part, int nwg, int K, int batch, unsigned long long* flips,
+                             unsigned long long* fallbacks, unsigned long long* nonfinite, hipStream_t st);
+size_t row_fast_lds_bytes(int prec, int n, int log2L);
+size_t heat_fast_lds_bytes(int prec, int log2L, int TX);
+
 }  // namespace mbo

@@ -344,6 +344,48 @@ hipError_t launch_fill_uniform(int prec, void* p, int64_t count, uint64_t seed, 
     return hipGetLastError();
 }
 
+// One workgroup per (field, iteration): the sums of the unpacked counts of
+// every row-pass workgroup, in a fixed order.
+__global__ void __launch_bounds__(256) sum_counts(const unsigned long long* part, int nwg, int K,
+                                                  unsigned long long* flips, unsigned long long* fallbacks,
+                                                  unsigned long long* nonfinite)
+{
+    __shared__ unsigned long long sh[3][256];
+    const int64_t slot = blockIdx.x;  // b * K + s
+    const unsigned long long* pp = part + slot * (int64_t)nwg;
+    const unsigned long long m21 = (1ull << 21) - 1;
+    unsigned long long f = 0, fb = 0, bad = 0;
+    for (int i = threadIdx.x; i < nwg; i += 256) {
+        const unsigned long long v = pp[i];
+        f += v & m21;
+        fb += (v >> 21) & m21;
+        bad += v >> 42;
+    }
+    sh[0][threadIdx.x] = f;
+    sh[1][threadIdx.x] = fb;
+    sh[2][threadIdx.x] = bad;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        flips[slot] = sh[0][0];
+        fallbacks[slot] = sh[1][0];
+        nonfinite[slot] = sh[2][0];
+    }
+}
+
+hipError_t launch_sum_counts(const unsigned long long* part, int nwg, int K, int batch, unsigned long long* flips,
+                             unsigned long long* fallbacks, unsigned long long* nonfinite, hipStream_t st)
+{
+    if (K <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sum_counts, dim3((unsigned)((int64_t)batch * K)), dim3(256), 0, st, part, nwg, K, flips,
+                       fallbacks, nonfinite);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st)
 {
     const int64_t total = (int64_t)a.batch * (a.K + 1);

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_PKG, "libmbo.so")
 
 F64, F32, F32_F64FALLBACK = 0, 1, 2
 GD1, GD3 = 1, 3
+PATH_GENERIC, PATH_FULL, PATH_BANDED = 0, 1, 2
 _STATUS = {0: "MBO_OK", 1: "MBO_ERR_INVALID_ARG", 2: "MBO_ERR_UNSUPPORTED", 3: "MBO_ERR_ALLOC",
            4: "MBO_ERR_HIP", 5: "MBO_ERR_NONFINITE"}
 
@@ -35,7 +36,7 @@ EXPORTS = ("mbo_plan", "mbo_plan_destroy", "mbo_plan_set_tau", "mbo_plan_set_str
            "mbo_surface_info",
            "mbo_surface_points", "mbo_surface_diffuse", "mbo_surface_iterate", "mbo_surface_last_error",
            "mbo_surface_volume_weights", "mbo_surface_volume_select", "mbo_surface_iterate_volume",
-           "mbo_status_string", "mbo_last_error")
+           "mbo_plan_set_path", "mbo_plan_path", "mbo_status_string", "mbo_last_error")
 
 
 class FieldDesc(ctypes.Structure):
@@ -76,6 +77,8 @@ def load(path: str = LIB_PATH):
     lib.mbo_plan_batched.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(FieldDesc),
                                      ctypes.c_int, ctypes.c_double, ctypes.c_int, vp]
     lib.mbo_plan_tuning.argtypes = [vp, ctypes.c_int, ip, ip, ip, ip]
+    lib.mbo_plan_set_path.argtypes = [vp, ctypes.c_int]
+    lib.mbo_plan_path.argtypes = [vp, ctypes.c_int, ip, ip, ip]
     lib.mbo_plan_autotune.argtypes = [vp]
     lib.mbo_step.argtypes = [vp, vp, vp]
     lib.mbo_step_vjp.argtypes = [vp, vp, vp, vp]
@@ -370,6 +373,17 @@ class Plan:
         _check(self._lib.mbo_plan_tuning(self._h, int(field), ctypes.byref(r), ctypes.byref(n),
                                          ctypes.byref(t), ctypes.byref(x)), self._h)
         return r.value, n.value, t.value, x.value
+
+    def set_path(self, path: int):
+        """Kernels of iterate(): PATH_BANDED (default), PATH_FULL or PATH_GENERIC."""
+        _check(self._lib.mbo_plan_set_path(self._h, int(path)), self._h)
+
+    def path(self, field: int = 0):
+        """(path in effect, kept half-width along the last axis, modes stored per row)."""
+        p, c, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.mbo_plan_path(self._h, int(field), ctypes.byref(p), ctypes.byref(c),
+                                       ctypes.byref(w)), self._h)
+        return p.value, c.value, w.value
 
     def close(self):
         if getattr(self, "_h", None):

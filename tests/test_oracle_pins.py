@@ -439,3 +439,31 @@ def test_iterate_tolerance_stop():
     A = np.broadcast_to(q[:, :, None, None], (2, 2, 8, 8)).copy()
     r = oracle.iterate(A, 1e-3, 10, tol=1e-12)
     assert r["iters"] == 1 and len(r["energy"]) == 2
+
+
+@pytest.mark.parametrize("n,grid,seed", [(2, (16, 16), 95), (3, (16, 8), 96), (1, (32, 32), 97)])
+def test_iterate_logs_from_consecutive_iterates(n, grid, seed):
+    """The integer and change logs of Algorithm 1 against their definitions on the
+    iterates themselves: flips_s = #{p : sgn det A_s(p) != sgn det A_{s-1}(p)} with
+    sgn(0) = +1 (A_0 the raw input, so s = 1 counts against its sign) and
+    delta_s = max_p |A_s(p) - A_{s-1}(p)|.  The iterates come from single steps of the
+    oracle, the signs from numpy's determinant, so an index shift, a count against
+    the diffused matrix instead of A_{s-1}, or a wrong reduction shows up."""
+    tau, K = 2e-3, 6
+    A0 = inputs.uniform_field(n, grid, seed)
+    full = oracle.iterate(A0, tau, K, tol=1e-300)  # a tolerance no step meets: logs kept, all K run
+    assert full["iters"] == K
+    its = [A0]
+    for _ in range(K):
+        its.append(oracle.iterate(its[-1], tau, 1)["A"])
+    assert np.abs(its[-1] - full["A"]).max() == 0.0
+
+    def sgn_det(A):
+        d = np.linalg.det(point_major(A))
+        return np.where(d >= 0, 1, -1)
+
+    flips = [int(np.count_nonzero(sgn_det(its[s]) != sgn_det(its[s - 1]))) for s in range(1, K + 1)]
+    delta = [float(np.abs(its[s] - its[s - 1]).max()) for s in range(1, K + 1)]
+    assert list(full["flips"]) == flips
+    assert np.array_equal(full["delta"], np.array(delta))
+    assert sum(flips[1:]) > 0  # the check is not vacuous past the first step
