@@ -158,6 +158,12 @@ mbo_status mbo_diffuse(mbo_plan_t plan, const void* A_in, void* A_out);
  * Returns MBO_ERR_NONFINITE (after synchronising) if any input value is NaN/Inf. */
 mbo_status mbo_project(mbo_plan_t plan, const void* A_in, void* A_out, int8_t* det_sign);
 
+/* Counts of the last mbo_project call on this plan (all fields): points
+ * re-projected in double (MBO_F32_F64FALLBACK: float-computed smallest singular
+ * value below sigma_fallback) and points whose input held NaN/Inf.  Nullable
+ * outputs. */
+mbo_status mbo_last_project_counts(mbo_plan_t plan, int64_t* fallbacks, int64_t* nonfinite);
+
 /* Algorithm 1: A_s = P(e^{tau Delta} A_{s-1}) for s = 1..max_iter, in place on A
  * (device, holds A_0 on entry and the last iterate on return).  A_0 need not be
  * orthogonal: the first step diffuses whatever is given.

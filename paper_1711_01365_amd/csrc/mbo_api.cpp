@@ -129,7 +129,9 @@ struct mbo_plan_s {
     int band_c = 0, band_W = 0;
     int fast_tx = 0, tune_fast_tx = 0;
     void* lam_col = nullptr;
-    unsigned long long* cnt_part = nullptr;  // row-pass counts per workgroup [batch][log_K][workgroups]
+    unsigned long long* cnt_part = nullptr;
+    // counts of the last mbo_project: double re-projections, non-finite inputs
+    int64_t last_fb = 0, last_bad = 0;  // row-pass counts per workgroup [batch][log_K][workgroups]
 
     // cached iteration graph
     hipGraphExec_t gexec = nullptr;
@@ -2258,6 +2260,9 @@ mbo_status mbo_project(mbo_plan_t p, const void* A_in, void* A_out, int8_t* det_
     if (p->group) {
         if (det_sign) return fail(p, MBO_ERR_UNSUPPORTED, "det_sign is not available for a batched plan");
         for (mbo_plan_t m : p->members) {
+            m->last_fb = m->last_bad = 0;
+        }
+        for (mbo_plan_t m : p->members) {
             const mbo_status s = mbo_project(m, A_in, A_out, nullptr);
             if (s != MBO_OK) return fail(p, s, "%s", m->err.c_str());
         }
@@ -2278,7 +2283,22 @@ mbo_status mbo_project(mbo_plan_t p, const void* A_in, void* A_out, int8_t* det_
     unsigned long long h[4];
     HIP_TRY(p, hipMemcpyAsync(h, p->counters, sizeof h, hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(p, hipStreamSynchronize(p->stream));
+    p->last_fb = (int64_t)h[1];
+    p->last_bad = (int64_t)h[0];
     if (h[0]) return fail(p, MBO_ERR_NONFINITE, "%llu points with NaN/Inf input", h[0]);
+    return MBO_OK;
+}
+
+mbo_status mbo_last_project_counts(mbo_plan_t p, int64_t* fallbacks, int64_t* nonfinite)
+{
+    if (!p) return MBO_ERR_INVALID_ARG;
+    int64_t fb = p->last_fb, bad = p->last_bad;
+    for (mbo_plan_t m : p->members) {
+        fb += m->last_fb;
+        bad += m->last_bad;
+    }
+    if (fallbacks) *fallbacks = fb;
+    if (nonfinite) *nonfinite = bad;
     return MBO_OK;
 }
 

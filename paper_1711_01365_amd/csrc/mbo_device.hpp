@@ -448,12 +448,10 @@ __device__ __forceinline__ void polar2(const T* a_in, T* q, int& dsign, T& smin)
 // stops after a sweep without rotations, or after a sweep whose rotations all
 // had |s| < sdone (the inner products left are then of order s^2, below the
 // tolerance, so the confirming sweep is skipped).
-template <typename T, int n, bool FOR_FLOAT = false>
+template <typename T, int n>
 __device__ __forceinline__ void jacobi_sweeps(T (&W)[n][n], T (&V)[n][n])
 {
-    // a double run whose result is rounded to float may stop once the
-    // remaining inner products (of order s^2) are far below float rounding
-    constexpr T sdone = FOR_FLOAT ? (T)1e-6 : num<T>::sdone;
+    constexpr T sdone = num<T>::sdone;
 #pragma unroll 1
     for (int sweep = 0; sweep < 30; ++sweep) {
         bool rotated = false;
@@ -537,6 +535,54 @@ __device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const T (&V)[n][n], 
         const T inv = filled[j] ? num<T>::rsq(ss[j]) : (T)0;
 #pragma unroll
         for (int i = 0; i < n; ++i) W[i][j] *= inv;  // W becomes U
+    }
+    if constexpr (n == 3 || n == 4) {
+        if (!anyzero) {
+            // The column of the smallest singular value from the others: the
+            // unit vector orthogonal to them (cross product; for n = 4 the
+            // generalised one), signed like w_min.  Dividing w_min by its small
+            // norm would carry an error of about eps sigma_max / sigma_min into
+            // U even where the polar factor is well conditioned
+            // (sigma_{n-1} + sigma_n large); the completion does not.
+            int jm = 0;
+#pragma unroll
+            for (int j = 1; j < n; ++j) jm = sg[j] < sg[jm] ? j : jm;
+            T cv[n];
+            if constexpr (n == 3) {
+                const int a = jm == 0 ? 1 : 0, b = jm == 2 ? 1 : 2;
+                cv[0] = W[1][a] * W[2][b] - W[2][a] * W[1][b];
+                cv[1] = W[2][a] * W[0][b] - W[0][a] * W[2][b];
+                cv[2] = W[0][a] * W[1][b] - W[1][a] * W[0][b];
+            } else {
+                int o[3], k = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (j != jm) o[k++] = j;
+                // cv_i = (-1)^i det of the 3x3 rows other than i of [u_o0 u_o1 u_o2]
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    int r[3], m = 0;
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr)
+                        if (rr != i) r[m++] = rr;
+                    const T d = W[r[0]][o[0]] * (W[r[1]][o[1]] * W[r[2]][o[2]] - W[r[2]][o[1]] * W[r[1]][o[2]]) -
+                                W[r[1]][o[0]] * (W[r[0]][o[1]] * W[r[2]][o[2]] - W[r[2]][o[1]] * W[r[0]][o[2]]) +
+                                W[r[2]][o[0]] * (W[r[0]][o[1]] * W[r[1]][o[2]] - W[r[1]][o[1]] * W[r[0]][o[2]]);
+                    cv[i] = (i & 1) ? -d : d;
+                }
+            }
+            T cn = 0, dt = 0;
+#pragma unroll
+            for (int i = 0; i < n; ++i) {
+                cn += cv[i] * cv[i];
+                dt += cv[i] * W[i][jm];
+            }
+            if (cn > (T)0) {
+                const T inv = (dt < (T)0 ? (T)-1 : (T)1) * num<T>::rsq(cn);
+#pragma unroll
+                for (int i = 0; i < n; ++i) W[i][jm] = cv[i] * inv;
+            }
+        }
     }
     int lastz = -1;
     if (anyzero) {
@@ -627,8 +673,10 @@ __device__ __forceinline__ void polar_jacobi(const T* a_in, T* q, int& dsign, T&
 // The same in double, warm-started from the right singular vectors V0 of a
 // float run on the same matrix, for a result that is rounded to float: V0 is
 // re-orthonormalised in double (modified Gram-Schmidt), W = A V0 is then nearly
-// column-orthogonal and one sweep (rotations of order float rounding) leaves
-// inner products of order 1e-14, far below what the float result resolves.
+// column-orthogonal, and the sweeps (rotations of order float rounding) run to
+// the double stopping rule: the points that come here may have an
+// ill-conditioned polar factor (2 / (sigma_{n-1} + sigma_n) up to ~1e7), which
+// would carry a looser stop into the float result.
 template <int n>
 __device__ __forceinline__ void polar_jacobi_warm(const double* a_in, const float (&V0)[n][n],
                                                   double* q, int& dsign, double& smin)
@@ -665,7 +713,7 @@ __device__ __forceinline__ void polar_jacobi_warm(const double* a_in, const floa
             for (int k = 0; k < n; ++k) v += a_in[i * n + k] * V[k][j];
             W[i][j] = ldexp(v, -ex);
         }
-    jacobi_sweeps<double, n, true>(W, V);
+    jacobi_sweeps<double, n>(W, V);
     jacobi_finish<double, n>(W, V, ex, q, dsign, smin);
 }
 
@@ -779,6 +827,30 @@ __device__ __forceinline__ void cofactor3(const float* x, float* c)
     c[8] = x[0] * x[4] - x[1] * x[3];
 }
 
+// Whether the float 3x3 matrix a (cofactors C, det, squared cofactor norm cf2)
+// certainly has sigma_min > thr.
+__device__ __forceinline__ bool newton3_certain(const float* a, const float* C, float det, float cf2, float thr)
+{
+    // 1/|A^{-1}|_F = |det| / |cof A|_F <= sigma_min, so |det| > thr |cof|_F
+    // proves sigma_min > thr, provided the float det and cofactors are
+    // accurate enough: a cofactor carries an error of at most 2u|A|_F^2 and
+    // det at most 4u|A|_F^3 + 3u|A|_F|cof|_F (u = 2^-24), so the test is made
+    // with that margin (doubled).  Without it a numerically rank-1 matrix
+    // (sigma_2 near u sigma_1), whose float cofactors are mostly rounding,
+    // could pass.  Strict: det = 0 with a zero cofactor matrix (rank <= 1, the
+    // zero matrix) fails, and so does a matrix whose squared cofactor norm is
+    // not a normal float with room (|A| below ~1e-9: the first step's products
+    // would underflow; Jacobi rescales by a power of two); also NaN.
+    float af2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) af2 += a[k] * a[k];
+    const float an = num<float>::sqrt_(af2), cn = num<float>::sqrt_(cf2);
+    const float u = 5.9604644775390625e-08f;
+    const float margin = 2.f * u * (thr * (6.f * af2 + cn) + an * (4.f * af2 + 3.f * cn));
+    const float adet = det < 0.f ? -det : det;
+    return (cf2 >= 1e-36f) && (adet > thr * cn + margin);
+}
+
 // Closest orthogonal matrix of a float 3x3 matrix by the scaled Newton
 // iteration for the polar decomposition, X <- (zeta X + X^{-T} / zeta) / 2
 // (Higham, 1986), with Frobenius-norm scaling zeta = (|X^{-1}|_F / |X|_F)^{1/2}
@@ -786,9 +858,9 @@ __device__ __forceinline__ void cofactor3(const float* x, float* c)
 // every singular value s to (zeta s + 1/(zeta s)) / 2 and keeps U, V and the
 // sign of det, so the limit is U V^t; convergence is quadratic, and a step
 // below 3e-4 leaves an error below the float rounding of the result.  Returns
-// false (q unset) when 1/|A^{-1}|_F <= thr, i.e. possibly
-// sigma_min <= sqrt(3) thr, or A is singular; then sigma_min is decided by the
-// Jacobi route.  Otherwise sigma_min > thr.
+// false (q unset) unless newton3_certain proves sigma_min > thr (it fails when
+// sigma_min may be at most about sqrt(3) thr, when A is singular or numerically
+// of rank 1); sigma_min is then decided by the Jacobi route.
 __device__ __forceinline__ bool polar_newton3(const float* a, float* q, int& dsign, float thr)
 {
     float X[9], C[9];
@@ -799,12 +871,7 @@ __device__ __forceinline__ bool polar_newton3(const float* a, float* q, int& dsi
     float cf2 = 0.f;
 #pragma unroll
     for (int k = 0; k < 9; ++k) cf2 += C[k] * C[k];
-    const float adet = det < 0.f ? -det : det;
-    // strict: det = 0 with a zero cofactor matrix (rank <= 1, the zero matrix)
-    // takes the Jacobi route too, and so does a matrix whose squared cofactor
-    // norm is not a normal float with room (|A| below ~1e-9: the first step's
-    // products would underflow; Jacobi rescales by a power of two); also NaN
-    if (!(cf2 >= 1e-36f) || !(adet > thr * num<float>::sqrt_(cf2))) return false;
+    if (!newton3_certain(X, C, det, cf2, thr)) return false;
     dsign = det >= 0.f ? 1 : -1;
     bool scaled = true;
 #pragma unroll 1

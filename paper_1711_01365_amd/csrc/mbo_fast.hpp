@@ -48,16 +48,17 @@ __device__ __forceinline__ int band_slot(int kx, int L, int c, int W)
 }
 
 // ---------------------------------------------------------------------------
-// Float n = 3 Newton polar iteration, split so that the workgroup can decide
-// which points it runs before iterating (same arithmetic as polar_newton3).
+// Float n = 3 Newton polar iteration (Higham, 1986), split so that the
+// workgroup can decide which points it runs before iterating: the steps of
+// polar_newton3 with hardware reciprocals.
 // ---------------------------------------------------------------------------
 struct Newton3 {
     float X[9], C[9];
     float det, cf2;
 };
 
-// True when 1/|A^{-1}|_F > thr (then sigma_min > thr) and the cofactor norm is
-// a normal float with room; otherwise the point goes to the Jacobi route.
+// True when the float test of newton3_certain proves sigma_min > thr;
+// otherwise the point goes to the Jacobi route.
 __device__ __forceinline__ bool newton3_init(const float* a, Newton3& s, float thr)
 {
 #pragma unroll
@@ -67,8 +68,7 @@ __device__ __forceinline__ bool newton3_init(const float* a, Newton3& s, float t
     s.cf2 = 0.f;
 #pragma unroll
     for (int k = 0; k < 9; ++k) s.cf2 += s.C[k] * s.C[k];
-    const float adet = s.det < 0.f ? -s.det : s.det;
-    return (s.cf2 >= 1e-36f) && (adet > thr * num<float>::sqrt_(s.cf2));
+    return newton3_certain(s.X, s.C, s.det, s.cf2, thr);
 }
 
 __device__ __forceinline__ void newton3_run(Newton3& s, float* q, int& dsign)
@@ -87,11 +87,14 @@ __device__ __forceinline__ void newton3_run(Newton3& s, float* q, int& dsign)
         float xf2 = 0.f;
 #pragma unroll
         for (int k = 0; k < 9; ++k) xf2 += s.X[k] * s.X[k];
-        const float idet = 1.0f / s.det;
+        // hardware reciprocal (about 1 ulp): the iteration corrects its own
+        // rounding, and a relative error of one ulp in the step's two scalar
+        // factors stays below the float rounding of the result
+        const float idet = num<float>::rcp(s.det);
         const float zeta = scaled ? num<float>::sqrt_(num<float>::sqrt_(s.cf2) * (idet < 0.f ? -idet : idet) *
                                                       num<float>::rsq(xf2))
                                   : 1.0f;
-        const float cx = 0.5f * zeta, cc = 0.5f * idet / zeta;
+        const float cx = 0.5f * zeta, cc = 0.5f * idet * num<float>::rcp(zeta);
         float diff = 0.f;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {

@@ -36,7 +36,7 @@ EXPORTS = ("mbo_plan", "mbo_plan_destroy", "mbo_plan_set_tau", "mbo_plan_set_str
            "mbo_surface_info",
            "mbo_surface_points", "mbo_surface_diffuse", "mbo_surface_iterate", "mbo_surface_last_error",
            "mbo_surface_volume_weights", "mbo_surface_volume_select", "mbo_surface_iterate_volume",
-           "mbo_plan_set_path", "mbo_plan_path", "mbo_status_string", "mbo_last_error")
+           "mbo_plan_set_path", "mbo_plan_path", "mbo_last_project_counts", "mbo_status_string", "mbo_last_error")
 
 
 class FieldDesc(ctypes.Structure):
@@ -78,6 +78,7 @@ def load(path: str = LIB_PATH):
                                      ctypes.c_int, ctypes.c_double, ctypes.c_int, vp]
     lib.mbo_plan_tuning.argtypes = [vp, ctypes.c_int, ip, ip, ip, ip]
     lib.mbo_plan_set_path.argtypes = [vp, ctypes.c_int]
+    lib.mbo_last_project_counts.argtypes = [vp, i64p, i64p]
     lib.mbo_plan_path.argtypes = [vp, ctypes.c_int, ip, ip, ip]
     lib.mbo_plan_autotune.argtypes = [vp]
     lib.mbo_step.argtypes = [vp, vp, vp]
@@ -200,6 +201,14 @@ class Plan:
                                      ctypes.c_void_p(ds.data_ptr()) if ds is not None else None),
                self._h)
         return (A_out, ds) if det_sign else A_out
+
+    def last_project_counts(self):
+        """(points re-projected in double, points with NaN/Inf input) of the last project()."""
+        fb, bad = np.zeros(1, dtype=np.int64), np.zeros(1, dtype=np.int64)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        _check(self._lib.mbo_last_project_counts(self._h, fb.ctypes.data_as(i64p), bad.ctypes.data_as(i64p)),
+               self._h)
+        return int(fb[0]), int(bad[0])
 
     def step(self, A_prev, A_next=None):
         """A_next = P(e^{tau Delta} A_prev), asynchronous (no logs, no NaN check)."""

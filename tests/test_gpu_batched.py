@@ -162,3 +162,82 @@ def test_batched_configuration(torch_cuda):
         I = torch.eye(m.n, dtype=torch.float64, device="cuda")
         assert (M.transpose(1, 2).contiguous() @ M.contiguous() - I).abs().max().item() < 1e-5
     note("  %d of %d fields bitwise equal to their single runs" % (nbit, len(spec)))
+
+
+def _class_members():
+    """First member of every (n, N) class of the batched configuration."""
+    bw = inputs.BatchedWorkload()
+    first = {}
+    for i, m in enumerate(bw.members):
+        first.setdefault((m.n, m.grid[0]), i)
+    return bw, sorted(first.items())
+
+
+_BW, _CLASSES = _class_members()
+
+
+def _pm(A):
+    n = A.shape[0]
+    return np.moveaxis(A.reshape(n, n, -1), -1, 0)
+
+
+def _fp32_step_ok(err, gap, e_heat):
+    u32 = 2.0 ** -24
+    bound = np.maximum(1e-5, 4.0 * (e_heat + 8 * u32) / gap)
+    return bool(np.all(err <= bound)) and (not np.any(gap >= 0.1) or err[gap >= 0.1].max() <= 1e-5)
+
+
+@pytest.fixture(scope="module")
+def batched_config_plan(torch_cuda):
+    from paper_1711_01365_amd import mbo
+    spec = [(m.grid, m.n, m.tau) for m in _BW.members]
+    return mbo.BatchedPlan(spec, precision=F32, autotune=True)
+
+
+@pytest.mark.parametrize("cls,field", _CLASSES, ids=["n%d_%d" % c for c, _ in _CLASSES])
+def test_batched_configuration_class_against_oracle(torch_cuda, batched_config_plan, cls, field):
+    """One field of each (n, N) class of the batched configuration, at its real
+    size, inside the full 64-field FP32 plan: steps 1 and 2 against the FP64
+    oracle's steps from the same float input (step 2 from the oracle's own iterate
+    1), per point within the FP32 bound (1e-5 where sigma_{n-1} + sigma_n >= 0.1,
+    the first-order bound of the measured diffusion error elsewhere), and the
+    logged energy of the step equal to the oracle's within FP32 rounding."""
+    torch = torch_cuda
+    bp = batched_config_plan
+    m = _BW.members[field]
+    note("batched class n=%d N=%d: field %d, tau %.3g" % (cls[0], cls[1], field, m.tau))
+    base = [m2.field().astype(np.float32) for m2 in _BW.members]
+    start = m.field()
+    for step in (1, 2):
+        A32 = start.astype(np.float32)
+        A64 = A32.astype(np.float64)
+        fields = list(base)
+        fields[field] = A32
+        flat = bp.pack([torch.tensor(f, dtype=torch.float32, device="cuda") for f in fields])
+        Hg = bp.unpack(bp.diffuse(flat))[field].cpu().numpy().reshape(A64.shape)
+        Ht, _ = oracle.heat(A64.reshape((m.n * m.n,) + m.grid), m.tau, 2)
+        Ht = Ht.reshape(A64.shape)
+        e_heat = float(np.abs(Hg - Ht).max())
+        r = bp.iterate(flat, 1)
+        out = bp.unpack(flat)[field].cpu().numpy().reshape(A64.shape)
+        ro = oracle.iterate(A64, m.tau, 1)
+        Hp = _pm(Ht)
+        s = np.linalg.svd(Hp, compute_uv=False)
+        gap = s[:, -2] + s[:, -1]
+        err = np.abs(_pm(out - ro["A"])).max(axis=(1, 2))
+        # det-sign ties: where the FP32 and FP64 runs land in different components
+        # of O(n) the diffused matrix must be within what the FP32 diffusion error
+        # can move det across zero, |d det| <= |cof H|_F |dH|_F, doubled (the plan
+        # is plain FP32: such points get no double re-projection)
+        cof = np.sqrt(sum(np.prod(np.delete(s, i, axis=1), axis=1) ** 2 for i in range(m.n)))
+        tie_bound = 2.0 * m.n * (e_heat + 8 * 2.0 ** -24) * cof
+        mism = (np.linalg.det(_pm(out)) >= 0) != (np.linalg.det(_pm(ro["A"])) >= 0)
+        note("  step %d: diffusion err %.3g, step err max %.3g (%.3g off the %d det-sign ties), "
+             "well-conditioned %d pts max %.3g" % (
+                 step, e_heat, err.max(), err[~mism].max(), int(mism.sum()), int((gap >= 0.1).sum()),
+                 err[gap >= 0.1].max() if (gap >= 0.1).any() else 0))
+        assert e_heat <= 2e-6
+        assert np.all(np.abs(np.linalg.det(Hp[mism])) <= tie_bound[mism])
+        assert _fp32_step_ok(err[~mism], gap[~mism], e_heat)
+        assert abs(r["energy"][field][1] - ro["energy"][1]) <= 1e-5 * abs(ro["energy"][1])
+        start = ro["A"]

@@ -93,7 +93,7 @@ def test_examples_f64_match_oracle(torch_cuda, name):
     logs = plan.iterate(X, K)
     err = float(np.abs(X.cpu().numpy().reshape(A0.shape) - ref["A"]).max())
     note(name, "max |A - A_oracle| = %.3g" % err)
-    assert err <= 1e-8
+    assert err <= 1e-12
     assert np.array_equal(logs["flips"][0], ref["flips"])
     assert np.abs(logs["energy"][0] - ref["energy"]).max() <= 1e-9 * np.abs(ref["energy"]).max()
     plan.close()

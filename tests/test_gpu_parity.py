@@ -4,7 +4,10 @@ Tolerances: FP64 path <= 1e-12 max-abs on field entries; FP32 path <= 1e-5 on
 points whose projection is well conditioned (sigma_{n-1} + sigma_n >= 0.1, the
 polar factor's absolute condition number being 2 / (sigma_{n-1} + sigma_n));
 integer diagnostics (det signs, flip counts, iteration counts) identical, a det
-mismatch being allowed only where |det| of the diffused matrix is below 1e-12.
+mismatch being allowed only at a tie: where |det| of the diffused matrix lies
+within the perturbation the path's own diffusion error can make (1e-12 for the
+FP64 path; for the FP32 path first order in the measured diffusion error,
+|d det| <= |cof|_F |dA|_F).
 """
 import sys
 
@@ -110,6 +113,60 @@ def test_project_f32(torch_cuda, n, prec):
         small = s[:, -1] < 1e-4
         if small.any():
             assert err[small].max() <= 1e-5
+
+
+def svd_field(n, grid, seed):
+    """U diag(s) V^t per point, U and V Haar in O(n), with the smallest singular
+    value log-uniform in [1e-7, 1e-2] (about two thirds of the points below the
+    fallback threshold 1e-3); on every other point the second smallest is small too
+    (log-uniform between the smallest and 1e-3), so that the polar factor is ill
+    conditioned there (condition 2 / (sigma_{n-1} + sigma_n))."""
+    rng = np.random.default_rng(seed)
+    P = int(np.prod(grid))
+
+    def haar(k):
+        Q, R = np.linalg.qr(rng.standard_normal((k, n, n)))
+        return Q * np.sign(np.diagonal(R, axis1=1, axis2=2))[:, None, :]
+    s = rng.uniform(0.3, 1.5, size=(P, n))
+    smin = 10.0 ** rng.uniform(-7, -2, size=P)
+    s[:, -1] = smin
+    if n >= 3:
+        both = np.arange(P) % 2 == 1
+        s[both, -2] = smin[both] * 10.0 ** rng.uniform(0, np.log10(1e-3 / smin[both]).clip(0))
+    M = haar(P) @ (s[:, :, None] * haar(P))
+    return np.ascontiguousarray(np.moveaxis(M.reshape(P, n * n), 0, -1)).reshape((n, n) + tuple(grid))
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_project_fallback_targeted(torch_cuda, n):
+    """MBO_F32_F64FALLBACK on matrices built with sigma_min spread over [1e-7, 1e-2]:
+    every point below the threshold (sigma_min of the float input, computed in
+    double) is counted as a fallback, no other, and those points come back at the
+    double result rounded to float (<= 1e-6 from the FP64 oracle's projection of
+    the same float input); for n >= 3, where the field also holds ill-conditioned
+    polar factors, the plain FP32 projection is measurably worse there."""
+    torch = torch_cuda
+    grid = (64, 64)
+    A32 = svd_field(n, grid, 1200 + n).astype(np.float32)
+    A64 = A32.astype(np.float64)
+    s = np.linalg.svd(point_major(A64), compute_uv=False)
+    below = s[:, -1] < 1e-3
+    note("fallback targeted n=%d: %d of %d points below 1e-3" % (n, int(below.sum()), below.size))
+    Qo = oracle.project(A64)[0]
+    P = plan(grid, n, 1e-3, FB)
+    Q = P.project(to_dev(torch, A32, torch.float32)).cpu().numpy()
+    fb, bad = P.last_project_counts()
+    assert bad == 0
+    assert fb == int(below.sum())
+    err = np.abs(point_major(Q - Qo)).max(axis=(1, 2))
+    note("  fallback points: max err %.3g (n=%d)" % (err[below].max(), n))
+    assert err[below].max() <= 1e-6
+    if n >= 3:
+        P32 = plan(grid, n, 1e-3, F32)
+        Q32 = P32.project(to_dev(torch, A32, torch.float32)).cpu().numpy()
+        e32 = np.abs(point_major(Q32 - Qo)).max(axis=(1, 2))
+        note("  plain FP32 on the same points: max err %.3g" % e32[below].max())
+        assert e32[below].max() > 1e-5
 
 
 def test_project_singular_and_special_inputs(torch_cuda):
@@ -668,7 +725,23 @@ def test_bench_configuration_properties(torch_cuda):
     note("bench config step 200: diffusion err %.3g, step err max %.3g, well-cond (%d pts) %.3g"
          % (e_heat, err.max(), int((gap >= 0.1).sum()), err[gap >= 0.1].max() if (gap >= 0.1).any() else 0))
     assert fp32_step_ok(err, gap, e_heat)
-    assert abs(int(r2["flips"][0][0]) - int(ro["flips"][0])) <= 2
+    # det signs point by point: a point whose sign differs from the oracle's must
+    # be a tie, |det H A_199| within what the FP32 diffusion error can move it
+    # (first order: |d det| <= |cof|_F |dA|_F <= |cof|_F * 3 e_heat, doubled)
+    sg = np.linalg.det(point_major(t.cpu().numpy()).astype(np.float64)) >= 0
+    so = np.linalg.det(point_major(ro["A"])) >= 0
+    Hp = point_major(Ht)
+    dets = np.linalg.det(Hp)
+    cof = np.linalg.norm(np.stack([np.cross(Hp[:, 1], Hp[:, 2]), np.cross(Hp[:, 2], Hp[:, 0]),
+                                   np.cross(Hp[:, 0], Hp[:, 1])], axis=1), axis=(1, 2))
+    tie_bound = 2.0 * 3.0 * (e_heat + 8 * 2.0 ** -24) * cof
+    mism = np.nonzero(sg != so)[0]
+    note("bench config step 200: flips %d (oracle %d), det-sign mismatches %d at %s, |det H A| there %s, "
+         "tie bounds %s" % (int(r2["flips"][0][0]), int(ro["flips"][0]), mism.size, list(mism[:8]),
+                            list(np.abs(dets[mism][:8])), list(tie_bound[mism][:8])))
+    assert np.all(np.abs(dets[mism]) <= tie_bound[mism])
+    # every flip the two runs count differently is one of those ties
+    assert abs(int(r2["flips"][0][0]) - int(ro["flips"][0])) <= mism.size
     assert abs(r2["energy"][0][1] - ro["energy"][1]) <= 1e-5 * abs(ro["energy"][1])
 
 

@@ -310,7 +310,10 @@ def test_iterate_volume_star_defect(torch_cuda, prec):
     slack = 1e-12 if prec == "f64" else 1e-5
     assert np.all(np.diff(E) <= slack * np.abs(E[:-1]))
     ref = oracle.iterate_volume(A0, tau, K)
-    assert np.abs(E - ref["energy"]).max() <= 1e-3 * np.abs(ref["energy"]).max()
+    # double: the states agree to rounding, so do the energies; float: the FP32
+    # iterates move the energy by its rounding-level perturbations only
+    rel = 1e-9 if prec == "f64" else 1e-3
+    assert np.abs(E - ref["energy"]).max() <= rel * np.abs(ref["energy"]).max()
     note(prec, "E_0 %.6g E_K %.6g (oracle %.6g)" % (E[0], E[-1], ref["energy"][-1]))
     plan.close()
 
