@@ -486,24 +486,48 @@ def run_batched(precision, autotune, steps):
             "ms_per_run": 1000.0 * sec / steps, "plan_s": plan_s, "autotune": bool(autotune)}
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """The FP64 oracle on the first iterations of the same workload."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, runs=3, iters=20, iters_1t=3):
+    """The FP64 oracle on the host's cores: the median of `runs` runs of the
+    first `iters` iterations of the same workload with every OpenMP thread, and
+    one run of `iters_1t` iterations on one thread (about 15 s in all)."""
     import oracle
     A0 = w.field()
-    t0 = time.perf_counter()
-    oracle.iterate(A0, w.tau, 1)
-    t1 = time.perf_counter() - t0
-    iters = int(max(2, min(50, budget_s / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    oracle.iterate(A0, w.tau, iters)
-    sec = time.perf_counter() - t0
+    oracle.iterate(A0, w.tau, 1)  # builds and loads the library, warms the pages
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        oracle.iterate(A0, w.tau, iters)
+        times.append(time.perf_counter() - t0)
+    sec = sorted(times)[len(times) // 2]
+    threads = oracle.num_threads()
+    one = None
+    if iters_1t > 0:
+        oracle.set_num_threads(1)
+        t0 = time.perf_counter()
+        oracle.iterate(A0, w.tau, iters_1t)
+        one = w.points * iters_1t / (time.perf_counter() - t0)
+        oracle.set_num_threads(threads)
     return {
         "value": w.points * iters / sec,
         "unit": "point-iterations/s",
-        "cores": oracle.num_threads(),
+        "cores": threads,
         "kind": "oracle",
-        "sample": "first %d of the %d iterations of the same 512x512 n=3 workload, FP64 C oracle "
-                  "(%.1f s)" % (iters, w.iters, sec),
+        "sample": "median of %d runs of the first %d of the %d iterations of the same 512x512 n=3 workload, "
+                  "FP64 C oracle on %d threads (%.2f s each); one thread: %d iterations"
+                  % (runs, iters, w.iters, threads, sec, iters_1t),
+        "value_1_thread": one,
+        "cpu_model": cpu_model(),
     }
 
 

@@ -1314,10 +1314,13 @@ int orc_surface_iterate_volume(int64_t m, const double* xq, const double* xc, co
     return rc;
 }
 
-/* Number of threads the OpenMP loops above use (1 without OpenMP). */
+/* Number of threads the OpenMP loops above use (1 without OpenMP), and its
+ * setter for the loops that follow (timing on a chosen number of threads). */
 #ifdef _OPENMP
 #include <omp.h>
 int orc_num_threads(void) { return omp_get_max_threads(); }
+void orc_set_num_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }
 #else
 int orc_num_threads(void) { return 1; }
+void orc_set_num_threads(int t) { (void)t; }
 #endif

@@ -56,7 +56,8 @@ class UnrolledMBO(torch.autograd.Function):
         G = grad_out.detach().to(plan.dtype).contiguous().clone()
         # dL/dtau accumulates on the device; one read at the end
         dtau = torch.zeros(plan.batch, dtype=torch.float64, device=G.device)
-        for j in reversed(range(len(ctx.ckpts))):
+        # K = 0: A_K = A_0, so dL/dA_0 = G and dL/dtau = 0 (no step to pull back through)
+        for j in reversed(range(len(ctx.ckpts) if K > 0 else 0)):
             s0, s1 = j * c, min(j * c + c, K)
             prev = [ctx.ckpts[j]]  # A_{s-1} for s = s0+1 .. s1, recomputed
             for _ in range(s0 + 1, s1):

@@ -35,6 +35,24 @@ int ilog2(int64_t v)
 
 bool is_pow2(int64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
 
+// The integer a C caller passed for an enum parameter.  Read as bytes: a value
+// outside the enumerators may arrive, and reading it as the enum type would be
+// undefined in C++ before it can be rejected.
+template <typename E>
+int raw_enum(const E& e)
+{
+    int v = 0;
+    static_assert(sizeof(E) == sizeof(int), "enums of the ABI are int-sized");
+    std::memcpy(&v, &e, sizeof v);
+    return v;
+}
+
+bool valid_precision(const mbo_precision& prec)
+{
+    const int v = raw_enum(prec);
+    return v == MBO_F64 || v == MBO_F32 || v == MBO_F32_F64FALLBACK;
+}
+
 int lds_len(int L) { return (L - 1) + ((L - 1) >> 3) + 1; }  // lds_pad(L-1) + 1
 
 struct ColCfg {
@@ -2021,8 +2039,8 @@ mbo_status mbo_plan(mbo_plan_t* out, int d, const int64_t* N, int n, int64_t bat
     *out = nullptr;
     if (!N) return fail(nullptr, MBO_ERR_INVALID_ARG, "N is NULL");
     if (batch < 1) return fail(nullptr, MBO_ERR_INVALID_ARG, "batch must be >= 1");
-    if (prec != MBO_F64 && prec != MBO_F32 && prec != MBO_F32_F64FALLBACK)
-        return fail(nullptr, MBO_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
+    if (!valid_precision(prec))
+        return fail(nullptr, MBO_ERR_INVALID_ARG, "unknown precision %d", raw_enum(prec));
     const mbo_status cs = check_shape(d, N, n, tau);
     if (cs != MBO_OK) return cs;
 
@@ -2045,8 +2063,8 @@ mbo_status mbo_plan_batched(mbo_plan_t* out, int count, const mbo_field_desc* de
     if (!out) return fail(nullptr, MBO_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (count < 1 || !descs) return fail(nullptr, MBO_ERR_INVALID_ARG, "count < 1 or descs is NULL");
-    if (prec != MBO_F64 && prec != MBO_F32 && prec != MBO_F32_F64FALLBACK)
-        return fail(nullptr, MBO_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
+    if (!valid_precision(prec))
+        return fail(nullptr, MBO_ERR_INVALID_ARG, "unknown precision %d", raw_enum(prec));
     for (int f = 0; f < count; ++f) {
         const mbo_status cs = check_shape(descs[f].d, descs[f].N, descs[f].n, descs[f].tau);
         if (cs != MBO_OK) {
@@ -2172,14 +2190,15 @@ mbo_status mbo_plan_set_tau(mbo_plan_t p, double tau)
 mbo_status mbo_plan_set_path(mbo_plan_t p, mbo_path path)
 {
     if (!p) return MBO_ERR_INVALID_ARG;
-    if (path != MBO_PATH_GENERIC && path != MBO_PATH_FULL && path != MBO_PATH_BANDED)
-        return fail(p, MBO_ERR_INVALID_ARG, "unknown path %d", (int)path);
+    const int pv = raw_enum(path);
+    if (pv != MBO_PATH_GENERIC && pv != MBO_PATH_FULL && pv != MBO_PATH_BANDED)
+        return fail(p, MBO_ERR_INVALID_ARG, "unknown path %d", pv);
     HIP_TRY(p, hipSetDevice(p->device));
     HIP_TRY(p, hipStreamSynchronize(p->stream));
     drop_graph(p);
     std::vector<mbo_plan_t> plans = p->group ? p->members : std::vector<mbo_plan_t>(1, p);
     for (mbo_plan_t m : plans) {
-        m->path = (int)path;
+        m->path = pv;
         drop_logs(m);  // the heat pass's partial count may change
         config_fast(m);
         const mbo_status s = build_fast_tables(m);
@@ -2748,8 +2767,8 @@ mbo_status surface_create(mbo_surface_t* out, int kind, double radius, double dx
         return sfail(nullptr, MBO_ERR_INVALID_ARG, "radius, dx, tau must be finite and > 0, eps in (0, 0.5)");
     if (p < 1 || p > 8) return sfail(nullptr, MBO_ERR_INVALID_ARG, "p must be in [1, 8]");
     if (n < 1 || n > 4) return sfail(nullptr, MBO_ERR_INVALID_ARG, "n must be in [1, 4]");
-    if (prec != MBO_F64 && prec != MBO_F32 && prec != MBO_F32_F64FALLBACK)
-        return sfail(nullptr, MBO_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
+    if (!valid_precision(prec))
+        return sfail(nullptr, MBO_ERR_INVALID_ARG, "unknown precision %d", raw_enum(prec));
     mbo_surface_t s = new mbo_surface_s();
     auto bail = [&](mbo_status st) {
         g_plan_error = s->err;

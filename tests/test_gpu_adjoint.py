@@ -257,6 +257,20 @@ def test_unrolled_grad_f64_small(torch_cuda, n, grid, K, ck):
     assert e_a <= 1e-10 and e_t <= 1e-10
 
 
+def test_unrolled_grad_zero_steps(torch_cuda):
+    """K = 0: A_K = A_0, so the loss gradient in A_0 is A_0 - A_target itself and
+    the tau-gradient is exactly zero (the oracle's K = 0 run says the same)."""
+    torch = torch_cuda
+    n, grid, tau = 3, (16, 16), 2e-3
+    A0 = inputs.uniform_field(n, grid, 130)
+    T = oracle.project(inputs.normal_field(n, grid, 131))[0]
+    ref = oracle.unroll_grad(A0, T, tau, 0)
+    loss, gA, gt, _ = gpu_grad(torch, A0, T, tau, 0, 4, F64)
+    assert abs(loss - ref["loss"]) <= 1e-12 * ref["loss"]
+    assert np.array_equal(gA, A0 - T) and np.array_equal(ref["gA0"], A0 - T)
+    assert gt == 0.0 and ref["gtau"] == 0.0
+
+
 def test_unrolled_grad_checkpoint_invariant(torch_cuda):
     """Recomputation reproduces the forward iterates: every checkpoint interval
     gives the same gradient."""

@@ -491,6 +491,44 @@ def test_iterate_zero_and_rank_one_fields(torch_cuda, prec):
         P.close()
 
 
+@pytest.mark.parametrize("path", [0, 1, 2])
+@pytest.mark.parametrize("prec", [F64, FB])
+def test_iterate_nonfinite_is_reported(torch_cuda, path, prec):
+    """A NaN in the field reaches the projections of the first iteration (the
+    diffusion spreads it); mbo_iterate returns MBO_ERR_NONFINITE after the run,
+    on every kernel path, and a finite field on the same plan runs clean after it."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    grid, n = (64, 64), 3
+    A = inputs.uniform_field(n, grid, 1300)
+    A[1, 2, 5, 7] = np.nan
+    dt = torch.float64 if prec == F64 else torch.float32
+    P = plan(grid, n, 1e-3, prec)
+    P.set_path(path)
+    with pytest.raises(mbo.MboError) as e:
+        P.iterate(to_dev(torch, A, dt), 3)
+    assert e.value.status == 5
+    B = inputs.uniform_field(n, grid, 1301)
+    P.iterate(to_dev(torch, B, dt), 3)
+
+
+def test_plan_allocation_failure_is_reported(torch_cuda):
+    """A plan whose workspace exceeds the device memory (2048^2, n = 4, 100000
+    fields: ~5e16 bytes of spectra) is refused with MBO_ERR_ALLOC, no plan is
+    returned, and the device is usable afterwards."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    with pytest.raises(mbo.MboError) as e:
+        mbo.Plan((2048, 2048), 4, 1e-3, precision=F32, batch=100000)
+    assert e.value.status == 3
+    note("allocation failure: %s" % e.value)
+    P = plan((32, 32), 2, 1e-3, F64)
+    A = inputs.uniform_field(2, (32, 32), 1302)
+    t = to_dev(torch, A, torch.float64)
+    P.iterate(t, 2)
+    assert np.abs(t.cpu().numpy() - oracle.iterate(A, 1e-3, 2)["A"]).max() <= 1e-12
+
+
 def test_iterate_tolerance_stop_matches_oracle(torch_cuda):
     torch = torch_cuda
     tau = 2e-3
