@@ -543,6 +543,9 @@ def main():
                          "batched, volume-preserving, paper examples, relaxed flows, sphere, "
                          "volume-preserving sphere, adjoint)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--legs", default="control,3d,batched,volume,examples,relaxed,adjoint",
+                    help="legs beside the main line (comma list of control, 3d, batched, volume, "
+                         "examples, relaxed, adjoint, sphere)")
     ap.add_argument("--volume-only", action="store_true",
                     help="only the volume-preserving legs (for profiling them)")
     ap.add_argument("--peanut", action="store_true",
@@ -631,32 +634,39 @@ def main():
         out["f64"] = {"value": f64["value"], "ms_per_step": f64["ms_per_step"],
                       "kernels_us": {"row_pass": f64["row_us"], "heat_pass": f64["heat_us"]},
                       "f32_over_f64": main_run["value"] / f64["value"]}
-    if not args.no_extra:
+    legs = set() if args.no_extra else set(x.strip() for x in args.legs.split(",") if x.strip())
+    if "control" in legs:
         out["control_2048"] = run_control_2048()
         log("2048^2 control: %.3e point-iter/s, row %.1f us (%.0f GB/s), heat %.1f us (%.0f GB/s)"
             % (out["control_2048"]["value"], out["control_2048"]["row_us"], out["control_2048"]["row_GBps"],
                out["control_2048"]["heat_us"], out["control_2048"]["heat_GBps"]))
+    if "3d" in legs:
         out["config_3d"] = run_3d(3, 1)
         log("3-D n=3 128^3 fp32+fallback: %.3e point-iter/s" % out["config_3d"]["value"])
+    if "batched" in legs:
         out["batched"] = {"f32_autotuned": run_batched(mbo.F32, True, 3),
                           "f32_fixed_rules": run_batched(mbo.F32, False, 3),
                           "f64_autotuned": run_batched(mbo.F64, True, 2)}
         log("batched 64 fields: f32 tuned %.3e, f32 rules %.3e, f64 tuned %.3e point-iter/s"
             % (out["batched"]["f32_autotuned"]["value"], out["batched"]["f32_fixed_rules"]["value"],
                out["batched"]["f64_autotuned"]["value"]))
+    if "volume" in legs:
         out["volume_preserving"] = {"n3_512x512_haar": run_volume(inputs.VOLUME_HAAR_512, 3, 1),
                                     "n2_1024x1024_star": run_volume(inputs.VOLUME_STAR_1024, 3, 1)}
         for k, r in out["volume_preserving"].items():
             log("volume-preserving %s: %.3e point-iter/s, %.1f us/iteration (plain %.1f us)"
                 % (k, r["value"], r["us_per_iteration"], r["plain_mbo_us_per_iteration"]))
+    if "examples" in legs:
         out["paper_examples"] = run_examples(3)
         for k, r in out["paper_examples"].items():
             log("paper example %s: %.3e point-iter/s, %.1f us/iteration, end: %d SO(2) points, index %s"
                 % (k, r["value"], r["us_per_iteration"], r["so2_points_end"], r["index_end"]))
+    if "relaxed" in legs:
         out["relaxed_flows"] = run_relaxed(3)
         for k, r in out["relaxed_flows"].items():
             log("relaxed flow %s: %.3e point-steps/s, %.1f us/step, E %.4g -> %.4g"
                 % (k, r["value"], r["us_per_step"], r["energy_first_last"][0], r["energy_first_last"][1]))
+    if "sphere" in legs:
         out["sphere"] = run_surface(1)
         for k, r in out["sphere"].items():
             log("sphere %s: %.3e sample-steps/s, %.1f us/step, diffuse %.1f us, m=%d grid=%d^3, SO-(3) %s"
@@ -671,6 +681,7 @@ def main():
             r = out["peanut"]
             log("peanut: %.3e sample-steps/s, %.1f us/step, m=%d, set-up %.1f s"
                 % (r["value"], r["us_per_step"], r["samples"], r["setup_s"]))
+    if "adjoint" in legs:
         out["adjoint"] = {"f32_f64fallback": run_adjoint(mbo.F32_F64FALLBACK, 2),
                           "f64": run_adjoint(mbo.F64, 2)}
         log("adjoint K=50 256^2: fp32+fb fwd %.1f ms bwd %.1f ms, fp64 fwd %.1f ms bwd %.1f ms"

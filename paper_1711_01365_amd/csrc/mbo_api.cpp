@@ -80,6 +80,12 @@ struct mbo_plan_s {
     int64_t npts = 1;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;
+    // a batched plan: side streams (default priority) its field classes run on
+    // concurrently, and the events of the fork and of each class's end
+    std::vector<hipStream_t> side;
+    std::vector<int> side_of;       // stream of each member class
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;  // per side stream
     size_t lds_max = 65536;
 
     void* Z = nullptr;
@@ -275,6 +281,9 @@ void destroy(mbo_plan_t p)
     free_dev(p->pen_sum);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     if (p->cap) (void)hipStreamDestroy(p->cap);
+    for (hipStream_t q : p->side) (void)hipStreamDestroy(q);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    for (hipEvent_t e : p->ev_join) (void)hipEventDestroy(e);
     delete p;
 }
 
@@ -404,7 +413,10 @@ void config_fast(mbo_plan_t p)
     p->band_W = (int)p->N[p->d - 1];
     if (p->path == MBO_PATH_GENERIC || p->d != 2) return;
     const int64_t N0 = p->N[0], N1 = p->N[1];
-    if (N1 > 512 || N0 < 64 || N0 > 2048) return;
+    if (N1 < 8 || N1 > 2048 || N0 < 64 || N0 > 2048) return;
+    // the row pass keeps a workgroup's lines (512 points, or one row) in LDS
+    // beside its static arrays (the helper's queue, at most 4 KiB)
+    if (row_fast_lds_bytes(p->pk, p->n, ilog2((int)N1)) + 4352 > p->lds_max) return;
     if (p->path == MBO_PATH_BANDED) {
         std::vector<double> taus = p->per_field_tau ? p->taus : std::vector<double>(1, p->tau);
         const double eta = p->pk == 1 ? 1e-12 : 1e-20;
@@ -664,8 +676,14 @@ int energy_partials(mbo_plan_t p)
     return (int)(p->heat.grid.x * ((bx % 64) ? 1 : bx / 64));  // = col_args(p, p->heat).nwg
 }
 
-// Workgroups of the band-limited row pass per field (512 points each).
-int fast_row_groups(mbo_plan_t p) { return (int)((p->npts + 511) / 512); }
+// Workgroups of the band-limited row pass per field (512 points, or one row
+// of 1024 or 2048 points, each).
+int fast_row_groups(mbo_plan_t p)
+{
+    const int64_t rows = p->npts / p->N[1];
+    const int rpw = row_fast_rows_per_group(ilog2((int)p->N[1]));
+    return (int)((rows + rpw - 1) / rpw);
+}
 
 // Grid of the band-limited heat pass and its energy partials per field and
 // iterate (one per wave).
@@ -1452,6 +1470,39 @@ mbo_status energy_into(mbo_plan_t p, const void* A, double* E, const std::vector
     return MBO_OK;
 }
 
+// Side streams of a batched plan: as many as the device runs queues at once
+// (four), each class dealt to the least loaded one, largest classes first
+// (estimated work: fields x points x n^2 x log2 of the points).
+mbo_status setup_side_streams(mbo_plan_t g)
+{
+    const int ns = std::min<int>(4, (int)g->members.size());
+    for (int i = 0; i < ns; ++i) {
+        hipStream_t q = nullptr;
+        HIP_TRY(g, hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+        g->side.push_back(q);
+        hipEvent_t e = nullptr;
+        HIP_TRY(g, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        g->ev_join.push_back(e);
+    }
+    HIP_TRY(g, hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
+    std::vector<std::pair<double, int>> work;
+    for (size_t m = 0; m < g->members.size(); ++m) {
+        const mbo_plan_t c = g->members[m];
+        work.emplace_back((double)c->batch * (double)c->npts * c->n * c->n * std::log2((double)c->npts), (int)m);
+    }
+    std::sort(work.begin(), work.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+        return a.first > b.first;
+    });
+    std::vector<double> load((size_t)ns, 0.0);
+    g->side_of.assign(g->members.size(), 0);
+    for (const auto& w : work) {
+        const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        g->side_of[(size_t)w.second] = q;
+        load[(size_t)q] += w.first;
+    }
+    return MBO_OK;
+}
+
 std::vector<int> member_fields(mbo_plan_t g, int mi)
 {
     std::vector<int> map;
@@ -2129,6 +2180,8 @@ mbo_status mbo_plan_batched(mbo_plan_t* out, int count, const mbo_field_desc* de
         if (st == MBO_OK && autotune) st = autotune_plan(m);
         if (st != MBO_OK) return bail(st, "field class " + std::to_string(c) + ": " + m->err);
     }
+    const mbo_status ss = setup_side_streams(g);
+    if (ss != MBO_OK) return bail(ss, g->err);
     *out = g;
     return MBO_OK;
 }
@@ -2483,41 +2536,54 @@ mbo_status mbo_iterate(mbo_plan_t p, void* A, int max_iter, double tol, int* ite
         p->ev_K = K;
         drop_graph(p);
     }
-    auto enqueue_all = [&](hipStream_t st) -> hipError_t {
-        if (!p->group) return enqueue_iterate(p, A, K, tol, want_energy, st);
-        for (mbo_plan_t m : p->members) {
-            hipError_t e = enqueue_iterate(m, A, K, tol, want_energy, st);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
-    };
     const int key = (tol > 0.0 ? 1 : 0) | (want_energy ? 2 : 0) | (p->timing ? 4 : 0);
-    if (use_graphs() && !p->timing) {
-        if (!(p->gexec && p->g_A == A && p->g_K == K && p->g_key == key && p->g_tol == tol)) {
-            drop_graph(p);
-            hipGraph_t g = nullptr;
-            HIP_TRY(p, hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
-            hipError_t e = enqueue_all(p->cap);
-            hipError_t e2 = hipStreamEndCapture(p->cap, &g);
-            if (e != hipSuccess || e2 != hipSuccess) {
-                if (g) (void)hipGraphDestroy(g);
-                return fail(p, MBO_ERR_HIP, "graph capture failed: %s",
-                            hipGetErrorString(e != hipSuccess ? e : e2));
-            }
-            hipError_t e3 = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e3 != hipSuccess) {
-                p->gexec = nullptr;
-                return fail(p, MBO_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e3));
-            }
-            p->g_A = A;
-            p->g_K = K;
-            p->g_key = key;
-            p->g_tol = tol;
+    // the iteration of plan q captured into its own graph (re-captured when the
+    // field pointer, K, tol or the logs asked for change)
+    auto ensure_graph = [&](mbo_plan_t q) -> mbo_status {
+        if (q->gexec && q->g_A == A && q->g_K == K && q->g_key == key && q->g_tol == tol) return MBO_OK;
+        drop_graph(q);
+        hipGraph_t g = nullptr;
+        HIP_TRY(q, hipStreamBeginCapture(q->cap, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_iterate(q, A, K, tol, want_energy, q->cap);
+        hipError_t e2 = hipStreamEndCapture(q->cap, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(q, MBO_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
         }
-        HIP_TRY(p, hipGraphLaunch(p->gexec, p->stream));
+        hipError_t e3 = hipGraphInstantiate(&q->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) {
+            q->gexec = nullptr;
+            return fail(q, MBO_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e3));
+        }
+        q->g_A = A;
+        q->g_K = K;
+        q->g_key = key;
+        q->g_tol = tol;
+        return MBO_OK;
+    };
+    if (use_graphs() && !p->timing) {
+        if (!p->group) {
+            if ((s = ensure_graph(p)) != MBO_OK) return s;
+            HIP_TRY(p, hipGraphLaunch(p->gexec, p->stream));
+        } else {
+            // the field classes are independent: each runs its own graph on a
+            // side stream, forked from and joined back into the plan's stream
+            for (mbo_plan_t m : p->members)
+                if ((s = ensure_graph(m)) != MBO_OK) return fail(p, s, "%s", m->err.c_str());
+            HIP_TRY(p, hipEventRecord(p->ev_fork, p->stream));
+            for (hipStream_t q : p->side) HIP_TRY(p, hipStreamWaitEvent(q, p->ev_fork, 0));
+            for (size_t mi = 0; mi < p->members.size(); ++mi)
+                HIP_TRY(p, hipGraphLaunch(p->members[mi]->gexec, p->side[(size_t)p->side_of[mi]]));
+            for (size_t q = 0; q < p->side.size(); ++q) {
+                HIP_TRY(p, hipEventRecord(p->ev_join[q], p->side[q]));
+                HIP_TRY(p, hipStreamWaitEvent(p->stream, p->ev_join[q], 0));
+            }
+        }
+    } else if (!p->group) {
+        HIP_TRY(p, enqueue_iterate(p, A, K, tol, want_energy, p->stream));
     } else {
-        HIP_TRY(p, enqueue_all(p->stream));
+        for (mbo_plan_t m : p->members) HIP_TRY(p, enqueue_iterate(m, A, K, tol, want_energy, p->stream));
     }
 
     // one copy of the logs at the end

@@ -15,11 +15,13 @@
 // the column pass transforms only those W columns.  With c >= N/2 nothing is
 // dropped and W = N.
 //
-//   row_fast   one workgroup owns 512 points (512/L whole rows, L <= 512): the
-//              line groups of its packed planes load their kept modes straight
-//              into the FFT register layout (lane t holds x[t + e L/8]),
-//              inverse-FFT inside one wave and leave the lines in LDS; one
-//              thread per point projects (Lemma 1.1) with the det-sign,
+//   row_fast   one workgroup owns 512 points (512/L whole rows) or, for rows of
+//              1024 and 2048 points, one row: the line groups of its packed
+//              planes load their kept modes straight into the FFT register
+//              layout (lane t holds x[t + e L/8]), inverse-FFT (inside one wave
+//              for L <= 512, with workgroup exchanges and in rounds of lines
+//              beyond) and leave the lines in LDS; 512 threads, one to four
+//              points each, project (Lemma 1.1) with the det-sign,
 //              fallback, non-finite and change diagnostics; the line groups
 //              forward-FFT and store the kept modes.  Float plans with n = 3
 //              run the Newton polar iteration on every point that is certainly
@@ -114,43 +116,48 @@ __device__ __forceinline__ void newton3_run(Newton3& s, float* q, int& dsign)
 // Row pass
 // ---------------------------------------------------------------------------
 
-constexpr int FAST_POINTS = 512;  // points per row-pass workgroup
-
-template <typename T, int n>
-constexpr bool row_fast_helper() { return sizeof(T) == 4 && n == 3; }
-
-template <typename T, int n>
-constexpr int row_fast_threads() { return FAST_POINTS + (row_fast_helper<T, n>() ? 64 : 0); }
-
-// LDS bytes of a row-pass workgroup: every packed line of its rows, re and im.
+// Shape of a row-pass workgroup: 512 points (512/L rows) for L <= 512, one row
+// of L points otherwise; 512 projection threads (PPT points each); the line
+// groups of L/8 threads run in ROUNDS rounds of G lines over NT threads; float
+// n = 3 adds a helper wave (threads NT .. NT + 63).
 template <typename T, int n, int LOG2L>
-constexpr size_t row_fast_lds()
-{
-    return (size_t)((n * n + 1) / 2) * (FAST_POINTS >> LOG2L) * ((1 << LOG2L) + (1 << LOG2L) / 8) * 2 * sizeof(T);
-}
-
-// waves per SIMD the instance is compiled for (two workgroups per CU)
-template <typename T, int n>
-constexpr int row_fast_waves() { return row_fast_helper<T, n>() ? 5 : 4; }
+struct RowFastShape {
+    static constexpr int L = 1 << LOG2L;
+    static constexpr int Tn = L / 8;
+    static constexpr int NN = n * n;
+    static constexpr int PL = (NN + 1) / 2;
+    static constexpr int RPW = L >= 512 ? 1 : 512 / L;
+    static constexpr int P = RPW * L;
+    static constexpr int PPT = P / 512;
+    static constexpr int LINES = RPW * PL;
+    static constexpr bool WAVE_LINE = LOG2L <= 9;
+    static constexpr bool HELPER = sizeof(T) == 4 && n == 3;
+    static constexpr int NTMAX = 1024 - (HELPER ? 64 : 0);
+    static constexpr int NT_LINES = LINES * Tn < NTMAX / Tn * Tn ? LINES * Tn : NTMAX / Tn * Tn;
+    static constexpr int NT = WAVE_LINE ? 512 : (NT_LINES > 512 ? NT_LINES : 512);
+    static constexpr int G = NT / Tn;  // lines per round
+    static constexpr int ROUNDS = (LINES + G - 1) / G;
+    static constexpr int THREADS = NT + (HELPER ? 64 : 0);
+    static constexpr int LP = L + L / 8;  // padded LDS line
+    static constexpr size_t LDS = (size_t)LINES * LP * 2 * sizeof(T);
+    // waves per SIMD the instance is compiled for: two 512-point workgroups
+    // per CU for short rows, one long-row workgroup
+    static constexpr int WAVES = WAVE_LINE ? (HELPER ? 5 : 4) : (THREADS + 255) / 256;
+};
 
 template <typename T, int n, int LOG2L>
-__global__ void __launch_bounds__((row_fast_threads<T, n>()), (row_fast_waves<T, n>())) row_fast(const FastRowArgs a)
+__global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFastShape<T, n, LOG2L>::WAVES))
+    row_fast(const FastRowArgs a)
 {
-    constexpr int NN = n * n;
-    constexpr int PL = (NN + 1) / 2;
-    constexpr int L = 1 << LOG2L;
-    constexpr int Tn = L / 8;
-    constexpr int RPW = FAST_POINTS / L;  // rows per workgroup (L <= 512)
-    constexpr int LINES = RPW * PL;
-    constexpr int NFFT = LINES * Tn;      // threads of the line groups
-    constexpr int LP = L + L / 8;         // padded line length
-    constexpr bool HELPER = row_fast_helper<T, n>();
-    static_assert(LOG2L <= 9, "a line must fit in one wave");
+    typedef RowFastShape<T, n, LOG2L> S;
+    constexpr int NN = S::NN, PL = S::PL, L = S::L, Tn = S::Tn, RPW = S::RPW, LP = S::LP;
+    constexpr int G = S::G, ROUNDS = S::ROUNDS, NT = S::NT, PPT = S::PPT;
+    constexpr bool HELPER = S::HELPER;
     typedef typename cx<T>::type C;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lr = reinterpret_cast<T*>(smem_raw);
-    T* li = lr + (size_t)LINES * LP;
-    __shared__ unsigned short fq[HELPER ? FAST_POINTS : 1];
+    T* li = lr + (size_t)S::LINES * LP;
+    __shared__ unsigned short fq[HELPER ? S::P : 1];
     __shared__ int fq_n;
     __shared__ unsigned long long wg_cnt[2];
 
@@ -168,61 +175,84 @@ __global__ void __launch_bounds__((row_fast_threads<T, n>()), (row_fast_waves<T,
     C* Zb = reinterpret_cast<C*>(a.Z) + (size_t)b * PL * a.rows * W;
 
     // Every global load that does not depend on another is issued first (the
-    // kept modes, the twiddles, the previous det signs, the stop mark): at the
-    // start of a launch each round trip to memory is a cold miss, and none of
-    // them waits for another.
-    const int j = tid / Tn, t = tid - (tid / Tn) * Tn;
+    // kept modes of the first round of lines, the twiddles, the previous det
+    // signs, the stop mark): at the start of a launch each round trip to memory
+    // is a cold miss, and none of them waits for another.
+    const int g = tid / Tn, t = tid - (tid / Tn) * Tn;
     const int pt = lds_pad(t);
-    const bool fft_thread = tid < NFFT;
-    T r[8], im[8];
+    const bool fft_thread = tid < NT;
     Twiddles<T, LOG2L> tw;
-    if ((flags & RF_INVERSE) && fft_thread) {
-        const int rloc = j / PL, pl = j - (j / PL) * PL;
-        const bool live = row0 + rloc < a.rows;
-        const C* zr = Zb + ((size_t)pl * a.rows + (live ? row0 + rloc : 0)) * W;
+    T r[1][8], im[1][8];
+    auto load_line = [&](int j) {
+        const int rl = j / PL, pl = j - (j / PL) * PL;
+        const bool live = j < S::LINES && row0 + rl < a.rows;
+        const C* zr = Zb + ((size_t)pl * a.rows + (live ? row0 + rl : 0)) * W;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int w = band_slot(t + e * Tn, L, c, W);
             C v;
             if (live && w >= 0) v = zr[w];
             else { v.x = 0; v.y = 0; }
-            r[e] = v.x;
-            im[e] = v.y;
+            r[0][e] = v.x;
+            im[0][e] = v.y;
         }
-    }
+    };
+    if ((flags & RF_INVERSE) && fft_thread) load_line(g);
     if (fft_thread && (flags & (RF_INVERSE | RF_FORWARD)))
         load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
-    const bool pthread = tid < FAST_POINTS;
-    const int rloc = tid >> LOG2L, xc = tid & (L - 1);
-    const bool plive = pthread && row0 + rloc < a.rows;
-    const int64_t x = (row0 + rloc) * L + xc;
     int8_t* sgn = a.sgn + (size_t)b * npts;
-    const int8_t s_old = (plive && (flags & RF_SIGN)) ? sgn[x] : (int8_t)0;
+    int8_t s_old[PPT];
+#pragma unroll
+    for (int pp = 0; pp < PPT; ++pp) {
+        const int idx = pp * 512 + tid;
+        const bool live = tid < 512 && row0 + (idx >> LOG2L) < a.rows;
+        s_old[pp] = (live && (flags & RF_SIGN)) ? sgn[(row0 + (idx >> LOG2L)) * L + (idx & (L - 1))] : (int8_t)0;
+    }
     const int stop = (flags & RF_CHECK_STOP) ? a.stop_iter[b] : a.iter;
 
     // ---- phase 1: inverse FFT of each line, natural order into LDS
-    if ((flags & RF_INVERSE) && fft_thread) {
-        T* lrj = lr + (size_t)j * LP;
-        T* lij = li + (size_t)j * LP;
-        fft_wave<T, +1, LOG2L>(r, im, lrj, lij, t, tw, true);
-        wave_lds_sync();  // the line's last exchange has been read
+    if (flags & RF_INVERSE) {
+#pragma unroll 1
+        for (int rd = 0; rd < ROUNDS; ++rd) {
+            const int j = rd * G + g;
+            const bool act = fft_thread && j < S::LINES;
+            if (rd > 0 && fft_thread) load_line(j);
+            T* lrj = lr + (size_t)(act ? j : 0) * LP;
+            T* lij = li + (size_t)(act ? j : 0) * LP;
+            if constexpr (S::WAVE_LINE) {
+                if (act) {
+                    fft_wave<T, +1, LOG2L>(r[0], im[0], lrj, lij, t, tw, true);
+                    wave_lds_sync();  // the line's last exchange has been read
+                }
+            } else {
+                fft_lines<T, +1, 1, LOG2L>(r, im, lrj, lij, 0, 1, 0, t, tw, act);
+                __syncthreads();  // the line's last exchange has been read
+            }
+            if (act) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            lrj[lds_pad_at<Tn>(t, pt, e)] = r[e];
-            lij[lds_pad_at<Tn>(t, pt, e)] = im[e];
+                for (int e = 0; e < 8; ++e) {
+                    lrj[lds_pad_at<Tn>(t, pt, e)] = r[0][e];
+                    lij[lds_pad_at<Tn>(t, pt, e)] = im[0][e];
+                }
+            }
         }
     }
     // a field that already stopped is left alone (uniform per workgroup; the
     // loads above only read)
     if (stop < a.iter) return;
 
-    // ---- phase 2: one point per thread
+    // ---- phase 2: PPT points per projection thread
     T* Aout = reinterpret_cast<T*>(a.Aout) + field_base(a.foff, b, NN * npts);
-    T* lrp = lr + (size_t)rloc * PL * LP + lds_pad(xc);
-    T* lip = li + (size_t)rloc * PL * LP + lds_pad(xc);
     unsigned long long nflip = 0, nfb = 0, nbad = 0;
     double dmax = 0.0;
     const bool fallback = (flags & RF_FALLBACK) != 0;
+    auto point_of = [&](int idx, int64_t& xp, T*& lrq, T*& liq) {
+        const int rq = idx >> LOG2L, xq = idx & (L - 1);
+        xp = (row0 + rq) * L + xq;
+        lrq = lr + (size_t)rq * PL * LP + lds_pad(xq);
+        liq = li + (size_t)rq * PL * LP + lds_pad(xq);
+        return row0 + rq < a.rows;
+    };
 
     // diagnostics and write-back of a projected point (LDS slot at lrq/liq)
     auto finish = [&](int64_t xp, T* lrq, T* liq, const T (&qv)[NN], int ds, int8_t so) {
@@ -248,50 +278,71 @@ __global__ void __launch_bounds__((row_fast_threads<T, n>()), (row_fast_waves<T,
         }
         if (NN & 1) liq[(NN >> 1) * LP] = (T)0;
     };
+    auto load_point = [&](const T* lrq, const T* liq, T (&av)[NN]) {
+#pragma unroll
+        for (int k = 0; k < NN; ++k) av[k] = (k & 1) ? liq[(k >> 1) * LP] : lrq[(k >> 1) * LP];
+    };
 
     if (flags & RF_LOAD_REAL) {
-        // forward transform of a real field: the point's entries from A
-        if (plive) {
-            const T* A = reinterpret_cast<const T*>(a.Ain) + field_base(a.foff, b, NN * npts);
-            T av[NN];
+        // forward transform of a real field: the points' entries from A
+        const T* A = reinterpret_cast<const T*>(a.Ain) + field_base(a.foff, b, NN * npts);
+#pragma unroll 1
+        for (int pp = 0; pp < PPT; ++pp) {
+            int64_t xp;
+            T *lrq, *liq;
+            if (tid < 512 && point_of(pp * 512 + tid, xp, lrq, liq)) {
+                T av[NN];
 #pragma unroll
-            for (int k = 0; k < NN; ++k) av[k] = A[(int64_t)k * npts + x];
-            if (flags & RF_SIGN_INIT) sgn[x] = det_n<T, n>(av) >= (T)0 ? 1 : -1;
+                for (int k = 0; k < NN; ++k) av[k] = A[(int64_t)k * npts + xp];
+                if (flags & RF_SIGN_INIT) sgn[xp] = det_n<T, n>(av) >= (T)0 ? 1 : -1;
 #pragma unroll
-            for (int k = 0; k < NN; ++k) {
-                if (k & 1) lip[(k >> 1) * LP] = av[k];
-                else lrp[(k >> 1) * LP] = av[k];
+                for (int k = 0; k < NN; ++k) {
+                    if (k & 1) liq[(k >> 1) * LP] = av[k];
+                    else lrq[(k >> 1) * LP] = av[k];
+                }
+                if (NN & 1) liq[(NN >> 1) * LP] = (T)0;
             }
-            if (NN & 1) lip[(NN >> 1) * LP] = (T)0;
         }
     }
     __syncthreads();
 
     if (flags & RF_PROJECT) {
-        T av[NN];
-        if (plive) {
-#pragma unroll
-            for (int k = 0; k < NN; ++k) av[k] = (k & 1) ? lip[(k >> 1) * LP] : lrp[(k >> 1) * LP];
-            nbad += all_finite<T, NN>(av) ? 0ull : 1ull;
-        }
         if constexpr (HELPER) {
-            // which points are certainly well conditioned: the Newton iteration;
-            // the others are queued for the helper wave
-            Newton3 ns;
-            bool ok = false;
-            if (plive) {
-                ok = newton3_init(av, ns, (float)a.sigma_fb);
-                if (!ok) fq[atomicAdd(&fq_n, 1)] = (unsigned short)tid;
+            // which points are certainly well conditioned: the Newton
+            // iteration; the others are queued for the helper wave
+            Newton3 ns;       // kept from the test when each thread has one point
+            unsigned ok = 0;  // bit pp: point pp runs Newton
+#pragma unroll 1
+            for (int pp = 0; pp < PPT; ++pp) {
+                int64_t xp;
+                T *lrq, *liq;
+                if (tid < 512 && point_of(pp * 512 + tid, xp, lrq, liq)) {
+                    T av[NN];
+                    load_point(lrq, liq, av);
+                    nbad += all_finite<T, NN>(av) ? 0ull : 1ull;
+                    if (newton3_init(av, ns, (float)a.sigma_fb)) ok |= 1u << pp;
+                    else fq[atomicAdd(&fq_n, 1)] = (unsigned short)(pp * 512 + tid);
+                }
             }
             __syncthreads();
-            if (pthread) {
-                if (ok) {
+            if (tid < 512) {
+#pragma unroll 1
+                for (int pp = 0; pp < PPT; ++pp) {
+                    if (!(ok >> pp & 1u)) continue;
+                    int64_t xp;
+                    T *lrq, *liq;
+                    (void)point_of(pp * 512 + tid, xp, lrq, liq);
+                    if constexpr (PPT > 1) {
+                        T av[NN];
+                        load_point(lrq, liq, av);
+                        (void)newton3_init(av, ns, (float)a.sigma_fb);
+                    }
                     T qv[NN];
                     int ds;
                     newton3_run(ns, qv, ds);
-                    finish(x, lrp, lip, qv, ds, s_old);
+                    finish(xp, lrq, liq, qv, ds, s_old[pp]);
                 }
-            } else {
+            } else if (tid >= NT) {
                 // the helper wave: Jacobi in float, and in double (warm-started
                 // from the float right singular vectors) when sigma_min < sigma_fb
                 __builtin_amdgcn_s_setprio(3);
@@ -299,14 +350,11 @@ __global__ void __launch_bounds__((row_fast_threads<T, n>()), (row_fast_waves<T,
                 const int lane = tid & 63;
 #pragma unroll 1
                 for (int qi = lane; qi < nq; qi += 64) {
-                    const int pi = fq[qi];
-                    const int rq = pi >> LOG2L, xq = pi & (L - 1);
-                    const int64_t xp = (row0 + rq) * L + xq;
-                    T* lrq = lr + (size_t)rq * PL * LP + lds_pad(xq);
-                    T* liq = li + (size_t)rq * PL * LP + lds_pad(xq);
+                    int64_t xp;
+                    T *lrq, *liq;
+                    (void)point_of(fq[qi], xp, lrq, liq);
                     float aq[NN], qv[NN];
-#pragma unroll
-                    for (int k = 0; k < NN; ++k) aq[k] = (k & 1) ? liq[(k >> 1) * LP] : lrq[(k >> 1) * LP];
+                    load_point(lrq, liq, aq);
                     int ds;
                     if (fallback) {
                         float V[n][n];
@@ -328,50 +376,70 @@ __global__ void __launch_bounds__((row_fast_threads<T, n>()), (row_fast_waves<T,
                 __builtin_amdgcn_s_setprio(0);
             }
         } else {
-            if (plive) {
-                T qv[NN];
-                int ds;
-                if (project_point_fb<T, n>(av, qv, ds, fallback, a.sigma_fb)) ++nfb;
-                finish(x, lrp, lip, qv, ds, s_old);
+#pragma unroll 1
+            for (int pp = 0; pp < PPT; ++pp) {
+                int64_t xp;
+                T *lrq, *liq;
+                if (tid < 512 && point_of(pp * 512 + tid, xp, lrq, liq)) {
+                    T av[NN], qv[NN];
+                    load_point(lrq, liq, av);
+                    nbad += all_finite<T, NN>(av) ? 0ull : 1ull;
+                    int ds;
+                    if (project_point_fb<T, n>(av, qv, ds, fallback, a.sigma_fb)) ++nfb;
+                    finish(xp, lrq, liq, qv, ds, s_old[pp]);
+                }
             }
         }
         __syncthreads();
     }
 
     // ---- phase 3: forward FFT of the lines, store the kept modes
-    if ((flags & RF_FORWARD) && fft_thread) {
-        const int rl = j / PL, pl = j - (j / PL) * PL;
-        T* lrj = lr + (size_t)j * LP;
-        T* lij = li + (size_t)j * LP;
+    if (flags & RF_FORWARD) {
+#pragma unroll 1
+        for (int rd = 0; rd < ROUNDS; ++rd) {
+            const int j = rd * G + g;
+            const bool act = fft_thread && j < S::LINES;
+            const int rl = j / PL, pl = j - (j / PL) * PL;
+            T* lrj = lr + (size_t)(act ? j : 0) * LP;
+            T* lij = li + (size_t)(act ? j : 0) * LP;
+            if (act) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            r[e] = lrj[lds_pad_at<Tn>(t, pt, e)];
-            im[e] = lij[lds_pad_at<Tn>(t, pt, e)];
-        }
-        wave_lds_sync();  // every lane has read its elements before the exchanges
-        fft_wave<T, -1, LOG2L>(r, im, lrj, lij, t, tw, true);
-        if (row0 + rl < a.rows) {
-            C* zr = Zb + ((size_t)pl * a.rows + row0 + rl) * W;
-            // slots w < W - c take mode w (zero when w > c); slots w >= W - c
-            // take mode L - W + w
+                for (int e = 0; e < 8; ++e) {
+                    r[0][e] = lrj[lds_pad_at<Tn>(t, pt, e)];
+                    im[0][e] = lij[lds_pad_at<Tn>(t, pt, e)];
+                }
+            }
+            if constexpr (S::WAVE_LINE) {
+                if (act) {
+                    wave_lds_sync();  // every lane has read its elements before the exchanges
+                    fft_wave<T, -1, LOG2L>(r[0], im[0], lrj, lij, t, tw, true);
+                }
+            } else {
+                fft_lines<T, -1, 1, LOG2L>(r, im, lrj, lij, 0, 1, 0, t, tw, act);
+            }
+            if (act && row0 + rl < a.rows) {
+                C* zr = Zb + ((size_t)pl * a.rows + row0 + rl) * W;
+                // slots w < W - c take mode w (zero when w > c); slots w >= W - c
+                // take mode L - W + w
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int kx = t + e * Tn;
-                C v;
-                v.x = r[e];
-                v.y = im[e];
-                if (kx < W - c) {
-                    if (kx > c) { v.x = 0; v.y = 0; }
-                    zr[kx] = v;
-                } else if (kx >= L - c) {
-                    zr[W - L + kx] = v;
+                for (int e = 0; e < 8; ++e) {
+                    const int kx = t + e * Tn;
+                    C v;
+                    v.x = r[0][e];
+                    v.y = im[0][e];
+                    if (kx < W - c) {
+                        if (kx > c) { v.x = 0; v.y = 0; }
+                        zr[kx] = v;
+                    } else if (kx >= L - c) {
+                        zr[W - L + kx] = v;
+                    }
                 }
             }
         }
     }
 
     if (flags & (RF_PROJECT | RF_TRACK)) {
-        // counts of the workgroup: packed 21 bits each (at most 512 per workgroup)
+        // counts of the workgroup: packed 21 bits each (at most 2048 per workgroup)
         unsigned long long packed = wave_sum(nflip | (nfb << 21) | (nbad << 42));
         unsigned long long dbits = (unsigned long long)__double_as_longlong(dmax);
 #pragma unroll

@@ -22,13 +22,26 @@ hipError_t launch_heat_fast(int prec, int log2L, int TX, const FastColArgs& a, d
     return launch_heat_fast_f64(log2L, TX, a, grid, st, prepare, ev0, ev1);
 }
 
-int row_fast_block(int prec, int n) { return prec == 1 && n == 3 ? row_fast_threads<float, 3>() : FAST_POINTS; }
+template <typename T>
+static size_t row_lds_t(int n, int log2L)
+{
+#define MBO_ROW_LDS(NV, LG) \
+    if (n == NV && log2L == LG) return RowFastShape<T, NV, LG>::LDS;
+#define MBO_ROW_LDS_N(NV) \
+    MBO_ROW_LDS(NV, 3) MBO_ROW_LDS(NV, 4) MBO_ROW_LDS(NV, 5) MBO_ROW_LDS(NV, 6) MBO_ROW_LDS(NV, 7) \
+    MBO_ROW_LDS(NV, 8) MBO_ROW_LDS(NV, 9) MBO_ROW_LDS(NV, 10) MBO_ROW_LDS(NV, 11)
+    MBO_ROW_LDS_N(1) MBO_ROW_LDS_N(2) MBO_ROW_LDS_N(3) MBO_ROW_LDS_N(4)
+#undef MBO_ROW_LDS_N
+#undef MBO_ROW_LDS
+    return 0;
+}
 
 size_t row_fast_lds_bytes(int prec, int n, int log2L)
 {
-    const int L = 1 << log2L;
-    return (size_t)((n * n + 1) / 2) * (FAST_POINTS / L) * (L + L / 8) * 2 * (prec == 1 ? 4 : 8);
+    return prec == 1 ? row_lds_t<float>(n, log2L) : row_lds_t<double>(n, log2L);
 }
+
+int row_fast_rows_per_group(int log2L) { return log2L >= 9 ? 1 : 512 >> log2L; }
 
 size_t heat_fast_lds_bytes(int prec, int log2L, int TX)
 {

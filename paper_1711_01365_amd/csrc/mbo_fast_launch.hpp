@@ -1,5 +1,5 @@
 // Launchers of the band-limited passes (mbo_fast.hpp) for one precision T:
-// row_fast for n = 1..4 and row lengths 2^3..2^9, heat_fast for column lengths
+// row_fast for n = 1..4 and row lengths 2^3..2^11, heat_fast for column lengths
 // 2^6..2^11 and tiles of TX = 1..16 columns with 64..1024 threads.
 #pragma once
 
@@ -13,10 +13,11 @@ template <typename T, int n, int LG>
 static hipError_t row_fast_go(const FastRowArgs& a, dim3 g, hipStream_t st, bool prepare, hipEvent_t ev0,
                               hipEvent_t ev1)
 {
-    const size_t lds = row_fast_lds<T, n, LG>();
+    typedef RowFastShape<T, n, LG> S;
+    const size_t lds = S::LDS;
     const void* f = reinterpret_cast<const void*>(&row_fast<T, n, LG>);
     if (prepare) return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    const dim3 bl(row_fast_threads<T, n>());
+    const dim3 bl(S::THREADS);
     if (ev0) hipExtLaunchKernelGGL((row_fast<T, n, LG>), g, bl, lds, st, ev0, ev1, 0, a);
     else hipLaunchKernelGGL((row_fast<T, n, LG>), g, bl, lds, st, a);
     return hipGetLastError();
@@ -34,6 +35,8 @@ static hipError_t row_fast_n(int log2L, const FastRowArgs& a, dim3 g, hipStream_
     case 7: return row_fast_go<T, n, 7>(a, g, st, prepare, ev0, ev1);
     case 8: return row_fast_go<T, n, 8>(a, g, st, prepare, ev0, ev1);
     case 9: return row_fast_go<T, n, 9>(a, g, st, prepare, ev0, ev1);
+    case 10: return row_fast_go<T, n, 10>(a, g, st, prepare, ev0, ev1);
+    case 11: return row_fast_go<T, n, 11>(a, g, st, prepare, ev0, ev1);
     }
     return hipErrorInvalidValue;
 }

@@ -409,13 +409,13 @@ hipError_t launch_row_fast(int prec, int n, int log2L, const FastRowArgs& a, dim
                            bool prepare = false, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_heat_fast(int prec, int log2L, int TX, const FastColArgs& a, dim3 grid, hipStream_t st,
                             bool prepare = false, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-// threads and LDS bytes of a row_fast workgroup, LDS bytes of a heat_fast workgroup
-int row_fast_block(int prec, int n);
 // flips / fallbacks / non-finite of every iteration and field from the row
 // pass's per-workgroup packed counts [batch][K][nwg]
 hipError_t launch_sum_counts(const unsigned long long* part, int nwg, int K, int batch, unsigned long long* flips,
                              unsigned long long* fallbacks, unsigned long long* nonfinite, hipStream_t st);
+// dynamic LDS bytes and rows of a row_fast workgroup, LDS bytes of a heat_fast workgroup
 size_t row_fast_lds_bytes(int prec, int n, int log2L);
+int row_fast_rows_per_group(int log2L);
 size_t heat_fast_lds_bytes(int prec, int log2L, int TX);
 
 }  // namespace mbo

@@ -464,6 +464,99 @@ def test_iterate_long_axes_fp32_fallback(torch_cuda, grid):
     assert fp32_step_ok(err, gap, e_heat)
 
 
+BANDED_LONG_F64 = [((64, 1024), 3), ((64, 1024), 4), ((128, 2048), 2), ((64, 2048), 1), ((64, 512), 3)]
+
+
+def assert_banded(P, L):
+    """The plan runs the band-limited passes with fewer stored modes than L."""
+    from paper_1711_01365_amd import mbo
+    path, c, W = P.path()
+    note("path %d, half-width %d, stored modes %d of %d" % (path, c, W, L))
+    assert path == mbo.PATH_BANDED and 2 * c + 1 <= W < L
+
+
+@pytest.mark.parametrize("grid,n", BANDED_LONG_F64)
+def test_iterate_banded_rows_f64(torch_cuda, grid, n):
+    """Three FP64 steps through the band-limited row pass (rows of 512 points, one
+    wave per line; rows of 1024 and 2048 points, lines exchanged through
+    workgroup barriers, in rounds of lines, several points per thread) against
+    the oracle: entries to 1e-12 (the dropped row modes weigh at most 1e-20 of
+    max|A|), flips identical, energies to 1e-10 of the largest."""
+    torch = torch_cuda
+    tau, K = 2e-4, 3
+    A0 = inputs.uniform_field(n, grid, 23)
+    note("banded f64 grid=%s n=%d" % (grid, n))
+    P = plan(grid, n, tau, F64)
+    assert_banded(P, grid[-1])
+    t = to_dev(torch, A0, torch.float64)
+    r = P.iterate(t, K)
+    ro = oracle.iterate(A0, tau, K)
+    err = float(np.abs(t.cpu().numpy() - ro["A"]).max())
+    note("banded f64 max err %.3g" % err)
+    assert err <= 1e-12
+    compare_runs(r, ro, K, 1e-12)
+
+
+@pytest.mark.parametrize("grid,n", [((64, 1024), 3), ((64, 2048), 3), ((64, 2048), 4), ((128, 1024), 2),
+                                    ((64, 2048), 2)])
+def test_iterate_banded_rows_fp32_fallback(torch_cuda, grid, n):
+    """One FP32 + FP64-fallback step through the band-limited row pass with rows
+    of 1024 and 2048 points (n = 3: the helper wave's queue of up to 2048 points
+    per workgroup) against the FP64 oracle, to the FP32 bar; the fallback count
+    against the points whose float sigma_min is below the threshold is checked
+    by the targeted test."""
+    torch = torch_cuda
+    tau = 2e-4
+    A0 = inputs.uniform_field(n, grid, 29).astype(np.float32)
+    A64 = A0.astype(np.float64)
+    note("banded f32+fb grid=%s n=%d" % (grid, n))
+    P = plan(grid, n, tau, FB)
+    assert_banded(P, grid[-1])
+    Ht, _ = oracle.heat(A64, tau, len(grid))
+    Hg = P.diffuse(to_dev(torch, A0, torch.float32)).cpu().numpy()
+    e_heat = float(np.abs(Hg - Ht).max())
+    t = to_dev(torch, A0, torch.float32)
+    r = P.iterate(t, 1)
+    ro = oracle.iterate(A64, tau, 1)
+    gap = sigma_gap(Ht)
+    err = np.abs(point_major(t.cpu().numpy() - ro["A"])).max(axis=(1, 2))
+    note("banded f32+fb: diffusion err %.3g, step err max %.3g, fallbacks %d"
+         % (e_heat, err.max(), r["fallbacks"][0][0]))
+    assert e_heat <= 2e-6
+    assert fp32_step_ok(err, gap, e_heat)
+    assert abs(r["energy"][0][0] - ro["energy"][0]) <= 1e-5 * abs(ro["energy"][0])
+
+
+@pytest.mark.parametrize("grid,n", [((64, 2048), 3), ((64, 1024), 4)])
+def test_banded_rows_match_the_full_path(torch_cuda, grid, n):
+    """Five FP32 + fallback steps: the band-limited passes against every row mode
+    kept (PATH_FULL), both on the GPU: the two differ by the dropped modes (at
+    most 1e-12 max|A| per step) and float rounding, so entries agree to the FP32
+    bar where the projection is well conditioned, and det signs agree except at
+    ties."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    tau, K = 2e-4, 5
+    A0 = inputs.uniform_field(n, grid, 31).astype(np.float32)
+    out = []
+    for path in (mbo.PATH_BANDED, mbo.PATH_FULL):
+        P = plan(grid, n, tau, FB)
+        P.set_path(path)
+        assert P.path()[0] == path
+        t = to_dev(torch, A0, torch.float32)
+        P.iterate(t, K - 1)
+        H = P.diffuse(t).cpu().numpy()
+        P.iterate(t, 1)
+        out.append((t.cpu().numpy(), H))
+        P.close()
+    (Ab, Hb), (Af, Hf) = out
+    gap = sigma_gap(Hf.astype(np.float64))
+    err = np.abs(point_major(Ab - Af)).max(axis=(1, 2))
+    note("banded vs full: max err %.3g, well-conditioned max %.3g"
+         % (err.max(), err[gap >= 0.1].max() if np.any(gap >= 0.1) else 0.0))
+    assert err[gap >= 0.1].max() <= 1e-5
+
+
 @pytest.mark.parametrize("prec", [F64, F32, FB])
 def test_iterate_zero_and_rank_one_fields(torch_cuda, prec):
     """Degenerate fields: the zero field diffuses to itself and every point
