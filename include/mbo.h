@@ -75,7 +75,9 @@ typedef enum {
                                  n >= 3 */
     MBO_ERR_ALLOC = 3,        /* device allocation failed */
     MBO_ERR_HIP = 4,          /* a HIP runtime call failed (see mbo_last_error) */
-    MBO_ERR_NONFINITE = 5     /* NaN or Inf met in the input of a projection */
+    MBO_ERR_NONFINITE = 5,    /* NaN or Inf met in the input of a projection */
+    MBO_ERR_SCRATCH = 6       /* mbo_step_static: the field's working memory
+                                 exceeds MBO_STEP_STATIC_MAX_BYTES */
 } mbo_status;
 
 typedef enum {
@@ -95,8 +97,8 @@ typedef enum {
  * tau and grid leave nothing to drop runs the same kernels with every mode kept.
  * MBO_PATH_FULL runs the same kernels with every mode kept; MBO_PATH_GENERIC the
  * general kernels (any d, any row length), which the other calls always use.
- * The band-limited kernels serve d = 2 with a last axis of at most 512 points
- * and a first axis of at least 64; other shapes run the general kernels. */
+ * The band-limited kernels serve d = 2 with a first axis of at least 64 points
+ * (every last axis a plan accepts); other shapes run the general kernels. */
 typedef enum {
     MBO_PATH_GENERIC = 0,
     MBO_PATH_FULL = 1,
@@ -467,6 +469,42 @@ mbo_status mbo_diffuse_dtau(mbo_plan_t plan, const void* A, void* out, const voi
  * Used to recompute iterates between checkpoints of the adjoint. */
 mbo_status mbo_step(mbo_plan_t plan, const void* A_prev, void* A_next);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one step of
+ * Algorithm 1, A_next = P(e^{tau Delta} A_prev), of ONE field on the 2-D grid
+ * N0 x N1 with n x n entries, with no plan.  Results are those of mbo_step on a
+ * plan (1, {N0, N1}, n, tau, prec, sigma_fallback) with the default path and no
+ * autotuning: the same band-limited kernels, launch shapes and tables.
+ *   Arguments  N0, N1: powers of two in [8, 2048], N0 >= 64 (the band-limited
+ *              kernels' range; MBO_ERR_UNSUPPORTED otherwise); n in [1, 4];
+ *              prec, tau, sigma_fallback as for mbo_plan; A_prev (read) and
+ *              A_next (written): device fields [n][n][N0][N1] of the precision's
+ *              element type, caller-owned, A_next not aliasing A_prev;
+ *              hip_stream: the stream all work is enqueued on (NULL = default).
+ *   Memory     calls no allocator.  The working memory (the kept row spectra of
+ *              the ceil(n^2/2) packed planes, twiddles, heat-symbol factors)
+ *              lives in one fixed device array of MBO_STEP_STATIC_MAX_BYTES per
+ *              GPU, held from the library's first use on that GPU until the
+ *              process ends; a field that needs more is refused with
+ *              MBO_ERR_SCRATCH (mbo_last_error(NULL) gives the sizes).  In
+ *              float with n = 3 and tau = 2e-4, 512 x 512 needs about 2.5 MiB
+ *              and 2048 x 2048 about 10 MiB; with every row mode kept the
+ *              spectra take 8 ceil(n^2/2) N0 N1 bytes (16 in double).
+ *   Sharing    every call on a GPU uses that GPU's one array: calls that overlap
+ *              on one GPU (on two streams, or from two host threads without
+ *              ordering) race.  Nothing is carried between calls: each call
+ *              rebuilds its tables, and the forward pass writes every stored
+ *              slot, so nothing needs clearing.
+ *   Set-up     the first call on a device resolves the array's address
+ *              (hipGetSymbolAddress) with that device current; make that first
+ *              call outside graph capture.
+ *   Errors     asynchronous like mbo_step: no synchronisation, no NaN check.
+ *              Argument errors are returned before anything is enqueued;
+ *              mbo_last_error(NULL) describes them. */
+#define MBO_STEP_STATIC_MAX_BYTES 67108864 /* 64 MiB */
+mbo_status mbo_step_static(int64_t N0, int64_t N1, int n, mbo_precision prec, double tau, double sigma_fallback,
+                           const void* A_prev, void* A_next, void* hip_stream);
+
 /* Backward step of the adjoint (the chain rule through one step of
  * Algorithm 1), asynchronous: with A~ = e^{tau Delta} A_prev and on entry G =
  * Gbar_s, the cotangent of A_s = P(A~),
@@ -481,8 +519,9 @@ mbo_status mbo_step_vjp(mbo_plan_t plan, const void* A_prev, void* G, double* dt
 /* Human-readable name of a status code (static storage). */
 const char* mbo_status_string(mbo_status s);
 
-/* Description of the last error on this plan (or of the last failed mbo_plan
- * call when plan is NULL).  Valid until the next call on the same plan. */
+/* Description of the last error on this plan (or, when plan is NULL, of the
+ * last failed plan-less call on this thread: mbo_plan, mbo_plan_batched or
+ * mbo_step_static).  Valid until the next call on the same plan. */
 const char* mbo_last_error(mbo_plan_t plan);
 
 #ifdef __cplusplus

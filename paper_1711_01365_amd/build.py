@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libmbo.so")
 SOURCES = ["mbo_row_f32.hip", "mbo_row_f64.hip", "mbo_col_f32.hip", "mbo_col_f64.hip",
            "mbo_vprow_f32.hip", "mbo_vprow_f64.hip", "mbo_volume.hip", "mbo_relaxrow_f32.hip",
            "mbo_relaxrow_f64.hip", "mbo_misc.hip", "mbo_fast_f32.hip", "mbo_fast_f64.hip", "mbo_surface.hip", "mbo_surfvol.hip",
-           "mbo_api.cpp"]
+           "mbo_static.hip", "mbo_api.cpp"]
 HEADERS = ["mbo_device.hpp", "mbo_kernels.hpp", "mbo_internal.hpp", "mbo_volume.hpp", "mbo_fast.hpp",
            "mbo_fast_launch.hpp"]
 

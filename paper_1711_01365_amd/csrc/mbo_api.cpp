@@ -25,6 +25,9 @@ using namespace mbo;
 namespace {
 
 thread_local std::string g_plan_error;  // failures of mbo_plan (no plan to hold them)
+// failures of mbo_step_static, in a fixed buffer (that call allocates nothing)
+thread_local char g_static_error[256];
+thread_local bool g_static_failed = false;  // the last plan-less failure was mbo_step_static's
 
 int ilog2(int64_t v)
 {
@@ -64,6 +67,19 @@ struct ColCfg {
 };
 
 }  // namespace
+
+namespace mbo {
+
+void report_static_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_static_error, sizeof g_static_error, fmt, ap);
+    va_end(ap);
+    g_static_failed = true;
+}
+
+}  // namespace mbo
 
 struct mbo_plan_s {
     int device = 0;
@@ -375,33 +391,71 @@ mbo_status build_laplace_tables(mbo_plan_t p)
 // modes with |kx| > c changes a diffused value by at most
 // max|A| * S_y(tau) * sum_{|kx| > c} exp(-4 pi^2 tau kx^2), S_y the sum of the
 // column axis's factor over all its modes (|A^(k)| <= N0 N1 max|A|).  c is the
-// smallest half-width that keeps this below eta for every tau of the plan;
-// c = N1/2 keeps every mode.
-int band_halfwidth(int64_t N0, int64_t N1, const std::vector<double>& taus, double eta)
+// smallest half-width that keeps this below eta; c = N1/2 keeps every mode.
+// The tail sum is accumulated from the top (the dropped modes are the
+// smallest terms), so it only grows as c decreases.
+int band_halfwidth(int64_t N0, int64_t N1, double tau, double eta)
 {
     const double pi = 3.14159265358979323846;
-    int cmax = 0;
-    for (double tau : taus) {
-        double sy = 0.0;
-        for (int64_t m = 0; m < N0; ++m) {
-            const double k = (2 * m < N0) ? (double)m : (double)(m - N0);
-            sy += std::exp(-4.0 * pi * pi * tau * k * k);
-        }
-        // tail[c] = sum over the wrapped kx with |kx| > c, accumulated from the top
-        const int64_t h = N1 / 2;
-        std::vector<double> tail((size_t)h + 1, 0.0);
-        for (int64_t c = h - 1; c >= 0; --c) {
-            const double k = (double)(c + 1);
-            const double term = std::exp(-4.0 * pi * pi * tau * k * k);
-            // |kx| = c + 1 occurs twice, except the Nyquist mode N1/2 (once)
-            tail[(size_t)c] = tail[(size_t)c + 1] + (c + 1 == h ? 1.0 : 2.0) * term;
-        }
-        int c = 0;
-        while (c < h && sy * tail[(size_t)c] > eta) ++c;
-        cmax = c > cmax ? c : cmax;
+    double sy = 0.0;
+    for (int64_t m = 0; m < N0; ++m) {
+        const double k = (2 * m < N0) ? (double)m : (double)(m - N0);
+        sy += std::exp(-4.0 * pi * pi * tau * k * k);
     }
-    return cmax;
+    const int64_t h = N1 / 2;
+    double tail = 0.0;  // sum over |kx| > c
+    int64_t c = h;
+    while (c > 0) {
+        // |kx| = c occurs twice, except the Nyquist mode N1/2 (once)
+        const double k = (double)c;
+        const double t = tail + (c == h ? 1.0 : 2.0) * std::exp(-4.0 * pi * pi * tau * k * k);
+        if (sy * t > eta) break;
+        tail = t;
+        --c;
+    }
+    return (int)c;
 }
+
+}  // namespace
+
+namespace mbo {
+
+bool fast_layout(int64_t N0, int64_t N1, int n, int pk, const double* taus, int64_t ntau, bool banded,
+                 size_t lds_max, int tune_tx, int* band_c, int* band_W, int* heat_tx)
+{
+    if (N1 < 8 || N1 > 2048 || N0 < 64 || N0 > 2048) return false;
+    // the row pass keeps a workgroup's lines (512 points, or one row) in LDS
+    // beside its static arrays (the helper's queue, at most 4 KiB)
+    if (row_fast_lds_bytes(pk, n, ilog2((int)N1)) + 4352 > lds_max) return false;
+    int c = (int)(N1 / 2), W = (int)N1;
+    if (banded) {
+        const double eta = pk == 1 ? 1e-12 : 1e-20;
+        int cmax = 0;
+        for (int64_t i = 0; i < ntau; ++i) {
+            const int ci = band_halfwidth(N0, N1, taus[i], eta);
+            cmax = ci > cmax ? ci : cmax;
+        }
+        const int Wb = ((2 * cmax + 1) + 15) / 16 * 16;
+        if (Wb < N1) {
+            c = cmax;
+            W = Wb;
+        }
+    }
+    // heat tile: TX columns of 2^k with 64..1024 threads and TX | W
+    const int Tn = (int)(N0 / 8);
+    int tx = tune_tx ? tune_tx : 2;
+    while (tx * Tn < 64) tx *= 2;
+    while (tx > 1 && (tx * Tn > 1024 || W % tx)) tx /= 2;
+    if (tx * Tn < 64 || tx * Tn > 1024 || W % tx) return false;
+    *band_c = c;
+    *band_W = W;
+    *heat_tx = tx;
+    return true;
+}
+
+}  // namespace mbo
+
+namespace {
 
 // Whether mbo_iterate runs the band-limited passes, and their layout: kept
 // half-width c and stored modes W per row (a multiple of 16, at least 2c + 1;
@@ -412,27 +466,14 @@ void config_fast(mbo_plan_t p)
     p->band_c = (int)(p->N[p->d - 1] / 2);
     p->band_W = (int)p->N[p->d - 1];
     if (p->path == MBO_PATH_GENERIC || p->d != 2) return;
-    const int64_t N0 = p->N[0], N1 = p->N[1];
-    if (N1 < 8 || N1 > 2048 || N0 < 64 || N0 > 2048) return;
-    // the row pass keeps a workgroup's lines (512 points, or one row) in LDS
-    // beside its static arrays (the helper's queue, at most 4 KiB)
-    if (row_fast_lds_bytes(p->pk, p->n, ilog2((int)N1)) + 4352 > p->lds_max) return;
-    if (p->path == MBO_PATH_BANDED) {
-        std::vector<double> taus = p->per_field_tau ? p->taus : std::vector<double>(1, p->tau);
-        const double eta = p->pk == 1 ? 1e-12 : 1e-20;
-        const int c = band_halfwidth(N0, N1, taus, eta);
-        const int W = ((2 * c + 1) + 15) / 16 * 16;
-        if (W < N1) {
-            p->band_c = c;
-            p->band_W = W;
-        }
-    }
-    // heat tile: TX columns of 2^k with 64..1024 threads and TX | W
-    const int Tn = (int)(N0 / 8);
-    int tx = p->tune_fast_tx ? p->tune_fast_tx : 2;
-    while (tx * Tn < 64) tx *= 2;
-    while (tx > 1 && (tx * Tn > 1024 || p->band_W % tx)) tx /= 2;
-    if (tx * Tn < 64 || tx * Tn > 1024 || p->band_W % tx) return;
+    const double* taus = p->per_field_tau ? p->taus.data() : &p->tau;
+    const int64_t ntau = p->per_field_tau ? (int64_t)p->taus.size() : 1;
+    int c, W, tx;
+    if (!fast_layout(p->N[0], p->N[1], p->n, p->pk, taus, ntau, p->path == MBO_PATH_BANDED, p->lds_max,
+                     p->tune_fast_tx, &c, &W, &tx))
+        return;
+    p->band_c = c;
+    p->band_W = W;
     p->fast_tx = tx;
     p->fast = true;
 }
@@ -2073,19 +2114,22 @@ const char* mbo_status_string(mbo_status s)
     case MBO_ERR_ALLOC: return "MBO_ERR_ALLOC";
     case MBO_ERR_HIP: return "MBO_ERR_HIP";
     case MBO_ERR_NONFINITE: return "MBO_ERR_NONFINITE";
+    case MBO_ERR_SCRATCH: return "MBO_ERR_SCRATCH";
     }
     return "MBO_ERR_UNKNOWN";
 }
 
 const char* mbo_last_error(mbo_plan_t plan)
 {
-    return plan ? plan->err.c_str() : g_plan_error.c_str();
+    if (plan) return plan->err.c_str();
+    return g_static_failed ? g_static_error : g_plan_error.c_str();
 }
 
 mbo_status mbo_plan(mbo_plan_t* out, int d, const int64_t* N, int n, int64_t batch, double tau,
                     mbo_precision prec, double sigma_fallback, void* hip_stream)
 {
     g_plan_error.clear();
+    g_static_failed = false;
     if (!out) return fail(nullptr, MBO_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!N) return fail(nullptr, MBO_ERR_INVALID_ARG, "N is NULL");
@@ -2111,6 +2155,7 @@ mbo_status mbo_plan_batched(mbo_plan_t* out, int count, const mbo_field_desc* de
                             double sigma_fallback, int autotune, void* hip_stream)
 {
     g_plan_error.clear();
+    g_static_failed = false;
     if (!out) return fail(nullptr, MBO_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (count < 1 || !descs) return fail(nullptr, MBO_ERR_INVALID_ARG, "count < 1 or descs is NULL");
@@ -2826,6 +2871,7 @@ mbo_status surface_create(mbo_surface_t* out, int kind, double radius, double dx
                           int n, mbo_precision prec, void* hip_stream)
 {
     g_plan_error.clear();
+    g_static_failed = false;
     if (!out) return sfail(nullptr, MBO_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!(radius > 0.0) || !(dx > 0.0) || !(tau > 0.0) || !(eps > 0.0 && eps < 0.5) || !std::isfinite(radius) ||

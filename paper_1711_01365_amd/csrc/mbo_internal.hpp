@@ -413,6 +413,16 @@ hipError_t launch_heat_fast(int prec, int log2L, int TX, const FastColArgs& a, d
 // pass's per-workgroup packed counts [batch][K][nwg]
 hipError_t launch_sum_counts(const unsigned long long* part, int nwg, int K, int batch, unsigned long long* flips,
                              unsigned long long* fallbacks, unsigned long long* nonfinite, hipStream_t st);
+// Layout of the band-limited passes of a 2-D grid N0 x N1 with n x n entries in
+// precision pk (1 float, 0 double) for the diffusion times taus[0..ntau): kept
+// half-width, stored modes per row (every mode when banded is false or nothing
+// would be dropped), heat tile width (tune_tx, or the default rule when 0).
+// false when the band-limited kernels do not serve the shape.
+bool fast_layout(int64_t N0, int64_t N1, int n, int pk, const double* taus, int64_t ntau, bool banded,
+                 size_t lds_max, int tune_tx, int* band_c, int* band_W, int* heat_tx);
+// message of a failed plan-less call, returned by mbo_last_error(NULL) (fixed
+// buffer: allocates nothing)
+void report_static_error(const char* fmt, ...);
 // dynamic LDS bytes and rows of a row_fast workgroup, LDS bytes of a heat_fast workgroup
 size_t row_fast_lds_bytes(int prec, int n, int log2L);
 int row_fast_rows_per_group(int log2L);

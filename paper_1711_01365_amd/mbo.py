@@ -23,7 +23,8 @@ F64, F32, F32_F64FALLBACK = 0, 1, 2
 GD1, GD3 = 1, 3
 PATH_GENERIC, PATH_FULL, PATH_BANDED = 0, 1, 2
 _STATUS = {0: "MBO_OK", 1: "MBO_ERR_INVALID_ARG", 2: "MBO_ERR_UNSUPPORTED", 3: "MBO_ERR_ALLOC",
-           4: "MBO_ERR_HIP", 5: "MBO_ERR_NONFINITE"}
+           4: "MBO_ERR_HIP", 5: "MBO_ERR_NONFINITE", 6: "MBO_ERR_SCRATCH"}
+STEP_STATIC_MAX_BYTES = 64 << 20
 
 _lib = None
 
@@ -36,7 +37,8 @@ EXPORTS = ("mbo_plan", "mbo_plan_destroy", "mbo_plan_set_tau", "mbo_plan_set_str
            "mbo_surface_info",
            "mbo_surface_points", "mbo_surface_diffuse", "mbo_surface_iterate", "mbo_surface_last_error",
            "mbo_surface_volume_weights", "mbo_surface_volume_select", "mbo_surface_iterate_volume",
-           "mbo_plan_set_path", "mbo_plan_path", "mbo_last_project_counts", "mbo_status_string", "mbo_last_error")
+           "mbo_plan_set_path", "mbo_plan_path", "mbo_last_project_counts", "mbo_step_static", "mbo_status_string",
+           "mbo_last_error")
 
 
 class FieldDesc(ctypes.Structure):
@@ -82,6 +84,8 @@ def load(path: str = LIB_PATH):
     lib.mbo_plan_path.argtypes = [vp, ctypes.c_int, ip, ip, ip]
     lib.mbo_plan_autotune.argtypes = [vp]
     lib.mbo_step.argtypes = [vp, vp, vp]
+    lib.mbo_step_static.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, vp, vp, vp]
     lib.mbo_step_vjp.argtypes = [vp, vp, vp, vp]
     lib.mbo_volume_select.argtypes = [vp, vp, i64p, vp]
     lib.mbo_project_volume.argtypes = [vp, vp, vp, i64p, vp]
@@ -410,6 +414,30 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def step_static(A_prev, A_next, tau: float, precision: int = F32_F64FALLBACK, sigma_fallback: float = 0.0,
+                stream=None):
+    """mbo_step_static: one step A_next = P(e^{tau Delta} A_prev) of one 2-D field
+    (device tensors of shape (n, n, N0, N1)) with no plan and no device
+    allocation; asynchronous on `stream`."""
+    import torch
+    lib = load()
+    want = torch.float64 if precision == F64 else torch.float32
+    for name, A in (("A_prev", A_prev), ("A_next", A_next)):
+        if not isinstance(A, torch.Tensor) or not A.is_cuda:
+            raise TypeError("%s must be a CUDA/HIP tensor" % name)
+        if A.dtype != want:
+            raise TypeError("%s must be %s" % (name, want))
+        if A.dim() != 4 or A.shape[0] != A.shape[1] or not A.is_contiguous():
+            raise ValueError("%s must be a contiguous (n, n, N0, N1) tensor" % name)
+    if tuple(A_prev.shape) != tuple(A_next.shape):
+        raise ValueError("A_prev and A_next differ in shape")
+    n, _, N0, N1 = (int(v) for v in A_prev.shape)
+    _check(lib.mbo_step_static(N0, N1, n, int(precision), float(tau), float(sigma_fallback),
+                               ctypes.c_void_p(A_prev.data_ptr()), ctypes.c_void_p(A_next.data_ptr()),
+                               _stream_ptr(stream)), None)
+    return A_next
 
 
 class SphereSurface:

@@ -67,6 +67,25 @@ def test_plan_validation_codes(lib, kw, code):
     assert lib.mbo_last_error(None)  # a message is recorded
 
 
+@pytest.mark.parametrize("kw,code,msg", [
+    (dict(prec=7), 1, "precision"), (dict(n=0), 1, "n = 0"), (dict(n=5), 1, "n = 5"),
+    (dict(tau=0.0), 1, "tau"), (dict(tau=float("nan")), 1, "tau"),
+    (dict(a=None), 1, "NULL"), (dict(b=None), 1, "NULL"), (dict(b=0x1000), 1, "alias"),
+    (dict(N0=96), 2, "power of two"), (dict(N1=4), 2, "power of two"), (dict(N1=4096), 2, "power of two"),
+])
+def test_step_static_validation_codes(lib, kw, code, msg):
+    """mbo_step_static checks its arguments before it touches the device, and
+    mbo_last_error(NULL) names the failure (a fixed buffer: the call allocates
+    nothing); a later failed mbo_plan takes over mbo_last_error(NULL)."""
+    a = dict(N0=64, N1=64, n=3, prec=2, tau=1e-3, a=0x1000, b=0x2000)
+    a.update(kw)
+    rc = lib.mbo_step_static(a["N0"], a["N1"], a["n"], a["prec"], a["tau"], 0.0, a["a"], a["b"], None)
+    assert rc == code
+    assert msg in lib.mbo_last_error(None).decode()
+    rc, _ = _plan(lib, n=0)
+    assert rc == 1 and b"n" in lib.mbo_last_error(None)
+
+
 def test_null_plan_is_rejected(lib):
     assert lib.mbo_diffuse(None, None, None) == 1
     assert lib.mbo_project(None, None, None, None) == 1
