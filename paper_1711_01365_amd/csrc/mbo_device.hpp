@@ -448,8 +448,8 @@ __device__ __forceinline__ void polar2(const T* a_in, T* q, int& dsign, T& smin)
 // stops after a sweep without rotations, or after a sweep whose rotations all
 // had |s| < sdone (the inner products left are then of order s^2, below the
 // tolerance, so the confirming sweep is skipped).
-template <typename T, int n>
-__device__ __forceinline__ void jacobi_sweeps(T (&W)[n][n], T (&V)[n][n])
+template <typename T, int n, typename VM>
+__device__ __forceinline__ void jacobi_sweeps(T (&W)[n][n], VM& V)
 {
     constexpr T sdone = num<T>::sdone;
 #pragma unroll 1
@@ -497,9 +497,9 @@ __device__ __forceinline__ void jacobi_sweeps(T (&W)[n][n], T (&V)[n][n])
 // Q = U V^t from the orthogonalised columns W = U Sigma (scaled by 2^-ex).  On
 // return W holds U (completed for zero singular values) unless the matrix is
 // zero; sig (nullable) receives the singular values of the unscaled input.
-template <typename T, int n>
-__device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const T (&V)[n][n], int ex, T* q,
-                                              int& dsign, T& smin, T* sig = nullptr)
+template <typename T, int n, typename VM, typename Tq = T>
+__device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const VM& V, int ex, Tq* q, int& dsign, T& smin,
+                                              T* sig = nullptr)
 {
     T ss[n], sg[n];
     T smax = 0;
@@ -521,7 +521,7 @@ __device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const T (&V)[n][n], 
     }
     if (!(smax > (T)0)) {  // zero matrix (or NaN): identity
 #pragma unroll
-        for (int i = 0; i < n * n; ++i) q[i] = (i % (n + 1) == 0) ? (T)1 : (T)0;
+        for (int i = 0; i < n * n; ++i) q[i] = (i % (n + 1) == 0) ? (Tq)1 : (Tq)0;
         dsign = 1;
         return;
     }
@@ -544,30 +544,50 @@ __device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const T (&V)[n][n], 
             // norm would carry an error of about eps sigma_max / sigma_min into
             // U even where the polar factor is well conditioned
             // (sigma_{n-1} + sigma_n large); the completion does not.
+            // (columns picked by selects, not by a run-time index: an indexed
+            // register array would be placed in scratch memory)
             int jm = 0;
+            T sm = sg[0];
 #pragma unroll
-            for (int j = 1; j < n; ++j) jm = sg[j] < sg[jm] ? j : jm;
-            T cv[n];
+            for (int j = 1; j < n; ++j) {
+                jm = sg[j] < sm ? j : jm;
+                sm = sg[j] < sm ? sg[j] : sm;
+            }
+            T cv[n], wm[n];
+#pragma unroll
+            for (int i = 0; i < n; ++i) {
+                wm[i] = W[i][0];
+#pragma unroll
+                for (int j = 1; j < n; ++j) wm[i] = jm == j ? W[i][j] : wm[i];
+            }
             if constexpr (n == 3) {
-                const int a = jm == 0 ? 1 : 0, b = jm == 2 ? 1 : 2;
-                cv[0] = W[1][a] * W[2][b] - W[2][a] * W[1][b];
-                cv[1] = W[2][a] * W[0][b] - W[0][a] * W[2][b];
-                cv[2] = W[0][a] * W[1][b] - W[1][a] * W[0][b];
-            } else {
-                int o[3], k = 0;
+                T ua[3], ub[3];  // the two other columns, in increasing order
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (j != jm) o[k++] = j;
-                // cv_i = (-1)^i det of the 3x3 rows other than i of [u_o0 u_o1 u_o2]
+                for (int i = 0; i < 3; ++i) {
+                    ua[i] = jm == 0 ? W[i][1] : W[i][0];
+                    ub[i] = jm == 2 ? W[i][1] : W[i][2];
+                }
+                cv[0] = ua[1] * ub[2] - ua[2] * ub[1];
+                cv[1] = ua[2] * ub[0] - ua[0] * ub[2];
+                cv[2] = ua[0] * ub[1] - ua[1] * ub[0];
+            } else {
+                T u0[4], u1[4], u2[4];  // the three other columns, in increasing order
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    u0[i] = jm == 0 ? W[i][1] : W[i][0];
+                    u1[i] = jm <= 1 ? W[i][2] : W[i][1];
+                    u2[i] = jm <= 2 ? W[i][3] : W[i][2];
+                }
+                // cv_i = (-1)^i det of the 3x3 rows other than i of [u0 u1 u2]
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     int r[3], m = 0;
 #pragma unroll
                     for (int rr = 0; rr < 4; ++rr)
                         if (rr != i) r[m++] = rr;
-                    const T d = W[r[0]][o[0]] * (W[r[1]][o[1]] * W[r[2]][o[2]] - W[r[2]][o[1]] * W[r[1]][o[2]]) -
-                                W[r[1]][o[0]] * (W[r[0]][o[1]] * W[r[2]][o[2]] - W[r[2]][o[1]] * W[r[0]][o[2]]) +
-                                W[r[2]][o[0]] * (W[r[0]][o[1]] * W[r[1]][o[2]] - W[r[1]][o[1]] * W[r[0]][o[2]]);
+                    const T d = u0[r[0]] * (u1[r[1]] * u2[r[2]] - u1[r[2]] * u2[r[1]]) -
+                                u0[r[1]] * (u1[r[0]] * u2[r[2]] - u1[r[2]] * u2[r[0]]) +
+                                u0[r[2]] * (u1[r[0]] * u2[r[1]] - u1[r[1]] * u2[r[0]]);
                     cv[i] = (i & 1) ? -d : d;
                 }
             }
@@ -575,12 +595,14 @@ __device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const T (&V)[n][n], 
 #pragma unroll
             for (int i = 0; i < n; ++i) {
                 cn += cv[i] * cv[i];
-                dt += cv[i] * W[i][jm];
+                dt += cv[i] * wm[i];
             }
             if (cn > (T)0) {
                 const T inv = (dt < (T)0 ? (T)-1 : (T)1) * num<T>::rsq(cn);
 #pragma unroll
-                for (int i = 0; i < n; ++i) W[i][jm] = cv[i] * inv;
+                for (int i = 0; i < n; ++i)
+#pragma unroll
+                    for (int j = 0; j < n; ++j) W[i][j] = jm == j ? cv[i] * inv : W[i][j];
             }
         }
     }
@@ -628,9 +650,9 @@ __device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const T (&V)[n][n], 
             T v = 0;
 #pragma unroll
             for (int j = 0; j < n; ++j) v += W[i][j] * V[k][j];
-            q[i * n + k] = v;
+            q[i * n + k] = (Tq)v;
         }
-    T dq = det_n<T, n>(q);
+    Tq dq = det_n<Tq, n>(q);
     if (lastz >= 0 && dq < (T)0) {
         // the completed direction's sign is free: choose det Q = +1
 #pragma unroll
@@ -646,11 +668,11 @@ __device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const T (&V)[n][n], 
                 T v = 0;
 #pragma unroll
                 for (int j = 0; j < n; ++j) v += W[i][j] * V[k][j];
-                q[i * n + k] = v;
+                q[i * n + k] = (Tq)v;
             }
         dq = -dq;
     }
-    dsign = dq >= (T)0 ? 1 : -1;
+    dsign = dq >= (Tq)0 ? 1 : -1;
 }
 
 
@@ -715,6 +737,103 @@ __device__ __forceinline__ void polar_jacobi_warm(const double* a_in, const floa
         }
     jacobi_sweeps<double, n>(W, V);
     jacobi_finish<double, n>(W, V, ex, q, dsign, smin);
+}
+
+// An n x n matrix in LDS, one per lane of a wave: entry (i, j) of the lane's
+// matrix at p[(i n + j) * 64] (consecutive lanes, consecutive words).  Accesses
+// are volatile, so the matrix stays in LDS instead of taking registers.
+template <typename T, int n>
+struct LdsMat {
+    typedef __attribute__((address_space(3))) volatile T elem;  // in LDS: ds_ instructions
+    elem* p;
+    __device__ __forceinline__ explicit LdsMat(T* lds) : p((elem*)lds) {}
+    struct Row {
+        elem* r;
+        __device__ __forceinline__ elem& operator[](int j) const { return r[j * 64]; }
+    };
+    __device__ __forceinline__ Row operator[](int i) const { return Row{p + i * n * 64}; }
+};
+
+// polar_jacobi in float with V kept in LDS, for a wave whose register budget is
+// set by the rest of its kernel.  With fb set it is polar_jacobi_f32_fb: when
+// the smallest singular value is below sigma_fb it stops before forming Q and
+// returns true, V holding the right singular vectors that warm-start the double
+// run.  Otherwise the same arithmetic as polar_jacobi<float, n>.
+template <int n>
+__device__ __forceinline__ bool polar_jacobi_f32_lds(const float* a, float* q, int& dsign, LdsMat<float, n> V,
+                                                     bool fb, double sigma_fb)
+{
+    const int ex = scale_exponent<float, n>(a);
+    float W[n][n];
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            W[i][j] = ldexp(a[i * n + j], -ex);
+            V[i][j] = (i == j) ? 1.0f : 0.0f;
+        }
+    jacobi_sweeps<float, n>(W, V);
+    if (fb) {
+        float s2 = 0;
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            float v = 0;
+#pragma unroll
+            for (int i = 0; i < n; ++i) v += W[i][j] * W[i][j];
+            s2 = (j == 0 || v < s2) ? v : s2;
+        }
+        if ((double)ldexp(num<float>::sqrt_(s2), ex) < sigma_fb) return true;
+    }
+    float smin;
+    jacobi_finish<float, n>(W, V, ex, q, dsign, smin);
+    return false;
+}
+
+// polar_jacobi_warm with both the float V0 it starts from and its double V in
+// LDS, and the result rounded to float: the same arithmetic with about a third
+// of the registers.  The sign of det Q is taken from the rounded Q (orthogonal:
+// |det| = 1 up to rounding).
+template <int n>
+__device__ __forceinline__ void polar_jacobi_warm_lds(const float* a_in, LdsMat<float, n> V0, LdsMat<double, n> V,
+                                                      float* q, int& dsign)
+{
+    // the float entries widen exactly, so the float exponent is the double one
+    // and the products below read them directly (no double copy of A)
+    const int ex = scale_exponent<float, n>(a_in);
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int j = 0; j < n; ++j) V[i][j] = (double)V0[i][j];
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+#pragma unroll
+        for (int k = 0; k < j; ++k) {
+            double d = 0;
+#pragma unroll
+            for (int i = 0; i < n; ++i) d += V[i][k] * V[i][j];
+#pragma unroll
+            for (int i = 0; i < n; ++i) V[i][j] = V[i][j] - d * V[i][k];
+        }
+        double nn = 0;
+#pragma unroll
+        for (int i = 0; i < n; ++i) nn += V[i][j] * V[i][j];
+        const double inv = num<double>::rsq(nn);
+#pragma unroll
+        for (int i = 0; i < n; ++i) V[i][j] = V[i][j] * inv;
+    }
+    double W[n][n];
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            double v = 0;
+#pragma unroll
+            for (int k = 0; k < n; ++k) v += (double)a_in[i * n + k] * V[k][j];
+            W[i][j] = ldexp(v, -ex);
+        }
+    jacobi_sweeps<double, n>(W, V);
+    double smin;
+    jacobi_finish<double, n, LdsMat<double, n>, float>(W, V, ex, q, dsign, smin);
 }
 
 // Closest orthogonal matrix of a (n*n values).  Returns sgn det Q and the

@@ -158,6 +158,8 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
     T* lr = reinterpret_cast<T*>(smem_raw);
     T* li = lr + (size_t)S::LINES * LP;
     __shared__ unsigned short fq[HELPER ? S::P : 1];
+    __shared__ double hvd[HELPER ? NN * 64 : 1];  // the helper lanes' V, double
+    __shared__ float hvf[HELPER ? NN * 64 : 1];   // and float
     __shared__ int fq_n;
     __shared__ unsigned long long wg_cnt[2];
 
@@ -198,15 +200,17 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
         }
     };
     if ((flags & RF_INVERSE) && fft_thread) load_line(g);
-    if (fft_thread && (flags & (RF_INVERSE | RF_FORWARD)))
-        load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
+    if (fft_thread && (flags & RF_INVERSE)) load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
     int8_t* sgn = a.sgn + (size_t)b * npts;
-    int8_t s_old[PPT];
+    // previous det signs of the thread's points, a byte each (a register, not
+    // an array: the projection loops index it at run time)
+    unsigned s_old = 0;
 #pragma unroll
     for (int pp = 0; pp < PPT; ++pp) {
         const int idx = pp * 512 + tid;
         const bool live = tid < 512 && row0 + (idx >> LOG2L) < a.rows;
-        s_old[pp] = (live && (flags & RF_SIGN)) ? sgn[(row0 + (idx >> LOG2L)) * L + (idx & (L - 1))] : (int8_t)0;
+        const int8_t so = (live && (flags & RF_SIGN)) ? sgn[(row0 + (idx >> LOG2L)) * L + (idx & (L - 1))] : (int8_t)0;
+        s_old |= (unsigned)(uint8_t)so << (8 * pp);
     }
     const int stop = (flags & RF_CHECK_STOP) ? a.stop_iter[b] : a.iter;
 
@@ -340,7 +344,7 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
                     T qv[NN];
                     int ds;
                     newton3_run(ns, qv, ds);
-                    finish(xp, lrq, liq, qv, ds, s_old[pp]);
+                    finish(xp, lrq, liq, qv, ds, (int8_t)(s_old >> (8 * pp)));
                 }
             } else if (tid >= NT) {
                 // the helper wave: Jacobi in float, and in double (warm-started
@@ -356,20 +360,14 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
                     float aq[NN], qv[NN];
                     load_point(lrq, liq, aq);
                     int ds;
-                    if (fallback) {
-                        float V[n][n];
-                        if (polar_jacobi_f32_fb<n>(aq, qv, ds, V, a.sigma_fb)) {
-                            double ad[NN], qd[NN], smd;
-#pragma unroll
-                            for (int k = 0; k < NN; ++k) ad[k] = (double)aq[k];
-                            polar_jacobi_warm<n>(ad, V, qd, ds, smd);
-#pragma unroll
-                            for (int k = 0; k < NN; ++k) qv[k] = (float)qd[k];
-                            ++nfb;
-                        }
-                    } else {
-                        float smin;
-                        polar_jacobi<float, n>(aq, qv, ds, smin);
+                    // the Jacobi routes keep V in LDS: in registers they would
+                    // raise the kernel's register peak past its occupancy's
+                    // budget, and the spills would put every wave's launch
+                    // behind a scratch allocation
+                    const LdsMat<float, n> vf(hvf + lane);
+                    if (polar_jacobi_f32_lds<n>(aq, qv, ds, vf, fallback, a.sigma_fb)) {
+                        polar_jacobi_warm_lds<n>(aq, vf, LdsMat<double, n>(hvd + lane), qv, ds);
+                        ++nfb;
                     }
                     finish(xp, lrq, liq, qv, ds, (flags & RF_SIGN) ? sgn[xp] : (int8_t)0);
                 }
@@ -386,7 +384,7 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
                     nbad += all_finite<T, NN>(av) ? 0ull : 1ull;
                     int ds;
                     if (project_point_fb<T, n>(av, qv, ds, fallback, a.sigma_fb)) ++nfb;
-                    finish(xp, lrq, liq, qv, ds, s_old[pp]);
+                    finish(xp, lrq, liq, qv, ds, (int8_t)(s_old >> (8 * pp)));
                 }
             }
         }
@@ -395,6 +393,11 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
 
     // ---- phase 3: forward FFT of the lines, store the kept modes
     if (flags & RF_FORWARD) {
+        // the twiddles again (a hit in cache), into a fresh variable: the
+        // values of phase 1 kept alive across the projection would raise its
+        // register peak above what the kernel's occupancy allows
+        Twiddles<T, LOG2L> tw3;
+        if (fft_thread) load_twiddles<T, LOG2L>(tw3, reinterpret_cast<const C*>(a.tw), t);
 #pragma unroll 1
         for (int rd = 0; rd < ROUNDS; ++rd) {
             const int j = rd * G + g;
@@ -402,20 +405,21 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
             const int rl = j / PL, pl = j - (j / PL) * PL;
             T* lrj = lr + (size_t)(act ? j : 0) * LP;
             T* lij = li + (size_t)(act ? j : 0) * LP;
+            T r3[1][8], im3[1][8];  // fresh, as tw3
             if (act) {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    r[0][e] = lrj[lds_pad_at<Tn>(t, pt, e)];
-                    im[0][e] = lij[lds_pad_at<Tn>(t, pt, e)];
+                    r3[0][e] = lrj[lds_pad_at<Tn>(t, pt, e)];
+                    im3[0][e] = lij[lds_pad_at<Tn>(t, pt, e)];
                 }
             }
             if constexpr (S::WAVE_LINE) {
                 if (act) {
                     wave_lds_sync();  // every lane has read its elements before the exchanges
-                    fft_wave<T, -1, LOG2L>(r[0], im[0], lrj, lij, t, tw, true);
+                    fft_wave<T, -1, LOG2L>(r3[0], im3[0], lrj, lij, t, tw3, true);
                 }
             } else {
-                fft_lines<T, -1, 1, LOG2L>(r, im, lrj, lij, 0, 1, 0, t, tw, act);
+                fft_lines<T, -1, 1, LOG2L>(r3, im3, lrj, lij, 0, 1, 0, t, tw3, act);
             }
             if (act && row0 + rl < a.rows) {
                 C* zr = Zb + ((size_t)pl * a.rows + row0 + rl) * W;
@@ -425,8 +429,8 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
                 for (int e = 0; e < 8; ++e) {
                     const int kx = t + e * Tn;
                     C v;
-                    v.x = r[0][e];
-                    v.y = im[0][e];
+                    v.x = r3[0][e];
+                    v.y = im3[0][e];
                     if (kx < W - c) {
                         if (kx > c) { v.x = 0; v.y = 0; }
                         zr[kx] = v;

@@ -137,8 +137,9 @@ def test_batched_configuration(torch_cuda):
     """The batched configuration at full size: 64 fields (seed 3) of n in {2,3,4},
     grids 128^2..1024^2, log-uniform tau, 50 FP32 iterations in one graph, tiles
     chosen by the autotuner.  Every field equals its single-field run within FP32
-    rounding (bitwise where the launch shapes agree), is orthogonal at every
-    point, and its energy does not increase from s = 1 (FP32 slack)."""
+    rounding (bitwise where the launch shapes agree; its logged energy within the
+    rounding of the float energy terms), is orthogonal at every point, and its
+    energy does not increase from s = 1 (FP32 slack)."""
     torch = torch_cuda
     bw = inputs.BatchedWorkload()
     spec = [(m.grid, m.n, m.tau) for m in bw.members]
@@ -157,7 +158,12 @@ def test_batched_configuration(torch_cuda):
         assert diff <= 1e-5, (i, diff)
         E = r["energy"][i]
         assert np.all(np.diff(E[1:]) <= 1e-5 * abs(E[1]) + 1e-6)
-        assert abs(E[-1] - rs["energy"][0][-1]) <= 1e-5 * abs(E[-1])
+        # the logged energy (1/tau)(n - <A, HA>) is summed from float terms
+        # (about 8 per thread before the double reduction): launch shapes that
+        # differ (the autotuner's tiles against the single run's rule) change
+        # its rounding by up to about 8 n u_32 / tau
+        noise = 8 * m.n * 2.0 ** -23 / m.tau
+        assert abs(E[-1] - rs["energy"][0][-1]) <= 1e-5 * abs(E[-1]) + noise, (i, E[-1], rs["energy"][0][-1])
         M = outs[i].double().reshape(m.n, m.n, -1).permute(2, 0, 1)
         I = torch.eye(m.n, dtype=torch.float64, device="cuda")
         assert (M.transpose(1, 2).contiguous() @ M.contiguous() - I).abs().max().item() < 1e-5
