@@ -425,8 +425,9 @@ bool fast_layout(int64_t N0, int64_t N1, int n, int pk, const double* taus, int6
 {
     if (N1 < 8 || N1 > 2048 || N0 < 64 || N0 > 2048) return false;
     // the row pass keeps a workgroup's lines (512 points, or one row) in LDS
-    // beside its static arrays (the helper's queue, at most 4 KiB)
-    if (row_fast_lds_bytes(pk, n, ilog2((int)N1)) + 4352 > lds_max) return false;
+    // beside its static arrays (the helper wave's queue and matrices, at most
+    // 12 KiB)
+    if (row_fast_lds_bytes(pk, n, ilog2((int)N1)) + 12288 > lds_max) return false;
     int c = (int)(N1 / 2), W = (int)N1;
     if (banded) {
         const double eta = pk == 1 ? 1e-12 : 1e-20;

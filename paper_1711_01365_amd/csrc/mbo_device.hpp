@@ -435,6 +435,35 @@ __device__ __forceinline__ void polar2(const T* a_in, T* q, int& dsign, T& smin)
     smin = ldexp(smax > (T)0 ? ad * num<T>::rcp(smax) : (T)0, ex);
 }
 
+// An n x n matrix in LDS, one per lane of a wave: entry (i, j) of the lane's
+// matrix at p[(i n + j) * 64] (consecutive lanes, consecutive words).  The
+// routes that use it call mat_fence between steps (a compiler memory barrier):
+// the entries are then re-read from LDS at each step instead of being kept in
+// registers across the loop, while the reads of one step are still issued
+// together.
+template <typename T, int n>
+struct LdsMat {
+    typedef __attribute__((address_space(3))) T elem;  // in LDS: ds_ instructions
+    elem* p;
+    __device__ __forceinline__ explicit LdsMat(T* lds) : p((elem*)lds) {}
+    struct Row {
+        elem* r;
+        __device__ __forceinline__ elem& operator[](int j) const { return r[j * 64]; }
+    };
+    __device__ __forceinline__ Row operator[](int i) const { return Row{p + i * n * 64}; }
+};
+
+template <typename VM>
+__device__ __forceinline__ void mat_fence(const VM&)
+{
+}
+
+template <typename T, int n>
+__device__ __forceinline__ void mat_fence(const LdsMat<T, n>&)
+{
+    asm volatile("" ::: "memory");
+}
+
 // One-sided (Hestenes) Jacobi: rotate pairs of columns of W = A until they are
 // mutually orthogonal (to working precision), accumulating the rotations in V;
 // then sigma_j = |w_j|, U = W Sigma^{-1} and Q = U V^t.
@@ -488,6 +517,7 @@ __device__ __forceinline__ void jacobi_sweeps(T (&W)[n][n], VM& V)
                     V[i][p] = c * vp - sn * vr;
                     V[i][r] = sn * vp + c * vr;
                 }
+                mat_fence(V);
             }
         }
         if (!rotated || smax < sdone) break;
@@ -644,14 +674,16 @@ __device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const VM& V, int ex,
         }
     }
 #pragma unroll
-    for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
 #pragma unroll
-        for (int k = 0; k < n; ++k) {
+        for (int i = 0; i < n; ++i) {
             T v = 0;
 #pragma unroll
             for (int j = 0; j < n; ++j) v += W[i][j] * V[k][j];
             q[i * n + k] = (Tq)v;
         }
+        mat_fence(V);  // row k of V is not kept in registers beyond this
+    }
     Tq dq = det_n<Tq, n>(q);
     if (lastz >= 0 && dq < (T)0) {
         // the completed direction's sign is free: choose det Q = +1
@@ -662,14 +694,16 @@ __device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const VM& V, int ex,
             for (int i = 0; i < n; ++i) W[i][j] = -W[i][j];
         }
 #pragma unroll
-        for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) {
 #pragma unroll
-            for (int k = 0; k < n; ++k) {
+            for (int i = 0; i < n; ++i) {
                 T v = 0;
 #pragma unroll
                 for (int j = 0; j < n; ++j) v += W[i][j] * V[k][j];
                 q[i * n + k] = (Tq)v;
             }
+            mat_fence(V);
+        }
         dq = -dq;
     }
     dsign = dq >= (Tq)0 ? 1 : -1;
@@ -739,20 +773,6 @@ __device__ __forceinline__ void polar_jacobi_warm(const double* a_in, const floa
     jacobi_finish<double, n>(W, V, ex, q, dsign, smin);
 }
 
-// An n x n matrix in LDS, one per lane of a wave: entry (i, j) of the lane's
-// matrix at p[(i n + j) * 64] (consecutive lanes, consecutive words).  Accesses
-// are volatile, so the matrix stays in LDS instead of taking registers.
-template <typename T, int n>
-struct LdsMat {
-    typedef __attribute__((address_space(3))) volatile T elem;  // in LDS: ds_ instructions
-    elem* p;
-    __device__ __forceinline__ explicit LdsMat(T* lds) : p((elem*)lds) {}
-    struct Row {
-        elem* r;
-        __device__ __forceinline__ elem& operator[](int j) const { return r[j * 64]; }
-    };
-    __device__ __forceinline__ Row operator[](int i) const { return Row{p + i * n * 64}; }
-};
 
 // polar_jacobi in float with V kept in LDS, for a wave whose register budget is
 // set by the rest of its kernel.  With fb set it is polar_jacobi_f32_fb: when
@@ -772,6 +792,7 @@ __device__ __forceinline__ bool polar_jacobi_f32_lds(const float* a, float* q, i
             W[i][j] = ldexp(a[i * n + j], -ex);
             V[i][j] = (i == j) ? 1.0f : 0.0f;
         }
+    mat_fence(V);
     jacobi_sweeps<float, n>(W, V);
     if (fb) {
         float s2 = 0;
@@ -804,6 +825,7 @@ __device__ __forceinline__ void polar_jacobi_warm_lds(const float* a_in, LdsMat<
     for (int i = 0; i < n; ++i)
 #pragma unroll
         for (int j = 0; j < n; ++j) V[i][j] = (double)V0[i][j];
+    mat_fence(V);
 #pragma unroll
     for (int j = 0; j < n; ++j) {
 #pragma unroll
@@ -820,6 +842,7 @@ __device__ __forceinline__ void polar_jacobi_warm_lds(const float* a_in, LdsMat<
         const double inv = num<double>::rsq(nn);
 #pragma unroll
         for (int i = 0; i < n; ++i) V[i][j] = V[i][j] * inv;
+        mat_fence(V);
     }
     double W[n][n];
 #pragma unroll
@@ -831,6 +854,7 @@ __device__ __forceinline__ void polar_jacobi_warm_lds(const float* a_in, LdsMat<
             for (int k = 0; k < n; ++k) v += (double)a_in[i * n + k] * V[k][j];
             W[i][j] = ldexp(v, -ex);
         }
+    mat_fence(V);
     jacobi_sweeps<double, n>(W, V);
     double smin;
     jacobi_finish<double, n, LdsMat<double, n>, float>(W, V, ex, q, dsign, smin);

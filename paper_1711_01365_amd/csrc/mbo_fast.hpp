@@ -139,10 +139,19 @@ struct RowFastShape {
     static constexpr int ROUNDS = (LINES + G - 1) / G;
     static constexpr int THREADS = NT + (HELPER ? 64 : 0);
     static constexpr int LP = L + L / 8;  // padded LDS line
-    static constexpr size_t LDS = (size_t)LINES * LP * 2 * sizeof(T);
+    static constexpr size_t LDS_LINES = (size_t)LINES * LP * 2 * sizeof(T);
+    // the twiddle table staged in LDS, where it fits beside the lines and the
+    // static arrays (at most 12 KiB): one load per thread instead of 7 per
+    // radix-8 stage
+    static constexpr size_t TW_BYTES = (size_t)L * 2 * sizeof(T);
+    static constexpr bool TW_LDS = LDS_LINES + TW_BYTES + 12288 <= 163840;
+    static constexpr size_t LDS = LDS_LINES + (TW_LDS ? TW_BYTES : 0);
     // waves per SIMD the instance is compiled for: two 512-point workgroups
-    // per CU for short rows, one long-row workgroup
-    static constexpr int WAVES = WAVE_LINE ? (HELPER ? 5 : 4) : (THREADS + 255) / 256;
+    // per CU for short rows, one long-row workgroup.  A workgroup of nine waves
+    // puts three of them on one SIMD, and two such workgroups may put six on
+    // the same SIMD: with five waves' worth of registers the second would not
+    // fit beside the first and the grid would run as two rounds.
+    static constexpr int WAVES = WAVE_LINE ? (HELPER ? 6 : 4) : (THREADS + 255) / 256;
 };
 
 template <typename T, int n, int LOG2L>
@@ -200,7 +209,15 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
         }
     };
     if ((flags & RF_INVERSE) && fft_thread) load_line(g);
-    if (fft_thread && (flags & RF_INVERSE)) load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
+    const C* twg = reinterpret_cast<const C*>(a.tw);
+    C* twl = reinterpret_cast<C*>(smem_raw + S::LDS_LINES);
+    if constexpr (S::TW_LDS) {
+        if (flags & (RF_INVERSE | RF_FORWARD)) {
+            for (int m = tid; m < L; m += S::THREADS) twl[m] = twg[m];
+            __syncthreads();
+        }
+    }
+    if (fft_thread && (flags & RF_INVERSE)) load_twiddles<T, LOG2L>(tw, S::TW_LDS ? twl : twg, t);
     int8_t* sgn = a.sgn + (size_t)b * npts;
     // previous det signs of the thread's points, a byte each (a register, not
     // an array: the projection loops index it at run time)
@@ -362,8 +379,8 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
                     int ds;
                     // the Jacobi routes keep V in LDS: in registers they would
                     // raise the kernel's register peak past its occupancy's
-                    // budget, and the spills would put every wave's launch
-                    // behind a scratch allocation
+                    // budget (spills, or a second workgroup that no longer fits
+                    // on the CU)
                     const LdsMat<float, n> vf(hvf + lane);
                     if (polar_jacobi_f32_lds<n>(aq, qv, ds, vf, fallback, a.sigma_fb)) {
                         polar_jacobi_warm_lds<n>(aq, vf, LdsMat<double, n>(hvd + lane), qv, ds);
@@ -393,11 +410,11 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
 
     // ---- phase 3: forward FFT of the lines, store the kept modes
     if (flags & RF_FORWARD) {
-        // the twiddles again (a hit in cache), into a fresh variable: the
+        // the twiddles again (from LDS or cache), into a fresh variable: the
         // values of phase 1 kept alive across the projection would raise its
         // register peak above what the kernel's occupancy allows
         Twiddles<T, LOG2L> tw3;
-        if (fft_thread) load_twiddles<T, LOG2L>(tw3, reinterpret_cast<const C*>(a.tw), t);
+        if (fft_thread) load_twiddles<T, LOG2L>(tw3, S::TW_LDS ? twl : twg, t);
 #pragma unroll 1
         for (int rd = 0; rd < ROUNDS; ++rd) {
             const int j = rd * G + g;
@@ -472,6 +489,17 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
 // Column pass over the stored columns
 // ---------------------------------------------------------------------------
 
+// Dynamic LDS of a heat_fast workgroup: the TX padded lines, then the twiddle
+// table when it fits.
+template <typename T, int LOG2L, int TX>
+struct HeatFastShape {
+    static constexpr int L = 1 << LOG2L;
+    static constexpr size_t LINES = (size_t)TX * (L + L / 8) * 2 * sizeof(T);
+    static constexpr size_t TW_BYTES = (size_t)L * 2 * sizeof(T);
+    static constexpr bool TW_LDS = LINES + TW_BYTES <= 159744;
+    static constexpr size_t LDS = LINES + (TW_LDS ? TW_BYTES : 0);
+};
+
 template <typename T, int LOG2L, int TX>
 __global__ void __launch_bounds__(TX * (1 << LOG2L) / 8) heat_fast(const FastColArgs a)
 {
@@ -507,8 +535,17 @@ __global__ void __launch_bounds__(TX * (1 << LOG2L) / 8) heat_fast(const FastCol
     T lam[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) lam[e] = lrow[t + e * Tn];
+    // the twiddle table staged in LDS after the tile's lines where it fits:
+    // 8/TX loads per thread instead of 7 per radix-8 stage
+    const C* twg = reinterpret_cast<const C*>(a.tw);
+    C* twl = reinterpret_cast<C*>(li + (size_t)TX * LP);
+    if constexpr (HeatFastShape<T, LOG2L, TX>::TW_LDS) {
+#pragma unroll
+        for (int m = tid; m < L; m += TX * Tn) twl[m] = twg[m];
+        __syncthreads();
+    }
     Twiddles<T, LOG2L> tw;
-    load_twiddles<T, LOG2L>(tw, reinterpret_cast<const C*>(a.tw), t);
+    load_twiddles<T, LOG2L>(tw, HeatFastShape<T, LOG2L, TX>::TW_LDS ? twl : twg, t);
     const bool marks = a.iter > 0 && a.stop_iter;
     const int stop = marks ? a.stop_iter[b] : a.iter;
     const bool check_tol = marks && a.delta_bits && a.tol > 0.0 && a.iter >= 2;

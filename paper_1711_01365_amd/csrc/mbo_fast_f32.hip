@@ -43,10 +43,5 @@ size_t row_fast_lds_bytes(int prec, int n, int log2L)
 
 int row_fast_rows_per_group(int log2L) { return log2L >= 9 ? 1 : 512 >> log2L; }
 
-size_t heat_fast_lds_bytes(int prec, int log2L, int TX)
-{
-    const int L = 1 << log2L;
-    return (size_t)TX * (L + L / 8) * 2 * (prec == 1 ? 4 : 8);
-}
 
 }  // namespace mbo

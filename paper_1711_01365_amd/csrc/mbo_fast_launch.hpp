@@ -62,7 +62,7 @@ static hipError_t heat_fast_go(const FastColArgs& a, dim3 g, hipStream_t st, boo
     if constexpr (NT < 64 || NT > 1024) {
         return hipErrorInvalidValue;
     } else {
-        const size_t lds = (size_t)TX * ((1 << LG) + (1 << LG) / 8) * 2 * sizeof(T);
+        const size_t lds = HeatFastShape<T, LG, TX>::LDS;
         const void* f = reinterpret_cast<const void*>(&heat_fast<T, LG, TX>);
         if (prepare) return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (ev0) hipExtLaunchKernelGGL((heat_fast<T, LG, TX>), g, dim3(NT), lds, st, ev0, ev1, 0, a);

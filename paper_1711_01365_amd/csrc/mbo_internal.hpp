@@ -423,9 +423,8 @@ bool fast_layout(int64_t N0, int64_t N1, int n, int pk, const double* taus, int6
 // message of a failed plan-less call, returned by mbo_last_error(NULL) (fixed
 // buffer: allocates nothing)
 void report_static_error(const char* fmt, ...);
-// dynamic LDS bytes and rows of a row_fast workgroup, LDS bytes of a heat_fast workgroup
+// dynamic LDS bytes and rows of a row_fast workgroup
 size_t row_fast_lds_bytes(int prec, int n, int log2L);
 int row_fast_rows_per_group(int log2L);
-size_t heat_fast_lds_bytes(int prec, int log2L, int TX);
 
 }  // namespace mbo
