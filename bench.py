@@ -61,7 +61,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "row_pass_n3_512x512_f32fb_traffic.txt")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "row_fast_n3_512x512_f32fb_traffic.txt")
 
 
 def log(*a):
@@ -69,8 +69,8 @@ def log(*a):
 
 
 # sources that decide the row pass's code and launch shape (its traffic)
-ROW_PASS_SOURCES = ("mbo_device.hpp", "mbo_kernels.hpp", "mbo_internal.hpp", "mbo_volume.hpp",
-                    "mbo_row_f32.hip", "mbo_api.cpp")
+ROW_PASS_SOURCES = ("mbo_device.hpp", "mbo_kernels.hpp", "mbo_internal.hpp", "mbo_fast.hpp",
+                    "mbo_fast_launch.hpp", "mbo_fast_f32.hip", "mbo_api.cpp")
 
 
 def kernel_source_hash() -> str:
@@ -123,6 +123,7 @@ def run_gpu(w, precision, steps, warmup, timing_steps, autotune=True):
     A = A0.clone()
     plan = mbo.Plan(w.grid, w.n, w.tau, precision=precision)
     tuning = plan.autotune() if autotune else plan.tuning()
+    path = plan.path()
     for _ in range(warmup):
         A.copy_(A0)
         plan.iterate(A, w.iters)
@@ -158,6 +159,8 @@ def run_gpu(w, precision, steps, warmup, timing_steps, autotune=True):
                          "lines_per_heat_workgroup": tuning[2], "xcd_tile_order": tuning[3],
                          "autotuned": bool(autotune)},
         "flips_first": int(logs["flips"][0][0]),
+        "path": {"kind": {0: "generic", 1: "full", 2: "banded"}[path[0]], "half_width": path[1],
+                 "stored_modes": path[2]},
     }
 
 
@@ -604,8 +607,16 @@ def main():
     bytes_per_launch = 2 * w.n * w.n * 4 * w.points  # one read + one write of the FP32 field
     dominant_us = max(main_run["row_us"], main_run["heat_us"])
     dominant = "row_pass" if main_run["row_us"] >= main_run["heat_us"] else "heat_pass"
+    banded = main_run["path"]["kind"] != "generic"
+    kernel_name = {("row_pass", True): "row_fast<float, 3, 9>", ("row_pass", False): "row_pass<float, 3, 9, 0>",
+                   ("heat_pass", True): "heat_fast<float, 9, TX>",
+                   ("heat_pass", False): "col_pass<float, 2, 9>"}[(dominant, banded)]
     achieved = bytes_per_launch / (dominant_us * 1e-6) / 1e9
     traffic = read_traffic() if dominant == "row_pass" else None
+    # what the band-limited row pass moves: the kept modes of the five packed
+    # planes of every row, read and written (8 B each), and the det signs
+    pl = (w.n * w.n + 1) // 2
+    moved = 2 * pl * w.grid[0] * main_run["path"]["stored_modes"] * 8 + 2 * w.points
     out = {
         "metric": "MBO point-iterations/s (n=3, 512², FP32 vs FP64) + % of HBM peak",
         "value": main_run["value"],
@@ -622,10 +633,12 @@ def main():
         "config": {"workload": "n3_512x512_haar_tau2e-4_200it_f32_f64fallback", "n": 3,
                    "grid": [512, 512], "tau": 2e-4, "iterations": 200,
                    "precision": "f32 + f64 fallback (sigma_min < 1e-3)"},
-        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": kernel_name, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": dominant_us},
+                     "avg_launch_us": dominant_us,
+                     "moved_bytes_per_launch_model": moved if banded else bytes_per_launch},
+        "path": main_run["path"],
         "kernels_us": {"row_pass": main_run["row_us"], "heat_pass": main_run["heat_us"]},
         "fallback_points_total": main_run["fallbacks_total"],
         "launch_shape": main_run["launch_shape"],

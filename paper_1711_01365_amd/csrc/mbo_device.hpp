@@ -435,35 +435,6 @@ __device__ __forceinline__ void polar2(const T* a_in, T* q, int& dsign, T& smin)
     smin = ldexp(smax > (T)0 ? ad * num<T>::rcp(smax) : (T)0, ex);
 }
 
-// An n x n matrix in LDS, one per lane of a wave: entry (i, j) of the lane's
-// matrix at p[(i n + j) * 64] (consecutive lanes, consecutive words).  The
-// routes that use it call mat_fence between steps (a compiler memory barrier):
-// the entries are then re-read from LDS at each step instead of being kept in
-// registers across the loop, while the reads of one step are still issued
-// together.
-template <typename T, int n>
-struct LdsMat {
-    typedef __attribute__((address_space(3))) T elem;  // in LDS: ds_ instructions
-    elem* p;
-    __device__ __forceinline__ explicit LdsMat(T* lds) : p((elem*)lds) {}
-    struct Row {
-        elem* r;
-        __device__ __forceinline__ elem& operator[](int j) const { return r[j * 64]; }
-    };
-    __device__ __forceinline__ Row operator[](int i) const { return Row{p + i * n * 64}; }
-};
-
-template <typename VM>
-__device__ __forceinline__ void mat_fence(const VM&)
-{
-}
-
-template <typename T, int n>
-__device__ __forceinline__ void mat_fence(const LdsMat<T, n>&)
-{
-    asm volatile("" ::: "memory");
-}
-
 // One-sided (Hestenes) Jacobi: rotate pairs of columns of W = A until they are
 // mutually orthogonal (to working precision), accumulating the rotations in V;
 // then sigma_j = |w_j|, U = W Sigma^{-1} and Q = U V^t.
@@ -477,8 +448,8 @@ __device__ __forceinline__ void mat_fence(const LdsMat<T, n>&)
 // stops after a sweep without rotations, or after a sweep whose rotations all
 // had |s| < sdone (the inner products left are then of order s^2, below the
 // tolerance, so the confirming sweep is skipped).
-template <typename T, int n, typename VM>
-__device__ __forceinline__ void jacobi_sweeps(T (&W)[n][n], VM& V)
+template <typename T, int n>
+__device__ __forceinline__ void jacobi_sweeps(T (&W)[n][n], T (&V)[n][n])
 {
     constexpr T sdone = num<T>::sdone;
 #pragma unroll 1
@@ -517,7 +488,6 @@ __device__ __forceinline__ void jacobi_sweeps(T (&W)[n][n], VM& V)
                     V[i][p] = c * vp - sn * vr;
                     V[i][r] = sn * vp + c * vr;
                 }
-                mat_fence(V);
             }
         }
         if (!rotated || smax < sdone) break;
@@ -527,8 +497,8 @@ __device__ __forceinline__ void jacobi_sweeps(T (&W)[n][n], VM& V)
 // Q = U V^t from the orthogonalised columns W = U Sigma (scaled by 2^-ex).  On
 // return W holds U (completed for zero singular values) unless the matrix is
 // zero; sig (nullable) receives the singular values of the unscaled input.
-template <typename T, int n, typename VM, typename Tq = T>
-__device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const VM& V, int ex, Tq* q, int& dsign, T& smin,
+template <typename T, int n, typename Tq = T>
+__device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const T (&V)[n][n], int ex, Tq* q, int& dsign, T& smin,
                                               T* sig = nullptr)
 {
     T ss[n], sg[n];
@@ -674,16 +644,14 @@ __device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const VM& V, int ex,
         }
     }
 #pragma unroll
-    for (int k = 0; k < n; ++k) {
+    for (int i = 0; i < n; ++i)
 #pragma unroll
-        for (int i = 0; i < n; ++i) {
+        for (int k = 0; k < n; ++k) {
             T v = 0;
 #pragma unroll
             for (int j = 0; j < n; ++j) v += W[i][j] * V[k][j];
             q[i * n + k] = (Tq)v;
         }
-        mat_fence(V);  // row k of V is not kept in registers beyond this
-    }
     Tq dq = det_n<Tq, n>(q);
     if (lastz >= 0 && dq < (T)0) {
         // the completed direction's sign is free: choose det Q = +1
@@ -694,16 +662,14 @@ __device__ __forceinline__ void jacobi_finish(T (&W)[n][n], const VM& V, int ex,
             for (int i = 0; i < n; ++i) W[i][j] = -W[i][j];
         }
 #pragma unroll
-        for (int k = 0; k < n; ++k) {
+        for (int i = 0; i < n; ++i)
 #pragma unroll
-            for (int i = 0; i < n; ++i) {
+            for (int k = 0; k < n; ++k) {
                 T v = 0;
 #pragma unroll
                 for (int j = 0; j < n; ++j) v += W[i][j] * V[k][j];
                 q[i * n + k] = (Tq)v;
             }
-            mat_fence(V);
-        }
         dq = -dq;
     }
     dsign = dq >= (Tq)0 ? 1 : -1;
@@ -732,12 +698,15 @@ __device__ __forceinline__ void polar_jacobi(const T* a_in, T* q, int& dsign, T&
 // column-orthogonal, and the sweeps (rotations of order float rounding) run to
 // the double stopping rule: the points that come here may have an
 // ill-conditioned polar factor (2 / (sigma_{n-1} + sigma_n) up to ~1e7), which
-// would carry a looser stop into the float result.
+// would carry a looser stop into the float result.  A is read as float (its
+// entries widen exactly, so the products are those of a double copy and the
+// float exponent is the double one) and Q is rounded to float as it is formed;
+// the sign of det Q is taken from the rounded Q (orthogonal: |det| = 1 up to
+// rounding).  Both save the registers of a double copy.
 template <int n>
-__device__ __forceinline__ void polar_jacobi_warm(const double* a_in, const float (&V0)[n][n],
-                                                  double* q, int& dsign, double& smin)
+__device__ __forceinline__ void polar_jacobi_warm(const float* a_in, const float (&V0)[n][n], float* q, int& dsign)
 {
-    const int ex = scale_exponent<double, n>(a_in);
+    const int ex = scale_exponent<float, n>(a_in);
     double V[n][n], W[n][n];
 #pragma unroll
     for (int i = 0; i < n; ++i)
@@ -766,98 +735,12 @@ __device__ __forceinline__ void polar_jacobi_warm(const double* a_in, const floa
         for (int j = 0; j < n; ++j) {
             double v = 0;
 #pragma unroll
-            for (int k = 0; k < n; ++k) v += a_in[i * n + k] * V[k][j];
-            W[i][j] = ldexp(v, -ex);
-        }
-    jacobi_sweeps<double, n>(W, V);
-    jacobi_finish<double, n>(W, V, ex, q, dsign, smin);
-}
-
-
-// polar_jacobi in float with V kept in LDS, for a wave whose register budget is
-// set by the rest of its kernel.  With fb set it is polar_jacobi_f32_fb: when
-// the smallest singular value is below sigma_fb it stops before forming Q and
-// returns true, V holding the right singular vectors that warm-start the double
-// run.  Otherwise the same arithmetic as polar_jacobi<float, n>.
-template <int n>
-__device__ __forceinline__ bool polar_jacobi_f32_lds(const float* a, float* q, int& dsign, LdsMat<float, n> V,
-                                                     bool fb, double sigma_fb)
-{
-    const int ex = scale_exponent<float, n>(a);
-    float W[n][n];
-#pragma unroll
-    for (int i = 0; i < n; ++i)
-#pragma unroll
-        for (int j = 0; j < n; ++j) {
-            W[i][j] = ldexp(a[i * n + j], -ex);
-            V[i][j] = (i == j) ? 1.0f : 0.0f;
-        }
-    mat_fence(V);
-    jacobi_sweeps<float, n>(W, V);
-    if (fb) {
-        float s2 = 0;
-#pragma unroll
-        for (int j = 0; j < n; ++j) {
-            float v = 0;
-#pragma unroll
-            for (int i = 0; i < n; ++i) v += W[i][j] * W[i][j];
-            s2 = (j == 0 || v < s2) ? v : s2;
-        }
-        if ((double)ldexp(num<float>::sqrt_(s2), ex) < sigma_fb) return true;
-    }
-    float smin;
-    jacobi_finish<float, n>(W, V, ex, q, dsign, smin);
-    return false;
-}
-
-// polar_jacobi_warm with both the float V0 it starts from and its double V in
-// LDS, and the result rounded to float: the same arithmetic with about a third
-// of the registers.  The sign of det Q is taken from the rounded Q (orthogonal:
-// |det| = 1 up to rounding).
-template <int n>
-__device__ __forceinline__ void polar_jacobi_warm_lds(const float* a_in, LdsMat<float, n> V0, LdsMat<double, n> V,
-                                                      float* q, int& dsign)
-{
-    // the float entries widen exactly, so the float exponent is the double one
-    // and the products below read them directly (no double copy of A)
-    const int ex = scale_exponent<float, n>(a_in);
-#pragma unroll
-    for (int i = 0; i < n; ++i)
-#pragma unroll
-        for (int j = 0; j < n; ++j) V[i][j] = (double)V0[i][j];
-    mat_fence(V);
-#pragma unroll
-    for (int j = 0; j < n; ++j) {
-#pragma unroll
-        for (int k = 0; k < j; ++k) {
-            double d = 0;
-#pragma unroll
-            for (int i = 0; i < n; ++i) d += V[i][k] * V[i][j];
-#pragma unroll
-            for (int i = 0; i < n; ++i) V[i][j] = V[i][j] - d * V[i][k];
-        }
-        double nn = 0;
-#pragma unroll
-        for (int i = 0; i < n; ++i) nn += V[i][j] * V[i][j];
-        const double inv = num<double>::rsq(nn);
-#pragma unroll
-        for (int i = 0; i < n; ++i) V[i][j] = V[i][j] * inv;
-        mat_fence(V);
-    }
-    double W[n][n];
-#pragma unroll
-    for (int i = 0; i < n; ++i)
-#pragma unroll
-        for (int j = 0; j < n; ++j) {
-            double v = 0;
-#pragma unroll
             for (int k = 0; k < n; ++k) v += (double)a_in[i * n + k] * V[k][j];
             W[i][j] = ldexp(v, -ex);
         }
-    mat_fence(V);
     jacobi_sweeps<double, n>(W, V);
     double smin;
-    jacobi_finish<double, n, LdsMat<double, n>, float>(W, V, ex, q, dsign, smin);
+    jacobi_finish<double, n, float>(W, V, ex, q, dsign, smin);
 }
 
 // Closest orthogonal matrix of a (n*n values).  Returns sgn det Q and the
@@ -1101,12 +984,7 @@ __device__ __forceinline__ bool project_point_fb(const T* a, T* q, int& dsign, b
         if (fallback) {
             float V[n][n];
             if (!polar_jacobi_f32_fb<n>(a, q, dsign, V, sigma_fb)) return false;
-            double ad[NN], qd[NN], smd;
-#pragma unroll
-            for (int k = 0; k < NN; ++k) ad[k] = (double)a[k];
-            polar_jacobi_warm<n>(ad, V, qd, dsign, smd);
-#pragma unroll
-            for (int k = 0; k < NN; ++k) q[k] = (T)qd[k];
+            polar_jacobi_warm<n>(a, V, q, dsign);
             return true;
         }
     }

@@ -25,11 +25,10 @@
 //              fallback, non-finite and change diagnostics; the line groups
 //              forward-FFT and store the kept modes.  Float plans with n = 3
 //              run the Newton polar iteration on every point that is certainly
-//              well conditioned (1/|A^{-1}|_F > sigma_fb) and hand the others
-//              to one extra wave, raised in priority, that projects them by
-//              Jacobi (and in double when sigma_min < sigma_fb) while the other
-//              waves iterate, so the double work is off the row's critical
-//              path.
+//              well conditioned (1/|A^{-1}|_F > sigma_fb) and queue the others
+//              for the first wave done with its own points, which projects
+//              them by Jacobi (and in double when sigma_min < sigma_fb) at
+//              raised priority.
 //   heat_fast  a tile of TX stored columns of one packed plane: thread (t, cc)
 //              loads rows t + e L/8 of column cc (TX-wide coalesced segments),
 //              forward FFT along the column with workgroup exchanges, Lyapunov
@@ -118,8 +117,7 @@ __device__ __forceinline__ void newton3_run(Newton3& s, float* q, int& dsign)
 
 // Shape of a row-pass workgroup: 512 points (512/L rows) for L <= 512, one row
 // of L points otherwise; 512 projection threads (PPT points each); the line
-// groups of L/8 threads run in ROUNDS rounds of G lines over NT threads; float
-// n = 3 adds a helper wave (threads NT .. NT + 63).
+// groups of L/8 threads run in ROUNDS rounds of G lines over NT threads.
 template <typename T, int n, int LOG2L>
 struct RowFastShape {
     static constexpr int L = 1 << LOG2L;
@@ -132,26 +130,29 @@ struct RowFastShape {
     static constexpr int LINES = RPW * PL;
     static constexpr bool WAVE_LINE = LOG2L <= 9;
     static constexpr bool HELPER = sizeof(T) == 4 && n == 3;
-    static constexpr int NTMAX = 1024 - (HELPER ? 64 : 0);
+    // long rows: at most 768 threads for float n = 3 (twelve waves, a budget of
+    // 168 registers for the queued points' double Jacobi), else 1024
+    static constexpr int NTMAX = HELPER ? 768 : 1024;
     static constexpr int NT_LINES = LINES * Tn < NTMAX / Tn * Tn ? LINES * Tn : NTMAX / Tn * Tn;
     static constexpr int NT = WAVE_LINE ? 512 : (NT_LINES > 512 ? NT_LINES : 512);
     static constexpr int G = NT / Tn;  // lines per round
     static constexpr int ROUNDS = (LINES + G - 1) / G;
-    static constexpr int THREADS = NT + (HELPER ? 64 : 0);
+    static constexpr int THREADS = NT;
     static constexpr int LP = L + L / 8;  // padded LDS line
     static constexpr size_t LDS_LINES = (size_t)LINES * LP * 2 * sizeof(T);
     // the twiddle table staged in LDS, where it fits beside the lines and the
-    // static arrays (at most 12 KiB): one load per thread instead of 7 per
-    // radix-8 stage
+    // static arrays (the queue, at most 4 KiB; 12 KiB are reserved): one load
+    // per thread instead of 7 per radix-8 stage
     static constexpr size_t TW_BYTES = (size_t)L * 2 * sizeof(T);
     static constexpr bool TW_LDS = LDS_LINES + TW_BYTES + 12288 <= 163840;
     static constexpr size_t LDS = LDS_LINES + (TW_LDS ? TW_BYTES : 0);
     // waves per SIMD the instance is compiled for: two 512-point workgroups
-    // per CU for short rows, one long-row workgroup.  A workgroup of nine waves
-    // puts three of them on one SIMD, and two such workgroups may put six on
-    // the same SIMD: with five waves' worth of registers the second would not
-    // fit beside the first and the grid would run as two rounds.
-    static constexpr int WAVES = WAVE_LINE ? (HELPER ? 6 : 4) : (THREADS + 255) / 256;
+    // (eight waves each, two per SIMD) per CU for short rows, one long-row
+    // workgroup.  The register budget this leaves (128) holds the queued
+    // points' double Jacobi without spilling: any scratch use would delay the
+    // launch of the workgroups, and a ninth wave per workgroup would leave
+    // room for only one of them per CU at that budget.
+    static constexpr int WAVES = WAVE_LINE ? 4 : (THREADS + 255) / 256;
 };
 
 template <typename T, int n, int LOG2L>
@@ -167,9 +168,7 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
     T* lr = reinterpret_cast<T*>(smem_raw);
     T* li = lr + (size_t)S::LINES * LP;
     __shared__ unsigned short fq[HELPER ? S::P : 1];
-    __shared__ double hvd[HELPER ? NN * 64 : 1];  // the helper lanes' V, double
-    __shared__ float hvf[HELPER ? NN * 64 : 1];   // and float
-    __shared__ int fq_n;
+    __shared__ int fq_n, fq_claim;
     __shared__ unsigned long long wg_cnt[2];
 
     const int flags = a.flags;
@@ -177,6 +176,7 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
     const int tid = threadIdx.x;
     if (tid == 0) {
         fq_n = 0;
+        fq_claim = 0;
         wg_cnt[0] = 0;
         wg_cnt[1] = 0;
     }
@@ -330,7 +330,7 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
     if (flags & RF_PROJECT) {
         if constexpr (HELPER) {
             // which points are certainly well conditioned: the Newton
-            // iteration; the others are queued for the helper wave
+            // iteration; the others are queued
             Newton3 ns;       // kept from the test when each thread has one point
             unsigned ok = 0;  // bit pp: point pp runs Newton
 #pragma unroll 1
@@ -363,9 +363,17 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
                     newton3_run(ns, qv, ds);
                     finish(xp, lrq, liq, qv, ds, (int8_t)(s_old >> (8 * pp)));
                 }
-            } else if (tid >= NT) {
-                // the helper wave: Jacobi in float, and in double (warm-started
-                // from the float right singular vectors) when sigma_min < sigma_fb
+            }
+            // The queued points go to the first wave done with its own points
+            // (threads beyond the 512 projection threads, for long rows, have
+            // none): Jacobi in float, and in double (warm-started from the
+            // float right singular vectors) when sigma_min < sigma_fb.  A wave
+            // of its own would cost the registers that let two workgroups
+            // share a CU.
+            int claim = 0;
+            if ((tid & 63) == 0) claim = atomicAdd(&fq_claim, 1);
+            claim = __shfl(claim, 0, 64);
+            if (claim == 0) {
                 __builtin_amdgcn_s_setprio(3);
                 const int nq = fq_n;
                 const int lane = tid & 63;
@@ -377,14 +385,15 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
                     float aq[NN], qv[NN];
                     load_point(lrq, liq, aq);
                     int ds;
-                    // the Jacobi routes keep V in LDS: in registers they would
-                    // raise the kernel's register peak past its occupancy's
-                    // budget (spills, or a second workgroup that no longer fits
-                    // on the CU)
-                    const LdsMat<float, n> vf(hvf + lane);
-                    if (polar_jacobi_f32_lds<n>(aq, qv, ds, vf, fallback, a.sigma_fb)) {
-                        polar_jacobi_warm_lds<n>(aq, vf, LdsMat<double, n>(hvd + lane), qv, ds);
-                        ++nfb;
+                    if (fallback) {
+                        float V[n][n];
+                        if (polar_jacobi_f32_fb<n>(aq, qv, ds, V, a.sigma_fb)) {
+                            polar_jacobi_warm<n>(aq, V, qv, ds);
+                            ++nfb;
+                        }
+                    } else {
+                        float smin;
+                        polar_jacobi<float, n>(aq, qv, ds, smin);
                     }
                     finish(xp, lrq, liq, qv, ds, (flags & RF_SIGN) ? sgn[xp] : (int8_t)0);
                 }

@@ -447,19 +447,17 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L, RM>())) 
                     const int64_t x = (row0 + rloc) * L + (idx & (L - 1));
                     T* lrr = lr + (size_t)rloc * PL * lp + jx;
                     T* lir = li + (size_t)rloc * PL * lp + jx;
-                    double ad[NN], qd[NN], smd;
+                    float aq[NN];
                     float V[n][n];
 #pragma unroll
                     for (int k = 0; k < NN; ++k) {
-                        ad[k] = (double)((k & 1) ? lir[(k >> 1) * lp] : lrr[(k >> 1) * lp]);
+                        aq[k] = (k & 1) ? lir[(k >> 1) * lp] : lrr[(k >> 1) * lp];
                         // points beyond the stash start from V = I (a cold start)
                         V[k / n][k % n] = qi < SCAP ? fv[qi * NN + k] : (k / n == k % n ? 1.0f : 0.0f);
                     }
                     int ds;
-                    polar_jacobi_warm<n>(ad, V, qd, ds, smd);
                     T qv[NN];
-#pragma unroll
-                    for (int k = 0; k < NN; ++k) qv[k] = (T)qd[k];
+                    polar_jacobi_warm<n>(aq, V, qv, ds);
                     ++nfb;
                     finish(x, lrr, lir, qv, ds, (flags & RF_SIGN) ? sgn[x] : (int8_t)0);
                     if (flags & RF_STORE_REAL) {
