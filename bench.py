@@ -180,28 +180,20 @@ def run_control_2048():
 
 def run_3d(steps, warmup):
     """The 3-D configuration (n = 3, 128^3, 100 iterations, FP32 + FP64 fallback)
-    through the captured graph; point-iterations per second."""
-    import torch
+    through the captured graph; point-iterations per second.  Beside it the two
+    passes of an iteration (the row pass along the last axis with the
+    projection, the plane pass over the other two axes), timed with dispatch
+    events, and their algorithmic bandwidth (the field read once and written
+    once per pass)."""
     from paper_1711_01365_amd import inputs, mbo
     w = inputs.NORMAL_128_3D
-    A0 = torch.tensor(w.field(), dtype=torch.float32, device="cuda")
-    A = A0.clone()
-    plan = mbo.Plan(w.grid, w.n, w.tau, precision=mbo.F32_F64FALLBACK)
-    plan.autotune()
-    for _ in range(warmup):
-        A.copy_(A0)
-        plan.iterate(A, w.iters)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        A.copy_(A0)
-        plan.iterate(A, w.iters)
-    torch.cuda.synchronize()
-    sec = time.perf_counter() - t0
-    plan.close()
+    r = run_gpu(w, mbo.F32_F64FALLBACK, steps, warmup, timing_steps=2)
+    bpl = 2 * w.n * w.n * 4 * w.points
     return {"workload": "n3_128x128x128_normal_tau5e-4_100it_f32_f64fallback",
-            "value": w.points * w.iters * steps / sec, "unit": "point-iterations/s",
-            "ms_per_run": 1000.0 * sec / steps}
+            "value": r["value"], "unit": "point-iterations/s", "ms_per_run": r["ms_per_step"],
+            "row_us": r["row_us"], "plane_us": r["heat_us"], "bytes_per_launch": bpl,
+            "row_GBps": bpl / (r["row_us"] * 1e-6) / 1e9, "plane_GBps": bpl / (r["heat_us"] * 1e-6) / 1e9,
+            "path": r["path"], "fallbacks_total": r["fallbacks_total"]}
 
 
 def run_volume(w, steps, warmup):
@@ -555,6 +547,7 @@ def main():
                     help="also run the peanut of Section 6.3 (133 M samples; about a minute of host set-up)")
     ap.add_argument("--surface-only", action="store_true",
                     help="only the sphere legs, float surfaces (for profiling them)")
+    ap.add_argument("--only-3d", action="store_true", help="only the 3-D leg (for profiling it)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -579,6 +572,11 @@ def main():
             r = run_volume(wv, args.steps, args.warmup)
             log("volume-preserving %s: %.3e point-iter/s, %.1f us/iteration (plain %.1f us)"
                 % (wv.name, r["value"], r["us_per_iteration"], r["plain_mbo_us_per_iteration"]))
+        return
+    if args.only_3d:
+        r = run_3d(args.steps, args.warmup)
+        log("3-D %s: %.3e point-iter/s, row pass %.2f us (%.0f GB/s), plane pass %.2f us (%.0f GB/s)"
+            % (r["workload"], r["value"], r["row_us"], r["row_GBps"], r["plane_us"], r["plane_GBps"]))
         return
     if args.surface_only:
         r = run_surface(args.steps, (("f32_f64fallback", mbo.F32_F64FALLBACK),))["f32_f64fallback"]
@@ -654,8 +652,9 @@ def main():
             % (out["control_2048"]["value"], out["control_2048"]["row_us"], out["control_2048"]["row_GBps"],
                out["control_2048"]["heat_us"], out["control_2048"]["heat_GBps"]))
     if "3d" in legs:
-        out["config_3d"] = run_3d(3, 1)
-        log("3-D n=3 128^3 fp32+fallback: %.3e point-iter/s" % out["config_3d"]["value"])
+        out["config_3d"] = r = run_3d(3, 1)
+        log("3-D n=3 128^3 fp32+fallback: %.3e point-iter/s, row pass %.2f us (%.0f GB/s), plane pass "
+            "%.2f us (%.0f GB/s)" % (r["value"], r["row_us"], r["row_GBps"], r["plane_us"], r["plane_GBps"]))
     if "batched" in legs:
         out["batched"] = {"f32_autotuned": run_batched(mbo.F32, True, 3),
                           "f32_fixed_rules": run_batched(mbo.F32, False, 3),

@@ -169,6 +169,7 @@ struct mbo_plan_s {
     int band_c = 0, band_W = 0;
     int fast_tx = 0, tune_fast_tx = 0;
     void* lam_col = nullptr;
+    void* lam_y = nullptr;      // 3-D band-limited plane pass: axis-1 factor [N1] (per field with own tau)
     unsigned long long* cnt_part = nullptr;
     // counts of the last mbo_project: double re-projections, non-finite inputs
     int64_t last_fb = 0, last_bad = 0;  // row-pass counts per workgroup [batch][log_K][workgroups]
@@ -271,6 +272,7 @@ void destroy(mbo_plan_t p)
     free_dev(p->lam_row);
     free_dev(p->lam_inner);
     free_dev(p->lam_col);
+    free_dev(p->lam_y);
     free_dev(p->mu_row);
     free_dev(p->mu_inner);
     free_dev(p->dpart);
@@ -394,14 +396,21 @@ mbo_status build_laplace_tables(mbo_plan_t p)
 // smallest half-width that keeps this below eta; c = N1/2 keeps every mode.
 // The tail sum is accumulated from the top (the dropped modes are the
 // smallest terms), so it only grows as c decreases.
-int band_halfwidth(int64_t N0, int64_t N1, double tau, double eta)
+double axis_weight(int64_t N, double tau)
 {
     const double pi = 3.14159265358979323846;
-    double sy = 0.0;
-    for (int64_t m = 0; m < N0; ++m) {
-        const double k = (2 * m < N0) ? (double)m : (double)(m - N0);
-        sy += std::exp(-4.0 * pi * pi * tau * k * k);
+    double s = 0.0;
+    for (int64_t m = 0; m < N; ++m) {
+        const double k = (2 * m < N) ? (double)m : (double)(m - N);
+        s += std::exp(-4.0 * pi * pi * tau * k * k);
     }
+    return s;
+}
+
+// sy: the other axes' factors summed over all their modes (their product in 3-D)
+int band_halfwidth_w(double sy, int64_t N1, double tau, double eta)
+{
+    const double pi = 3.14159265358979323846;
     const int64_t h = N1 / 2;
     double tail = 0.0;  // sum over |kx| > c
     int64_t c = h;
@@ -414,6 +423,11 @@ int band_halfwidth(int64_t N0, int64_t N1, double tau, double eta)
         --c;
     }
     return (int)c;
+}
+
+int band_halfwidth(int64_t N0, int64_t N1, double tau, double eta)
+{
+    return band_halfwidth_w(axis_weight(N0, tau), N1, tau, eta);
 }
 
 }  // namespace
@@ -458,6 +472,41 @@ bool fast_layout(int64_t N0, int64_t N1, int n, int pk, const double* taus, int6
 
 namespace {
 
+// 3-D band-limited path (float plans): the row pass over the x rows and one
+// plane pass per (packed plane, stored x mode) holding the whole y-z plane in
+// LDS, so y and z planes of 64 or 128 points.  The kept x half-width bounds the
+// dropped symbol mass by eta with the y and z axes' summed factors.
+void config_fast3(mbo_plan_t p)
+{
+    const int64_t N0 = p->N[0], N1 = p->N[1], N2 = p->N[2];
+    if (p->pk != 1) return;
+    if ((N0 != 64 && N0 != 128) || (N1 != 64 && N1 != 128) || N2 < 8 || N2 > 2048) return;
+    if (row_fast_lds_bytes(p->pk, p->n, ilog2((int)N2)) + 12288 > p->lds_max) return;
+    if (plane_fast_lds_bytes(ilog2((int)N1), ilog2((int)N0)) > p->lds_max) return;
+    int c = (int)(N2 / 2), W = (int)N2;
+    if (p->path == MBO_PATH_BANDED) {
+        const double* taus = p->per_field_tau ? p->taus.data() : &p->tau;
+        const int64_t ntau = p->per_field_tau ? (int64_t)p->taus.size() : 1;
+        int cmax = 0;
+        for (int64_t i = 0; i < ntau; ++i) {
+            const double sy = axis_weight(N0, taus[i]) * axis_weight(N1, taus[i]);
+            const int ci = band_halfwidth_w(sy, N2, taus[i], 1e-12);
+            cmax = ci > cmax ? ci : cmax;
+        }
+        // the plane-major layout needs no alignment of W: a plane pass per
+        // kept mode, nothing for slots between the two halves of the band
+        const int Wb = 2 * cmax + 1;
+        if (Wb < N2) {
+            c = cmax;
+            W = Wb;
+        }
+    }
+    p->band_c = c;
+    p->band_W = W;
+    p->fast_tx = 1;
+    p->fast = true;
+}
+
 // Whether mbo_iterate runs the band-limited passes, and their layout: kept
 // half-width c and stored modes W per row (a multiple of 16, at least 2c + 1;
 // W = N1 when nothing would be saved), the heat tile width.
@@ -466,7 +515,11 @@ void config_fast(mbo_plan_t p)
     p->fast = false;
     p->band_c = (int)(p->N[p->d - 1] / 2);
     p->band_W = (int)p->N[p->d - 1];
-    if (p->path == MBO_PATH_GENERIC || p->d != 2) return;
+    if (p->path == MBO_PATH_GENERIC) return;
+    if (p->d == 3) {
+        config_fast3(p);
+        return;
+    }
     const double* taus = p->per_field_tau ? p->taus.data() : &p->tau;
     const int64_t ntau = p->per_field_tau ? (int64_t)p->taus.size() : 1;
     int c, W, tx;
@@ -485,9 +538,10 @@ void config_fast(mbo_plan_t p)
 mbo_status build_fast_tables(mbo_plan_t p)
 {
     free_dev(p->lam_col);
+    free_dev(p->lam_y);
     if (!p->fast) return MBO_OK;
     const int W = p->band_W, c = p->band_c;
-    const int64_t N1 = p->N[1];
+    const int64_t N1 = p->N[p->d - 1];
     const int64_t nt = p->per_field_tau ? p->batch : 1;
     const double pi = 3.14159265358979323846;
     std::vector<double> v;
@@ -507,7 +561,16 @@ mbo_status build_fast_tables(mbo_plan_t p)
         }
     }
     HIP_TRY(p, hipMalloc(&p->lam_col, v.size() * p->esz));
-    return upload(p, p->lam_col, v);
+    const mbo_status s = upload(p, p->lam_col, v);
+    if (s != MBO_OK || p->d != 3) return s;
+    // 3-D: the y factor, exp(-4 pi^2 tau ky^2) / N1 of the plane pass
+    std::vector<double> y;
+    for (int64_t b = 0; b < nt; ++b) {
+        std::vector<double> f = axis_symbol(p->N[1], p->per_field_tau ? p->taus[(size_t)b] : p->tau);
+        y.insert(y.end(), f.begin(), f.end());
+    }
+    HIP_TRY(p, hipMalloc(&p->lam_y, y.size() * p->esz));
+    return upload(p, p->lam_y, y);
 }
 
 // Twiddles exp(-2 pi i m / L), m < L, interleaved (re, im).
@@ -703,11 +766,15 @@ void prepare_fast_kernels(mbo_plan_t p)
     if (!p->fast) return;
     FastRowArgs r;
     std::memset(&r, 0, sizeof r);
-    (void)launch_row_fast(p->pk, p->n, ilog2((int)p->N[1]), r, dim3(1), nullptr, true);
+    (void)launch_row_fast(p->pk, p->n, ilog2((int)p->N[p->d - 1]), r, dim3(1), nullptr, true);
     FastColArgs h;
     std::memset(&h, 0, sizeof h);
-    for (int tx = 1; tx <= 16; tx *= 2)
-        (void)launch_heat_fast(p->pk, ilog2((int)p->N[0]), tx, h, dim3(1), nullptr, true);
+    if (p->d == 3) {
+        (void)launch_plane_fast(ilog2((int)p->N[1]), ilog2((int)p->N[0]), h, dim3(1), nullptr, true);
+    } else {
+        for (int tx = 1; tx <= 16; tx *= 2)
+            (void)launch_heat_fast(p->pk, ilog2((int)p->N[0]), tx, h, dim3(1), nullptr, true);
+    }
     (void)hipGetLastError();
 }
 
@@ -722,8 +789,9 @@ int energy_partials(mbo_plan_t p)
 // of 1024 or 2048 points, each).
 int fast_row_groups(mbo_plan_t p)
 {
-    const int64_t rows = p->npts / p->N[1];
-    const int rpw = row_fast_rows_per_group(ilog2((int)p->N[1]));
+    const int64_t L = p->N[p->d - 1];
+    const int64_t rows = p->npts / L;
+    const int rpw = row_fast_rows_per_group(ilog2((int)L));
     return (int)((rows + rpw - 1) / rpw);
 }
 
@@ -737,7 +805,8 @@ dim3 fast_heat_grid(mbo_plan_t p)
 int fast_energy_partials(mbo_plan_t p)
 {
     if (!p->fast) return 0;
-    const int nt = p->fast_tx * (int)(p->N[0] / 8);
+    const int nt = p->d == 3 ? plane_fast_threads(ilog2((int)p->N[1]), ilog2((int)p->N[0]))
+                             : p->fast_tx * (int)(p->N[0] / 8);
     return (int)fast_heat_grid(p).x * (nt / 64);
 }
 
@@ -828,12 +897,13 @@ FastRowArgs fast_row_args(mbo_plan_t p)
 {
     FastRowArgs a;
     std::memset(&a, 0, sizeof a);
-    a.L = (int)p->N[1];
+    a.L = (int)p->N[p->d - 1];
     a.band = p->band_c;
     a.W = p->band_W;
-    a.rows = p->N[0];
+    a.rows = p->npts / p->N[p->d - 1];
     a.npts = p->npts;
-    a.tw = p->tw[1];
+    a.tw = p->tw[p->d - 1];
+    a.plane_major = p->d == 3;
     a.Z = p->Z;
     a.sgn = p->sgn;
     a.sigma_fb = p->sigma_fb;
@@ -849,8 +919,14 @@ FastColArgs fast_col_args(mbo_plan_t p)
     a.L = (int)p->N[0];
     a.W = p->band_W;
     a.tiles = p->band_W / p->fast_tx;
-    a.field_elems = (int64_t)p->PL * p->N[0] * p->band_W;
+    a.field_elems = (int64_t)p->PL * (p->npts / p->N[p->d - 1]) * p->band_W;
     a.tw = p->tw[0];
+    if (p->d == 3) {
+        a.Ny = (int)p->N[1];
+        a.tw_y = p->tw[1];
+        a.lam_y = p->lam_y;
+        a.lam_y_stride = p->per_field_tau ? p->N[1] : 0;
+    }
     a.Z = p->Z;
     a.lam_row = p->lam_row;
     a.lam_col = p->lam_col;
@@ -866,12 +942,14 @@ hipError_t run_row_fast(mbo_plan_t p, const FastRowArgs& a, hipStream_t st, hipE
                         hipEvent_t ev1 = nullptr)
 {
     const dim3 g((unsigned)fast_row_groups(p), (unsigned)p->batch);
-    return launch_row_fast(p->pk, p->n, ilog2((int)p->N[1]), a, g, st, false, ev0, ev1);
+    return launch_row_fast(p->pk, p->n, ilog2((int)p->N[p->d - 1]), a, g, st, false, ev0, ev1);
 }
 
 hipError_t run_heat_fast(mbo_plan_t p, const FastColArgs& a, hipStream_t st, hipEvent_t ev0 = nullptr,
                          hipEvent_t ev1 = nullptr)
 {
+    if (p->d == 3)
+        return launch_plane_fast(ilog2((int)p->N[1]), ilog2((int)p->N[0]), a, fast_heat_grid(p), st, false, ev0, ev1);
     return launch_heat_fast(p->pk, ilog2((int)p->N[0]), p->fast_tx, a, fast_heat_grid(p), st, false, ev0, ev1);
 }
 
@@ -1399,6 +1477,12 @@ mbo_status autotune_plan(mbo_plan_t p)
     if (he != hipSuccess) return done(fail(p, MBO_ERR_HIP, "hipEventCreate: %s", hipGetErrorString(he)));
     double best = 0.0, t = 0.0;
     if ((s = time_iterations(p, A, reps, e0, e1, &best)) != MBO_OK) return done(s);
+    if (p->fast && p->d == 3) {
+        // the 3-D band-limited passes have no launch shape to choose
+        p->err.clear();
+        p->tuned = true;
+        return done(MBO_OK);
+    }
     if (p->fast) {
         // band-limited passes: the heat tile width and the XCD-aware tile order
         int best_tx = p->fast_tx;

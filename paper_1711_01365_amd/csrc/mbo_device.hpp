@@ -191,6 +191,32 @@ __device__ __forceinline__ void load_twiddles(Twiddles<T, LOG2L>& tw,
     }
 }
 
+// The twiddle table itself as the source of a transform's twiddles: each
+// stage loads its seven values just before it (cache or LDS hits), so only one
+// stage's twiddles take registers at a time.
+template <typename T, int LOG2L>
+struct TwiddleTable {
+    const typename cx<T>::type* table;
+};
+
+template <typename T, int LOG2L, int STAGE>
+__device__ __forceinline__ void stage_twiddles(const Twiddles<T, LOG2L>& tw, int, typename cx<T>::type (&w)[7])
+{
+#pragma unroll
+    for (int j = 0; j < 7; ++j) w[j] = tw.w[STAGE - 1][j];
+}
+
+template <typename T, int LOG2L, int STAGE>
+__device__ __forceinline__ void stage_twiddles(const TwiddleTable<T, LOG2L>& tw, int t, typename cx<T>::type (&w)[7])
+{
+    typedef FftShape<LOG2L> F;
+    const int lp = F::log2span(STAGE);
+    const int k = t & ((1 << lp) - 1);
+    const int shift = LOG2L - 3 - lp;
+#pragma unroll
+    for (int j = 1; j < 8; ++j) w[j - 1] = tw.table[(j * k) << shift];
+}
+
 // Butterflies of a span-1 stage of radix R: butterfly b uses registers b + j*(8/R).
 template <typename T, int R, int S>
 __device__ __forceinline__ void stage_span1(T (&r)[8], T (&im)[8])
@@ -216,20 +242,31 @@ __device__ __forceinline__ void stage_tw8(T (&r)[8], T (&im)[8], const typename 
     dft8<T, S>(r, im);
 }
 
-template <typename T, int S, int NP, int LOG2L, int STAGE>
+// LDS element index of position j of a line: padded (one slot per eight) or
+// plain, for lines whose own stride already spreads them over the banks.
+template <bool PADJ>
+__device__ __forceinline__ int line_index(int j)
+{
+    return PADJ ? lds_pad(j) : j;
+}
+
+template <typename T, int S, int NP, int LOG2L, int STAGE, bool PADJ = true, typename TW = Twiddles<T, LOG2L>>
 __device__ __forceinline__ void fft_stages(T (&r)[NP][8], T (&im)[NP][8], T* lr, T* li, int lplane,
-                                           int lmul, int ladd, int t, const Twiddles<T, LOG2L>& tw,
-                                           bool act)
+                                           int lmul, int ladd, int t, const TW& tw, bool act)
 {
     typedef FftShape<LOG2L> F;
     if constexpr (STAGE < F::NST) {
         constexpr int R = F::radix(STAGE);
         constexpr int lp = F::log2span(STAGE);
         constexpr int p = 1 << lp;
+        if constexpr (STAGE == 0) {
 #pragma unroll
-        for (int pl = 0; pl < NP; ++pl) {
-            if constexpr (STAGE == 0) stage_span1<T, R, S>(r[pl], im[pl]);
-            else stage_tw8<T, S>(r[pl], im[pl], tw.w[STAGE - 1]);
+            for (int pl = 0; pl < NP; ++pl) stage_span1<T, R, S>(r[pl], im[pl]);
+        } else {
+            typename cx<T>::type w[7];
+            stage_twiddles<T, LOG2L, STAGE>(tw, t, w);
+#pragma unroll
+            for (int pl = 0; pl < NP; ++pl) stage_tw8<T, S>(r[pl], im[pl], w);
         }
         if constexpr (STAGE != F::NST - 1) {
             __syncthreads();  // earlier readers of the LDS lines are done
@@ -242,7 +279,7 @@ __device__ __forceinline__ void fft_stages(T (&r)[NP][8], T (&im)[NP][8], T* lr,
                     for (int b = 0; b < B; ++b)
 #pragma unroll
                         for (int q = 0; q < R; ++q) {
-                            const int a = pl * lplane + lds_pad((t + b * F::Tn) * R + q) * lmul + ladd;
+                            const int a = pl * lplane + line_index<PADJ>((t + b * F::Tn) * R + q) * lmul + ladd;
                             lr[a] = r[pl][b + q * B];
                             li[a] = im[pl][b + q * B];
                         }
@@ -253,7 +290,7 @@ __device__ __forceinline__ void fft_stages(T (&r)[NP][8], T (&im)[NP][8], T* lr,
                 for (int pl = 0; pl < NP; ++pl)
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
-                        const int a = pl * lplane + lds_pad(base + q * p) * lmul + ladd;
+                        const int a = pl * lplane + line_index<PADJ>(base + q * p) * lmul + ladd;
                         lr[a] = r[pl][q];
                         li[a] = im[pl][q];
                     }
@@ -264,12 +301,12 @@ __device__ __forceinline__ void fft_stages(T (&r)[NP][8], T (&im)[NP][8], T* lr,
                 for (int pl = 0; pl < NP; ++pl)
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
-                        const int a = pl * lplane + lds_pad(t + e * F::Tn) * lmul + ladd;
+                        const int a = pl * lplane + line_index<PADJ>(t + e * F::Tn) * lmul + ladd;
                         r[pl][e] = lr[a];
                         im[pl][e] = li[a];
                     }
             }
-            fft_stages<T, S, NP, LOG2L, STAGE + 1>(r, im, lr, li, lplane, lmul, ladd, t, tw, act);
+            fft_stages<T, S, NP, LOG2L, STAGE + 1, PADJ, TW>(r, im, lr, li, lplane, lmul, ladd, t, tw, act);
         }
     }
 }
@@ -341,15 +378,15 @@ __device__ __forceinline__ void fft_wave(T (&r)[8], T (&im)[8], T* lr, T* li, in
 }
 
 // In-place FFT of NP lines (S = -1 forward, +1 inverse, unscaled).  LDS element
-// j of line pl is at lr/li[pl*lplane + lds_pad(j)*lmul + ladd].  Every thread of
-// the workgroup must call it (it contains barriers); threads with act = false
-// only take part in the barriers and touch no LDS.
-template <typename T, int S, int NP, int LOG2L>
+// j of line pl is at lr/li[pl*lplane + lds_pad(j)*lmul + ladd] (j*lmul + ladd
+// with PADJ = false).  Every thread of the workgroup must call it (it contains
+// barriers); threads with act = false only take part in the barriers and touch
+// no LDS.
+template <typename T, int S, int NP, int LOG2L, bool PADJ = true, typename TW = Twiddles<T, LOG2L>>
 __device__ __forceinline__ void fft_lines(T (&r)[NP][8], T (&im)[NP][8], T* lr, T* li, int lplane,
-                                          int lmul, int ladd, int t, const Twiddles<T, LOG2L>& tw,
-                                          bool act = true)
+                                          int lmul, int ladd, int t, const TW& tw, bool act = true)
 {
-    fft_stages<T, S, NP, LOG2L, 0>(r, im, lr, li, lplane, lmul, ladd, t, tw, act);
+    fft_stages<T, S, NP, LOG2L, 0, PADJ, TW>(r, im, lr, li, lplane, lmul, ladd, t, tw, act);
 }
 
 // ---------------------------------------------------------------------------

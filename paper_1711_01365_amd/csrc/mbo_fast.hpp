@@ -180,9 +180,16 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
         wg_cnt[0] = 0;
         wg_cnt[1] = 0;
     }
-    const int64_t row0 = (int64_t)blockIdx.x * RPW;
     const int64_t npts = a.npts;
     const int W = a.W, c = a.band;
+    const bool pm = a.plane_major != 0;
+    // Plane by plane, a workgroup's loads and stores of one mode cover RPW
+    // consecutive rows, part of a cache line: the eight XCDs (own L2 each) then
+    // take contiguous runs of row groups, so that the groups sharing a line
+    // run on one XCD.
+    const int64_t nwgx = gridDim.x;
+    const int64_t row0 = RPW * (((nwgx & 7) || !pm) ? (int64_t)blockIdx.x
+                                                    : (int64_t)(blockIdx.x & 7) * (nwgx >> 3) + (blockIdx.x >> 3));
     C* Zb = reinterpret_cast<C*>(a.Z) + (size_t)b * PL * a.rows * W;
 
     // Every global load that does not depend on another is issued first (the
@@ -194,15 +201,33 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
     const bool fft_thread = tid < NT;
     Twiddles<T, LOG2L> tw;
     T r[1][8], im[1][8];
+    // Line j of a round is row rl, packed plane pl of the workgroup (LDS line
+    // rl*PL + pl).  Spectra are stored row by row (Z[plane][row][w]) or, for
+    // the 3-D plane pass, plane by plane (Z[plane][w][row]): there the lines
+    // of one plane go to neighbouring groups, so that a wave's stores of one
+    // mode cover consecutive rows.
+    auto line_of = [&](int j, int& rl, int& pl) {
+        if (pm) {
+            rl = j % RPW;
+            pl = j / RPW;
+        } else {
+            rl = j / PL;
+            pl = j - (j / PL) * PL;
+        }
+    };
+    auto zat = [&](int pl, int64_t row, int w) -> size_t {
+        return pm ? ((size_t)pl * W + w) * a.rows + row : ((size_t)pl * a.rows + row) * W + w;
+    };
     auto load_line = [&](int j) {
-        const int rl = j / PL, pl = j - (j / PL) * PL;
+        int rl, pl;
+        line_of(j, rl, pl);
         const bool live = j < S::LINES && row0 + rl < a.rows;
-        const C* zr = Zb + ((size_t)pl * a.rows + (live ? row0 + rl : 0)) * W;
+        const int64_t row = live ? row0 + rl : 0;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int w = band_slot(t + e * Tn, L, c, W);
             C v;
-            if (live && w >= 0) v = zr[w];
+            if (live && w >= 0) v = Zb[zat(pl, row, w)];
             else { v.x = 0; v.y = 0; }
             r[0][e] = v.x;
             im[0][e] = v.y;
@@ -238,8 +263,11 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
             const int j = rd * G + g;
             const bool act = fft_thread && j < S::LINES;
             if (rd > 0 && fft_thread) load_line(j);
-            T* lrj = lr + (size_t)(act ? j : 0) * LP;
-            T* lij = li + (size_t)(act ? j : 0) * LP;
+            int rl, pl;
+            line_of(j, rl, pl);
+            const int lj = act ? rl * PL + pl : 0;
+            T* lrj = lr + (size_t)lj * LP;
+            T* lij = li + (size_t)lj * LP;
             if constexpr (S::WAVE_LINE) {
                 if (act) {
                     fft_wave<T, +1, LOG2L>(r[0], im[0], lrj, lij, t, tw, true);
@@ -428,9 +456,11 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
         for (int rd = 0; rd < ROUNDS; ++rd) {
             const int j = rd * G + g;
             const bool act = fft_thread && j < S::LINES;
-            const int rl = j / PL, pl = j - (j / PL) * PL;
-            T* lrj = lr + (size_t)(act ? j : 0) * LP;
-            T* lij = li + (size_t)(act ? j : 0) * LP;
+            int rl, pl;
+            line_of(j, rl, pl);
+            const int lj = act ? rl * PL + pl : 0;
+            T* lrj = lr + (size_t)lj * LP;
+            T* lij = li + (size_t)lj * LP;
             T r3[1][8], im3[1][8];  // fresh, as tw3
             if (act) {
 #pragma unroll
@@ -448,7 +478,7 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
                 fft_lines<T, -1, 1, LOG2L>(r3, im3, lrj, lij, 0, 1, 0, t, tw3, act);
             }
             if (act && row0 + rl < a.rows) {
-                C* zr = Zb + ((size_t)pl * a.rows + row0 + rl) * W;
+                const int64_t row = row0 + rl;
                 // slots w < W - c take mode w (zero when w > c); slots w >= W - c
                 // take mode L - W + w
 #pragma unroll
@@ -459,9 +489,9 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
                     v.y = im3[0][e];
                     if (kx < W - c) {
                         if (kx > c) { v.x = 0; v.y = 0; }
-                        zr[kx] = v;
+                        Zb[zat(pl, row, kx)] = v;
                     } else if (kx >= L - c) {
-                        zr[W - L + kx] = v;
+                        Zb[zat(pl, row, W - L + kx)] = v;
                     }
                 }
             }
@@ -594,6 +624,172 @@ __global__ void __launch_bounds__(TX * (1 << LOG2L) / 8) heat_fast(const FastCol
         v.y = im[0][e];
         Zc[(int64_t)(t + e * Tn) * a.W] = v;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Plane pass of the 3-D iteration (float): the heat step along y and z
+// ---------------------------------------------------------------------------
+
+// One workgroup per (field, packed plane, stored x mode w): the N0 x N1 plane of
+// that mode, contiguous in Z[plane][w][z][y] as the row pass stores it for
+// 3-D, is loaded once, transformed along y and then z in LDS, its Lyapunov
+// partial taken, multiplied by lambda_z(kz) lambda_y(ky) lambda_x(w),
+// transformed back along z and y, and stored in place: the whole diffusion
+// between two row passes in one read and one write of the spectra.  Each
+// thread holds two lines of eight values.  The plane sits in LDS as complex
+// pairs (real and imaginary part side by side: one address per element) in
+// rows of odd pitch, so that the z lines spread over the banks.
+template <typename T, int LOG2Y, int LOG2Z>
+struct PlaneFastShape {
+    static constexpr int NY = 1 << LOG2Y, NZ = 1 << LOG2Z;
+    static constexpr int TY = NY / 8, TZ = NZ / 8;
+    static constexpr int THREADS = NY * NZ / 16;
+    static constexpr int PZ = NY + 1;  // row pitch in complex elements
+    // the plane, then the y and z twiddle tables
+    static constexpr size_t LDS = ((size_t)NZ * PZ + NY + NZ) * 2 * sizeof(T);
+};
+
+template <typename T, int LOG2Y, int LOG2Z>
+__global__ void __launch_bounds__((PlaneFastShape<T, LOG2Y, LOG2Z>::THREADS)) plane_fast(const FastColArgs a)
+{
+    typedef PlaneFastShape<T, LOG2Y, LOG2Z> S;
+    typedef typename cx<T>::type C;
+    constexpr int NY = S::NY, NZ = S::NZ, TY = S::TY, TZ = S::TZ, PZ = S::PZ;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lc = reinterpret_cast<T*>(smem_raw);  // element o: lc[2 o] (real), lc[2 o + 1] (imaginary)
+
+    const int b = blockIdx.y;
+    const int tid = threadIdx.x;
+    const int64_t wg = blockIdx.x;  // packed plane * W + stored mode
+    const int w = (int)(wg % a.W);
+    C* Zp = reinterpret_cast<C*>(a.Z) + (size_t)b * a.field_elems + (size_t)wg * NZ * NY;
+    // y lines: group gy takes z = gy and gy + NZ/2, lane ty elements y = ty + e TY
+    const int gy = tid / TY, ty = tid - gy * TY;
+    T r[2][8], im[2][8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const C v = Zp[(gy + h * (NZ / 2)) * NY + ty + e * TY];
+            r[h][e] = v.x;
+            im[h][e] = v.y;
+        }
+    // z lines: group gz takes ky = gz and gz + NY/2, lane tz elements kz = tz + e TZ
+    const int gz = tid / TZ, tz = tid - gz * TZ;
+    const T* lz = reinterpret_cast<const T*>(a.lam_row) + b * a.lam_row_stride;
+    const T* ly = reinterpret_cast<const T*>(a.lam_y) + b * a.lam_y_stride;
+    const T lx = reinterpret_cast<const T*>(a.lam_col)[b * a.lam_col_stride + w];
+    // twiddles are read stage by stage from copies of the tables in LDS (the
+    // copies of global reads would be merged across the kernel and kept in
+    // registers, more than the 1024-thread instance's 128 hold), and the symbol
+    // where it is used
+    C* twl = reinterpret_cast<C*>(lc + 2 * (size_t)NZ * PZ);
+    for (int m = tid; m < NY + NZ; m += S::THREADS)
+        twl[m] = m < NY ? reinterpret_cast<const C*>(a.tw_y)[m] : reinterpret_cast<const C*>(a.tw)[m - NY];
+    __syncthreads();
+    const TwiddleTable<T, LOG2Y> twy{twl};
+    const TwiddleTable<T, LOG2Z> twz{twl + NY};
+    const bool marks = a.iter > 0 && a.stop_iter;
+    const int stop = marks ? a.stop_iter[b] : a.iter;
+    const bool check_tol = marks && a.delta_bits && a.tol > 0.0 && a.iter >= 2;
+    const unsigned long long dbits = check_tol ? a.delta_bits[(int64_t)b * a.K + (a.iter - 2)] : 0ull;
+    if (marks) {
+        if (stop < a.iter) return;  // uniform per workgroup
+        // the first pass of iteration s stops field b when s-1 changed it by <= tol
+        if (check_tol && __longlong_as_double((long long)dbits) <= a.tol) {
+            if (blockIdx.x == 0 && tid == 0) atomicMin(a.stop_iter + b, a.iter - 1);
+            return;
+        }
+    }
+    // A lane index the compiler takes as a new value: the index arithmetic of
+    // one transform is then not kept in registers for the transform back.
+    auto fresh = [](int v) {
+        asm volatile("" : "+v"(v));
+        return v;
+    };
+    // y line h of the group: element y at 2 ((gy + h NZ/2) PZ + y); z line h:
+    // element z at 2 (z PZ + gz + h NY/2)
+    const int yl = 2 * gy * PZ, yp = 2 * (NZ / 2) * PZ;
+    const int zl = 2 * gz, zp = 2 * (NY / 2);
+
+    // forward along y (rows z of the plane), the result to LDS
+    fft_lines<T, -1, 2, LOG2Y, false>(r, im, lc, lc + 1, yp, 2, yl, fresh(ty), twy);
+    __syncthreads();  // the rows' last exchanges have been read
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int o = yl + h * yp + 2 * (ty + e * TY);
+            lc[o] = r[h][e];
+            lc[o + 1] = im[h][e];
+        }
+    __syncthreads();
+    // forward along z (columns ky)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int o = zl + h * zp + 2 * PZ * (tz + e * TZ);
+            r[h][e] = lc[o];
+            im[h][e] = lc[o + 1];
+        }
+    fft_lines<T, -1, 2, LOG2Z, false>(r, im, lc, lc + 1, zp, 2 * PZ, zl, fresh(tz), twz);
+    T lzv[8], lyv[2];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) lzv[e] = lz[tz + e * TZ] * lx;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) lyv[h] = ly[gz + h * (NY / 2)];
+    if (a.epart) {
+        // this thread's terms in float, the wave's sum in double
+        T acc = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc += (lzv[e] * lyv[h]) * (r[h][e] * r[h][e] + im[h][e] * im[h][e]);
+        const double sum = wave_sum((double)acc);
+        const int slot = a.slot >= 0 ? a.slot : a.stop_iter[b];
+        if ((tid & 63) == 0)
+            a.epart[((int64_t)b * (a.K + 1) + slot) * a.nwg + wg * (blockDim.x >> 6) + (tid >> 6)] = sum;
+    }
+    if (!a.apply) return;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const T lm = lzv[e] * lyv[h];
+            r[h][e] *= lm;
+            im[h][e] *= lm;
+        }
+    // back along z, then y
+    fft_lines<T, +1, 2, LOG2Z, false>(r, im, lc, lc + 1, zp, 2 * PZ, zl, fresh(tz), twz);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int o = zl + h * zp + 2 * PZ * (tz + e * TZ);
+            lc[o] = r[h][e];
+            lc[o + 1] = im[h][e];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int o = yl + h * yp + 2 * (ty + e * TY);
+            r[h][e] = lc[o];
+            im[h][e] = lc[o + 1];
+        }
+    fft_lines<T, +1, 2, LOG2Y, false>(r, im, lc, lc + 1, yp, 2, yl, fresh(ty), twy);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            C v;
+            v.x = r[h][e];
+            v.y = im[h][e];
+            Zp[(gy + h * (NZ / 2)) * NY + ty + e * TY] = v;
+        }
 }
 
 }  // namespace mbo

@@ -22,6 +22,25 @@ hipError_t launch_heat_fast(int prec, int log2L, int TX, const FastColArgs& a, d
     return launch_heat_fast_f64(log2L, TX, a, grid, st, prepare, ev0, ev1);
 }
 
+// planes of 64 or 128 points along y and z
+hipError_t launch_plane_fast(int log2Y, int log2Z, const FastColArgs& a, dim3 grid, hipStream_t st, bool prepare,
+                             hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (log2Y == 6 && log2Z == 6) return plane_fast_go<float, 6, 6>(a, grid, st, prepare, ev0, ev1);
+    if (log2Y == 6 && log2Z == 7) return plane_fast_go<float, 6, 7>(a, grid, st, prepare, ev0, ev1);
+    if (log2Y == 7 && log2Z == 6) return plane_fast_go<float, 7, 6>(a, grid, st, prepare, ev0, ev1);
+    if (log2Y == 7 && log2Z == 7) return plane_fast_go<float, 7, 7>(a, grid, st, prepare, ev0, ev1);
+    return hipErrorInvalidValue;
+}
+
+int plane_fast_threads(int log2Y, int log2Z) { return (1 << (log2Y + log2Z)) / 16; }
+
+size_t plane_fast_lds_bytes(int log2Y, int log2Z)
+{
+    const int ny = 1 << log2Y;
+    return ((size_t)(1 << log2Z) * (ny + 1) + ny + (1 << log2Z)) * 2 * sizeof(float);
+}
+
 template <typename T>
 static size_t row_lds_t(int n, int log2L)
 {

@@ -100,4 +100,16 @@ static hipError_t heat_fast_t(int log2L, int TX, const FastColArgs& a, dim3 g, h
     return hipErrorInvalidValue;
 }
 
+template <typename T, int LY, int LZ>
+static hipError_t plane_fast_go(const FastColArgs& a, dim3 g, hipStream_t st, bool prepare, hipEvent_t ev0,
+                                hipEvent_t ev1)
+{
+    typedef PlaneFastShape<T, LY, LZ> S;
+    const void* f = reinterpret_cast<const void*>(&plane_fast<T, LY, LZ>);
+    if (prepare) return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::LDS);
+    if (ev0) hipExtLaunchKernelGGL((plane_fast<T, LY, LZ>), g, dim3(S::THREADS), S::LDS, st, ev0, ev1, 0, a);
+    else hipLaunchKernelGGL((plane_fast<T, LY, LZ>), g, dim3(S::THREADS), S::LDS, st, a);
+    return hipGetLastError();
+}
+
 }  // namespace mbo

@@ -370,7 +370,9 @@ struct FastRowArgs {
     int64_t rows;            // rows per field plane
     int64_t npts;            // points per field
     const void* tw;          // twiddles exp(-2 pi i m / L)
-    void* Z;                 // kept row spectra [batch][PL][rows][W] complex
+    void* Z;                 // kept row spectra [batch][PL][rows][W] complex, or
+                             // [batch][PL][W][rows] when plane_major
+    int plane_major;         // 3-D: spectra stored plane by plane for the plane pass
     const void* Ain;         // RF_LOAD_REAL: real field [batch][n*n][npts]
     void* Aout;              // RF_STORE_REAL / RF_TRACK: real field
     int8_t* sgn;             // det signs [batch][npts]
@@ -403,12 +405,23 @@ struct FastColArgs {
     const unsigned long long* delta_bits;  // nullable
     double tol;
     int apply;               // 1: multiply and transform back (heat step); 0: energy only
+    // the 3-D plane pass (L = N0 is the z axis): the y axis, its twiddles and
+    // heat factor [Ny] exp(-4 pi^2 tau ky^2) / Ny
+    int Ny;
+    const void* tw_y;
+    const void* lam_y;
+    int64_t lam_y_stride;
 };
 
 hipError_t launch_row_fast(int prec, int n, int log2L, const FastRowArgs& a, dim3 grid, hipStream_t st,
                            bool prepare = false, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_heat_fast(int prec, int log2L, int TX, const FastColArgs& a, dim3 grid, hipStream_t st,
                             bool prepare = false, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// the 3-D plane pass (float): one workgroup per (packed plane, stored x mode)
+hipError_t launch_plane_fast(int log2Y, int log2Z, const FastColArgs& a, dim3 grid, hipStream_t st,
+                             bool prepare = false, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+int plane_fast_threads(int log2Y, int log2Z);
+size_t plane_fast_lds_bytes(int log2Y, int log2Z);
 // flips / fallbacks / non-finite of every iteration and field from the row
 // pass's per-workgroup packed counts [batch][K][nwg]
 hipError_t launch_sum_counts(const unsigned long long* part, int nwg, int K, int batch, unsigned long long* flips,

@@ -58,14 +58,35 @@ def sigma_gap(At):
     return s[:, -2] + s[:, -1]
 
 
-def fp32_step_ok(err, gap, e_heat):
+def fp32_step_ok(err, gap, e_heat, ties=None):
     """FP32 one-step error per point against the FP64 oracle.  The FP32 diffusion
     perturbs the projected matrix by e_heat (measured); the first-order bound
     |dQ| <= 2 |dA| / (sigma_{n-1} + sigma_n) then caps what any FP32 projection
-    can reach.  Well-conditioned points (gap >= 0.1) must meet 1e-5 outright."""
+    can reach.  Well-conditioned points (gap >= 0.1) must meet 1e-5 outright.
+    Points in `ties` (see det_ties) are left out: there the perturbation can
+    flip the sign of det, and either polar factor is a correct result."""
     u32 = 2.0 ** -24
+    if ties is not None:
+        err, gap = err[~ties], gap[~ties]
     bound = np.maximum(1e-5, 4.0 * (e_heat + 8 * u32) / gap)
     return bool(np.all(err <= bound)) and (not np.any(gap >= 0.1) or err[gap >= 0.1].max() <= 1e-5)
+
+
+def det_ties(Ht, e_heat):
+    """Points whose det sign a diffusion error of e_heat (plus the rounding of the
+    float input) can change: |det H| <= 2 n (e_heat + 8u) |cof H|_F, the first-order
+    change of det being <cof H, dH>.  At such a point the closest orthogonal
+    matrix on the other side of det = 0 is as correct as the oracle's."""
+    Hp = point_major(Ht)
+    n = Hp.shape[1]
+    s = np.linalg.svd(Hp, compute_uv=False)
+    det = np.abs(np.linalg.det(Hp))
+    if n == 1:
+        cof = np.ones_like(det)
+    else:
+        # singular values of cof H: the products of all but one of those of H
+        cof = np.sqrt(sum(np.prod(np.delete(s, i, axis=1), axis=1) ** 2 for i in range(n)))
+    return det <= 2 * n * (e_heat + 8 * 2.0 ** -24) * cof
 
 
 def plan(grid, n, tau, prec, batch=1):
@@ -936,6 +957,99 @@ def test_3d_configuration_properties(torch_cuda):
     A9 = oracle.iterate(w.field(), w.tau, 9)["A"].astype(np.float32)
     r1, ro = step_from(A9, "step 10")
     assert abs(r1["energy"][0][1] - ro["energy"][1]) <= 1e-5 * abs(ro["energy"][1])
+
+
+BANDED_3D = [((64, 64, 128), 3, FB), ((128, 128, 64), 3, FB), ((64, 128, 32), 2, F32), ((128, 64, 16), 4, FB),
+             ((64, 64, 512), 1, F32)]
+
+
+@pytest.mark.parametrize("grid,n,prec", BANDED_3D)
+def test_iterate_3d_plane_pass_one_step(torch_cuda, grid, n, prec):
+    """The 3-D band-limited passes of float plans (the x-row pass storing the
+    kept x modes plane by plane, one plane pass per packed plane and stored x
+    mode doing the y and z transforms, the heat step and the Lyapunov partial in
+    LDS): one step against the FP64 oracle to the FP32 bar, and the logged energy
+    against the oracle's; twice, from A_0 (uniform entries: after diffusion most
+    points are ill conditioned) and from the GPU's own A_1 (a smooth field of
+    orthogonal matrices: most points well conditioned)."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    tau = 5e-4
+    P = plan(grid, n, tau, prec)
+    path, c, W = P.path()
+    note("3-D plane pass grid=%s n=%d: path %d, half-width %d, stored %d" % (grid, n, path, c, W))
+    assert path in (mbo.PATH_BANDED, mbo.PATH_FULL)
+    Ain = inputs.uniform_field(n, grid, 37).astype(np.float32)
+    for k in range(2):
+        A64 = Ain.astype(np.float64)
+        Ht, _ = oracle.heat(A64.reshape((n * n,) + grid), tau, 3)
+        Ht = Ht.reshape(A64.shape)
+        Hg = P.diffuse(to_dev(torch, Ain, torch.float32)).cpu().numpy()
+        e_heat = float(np.abs(Hg - Ht).max())
+        t = to_dev(torch, Ain, torch.float32)
+        r = P.iterate(t, 1)
+        ro = oracle.iterate(A64, tau, 1)
+        gap = sigma_gap(Ht) if n > 1 else np.abs(Ht.reshape(-1)) * 2
+        ties = det_ties(Ht, e_heat)
+        Q = t.cpu().numpy()
+        err = np.abs(point_major(Q - ro["A"])).max(axis=(1, 2))
+        Qp = point_major(Q.astype(np.float64))
+        orth = np.abs(np.einsum("pki,pkj->pij", Qp, Qp) - np.eye(n)).max()
+        note("  input %d: diffusion err %.3g, step err max %.3g, %d of %d points well conditioned, %d det "
+             "ties, fallbacks %d, |Q^t Q - I| %.3g, E0 %.6g (oracle %.6g)"
+             % (k, e_heat, err.max(), int((gap >= 0.1).sum()), gap.size, int(ties.sum()),
+                r["fallbacks"][0][0], orth, r["energy"][0][0], ro["energy"][0]))
+        assert e_heat <= 2e-6
+        assert fp32_step_ok(err, gap, e_heat, ties)
+        assert orth <= 1e-5
+        assert abs(r["energy"][0][0] - ro["energy"][0]) <= 1e-5 * abs(ro["energy"][0])
+        Ain = Q
+
+
+@pytest.mark.parametrize("grid,n", [((128, 128, 128), 3), ((64, 128, 64), 4)])
+def test_iterate_3d_plane_pass_matches_general_kernels(torch_cuda, grid, n):
+    """Five FP32 + fallback steps through the 3-D band-limited passes against the
+    general kernels (row pass and three strided passes, every mode kept), both on
+    the GPU.  Each step starts both paths from the same iterate (the general
+    path's trajectory): two correct FP32 projections may differ at a point whose
+    polar factor is ill conditioned, and the next diffusion spreads that
+    difference to its neighbours, so trajectories run apart are no measure of a
+    step.  Entries agree to the FP32 bar where the projection is well
+    conditioned and det is no tie (det_ties) at every step; the energies logged
+    by two independent runs of the five steps agree to FP32 rounding."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    tau, K = 5e-4, 5
+    A0 = inputs.normal_field(n, grid, 41).astype(np.float32)
+    Pb, Pg = plan(grid, n, tau, FB), plan(grid, n, tau, FB)
+    Pb.set_path(mbo.PATH_BANDED)
+    Pg.set_path(mbo.PATH_GENERIC)
+    t = to_dev(torch, A0, torch.float32)
+    worst = 0.0
+    for s in range(1, K + 1):
+        Hg = Pg.diffuse(t).cpu().numpy().astype(np.float64)
+        gap = sigma_gap(Hg)
+        # both diffusions lie within 2e-6 of the exact one (the one-step test)
+        ties = det_ties(Hg, 4e-6)
+        nb, ng = Pb.step(t), Pg.step(t)
+        err = np.abs(point_major((nb - ng).cpu().numpy())).max(axis=(1, 2))
+        wc = (gap >= 0.1) & ~ties
+        e_wc = float(err[wc].max()) if wc.any() else 0.0
+        note("3-D plane pass vs general kernels grid=%s n=%d step %d: max err %.3g, well conditioned %.3g "
+             "(%d of %d points, %d det ties)" % (grid, n, s, err.max(), e_wc, int(wc.sum()), wc.size,
+                                                int(ties.sum())))
+        assert e_wc <= 1e-5, s
+        worst = max(worst, e_wc)
+        t = ng
+    E = []
+    for P in (Pb, Pg):
+        t = to_dev(torch, A0, torch.float32)
+        E.append(P.iterate(t, K)["energy"][0])
+        P.close()
+    Eb, Eg = E
+    note("energies %s vs %s" % (Eb, Eg))
+    noise = 8 * n * 2.0 ** -23 / tau
+    assert np.all(np.abs(Eb - Eg) <= 1e-5 * np.abs(Eg) + noise)
 
 
 @pytest.mark.parametrize("grid,n,prec", [((64, 64), 3, F64), ((8, 32), 2, F64), ((16, 8, 16), 3, FB),
