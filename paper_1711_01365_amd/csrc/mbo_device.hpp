@@ -242,15 +242,23 @@ __device__ __forceinline__ void stage_tw8(T (&r)[8], T (&im)[8], const typename 
     dft8<T, S>(r, im);
 }
 
-// LDS element index of position j of a line: padded (one slot per eight) or
-// plain, for lines whose own stride already spreads them over the banks.
-template <bool PADJ>
+// LDS element index of position j of a line, by layout: LIX_PAD pads one slot
+// per eight; LIX_XOR keeps the line's L slots and swaps bits 1-3 of j with the
+// XOR of bits 4-6 (a permutation of each run of 16), which spreads the
+// exchanges of a radix-8 stage of a 64- or 128-point line over the banks when
+// the line's elements are 8 bytes apart or more (interleaved complex, or a
+// column of a padded plane); LIX_PLAIN leaves j as it is.
+enum { LIX_PLAIN = 0, LIX_PAD = 1, LIX_XOR = 2 };
+
+template <int LIX>
 __device__ __forceinline__ int line_index(int j)
 {
-    return PADJ ? lds_pad(j) : j;
+    if constexpr (LIX == LIX_PAD) return lds_pad(j);
+    else if constexpr (LIX == LIX_XOR) return j ^ (((j >> 4) & 7) << 1);
+    else return j;
 }
 
-template <typename T, int S, int NP, int LOG2L, int STAGE, bool PADJ = true, typename TW = Twiddles<T, LOG2L>>
+template <typename T, int S, int NP, int LOG2L, int STAGE, int PADJ = LIX_PAD, typename TW = Twiddles<T, LOG2L>>
 __device__ __forceinline__ void fft_stages(T (&r)[NP][8], T (&im)[NP][8], T* lr, T* li, int lplane,
                                            int lmul, int ladd, int t, const TW& tw, bool act)
 {
@@ -378,11 +386,10 @@ __device__ __forceinline__ void fft_wave(T (&r)[8], T (&im)[8], T* lr, T* li, in
 }
 
 // In-place FFT of NP lines (S = -1 forward, +1 inverse, unscaled).  LDS element
-// j of line pl is at lr/li[pl*lplane + lds_pad(j)*lmul + ladd] (j*lmul + ladd
-// with PADJ = false).  Every thread of the workgroup must call it (it contains
+// j of line pl is at lr/li[pl*lplane + line_index<PADJ>(j)*lmul + ladd].  Every thread of the workgroup must call it (it contains
 // barriers); threads with act = false only take part in the barriers and touch
 // no LDS.
-template <typename T, int S, int NP, int LOG2L, bool PADJ = true, typename TW = Twiddles<T, LOG2L>>
+template <typename T, int S, int NP, int LOG2L, int PADJ = LIX_PAD, typename TW = Twiddles<T, LOG2L>>
 __device__ __forceinline__ void fft_lines(T (&r)[NP][8], T (&im)[NP][8], T* lr, T* li, int lplane,
                                           int lmul, int ladd, int t, const TW& tw, bool act = true)
 {

@@ -713,7 +713,7 @@ __global__ void __launch_bounds__((PlaneFastShape<T, LOG2Y, LOG2Z>::THREADS)) pl
     const int zl = 2 * gz, zp = 2 * (NY / 2);
 
     // forward along y (rows z of the plane), the result to LDS
-    fft_lines<T, -1, 2, LOG2Y, false>(r, im, lc, lc + 1, yp, 2, yl, fresh(ty), twy);
+    fft_lines<T, -1, 2, LOG2Y, LIX_XOR>(r, im, lc, lc + 1, yp, 2, yl, fresh(ty), twy);
     __syncthreads();  // the rows' last exchanges have been read
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -733,7 +733,7 @@ __global__ void __launch_bounds__((PlaneFastShape<T, LOG2Y, LOG2Z>::THREADS)) pl
             r[h][e] = lc[o];
             im[h][e] = lc[o + 1];
         }
-    fft_lines<T, -1, 2, LOG2Z, false>(r, im, lc, lc + 1, zp, 2 * PZ, zl, fresh(tz), twz);
+    fft_lines<T, -1, 2, LOG2Z, LIX_XOR>(r, im, lc, lc + 1, zp, 2 * PZ, zl, fresh(tz), twz);
     T lzv[8], lyv[2];
 #pragma unroll
     for (int e = 0; e < 8; ++e) lzv[e] = lz[tz + e * TZ] * lx;
@@ -761,7 +761,7 @@ __global__ void __launch_bounds__((PlaneFastShape<T, LOG2Y, LOG2Z>::THREADS)) pl
             im[h][e] *= lm;
         }
     // back along z, then y
-    fft_lines<T, +1, 2, LOG2Z, false>(r, im, lc, lc + 1, zp, 2 * PZ, zl, fresh(tz), twz);
+    fft_lines<T, +1, 2, LOG2Z, LIX_XOR>(r, im, lc, lc + 1, zp, 2 * PZ, zl, fresh(tz), twz);
     __syncthreads();
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -780,7 +780,7 @@ __global__ void __launch_bounds__((PlaneFastShape<T, LOG2Y, LOG2Z>::THREADS)) pl
             r[h][e] = lc[o];
             im[h][e] = lc[o + 1];
         }
-    fft_lines<T, +1, 2, LOG2Y, false>(r, im, lc, lc + 1, yp, 2, yl, fresh(ty), twy);
+    fft_lines<T, +1, 2, LOG2Y, LIX_XOR>(r, im, lc, lc + 1, yp, 2, yl, fresh(ty), twy);
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
