@@ -189,10 +189,18 @@ def run_3d(steps, warmup):
     w = inputs.NORMAL_128_3D
     r = run_gpu(w, mbo.F32_F64FALLBACK, steps, warmup, timing_steps=2)
     bpl = 2 * w.n * w.n * 4 * w.points
+    # what the passes move: the kept x modes of the packed planes of every
+    # (z, y) row, read and written by both passes, and the row pass's det signs
+    pl = (w.n * w.n + 1) // 2
+    spectra = pl * r["path"]["stored_modes"] * (w.points // w.grid[2]) * 8
+    moved_row, moved_plane = 2 * spectra + 2 * w.points, 2 * spectra
     return {"workload": "n3_128x128x128_normal_tau5e-4_100it_f32_f64fallback",
             "value": r["value"], "unit": "point-iterations/s", "ms_per_run": r["ms_per_step"],
             "row_us": r["row_us"], "plane_us": r["heat_us"], "bytes_per_launch": bpl,
             "row_GBps": bpl / (r["row_us"] * 1e-6) / 1e9, "plane_GBps": bpl / (r["heat_us"] * 1e-6) / 1e9,
+            "moved_bytes_per_launch_model": {"row_pass": moved_row, "plane_pass": moved_plane},
+            "moved_GBps": {"row_pass": moved_row / (r["row_us"] * 1e-6) / 1e9,
+                           "plane_pass": moved_plane / (r["heat_us"] * 1e-6) / 1e9},
             "path": r["path"], "fallbacks_total": r["fallbacks_total"]}
 
 
