@@ -884,7 +884,8 @@ __device__ __forceinline__ T polar_vjp(const T* a, const T* g, T* ga)
 }
 
 // Cofactor matrix of a row-major 3x3 matrix (cof(X) = det(X) X^{-T}).
-__device__ __forceinline__ void cofactor3(const float* x, float* c)
+template <typename T>
+__device__ __forceinline__ void cofactor3(const T* x, T* c)
 {
     c[0] = x[4] * x[8] - x[5] * x[7];
     c[1] = x[5] * x[6] - x[3] * x[8];
@@ -897,86 +898,109 @@ __device__ __forceinline__ void cofactor3(const float* x, float* c)
     c[8] = x[0] * x[4] - x[1] * x[3];
 }
 
-// Whether the float 3x3 matrix a (cofactors C, det, squared cofactor norm cf2)
+// Constants of the Newton polar iteration by precision: the unit roundoff u,
+// the smallest squared cofactor norm accepted (the first step's products must
+// stay normal), and the step sizes that end the scaled phase and the iteration
+// (a step below `stop` leaves an error of about stop^2 / 2, below the rounding
+// of the result).
+template <typename T> struct newton3_consts;
+template <> struct newton3_consts<float> {
+    static constexpr float u = 5.9604644775390625e-08f;  // 2^-24
+    static constexpr float cf2_min = 1e-36f;
+    static constexpr float unscaled = 1e-2f, stop = 3e-4f;
+};
+template <> struct newton3_consts<double> {
+    static constexpr double u = 1.1102230246251565e-16;  // 2^-53
+    static constexpr double cf2_min = 1e-280;
+    static constexpr double unscaled = 1e-2, stop = 1e-7;
+};
+
+// Whether the 3x3 matrix a (cofactors C, det, squared cofactor norm cf2)
 // certainly has sigma_min > thr.
-__device__ __forceinline__ bool newton3_certain(const float* a, const float* C, float det, float cf2, float thr)
+template <typename T>
+__device__ __forceinline__ bool newton3_certain(const T* a, const T* C, T det, T cf2, T thr)
 {
     // 1/|A^{-1}|_F = |det| / |cof A|_F <= sigma_min, so |det| > thr |cof|_F
-    // proves sigma_min > thr, provided the float det and cofactors are
+    // proves sigma_min > thr, provided the computed det and cofactors are
     // accurate enough: a cofactor carries an error of at most 2u|A|_F^2 and
-    // det at most 4u|A|_F^3 + 3u|A|_F|cof|_F (u = 2^-24), so the test is made
-    // with that margin (doubled).  Without it a numerically rank-1 matrix
-    // (sigma_2 near u sigma_1), whose float cofactors are mostly rounding,
-    // could pass.  Strict: det = 0 with a zero cofactor matrix (rank <= 1, the
-    // zero matrix) fails, and so does a matrix whose squared cofactor norm is
-    // not a normal float with room (|A| below ~1e-9: the first step's products
-    // would underflow; Jacobi rescales by a power of two); also NaN.
-    float af2 = 0.f;
+    // det at most 4u|A|_F^3 + 3u|A|_F|cof|_F, so the test is made with that
+    // margin (doubled).  Without it a numerically rank-1 matrix (sigma_2 near
+    // u sigma_1), whose cofactors are mostly rounding, could pass.  Strict:
+    // det = 0 with a zero cofactor matrix (rank <= 1, the zero matrix) fails,
+    // and so does a matrix whose squared cofactor norm is not a normal number
+    // with room (the first step's products would underflow; Jacobi rescales by
+    // a power of two); also NaN.
+    T af2 = 0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) af2 += a[k] * a[k];
-    const float an = num<float>::sqrt_(af2), cn = num<float>::sqrt_(cf2);
-    const float u = 5.9604644775390625e-08f;
-    const float margin = 2.f * u * (thr * (6.f * af2 + cn) + an * (4.f * af2 + 3.f * cn));
-    const float adet = det < 0.f ? -det : det;
-    return (cf2 >= 1e-36f) && (adet > thr * cn + margin);
+    const T an = num<T>::sqrt_(af2), cn = num<T>::sqrt_(cf2);
+    const T u = newton3_consts<T>::u;
+    const T margin = (T)2 * u * (thr * ((T)6 * af2 + cn) + an * ((T)4 * af2 + (T)3 * cn));
+    const T adet = det < (T)0 ? -det : det;
+    return (cf2 >= newton3_consts<T>::cf2_min) && (adet > thr * cn + margin);
 }
 
-// Closest orthogonal matrix of a float 3x3 matrix by the scaled Newton
-// iteration for the polar decomposition, X <- (zeta X + X^{-T} / zeta) / 2
-// (Higham, 1986), with Frobenius-norm scaling zeta = (|X^{-1}|_F / |X|_F)^{1/2}
-// until the step is below 1e-2 and unscaled steps after it.  Each step maps
-// every singular value s to (zeta s + 1/(zeta s)) / 2 and keeps U, V and the
-// sign of det, so the limit is U V^t; convergence is quadratic, and a step
-// below 3e-4 leaves an error below the float rounding of the result.  Returns
-// false (q unset) unless newton3_certain proves sigma_min > thr (it fails when
-// sigma_min may be at most about sqrt(3) thr, when A is singular or numerically
-// of rank 1); sigma_min is then decided by the Jacobi route.
-__device__ __forceinline__ bool polar_newton3(const float* a, float* q, int& dsign, float thr)
+// Closest orthogonal matrix of a 3x3 matrix by the scaled Newton iteration for
+// the polar decomposition, X <- (zeta X + X^{-T} / zeta) / 2 (Higham, 1986),
+// with Frobenius-norm scaling zeta = (|X^{-1}|_F / |X|_F)^{1/2} until the step
+// is below newton3_consts::unscaled and unscaled steps after it.  Each step
+// maps every singular value s to (zeta s + 1/(zeta s)) / 2 and keeps U, V and
+// the sign of det, so the limit is U V^t; convergence is quadratic, and a step
+// below newton3_consts::stop leaves an error below the rounding of the result.
+// Returns false (q unset) unless newton3_certain proves sigma_min > thr (it
+// fails when sigma_min may be at most about sqrt(3) thr, when A is singular or
+// numerically of rank 1); such points go to the Jacobi route.
+template <typename T>
+__device__ __forceinline__ bool polar_newton3(const T* a, T* q, int& dsign, T thr)
 {
-    float X[9], C[9];
+    T X[9], C[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) X[k] = a[k];
     cofactor3(X, C);
-    float det = X[0] * C[0] + X[1] * C[1] + X[2] * C[2];
-    float cf2 = 0.f;
+    T det = X[0] * C[0] + X[1] * C[1] + X[2] * C[2];
+    T cf2 = 0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) cf2 += C[k] * C[k];
     if (!newton3_certain(X, C, det, cf2, thr)) return false;
-    dsign = det >= 0.f ? 1 : -1;
+    dsign = det >= (T)0 ? 1 : -1;
     bool scaled = true;
 #pragma unroll 1
     for (int it = 0; it < 16; ++it) {
         if (it > 0) {
             cofactor3(X, C);
             det = X[0] * C[0] + X[1] * C[1] + X[2] * C[2];
-            cf2 = 0.f;
+            cf2 = 0;
 #pragma unroll
             for (int k = 0; k < 9; ++k) cf2 += C[k] * C[k];
         }
-        float xf2 = 0.f;
+        T xf2 = 0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) xf2 += X[k] * X[k];
-        const float idet = 1.0f / det;
+        const T idet = (T)1 / det;
         // zeta^2 = |C/det|_F / |X|_F
-        const float zeta = scaled ? num<float>::sqrt_(num<float>::sqrt_(cf2) * (idet < 0.f ? -idet : idet) *
-                                                      num<float>::rsq(xf2))
-                                  : 1.0f;
-        const float cx = 0.5f * zeta, cc = 0.5f * idet / zeta;
-        float diff = 0.f;
+        const T zeta = scaled ? num<T>::sqrt_(num<T>::sqrt_(cf2) * (idet < (T)0 ? -idet : idet) * num<T>::rsq(xf2))
+                              : (T)1;
+        const T cx = (T)0.5 * zeta, cc = (T)0.5 * idet / zeta;
+        T diff = 0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const float xn = cx * X[k] + cc * C[k];
-            const float dv = xn - X[k];
-            diff = fmaxf(diff, dv < 0.f ? -dv : dv);
+            const T xn = cx * X[k] + cc * C[k];
+            const T dv = xn - X[k];
+            if constexpr (sizeof(T) == 4) diff = fmaxf(diff, dv < (T)0 ? -dv : dv);
+            else diff = fmax(diff, dv < (T)0 ? -dv : dv);
             X[k] = xn;
         }
-        if (diff < 1e-2f) scaled = false;
-        if (diff < 3e-4f) break;
+        if (diff < newton3_consts<T>::unscaled) scaled = false;
+        if (diff < newton3_consts<T>::stop) break;
     }
 #pragma unroll
     for (int k = 0; k < 9; ++k) q[k] = X[k];
     return true;
 }
+
+// Double plans take the Newton route for n = 3 points whose smallest singular
+// value is certainly above this (Jacobi below it).
+constexpr double kNewtonMinSigmaF64 = 1e-3;
 
 // Float Jacobi of a point of a plan with the double fallback: when the smallest
 // singular value is below sigma_fb it stops before forming Q and returns true,
@@ -1023,6 +1047,9 @@ __device__ __forceinline__ bool project_point_fb(const T* a, T* q, int& dsign, b
     if constexpr (sizeof(T) == 4 && n == 3) {
         // well-conditioned points (sigma_min >= sigma_fb): Newton, no fallback
         if (polar_newton3(a, q, dsign, (float)sigma_fb)) return false;
+    }
+    if constexpr (sizeof(T) == 8 && n == 3) {
+        if (polar_newton3(a, q, dsign, kNewtonMinSigmaF64)) return false;
     }
     if constexpr (sizeof(T) == 4 && n >= 3) {
         if (fallback) {

@@ -155,7 +155,7 @@ struct RowFastShape {
     static constexpr int WAVES = WAVE_LINE ? 4 : (THREADS + 255) / 256;
 };
 
-template <typename T, int n, int LOG2L>
+template <typename T, int n, int LOG2L, bool PM>
 __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFastShape<T, n, LOG2L>::WAVES))
     row_fast(const FastRowArgs a)
 {
@@ -182,7 +182,8 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
     }
     const int64_t npts = a.npts;
     const int W = a.W, c = a.band;
-    const bool pm = a.plane_major != 0;
+    // PM: spectra stored plane by plane (a.plane_major, the 3-D layout).
+    constexpr bool pm = PM;
     // Plane by plane, a workgroup's loads and stores of one mode cover RPW
     // consecutive rows, part of a cache line: the eight XCDs (own L2 each) then
     // take contiguous runs of row groups, so that the groups sharing a line

@@ -9,18 +9,37 @@
 
 namespace mbo {
 
-template <typename T, int n, int LG>
+template <typename T, int n, int LG, bool PM>
 static hipError_t row_fast_go(const FastRowArgs& a, dim3 g, hipStream_t st, bool prepare, hipEvent_t ev0,
                               hipEvent_t ev1)
 {
     typedef RowFastShape<T, n, LG> S;
     const size_t lds = S::LDS;
-    const void* f = reinterpret_cast<const void*>(&row_fast<T, n, LG>);
+    const void* f = reinterpret_cast<const void*>(&row_fast<T, n, LG, PM>);
     if (prepare) return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const dim3 bl(S::THREADS);
-    if (ev0) hipExtLaunchKernelGGL((row_fast<T, n, LG>), g, bl, lds, st, ev0, ev1, 0, a);
-    else hipLaunchKernelGGL((row_fast<T, n, LG>), g, bl, lds, st, a);
+    if (ev0) hipExtLaunchKernelGGL((row_fast<T, n, LG, PM>), g, bl, lds, st, ev0, ev1, 0, a);
+    else hipLaunchKernelGGL((row_fast<T, n, LG, PM>), g, bl, lds, st, a);
     return hipGetLastError();
+}
+
+// The row-major instance, and for float the plane-major one of the 3-D layout
+// (both prepared together).
+template <typename T, int n, int LG>
+static hipError_t row_fast_pm(const FastRowArgs& a, dim3 g, hipStream_t st, bool prepare, hipEvent_t ev0,
+                              hipEvent_t ev1)
+{
+    if constexpr (sizeof(T) == 4) {
+        if (prepare) {
+            const hipError_t e = row_fast_go<T, n, LG, true>(a, g, st, true, ev0, ev1);
+            if (e != hipSuccess) return e;
+        } else if (a.plane_major) {
+            return row_fast_go<T, n, LG, true>(a, g, st, false, ev0, ev1);
+        }
+    } else {
+        if (a.plane_major && !prepare) return hipErrorInvalidValue;  // float-only layout
+    }
+    return row_fast_go<T, n, LG, false>(a, g, st, prepare, ev0, ev1);
 }
 
 template <typename T, int n>
@@ -28,15 +47,15 @@ static hipError_t row_fast_n(int log2L, const FastRowArgs& a, dim3 g, hipStream_
                              hipEvent_t ev0, hipEvent_t ev1)
 {
     switch (log2L) {
-    case 3: return row_fast_go<T, n, 3>(a, g, st, prepare, ev0, ev1);
-    case 4: return row_fast_go<T, n, 4>(a, g, st, prepare, ev0, ev1);
-    case 5: return row_fast_go<T, n, 5>(a, g, st, prepare, ev0, ev1);
-    case 6: return row_fast_go<T, n, 6>(a, g, st, prepare, ev0, ev1);
-    case 7: return row_fast_go<T, n, 7>(a, g, st, prepare, ev0, ev1);
-    case 8: return row_fast_go<T, n, 8>(a, g, st, prepare, ev0, ev1);
-    case 9: return row_fast_go<T, n, 9>(a, g, st, prepare, ev0, ev1);
-    case 10: return row_fast_go<T, n, 10>(a, g, st, prepare, ev0, ev1);
-    case 11: return row_fast_go<T, n, 11>(a, g, st, prepare, ev0, ev1);
+    case 3: return row_fast_pm<T, n, 3>(a, g, st, prepare, ev0, ev1);
+    case 4: return row_fast_pm<T, n, 4>(a, g, st, prepare, ev0, ev1);
+    case 5: return row_fast_pm<T, n, 5>(a, g, st, prepare, ev0, ev1);
+    case 6: return row_fast_pm<T, n, 6>(a, g, st, prepare, ev0, ev1);
+    case 7: return row_fast_pm<T, n, 7>(a, g, st, prepare, ev0, ev1);
+    case 8: return row_fast_pm<T, n, 8>(a, g, st, prepare, ev0, ev1);
+    case 9: return row_fast_pm<T, n, 9>(a, g, st, prepare, ev0, ev1);
+    case 10: return row_fast_pm<T, n, 10>(a, g, st, prepare, ev0, ev1);
+    case 11: return row_fast_pm<T, n, 11>(a, g, st, prepare, ev0, ev1);
     }
     return hipErrorInvalidValue;
 }
