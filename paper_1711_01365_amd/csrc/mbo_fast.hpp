@@ -130,6 +130,9 @@ struct RowFastShape {
     static constexpr int LINES = RPW * PL;
     static constexpr bool WAVE_LINE = LOG2L <= 9;
     static constexpr bool HELPER = sizeof(T) == 4 && n == 3;
+    // float n = 4: points below sigma_fb are queued and re-projected in double
+    // after the pass's loop (the double Jacobi inside the loop would spill)
+    static constexpr bool DEFER4 = sizeof(T) == 4 && n == 4;
     // long rows: at most 768 threads for float n = 3 (twelve waves, a budget of
     // 168 registers for the queued points' double Jacobi), else 1024
     static constexpr int NTMAX = HELPER ? 768 : 1024;
@@ -167,7 +170,7 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lr = reinterpret_cast<T*>(smem_raw);
     T* li = lr + (size_t)S::LINES * LP;
-    __shared__ unsigned short fq[HELPER ? S::P : 1];
+    __shared__ unsigned short fq[(HELPER || S::DEFER4) ? S::P : 1];
     __shared__ int fq_n, fq_claim;
     __shared__ unsigned long long wg_cnt[2];
 
@@ -438,8 +441,43 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
                     load_point(lrq, liq, av);
                     nbad += all_finite<T, NN>(av) ? 0ull : 1ull;
                     int ds;
-                    if (project_point_fb<T, n>(av, qv, ds, fallback, a.sigma_fb)) ++nfb;
+                    if constexpr (S::DEFER4) {
+                        if (fallback) {
+                            float V[n][n];
+                            if (polar_jacobi_f32_fb<n>(av, qv, ds, V, a.sigma_fb)) {
+                                fq[atomicAdd(&fq_n, 1)] = (unsigned short)(pp * 512 + tid);
+                                continue;
+                            }
+                        } else {
+                            T smin;
+                            project_point<T, n>(av, qv, ds, smin);
+                        }
+                    } else {
+                        if (project_point_fb<T, n>(av, qv, ds, fallback, a.sigma_fb)) ++nfb;
+                    }
                     finish(xp, lrq, liq, qv, ds, (int8_t)(s_old >> (8 * pp)));
+                }
+            }
+            if constexpr (S::DEFER4) {
+                // the queued points: float Jacobi again for its V, then the
+                // double Jacobi warm-started from it
+                if (fallback) {
+                    __syncthreads();
+                    const int nq = fq_n;
+#pragma unroll 1
+                    for (int qi = tid; qi < nq; qi += S::THREADS) {
+                        int64_t xp;
+                        T *lrq, *liq;
+                        (void)point_of(fq[qi], xp, lrq, liq);
+                        float aq[NN], qv[NN];
+                        load_point(lrq, liq, aq);
+                        float V[n][n];
+                        int ds;
+                        (void)polar_jacobi_f32_fb<n>(aq, qv, ds, V, a.sigma_fb);
+                        polar_jacobi_warm<n>(aq, V, qv, ds);
+                        ++nfb;
+                        finish(xp, lrq, liq, qv, ds, (flags & RF_SIGN) ? sgn[xp] : (int8_t)0);
+                    }
                 }
             }
         }
