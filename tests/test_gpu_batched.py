@@ -247,3 +247,56 @@ def test_batched_configuration_class_against_oracle(torch_cuda, batched_config_p
         assert _fp32_step_ok(err[~mism], gap[~mism], e_heat)
         assert abs(r["energy"][field][1] - ro["energy"][1]) <= 1e-5 * abs(ro["energy"][1])
         start = ro["A"]
+
+
+BANDED_3D_MIXED = [((64, 64, 128), 3, 5e-4, "normal"), ((64, 64, 128), 3, 1e-3, "uniform"),
+                   ((128, 64, 32), 2, 5e-4, "uniform"), ((64, 128, 64), 4, 8e-4, "normal")]
+
+
+def test_batched_3d_plane_pass_against_oracle(torch_cuda):
+    """Float 3-D fields in one batched plan run the band-limited passes (x-row
+    pass, plane pass), two of them in one class with their own tau (the symbols
+    per field, the band the widest of the class).  Two steps of every field, each
+    from the same float input as the FP64 oracle's step (the second from the
+    plan's own first iterate, a smooth field): per point within the FP32 bound,
+    det-sign differences only at ties, and the step's logged energy within FP32
+    rounding of the oracle's."""
+    torch = torch_cuda
+    from paper_1711_01365_amd import mbo
+    spec = [(g, n, t) for g, n, t, _ in BANDED_3D_MIXED]
+    bp = mbo.BatchedPlan(spec, precision=FB, autotune=False)
+    paths = [bp.path(i) for i in range(len(spec))]
+    note("3-D batched paths (path, half-width, stored modes): %s" % paths)
+    assert all(p[0] in (mbo.PATH_BANDED, mbo.PATH_FULL) for p in paths)
+    assert paths[0][0] == paths[1][0] == mbo.PATH_BANDED  # the class of two taus keeps a band
+    fields = [gen(init, n, grid, 700 + i).astype(np.float32)
+              for i, (grid, n, tau, init) in enumerate(BANDED_3D_MIXED)]
+    for step in (1, 2):
+        flat = bp.pack([torch.tensor(f, device="cuda") for f in fields])
+        H = [h.cpu().numpy() for h in bp.unpack(bp.diffuse(flat))]
+        r = bp.iterate(flat, 1)
+        outs = [o.cpu().numpy() for o in bp.unpack(flat)]
+        for i, (grid, n, tau, _) in enumerate(BANDED_3D_MIXED):
+            A64 = fields[i].astype(np.float64)
+            Ht, _ = oracle.heat(A64.reshape((n * n,) + grid), tau, 3)
+            Ht = Ht.reshape(A64.shape)
+            e_heat = float(np.abs(H[i].reshape(A64.shape) - Ht).max())
+            ro = oracle.iterate(A64, tau, 1)
+            out = outs[i].reshape(A64.shape)
+            Hp = _pm(Ht)
+            s = np.linalg.svd(Hp, compute_uv=False)
+            gap = s[:, -2] + s[:, -1] if n > 1 else 2 * np.abs(Hp.reshape(-1))
+            err = np.abs(_pm(out - ro["A"])).max(axis=(1, 2))
+            cof = np.sqrt(sum(np.prod(np.delete(s, j, axis=1), axis=1) ** 2 for j in range(n)))
+            tie_bound = 2.0 * n * (e_heat + 8 * 2.0 ** -24) * cof
+            mism = (np.linalg.det(_pm(out)) >= 0) != (np.linalg.det(_pm(ro["A"])) >= 0)
+            note("3-D batched step %d field %d grid=%s n=%d tau=%g: diffusion err %.3g, step err max %.3g "
+                 "(%.3g off the %d det-sign ties), %d well conditioned"
+                 % (step, i, grid, n, tau, e_heat, err.max(), err[~mism].max(), int(mism.sum()),
+                    int((gap >= 0.1).sum())))
+            assert e_heat <= 2e-6
+            assert np.all(np.abs(np.linalg.det(Hp[mism])) <= tie_bound[mism])
+            assert _fp32_step_ok(err[~mism], gap[~mism], e_heat)
+            assert abs(r["energy"][i][0] - ro["energy"][0]) <= 1e-5 * abs(ro["energy"][0])
+            fields[i] = out.astype(np.float32)
+    bp.close()
