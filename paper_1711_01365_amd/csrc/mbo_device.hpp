@@ -900,20 +900,36 @@ __device__ __forceinline__ void cofactor3(const T* x, T* c)
 
 // Constants of the Newton polar iteration by precision: the unit roundoff u,
 // the smallest squared cofactor norm accepted (the first step's products must
-// stay normal), and the step sizes that end the scaled phase and the iteration
-// (a step below `stop` leaves an error of about stop^2 / 2, below the rounding
-// of the result).
+// stay normal), and the bounds on |X|_F^2 - 3 that end the scaled phase and
+// start the last step (newton3_near_done).
 template <typename T> struct newton3_consts;
 template <> struct newton3_consts<float> {
     static constexpr float u = 5.9604644775390625e-08f;  // 2^-24
     static constexpr float cf2_min = 1e-36f;
-    static constexpr float unscaled = 1e-2f, stop = 3e-4f;
+    static constexpr float unscaled = 2e-2f, last = 1.2e-3f;
 };
 template <> struct newton3_consts<double> {
     static constexpr double u = 1.1102230246251565e-16;  // 2^-53
     static constexpr double cf2_min = 1e-280;
-    static constexpr double unscaled = 1e-2, stop = 1e-7;
+    static constexpr double unscaled = 2e-2, last = 1e-7;
 };
+
+// Stopping test of the Newton polar iteration from xf2 = |X|_F^2 at the start
+// of a step after the first.  A step maps each singular value s to
+// (z s + 1/(z s)) / 2 >= 1, so from then on xf2 - 3 = sum (s_i^2 - 1) has no
+// negative term and bounds every s_i - 1 by half its value.  Scaling stops
+// once that is below unscaled / 2 (quadratic convergence takes over), and the
+// step is the last once it is below last / 2: the step then leaves an error of
+// about (last / 2)^2 / 2 (float: 1.8e-7, below the FP32 bar by far and about
+// the rounding of the result; double: 1.3e-15).  A rounding of xf2 below the
+// bound only ends the iteration where it has converged to that rounding.
+template <typename T>
+__device__ __forceinline__ void newton3_near_done(T xf2, bool& scaled, bool& last)
+{
+    const T e = xf2 - (T)3;
+    if (e < newton3_consts<T>::unscaled) scaled = false;
+    last = e < newton3_consts<T>::last;
+}
 
 // Whether the 3x3 matrix a (cofactors C, det, squared cofactor norm cf2)
 // certainly has sigma_min > thr.
@@ -942,11 +958,10 @@ __device__ __forceinline__ bool newton3_certain(const T* a, const T* C, T det, T
 
 // Closest orthogonal matrix of a 3x3 matrix by the scaled Newton iteration for
 // the polar decomposition, X <- (zeta X + X^{-T} / zeta) / 2 (Higham, 1986),
-// with Frobenius-norm scaling zeta = (|X^{-1}|_F / |X|_F)^{1/2} until the step
-// is below newton3_consts::unscaled and unscaled steps after it.  Each step
-// maps every singular value s to (zeta s + 1/(zeta s)) / 2 and keeps U, V and
-// the sign of det, so the limit is U V^t; convergence is quadratic, and a step
-// below newton3_consts::stop leaves an error below the rounding of the result.
+// with Frobenius-norm scaling zeta = (|X^{-1}|_F / |X|_F)^{1/2} until the
+// singular values are near 1 and unscaled steps after it (newton3_near_done).
+// Each step maps every singular value s to (zeta s + 1/(zeta s)) / 2 and keeps
+// U, V and the sign of det, so the limit is U V^t; convergence is quadratic.
 // Returns false (q unset) unless newton3_certain proves sigma_min > thr (it
 // fails when sigma_min may be at most about sqrt(3) thr, when A is singular or
 // numerically of rank 1); such points go to the Jacobi route.
@@ -976,22 +991,16 @@ __device__ __forceinline__ bool polar_newton3(const T* a, T* q, int& dsign, T th
         T xf2 = 0;
 #pragma unroll
         for (int k = 0; k < 9; ++k) xf2 += X[k] * X[k];
+        bool last = false;
+        if (it > 0) newton3_near_done(xf2, scaled, last);
         const T idet = (T)1 / det;
         // zeta^2 = |C/det|_F / |X|_F
         const T zeta = scaled ? num<T>::sqrt_(num<T>::sqrt_(cf2) * (idet < (T)0 ? -idet : idet) * num<T>::rsq(xf2))
                               : (T)1;
         const T cx = (T)0.5 * zeta, cc = (T)0.5 * idet / zeta;
-        T diff = 0;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const T xn = cx * X[k] + cc * C[k];
-            const T dv = xn - X[k];
-            if constexpr (sizeof(T) == 4) diff = fmaxf(diff, dv < (T)0 ? -dv : dv);
-            else diff = fmax(diff, dv < (T)0 ? -dv : dv);
-            X[k] = xn;
-        }
-        if (diff < newton3_consts<T>::unscaled) scaled = false;
-        if (diff < newton3_consts<T>::stop) break;
+        for (int k = 0; k < 9; ++k) X[k] = cx * X[k] + cc * C[k];
+        if (last) break;
     }
 #pragma unroll
     for (int k = 0; k < 9; ++k) q[k] = X[k];

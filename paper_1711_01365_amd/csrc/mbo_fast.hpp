@@ -88,6 +88,9 @@ __device__ __forceinline__ void newton3_run(Newton3& s, float* q, int& dsign)
         float xf2 = 0.f;
 #pragma unroll
         for (int k = 0; k < 9; ++k) xf2 += s.X[k] * s.X[k];
+        // the stopping test of polar_newton3 (newton3_near_done)
+        bool last = false;
+        if (it > 0) newton3_near_done(xf2, scaled, last);
         // hardware reciprocal (about 1 ulp): the iteration corrects its own
         // rounding, and a relative error of one ulp in the step's two scalar
         // factors stays below the float rounding of the result
@@ -96,16 +99,9 @@ __device__ __forceinline__ void newton3_run(Newton3& s, float* q, int& dsign)
                                                       num<float>::rsq(xf2))
                                   : 1.0f;
         const float cx = 0.5f * zeta, cc = 0.5f * idet * num<float>::rcp(zeta);
-        float diff = 0.f;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const float xn = cx * s.X[k] + cc * s.C[k];
-            const float dv = xn - s.X[k];
-            diff = fmaxf(diff, dv < 0.f ? -dv : dv);
-            s.X[k] = xn;
-        }
-        if (diff < 1e-2f) scaled = false;
-        if (diff < 3e-4f) break;
+        for (int k = 0; k < 9; ++k) s.X[k] = cx * s.X[k] + cc * s.C[k];
+        if (last) break;
     }
 #pragma unroll
     for (int k = 0; k < 9; ++k) q[k] = s.X[k];
