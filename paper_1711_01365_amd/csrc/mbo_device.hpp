@@ -898,6 +898,49 @@ __device__ __forceinline__ void cofactor3(const T* x, T* c)
     c[8] = x[0] * x[4] - x[1] * x[3];
 }
 
+// Cofactor matrix of a row-major 4x4 matrix, from the 2x2 minors of rows 0-1
+// (s) and rows 2-3 (t): a cofactor of row 0 or 1 expands its 3x3 minor along
+// the other of the two rows against t, one of row 2 or 3 along the other of
+// those rows against s.
+template <typename T>
+__device__ __forceinline__ void cofactor4(const T* x, T* c)
+{
+    const T* a = x;
+    const T* b = x + 4;
+    const T* e = x + 8;
+    const T* d = x + 12;
+    const T s01 = a[0] * b[1] - a[1] * b[0], s02 = a[0] * b[2] - a[2] * b[0], s03 = a[0] * b[3] - a[3] * b[0];
+    const T s12 = a[1] * b[2] - a[2] * b[1], s13 = a[1] * b[3] - a[3] * b[1], s23 = a[2] * b[3] - a[3] * b[2];
+    const T t01 = e[0] * d[1] - e[1] * d[0], t02 = e[0] * d[2] - e[2] * d[0], t03 = e[0] * d[3] - e[3] * d[0];
+    const T t12 = e[1] * d[2] - e[2] * d[1], t13 = e[1] * d[3] - e[3] * d[1], t23 = e[2] * d[3] - e[3] * d[2];
+    // minors of rows {1,2,3} (row 0's cofactors) and {0,2,3} (row 1's)
+    c[0] = b[1] * t23 - b[2] * t13 + b[3] * t12;
+    c[1] = -(b[0] * t23 - b[2] * t03 + b[3] * t02);
+    c[2] = b[0] * t13 - b[1] * t03 + b[3] * t01;
+    c[3] = -(b[0] * t12 - b[1] * t02 + b[2] * t01);
+    c[4] = -(a[1] * t23 - a[2] * t13 + a[3] * t12);
+    c[5] = a[0] * t23 - a[2] * t03 + a[3] * t02;
+    c[6] = -(a[0] * t13 - a[1] * t03 + a[3] * t01);
+    c[7] = a[0] * t12 - a[1] * t02 + a[2] * t01;
+    // minors of rows {0,1,3} (row 2's) and {0,1,2} (row 3's)
+    c[8] = d[1] * s23 - d[2] * s13 + d[3] * s12;
+    c[9] = -(d[0] * s23 - d[2] * s03 + d[3] * s02);
+    c[10] = d[0] * s13 - d[1] * s03 + d[3] * s01;
+    c[11] = -(d[0] * s12 - d[1] * s02 + d[2] * s01);
+    c[12] = -(e[1] * s23 - e[2] * s13 + e[3] * s12);
+    c[13] = e[0] * s23 - e[2] * s03 + e[3] * s02;
+    c[14] = -(e[0] * s13 - e[1] * s03 + e[3] * s01);
+    c[15] = e[0] * s12 - e[1] * s02 + e[2] * s01;
+}
+
+template <typename T, int n>
+__device__ __forceinline__ void cofactor_n(const T* x, T* c)
+{
+    static_assert(n == 3 || n == 4, "cofactors of 3x3 and 4x4 matrices");
+    if constexpr (n == 3) cofactor3(x, c);
+    else cofactor4(x, c);
+}
+
 // Constants of the Newton polar iteration by precision: the unit roundoff u,
 // the smallest squared cofactor norm accepted (the first step's products must
 // stay normal), and the bounds on |X|_F^2 - 3 that end the scaled phase and
@@ -915,100 +958,116 @@ template <> struct newton3_consts<double> {
 };
 
 // Stopping test of the Newton polar iteration from xf2 = |X|_F^2 at the start
-// of a step after the first.  A step maps each singular value s to
-// (z s + 1/(z s)) / 2 >= 1, so from then on xf2 - 3 = sum (s_i^2 - 1) has no
+// of a step after the first (n x n).  A step maps each singular value s to
+// (z s + 1/(z s)) / 2 >= 1, so from then on xf2 - n = sum (s_i^2 - 1) has no
 // negative term and bounds every s_i - 1 by half its value.  Scaling stops
 // once that is below unscaled / 2 (quadratic convergence takes over), and the
 // step is the last once it is below last / 2: the step then leaves an error of
 // about (last / 2)^2 / 2 (float: 1.8e-7, below the FP32 bar by far and about
 // the rounding of the result; double: 1.3e-15).  A rounding of xf2 below the
 // bound only ends the iteration where it has converged to that rounding.
-template <typename T>
+template <typename T, int n = 3>
 __device__ __forceinline__ void newton3_near_done(T xf2, bool& scaled, bool& last)
 {
-    const T e = xf2 - (T)3;
+    const T e = xf2 - (T)n;
     if (e < newton3_consts<T>::unscaled) scaled = false;
     last = e < newton3_consts<T>::last;
 }
 
-// Whether the 3x3 matrix a (cofactors C, det, squared cofactor norm cf2)
-// certainly has sigma_min > thr.
-template <typename T>
+// Whether the n x n matrix a (n = 3, 4; cofactors C, det, squared cofactor
+// norm cf2) certainly has sigma_min > thr.
+template <typename T, int n = 3>
 __device__ __forceinline__ bool newton3_certain(const T* a, const T* C, T det, T cf2, T thr)
 {
     // 1/|A^{-1}|_F = |det| / |cof A|_F <= sigma_min, so |det| > thr |cof|_F
     // proves sigma_min > thr, provided the computed det and cofactors are
-    // accurate enough: a cofactor carries an error of at most 2u|A|_F^2 and
-    // det at most 4u|A|_F^3 + 3u|A|_F|cof|_F, so the test is made with that
-    // margin (doubled).  Without it a numerically rank-1 matrix (sigma_2 near
-    // u sigma_1), whose cofactors are mostly rounding, could pass.  Strict:
-    // det = 0 with a zero cofactor matrix (rank <= 1, the zero matrix) fails,
-    // and so does a matrix whose squared cofactor norm is not a normal number
-    // with room (the first step's products would underflow; Jacobi rescales by
-    // a power of two); also NaN.
+    // accurate enough.  n = 3: a cofactor (a 2x2 minor) carries an error of at
+    // most 2u|A|_F^2 and det at most 4u|A|_F^3 + 3u|A|_F|cof|_F.  n = 4: a
+    // cofactor (a 3x3 minor from 2x2 minors) at most 8u|A|_F^3, so 32u|A|_F^3
+    // over the matrix, and det at most 32u|A|_F^4 + 4u|A|_F|cof|_F.  The test
+    // is made with that margin (doubled).  Without it a numerically
+    // rank-deficient matrix, whose cofactors are mostly rounding, could pass.
+    // Strict: det = 0 with a zero cofactor matrix fails, and so does a matrix
+    // whose squared cofactor norm is not a normal number with room (the first
+    // step's products would underflow; Jacobi rescales by a power of two), one
+    // whose cofactors overflow (then thr |cof|_F is infinite), and NaN.
     T af2 = 0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) af2 += a[k] * a[k];
+    for (int k = 0; k < n * n; ++k) af2 += a[k] * a[k];
     const T an = num<T>::sqrt_(af2), cn = num<T>::sqrt_(cf2);
     const T u = newton3_consts<T>::u;
-    const T margin = (T)2 * u * (thr * ((T)6 * af2 + cn) + an * ((T)4 * af2 + (T)3 * cn));
+    T margin;
+    if constexpr (n == 3) margin = (T)2 * u * (thr * ((T)6 * af2 + cn) + an * ((T)4 * af2 + (T)3 * cn));
+    else margin = (T)2 * u * (thr * ((T)32 * an * af2 + cn) + an * ((T)32 * an * af2 + (T)4 * cn));
     const T adet = det < (T)0 ? -det : det;
     return (cf2 >= newton3_consts<T>::cf2_min) && (adet > thr * cn + margin);
 }
 
-// Closest orthogonal matrix of a 3x3 matrix by the scaled Newton iteration for
-// the polar decomposition, X <- (zeta X + X^{-T} / zeta) / 2 (Higham, 1986),
-// with Frobenius-norm scaling zeta = (|X^{-1}|_F / |X|_F)^{1/2} until the
-// singular values are near 1 and unscaled steps after it (newton3_near_done).
-// Each step maps every singular value s to (zeta s + 1/(zeta s)) / 2 and keeps
-// U, V and the sign of det, so the limit is U V^t; convergence is quadratic.
-// Returns false (q unset) unless newton3_certain proves sigma_min > thr (it
-// fails when sigma_min may be at most about sqrt(3) thr, when A is singular or
-// numerically of rank 1); such points go to the Jacobi route.
-template <typename T>
-__device__ __forceinline__ bool polar_newton3(const T* a, T* q, int& dsign, T thr)
+// Closest orthogonal matrix of an n x n matrix (n = 3, 4) by the scaled
+// Newton iteration for the polar decomposition, X <- (zeta X + X^{-T} / zeta)
+// / 2 (Higham, 1986), X^{-T} = cof(X) / det(X), with Frobenius-norm scaling
+// zeta = (|X^{-1}|_F / |X|_F)^{1/2} until the singular values are near 1 and
+// unscaled steps after it (newton3_near_done).  Each step maps every singular
+// value s to (zeta s + 1/(zeta s)) / 2 and keeps U, V and the sign of det, so
+// the limit is U V^t; convergence is quadratic.  Returns false (q unset)
+// unless newton3_certain proves sigma_min > thr (it fails when sigma_min may
+// be at most about sqrt(n) thr, when A is singular or numerically of lower
+// rank); such points go to the Jacobi route.
+template <typename T, int n>
+__device__ __forceinline__ bool polar_newton(const T* a, T* q, int& dsign, T thr)
 {
-    T X[9], C[9];
+    constexpr int NN = n * n;
+    T X[NN], C[NN];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) X[k] = a[k];
-    cofactor3(X, C);
-    T det = X[0] * C[0] + X[1] * C[1] + X[2] * C[2];
+    for (int k = 0; k < NN; ++k) X[k] = a[k];
+    cofactor_n<T, n>(X, C);
+    T det = 0;
+#pragma unroll
+    for (int j = 0; j < n; ++j) det += X[j] * C[j];
     T cf2 = 0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) cf2 += C[k] * C[k];
-    if (!newton3_certain(X, C, det, cf2, thr)) return false;
+    for (int k = 0; k < NN; ++k) cf2 += C[k] * C[k];
+    if (!newton3_certain<T, n>(X, C, det, cf2, thr)) return false;
     dsign = det >= (T)0 ? 1 : -1;
     bool scaled = true;
 #pragma unroll 1
     for (int it = 0; it < 16; ++it) {
         if (it > 0) {
-            cofactor3(X, C);
-            det = X[0] * C[0] + X[1] * C[1] + X[2] * C[2];
+            cofactor_n<T, n>(X, C);
+            det = 0;
+#pragma unroll
+            for (int j = 0; j < n; ++j) det += X[j] * C[j];
             cf2 = 0;
 #pragma unroll
-            for (int k = 0; k < 9; ++k) cf2 += C[k] * C[k];
+            for (int k = 0; k < NN; ++k) cf2 += C[k] * C[k];
         }
         T xf2 = 0;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) xf2 += X[k] * X[k];
+        for (int k = 0; k < NN; ++k) xf2 += X[k] * X[k];
         bool last = false;
-        if (it > 0) newton3_near_done(xf2, scaled, last);
+        if (it > 0) newton3_near_done<T, n>(xf2, scaled, last);
         const T idet = (T)1 / det;
         // zeta^2 = |C/det|_F / |X|_F
         const T zeta = scaled ? num<T>::sqrt_(num<T>::sqrt_(cf2) * (idet < (T)0 ? -idet : idet) * num<T>::rsq(xf2))
                               : (T)1;
         const T cx = (T)0.5 * zeta, cc = (T)0.5 * idet / zeta;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) X[k] = cx * X[k] + cc * C[k];
+        for (int k = 0; k < NN; ++k) X[k] = cx * X[k] + cc * C[k];
         if (last) break;
     }
 #pragma unroll
-    for (int k = 0; k < 9; ++k) q[k] = X[k];
+    for (int k = 0; k < NN; ++k) q[k] = X[k];
     return true;
 }
 
-// Double plans take the Newton route for n = 3 points whose smallest singular
-// value is certainly above this (Jacobi below it).
+template <typename T>
+__device__ __forceinline__ bool polar_newton3(const T* a, T* q, int& dsign, T thr)
+{
+    return polar_newton<T, 3>(a, q, dsign, thr);
+}
+
+// Double plans take the Newton route for n = 3, 4 points whose smallest
+// singular value is certainly above this (Jacobi below it).
 constexpr double kNewtonMinSigmaF64 = 1e-3;
 
 // Float Jacobi of a point of a plan with the double fallback: when the smallest
@@ -1053,12 +1112,12 @@ __device__ __forceinline__ bool project_point_fb(const T* a, T* q, int& dsign, b
                                                  double sigma_fb)
 {
     constexpr int NN = n * n;
-    if constexpr (sizeof(T) == 4 && n == 3) {
+    if constexpr (sizeof(T) == 4 && n >= 3) {
         // well-conditioned points (sigma_min >= sigma_fb): Newton, no fallback
-        if (polar_newton3(a, q, dsign, (float)sigma_fb)) return false;
+        if (polar_newton<float, n>(a, q, dsign, (float)sigma_fb)) return false;
     }
-    if constexpr (sizeof(T) == 8 && n == 3) {
-        if (polar_newton3(a, q, dsign, kNewtonMinSigmaF64)) return false;
+    if constexpr (sizeof(T) == 8 && n >= 3) {
+        if (polar_newton<double, n>(a, q, dsign, kNewtonMinSigmaF64)) return false;
     }
     if constexpr (sizeof(T) == 4 && n >= 3) {
         if (fallback) {

@@ -438,7 +438,9 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
                     nbad += all_finite<T, NN>(av) ? 0ull : 1ull;
                     int ds;
                     if constexpr (S::DEFER4) {
-                        if (fallback) {
+                        if (polar_newton<float, n>(av, qv, ds, (float)a.sigma_fb)) {
+                            // well conditioned: Newton, no fallback
+                        } else if (fallback) {
                             float V[n][n];
                             if (polar_jacobi_f32_fb<n>(av, qv, ds, V, a.sigma_fb)) {
                                 fq[atomicAdd(&fq_n, 1)] = (unsigned short)(pp * 512 + tid);

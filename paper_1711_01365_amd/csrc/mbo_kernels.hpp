@@ -403,7 +403,7 @@ __global__ void __launch_bounds__(512, (row_waves_per_simd<T, n, LOG2L, RM>())) 
                 bool queued = false;
                 if constexpr (DEFER) {
                     bool newton = false;
-                    if constexpr (n == 3) newton = polar_newton3(av, qv, ds, (float)a.sigma_fb);
+                    if constexpr (n >= 3) newton = polar_newton<float, n>(av, qv, ds, (float)a.sigma_fb);
                     if (newton) {
                     } else if (defer) {
                         float V[n][n];
