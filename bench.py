@@ -614,7 +614,7 @@ def main():
     dominant_us = max(main_run["row_us"], main_run["heat_us"])
     dominant = "row_pass" if main_run["row_us"] >= main_run["heat_us"] else "heat_pass"
     banded = main_run["path"]["kind"] != "generic"
-    kernel_name = {("row_pass", True): "row_fast<float, 3, 9>", ("row_pass", False): "row_pass<float, 3, 9, 0>",
+    kernel_name = {("row_pass", True): "row_fast<float, 3, 9, false>", ("row_pass", False): "row_pass<float, 3, 9, 0>",
                    ("heat_pass", True): "heat_fast<float, 9, TX>",
                    ("heat_pass", False): "col_pass<float, 2, 9>"}[(dominant, banded)]
     achieved = bytes_per_launch / (dominant_us * 1e-6) / 1e9
