@@ -675,7 +675,8 @@ __global__ void __launch_bounds__(TX * (1 << LOG2L) / 8) heat_fast(const FastCol
 // between two row passes in one read and one write of the spectra.  Each
 // thread holds two lines of eight values.  The plane sits in LDS as complex
 // pairs (real and imaginary part side by side: one address per element) in
-// rows of odd pitch, so that the z lines spread over the banks.
+// rows of odd pitch, so that the z lines spread over the banks; the exchanges
+// inside a line use the XOR-permuted positions of line_index<LIX_XOR>.
 template <typename T, int LOG2Y, int LOG2Z>
 struct PlaneFastShape {
     static constexpr int NY = 1 << LOG2Y, NZ = 1 << LOG2Z;
