@@ -111,6 +111,27 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 10}))
 
 
+def launch_shape(w, precision, path, tuning, autotune):
+    """Launch shape of the iteration's kernels.  The band-limited row pass has a
+    fixed shape per (n, row length) (512 points per workgroup, or one long row);
+    the heat tile width and the XCD order are tuned.  The general path reports
+    its tuned row-pass shape."""
+    from paper_1711_01365_amd import mbo
+    if path[0] == mbo.PATH_GENERIC:
+        return {"rows_per_row_workgroup": tuning[0], "row_workgroup_threads": tuning[1],
+                "lines_per_heat_workgroup": tuning[2], "xcd_tile_order": tuning[3], "autotuned": bool(autotune)}
+    L, n = w.grid[-1], w.n
+    tn, pl = L // 8, (n * n + 1) // 2
+    rows = 1 if L >= 512 else 512 // L
+    if L <= 512:
+        threads = 512
+    else:
+        ntmax = 768 if (precision != mbo.F64 and n == 3) else 1024
+        threads = max(512, min(rows * pl * tn, ntmax // tn * tn))
+    return {"rows_per_row_workgroup": rows, "row_workgroup_threads": threads,
+            "columns_per_heat_workgroup": tuning[2], "xcd_tile_order": tuning[3], "autotuned": bool(autotune)}
+
+
 def run_gpu(w, precision, steps, warmup, timing_steps, autotune=True):
     """Timed region: `steps` steps through the captured graph (the product path).
     Then `timing_steps` more steps with per-kernel HIP events (direct launches)."""
@@ -155,9 +176,7 @@ def run_gpu(w, precision, steps, warmup, timing_steps, autotune=True):
         "heat_us": float(np.mean(col_us)) if col_us else None,
         "energy_first_last": [float(logs["energy"][0][0]), float(logs["energy"][0][-1])],
         "fallbacks_total": int(logs["fallbacks"][0].sum()),
-        "launch_shape": {"rows_per_row_workgroup": tuning[0], "row_workgroup_threads": tuning[1],
-                         "lines_per_heat_workgroup": tuning[2], "xcd_tile_order": tuning[3],
-                         "autotuned": bool(autotune)},
+        "launch_shape": launch_shape(w, precision, path, tuning, autotune),
         "flips_first": int(logs["flips"][0][0]),
         "path": {"kind": {0: "generic", 1: "full", 2: "banded"}[path[0]], "half_width": path[1],
                  "stored_modes": path[2]},
