@@ -168,6 +168,11 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
     T* li = lr + (size_t)S::LINES * LP;
     __shared__ unsigned short fq[(HELPER || S::DEFER4) ? S::P : 1];
     __shared__ int fq_n, fq_claim;
+    // rows of at most 512 points (every wave holds points): the last wave's
+    // Newton points, handed to the other waves when it runs the queue
+    constexpr bool SPLIT = HELPER && S::THREADS == 512 && S::PPT == 1;
+    __shared__ int hq[SPLIT ? 64 : 1];
+    __shared__ int hq_n, hq_claim;
     __shared__ unsigned long long wg_cnt[2];
 
     const int flags = a.flags;
@@ -176,6 +181,8 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
     if (tid == 0) {
         fq_n = 0;
         fq_claim = 0;
+        hq_n = 0;
+        hq_claim = 0;
         wg_cnt[0] = 0;
         wg_cnt[1] = 0;
     }
@@ -369,39 +376,23 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
                     T av[NN];
                     load_point(lrq, liq, av);
                     nbad += all_finite<T, NN>(av) ? 0ull : 1ull;
-                    if (newton3_init(av, ns, (float)a.sigma_fb)) ok |= 1u << pp;
-                    else fq[atomicAdd(&fq_n, 1)] = (unsigned short)(pp * 512 + tid);
+                    if (newton3_init(av, ns, (float)a.sigma_fb)) {
+                        ok |= 1u << pp;
+                        // the last wave's Newton points, with their previous
+                        // det sign, for the other waves to take over when it
+                        // becomes the queue's wave
+                        if (SPLIT && tid >= 512 - 64)
+                            hq[atomicAdd(&hq_n, 1)] = (pp * 512 + tid) | ((int)(uint8_t)(s_old >> (8 * pp)) << 16);
+                    } else {
+                        fq[atomicAdd(&fq_n, 1)] = (unsigned short)(pp * 512 + tid);
+                    }
                 }
             }
             __syncthreads();
-            if (tid < 512) {
-#pragma unroll 1
-                for (int pp = 0; pp < PPT; ++pp) {
-                    if (!(ok >> pp & 1u)) continue;
-                    int64_t xp;
-                    T *lrq, *liq;
-                    (void)point_of(pp * 512 + tid, xp, lrq, liq);
-                    if constexpr (PPT > 1) {
-                        T av[NN];
-                        load_point(lrq, liq, av);
-                        (void)newton3_init(av, ns, (float)a.sigma_fb);
-                    }
-                    T qv[NN];
-                    int ds;
-                    newton3_run(ns, qv, ds);
-                    finish(xp, lrq, liq, qv, ds, (int8_t)(s_old >> (8 * pp)));
-                }
-            }
-            // The queued points go to the first wave done with its own points
-            // (threads beyond the 512 projection threads, for long rows, have
-            // none): Jacobi in float, and in double (warm-started from the
-            // float right singular vectors) when sigma_min < sigma_fb.  A wave
-            // of its own would cost the registers that let two workgroups
-            // share a CU.
-            int claim = 0;
-            if ((tid & 63) == 0) claim = atomicAdd(&fq_claim, 1);
-            claim = __shfl(claim, 0, 64);
-            if (claim == 0) {
+            // Queued points: Jacobi in float, and in double (warm-started from
+            // the float right singular vectors) when sigma_min < sigma_fb, at
+            // raised priority, one point per lane of the wave that runs them.
+            auto run_queue = [&]() {
                 __builtin_amdgcn_s_setprio(3);
                 const int nq = fq_n;
                 const int lane = tid & 63;
@@ -426,6 +417,65 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
                     finish(xp, lrq, liq, qv, ds, (flags & RF_SIGN) ? sgn[xp] : (int8_t)0);
                 }
                 __builtin_amdgcn_s_setprio(0);
+            };
+            // With every wave holding points (rows of at most 512 points) and a
+            // non-empty queue, the last wave starts on the queue at once and
+            // the first wave done with its own points takes the last wave's
+            // Newton points: the queue's serial Jacobi chain then overlaps the
+            // other waves' Newton iterations instead of following them.
+            const bool split = SPLIT && fq_n > 0;
+            const bool qwave = split && tid >= 512 - 64;
+            if (tid < 512 && !qwave) {
+#pragma unroll 1
+                for (int pp = 0; pp < PPT; ++pp) {
+                    if (!(ok >> pp & 1u)) continue;
+                    int64_t xp;
+                    T *lrq, *liq;
+                    (void)point_of(pp * 512 + tid, xp, lrq, liq);
+                    if constexpr (PPT > 1) {
+                        T av[NN];
+                        load_point(lrq, liq, av);
+                        (void)newton3_init(av, ns, (float)a.sigma_fb);
+                    }
+                    T qv[NN];
+                    int ds;
+                    newton3_run(ns, qv, ds);
+                    finish(xp, lrq, liq, qv, ds, (int8_t)(s_old >> (8 * pp)));
+                }
+            }
+            if (split) {
+                if (qwave) {
+                    run_queue();
+                } else {
+                    // the last wave's Newton points, one per lane of the first
+                    // wave(s) to get here (hq_n is final since the barrier)
+#pragma unroll 1
+                    for (;;) {
+                        const int i = atomicAdd(&hq_claim, 1);
+                        if (i >= hq_n) break;
+                        const int e = hq[i];
+                        int64_t xp;
+                        T *lrq, *liq;
+                        (void)point_of(e & 0xffff, xp, lrq, liq);
+                        T av[NN];
+                        load_point(lrq, liq, av);
+                        Newton3 hs;
+                        (void)newton3_init(av, hs, (float)a.sigma_fb);
+                        T qv[NN];
+                        int ds;
+                        newton3_run(hs, qv, ds);
+                        finish(xp, lrq, liq, qv, ds, (int8_t)(e >> 16));
+                    }
+                }
+            } else {
+                // The queued points go to the first wave done with its own
+                // points (threads beyond the 512 projection threads, for long
+                // rows, have none).  A wave of its own would cost the registers
+                // that let two workgroups share a CU.
+                int claim = 0;
+                if ((tid & 63) == 0) claim = atomicAdd(&fq_claim, 1);
+                claim = __shfl(claim, 0, 64);
+                if (claim == 0) run_queue();
             }
         } else {
 #pragma unroll 1
