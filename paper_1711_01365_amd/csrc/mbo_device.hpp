@@ -81,14 +81,12 @@ __device__ __forceinline__ void dft4(T* r, T* i)
     r[3] = t1r - t3r; i[3] = t1i - t3i;
 }
 
+// Second half of the length-8 DFT: the length-4 DFTs of the even (er, ei)
+// and odd (orr, oi) inputs are combined through exp(S 2 pi i k / 8).
 template <typename T, int S>
-__device__ __forceinline__ void dft8(T* r, T* i)
+__device__ __forceinline__ void dft8_combine(const T (&er)[4], const T (&ei)[4], T (&orr)[4], T (&oi)[4], T* r, T* i)
 {
     const T c = (T)0.70710678118654752440084436210485;
-    T er[4] = {r[0], r[2], r[4], r[6]}, ei[4] = {i[0], i[2], i[4], i[6]};
-    T orr[4] = {r[1], r[3], r[5], r[7]}, oi[4] = {i[1], i[3], i[5], i[7]};
-    dft4<T, S>(er, ei);
-    dft4<T, S>(orr, oi);
     // odd half times exp(S 2 pi i k / 8), k = 1, 2, 3
     {
         T x = orr[1], y = oi[1];
@@ -106,6 +104,60 @@ __device__ __forceinline__ void dft8(T* r, T* i)
         r[k] = er[k] + orr[k]; i[k] = ei[k] + oi[k];
         r[k + 4] = er[k] - orr[k]; i[k + 4] = ei[k] - oi[k];
     }
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void dft8(T* r, T* i)
+{
+    T er[4] = {r[0], r[2], r[4], r[6]}, ei[4] = {i[0], i[2], i[4], i[6]};
+    T orr[4] = {r[1], r[3], r[5], r[7]}, oi[4] = {i[1], i[3], i[5], i[7]};
+    dft4<T, S>(er, ei);
+    dft4<T, S>(orr, oi);
+    dft8_combine<T, S>(er, ei, orr, oi, r, i);
+}
+
+// dft8 of inputs 1..6 known to be zero: the two length-4 DFTs reduce to copies
+// and sign changes of inputs 0 and 7 (adding or subtracting an exact zero), so
+// the result is that of dft8, with fewer operations.
+template <typename T, int S>
+__device__ __forceinline__ void dft8_in07(T* r, T* i)
+{
+    const T x0r = r[0], x0i = i[0], x7r = r[7], x7i = i[7];
+    T er[4] = {x0r, x0r, x0r, x0r}, ei[4] = {x0i, x0i, x0i, x0i};
+    // odd inputs (0, 0, 0, x7): dft4 gives (x7, -S i x7... ) as below
+    T t3r = -x7r, t3i = -x7i;
+    mul_si<T, S>(t3r, t3i);
+    T orr[4] = {x7r, t3r, -x7r, -t3r}, oi[4] = {x7i, t3i, -x7i, -t3i};
+    dft8_combine<T, S>(er, ei, orr, oi, r, i);
+}
+
+// dft8 of which only outputs 0 and 7 are needed: the operations of dft8 that
+// lead to them, in the same order (the same values); outputs 1..6 are left
+// unset.
+template <typename T, int S>
+__device__ __forceinline__ void dft8_out07(T* r, T* i)
+{
+    const T c = (T)0.70710678118654752440084436210485;
+    // even inputs 0, 2, 4, 6: outputs 0 and 3 of their dft4
+    const T e0r = r[0] + r[4], e0i = i[0] + i[4];
+    const T e1r = r[0] - r[4], e1i = i[0] - i[4];
+    const T e2r = r[2] + r[6], e2i = i[2] + i[6];
+    T e3r = r[2] - r[6], e3i = i[2] - i[6];
+    mul_si<T, S>(e3r, e3i);
+    const T er0 = e0r + e2r, ei0 = e0i + e2i;
+    const T er3 = e1r - e3r, ei3 = e1i - e3i;
+    // odd inputs 1, 3, 5, 7
+    const T o0r = r[1] + r[5], o0i = i[1] + i[5];
+    const T o1r = r[1] - r[5], o1i = i[1] - i[5];
+    const T o2r = r[3] + r[7], o2i = i[3] + i[7];
+    T o3r = r[3] - r[7], o3i = i[3] - i[7];
+    mul_si<T, S>(o3r, o3i);
+    const T or0 = o0r + o2r, oi0 = o0i + o2i;
+    const T x = o1r - o3r, y = o1i - o3i;
+    const T or3 = c * (-x - (T)S * y);
+    const T oi3 = c * ((T)S * x - y);
+    r[0] = er0 + or0; i[0] = ei0 + oi0;
+    r[7] = er3 - or3; i[7] = ei3 - oi3;
 }
 
 template <typename T, int R, int S>
@@ -328,20 +380,32 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
+// Pruning of a line transform (band-limited lines, half-width c < L/8):
+// FFT_IN07, the inputs x[t + e L/8] with 1 <= e <= 6 are zero (radix-8 first
+// stage only); FFT_OUT07, only the outputs x[t + e L/8] with e = 0 or 7 are
+// used (the others are left unset).
+enum { FFT_FULL = 0, FFT_IN07 = 1, FFT_OUT07 = 2 };
+
 // The same transform for a line whose L/8 threads lie inside one wave
 // (L <= 512): exchanges need no workgroup barrier.  LDS element j of the line is
 // at lr/li[lds_pad(j)].  Threads with act = false touch no LDS.
-template <typename T, int S, int LOG2L, int STAGE = 0>
+template <typename T, int S, int LOG2L, int STAGE = 0, int PR = FFT_FULL>
 __device__ __forceinline__ void fft_wave(T (&r)[8], T (&im)[8], T* lr, T* li, int t,
                                          const Twiddles<T, LOG2L>& tw, bool act)
 {
     typedef FftShape<LOG2L> F;
     static_assert(LOG2L <= 9, "a line must fit in one wave");
+    static_assert(!(PR & FFT_IN07) || F::radix(0) == 8, "input pruning needs a radix-8 first stage");
     if constexpr (STAGE < F::NST) {
         constexpr int R = F::radix(STAGE);
         constexpr int p = 1 << F::log2span(STAGE);
-        if constexpr (STAGE == 0) stage_span1<T, R, S>(r, im);
-        else stage_tw8<T, S>(r, im, tw.w[STAGE - 1]);
+        if constexpr (STAGE == 0 && (PR & FFT_IN07)) dft8_in07<T, S>(r, im);
+        else if constexpr (STAGE == 0) stage_span1<T, R, S>(r, im);
+        else if constexpr (STAGE == F::NST - 1 && (PR & FFT_OUT07)) {
+#pragma unroll
+            for (int j = 1; j < 8; ++j) twiddle<T, S>(r[j], im[j], tw.w[STAGE - 1][j - 1]);
+            dft8_out07<T, S>(r, im);
+        } else stage_tw8<T, S>(r, im, tw.w[STAGE - 1]);
         if constexpr (STAGE != F::NST - 1) {
             wave_lds_sync();  // earlier reads of the line are done
             if (act) {
@@ -380,7 +444,7 @@ __device__ __forceinline__ void fft_wave(T (&r)[8], T (&im)[8], T* lr, T* li, in
                     im[e] = li[a];
                 }
             }
-            fft_wave<T, S, LOG2L, STAGE + 1>(r, im, lr, li, t, tw, act);
+            fft_wave<T, S, LOG2L, STAGE + 1, PR>(r, im, lr, li, t, tw, act);
         }
     }
 }

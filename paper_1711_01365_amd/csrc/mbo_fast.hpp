@@ -277,7 +277,13 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
             T* lij = li + (size_t)lj * LP;
             if constexpr (S::WAVE_LINE) {
                 if (act) {
-                    fft_wave<T, +1, LOG2L>(r[0], im[0], lrj, lij, t, tw, true);
+                    // with c < L/8 only the loads e = 0, 7 hold kept modes
+                    if constexpr (FftShape<LOG2L>::R0 == 1 && FftShape<LOG2L>::NST > 1) {
+                        if (c < Tn) fft_wave<T, +1, LOG2L, 0, FFT_IN07>(r[0], im[0], lrj, lij, t, tw, true);
+                        else fft_wave<T, +1, LOG2L>(r[0], im[0], lrj, lij, t, tw, true);
+                    } else {
+                        fft_wave<T, +1, LOG2L>(r[0], im[0], lrj, lij, t, tw, true);
+                    }
                     wave_lds_sync();  // the line's last exchange has been read
                 }
             } else {
@@ -559,7 +565,13 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
             if constexpr (S::WAVE_LINE) {
                 if (act) {
                     wave_lds_sync();  // every lane has read its elements before the exchanges
-                    fft_wave<T, -1, LOG2L>(r3[0], im3[0], lrj, lij, t, tw3, true);
+                    // with c < L/8 only the modes e = 0, 7 are stored
+                    if constexpr (FftShape<LOG2L>::NST > 1) {
+                        if (c < Tn) fft_wave<T, -1, LOG2L, 0, FFT_OUT07>(r3[0], im3[0], lrj, lij, t, tw3, true);
+                        else fft_wave<T, -1, LOG2L>(r3[0], im3[0], lrj, lij, t, tw3, true);
+                    } else {
+                        fft_wave<T, -1, LOG2L>(r3[0], im3[0], lrj, lij, t, tw3, true);
+                    }
                 }
             } else {
                 fft_lines<T, -1, 1, LOG2L>(r3, im3, lrj, lij, 0, 1, 0, t, tw3, act);
