@@ -277,8 +277,10 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
             T* lij = li + (size_t)lj * LP;
             if constexpr (S::WAVE_LINE) {
                 if (act) {
-                    // with c < L/8 only the loads e = 0, 7 hold kept modes
-                    if constexpr (FftShape<LOG2L>::R0 == 1 && FftShape<LOG2L>::NST > 1) {
+                    // with c < L/8 only the loads e = 0, 7 hold kept modes (float, n <= 3:
+                    // the double and n = 4 instances have no registers to spare for a
+                    // second copy of the transform)
+                    if constexpr (sizeof(T) == 4 && n <= 3 && FftShape<LOG2L>::R0 == 1 && FftShape<LOG2L>::NST > 1) {
                         if (c < Tn) fft_wave<T, +1, LOG2L, 0, FFT_IN07>(r[0], im[0], lrj, lij, t, tw, true);
                         else fft_wave<T, +1, LOG2L>(r[0], im[0], lrj, lij, t, tw, true);
                     } else {
@@ -566,7 +568,7 @@ __global__ void __launch_bounds__((RowFastShape<T, n, LOG2L>::THREADS), (RowFast
                 if (act) {
                     wave_lds_sync();  // every lane has read its elements before the exchanges
                     // with c < L/8 only the modes e = 0, 7 are stored
-                    if constexpr (FftShape<LOG2L>::NST > 1) {
+                    if constexpr (sizeof(T) == 4 && n <= 3 && FftShape<LOG2L>::NST > 1) {
                         if (c < Tn) fft_wave<T, -1, LOG2L, 0, FFT_OUT07>(r3[0], im3[0], lrj, lij, t, tw3, true);
                         else fft_wave<T, -1, LOG2L>(r3[0], im3[0], lrj, lij, t, tw3, true);
                     } else {
