@@ -578,6 +578,66 @@ def test_banded_rows_match_the_full_path(torch_cuda, grid, n):
     assert err[gap >= 0.1].max() <= 1e-5
 
 
+def small_sigma_field(n, grid, seed):
+    """U diag(1, 0.7, s(x, y)) V^t with U, V fixed Haar-random orthogonal matrices
+    and s = 10^(-5 + 3 (1 + sin(2 pi x) cos(2 pi y)) / 2), smooth on the torus:
+    diffusion acts on s alone (H A = U diag(1, 0.7, H s) V^t), so the diffused
+    field keeps sigma_min = H s in [1e-5, 1e-2] and its polar factor is U V^t at
+    every point (condition 2 / (0.7 + H s))."""
+    rng = np.random.default_rng(seed)
+
+    def haar():
+        Q, R = np.linalg.qr(rng.standard_normal((n, n)))
+        return Q * np.sign(np.diag(R))[None, :]
+    U, V = haar(), haar()
+    x = np.arange(grid[1]) / grid[1]
+    y = np.arange(grid[0]) / grid[0]
+    sm = 10.0 ** (-5.0 + 1.5 * (1.0 + np.sin(2 * np.pi * x)[None, :] * np.cos(2 * np.pi * y)[:, None]))
+    sv = np.ones((n,) + tuple(grid))
+    sv[1] = 0.7
+    sv[n - 1] = sm
+    return np.einsum("ik,k...,jk->ij...", U, sv, V), U @ V.T
+
+
+@pytest.mark.parametrize("grid,tau", [((64, 512), 2e-4), ((64, 64), 2e-2)])
+def test_row_pass_queue_of_small_sigma_points(torch_cuda, grid, tau):
+    """One FP32 + FP64-fallback step of a field whose diffused points mostly fall
+    below the Newton precheck (sigma_min in [1e-5, 1e-2]): more points go to the
+    row pass's queue than one wave holds (its wave loops over them while the other
+    waves take its Newton points), and with the kept half-width below L/8 the line
+    transforms are pruned.  The exact step is U V^t at every point: the result
+    matches it and the FP64 oracle's step to 1e-5, det signs are those of U V^t,
+    and the fallback count lies between the oracle's counts of diffused points
+    below 0.95e-3 and 1.05e-3."""
+    torch = torch_cuda
+    n = 3
+    A0, Q = small_sigma_field(n, grid, 1400 + grid[1])
+    A32 = A0.astype(np.float32)
+    A64 = A32.astype(np.float64)
+    P = plan(grid, n, tau, FB)
+    assert_banded(P, grid[-1])
+    _, c, _W = P.path()
+    assert c < grid[-1] // 8  # pruned transforms
+    Ht, _ = oracle.heat(A64, tau, 2)
+    smin = np.linalg.svd(point_major(Ht), compute_uv=False)[:, -1]
+    lo, hi = int((smin < 0.95e-3).sum()), int((smin < 1.05e-3).sum())
+    t = to_dev(torch, A32, torch.float32)
+    r = P.iterate(t, 1)
+    ro = oracle.iterate(A64, tau, 1)
+    A1 = t.cpu().numpy().astype(np.float64)
+    e_orc = float(np.abs(A1 - ro["A"]).max())
+    e_uv = float(np.abs(point_major(A1) - Q[None]).max())
+    fb = int(r["fallbacks"][0][0])
+    note("small-sigma queue grid=%s tau=%g: %d of %d points below 1e-3, fallbacks %d, "
+         "err vs oracle %.3g, vs U V^t %.3g" % (grid, tau, lo, smin.size, fb, e_orc, e_uv))
+    assert lo > smin.size // 4
+    assert lo <= fb <= hi
+    assert e_orc <= 1e-5 and e_uv <= 1e-5
+    assert int(r["flips"][0][0]) == int(ro["flips"][0])
+    assert np.array_equal(np.sign(np.linalg.det(point_major(A1))),
+                          np.full(smin.size, np.sign(np.linalg.det(Q))))
+
+
 @pytest.mark.parametrize("prec", [F64, F32, FB])
 def test_iterate_zero_and_rank_one_fields(torch_cuda, prec):
     """Degenerate fields: the zero field diffuses to itself and every point
